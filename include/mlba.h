@@ -1,0 +1,178 @@
+/*
+ * mlba.h -- C ABI of the MI355X (gfx950) library for preconditioned
+ * modified linearized Bregman (MLBA) frame-based deblurring.
+ *
+ * Method: Cai, Donatelli, Bianchi, Huang, "Regularization preconditioners for
+ * frame-based image deblurring with reduced boundary artifacts"
+ * (arXiv:1504.07234).  One iteration is eq. (MLBA2) of section 3:
+ *
+ *     x^k     = delta_k S_mu(z^k)                      (eq. soft)
+ *     r^k     = g - A W^T x^k                           (eqs. modeld, wavecoeff)
+ *     z^{k+1} = z^k + W A^T P_{alpha_k} r^k             (eq. MLBA2)
+ *
+ * with A the blur of section 2, W the linear B-spline framelet of section
+ * 6.1 and P the spectral Tikhonov preconditioner of Algorithm 1 (BCCB/FFT,
+ * eq. Alg1) or Algorithm 3 (symmetrised PSF, DCT, eq. Alg3).
+ *
+ * Conventions shared by every entry point
+ *   - Images are row-major float32 arrays, element (y, x) at y*side + x.
+ *     Observed images are n x n.  The unknown image is N x N with
+ *     N = n + p - 1 for MLBA_BC_RECT (section 2.1) and N = n otherwise.
+ *   - Frame coefficients are band-planar float32 [bands][N][N] with
+ *     bands = 8*levels + 1: band 0 is the final low-pass image, then for each
+ *     level l = 1..levels the eight pairs (i,j) = (0,1),(0,2),(1,0),(1,1),
+ *     (1,2),(2,0),(2,1),(2,2), where (i,j) applies mask b_i along x and b_j
+ *     along y (section 6.1; level l uses dilation 2^(l-1)).
+ *   - The PSF is p x p float32 (p odd), centre (c, c), c = (p-1)/2.
+ *   - Every pointer named as "device" must point to device memory of the
+ *     current HIP device; "host" pointers are read before the call returns.
+ *     The caller owns every buffer it passes; the library never frees them.
+ *   - Work is enqueued on `stream` and is asynchronous unless stated.  A plan
+ *     owns its workspace (allocated by mlba_plan_create), so one plan must
+ *     not be used by two streams at the same time.  Entry points other than
+ *     mlba_plan_create / mlba_plan_destroy / mlba_batch_create /
+ *     mlba_batch_destroy allocate no device memory.
+ *   - Errors: every call returns an int status.  Negative values are
+ *     errors (nothing was enqueued), MLBA_WARN_DIVERGED is a warning.
+ *     No C++ exception crosses this interface.
+ */
+#ifndef MLBA_H
+#define MLBA_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes --------------------------------------------------- */
+#define MLBA_OK              0
+#define MLBA_WARN_DIVERGED   1   /* residual became non-finite or grew 1e3-fold */
+#define MLBA_EINVAL         -1   /* bad argument (null, size, odd/even rules)    */
+#define MLBA_EUNSUPPORTED   -2   /* size outside the supported transforms        */
+#define MLBA_EHIP           -3   /* a HIP runtime call failed (mlba_last_hip_error) */
+#define MLBA_ENOMEM         -4   /* device allocation failed                     */
+
+/* ---- boundary models (section 2) ------------------------------------ */
+#define MLBA_BC_RECT      0  /* rectangular n^2 x m^2 A = M A_big, eq. (Arect) */
+#define MLBA_BC_REFLECT   1  /* reflective (half-sample symmetric) pad, Table 1 */
+#define MLBA_BC_PERIODIC  2  /* periodic pad, Table 1                          */
+#define MLBA_BC_ZERO      3  /* zero pad, Table 1                              */
+
+/* ---- preconditioners (section 4) ------------------------------------ */
+#define MLBA_PRECOND_BCCB 0  /* P = (C C^T + alpha I)^-1 by 2-D FFT, Algorithm 1 */
+#define MLBA_PRECOND_DCT  1  /* P = (Q Q^T + alpha I)^-1 by 2-D DCT of the
+                                symmetrised PSF, Algorithm 3                  */
+#define MLBA_PRECOND_NONE 2  /* P = I: plain linearized Bregman, eq. (iterLinBreg) */
+
+/* ---- alpha schedules ------------------------------------------------- */
+#define MLBA_ALPHA_CONST      0  /* alpha_k = alpha0                              */
+#define MLBA_ALPHA_GEOMETRIC  1  /* alpha_k = max(alpha0 * ratio^k, alpha_floor)  */
+#define MLBA_ALPHA_TABLE      2  /* alpha_k = table[k] (host, >= k0+iters values) */
+
+typedef struct mlba_alpha_schedule {
+    int kind;
+    double alpha0;
+    double ratio;
+    double alpha_floor;
+    const double* table;  /* host; used when kind == MLBA_ALPHA_TABLE */
+    int table_len;
+} mlba_alpha_schedule;
+
+/* Discrepancy-principle stop, eq. (discrpr): stop at the first k with
+ * ||r^k|| <= gamma * noise_norm.  Checked every `check_every` iterations
+ * (one device->host copy of a scalar per check). */
+typedef struct mlba_stop {
+    double noise_norm;
+    double gamma;
+    int check_every;
+} mlba_stop;
+
+/* Parameters of a restoration run. */
+typedef struct mlba_params {
+    mlba_alpha_schedule alpha;
+    const double* mu;          /* host, n_mu values: 1 (all bands) or `bands`  */
+    int n_mu;
+    double delta;              /* > 0: step delta_k = delta;
+                                  <= 0: delta_k = 0.9 / max(||A^T P_{alpha_k} A||, 0.9),
+                                  estimated by mlba_plan_opnorm (section 3,
+                                  convergence theorem for MLBA)               */
+    const double* delta_table; /* host, optional: delta_k = delta_table[k] for
+                                  k = 0 .. k0+iters (k0+iters+1 values); the
+                                  last value scales the returned image        */
+    int iters;                 /* iterations to run                           */
+    int k0;                    /* global index of the first iteration (resume) */
+    const mlba_stop* stop;     /* optional discrepancy stop (NULL: fixed iters) */
+} mlba_params;
+
+typedef struct mlba_plan_s* mlba_plan_t;
+
+/* ---- library --------------------------------------------------------- */
+const char* mlba_status_string(int status);
+int mlba_last_hip_error(void);   /* hipError_t of the last MLBA_EHIP on this thread */
+int mlba_version(void);
+
+/* ---- plans ------------------------------------------------------------
+ * mlba_plan_create: n observed side, p odd PSF side (3 <= p <= n), bc one of
+ * MLBA_BC_*, precond one of MLBA_PRECOND_*, levels in [1, 4] with
+ * 2^(levels-1) < N.  The transforms of P need n = 2^a 3^b, a >= 1,
+ * 8 <= n <= 4096 (MLBA_EUNSUPPORTED otherwise).  psf: device p x p.
+ * Allocates the workspace, copies the PSF and computes the spectrum of
+ * (C C^T) or (Q Q^T) on `stream` (section 4.1 / 4.3).  The plan keeps no
+ * reference to `psf`. */
+int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int levels,
+                     const float* psf, hipStream_t stream);
+/* Replace the PSF (same p) and recompute the spectrum. psf: device p x p. */
+int mlba_plan_set_psf(mlba_plan_t plan, const float* psf, hipStream_t stream);
+int mlba_plan_destroy(mlba_plan_t plan);
+/* Sizes: observed side n, PSF side p, unknown side N, number of bands. */
+int mlba_plan_dims(mlba_plan_t plan, int* n, int* p, int* N, int* bands);
+/* ||A^T P_alpha A|| by `iters` power iterations (synchronous; result on host). */
+int mlba_plan_opnorm(mlba_plan_t plan, double alpha, int iters, double* out, hipStream_t stream);
+
+/* ---- operators (each one device pass, asynchronous) --------------------- */
+/* y = A u.   u: device N x N, y: device n x n (section 2, eq. Arect / Table 1). */
+int mlba_apply_A(mlba_plan_t plan, const float* u, float* y, hipStream_t stream);
+/* r = g - A u.  g, r: device n x n, u: device N x N. */
+int mlba_residual(mlba_plan_t plan, const float* g, const float* u, float* r, hipStream_t stream);
+/* w = A^T y.  y: device n x n, w: device N x N (section 2.1: A^T = A_big^T M^T;
+ * for imposed boundaries the exact transpose of the padding). */
+int mlba_apply_At(mlba_plan_t plan, const float* y, float* w, hipStream_t stream);
+/* t = P_alpha r.  r, t: device n x n, may alias (section 4, Algorithms 1 / 3). */
+int mlba_apply_P(mlba_plan_t plan, const float* r, float* t, double alpha, hipStream_t stream);
+/* z = W f.  f: device N x N, z: device [bands][N][N] (section 6.1). */
+int mlba_framelet_analysis(mlba_plan_t plan, const float* f, float* z, hipStream_t stream);
+/* z += W w: the Bregman update of eq. (MLBA2).  w: device N x N. */
+int mlba_analysis_update(mlba_plan_t plan, const float* w, float* z, hipStream_t stream);
+/* f = W^T z.  z: device [bands][N][N], f: device N x N. */
+int mlba_framelet_synthesis(mlba_plan_t plan, const float* z, float* f, hipStream_t stream);
+/* f = W^T (delta S_mu(z)): threshold fused into synthesis (eqs. soft, MLBA2).
+ * mu: host, n_mu = 1 or bands values. */
+int mlba_threshold_synthesis(mlba_plan_t plan, const float* z, const double* mu, int n_mu,
+                             double delta, float* f, hipStream_t stream);
+/* x = delta S_mu(z) over `bands` planes of `band_elems` elements (eq. soft).
+ * z, x: device, may alias.  mu: host, n_mu = 1 or `bands` values (<= 64). */
+int mlba_soft_threshold(const float* z, float* x, int bands, size_t band_elems,
+                        const double* mu, int n_mu, double delta, hipStream_t stream);
+
+/* ---- restoration --------------------------------------------------------
+ * Runs params->iters iterations of eq. (MLBA2) from the state z_state
+ * (device [bands][N][N], in/out; pass NULL to start from z = 0 in the plan's
+ * own state buffer) and writes f_out = W^T(delta_K S_mu(z^K)) (device N x N).
+ * g: device n x n.  rnorm_out: optional host array receiving ||r^k|| for each
+ * iteration run (synchronous copy at the end).  iters_done: optional host
+ * int receiving the number of iterations run (smaller than iters only when
+ * the discrepancy stop fired).  Returns MLBA_WARN_DIVERGED when a residual
+ * norm was non-finite or exceeded 1e3 times the first one (rnorm is then
+ * always computed); otherwise the call is asynchronous unless rnorm_out,
+ * iters_done, params->stop or an automatic delta is requested. */
+int mlba_restore(mlba_plan_t plan, const float* g, const mlba_params* params,
+                 float* f_out, float* z_state, double* rnorm_out, int* iters_done,
+                 hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLBA_H */

@@ -81,7 +81,7 @@ def delta_table(H, n, bc, precond, alphas, delta: float, count: int) -> np.ndarr
     for k in range(count):
         a = float(alphas[min(k, len(alphas) - 1)])
         if a not in cache:
-            cache[a] = delta_auto(opnorm(H, n, bc, precond, a))
+            cache[a] = delta_auto(opnorm(H, n, bc, precond, a, tol=1e-4))
         out[k] = cache[a]
     return out
 

@@ -1,0 +1,97 @@
+"""ctypes declarations of the C ABI in include/mlba.h.
+
+Loading fails loudly when the library has not been built: there is no
+fallback implementation anywhere in this package.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmlba.so")
+
+# status codes
+OK, WARN_DIVERGED, EINVAL, EUNSUPPORTED, EHIP, ENOMEM = 0, 1, -1, -2, -3, -4
+# boundary models / preconditioners / schedules
+BC_RECT, BC_REFLECT, BC_PERIODIC, BC_ZERO = 0, 1, 2, 3
+PRECOND_BCCB, PRECOND_DCT, PRECOND_NONE = 0, 1, 2
+ALPHA_CONST, ALPHA_GEOMETRIC, ALPHA_TABLE = 0, 1, 2
+
+c_int, c_double, c_size_t, c_void_p = ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
+c_dbl_p = ctypes.POINTER(ctypes.c_double)
+c_int_p = ctypes.POINTER(ctypes.c_int)
+
+
+class AlphaSchedule(ctypes.Structure):
+    _fields_ = [("kind", c_int), ("alpha0", c_double), ("ratio", c_double), ("alpha_floor", c_double),
+                ("table", c_dbl_p), ("table_len", c_int)]
+
+
+class Stop(ctypes.Structure):
+    _fields_ = [("noise_norm", c_double), ("gamma", c_double), ("check_every", c_int)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("alpha", AlphaSchedule), ("mu", c_dbl_p), ("n_mu", c_int), ("delta", c_double),
+                ("delta_table", c_dbl_p), ("iters", c_int), ("k0", c_int),
+                ("stop", ctypes.POINTER(Stop))]
+
+
+# name -> (restype, argtypes); every symbol declared in include/mlba.h
+SIGNATURES = {
+    "mlba_status_string": (ctypes.c_char_p, [c_int]),
+    "mlba_last_hip_error": (c_int, []),
+    "mlba_version": (c_int, []),
+    "mlba_plan_create": (c_int, [ctypes.POINTER(c_void_p), c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p]),
+    "mlba_plan_set_psf": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "mlba_plan_destroy": (c_int, [c_void_p]),
+    "mlba_plan_dims": (c_int, [c_void_p, c_int_p, c_int_p, c_int_p, c_int_p]),
+    "mlba_plan_opnorm": (c_int, [c_void_p, c_double, c_int, c_dbl_p, c_void_p]),
+    "mlba_apply_A": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "mlba_residual": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "mlba_apply_At": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "mlba_apply_P": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_void_p]),
+    "mlba_framelet_analysis": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "mlba_analysis_update": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "mlba_framelet_synthesis": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "mlba_threshold_synthesis": (c_int, [c_void_p, c_void_p, c_dbl_p, c_int, c_double, c_void_p, c_void_p]),
+    "mlba_soft_threshold": (c_int, [c_void_p, c_void_p, c_int, c_size_t, c_dbl_p, c_int, c_double, c_void_p]),
+    "mlba_restore": (c_int, [c_void_p, c_void_p, ctypes.POINTER(Params), c_void_p, c_void_p, c_dbl_p, c_int_p,
+                             c_void_p]),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libmlba.so and declare every entry point."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1504_07234_amd.build` "
+                           "(or __graft_entry__.build()); there is no fallback implementation")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class MLBAError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = load()
+        msg = lib.mlba_status_string(status).decode()
+        if status == EHIP:
+            msg += f" (hipError {lib.mlba_last_hip_error()})"
+        super().__init__(f"{where}: {msg} [{status}]")
+        self.status = status
+
+
+def check(status: int, where: str) -> int:
+    if status < 0:
+        raise MLBAError(status, where)
+    return status

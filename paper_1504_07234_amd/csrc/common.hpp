@@ -1,0 +1,71 @@
+// Shared device helpers for the MLBA library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mlba {
+
+constexpr int kBlock = 256;  // threads per workgroup for every kernel here
+
+// Boundary extension applied when a kernel reads outside [0, S):
+//   EXT_ZERO     value 0
+//   EXT_REFLECT  half-sample mirror, position x -> s or 2S-1-s, s = x mod 2S
+//   EXT_PERIODIC position x -> x mod S
+enum Ext : int { EXT_ZERO = 0, EXT_REFLECT = 1, EXT_PERIODIC = 2 };
+
+__device__ __forceinline__ int mod_pos(int x, int m) {
+    int r = x % m;
+    return r < 0 ? r + m : r;
+}
+
+// Reflected index; *flipped is set when the position lands on a mirrored copy.
+__device__ __forceinline__ int reflect_index(int x, int S, bool* flipped) {
+    int s = mod_pos(x, 2 * S);
+    *flipped = s >= S;
+    return *flipped ? 2 * S - 1 - s : s;
+}
+
+__device__ __forceinline__ int reflect_index(int x, int S) {
+    int s = mod_pos(x, 2 * S);
+    return s >= S ? 2 * S - 1 - s : s;
+}
+
+// Read src[y][x] of an S x S image under extension `ext`.
+__device__ __forceinline__ float fetch_ext(const float* __restrict__ src, int S, int y, int x, int ext) {
+    if (y >= 0 && y < S && x >= 0 && x < S) return src[(size_t)y * S + x];
+    if (ext == EXT_ZERO) return 0.0f;
+    if (ext == EXT_PERIODIC) return src[(size_t)mod_pos(y, S) * S + mod_pos(x, S)];
+    return src[(size_t)reflect_index(y, S) * S + reflect_index(x, S)];
+}
+
+// Soft threshold of eq. (soft), scaled: delta * sgn(v) * max(|v| - mu, 0).
+// A tie |v| == mu gives 0.
+__device__ __forceinline__ float shrink(float v, float mu, float delta) {
+    float a = fabsf(v) - mu;
+    return a > 0.0f ? copysignf(a * delta, v) : 0.0f;
+}
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// Wave-level then workgroup-level sum of a double (blockDim.x == kBlock).
+__device__ __forceinline__ double block_sum(double v, double* smem /* >= kBlock/64 */) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) smem[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += smem[i];
+    }
+    __syncthreads();
+    return t;  // valid in thread 0
+}
+
+}  // namespace mlba

@@ -1,0 +1,527 @@
+// Spectral Tikhonov preconditioners (paper section 4):
+//   Algorithm 1: P r = F^-1[ F r / (|Lambda|^2 + alpha) ]   (2-D DFT, BCCB C)
+//   Algorithm 3: P r = C2^T[ C2 r / (lambda^2 + alpha) ]     (2-D DCT-II, Q of the
+//                symmetrised PSF)
+//
+// Both are three passes over an n x n image:
+//   1. rows: two real rows are packed into one complex sequence, transformed
+//      in LDS and split; the result is written transposed (frequency-major), so
+//   2. columns become contiguous: forward transform, multiply by the
+//      spectral filter, inverse transform, all in LDS in one kernel;
+//   3. rows: gather transposed, inverse transform, write rows.
+//
+// The complex FFT is a mixed-radix (8, 4, 2, 3) Stockham autosort transform
+// held in LDS; every thread carries up to 16 complex values per stage in
+// registers between the read and the write barrier.  Twiddles come from a
+// table of exp(-2 pi i q / n) computed in double precision on the host.
+// The DCT-II of length n is computed from a length-n complex FFT of the even
+// samples followed by the reversed odd samples, with a quarter-sample
+// post-twiddle (Makhoul's reordering); DCT-III inverts those steps.
+// All transforms here are unnormalised; the filter carries the 1/n^2.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mlba {
+
+constexpr int FFT_EPT = 16;  // complex values per thread per stage (max)
+constexpr int FFT_MAX_ELEMS = FFT_EPT * kBlock;  // complex values per workgroup (32 KB of LDS)
+
+template <int DIR>
+__device__ __forceinline__ float2 twiddle(const float2* __restrict__ tw, int q) {
+    const float2 w = tw[q];
+    return DIR < 0 ? w : make_float2(w.x, -w.y);
+}
+
+// a * (DIR i)
+template <int DIR>
+__device__ __forceinline__ float2 mul_i(float2 a) {
+    return DIR < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft4(float2* v) {
+    const float2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    const float2 s13 = cadd(v[1], v[3]), d13 = mul_i<DIR>(csub(v[1], v[3]));
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, d13);
+    v[3] = csub(d02, d13);
+}
+
+template <int R, int DIR>
+__device__ __forceinline__ void dft(float2* v) {
+    if constexpr (R == 2) {
+        const float2 t = v[0];
+        v[0] = cadd(t, v[1]);
+        v[1] = csub(t, v[1]);
+    } else if constexpr (R == 3) {
+        const float s3 = 0.86602540378443865f;  // sqrt(3)/2
+        const float2 t = cadd(v[1], v[2]);
+        const float2 d = cscale(mul_i<DIR>(csub(v[1], v[2])), s3);
+        const float2 m = make_float2(v[0].x - 0.5f * t.x, v[0].y - 0.5f * t.y);
+        v[0] = cadd(v[0], t);
+        v[1] = cadd(m, d);
+        v[2] = csub(m, d);
+    } else if constexpr (R == 4) {
+        dft4<DIR>(v);
+    } else {  // R == 8: two length-4 transforms and the eighth-root twiddles
+        float2 e[4] = {v[0], v[2], v[4], v[6]};
+        float2 o[4] = {v[1], v[3], v[5], v[7]};
+        dft4<DIR>(e);
+        dft4<DIR>(o);
+        const float h = 0.70710678118654752f;
+        const float sg = (float)DIR;
+        const float2 o1 = make_float2(h * (o[1].x - sg * o[1].y), h * (o[1].y + sg * o[1].x));
+        const float2 o2 = mul_i<DIR>(o[2]);
+        const float2 o3 = make_float2(h * (-o[3].x - sg * o[3].y), h * (-o[3].y + sg * o[3].x));
+        v[0] = cadd(e[0], o[0]);
+        v[4] = csub(e[0], o[0]);
+        v[1] = cadd(e[1], o1);
+        v[5] = csub(e[1], o1);
+        v[2] = cadd(e[2], o2);
+        v[6] = csub(e[2], o2);
+        v[3] = cadd(e[3], o3);
+        v[7] = csub(e[3], o3);
+    }
+}
+
+// One Stockham stage of radix R over `batch` sequences of length n stored
+// back to back in `buf`.  Ns is the product of the radices already applied.
+template <int R, int DIR>
+__device__ __forceinline__ void stockham_stage(float2* buf, int n, int batch, int Ns,
+                                               const float2* __restrict__ tw) {
+    constexpr int MAXB = (FFT_EPT + R - 1) / R;
+    const int nb = n / R;
+    const int total = nb * batch;
+    const int step = n / (Ns * R);
+    float2 v[MAXB][R];
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int t = threadIdx.x + i * kBlock;
+        if (t < total) {
+            const int b = t / nb;
+            const int j = t - b * nb;
+            const int jm = j % Ns;
+            const float2* src = buf + b * n + j;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float2 x = src[r * nb];
+                if (r > 0) x = cmul(x, twiddle<DIR>(tw, r * jm * step));
+                v[i][r] = x;
+            }
+            dft<R, DIR>(v[i]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int t = threadIdx.x + i * kBlock;
+        if (t < total) {
+            const int b = t / nb;
+            const int j = t - b * nb;
+            const int jm = j % Ns;
+            float2* dst = buf + b * n + (j - jm) * R + jm;
+#pragma unroll
+            for (int r = 0; r < R; ++r) dst[r * Ns] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+// In-LDS transform of `batch` sequences; DIR = -1 forward, +1 inverse
+// (unnormalised).  The caller synchronises before the call.
+template <int DIR>
+__device__ void lds_fft(float2* buf, const FftDesc& fd, int batch, const float2* __restrict__ tw) {
+    int Ns = 1;
+    for (int s = 0; s < fd.nst; ++s) {
+        const int R = fd.radix[s];
+        if (R == 8) stockham_stage<8, DIR>(buf, fd.n, batch, Ns, tw);
+        else if (R == 4) stockham_stage<4, DIR>(buf, fd.n, batch, Ns, tw);
+        else if (R == 2) stockham_stage<2, DIR>(buf, fd.n, batch, Ns, tw);
+        else stockham_stage<3, DIR>(buf, fd.n, batch, Ns, tw);
+        Ns *= R;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// BCCB (Algorithm 1)
+// ---------------------------------------------------------------------------
+
+// G row pairs per workgroup -> T[k][row], k = 0..n/2 (row stride n complex)
+__global__ __launch_bounds__(kBlock) void fft_rows_r2c_kernel(const float* __restrict__ src, int n,
+                                                              float2* __restrict__ T, FftDesc fd,
+                                                              const float2* __restrict__ tw, int G) {
+    extern __shared__ float2 buf[];
+    const int row0 = blockIdx.x * 2 * G;
+    for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
+        const int g = idx / n;
+        const int x = idx - g * n;
+        const size_t ra = (size_t)(row0 + 2 * g) * n;
+        buf[idx] = make_float2(src[ra + x], src[ra + n + x]);
+    }
+    __syncthreads();
+    lds_fft<-1>(buf, fd, G, tw);
+    const int half = n / 2 + 1;
+    for (int idx = threadIdx.x; idx < G * half; idx += kBlock) {
+        const int k = idx / G;
+        const int g = idx - k * G;
+        const float2 Z = buf[g * n + k];
+        const float2 Zc = cconj(buf[g * n + (k == 0 ? 0 : n - k)]);
+        const float2 Xa = cscale(cadd(Z, Zc), 0.5f);
+        const float2 D = csub(Z, Zc);
+        const float2 Xb = make_float2(0.5f * D.y, -0.5f * D.x);  // D / (2i)
+        *reinterpret_cast<float4*>(T + (size_t)k * n + row0 + 2 * g) = make_float4(Xa.x, Xa.y, Xb.x, Xb.y);
+    }
+}
+
+// CC rows of T per workgroup: forward FFT along the column index, then either
+// the filter inv / (spec + alpha) and the inverse FFT (mode 0), or |.|^2 into
+// `power` (mode 1).
+__global__ __launch_bounds__(kBlock) void fft_cols_kernel(float2* __restrict__ T, int n,
+                                                          const float* __restrict__ spec, float alpha,
+                                                          float inv, FftDesc fd,
+                                                          const float2* __restrict__ tw, int CC, int mode,
+                                                          float* __restrict__ power) {
+    extern __shared__ float2 buf[];
+    const int half = n / 2 + 1;
+    const int k0 = blockIdx.x * CC;
+    const int cc = min(CC, half - k0);
+    const size_t base = (size_t)k0 * n;
+    for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) buf[idx] = T[base + idx];
+    __syncthreads();
+    lds_fft<-1>(buf, fd, cc, tw);
+    if (mode == 1) {
+        for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
+            const float2 v = buf[idx];
+            power[base + idx] = v.x * v.x + v.y * v.y;
+        }
+        return;
+    }
+    for (int idx = threadIdx.x; idx < cc * n; idx += kBlock)
+        buf[idx] = cscale(buf[idx], inv / (spec[base + idx] + alpha));
+    __syncthreads();
+    lds_fft<1>(buf, fd, cc, tw);
+    for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) T[base + idx] = buf[idx];
+}
+
+__global__ __launch_bounds__(kBlock) void fft_rows_c2r_kernel(const float2* __restrict__ T, int n,
+                                                              float* __restrict__ dst, FftDesc fd,
+                                                              const float2* __restrict__ tw, int G) {
+    extern __shared__ float2 buf[];
+    const int row0 = blockIdx.x * 2 * G;
+    const int half = n / 2 + 1;
+    for (int idx = threadIdx.x; idx < G * half; idx += kBlock) {
+        const int k = idx / G;
+        const int g = idx - k * G;
+        const float4 q = *reinterpret_cast<const float4*>(T + (size_t)k * n + row0 + 2 * g);
+        float2 Xa = make_float2(q.x, q.y), Xb = make_float2(q.z, q.w);
+        const bool edge = (k == 0) || (2 * k == n);
+        if (edge) {  // spectra of real rows are real at DC and Nyquist
+            Xa.y = 0.0f;
+            Xb.y = 0.0f;
+        }
+        buf[g * n + k] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);  // Xa + i Xb
+        if (!edge) buf[g * n + n - k] = make_float2(Xa.x + Xb.y, -Xa.y + Xb.x);  // conj(Xa) + i conj(Xb)
+    }
+    __syncthreads();
+    lds_fft<1>(buf, fd, G, tw);
+    for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
+        const int g = idx / n;
+        const int x = idx - g * n;
+        const size_t ra = (size_t)(row0 + 2 * g) * n;
+        const float2 v = buf[idx];
+        dst[ra + x] = v.x;
+        dst[ra + n + x] = v.y;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// DCT (Algorithm 3)
+// ---------------------------------------------------------------------------
+
+// position of sample l in the reordered sequence (evens ascending, odds descending)
+__device__ __forceinline__ int dct_perm(int l, int n) { return (l & 1) ? n - 1 - (l >> 1) : (l >> 1); }
+
+__device__ __forceinline__ float re_mul(float2 w, float2 v) { return w.x * v.x - w.y * v.y; }
+
+// G row pairs -> Tr[k][row] (real, row stride n), k = 0..n-1
+__global__ __launch_bounds__(kBlock) void dct_rows_fwd_kernel(const float* __restrict__ src, int n,
+                                                              float* __restrict__ Tr, FftDesc fd,
+                                                              const float2* __restrict__ tw,
+                                                              const float2* __restrict__ dtw, int G) {
+    extern __shared__ float2 buf[];
+    const int row0 = blockIdx.x * 2 * G;
+    for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
+        const int g = idx / n;
+        const int x = idx - g * n;
+        const size_t ra = (size_t)(row0 + 2 * g) * n;
+        buf[g * n + dct_perm(x, n)] = make_float2(src[ra + x], src[ra + n + x]);
+    }
+    __syncthreads();
+    lds_fft<-1>(buf, fd, G, tw);
+    for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
+        const int k = idx / G;
+        const int g = idx - k * G;
+        const float2 Z = buf[g * n + k];
+        const float2 Zc = cconj(buf[g * n + (k == 0 ? 0 : n - k)]);
+        const float2 Va = cscale(cadd(Z, Zc), 0.5f);
+        const float2 D = csub(Z, Zc);
+        const float2 Vb = make_float2(0.5f * D.y, -0.5f * D.x);
+        const float2 w = dtw[k];
+        *reinterpret_cast<float2*>(Tr + (size_t)k * n + row0 + 2 * g) = make_float2(re_mul(w, Va), re_mul(w, Vb));
+    }
+}
+
+// CP pairs of Tr rows per workgroup: DCT-II along the row, multiply by
+// inv / (spec + alpha), DCT-III back.
+__global__ __launch_bounds__(kBlock) void dct_cols_filter_kernel(float* __restrict__ Tr, int n,
+                                                                 const float* __restrict__ spec, float alpha,
+                                                                 float inv, FftDesc fd,
+                                                                 const float2* __restrict__ tw,
+                                                                 const float2* __restrict__ dtw, int CP) {
+    extern __shared__ float2 buf[];
+    const int pairs = n / 2;
+    const int p0 = blockIdx.x * CP;
+    const int cp = min(CP, pairs - p0);
+    const int total = cp * n;
+    for (int idx = threadIdx.x; idx < total; idx += kBlock) {
+        const int q = idx / n;
+        const int l = idx - q * n;
+        const size_t r1 = (size_t)(2 * (p0 + q)) * n;
+        buf[q * n + dct_perm(l, n)] = make_float2(Tr[r1 + l], Tr[r1 + n + l]);
+    }
+    __syncthreads();
+    lds_fft<-1>(buf, fd, cp, tw);
+
+    float2 keep[FFT_EPT];
+#pragma unroll
+    for (int i = 0; i < FFT_EPT; ++i) {
+        const int idx = threadIdx.x + i * kBlock;
+        if (idx < total) {
+            const int q = idx / n;
+            const int l = idx - q * n;
+            const float2 Z = buf[q * n + l];
+            const float2 Zc = cconj(buf[q * n + (l == 0 ? 0 : n - l)]);
+            const float2 V1 = cscale(cadd(Z, Zc), 0.5f);
+            const float2 D = csub(Z, Zc);
+            const float2 V2 = make_float2(0.5f * D.y, -0.5f * D.x);
+            const float2 w = dtw[l];
+            const size_t r1 = (size_t)(2 * (p0 + q)) * n;
+            const float f1 = inv / (spec[r1 + l] + alpha);
+            const float f2 = inv / (spec[r1 + n + l] + alpha);
+            keep[i] = make_float2(re_mul(w, V1) * f1, re_mul(w, V2) * f2);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < FFT_EPT; ++i) {
+        const int idx = threadIdx.x + i * kBlock;
+        if (idx < total) buf[idx] = keep[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < FFT_EPT; ++i) {
+        const int idx = threadIdx.x + i * kBlock;
+        if (idx < total) {
+            const int q = idx / n;
+            const int l = idx - q * n;
+            const float2 Y = buf[q * n + l];
+            const float2 Yr = (l == 0) ? make_float2(0.0f, 0.0f) : buf[q * n + n - l];
+            const float2 wc = cconj(dtw[l]);
+            const float2 V1 = cmul(wc, make_float2(Y.x, -Yr.x));
+            const float2 V2 = cmul(wc, make_float2(Y.y, -Yr.y));
+            keep[i] = make_float2(V1.x - V2.y, V1.y + V2.x);  // V1 + i V2
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < FFT_EPT; ++i) {
+        const int idx = threadIdx.x + i * kBlock;
+        if (idx < total) buf[idx] = keep[i];
+    }
+    __syncthreads();
+    lds_fft<1>(buf, fd, cp, tw);
+    for (int idx = threadIdx.x; idx < total; idx += kBlock) {
+        const int q = idx / n;
+        const int l = idx - q * n;
+        const size_t r1 = (size_t)(2 * (p0 + q)) * n;
+        const float2 v = buf[q * n + dct_perm(l, n)];
+        Tr[r1 + l] = v.x;
+        Tr[r1 + n + l] = v.y;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void dct_rows_inv_kernel(const float* __restrict__ Tr, int n,
+                                                              float* __restrict__ dst, FftDesc fd,
+                                                              const float2* __restrict__ tw,
+                                                              const float2* __restrict__ dtw, int G) {
+    extern __shared__ float2 buf[];
+    const int row0 = blockIdx.x * 2 * G;
+    const int total = G * n;
+    for (int idx = threadIdx.x; idx < total; idx += kBlock) {
+        const int k = idx / G;
+        const int g = idx - k * G;
+        buf[g * n + k] = *reinterpret_cast<const float2*>(Tr + (size_t)k * n + row0 + 2 * g);
+    }
+    __syncthreads();
+    float2 keep[FFT_EPT];
+#pragma unroll
+    for (int i = 0; i < FFT_EPT; ++i) {
+        const int idx = threadIdx.x + i * kBlock;
+        if (idx < total) {
+            const int g = idx / n;
+            const int k = idx - g * n;
+            const float2 Y = buf[g * n + k];
+            const float2 Yr = (k == 0) ? make_float2(0.0f, 0.0f) : buf[g * n + n - k];
+            const float2 wc = cconj(dtw[k]);
+            const float2 Va = cmul(wc, make_float2(Y.x, -Yr.x));
+            const float2 Vb = cmul(wc, make_float2(Y.y, -Yr.y));
+            keep[i] = make_float2(Va.x - Vb.y, Va.y + Vb.x);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < FFT_EPT; ++i) {
+        const int idx = threadIdx.x + i * kBlock;
+        if (idx < total) buf[idx] = keep[i];
+    }
+    __syncthreads();
+    lds_fft<1>(buf, fd, G, tw);
+    for (int idx = threadIdx.x; idx < total; idx += kBlock) {
+        const int g = idx / n;
+        const int x = idx - g * n;
+        const size_t ra = (size_t)(row0 + 2 * g) * n;
+        const float2 v = buf[g * n + dct_perm(x, n)];
+        dst[ra + x] = v.x;
+        dst[ra + n + x] = v.y;
+    }
+}
+
+// lambda of the reflective blur of the symmetrised PSF:
+//   lambda[ky][kx] = sum_{a,b} H~[a][b] cos(pi ky (a-c)/n) cos(pi kx (b-c)/n)
+// written squared into spec[kx][ky]; costab[q] = cos(pi q / n), q < 2n.
+__global__ __launch_bounds__(kBlock) void dct_spectrum_kernel(const float* __restrict__ psf, int p, int n,
+                                                              float* __restrict__ spec,
+                                                              const float* __restrict__ costab) {
+    const int ky = blockIdx.x * kBlock + threadIdx.x;
+    const int kx = blockIdx.y;
+    if (ky >= n) return;
+    const int c = (p - 1) / 2;
+    const int n2 = 2 * n;
+    float acc = 0.0f;
+    for (int a = 0; a < p; ++a) {
+        const float cy = costab[mod_pos(ky * (a - c), n2)];
+        float row = 0.0f;
+        for (int b = 0; b < p; ++b) {
+            const float hs = 0.25f * (psf[a * p + b] + psf[(p - 1 - a) * p + b] + psf[a * p + (p - 1 - b)] +
+                                      psf[(p - 1 - a) * p + (p - 1 - b)]);
+            row += hs * costab[mod_pos(kx * (b - c), n2)];
+        }
+        acc += cy * row;
+    }
+    spec[(size_t)kx * n + ky] = acc * acc;
+}
+
+__global__ __launch_bounds__(kBlock) void pad_psf_kernel(const float* __restrict__ psf, int p,
+                                                         float* __restrict__ dst, int n) {
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= (size_t)n * n) return;
+    const int y = (int)(i / n), x = (int)(i % n);
+    dst[i] = (y < p && x < p) ? psf[y * p + x] : 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------
+
+static int pick_pairs_per_block(int n) {
+    // two rows per pair; stay within the LDS budget; keep >= ~512 workgroups
+    int target = n >= 2048 ? 2 : 1;
+    int G = 1;
+    while (G * 2 <= target && (G * 2) * n <= FFT_MAX_ELEMS && ((n / 2) % (G * 2)) == 0) G *= 2;
+    return G;
+}
+
+static int pick_cols_per_block(int n) {
+    int cc = 1024 / n;
+    if (cc < 1) cc = 1;
+    while (cc * n > FFT_MAX_ELEMS) cc /= 2;
+    return cc;
+}
+
+hipError_t launch_fft_rows_r2c(const float* src, int n, float2* T, const FftDesc& fd, const float2* tw,
+                               hipStream_t s) {
+    const int G = pick_pairs_per_block(n);
+    const size_t lds = (size_t)G * n * sizeof(float2);
+    hipLaunchKernelGGL(fft_rows_r2c_kernel, dim3(n / (2 * G)), dim3(kBlock), lds, s, src, n, T, fd, tw, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_cols_filter(float2* T, int n, const float* spec, float alpha, float inv, const FftDesc& fd,
+                                  const float2* tw, hipStream_t s) {
+    const int CC = pick_cols_per_block(n);
+    const int half = n / 2 + 1;
+    const size_t lds = (size_t)CC * n * sizeof(float2);
+    hipLaunchKernelGGL(fft_cols_kernel, dim3((half + CC - 1) / CC), dim3(kBlock), lds, s, T, n, spec, alpha,
+                       inv, fd, tw, CC, 0, (float*)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_cols_power(const float2* T, int n, float* spec, const FftDesc& fd, const float2* tw,
+                                 hipStream_t s) {
+    const int CC = pick_cols_per_block(n);
+    const int half = n / 2 + 1;
+    const size_t lds = (size_t)CC * n * sizeof(float2);
+    hipLaunchKernelGGL(fft_cols_kernel, dim3((half + CC - 1) / CC), dim3(kBlock), lds, s,
+                       const_cast<float2*>(T), n, (const float*)nullptr, 0.0f, 1.0f, fd, tw, CC, 1, spec);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_rows_c2r(const float2* T, int n, float* dst, const FftDesc& fd, const float2* tw,
+                               hipStream_t s) {
+    const int G = pick_pairs_per_block(n);
+    const size_t lds = (size_t)G * n * sizeof(float2);
+    hipLaunchKernelGGL(fft_rows_c2r_kernel, dim3(n / (2 * G)), dim3(kBlock), lds, s, T, n, dst, fd, tw, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_dct_rows_fwd(const float* src, int n, float* Tr, const FftDesc& fd, const float2* tw,
+                               const float2* dtw, hipStream_t s) {
+    const int G = pick_pairs_per_block(n);
+    const size_t lds = (size_t)G * n * sizeof(float2);
+    hipLaunchKernelGGL(dct_rows_fwd_kernel, dim3(n / (2 * G)), dim3(kBlock), lds, s, src, n, Tr, fd, tw, dtw, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_dct_cols_filter(float* Tr, int n, const float* spec, float alpha, float inv, const FftDesc& fd,
+                                  const float2* tw, const float2* dtw, hipStream_t s) {
+    int CP = pick_cols_per_block(n);
+    const int pairs = n / 2;
+    const size_t lds = (size_t)CP * n * sizeof(float2);
+    hipLaunchKernelGGL(dct_cols_filter_kernel, dim3((pairs + CP - 1) / CP), dim3(kBlock), lds, s, Tr, n, spec,
+                       alpha, inv, fd, tw, dtw, CP);
+    return hipGetLastError();
+}
+
+hipError_t launch_dct_rows_inv(const float* Tr, int n, float* dst, const FftDesc& fd, const float2* tw,
+                               const float2* dtw, hipStream_t s) {
+    const int G = pick_pairs_per_block(n);
+    const size_t lds = (size_t)G * n * sizeof(float2);
+    hipLaunchKernelGGL(dct_rows_inv_kernel, dim3(n / (2 * G)), dim3(kBlock), lds, s, Tr, n, dst, fd, tw, dtw, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_dct_spectrum(const float* psf, int p, int n, float* spec, const float* costab, hipStream_t s) {
+    dim3 grid((n + kBlock - 1) / kBlock, n);
+    hipLaunchKernelGGL(dct_spectrum_kernel, grid, dim3(kBlock), 0, s, psf, p, n, spec, costab);
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_psf(const float* psf, int p, float* dst, int n, hipStream_t s) {
+    const size_t tot = (size_t)n * n;
+    hipLaunchKernelGGL(pad_psf_kernel, dim3((unsigned)((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, psf, p,
+                       dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace mlba

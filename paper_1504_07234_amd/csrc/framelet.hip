@@ -1,0 +1,235 @@
+// Undecimated linear B-spline framelet, one level per launch (paper section
+// 6.1).  Masks at offsets (-d, 0, +d):
+//   b0 = (1/4, 1/2, 1/4),  b1 = (-sqrt2/4, 0, sqrt2/4),  b2 = (-1/4, 1/2, -1/4)
+// (b1 oriented as the rows of the matrix printed in section 6.1).  Band (i,j)
+// applies b_i along x and b_j along y under half-sample reflective extension.
+//
+// Data layout: one thread per column of a 16-row strip.  A workgroup covers
+// 256 - 2d output columns plus a d-column halo on each side; every thread
+// streams its column (16 + 2d rows, coalesced across the wavefront) through
+// registers, applies the y-direction filters there, parks the three
+// y-filtered columns in LDS, and after one barrier applies the x-direction
+// filters from LDS for the interior columns.
+//
+// The transpose (synthesis) uses the fact that for a symmetric mask the
+// reflective operator's transpose is the mirrored mask applied to the
+// symmetrically extended input, while for the antisymmetric mask b1 the
+// input must be extended antisymmetrically (its mirrored copies change
+// sign).  The soft threshold of eq. (soft) is applied to each coefficient as
+// it is loaded.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mlba {
+
+constexpr int FR_TY = 16;
+constexpr float kB1 = 0.35355339059327376f;  // sqrt(2) / 4
+
+// pair (i, j) != (0, 0) -> position in the level's band block
+__host__ __device__ constexpr int pair_slot(int i, int j) { return i * 3 + j - 1; }
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void analysis_level_kernel(const float* __restrict__ v, int N,
+                                                                float* __restrict__ zlev,
+                                                                float* __restrict__ low,
+                                                                int accum_bands, int accum_low) {
+    constexpr int IW = kBlock - 2 * D;
+    __shared__ float gy[3][FR_TY][kBlock];
+    const int x0 = blockIdx.x * IW;
+    const int y0 = blockIdx.y * FR_TY;
+    const int c = threadIdx.x;
+    const int gx = reflect_index(x0 - D + c, N);
+
+    float col[FR_TY + 2 * D];
+#pragma unroll
+    for (int q = 0; q < FR_TY + 2 * D; ++q) col[q] = v[(size_t)reflect_index(y0 - D + q, N) * N + gx];
+#pragma unroll
+    for (int r = 0; r < FR_TY; ++r) {
+        const float a = col[r], b = col[r + D], e = col[r + 2 * D];  // v[y-d], v[y], v[y+d]
+        gy[0][r][c] = 0.25f * a + 0.5f * b + 0.25f * e;
+        gy[1][r][c] = kB1 * (e - a);
+        gy[2][r][c] = -0.25f * a + 0.5f * b - 0.25f * e;
+    }
+    __syncthreads();
+
+    if (c < D || c >= kBlock - D) return;
+    const int x = x0 + c - D;
+    if (x >= N) return;
+    const size_t NN = (size_t)N * N;
+    for (int r = 0; r < FR_TY; ++r) {
+        const int y = y0 + r;
+        if (y >= N) break;
+        const size_t o = (size_t)y * N + x;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const float l = gy[j][r][c - D], m = gy[j][r][c], rr = gy[j][r][c + D];
+            const float h0 = 0.25f * l + 0.5f * m + 0.25f * rr;
+            const float h1 = kB1 * (rr - l);
+            const float h2 = -0.25f * l + 0.5f * m - 0.25f * rr;
+            if (j == 0) {
+                if (accum_low) low[o] += h0; else low[o] = h0;
+            } else {
+                float* p0 = zlev + pair_slot(0, j) * NN + o;
+                if (accum_bands) *p0 += h0; else *p0 = h0;
+            }
+            float* p1 = zlev + pair_slot(1, j) * NN + o;
+            float* p2 = zlev + pair_slot(2, j) * NN + o;
+            if (accum_bands) {
+                *p1 += h1;
+                *p2 += h2;
+            } else {
+                *p1 = h1;
+                *p2 = h2;
+            }
+        }
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void synthesis_level_kernel(const float* __restrict__ zlev,
+                                                                 const float* __restrict__ low, int N,
+                                                                 float* __restrict__ out, LevelMu mu,
+                                                                 float delta, int thr_low, int thr_bands) {
+    constexpr int IW = kBlock - 2 * D;
+    __shared__ float ys[3][FR_TY][kBlock];
+    const int x0 = blockIdx.x * IW;
+    const int y0 = blockIdx.y * FR_TY;
+    const int c = threadIdx.x;
+    bool fx;
+    const int gx = reflect_index(x0 - D + c, N, &fx);
+    const size_t NN = (size_t)N * N;
+
+    // rows of the strip with halo, and whether each is a mirrored copy
+    int rowi[FR_TY + 2 * D];
+    bool rowf[FR_TY + 2 * D];
+#pragma unroll
+    for (int q = 0; q < FR_TY + 2 * D; ++q) {
+        bool f;
+        rowi[q] = reflect_index(y0 - D + q, N, &f);
+        rowf[q] = f;
+    }
+
+    float acc[3][FR_TY];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int r = 0; r < FR_TY; ++r) acc[i][r] = 0.0f;
+
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const bool is_low = (i == 0 && j == 0);
+            const float* src = is_low ? low : zlev + pair_slot(i, j) * NN;
+            const bool thr = is_low ? (thr_low != 0) : (thr_bands != 0);
+            const float m = is_low ? mu.low : mu.band[pair_slot(i, j)];
+            const float sx = (i == 1 && fx) ? -1.0f : 1.0f;
+            float col[FR_TY + 2 * D];
+#pragma unroll
+            for (int q = 0; q < FR_TY + 2 * D; ++q) {
+                float val = src[(size_t)rowi[q] * N + gx];
+                if (thr) val = shrink(val, m, delta);
+                const float sy = (j == 1 && rowf[q]) ? -1.0f : 1.0f;
+                col[q] = sx * sy * val;
+            }
+            // transpose along y: sum_k b_j[k] w~[y - k d]
+#pragma unroll
+            for (int r = 0; r < FR_TY; ++r) {
+                const float wm = col[r], w0 = col[r + D], wp = col[r + 2 * D];  // y-d, y, y+d
+                if (j == 0) acc[i][r] += 0.25f * wp + 0.5f * w0 + 0.25f * wm;
+                else if (j == 1) acc[i][r] += kB1 * (wm - wp);
+                else acc[i][r] += -0.25f * wp + 0.5f * w0 - 0.25f * wm;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int r = 0; r < FR_TY; ++r) ys[i][r][c] = acc[i][r];
+    __syncthreads();
+
+    if (c < D || c >= kBlock - D) return;
+    const int x = x0 + c - D;
+    if (x >= N) return;
+    for (int r = 0; r < FR_TY; ++r) {
+        const int y = y0 + r;
+        if (y >= N) break;
+        // transpose along x: sum_i sum_k b_i[k] Y_i[x - k d]
+        float s = 0.0f;
+        {
+            const float l = ys[0][r][c - D], m = ys[0][r][c], rr = ys[0][r][c + D];
+            s += 0.25f * rr + 0.5f * m + 0.25f * l;
+        }
+        {
+            const float l = ys[1][r][c - D], rr = ys[1][r][c + D];
+            s += kB1 * (l - rr);
+        }
+        {
+            const float l = ys[2][r][c - D], m = ys[2][r][c], rr = ys[2][r][c + D];
+            s += -0.25f * rr + 0.5f * m - 0.25f * l;
+        }
+        out[(size_t)y * N + x] = s;
+    }
+}
+
+template <int D>
+static hipError_t launch_an(const float* v, int N, float* zlev, float* low, int ab, int al, hipStream_t s) {
+    constexpr int IW = kBlock - 2 * D;
+    dim3 grid((N + IW - 1) / IW, (N + FR_TY - 1) / FR_TY);
+    hipLaunchKernelGGL((analysis_level_kernel<D>), grid, dim3(kBlock), 0, s, v, N, zlev, low, ab, al);
+    return hipGetLastError();
+}
+
+hipError_t launch_analysis_level(const float* v, int N, int d, float* zlev, float* low, int accum_bands,
+                                 int accum_low, hipStream_t s) {
+    switch (d) {
+        case 1: return launch_an<1>(v, N, zlev, low, accum_bands, accum_low, s);
+        case 2: return launch_an<2>(v, N, zlev, low, accum_bands, accum_low, s);
+        case 4: return launch_an<4>(v, N, zlev, low, accum_bands, accum_low, s);
+        case 8: return launch_an<8>(v, N, zlev, low, accum_bands, accum_low, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int D>
+static hipError_t launch_syn(const float* zlev, const float* low, int N, float* out, LevelMu mu, float delta,
+                             int tl, int tb, hipStream_t s) {
+    constexpr int IW = kBlock - 2 * D;
+    dim3 grid((N + IW - 1) / IW, (N + FR_TY - 1) / FR_TY);
+    hipLaunchKernelGGL((synthesis_level_kernel<D>), grid, dim3(kBlock), 0, s, zlev, low, N, out, mu, delta,
+                       tl, tb);
+    return hipGetLastError();
+}
+
+hipError_t launch_synthesis_level(const float* zlev, const float* low, int N, int d, float* out, LevelMu mu,
+                                  float delta, int thr_low, int thr_bands, hipStream_t s) {
+    switch (d) {
+        case 1: return launch_syn<1>(zlev, low, N, out, mu, delta, thr_low, thr_bands, s);
+        case 2: return launch_syn<2>(zlev, low, N, out, mu, delta, thr_low, thr_bands, s);
+        case 4: return launch_syn<4>(zlev, low, N, out, mu, delta, thr_low, thr_bands, s);
+        case 8: return launch_syn<8>(zlev, low, N, out, mu, delta, thr_low, thr_bands, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void soft_threshold_kernel(const float* __restrict__ z,
+                                                                float* __restrict__ x, size_t band_elems,
+                                                                BandMu mu, float delta) {
+    const int b = blockIdx.y;
+    const size_t base = (size_t)b * band_elems;
+    const float m = mu.v[b];
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < band_elems; i += (size_t)gridDim.x * kBlock)
+        x[base + i] = shrink(z[base + i], m, delta);
+}
+
+hipError_t launch_soft_threshold(const float* z, float* x, int bands, size_t band_elems, BandMu mu,
+                                 float delta, hipStream_t s) {
+    size_t blocks = (band_elems + kBlock - 1) / kBlock;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks == 0) return hipSuccess;
+    dim3 grid((unsigned)blocks, bands);
+    hipLaunchKernelGGL(soft_threshold_kernel, grid, dim3(kBlock), 0, s, z, x, band_elems, mu, delta);
+    return hipGetLastError();
+}
+
+}  // namespace mlba

@@ -1,0 +1,93 @@
+// Internal launcher interface between the kernel translation units and the
+// C ABI implementation.  Every launcher enqueues on `s` and returns the
+// hipError_t of the launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+namespace mlba {
+
+// Mixed-radix plan of a length-n complex FFT (n = 2^a 3^b).
+struct FftDesc {
+    int n;
+    int nst;
+    int radix[24];
+};
+
+// Soft-threshold parameters of one framelet level: mu of the low-pass input
+// (used when it is thresholded) and mu of the eight detail bands.
+struct LevelMu {
+    float low;
+    float band[8];
+};
+
+struct BandMu {
+    float v[64];
+};
+
+// ---- blur (direct convolution) -------------------------------------------
+// dst[y][x] = (g ? g[y][x] - s : s),  s = sum_{a,b} K[a][b] src_ext[y+org+a][x+org+b]
+// with K = H rotated by 180 degrees (flip = 1, the blur A) or K = H
+// (flip = 0, the correlation of A^T).  src is S x S, dst is D x D.
+// partials (optional, needs g): one double per workgroup with sum of dst^2.
+hipError_t launch_conv(const float* src, int S, int ext, int org, float* dst, int D,
+                       const float* g, const float* psf, int p, int flip, double* partials,
+                       int* n_partials, hipStream_t s);
+int conv_partials_count(int D);
+
+// Transpose of the reflective padding: w[y][x] = sum of wext over the
+// positions of the (n+2c)^2 padded grid that copy pixel (y, x).
+hipError_t launch_fold_reflect(const float* wext, int m, float* w, int n, int c, hipStream_t s);
+
+// ---- framelet -----------------------------------------------------------
+// analysis level with dilation d: bands (+)= B_i B_j v, low (+)= B_0 B_0 v
+hipError_t launch_analysis_level(const float* v, int N, int d, float* zlev, float* low,
+                                 int accum_bands, int accum_low, hipStream_t s);
+// synthesis level with dilation d (transpose), optional threshold of inputs
+hipError_t launch_synthesis_level(const float* zlev, const float* low, int N, int d, float* out,
+                                  LevelMu mu, float delta, int thr_low, int thr_bands,
+                                  hipStream_t s);
+hipError_t launch_soft_threshold(const float* z, float* x, int bands, size_t band_elems,
+                                 BandMu mu, float delta, hipStream_t s);
+
+// ---- spectral preconditioner --------------------------------------------
+// BCCB: rows r2c -> T (half spectrum, transposed [n/2+1][n] complex)
+hipError_t launch_fft_rows_r2c(const float* src, int n, float2* T, const FftDesc& fd,
+                               const float2* tw, hipStream_t s);
+// columns: forward FFT, scale by inv / (spec + alpha), inverse FFT (in place)
+hipError_t launch_fft_cols_filter(float2* T, int n, const float* spec, float alpha, float inv,
+                                  const FftDesc& fd, const float2* tw, hipStream_t s);
+// columns: forward FFT, write spec = |.|^2 (same transposed layout)
+hipError_t launch_fft_cols_power(const float2* T, int n, float* spec, const FftDesc& fd,
+                                 const float2* tw, hipStream_t s);
+hipError_t launch_fft_rows_c2r(const float2* T, int n, float* dst, const FftDesc& fd,
+                               const float2* tw, hipStream_t s);
+// DCT: rows DCT-II -> Tr (transposed, real [n][n]); columns DCT-II, filter,
+// DCT-III; rows DCT-III -> dst.  Unnormalised transforms; `inv` carries 1/n^2.
+hipError_t launch_dct_rows_fwd(const float* src, int n, float* Tr, const FftDesc& fd,
+                               const float2* tw, const float2* dtw, hipStream_t s);
+hipError_t launch_dct_cols_filter(float* Tr, int n, const float* spec, float alpha, float inv,
+                                  const FftDesc& fd, const float2* tw, const float2* dtw,
+                                  hipStream_t s);
+hipError_t launch_dct_rows_inv(const float* Tr, int n, float* dst, const FftDesc& fd,
+                               const float2* tw, const float2* dtw, hipStream_t s);
+// spec[kx][ky] = lambda[ky][kx]^2 for the symmetrised PSF (Algorithm 3)
+hipError_t launch_dct_spectrum(const float* psf, int p, int n, float* spec, const float* costab,
+                               hipStream_t s);
+// place the PSF in the top-left corner of a zeroed n x n image
+hipError_t launch_pad_psf(const float* psf, int p, float* dst, int n, hipStream_t s);
+
+// ---- reductions and small helpers ---------------------------------------
+// out[0] = sum of partials[0..count) in a fixed order (double)
+hipError_t launch_sum_partials(const double* partials, int count, double* out, hipStream_t s);
+// partial sums of a*b over `count` floats (one double per workgroup); returns #partials
+hipError_t launch_dot_partials(const float* a, const float* b, size_t count, double* partials,
+                               int* n_partials, hipStream_t s);
+hipError_t launch_scale(float* x, size_t count, const double* inv_norm_sq_or_null, float factor,
+                        hipStream_t s);
+hipError_t launch_fill_hash(float* x, size_t count, unsigned seed, hipStream_t s);
+hipError_t launch_fill(float* x, size_t count, float value, hipStream_t s);
+int reduce_partials_cap();
+
+}  // namespace mlba

@@ -1,0 +1,587 @@
+// C ABI of the MLBA library: plans, per-operator entry points and the
+// restoration loop of eq. (MLBA2).  See include/mlba.h for the contract.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "mlba.h"
+
+using namespace mlba;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+#define HIPCHK(expr)                          \
+    do {                                      \
+        hipError_t e_ = (expr);               \
+        if (e_ != hipSuccess) {               \
+            g_last_hip = (int)e_;             \
+            return MLBA_EHIP;                 \
+        }                                     \
+    } while (0)
+
+#define STCHK(expr)              \
+    do {                         \
+        int st_ = (expr);        \
+        if (st_ < 0) return st_; \
+    } while (0)
+
+bool factor_23(int n, int* a, int* b) {
+    *a = 0;
+    *b = 0;
+    while (n % 2 == 0) {
+        n /= 2;
+        ++*a;
+    }
+    while (n % 3 == 0) {
+        n /= 3;
+        ++*b;
+    }
+    return n == 1;
+}
+
+}  // namespace
+
+struct mlba_plan_s {
+    int n = 0, p = 0, c = 0, N = 0, bc = 0, precond = 0, levels = 0, bands = 0;
+    FftDesc fd{};
+    float* psf = nullptr;
+    float* spec = nullptr;     // BCCB: [n/2+1][n] |Lambda|^2 (transposed); DCT: [n][n] lambda^2
+    float2* tw = nullptr;      // exp(-2 pi i q / n)
+    float2* dtw = nullptr;     // exp(-i pi k / (2n))
+    float* costab = nullptr;   // cos(pi q / n), q < 2n
+    void* swork = nullptr;     // spectral workspace
+    float* u = nullptr;        // N x N synthesis output
+    float* r = nullptr;        // n x n residual
+    float* t = nullptr;        // n x n preconditioned residual
+    float* w = nullptr;        // N x N A^T t
+    float* wext = nullptr;     // m x m full correlation (reflective boundary)
+    float* tmp[2] = {nullptr, nullptr};  // N x N level intermediates
+    float* pv = nullptr;       // N x N power-iteration vector
+    float* z = nullptr;        // [bands][N][N] state when the caller passes none
+    double* partials = nullptr;
+    int partials_cap = 0;
+    double* scal = nullptr;    // device scalars
+    double* rn = nullptr;      // ||r^k||^2 history ring
+    int rn_cap = 0;
+    std::vector<void*> allocs;
+};
+
+namespace {
+
+int dalloc(mlba_plan_s* P, void** ptr, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) {
+        g_last_hip = (int)e;
+        *ptr = nullptr;
+        return MLBA_ENOMEM;
+    }
+    P->allocs.push_back(*ptr);
+    return MLBA_OK;
+}
+
+template <class T>
+int dalloc_t(mlba_plan_s* P, T** ptr, size_t count) {
+    void* v = nullptr;
+    int st = dalloc(P, &v, count * sizeof(T));
+    *ptr = (T*)v;
+    return st;
+}
+
+void free_plan(mlba_plan_s* P) {
+    for (void* a : P->allocs) hipFree(a);
+    P->allocs.clear();
+    delete P;
+}
+
+size_t NN(const mlba_plan_s* P) { return (size_t)P->N * P->N; }
+
+int ext_of_bc(int bc) {
+    return bc == MLBA_BC_REFLECT ? EXT_REFLECT : (bc == MLBA_BC_PERIODIC ? EXT_PERIODIC : EXT_ZERO);
+}
+
+// r = g - A u (g may be null: y = A u); partial sums of r^2 into P->partials
+int do_blur(mlba_plan_s* P, const float* u, const float* g, float* y, bool want_norm, int* nparts,
+            hipStream_t s) {
+    const int org = P->bc == MLBA_BC_RECT ? 0 : -P->c;
+    HIPCHK(launch_conv(u, P->N, ext_of_bc(P->bc), org, y, P->n, g, P->psf, P->p, 1,
+                       want_norm ? P->partials : nullptr, nparts, s));
+    return MLBA_OK;
+}
+
+int do_blurT(mlba_plan_s* P, const float* y, float* w, hipStream_t s) {
+    switch (P->bc) {
+        case MLBA_BC_RECT:
+            HIPCHK(launch_conv(y, P->n, EXT_ZERO, -(P->p - 1), w, P->N, nullptr, P->psf, P->p, 0, nullptr,
+                               nullptr, s));
+            break;
+        case MLBA_BC_REFLECT: {
+            const int m = P->n + P->p - 1;
+            HIPCHK(launch_conv(y, P->n, EXT_ZERO, -(P->p - 1), P->wext, m, nullptr, P->psf, P->p, 0, nullptr,
+                               nullptr, s));
+            HIPCHK(launch_fold_reflect(P->wext, m, w, P->n, P->c, s));
+            break;
+        }
+        case MLBA_BC_PERIODIC:
+            HIPCHK(launch_conv(y, P->n, EXT_PERIODIC, -P->c, w, P->n, nullptr, P->psf, P->p, 0, nullptr, nullptr,
+                               s));
+            break;
+        default:
+            HIPCHK(launch_conv(y, P->n, EXT_ZERO, -P->c, w, P->n, nullptr, P->psf, P->p, 0, nullptr, nullptr, s));
+    }
+    return MLBA_OK;
+}
+
+int do_precond(mlba_plan_s* P, const float* r, float* t, double alpha, hipStream_t s) {
+    const int n = P->n;
+    const float inv = (float)(1.0 / ((double)n * (double)n));
+    if (P->precond == MLBA_PRECOND_BCCB) {
+        float2* T = (float2*)P->swork;
+        HIPCHK(launch_fft_rows_r2c(r, n, T, P->fd, P->tw, s));
+        HIPCHK(launch_fft_cols_filter(T, n, P->spec, (float)alpha, inv, P->fd, P->tw, s));
+        HIPCHK(launch_fft_rows_c2r(T, n, t, P->fd, P->tw, s));
+    } else if (P->precond == MLBA_PRECOND_DCT) {
+        float* Tr = (float*)P->swork;
+        HIPCHK(launch_dct_rows_fwd(r, n, Tr, P->fd, P->tw, P->dtw, s));
+        HIPCHK(launch_dct_cols_filter(Tr, n, P->spec, (float)alpha, inv, P->fd, P->tw, P->dtw, s));
+        HIPCHK(launch_dct_rows_inv(Tr, n, t, P->fd, P->tw, P->dtw, s));
+    } else if (r != t) {
+        HIPCHK(hipMemcpyAsync(t, r, (size_t)n * n * sizeof(float), hipMemcpyDeviceToDevice, s));
+    }
+    return MLBA_OK;
+}
+
+int compute_spectrum(mlba_plan_s* P, hipStream_t s) {
+    const int n = P->n;
+    if (P->precond == MLBA_PRECOND_BCCB) {
+        HIPCHK(launch_pad_psf(P->psf, P->p, P->r, n, s));
+        HIPCHK(launch_fft_rows_r2c(P->r, n, (float2*)P->swork, P->fd, P->tw, s));
+        HIPCHK(launch_fft_cols_power((const float2*)P->swork, n, P->spec, P->fd, P->tw, s));
+    } else if (P->precond == MLBA_PRECOND_DCT) {
+        HIPCHK(launch_dct_spectrum(P->psf, P->p, n, P->spec, P->costab, s));
+    }
+    return MLBA_OK;
+}
+
+LevelMu level_mu(const float* mub, int lev) {
+    LevelMu m;
+    m.low = mub[0];
+    for (int q = 0; q < 8; ++q) m.band[q] = mub[1 + 8 * (lev - 1) + q];
+    return m;
+}
+
+// z (+)= W v over all levels
+int do_analysis(mlba_plan_s* P, const float* v, float* z, bool accum, hipStream_t s) {
+    const size_t nn = NN(P);
+    const float* in = v;
+    for (int lev = 1; lev <= P->levels; ++lev) {
+        const int d = 1 << (lev - 1);
+        float* zlev = z + (size_t)(1 + 8 * (lev - 1)) * nn;
+        const bool last = lev == P->levels;
+        float* low = last ? z : P->tmp[lev & 1];
+        HIPCHK(launch_analysis_level(in, P->N, d, zlev, low, accum ? 1 : 0, (accum && last) ? 1 : 0, s));
+        in = low;
+    }
+    return MLBA_OK;
+}
+
+// f = W^T (delta S_mu(z)) (thr) or W^T z
+int do_synthesis(mlba_plan_s* P, const float* z, float* f, bool thr, const float* mub, float delta,
+                 hipStream_t s) {
+    const size_t nn = NN(P);
+    static const float zeros[64] = {0};
+    const float* mu = thr ? mub : zeros;
+    const float* low = z;
+    for (int lev = P->levels; lev >= 1; --lev) {
+        const int d = 1 << (lev - 1);
+        const float* zlev = z + (size_t)(1 + 8 * (lev - 1)) * nn;
+        float* out = lev == 1 ? f : P->tmp[lev & 1];
+        const bool top = lev == P->levels;
+        HIPCHK(launch_synthesis_level(zlev, low, P->N, d, out, level_mu(mu, lev), thr ? delta : 1.0f,
+                                      (thr && top) ? 1 : 0, thr ? 1 : 0, s));
+        low = out;
+    }
+    return MLBA_OK;
+}
+
+int expand_mu(const mlba_plan_s* P, const double* mu, int n_mu, float* out) {
+    if (!mu || (n_mu != 1 && n_mu != P->bands)) return MLBA_EINVAL;
+    for (int b = 0; b < P->bands; ++b) {
+        const double v = mu[n_mu == 1 ? 0 : b];
+        if (!(v >= 0.0) || !isfinite(v)) return MLBA_EINVAL;
+        out[b] = (float)v;
+    }
+    return MLBA_OK;
+}
+
+int opnorm_impl(mlba_plan_s* P, double alpha, int iters, double* out, hipStream_t s) {
+    const size_t nn = NN(P);
+    float* v = P->pv;
+    float* w = P->u;  // the synthesis buffer is free while estimating
+    HIPCHK(launch_fill_hash(v, nn, 7u, s));
+    int np = 0;
+    HIPCHK(launch_dot_partials(v, v, nn, P->partials, &np, s));
+    HIPCHK(launch_sum_partials(P->partials, np, P->scal, s));
+    HIPCHK(launch_scale(v, nn, P->scal, 1.0f, s));
+    for (int it = 0; it < iters; ++it) {
+        STCHK(do_blur(P, v, nullptr, P->r, false, nullptr, s));
+        STCHK(do_precond(P, P->r, P->t, alpha, s));
+        STCHK(do_blurT(P, P->t, w, s));
+        HIPCHK(launch_dot_partials(v, w, nn, P->partials, &np, s));
+        HIPCHK(launch_sum_partials(P->partials, np, P->scal + 1, s));
+        HIPCHK(launch_dot_partials(w, w, nn, P->partials, &np, s));
+        HIPCHK(launch_sum_partials(P->partials, np, P->scal, s));
+        HIPCHK(launch_scale(w, nn, P->scal, 1.0f, s));
+        float* x = v;
+        v = w;
+        w = x;
+    }
+    double host[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(host, P->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *out = host[1];
+    return MLBA_OK;
+}
+
+double alpha_at(const mlba_alpha_schedule& a, int k) {
+    switch (a.kind) {
+        case MLBA_ALPHA_GEOMETRIC: {
+            const double v = a.alpha0 * pow(a.ratio, (double)k);
+            return v > a.alpha_floor ? v : a.alpha_floor;
+        }
+        case MLBA_ALPHA_TABLE:
+            return a.table[k];
+        default:
+            return a.alpha0;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mlba_status_string(int status) {
+    switch (status) {
+        case MLBA_OK: return "ok";
+        case MLBA_WARN_DIVERGED: return "warning: residual diverged";
+        case MLBA_EINVAL: return "invalid argument";
+        case MLBA_EUNSUPPORTED: return "unsupported size";
+        case MLBA_EHIP: return "HIP runtime error";
+        case MLBA_ENOMEM: return "device allocation failed";
+        default: return "unknown status";
+    }
+}
+
+int mlba_last_hip_error(void) { return g_last_hip; }
+
+int mlba_version(void) { return 1; }
+
+int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int levels, const float* psf,
+                     hipStream_t s) {
+    if (!plan || !psf) return MLBA_EINVAL;
+    *plan = nullptr;
+    if (n < 2 || p < 1 || (p % 2) == 0 || p > n) return MLBA_EINVAL;
+    if (bc < MLBA_BC_RECT || bc > MLBA_BC_ZERO) return MLBA_EINVAL;
+    if (precond < MLBA_PRECOND_BCCB || precond > MLBA_PRECOND_NONE) return MLBA_EINVAL;
+    if (levels < 1 || levels > 4) return MLBA_EINVAL;
+    const int N = bc == MLBA_BC_RECT ? n + p - 1 : n;
+    if ((1 << (levels - 1)) >= N) return MLBA_EINVAL;
+    int a2 = 0, b3 = 0;
+    if (precond != MLBA_PRECOND_NONE) {
+        if (!factor_23(n, &a2, &b3) || a2 < 1 || n < 8 || n > 4096) return MLBA_EUNSUPPORTED;
+    }
+
+    mlba_plan_s* P = new (std::nothrow) mlba_plan_s();
+    if (!P) return MLBA_ENOMEM;
+    P->n = n;
+    P->p = p;
+    P->c = (p - 1) / 2;
+    P->N = N;
+    P->bc = bc;
+    P->precond = precond;
+    P->levels = levels;
+    P->bands = 8 * levels + 1;
+
+    int st = MLBA_OK;
+    const size_t nn = (size_t)N * N, obs = (size_t)n * n;
+    const int m = n + p - 1;
+    P->partials_cap = conv_partials_count(n);
+    if (P->partials_cap < reduce_partials_cap()) P->partials_cap = reduce_partials_cap();
+    P->rn_cap = 1 << 16;
+#define ALLOC(ptr, count)                                  \
+    do {                                                   \
+        st = dalloc_t(P, &(ptr), (count));                 \
+        if (st) {                                          \
+            free_plan(P);                                  \
+            return st;                                     \
+        }                                                  \
+    } while (0)
+    ALLOC(P->psf, (size_t)p * p);
+    ALLOC(P->u, nn);
+    ALLOC(P->r, obs);
+    ALLOC(P->t, obs);
+    ALLOC(P->w, nn);
+    ALLOC(P->tmp[0], nn);
+    ALLOC(P->tmp[1], nn);
+    ALLOC(P->pv, nn);
+    ALLOC(P->z, nn * P->bands);
+    ALLOC(P->partials, (size_t)P->partials_cap);
+    ALLOC(P->scal, 8);
+    ALLOC(P->rn, (size_t)P->rn_cap);
+    if (bc == MLBA_BC_REFLECT) ALLOC(P->wext, (size_t)m * m);
+
+    if (precond != MLBA_PRECOND_NONE) {
+        FftDesc& fd = P->fd;
+        fd.n = n;
+        fd.nst = 0;
+        int a = a2;
+        while (a >= 3) {
+            fd.radix[fd.nst++] = 8;
+            a -= 3;
+        }
+        if (a == 2) fd.radix[fd.nst++] = 4;
+        if (a == 1) fd.radix[fd.nst++] = 2;
+        for (int i = 0; i < b3; ++i) fd.radix[fd.nst++] = 3;
+
+        std::vector<float2> tw(n), dtw(n);
+        std::vector<float> cost(2 * n);
+        const double pi = 3.14159265358979323846;
+        for (int q = 0; q < n; ++q) {
+            const double ang = -2.0 * pi * (double)q / (double)n;
+            tw[q] = make_float2((float)cos(ang), (float)sin(ang));
+            const double ang2 = -pi * (double)q / (2.0 * (double)n);
+            dtw[q] = make_float2((float)cos(ang2), (float)sin(ang2));
+        }
+        for (int q = 0; q < 2 * n; ++q) cost[q] = (float)cos(pi * (double)q / (double)n);
+        ALLOC(P->tw, (size_t)n);
+        ALLOC(P->dtw, (size_t)n);
+        ALLOC(P->costab, (size_t)2 * n);
+        if (precond == MLBA_PRECOND_BCCB) {
+            ALLOC(P->spec, (size_t)(n / 2 + 1) * n);
+            float2* T = nullptr;
+            ALLOC(T, (size_t)(n / 2 + 1) * n);
+            P->swork = T;
+        } else {
+            ALLOC(P->spec, obs);
+            float* Tr = nullptr;
+            ALLOC(Tr, obs);
+            P->swork = Tr;
+        }
+#undef ALLOC
+        hipError_t e = hipMemcpyAsync(P->tw, tw.data(), n * sizeof(float2), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(P->dtw, dtw.data(), n * sizeof(float2), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(P->costab, cost.data(), 2 * n * sizeof(float), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);  // host tables go out of scope
+        if (e != hipSuccess) {
+            g_last_hip = (int)e;
+            free_plan(P);
+            return MLBA_EHIP;
+        }
+    }
+    st = mlba_plan_set_psf(P, psf, s);
+    if (st < 0) {
+        free_plan(P);
+        return st;
+    }
+    *plan = P;
+    return MLBA_OK;
+}
+
+int mlba_plan_set_psf(mlba_plan_t P, const float* psf, hipStream_t s) {
+    if (!P || !psf) return MLBA_EINVAL;
+    HIPCHK(hipMemcpyAsync(P->psf, psf, (size_t)P->p * P->p * sizeof(float), hipMemcpyDeviceToDevice, s));
+    return compute_spectrum(P, s);
+}
+
+int mlba_plan_destroy(mlba_plan_t P) {
+    if (!P) return MLBA_EINVAL;
+    hipDeviceSynchronize();
+    free_plan(P);
+    return MLBA_OK;
+}
+
+int mlba_plan_dims(mlba_plan_t P, int* n, int* p, int* N, int* bands) {
+    if (!P) return MLBA_EINVAL;
+    if (n) *n = P->n;
+    if (p) *p = P->p;
+    if (N) *N = P->N;
+    if (bands) *bands = P->bands;
+    return MLBA_OK;
+}
+
+int mlba_plan_opnorm(mlba_plan_t P, double alpha, int iters, double* out, hipStream_t s) {
+    if (!P || !out || iters < 1 || !(alpha > 0.0 || P->precond == MLBA_PRECOND_NONE)) return MLBA_EINVAL;
+    return opnorm_impl(P, alpha, iters, out, s);
+}
+
+int mlba_apply_A(mlba_plan_t P, const float* u, float* y, hipStream_t s) {
+    if (!P || !u || !y) return MLBA_EINVAL;
+    return do_blur(P, u, nullptr, y, false, nullptr, s);
+}
+
+int mlba_residual(mlba_plan_t P, const float* g, const float* u, float* r, hipStream_t s) {
+    if (!P || !g || !u || !r) return MLBA_EINVAL;
+    return do_blur(P, u, g, r, false, nullptr, s);
+}
+
+int mlba_apply_At(mlba_plan_t P, const float* y, float* w, hipStream_t s) {
+    if (!P || !y || !w) return MLBA_EINVAL;
+    return do_blurT(P, y, w, s);
+}
+
+int mlba_apply_P(mlba_plan_t P, const float* r, float* t, double alpha, hipStream_t s) {
+    if (!P || !r || !t) return MLBA_EINVAL;
+    if (P->precond != MLBA_PRECOND_NONE && !(alpha > 0.0)) return MLBA_EINVAL;
+    return do_precond(P, r, t, alpha, s);
+}
+
+int mlba_framelet_analysis(mlba_plan_t P, const float* f, float* z, hipStream_t s) {
+    if (!P || !f || !z) return MLBA_EINVAL;
+    return do_analysis(P, f, z, false, s);
+}
+
+int mlba_analysis_update(mlba_plan_t P, const float* w, float* z, hipStream_t s) {
+    if (!P || !w || !z) return MLBA_EINVAL;
+    return do_analysis(P, w, z, true, s);
+}
+
+int mlba_framelet_synthesis(mlba_plan_t P, const float* z, float* f, hipStream_t s) {
+    if (!P || !z || !f) return MLBA_EINVAL;
+    return do_synthesis(P, z, f, false, nullptr, 1.0f, s);
+}
+
+int mlba_threshold_synthesis(mlba_plan_t P, const float* z, const double* mu, int n_mu, double delta, float* f,
+                             hipStream_t s) {
+    if (!P || !z || !f || !isfinite(delta)) return MLBA_EINVAL;
+    float mub[64];
+    STCHK(expand_mu(P, mu, n_mu, mub));
+    return do_synthesis(P, z, f, true, mub, (float)delta, s);
+}
+
+int mlba_soft_threshold(const float* z, float* x, int bands, size_t band_elems, const double* mu, int n_mu,
+                        double delta, hipStream_t s) {
+    if (!z || !x || !mu || bands < 1 || bands > 64 || (n_mu != 1 && n_mu != bands) || !isfinite(delta))
+        return MLBA_EINVAL;
+    BandMu m;
+    for (int b = 0; b < bands; ++b) {
+        const double v = mu[n_mu == 1 ? 0 : b];
+        if (!(v >= 0.0) || !isfinite(v)) return MLBA_EINVAL;
+        m.v[b] = (float)v;
+    }
+    HIPCHK(launch_soft_threshold(z, x, bands, band_elems, m, (float)delta, s));
+    return MLBA_OK;
+}
+
+int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f_out, float* z_state,
+                 double* rnorm_out, int* iters_done, hipStream_t s) {
+    if (!P || !g || !prm || !f_out) return MLBA_EINVAL;
+    const int iters = prm->iters, k0 = prm->k0;
+    if (iters < 0 || k0 < 0) return MLBA_EINVAL;
+    const mlba_alpha_schedule& as = prm->alpha;
+    if (as.kind < MLBA_ALPHA_CONST || as.kind > MLBA_ALPHA_TABLE) return MLBA_EINVAL;
+    if (as.kind == MLBA_ALPHA_TABLE && (!as.table || as.table_len < k0 + iters)) return MLBA_EINVAL;
+    if (as.kind == MLBA_ALPHA_GEOMETRIC && !(as.ratio > 0.0)) return MLBA_EINVAL;
+    const mlba_stop* stop = prm->stop;
+    if (stop && (stop->check_every < 1 || !(stop->noise_norm >= 0.0))) return MLBA_EINVAL;
+    float mub[64];
+    STCHK(expand_mu(P, prm->mu, prm->n_mu, mub));
+
+    // schedules for k = k0 .. k0 + iters (the last entry scales the output)
+    std::vector<double> alpha(iters + 1), delta(iters + 1);
+    for (int i = 0; i <= iters; ++i) {
+        alpha[i] = alpha_at(as, k0 + (i < iters ? i : (iters > 0 ? iters - 1 : 0)));
+        if (P->precond != MLBA_PRECOND_NONE && !(alpha[i] > 0.0)) return MLBA_EINVAL;
+    }
+    if (prm->delta_table) {
+        for (int i = 0; i <= iters; ++i) delta[i] = prm->delta_table[k0 + i];
+    } else if (prm->delta > 0.0) {
+        for (int i = 0; i <= iters; ++i) delta[i] = prm->delta;
+    } else {
+        std::vector<double> seen_a, seen_d;
+        for (int i = 0; i <= iters; ++i) {
+            size_t j = 0;
+            while (j < seen_a.size() && seen_a[j] != alpha[i]) ++j;
+            if (j == seen_a.size()) {
+                double nrm = 0.0;
+                STCHK(opnorm_impl(P, alpha[i], 50, &nrm, s));
+                seen_a.push_back(alpha[i]);
+                seen_d.push_back(0.9 / (nrm > 0.9 ? nrm : 0.9));
+            }
+            delta[i] = seen_d[j];
+        }
+    }
+    for (int i = 0; i <= iters; ++i)
+        if (!isfinite(delta[i])) return MLBA_EINVAL;
+
+    const size_t nn = NN(P);
+    float* z = z_state ? z_state : P->z;
+    if (!z_state) HIPCHK(launch_fill(z, nn * P->bands, 0.0f, s));
+
+    const bool track = rnorm_out || iters_done || stop;
+    std::vector<double> rn_host;
+    if (track) rn_host.reserve(iters);
+    int done = 0;
+    bool stopped = false;
+    int ring_base = 0;  // iteration index stored at rn[0]
+    auto drain = [&](int upto) -> int {  // copy rn[ring] for iterations [rn_host.size(), upto)
+        const int from = (int)rn_host.size();
+        if (upto <= from) return MLBA_OK;
+        std::vector<double> buf(upto - from);
+        HIPCHK(hipMemcpyAsync(buf.data(), P->rn + (from - ring_base), (upto - from) * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (double v : buf) rn_host.push_back(v);
+        return MLBA_OK;
+    };
+
+    for (int i = 0; i < iters; ++i) {
+        if (i - ring_base >= P->rn_cap) {
+            if (track) STCHK(drain(i));
+            ring_base = i;
+        }
+        STCHK(do_synthesis(P, z, P->u, true, mub, (float)delta[i], s));
+        int np = 0;
+        STCHK(do_blur(P, P->u, g, P->r, true, &np, s));
+        HIPCHK(launch_sum_partials(P->partials, np, P->rn + (i - ring_base), s));
+        if (stop && (i % stop->check_every) == 0) {
+            STCHK(drain(i + 1));
+            if (sqrt(rn_host.back()) <= stop->gamma * stop->noise_norm) {
+                // x^k already satisfies the discrepancy principle: return W^T x^k
+                rn_host.pop_back();
+                HIPCHK(hipMemcpyAsync(f_out, P->u, nn * sizeof(float), hipMemcpyDeviceToDevice, s));
+                stopped = true;
+                break;
+            }
+        }
+        STCHK(do_precond(P, P->r, P->t, alpha[i], s));
+        STCHK(do_blurT(P, P->t, P->w, s));
+        STCHK(do_analysis(P, P->w, z, true, s));
+        done = i + 1;
+    }
+    if (!stopped) STCHK(do_synthesis(P, z, f_out, true, mub, (float)delta[done], s));
+
+    int status = MLBA_OK;
+    if (track) {
+        STCHK(drain(done));
+        rn_host.resize(done);
+        double first = -1.0;
+        for (int i = 0; i < done; ++i) {
+            const double v = sqrt(rn_host[i]);
+            if (rnorm_out) rnorm_out[i] = v;
+            if (first < 0.0) first = v;
+            if (!isfinite(v) || v > 1e3 * first) status = MLBA_WARN_DIVERGED;
+        }
+        if (iters_done) *iters_done = done;
+    }
+    return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Deterministic reductions and small vector helpers.  Every sum is taken in
+// double with a fixed assignment of elements to threads and a fixed
+// combination tree, so repeated runs give bit-identical results.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mlba {
+
+constexpr int kReduceBlocks = 1024;
+
+int reduce_partials_cap() { return kReduceBlocks; }
+
+__global__ __launch_bounds__(kBlock) void sum_partials_kernel(const double* __restrict__ partials, int count,
+                                                              double* __restrict__ out) {
+    __shared__ double red[kBlock / 64];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < count; i += kBlock) s += partials[i];
+    const double t = block_sum(s, red);
+    if (threadIdx.x == 0) *out = t;
+}
+
+hipError_t launch_sum_partials(const double* partials, int count, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kBlock), 0, s, partials, count, out);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void dot_partials_kernel(const float* __restrict__ a,
+                                                              const float* __restrict__ b, size_t count,
+                                                              double* __restrict__ partials) {
+    __shared__ double red[kBlock / 64];
+    double s = 0.0;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (size_t)gridDim.x * kBlock)
+        s += (double)a[i] * (double)b[i];
+    const double t = block_sum(s, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+hipError_t launch_dot_partials(const float* a, const float* b, size_t count, double* partials, int* n_partials,
+                               hipStream_t s) {
+    size_t blocks = (count + kBlock - 1) / kBlock;
+    if (blocks > (size_t)kReduceBlocks) blocks = kReduceBlocks;
+    if (blocks == 0) blocks = 1;
+    *n_partials = (int)blocks;
+    hipLaunchKernelGGL(dot_partials_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, a, b, count, partials);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void scale_kernel(float* __restrict__ x, size_t count,
+                                                       const double* __restrict__ nrm2, float factor) {
+    const float f = nrm2 ? (float)((double)factor / sqrt(*nrm2)) : factor;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (size_t)gridDim.x * kBlock)
+        x[i] *= f;
+}
+
+hipError_t launch_scale(float* x, size_t count, const double* nrm2, float factor, hipStream_t s) {
+    size_t blocks = (count + kBlock - 1) / kBlock;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(scale_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, x, count, nrm2, factor);
+    return hipGetLastError();
+}
+
+// A counter-based hash (64-bit SplitMix finaliser) mapped to [-1, 1).
+__device__ __forceinline__ float hash_unit(unsigned long long i, unsigned seed) {
+    unsigned long long z = i + 0x9E3779B97F4A7C15ull * (unsigned long long)(seed + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (float)((double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0);
+}
+
+__global__ __launch_bounds__(kBlock) void fill_hash_kernel(float* __restrict__ x, size_t count, unsigned seed) {
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (size_t)gridDim.x * kBlock)
+        x[i] = hash_unit(i, seed);
+}
+
+hipError_t launch_fill_hash(float* x, size_t count, unsigned seed, hipStream_t s) {
+    size_t blocks = (count + kBlock - 1) / kBlock;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_hash_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, x, count, seed);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void fill_kernel(float* __restrict__ x, size_t count, float value) {
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (size_t)gridDim.x * kBlock)
+        x[i] = value;
+}
+
+hipError_t launch_fill(float* x, size_t count, float value, hipStream_t s) {
+    size_t blocks = (count + kBlock - 1) / kBlock;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, x, count, value);
+    return hipGetLastError();
+}
+
+}  // namespace mlba

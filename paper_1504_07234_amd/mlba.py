@@ -1,0 +1,216 @@
+"""Python binding of libmlba: argument marshalling over the C ABI.
+
+PyTorch supplies device memory and the stream; every computation happens in
+the HIP kernels behind include/mlba.h.  All tensors must be contiguous
+float32 tensors on the current HIP device.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import check
+
+RECT, REFLECT, PERIODIC, ZERO = _lib.BC_RECT, _lib.BC_REFLECT, _lib.BC_PERIODIC, _lib.BC_ZERO
+BCCB, DCT, NONE = _lib.PRECOND_BCCB, _lib.PRECOND_DCT, _lib.PRECOND_NONE
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str, shape=None) -> ctypes.c_void_p:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dbl_array(values):
+    arr = (ctypes.c_double * len(values))(*[float(v) for v in values])
+    return arr, ctypes.cast(arr, _lib.c_dbl_p)
+
+
+@dataclass
+class RestoreInfo:
+    status: int
+    iters_done: int
+    rnorm: list
+
+
+class Plan:
+    """A restoration plan: sizes, boundary model, preconditioner, framelet
+    levels and the PSF (copied to the plan; its spectrum is computed at
+    creation)."""
+
+    def __init__(self, n: int, p: int, bc: int, precond: int, levels: int, psf: torch.Tensor, stream=None):
+        self._lib = _lib.load()
+        self._h = ctypes.c_void_p()
+        psf = psf.contiguous()
+        check(self._lib.mlba_plan_create(ctypes.byref(self._h), n, p, bc, precond, levels,
+                                         _dev(psf, "psf", (p, p)), _stream(stream)), "mlba_plan_create")
+        dims = [ctypes.c_int() for _ in range(4)]
+        check(self._lib.mlba_plan_dims(self._h, *[ctypes.byref(d) for d in dims]), "mlba_plan_dims")
+        self.n, self.p, self.N, self.bands = (d.value for d in dims)
+        self.bc, self.precond, self.levels = bc, precond, levels
+
+    # -- lifetime ----------------------------------------------------------
+    def close(self):
+        if self._h:
+            torch.cuda.synchronize()
+            self._lib.mlba_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- helpers -----------------------------------------------------------
+    def _new(self, *shape):
+        return torch.empty(shape, dtype=torch.float32, device="cuda")
+
+    def set_psf(self, psf: torch.Tensor, stream=None):
+        psf = psf.contiguous()
+        check(self._lib.mlba_plan_set_psf(self._h, _dev(psf, "psf", (self.p, self.p)), _stream(stream)),
+              "mlba_plan_set_psf")
+
+    def opnorm(self, alpha: float, iters: int = 50, stream=None) -> float:
+        out = ctypes.c_double()
+        check(self._lib.mlba_plan_opnorm(self._h, float(alpha), int(iters), ctypes.byref(out), _stream(stream)),
+              "mlba_plan_opnorm")
+        return out.value
+
+    # -- operators ---------------------------------------------------------
+    def apply_A(self, u, out=None, stream=None):
+        out = self._new(self.n, self.n) if out is None else out
+        check(self._lib.mlba_apply_A(self._h, _dev(u, "u", (self.N, self.N)), _dev(out, "out", (self.n, self.n)),
+                                     _stream(stream)), "mlba_apply_A")
+        return out
+
+    def residual(self, g, u, out=None, stream=None):
+        out = self._new(self.n, self.n) if out is None else out
+        check(self._lib.mlba_residual(self._h, _dev(g, "g", (self.n, self.n)), _dev(u, "u", (self.N, self.N)),
+                                      _dev(out, "out", (self.n, self.n)), _stream(stream)), "mlba_residual")
+        return out
+
+    def apply_At(self, y, out=None, stream=None):
+        out = self._new(self.N, self.N) if out is None else out
+        check(self._lib.mlba_apply_At(self._h, _dev(y, "y", (self.n, self.n)), _dev(out, "out", (self.N, self.N)),
+                                      _stream(stream)), "mlba_apply_At")
+        return out
+
+    def apply_P(self, r, alpha: float, out=None, stream=None):
+        out = self._new(self.n, self.n) if out is None else out
+        check(self._lib.mlba_apply_P(self._h, _dev(r, "r", (self.n, self.n)), _dev(out, "out", (self.n, self.n)),
+                                     float(alpha), _stream(stream)), "mlba_apply_P")
+        return out
+
+    def analysis(self, f, out=None, stream=None):
+        out = self._new(self.bands, self.N, self.N) if out is None else out
+        check(self._lib.mlba_framelet_analysis(self._h, _dev(f, "f", (self.N, self.N)),
+                                               _dev(out, "out", (self.bands, self.N, self.N)), _stream(stream)),
+              "mlba_framelet_analysis")
+        return out
+
+    def analysis_update(self, w, z, stream=None):
+        check(self._lib.mlba_analysis_update(self._h, _dev(w, "w", (self.N, self.N)),
+                                             _dev(z, "z", (self.bands, self.N, self.N)), _stream(stream)),
+              "mlba_analysis_update")
+        return z
+
+    def synthesis(self, z, out=None, stream=None):
+        out = self._new(self.N, self.N) if out is None else out
+        check(self._lib.mlba_framelet_synthesis(self._h, _dev(z, "z", (self.bands, self.N, self.N)),
+                                                _dev(out, "out", (self.N, self.N)), _stream(stream)),
+              "mlba_framelet_synthesis")
+        return out
+
+    def threshold_synthesis(self, z, mu, delta: float, out=None, stream=None):
+        out = self._new(self.N, self.N) if out is None else out
+        mus = [mu] if isinstance(mu, (int, float)) else list(mu)
+        arr, ptr = _dbl_array(mus)
+        check(self._lib.mlba_threshold_synthesis(self._h, _dev(z, "z", (self.bands, self.N, self.N)), ptr,
+                                                 len(mus), float(delta), _dev(out, "out", (self.N, self.N)),
+                                                 _stream(stream)), "mlba_threshold_synthesis")
+        return out
+
+    # -- restoration -------------------------------------------------------
+    def restore(self, g, *, alpha=0.05, alpha_kind: int = _lib.ALPHA_CONST, alpha_ratio: float = 1.0,
+                alpha_floor: float = 0.0, alpha_table=None, mu=1e-3, delta: float = 0.0, delta_table=None,
+                iters: int = 50, k0: int = 0, z=None, out=None, stop=None, track: bool = True, stream=None):
+        """Run `iters` iterations of eq. (MLBA2); returns (f, RestoreInfo).
+
+        z: optional state tensor [bands, N, N] (in/out, resume with k0).
+        stop: optional (noise_norm, gamma, check_every) discrepancy stop.
+        track: read back the residual norms (synchronises at the end)."""
+        out = self._new(self.N, self.N) if out is None else out
+        sched = _lib.AlphaSchedule()
+        sched.kind = int(alpha_kind)
+        sched.alpha0 = float(alpha)
+        sched.ratio = float(alpha_ratio)
+        sched.alpha_floor = float(alpha_floor)
+        keep = []
+        if alpha_table is not None:
+            arr, ptr = _dbl_array(alpha_table)
+            keep.append(arr)
+            sched.kind = _lib.ALPHA_TABLE
+            sched.table = ptr
+            sched.table_len = len(alpha_table)
+        prm = _lib.Params()
+        prm.alpha = sched
+        mus = [mu] if isinstance(mu, (int, float)) else list(mu)
+        marr, mptr = _dbl_array(mus)
+        keep.append(marr)
+        prm.mu = mptr
+        prm.n_mu = len(mus)
+        prm.delta = float(delta)
+        if delta_table is not None:
+            darr, dptr = _dbl_array(delta_table)
+            keep.append(darr)
+            prm.delta_table = dptr
+        prm.iters = int(iters)
+        prm.k0 = int(k0)
+        if stop is not None:
+            st = _lib.Stop(float(stop[0]), float(stop[1]), int(stop[2]))
+            keep.append(st)
+            prm.stop = ctypes.pointer(st)
+        zp = ctypes.c_void_p() if z is None else _dev(z, "z", (self.bands, self.N, self.N))
+        rn = (ctypes.c_double * max(1, iters))() if track else None
+        done = ctypes.c_int(iters)
+        status = self._lib.mlba_restore(self._h, _dev(g, "g", (self.n, self.n)), ctypes.byref(prm),
+                                        _dev(out, "out", (self.N, self.N)), zp,
+                                        ctypes.cast(rn, _lib.c_dbl_p) if track else None,
+                                        ctypes.byref(done) if track else None, _stream(stream))
+        check(status, "mlba_restore")
+        info = RestoreInfo(status, done.value, list(rn[:done.value]) if track else [])
+        return out, info
+
+
+def soft_threshold(z: torch.Tensor, mu, delta: float = 1.0, out=None, stream=None):
+    """x = delta * S_mu(z) over the leading (band) axis of z."""
+    lib = _lib.load()
+    out = torch.empty_like(z) if out is None else out
+    bands = z.shape[0] if z.dim() >= 2 else 1
+    elems = z.numel() // bands
+    mus = [mu] if isinstance(mu, (int, float)) else list(mu)
+    arr, ptr = _dbl_array(mus)
+    check(lib.mlba_soft_threshold(_dev(z, "z"), _dev(out, "out", tuple(z.shape)), bands, elems, ptr, len(mus),
+                                  float(delta), _stream(stream)), "mlba_soft_threshold")
+    return out

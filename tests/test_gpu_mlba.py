@@ -1,0 +1,173 @@
+"""End-to-end parity of the HIP restoration loop (eq. MLBA2) against the FP64
+oracle, on the seeded workloads, through the C ABI ``mlba_restore``.
+
+Bar: the restored image after the full iteration count within 1e-4
+(||.||_2-relative) of the oracle, the residual-norm history within 1e-4;
+the oracle and the GPU get the same alpha_k and delta_k tables.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import blur as oblur
+from oracle import mlba as omlba
+from tests._util import announce, cuda, host, observed, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL_IMAGE = 1e-4
+
+
+@pytest.fixture(scope="module")
+def mlba():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1504_07234_amd import mlba as m
+    return m
+
+
+def _schedules(w, iters):
+    alphas = omlba.alpha_table(w.alpha_kind, w.alpha0, iters, w.alpha_ratio, w.alpha_floor)
+    deltas = omlba.delta_table(w.psf, w.n, w.bc, w.precond, alphas, w.delta, iters + 1)
+    return alphas, deltas
+
+
+def _run_both(mlba, w, iters, alphas, deltas, g):
+    with mlba.Plan(w.n, w.p, w.bc, w.precond, w.levels, cuda(w.psf)) as plan:
+        f, info = plan.restore(cuda(g), alpha_table=alphas, mu=w.mu, delta_table=deltas, iters=iters)
+        f = host(f)
+    ref = omlba.mlba(g, w.psf, w.bc, w.precond, w.levels, alphas, deltas, w.mu, iters)
+    return f, info, ref
+
+
+def test_small_workload_auto_step(mlba):
+    """72 x 72 unknown, 9 x 9 Gaussian, BCCB alpha = 0.05, 1 level, 50 its."""
+    w = synth.make_workload("plain-fp64-72")
+    announce("restore plain-fp64-72 auto step")
+    g, nn = observed(w, oblur)
+    alphas, deltas = _schedules(dataclasses.replace(w, delta=0.0), w.iters)
+    f, info, ref = _run_both(mlba, w, w.iters, alphas, deltas, g)
+    assert info.status == 0 and info.iters_done == w.iters
+    e = rel_err(f, ref["f"])
+    print(f"  image rel err {e:.2e}; rnorm last gpu {info.rnorm[-1]:.5f} oracle {ref['rnorm'][-1]:.5f}", flush=True)
+    assert e < TOL_IMAGE
+    assert rel_err(info.rnorm, ref["rnorm"]) < TOL_IMAGE
+
+
+def test_small_workload_literal_step_diverges(mlba):
+    """The literal unit step violates the convergence condition (the operator
+    norm is about 3.2 at alpha = 0.05): both sides diverge and the library
+    reports MLBA_WARN_DIVERGED."""
+    w = synth.make_workload("plain-fp64-72")
+    announce("restore plain-fp64-72 literal step")
+    g, _ = observed(w, oblur)
+    alphas = np.full(w.iters, w.alpha0)
+    deltas = np.full(w.iters + 1, 1.0)
+    f, info, ref = _run_both(mlba, w, w.iters, alphas, deltas, g)
+    assert info.status == 1  # MLBA_WARN_DIVERGED
+    assert ref["rnorm"][-1] > 1e3 * ref["rnorm"][0]
+    # both blow up along the same direction: the FP32 history still tracks FP64
+    assert rel_err(info.rnorm, ref["rnorm"]) < 1e-3
+
+
+@pytest.mark.parametrize("name", ["rect-bccb-512", "reflect-dct-512", "rect-bccb-geometric-512"])
+def test_512_workloads_200_iterations(mlba, name):
+    w = synth.make_workload(name)
+    announce(f"restore {name} {w.iters} iterations")
+    g, nn = observed(w, oblur)
+    alphas, deltas = _schedules(w, w.iters)
+    f, info, ref = _run_both(mlba, w, w.iters, alphas, deltas, g)
+    e = rel_err(f, ref["f"])
+    er = rel_err(info.rnorm, ref["rnorm"])
+    print(f"  image rel err {e:.2e}, rnorm rel err {er:.2e}, final rnorm {info.rnorm[-1]:.4f} (noise {nn:.4f})",
+          flush=True)
+    assert info.status == 0 and info.iters_done == w.iters
+    assert e < TOL_IMAGE
+    assert er < TOL_IMAGE
+
+
+def test_full_size_iterations(mlba):
+    """2048 x 2048 observed, 31 x 31 disk, 3 levels: the bench workload, a few
+    iterations compared in full (state z and image)."""
+    w = synth.make_workload("rect-bccb-2048")
+    iters = 3
+    announce(f"restore rect-bccb-2048 {iters} iterations")
+    g, _ = observed(w, oblur)
+    alphas = np.full(iters, w.alpha0)
+    deltas = np.full(iters + 1, 0.3)
+    with mlba.Plan(w.n, w.p, w.bc, w.precond, w.levels, cuda(w.psf)) as plan:
+        import torch
+        z = torch.zeros((plan.bands, plan.N, plan.N), dtype=torch.float32, device="cuda")
+        f, info = plan.restore(cuda(g), alpha_table=alphas, mu=w.mu, delta_table=deltas, iters=iters, z=z)
+        f, z = host(f), host(z)
+    ref = omlba.mlba(g, w.psf, w.bc, w.precond, w.levels, alphas, deltas, w.mu, iters)
+    print(f"  image {rel_err(f, ref['f']):.2e} state {rel_err(z, ref['z']):.2e}", flush=True)
+    assert rel_err(f, ref["f"]) < 1e-5
+    assert rel_err(z, ref["z"]) < 1e-5
+    assert rel_err(info.rnorm, ref["rnorm"]) < 1e-6
+
+
+@pytest.mark.parametrize("n,p,bc,pc,L", [(96, 17, 0, 0, 2), (96, 17, 1, 1, 3), (192, 11, 3, 0, 2),
+                                         (128, 7, 2, 0, 4), (384, 25, 0, 1, 2)])
+def test_ragged_and_mixed_models(mlba, n, p, bc, pc, L):
+    announce(f"restore n={n} p={p} bc={bc} pc={pc} L={L}")
+    gen = synth.rng(n + p + bc * 7 + pc)
+    truth = synth.shapes_image(n + p - 1, gen, n_rect=6, n_disk=3, n_bumps=3)
+    H = synth.motion_psf(p, p - 2.0, gen.uniform(0, np.pi))
+    b = oblur.blur(truth, H, 0)
+    g = synth.add_noise(b, synth.white_noise((n, n), gen), 0.01)
+    iters = 40
+    alphas = np.full(iters, 0.1)
+    d = omlba.delta_auto(omlba.opnorm(H, n, bc, pc, 0.1, tol=1e-6))
+    deltas = np.full(iters + 1, d)
+    mu = np.linspace(1e-3, 3e-3, 8 * L + 1)
+    with mlba.Plan(n, p, bc, pc, L, cuda(H)) as plan:
+        f, info = plan.restore(cuda(g), alpha_table=alphas, mu=mu, delta_table=deltas, iters=iters)
+        f = host(f)
+    ref = omlba.mlba(g, H, bc, pc, L, alphas, deltas, mu, iters)
+    assert rel_err(f, ref["f"]) < TOL_IMAGE
+    assert rel_err(info.rnorm, ref["rnorm"]) < TOL_IMAGE
+
+
+def test_resume_and_determinism(mlba):
+    import torch
+    w = synth.make_workload("plain-fp64-72")
+    announce("resume + determinism")
+    g, _ = observed(w, oblur)
+    it = 12
+    alphas = np.full(it, 0.05)
+    deltas = np.full(it + 1, 0.25)
+    with mlba.Plan(w.n, w.p, w.bc, w.precond, w.levels, cuda(w.psf)) as plan:
+        z1 = torch.zeros((plan.bands, plan.N, plan.N), device="cuda")
+        f1, i1 = plan.restore(cuda(g), alpha_table=alphas, mu=w.mu, delta_table=deltas, iters=it, z=z1)
+        z2 = torch.zeros_like(z1)
+        _, ia = plan.restore(cuda(g), alpha_table=alphas, mu=w.mu, delta_table=deltas, iters=5, z=z2)
+        f2, ib = plan.restore(cuda(g), alpha_table=alphas, mu=w.mu, delta_table=deltas, iters=7, k0=5, z=z2)
+        f3, i3 = plan.restore(cuda(g), alpha_table=alphas, mu=w.mu, delta_table=deltas, iters=it)
+        assert torch.equal(z1, z2)
+        assert torch.equal(f1, f2) and torch.equal(f1, f3)
+        assert i1.rnorm == ia.rnorm + ib.rnorm == i3.rnorm
+
+
+def test_discrepancy_stop(mlba):
+    """eq. (discrpr): stop at the first k with ||r^k|| <= gamma * ||eta||."""
+    w = synth.make_workload("plain-fp64-72")
+    announce("discrepancy stop")
+    g, nn = observed(w, oblur)
+    it = 50
+    alphas = np.full(it, 0.05)
+    d = omlba.delta_auto(omlba.opnorm(w.psf, w.n, 0, 0, 0.05))
+    deltas = np.full(it + 1, d)
+    ref = omlba.mlba(g, w.psf, 0, 0, 1, alphas, deltas, w.mu, it)
+    gamma = 1.2
+    k_star = int(np.argmax(ref["rnorm"] <= gamma * nn))
+    assert ref["rnorm"][k_star] <= gamma * nn and k_star > 0
+    with mlba.Plan(w.n, w.p, 0, 0, 1, cuda(w.psf)) as plan:
+        f, info = plan.restore(cuda(g), alpha_table=alphas, mu=w.mu, delta_table=deltas, iters=it,
+                               stop=(nn, gamma, 1))
+        f = host(f)
+    assert info.iters_done == k_star
+    ref_k = omlba.mlba(g, w.psf, 0, 0, 1, alphas, deltas, w.mu, k_star)
+    assert rel_err(f, ref_k["f"]) < TOL_IMAGE
