@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Throughput of the MLBA deblurring iteration on one MI355X.
+
+A step is one full iteration of eq. (MLBA2) -- threshold + synthesis, blur and
+residual, spectral preconditioner, adjoint blur, analysis + Bregman update --
+on the 2048 x 2048 throughput workload (31 x 31 out-of-focus disk PSF,
+rectangular blur model, 2078 x 2078 unknown, BCCB preconditioner with
+alpha = 0.02, 3-level framelet, 25 bands).  Inputs are synthetic (seeded
+scene, PSF and noise) and resident in HBM before the timed region starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line: Mpixel-iter/s over the observed pixels, the
+per-phase breakdown measured with HIP events on the library's stream during
+the timed region, the roofline of the dominant kernel, and the FP64 oracle
+timed on the host cores over a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import resource
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MLBA Mpixel-iter/s at 2048² FP32 (% HBM roofline); batched vs plain; bwd/fwd ratio"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, non-packed FP32
+
+
+def phase_model(n, p, N, B):
+    """Algorithmic bytes and flops of each phase of one iteration (float32).
+
+    synthesis : read z (B N^2), write u (N^2)
+    blur      : read u (N^2), read g (n^2), write r (n^2); 2 p^2 n^2 flops
+    precond   : read r (n^2), write t (n^2)
+    blur_t    : read t (n^2), write w (N^2); 2 p^2 n^2 flops
+    analysis  : read w (N^2), read and write z (2 B N^2)
+    """
+    f4 = 4.0
+    return {
+        "synthesis": {"bytes": f4 * (B * N * N + N * N), "flops": 0.0},
+        "blur": {"bytes": f4 * (N * N + 2 * n * n), "flops": 2.0 * p * p * n * n},
+        "precond": {"bytes": f4 * (2 * n * n), "flops": 0.0},
+        "blur_t": {"bytes": f4 * (n * n + N * N), "flops": 2.0 * p * p * n * n},
+        "analysis": {"bytes": f4 * (N * N + 2 * B * N * N), "flops": 0.0},
+    }
+
+
+def cpu_baseline(w, g64, delta, iters):
+    """The FP64 oracle, as it stands, on `iters` iterations of the same
+    workload (bounded sample)."""
+    import numpy as np
+    from oracle import mlba as omlba
+
+    alphas = np.full(iters, w.alpha0)
+    deltas = np.full(iters + 1, delta)
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    omlba.mlba(g64, w.psf, w.bc, w.precond, w.levels, alphas, deltas, w.mu, iters)
+    wall = time.perf_counter() - t0
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    cores = max(1, int(round(cpu / wall)))
+    return {
+        "value": w.n * w.n * iters / wall / 1e6,
+        "unit": "Mpixel-iter/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"{iters} FP64 iterations of the {w.name} workload ({w.n}x{w.n} observed, "
+                  f"{w.N}x{w.N} unknown, p={w.p}, {w.levels} levels) in {wall:.1f} s",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="rect-bccb-2048")
+    ap.add_argument("--cpu-iters", type=int, default=3, help="oracle iterations for the CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is described in DESIGN.md, not built)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1504_07234_amd import mlba
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+    w = synth.make_workload(args.workload)
+    n, p = w.n, w.p
+
+    # ---- inputs in HBM: scene, PSF, observed image g = A f + eta --------
+    psf = torch.as_tensor(w.psf, dtype=torch.float32).cuda()
+    plan = mlba.Plan(n, p, w.bc, w.precond, w.levels, psf)
+    N, B = plan.N, plan.bands
+    # the scene extends beyond the field of view: observe it through the rectangular blur
+    with mlba.Plan(n, p, mlba.RECT, mlba.NONE, 1, psf) as rect:
+        blurred = rect.apply_A(torch.as_tensor(w.truth, dtype=torch.float32).cuda())
+    xi = torch.as_tensor(w.xi, dtype=torch.float32).cuda()
+    g = blurred + (w.noise_level * blurred.double().norm() / xi.double().norm()).float() * xi
+    g = g.contiguous()
+    opn = plan.opnorm(w.alpha0, 50)
+    delta = 0.9 / max(opn, 0.9)
+    z = torch.zeros((B, N, N), dtype=torch.float32, device="cuda")
+    f = torch.empty((N, N), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+
+    # ---- warmup ---------------------------------------------------------
+    plan.restore(g, alpha=w.alpha0, mu=w.mu, delta=delta, iters=args.warmup, z=z, out=f, track=False)
+    torch.cuda.synchronize()
+
+    # ---- timed region: K iterations, phase events on the library stream --
+    plan.profile_begin(args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.restore(g, alpha=w.alpha0, mu=w.mu, delta=delta, iters=args.steps, k0=args.warmup, z=z, out=f,
+                 track=False)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    phases, rec = plan.profile_end()
+    _, info = plan.restore(g, alpha=w.alpha0, mu=w.mu, delta=delta, iters=1, k0=args.warmup + args.steps, z=z,
+                           out=f, track=True)
+    assert np.isfinite(info.rnorm[0]), "non-finite residual"
+
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = n * n * args.steps / elapsed / 1e6
+    model = phase_model(n, p, N, B)
+    phase_out = {}
+    for ph, (ms, launches) in phases.items():
+        per_iter_ms = ms / max(rec, 1)
+        b, fl = model[ph]["bytes"], model[ph]["flops"]
+        phase_out[ph] = {
+            "ms_per_iter": round(per_iter_ms, 4),
+            "launches_per_iter": launches // max(rec, 1),
+            "GBs": round(b / (per_iter_ms * 1e-3) / 1e9, 1) if per_iter_ms > 0 else None,
+            "TFLOPs": round(fl / (per_iter_ms * 1e-3) / 1e12, 2) if fl and per_iter_ms > 0 else None,
+        }
+    def roofline_of(ph):
+        """Roofline of the phase's main kernel from the live event times."""
+        ms_iter = phases[ph][0] / max(rec, 1)
+        nl = max(1, phases[ph][1] // max(rec, 1))
+        if ph == "blur":  # conv + one tiny reduction launch: the conv is the kernel
+            nl = 1
+        launch_ms = ms_iter / nl
+        if model[ph]["flops"] > 0:
+            ach = model[ph]["flops"] / nl / (launch_ms * 1e-3) / 1e12
+            r = {"bound": "alu", "achieved": round(ach, 2), "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                 "frac": round(ach / FP32_VALU_PEAK_TFLOPS, 4), "traffic": None}
+        else:
+            ach = model[ph]["bytes"] / nl / (launch_ms * 1e-3) / 1e9
+            r = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+        r["kernel_phase"] = ph
+        r["launch_ms"] = round(launch_ms, 4)
+        return r
+
+    # dominant kernel: the longest single launch of an iteration
+    dom = max(phases, key=lambda ph: phases[ph][0] / max(1, (1 if ph == "blur" else phases[ph][1])))
+    roof = roofline_of(dom)
+    roof_hbm = roofline_of("analysis")
+    total_bytes = sum(m["bytes"] for m in model.values())
+    hbm_frac = (total_bytes / (HBM_PEAK_GBS * 1e9)) / (ms_per_step * 1e-3)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "Mpixel-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": n, "p": p, "N": N, "levels": w.levels, "bands": B,
+                   "boundary": "rect", "precond": "bccb", "alpha": w.alpha0, "mu": w.mu,
+                   "delta": round(delta, 6), "state": "explicit z"},
+        "hbm_roofline_frac_whole_step": round(hbm_frac, 4),
+        "phases": phase_out,
+        "roofline": roof,
+        "roofline_hbm": roof_hbm,
+    }
+    if not args.no_cpu:
+        from oracle import blur as oblur
+        g64 = synth.add_noise(oblur.blur(w.truth, w.psf, oblur.RECT), w.xi, w.noise_level)
+        out["cpu_baseline"] = cpu_baseline(w, g64, delta, args.cpu_iters)
+    plan.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -114,10 +114,10 @@ int mlba_last_hip_error(void);   /* hipError_t of the last MLBA_EHIP on this thr
 int mlba_version(void);
 
 /* ---- plans ------------------------------------------------------------
- * mlba_plan_create: n observed side, p odd PSF side (3 <= p <= n), bc one of
+ * mlba_plan_create: n observed side, p odd PSF side (1 <= p <= n, p <= 49), bc one of
  * MLBA_BC_*, precond one of MLBA_PRECOND_*, levels in [1, 4] with
  * 2^(levels-1) < N.  The transforms of P need n = 2^a 3^b, a >= 1,
- * 8 <= n <= 4096 (MLBA_EUNSUPPORTED otherwise).  psf: device p x p.
+ * 8 <= n <= 2048 (MLBA_EUNSUPPORTED otherwise).  psf: device p x p.
  * Allocates the workspace, copies the PSF and computes the spectrum of
  * (C C^T) or (Q Q^T) on `stream` (section 4.1 / 4.3).  The plan keeps no
  * reference to `psf`. */
@@ -170,6 +170,24 @@ int mlba_soft_threshold(const float* z, float* x, int bands, size_t band_elems,
 int mlba_restore(mlba_plan_t plan, const float* g, const mlba_params* params,
                  float* f_out, float* z_state, double* rnorm_out, int* iters_done,
                  hipStream_t stream);
+
+/* ---- phase timing (profiling aid) ----------------------------------------
+ * Phases of one iteration of eq. (MLBA2) as the library runs them. */
+#define MLBA_PHASE_SYNTHESIS 0  /* x = delta S_mu(z), u = W^T x (levels launches)   */
+#define MLBA_PHASE_BLUR      1  /* r = g - A u and ||r||^2                           */
+#define MLBA_PHASE_PRECOND   2  /* t = P_alpha r (three transform passes)            */
+#define MLBA_PHASE_BLUR_T    3  /* w = A^T t                                         */
+#define MLBA_PHASE_ANALYSIS  4  /* z += W w (levels launches)                        */
+#define MLBA_NPHASES         5
+/* mlba_profile_begin: the following mlba_restore calls on this plan record a
+ * HIP event on their stream before each phase and after the last, for at most
+ * max_iters iterations in total (host-side event objects, no device memory).
+ * mlba_profile_end: waits for those events and writes, per phase, the summed
+ * milliseconds (ms[MLBA_NPHASES], host) and the number of kernel launches
+ * (launches[MLBA_NPHASES], host, optional), plus the number of iterations
+ * recorded (iters, optional); then releases the events. */
+int mlba_profile_begin(mlba_plan_t plan, int max_iters);
+int mlba_profile_end(mlba_plan_t plan, double* ms, int* launches, int* iters);
 
 #ifdef __cplusplus
 }

@@ -3,12 +3,13 @@
 // extended image with the PSF; A^T y is the full correlation of y with the
 // PSF, followed for imposed boundaries by the transpose of the padding).
 //
-// One workgroup computes a 32 x 64 output tile.  The (32+p-1) x (64+p-1)
-// input window is staged once in LDS under the requested boundary extension;
-// every thread then owns eight horizontally adjacent outputs and, for each of
-// the p PSF rows, loads 8+p-1 window values into registers and applies the p
-// taps of that row to all eight accumulators.  PSF taps are wavefront-uniform
-// and are read through the scalar cache.  The PSF side is a template
+// One workgroup computes a (32 RY) x 64 output tile.  The (32 RY + p - 1) x
+// (64 + p - 1) input window is staged once in LDS under the requested
+// boundary extension; every thread then owns an RY x 8 block of outputs and
+// walks the p + RY - 1 input rows that feed it: each row segment (8 + p - 1
+// values) is loaded into registers once and applied to every output row it
+// contributes to (RY = 2 halves the LDS reads per FMA).  PSF taps are
+// wavefront-uniform and are read through the scalar cache.  The PSF side is a template
 // parameter for the odd sizes 1..33 (fully unrolled tap loops); larger PSFs
 // use a generic kernel.
 #include "common.hpp"
@@ -16,21 +17,29 @@
 
 namespace mlba {
 
-constexpr int CONV_TY = 32;
-constexpr int CONV_TX = 64;
+constexpr int CONV_TX = 64;  // output columns per workgroup (eight per thread)
 constexpr int CONV_RX = 8;
+// output rows per workgroup: 32 * RY with RY output rows per thread
+template <int RY>
+constexpr int conv_ty() { return 32 * RY; }
 
 __host__ __device__ constexpr int conv_stride(int w) { return ((w + 7) / 8) * 8 + 1; }
 
 template <int P, bool FLIP>
+__device__ __forceinline__ float conv_tap(const float* __restrict__ psf, int a, int b) {
+    return FLIP ? psf[(P - 1 - a) * P + (P - 1 - b)] : psf[a * P + b];
+}
+
+template <int P, bool FLIP, int RY>
 __global__ __launch_bounds__(kBlock) void conv_kernel(const float* __restrict__ src, int S, int ext,
                                                       int org, float* __restrict__ dst, int D,
                                                       const float* __restrict__ g,
                                                       const float* __restrict__ psf,
                                                       double* __restrict__ partials) {
+    constexpr int CONV_TY = conv_ty<RY>();
     constexpr int TH = CONV_TY + P - 1;
     constexpr int TW = CONV_TX + P - 1;
-    constexpr int LS = conv_stride(TW);  // odd multiple-of-8-plus-1 stride: conflict-free rows
+    constexpr int LS = conv_stride(TW);  // 8k+1 row stride: rows start on distinct banks
     __shared__ float tile[TH * LS];
     __shared__ double red[kBlock / 64];
 
@@ -43,39 +52,50 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(const float* __restrict__ 
     }
     __syncthreads();
 
+    // thread: output rows RY*ty .. RY*ty+RY-1, columns tx0 .. tx0+7; input
+    // row RY*ty + q feeds output row RY*ty + h with kernel row q - h
     const int ty = threadIdx.x >> 3;
     const int tx0 = (threadIdx.x & 7) * CONV_RX;
-    float acc[CONV_RX];
+    float acc[RY][CONV_RX];
 #pragma unroll
-    for (int r = 0; r < CONV_RX; ++r) acc[r] = 0.0f;
-
-    for (int a = 0; a < P; ++a) {
-        const float* row = tile + (ty + a) * LS + tx0;
+    for (int h = 0; h < RY; ++h)
+#pragma unroll
+        for (int r = 0; r < CONV_RX; ++r) acc[h][r] = 0.0f;
+    for (int q = 0; q < P + RY - 1; ++q) {
+        const float* row = tile + (RY * ty + q) * LS + tx0;
         float seg[CONV_RX + P - 1];
 #pragma unroll
-        for (int q = 0; q < CONV_RX + P - 1; ++q) seg[q] = row[q];
-        const float* hrow = FLIP ? psf + (P - 1 - a) * P : psf + a * P;
+        for (int k = 0; k < CONV_RX + P - 1; ++k) seg[k] = row[k];
 #pragma unroll
-        for (int b = 0; b < P; ++b) {
-            const float h = FLIP ? hrow[P - 1 - b] : hrow[b];
+        for (int h = 0; h < RY; ++h) {
+            const int a = q - h;
+            if (a >= 0 && a < P) {
 #pragma unroll
-            for (int r = 0; r < CONV_RX; ++r) acc[r] = fmaf(h, seg[r + b], acc[r]);
+                for (int b = 0; b < P; ++b) {
+                    const float t = conv_tap<P, FLIP>(psf, a, b);
+#pragma unroll
+                    for (int r = 0; r < CONV_RX; ++r) acc[h][r] = fmaf(t, seg[r + b], acc[h][r]);
+                }
+            }
         }
     }
 
-    const int y = oy0 + ty;
     double ss = 0.0;
-    if (y < D) {
 #pragma unroll
-        for (int r = 0; r < CONV_RX; ++r) {
-            const int x = ox0 + tx0 + r;
-            if (x < D) {
-                float v = acc[r];
-                if (g) {
-                    v = g[(size_t)y * D + x] - v;
-                    ss += (double)v * (double)v;
+    for (int h = 0; h < RY; ++h) {
+        const int y = oy0 + RY * ty + h;
+        if (y < D) {
+#pragma unroll
+            for (int r = 0; r < CONV_RX; ++r) {
+                const int x = ox0 + tx0 + r;
+                if (x < D) {
+                    float v = acc[h][r];
+                    if (g) {
+                        v = g[(size_t)y * D + x] - v;
+                        ss += (double)v * (double)v;
+                    }
+                    dst[(size_t)y * D + x] = v;
                 }
-                dst[(size_t)y * D + x] = v;
             }
         }
     }
@@ -93,6 +113,7 @@ __global__ __launch_bounds__(kBlock) void conv_kernel_generic(const float* __res
                                                               int flip, double* __restrict__ partials) {
     extern __shared__ float smem[];
     __shared__ double red[kBlock / 64];
+    constexpr int CONV_TY = conv_ty<2>();
     const int TH = CONV_TY + P - 1;
     const int TW = CONV_TX + P - 1;
     const int LS = conv_stride(TW);
@@ -109,29 +130,31 @@ __global__ __launch_bounds__(kBlock) void conv_kernel_generic(const float* __res
     __syncthreads();
     const int ty = threadIdx.x >> 3;
     const int tx0 = (threadIdx.x & 7) * CONV_RX;
-    float acc[CONV_RX];
-#pragma unroll
-    for (int r = 0; r < CONV_RX; ++r) acc[r] = 0.0f;
-    for (int a = 0; a < P; ++a) {
-        const float* row = tile + (ty + a) * LS + tx0;
-        for (int b = 0; b < P; ++b) {
-            const float h = kern[a * P + b];
-#pragma unroll
-            for (int r = 0; r < CONV_RX; ++r) acc[r] = fmaf(h, row[r + b], acc[r]);
-        }
-    }
-    const int y = oy0 + ty;
     double ss = 0.0;
-    if (y < D) {
-        for (int r = 0; r < CONV_RX; ++r) {
-            const int x = ox0 + tx0 + r;
-            if (x < D) {
-                float v = acc[r];
-                if (g) {
-                    v = g[(size_t)y * D + x] - v;
-                    ss += (double)v * (double)v;
+    for (int h = 0; h < 2; ++h) {
+        float acc[CONV_RX];
+#pragma unroll
+        for (int r = 0; r < CONV_RX; ++r) acc[r] = 0.0f;
+        for (int a = 0; a < P; ++a) {
+            const float* row = tile + (2 * ty + h + a) * LS + tx0;
+            for (int b = 0; b < P; ++b) {
+                const float k = kern[a * P + b];
+#pragma unroll
+                for (int r = 0; r < CONV_RX; ++r) acc[r] = fmaf(k, row[r + b], acc[r]);
+            }
+        }
+        const int y = oy0 + 2 * ty + h;
+        if (y < D) {
+            for (int r = 0; r < CONV_RX; ++r) {
+                const int x = ox0 + tx0 + r;
+                if (x < D) {
+                    float v = acc[r];
+                    if (g) {
+                        v = g[(size_t)y * D + x] - v;
+                        ss += (double)v * (double)v;
+                    }
+                    dst[(size_t)y * D + x] = v;
                 }
-                dst[(size_t)y * D + x] = v;
             }
         }
     }
@@ -141,32 +164,52 @@ __global__ __launch_bounds__(kBlock) void conv_kernel_generic(const float* __res
     }
 }
 
+// Output-tile height: two rows per thread (fewer LDS reads per FMA) unless
+// the 64-row tiling leaves a nearly empty second round of workgroups, in
+// which case one row per thread (32-row tiles) balances better.
+static int conv_rows_per_thread(int D, int p) {
+    const long t2 = (long)((D + CONV_TX - 1) / CONV_TX) * ((D + 63) / 64);
+    const int lds2 = (64 + p - 1) * conv_stride(CONV_TX + p - 1) * 4;
+    const long slots = 256L * (160 * 1024 / lds2);
+    const long rounds = (t2 + slots - 1) / slots;
+    const double fill = (double)t2 / (double)(rounds * slots);
+    return fill >= 0.75 ? 2 : 1;
+}
+
 int conv_partials_count(int D) {
-    return ((D + CONV_TX - 1) / CONV_TX) * ((D + CONV_TY - 1) / CONV_TY);
+    // upper bound over both tilings
+    return ((D + CONV_TX - 1) / CONV_TX) * ((D + 31) / 32);
+}
+
+template <int P, int RY>
+static hipError_t launch_fixed_ry(const float* src, int S, int ext, int org, float* dst, int D, const float* g,
+                                  const float* psf, int flip, double* partials, int* n_partials, hipStream_t s) {
+    dim3 grid((D + CONV_TX - 1) / CONV_TX, (D + conv_ty<RY>() - 1) / conv_ty<RY>());
+    if (n_partials) *n_partials = (int)(grid.x * grid.y);
+    if (flip)
+        hipLaunchKernelGGL((conv_kernel<P, true, RY>), grid, dim3(kBlock), 0, s, src, S, ext, org, dst, D, g,
+                           psf, partials);
+    else
+        hipLaunchKernelGGL((conv_kernel<P, false, RY>), grid, dim3(kBlock), 0, s, src, S, ext, org, dst, D, g,
+                           psf, partials);
+    return hipGetLastError();
 }
 
 template <int P>
-static hipError_t launch_fixed(dim3 grid, const float* src, int S, int ext, int org, float* dst, int D,
-                               const float* g, const float* psf, int flip, double* partials,
-                               hipStream_t s) {
-    if (flip)
-        hipLaunchKernelGGL((conv_kernel<P, true>), grid, dim3(kBlock), 0, s, src, S, ext, org, dst, D, g,
-                           psf, partials);
-    else
-        hipLaunchKernelGGL((conv_kernel<P, false>), grid, dim3(kBlock), 0, s, src, S, ext, org, dst, D, g,
-                           psf, partials);
-    return hipGetLastError();
+static hipError_t launch_fixed(const float* src, int S, int ext, int org, float* dst, int D, const float* g,
+                               const float* psf, int flip, double* partials, int* n_partials, hipStream_t s) {
+    if (conv_rows_per_thread(D, P) == 2)
+        return launch_fixed_ry<P, 2>(src, S, ext, org, dst, D, g, psf, flip, partials, n_partials, s);
+    return launch_fixed_ry<P, 1>(src, S, ext, org, dst, D, g, psf, flip, partials, n_partials, s);
 }
 
 hipError_t launch_conv(const float* src, int S, int ext, int org, float* dst, int D, const float* g,
                        const float* psf, int p, int flip, double* partials, int* n_partials,
                        hipStream_t s) {
-    dim3 grid((D + CONV_TX - 1) / CONV_TX, (D + CONV_TY - 1) / CONV_TY);
-    if (n_partials) *n_partials = (int)(grid.x * grid.y);
     switch (p) {
 #define MLBA_CONV_CASE(PP) \
     case PP:               \
-        return launch_fixed<PP>(grid, src, S, ext, org, dst, D, g, psf, flip, partials, s);
+        return launch_fixed<PP>(src, S, ext, org, dst, D, g, psf, flip, partials, n_partials, s);
         MLBA_CONV_CASE(1)
         MLBA_CONV_CASE(3)
         MLBA_CONV_CASE(5)
@@ -186,7 +229,10 @@ hipError_t launch_conv(const float* src, int S, int ext, int org, float* dst, in
         MLBA_CONV_CASE(33)
 #undef MLBA_CONV_CASE
         default: {
-            const int TH = CONV_TY + p - 1;
+            constexpr int TY = conv_ty<2>();
+            dim3 grid((D + CONV_TX - 1) / CONV_TX, (D + TY - 1) / TY);
+            if (n_partials) *n_partials = (int)(grid.x * grid.y);
+            const int TH = TY + p - 1;
             const int LS = conv_stride(CONV_TX + p - 1);
             const size_t lds = (size_t)(TH * LS + p * p) * sizeof(float);
             if (lds > 64 * 1024) return hipErrorInvalidValue;

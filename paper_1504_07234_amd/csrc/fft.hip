@@ -11,7 +11,7 @@
 //   3. rows: gather transposed, inverse transform, write rows.
 //
 // The complex FFT is a mixed-radix (8, 4, 2, 3) Stockham autosort transform
-// held in LDS; every thread carries up to 16 complex values per stage in
+// held in LDS; every thread carries up to 8 complex values per stage in
 // registers between the read and the write barrier.  Twiddles come from a
 // table of exp(-2 pi i q / n) computed in double precision on the host.
 // The DCT-II of length n is computed from a length-n complex FFT of the even
@@ -23,13 +23,34 @@
 
 namespace mlba {
 
-constexpr int FFT_EPT = 16;  // complex values per thread per stage (max)
-constexpr int FFT_MAX_ELEMS = FFT_EPT * kBlock;  // complex values per workgroup (32 KB of LDS)
+constexpr int FFT_EPT = 8;  // complex values per thread per stage (max)
+constexpr int FFT_MAX_ELEMS = FFT_EPT * kBlock;  // complex values per workgroup (16 KB of LDS)
+
+// LDS slot of element i: one padding slot after every 8 elements, so that the
+// power-of-two strides of the Stockham writes do not pile onto one bank.
+__host__ __device__ __forceinline__ int lds_slot(int i) { return i + (i >> 3); }
+__host__ __device__ constexpr int lds_data_slots(int elems) { return elems + elems / 8 + 1; }
+__host__ __device__ constexpr size_t lds_bytes(int elems, int n) { return (size_t)lds_data_slots(elems) * 8 + 0 * n; }
 
 template <int DIR>
 __device__ __forceinline__ float2 twiddle(const float2* __restrict__ tw, int q) {
     const float2 w = tw[q];
     return DIR < 0 ? w : make_float2(w.x, -w.y);
+}
+
+// w[r] = W^(r*e) for r = 1..R-1, W = exp(DIR 2 pi i / n), e = jm * step.
+// Powers 1, 2, 4 come from the table; the others are one product away.
+template <int R, int DIR>
+__device__ __forceinline__ void twiddle_powers(const float2* __restrict__ tw, int e, int n, float2* w) {
+    w[1] = twiddle<DIR>(tw, e);
+    if constexpr (R >= 3) w[2] = twiddle<DIR>(tw, 2 * e);
+    if constexpr (R >= 4) w[3] = cmul(w[1], w[2]);
+    if constexpr (R == 8) {
+        w[4] = twiddle<DIR>(tw, 4 * e);
+        w[5] = cmul(w[1], w[4]);
+        w[6] = cmul(w[2], w[4]);
+        w[7] = cmul(w[3], w[4]);
+    }
 }
 
 // a * (DIR i)
@@ -85,28 +106,35 @@ __device__ __forceinline__ void dft(float2* v) {
     }
 }
 
-// One Stockham stage of radix R over `batch` sequences of length n stored
-// back to back in `buf`.  Ns is the product of the radices already applied.
+// One Stockham stage of radix R.  The workgroup holds up to kBlock >> seq_shift
+// sequences of length n back to back in `buf`; sequence b is owned by the
+// 2^seq_shift threads with threadIdx.x >> seq_shift == b (only the first nseq
+// sequences are live).  Ns is the product of the radices already applied;
+// ns_shift = log2(Ns) when Ns is a power of two (every radix-2/4/8 stage,
+// since radix-3 stages run last), -1 otherwise.
 template <int R, int DIR>
-__device__ __forceinline__ void stockham_stage(float2* buf, int n, int batch, int Ns,
-                                               const float2* __restrict__ tw) {
+__device__ __forceinline__ void stockham_stage(float2* buf, int n, int nseq, int seq_shift, int Ns,
+                                               int ns_shift, const float2* __restrict__ tw) {
     constexpr int MAXB = (FFT_EPT + R - 1) / R;
     const int nb = n / R;
-    const int total = nb * batch;
+    const int nthr = 1 << seq_shift;
+    const int b = threadIdx.x >> seq_shift;
+    const int tl = threadIdx.x & (nthr - 1);
+    const bool live = b < nseq;
     const int step = n / (Ns * R);
+    const int base0 = b * n;
     float2 v[MAXB][R];
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
-        const int t = threadIdx.x + i * kBlock;
-        if (t < total) {
-            const int b = t / nb;
-            const int j = t - b * nb;
-            const int jm = j % Ns;
-            const float2* src = buf + b * n + j;
+        const int j = tl + i * nthr;
+        if (live && j < nb) {
+            const int jm = ns_shift >= 0 ? (j & (Ns - 1)) : (j % Ns);
+            float2 w[R];
+            if (jm > 0) twiddle_powers<R, DIR>(tw, jm * step, n, w);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                float2 x = src[r * nb];
-                if (r > 0) x = cmul(x, twiddle<DIR>(tw, r * jm * step));
+                float2 x = buf[lds_slot(base0 + j + r * nb)];
+                if (r > 0 && jm > 0) x = cmul(x, w[r]);
                 v[i][r] = x;
             }
             dft<R, DIR>(v[i]);
@@ -115,31 +143,30 @@ __device__ __forceinline__ void stockham_stage(float2* buf, int n, int batch, in
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
-        const int t = threadIdx.x + i * kBlock;
-        if (t < total) {
-            const int b = t / nb;
-            const int j = t - b * nb;
-            const int jm = j % Ns;
-            float2* dst = buf + b * n + (j - jm) * R + jm;
+        const int j = tl + i * nthr;
+        if (live && j < nb) {
+            const int jm = ns_shift >= 0 ? (j & (Ns - 1)) : (j % Ns);
+            const int dst = base0 + (j - jm) * R + jm;
 #pragma unroll
-            for (int r = 0; r < R; ++r) dst[r * Ns] = v[i][r];
+            for (int r = 0; r < R; ++r) buf[lds_slot(dst + r * Ns)] = v[i][r];
         }
     }
     __syncthreads();
 }
 
-// In-LDS transform of `batch` sequences; DIR = -1 forward, +1 inverse
+// In-LDS transform of nseq sequences; DIR = -1 forward, +1 inverse
 // (unnormalised).  The caller synchronises before the call.
 template <int DIR>
-__device__ void lds_fft(float2* buf, const FftDesc& fd, int batch, const float2* __restrict__ tw) {
-    int Ns = 1;
+__device__ void lds_fft(float2* buf, const FftDesc& fd, int nseq, int seq_shift, const float2* __restrict__ tw) {
+    int Ns = 1, ns_shift = 0;
     for (int s = 0; s < fd.nst; ++s) {
         const int R = fd.radix[s];
-        if (R == 8) stockham_stage<8, DIR>(buf, fd.n, batch, Ns, tw);
-        else if (R == 4) stockham_stage<4, DIR>(buf, fd.n, batch, Ns, tw);
-        else if (R == 2) stockham_stage<2, DIR>(buf, fd.n, batch, Ns, tw);
-        else stockham_stage<3, DIR>(buf, fd.n, batch, Ns, tw);
+        if (R == 8) stockham_stage<8, DIR>(buf, fd.n, nseq, seq_shift, Ns, ns_shift, tw);
+        else if (R == 4) stockham_stage<4, DIR>(buf, fd.n, nseq, seq_shift, Ns, ns_shift, tw);
+        else if (R == 2) stockham_stage<2, DIR>(buf, fd.n, nseq, seq_shift, Ns, ns_shift, tw);
+        else stockham_stage<3, DIR>(buf, fd.n, nseq, seq_shift, Ns, ns_shift, tw);
         Ns *= R;
+        ns_shift = (R == 3 || ns_shift < 0) ? -1 : ns_shift + (R == 8 ? 3 : (R == 4 ? 2 : 1));
     }
 }
 
@@ -147,89 +174,95 @@ __device__ void lds_fft(float2* buf, const FftDesc& fd, int batch, const float2*
 // BCCB (Algorithm 1)
 // ---------------------------------------------------------------------------
 
-// G row pairs per workgroup -> T[k][row], k = 0..n/2 (row stride n complex)
+// G row pairs per workgroup -> T[k][row], k = 0..n/2 (row stride ts complex)
 __global__ __launch_bounds__(kBlock) void fft_rows_r2c_kernel(const float* __restrict__ src, int n,
-                                                              float2* __restrict__ T, FftDesc fd,
-                                                              const float2* __restrict__ tw, int G) {
+                                                              float2* __restrict__ T, int ts, FftDesc fd,
+                                                              const float2* __restrict__ tw, int G, int seq_shift) {
     extern __shared__ float2 buf[];
     const int row0 = blockIdx.x * 2 * G;
     for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
         const int g = idx / n;
         const int x = idx - g * n;
         const size_t ra = (size_t)(row0 + 2 * g) * n;
-        buf[idx] = make_float2(src[ra + x], src[ra + n + x]);
+        buf[lds_slot(idx)] = make_float2(src[ra + x], src[ra + n + x]);
     }
     __syncthreads();
-    lds_fft<-1>(buf, fd, G, tw);
+    lds_fft<-1>(buf, fd, G, seq_shift, tw);
     const int half = n / 2 + 1;
     for (int idx = threadIdx.x; idx < G * half; idx += kBlock) {
         const int k = idx / G;
         const int g = idx - k * G;
-        const float2 Z = buf[g * n + k];
-        const float2 Zc = cconj(buf[g * n + (k == 0 ? 0 : n - k)]);
+        const float2 Z = buf[lds_slot(g * n + k)];
+        const float2 Zc = cconj(buf[lds_slot(g * n + (k == 0 ? 0 : n - k))]);
         const float2 Xa = cscale(cadd(Z, Zc), 0.5f);
         const float2 D = csub(Z, Zc);
         const float2 Xb = make_float2(0.5f * D.y, -0.5f * D.x);  // D / (2i)
-        *reinterpret_cast<float4*>(T + (size_t)k * n + row0 + 2 * g) = make_float4(Xa.x, Xa.y, Xb.x, Xb.y);
+        *reinterpret_cast<float4*>(T + (size_t)k * ts + row0 + 2 * g) = make_float4(Xa.x, Xa.y, Xb.x, Xb.y);
     }
 }
 
 // CC rows of T per workgroup: forward FFT along the column index, then either
 // the filter inv / (spec + alpha) and the inverse FFT (mode 0), or |.|^2 into
 // `power` (mode 1).
-__global__ __launch_bounds__(kBlock) void fft_cols_kernel(float2* __restrict__ T, int n,
+__global__ __launch_bounds__(kBlock) void fft_cols_kernel(float2* __restrict__ T, int n, int ts,
                                                           const float* __restrict__ spec, float alpha,
                                                           float inv, FftDesc fd,
                                                           const float2* __restrict__ tw, int CC, int mode,
-                                                          float* __restrict__ power) {
+                                                          float* __restrict__ power, int seq_shift) {
     extern __shared__ float2 buf[];
     const int half = n / 2 + 1;
     const int k0 = blockIdx.x * CC;
     const int cc = min(CC, half - k0);
-    const size_t base = (size_t)k0 * n;
-    for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) buf[idx] = T[base + idx];
+    const size_t base = (size_t)k0 * n;  // dense [n/2+1][n] spectrum
+    for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
+        const int q = idx / n;
+        buf[lds_slot(idx)] = T[(size_t)(k0 + q) * ts + (idx - q * n)];
+    }
     __syncthreads();
-    lds_fft<-1>(buf, fd, cc, tw);
+    lds_fft<-1>(buf, fd, cc, seq_shift, tw);
     if (mode == 1) {
         for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
-            const float2 v = buf[idx];
+            const float2 v = buf[lds_slot(idx)];
             power[base + idx] = v.x * v.x + v.y * v.y;
         }
         return;
     }
     for (int idx = threadIdx.x; idx < cc * n; idx += kBlock)
-        buf[idx] = cscale(buf[idx], inv / (spec[base + idx] + alpha));
+        buf[lds_slot(idx)] = cscale(buf[lds_slot(idx)], inv / (spec[base + idx] + alpha));
     __syncthreads();
-    lds_fft<1>(buf, fd, cc, tw);
-    for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) T[base + idx] = buf[idx];
+    lds_fft<1>(buf, fd, cc, seq_shift, tw);
+    for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
+        const int q = idx / n;
+        T[(size_t)(k0 + q) * ts + (idx - q * n)] = buf[lds_slot(idx)];
+    }
 }
 
-__global__ __launch_bounds__(kBlock) void fft_rows_c2r_kernel(const float2* __restrict__ T, int n,
+__global__ __launch_bounds__(kBlock) void fft_rows_c2r_kernel(const float2* __restrict__ T, int n, int ts,
                                                               float* __restrict__ dst, FftDesc fd,
-                                                              const float2* __restrict__ tw, int G) {
+                                                              const float2* __restrict__ tw, int G, int seq_shift) {
     extern __shared__ float2 buf[];
     const int row0 = blockIdx.x * 2 * G;
     const int half = n / 2 + 1;
     for (int idx = threadIdx.x; idx < G * half; idx += kBlock) {
         const int k = idx / G;
         const int g = idx - k * G;
-        const float4 q = *reinterpret_cast<const float4*>(T + (size_t)k * n + row0 + 2 * g);
+        const float4 q = *reinterpret_cast<const float4*>(T + (size_t)k * ts + row0 + 2 * g);
         float2 Xa = make_float2(q.x, q.y), Xb = make_float2(q.z, q.w);
         const bool edge = (k == 0) || (2 * k == n);
         if (edge) {  // spectra of real rows are real at DC and Nyquist
             Xa.y = 0.0f;
             Xb.y = 0.0f;
         }
-        buf[g * n + k] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);  // Xa + i Xb
-        if (!edge) buf[g * n + n - k] = make_float2(Xa.x + Xb.y, -Xa.y + Xb.x);  // conj(Xa) + i conj(Xb)
+        buf[lds_slot(g * n + k)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);  // Xa + i Xb
+        if (!edge) buf[lds_slot(g * n + n - k)] = make_float2(Xa.x + Xb.y, -Xa.y + Xb.x);  // conj(Xa) + i conj(Xb)
     }
     __syncthreads();
-    lds_fft<1>(buf, fd, G, tw);
+    lds_fft<1>(buf, fd, G, seq_shift, tw);
     for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
         const int g = idx / n;
         const int x = idx - g * n;
         const size_t ra = (size_t)(row0 + 2 * g) * n;
-        const float2 v = buf[idx];
+        const float2 v = buf[lds_slot(idx)];
         dst[ra + x] = v.x;
         dst[ra + n + x] = v.y;
     }
@@ -244,41 +277,41 @@ __device__ __forceinline__ int dct_perm(int l, int n) { return (l & 1) ? n - 1 -
 
 __device__ __forceinline__ float re_mul(float2 w, float2 v) { return w.x * v.x - w.y * v.y; }
 
-// G row pairs -> Tr[k][row] (real, row stride n), k = 0..n-1
+// G row pairs -> Tr[k][row] (real, row stride ts), k = 0..n-1
 __global__ __launch_bounds__(kBlock) void dct_rows_fwd_kernel(const float* __restrict__ src, int n,
-                                                              float* __restrict__ Tr, FftDesc fd,
+                                                              float* __restrict__ Tr, int ts, FftDesc fd,
                                                               const float2* __restrict__ tw,
-                                                              const float2* __restrict__ dtw, int G) {
+                                                              const float2* __restrict__ dtw, int G, int seq_shift) {
     extern __shared__ float2 buf[];
     const int row0 = blockIdx.x * 2 * G;
     for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
         const int g = idx / n;
         const int x = idx - g * n;
         const size_t ra = (size_t)(row0 + 2 * g) * n;
-        buf[g * n + dct_perm(x, n)] = make_float2(src[ra + x], src[ra + n + x]);
+        buf[lds_slot(g * n + dct_perm(x, n))] = make_float2(src[ra + x], src[ra + n + x]);
     }
     __syncthreads();
-    lds_fft<-1>(buf, fd, G, tw);
+    lds_fft<-1>(buf, fd, G, seq_shift, tw);
     for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
         const int k = idx / G;
         const int g = idx - k * G;
-        const float2 Z = buf[g * n + k];
-        const float2 Zc = cconj(buf[g * n + (k == 0 ? 0 : n - k)]);
+        const float2 Z = buf[lds_slot(g * n + k)];
+        const float2 Zc = cconj(buf[lds_slot(g * n + (k == 0 ? 0 : n - k))]);
         const float2 Va = cscale(cadd(Z, Zc), 0.5f);
         const float2 D = csub(Z, Zc);
         const float2 Vb = make_float2(0.5f * D.y, -0.5f * D.x);
         const float2 w = dtw[k];
-        *reinterpret_cast<float2*>(Tr + (size_t)k * n + row0 + 2 * g) = make_float2(re_mul(w, Va), re_mul(w, Vb));
+        *reinterpret_cast<float2*>(Tr + (size_t)k * ts + row0 + 2 * g) = make_float2(re_mul(w, Va), re_mul(w, Vb));
     }
 }
 
 // CP pairs of Tr rows per workgroup: DCT-II along the row, multiply by
 // inv / (spec + alpha), DCT-III back.
-__global__ __launch_bounds__(kBlock) void dct_cols_filter_kernel(float* __restrict__ Tr, int n,
+__global__ __launch_bounds__(kBlock) void dct_cols_filter_kernel(float* __restrict__ Tr, int n, int ts,
                                                                  const float* __restrict__ spec, float alpha,
                                                                  float inv, FftDesc fd,
                                                                  const float2* __restrict__ tw,
-                                                                 const float2* __restrict__ dtw, int CP) {
+                                                                 const float2* __restrict__ dtw, int CP, int seq_shift) {
     extern __shared__ float2 buf[];
     const int pairs = n / 2;
     const int p0 = blockIdx.x * CP;
@@ -287,11 +320,11 @@ __global__ __launch_bounds__(kBlock) void dct_cols_filter_kernel(float* __restri
     for (int idx = threadIdx.x; idx < total; idx += kBlock) {
         const int q = idx / n;
         const int l = idx - q * n;
-        const size_t r1 = (size_t)(2 * (p0 + q)) * n;
-        buf[q * n + dct_perm(l, n)] = make_float2(Tr[r1 + l], Tr[r1 + n + l]);
+        const size_t r1 = (size_t)(2 * (p0 + q)) * ts;
+        buf[lds_slot(q * n + dct_perm(l, n))] = make_float2(Tr[r1 + l], Tr[r1 + ts + l]);
     }
     __syncthreads();
-    lds_fft<-1>(buf, fd, cp, tw);
+    lds_fft<-1>(buf, fd, cp, seq_shift, tw);
 
     float2 keep[FFT_EPT];
 #pragma unroll
@@ -300,15 +333,15 @@ __global__ __launch_bounds__(kBlock) void dct_cols_filter_kernel(float* __restri
         if (idx < total) {
             const int q = idx / n;
             const int l = idx - q * n;
-            const float2 Z = buf[q * n + l];
-            const float2 Zc = cconj(buf[q * n + (l == 0 ? 0 : n - l)]);
+            const float2 Z = buf[lds_slot(q * n + l)];
+            const float2 Zc = cconj(buf[lds_slot(q * n + (l == 0 ? 0 : n - l))]);
             const float2 V1 = cscale(cadd(Z, Zc), 0.5f);
             const float2 D = csub(Z, Zc);
             const float2 V2 = make_float2(0.5f * D.y, -0.5f * D.x);
             const float2 w = dtw[l];
-            const size_t r1 = (size_t)(2 * (p0 + q)) * n;
-            const float f1 = inv / (spec[r1 + l] + alpha);
-            const float f2 = inv / (spec[r1 + n + l] + alpha);
+            const size_t s1 = (size_t)(2 * (p0 + q)) * n;  // dense [n][n] spectrum
+            const float f1 = inv / (spec[s1 + l] + alpha);
+            const float f2 = inv / (spec[s1 + n + l] + alpha);
             keep[i] = make_float2(re_mul(w, V1) * f1, re_mul(w, V2) * f2);
         }
     }
@@ -316,7 +349,7 @@ __global__ __launch_bounds__(kBlock) void dct_cols_filter_kernel(float* __restri
 #pragma unroll
     for (int i = 0; i < FFT_EPT; ++i) {
         const int idx = threadIdx.x + i * kBlock;
-        if (idx < total) buf[idx] = keep[i];
+        if (idx < total) buf[lds_slot(idx)] = keep[i];
     }
     __syncthreads();
 #pragma unroll
@@ -325,8 +358,8 @@ __global__ __launch_bounds__(kBlock) void dct_cols_filter_kernel(float* __restri
         if (idx < total) {
             const int q = idx / n;
             const int l = idx - q * n;
-            const float2 Y = buf[q * n + l];
-            const float2 Yr = (l == 0) ? make_float2(0.0f, 0.0f) : buf[q * n + n - l];
+            const float2 Y = buf[lds_slot(q * n + l)];
+            const float2 Yr = (l == 0) ? make_float2(0.0f, 0.0f) : buf[lds_slot(q * n + n - l)];
             const float2 wc = cconj(dtw[l]);
             const float2 V1 = cmul(wc, make_float2(Y.x, -Yr.x));
             const float2 V2 = cmul(wc, make_float2(Y.y, -Yr.y));
@@ -337,31 +370,31 @@ __global__ __launch_bounds__(kBlock) void dct_cols_filter_kernel(float* __restri
 #pragma unroll
     for (int i = 0; i < FFT_EPT; ++i) {
         const int idx = threadIdx.x + i * kBlock;
-        if (idx < total) buf[idx] = keep[i];
+        if (idx < total) buf[lds_slot(idx)] = keep[i];
     }
     __syncthreads();
-    lds_fft<1>(buf, fd, cp, tw);
+    lds_fft<1>(buf, fd, cp, seq_shift, tw);
     for (int idx = threadIdx.x; idx < total; idx += kBlock) {
         const int q = idx / n;
         const int l = idx - q * n;
-        const size_t r1 = (size_t)(2 * (p0 + q)) * n;
-        const float2 v = buf[q * n + dct_perm(l, n)];
+        const size_t r1 = (size_t)(2 * (p0 + q)) * ts;
+        const float2 v = buf[lds_slot(q * n + dct_perm(l, n))];
         Tr[r1 + l] = v.x;
-        Tr[r1 + n + l] = v.y;
+        Tr[r1 + ts + l] = v.y;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void dct_rows_inv_kernel(const float* __restrict__ Tr, int n,
+__global__ __launch_bounds__(kBlock) void dct_rows_inv_kernel(const float* __restrict__ Tr, int n, int ts,
                                                               float* __restrict__ dst, FftDesc fd,
                                                               const float2* __restrict__ tw,
-                                                              const float2* __restrict__ dtw, int G) {
+                                                              const float2* __restrict__ dtw, int G, int seq_shift) {
     extern __shared__ float2 buf[];
     const int row0 = blockIdx.x * 2 * G;
     const int total = G * n;
     for (int idx = threadIdx.x; idx < total; idx += kBlock) {
         const int k = idx / G;
         const int g = idx - k * G;
-        buf[g * n + k] = *reinterpret_cast<const float2*>(Tr + (size_t)k * n + row0 + 2 * g);
+        buf[lds_slot(g * n + k)] = *reinterpret_cast<const float2*>(Tr + (size_t)k * ts + row0 + 2 * g);
     }
     __syncthreads();
     float2 keep[FFT_EPT];
@@ -371,8 +404,8 @@ __global__ __launch_bounds__(kBlock) void dct_rows_inv_kernel(const float* __res
         if (idx < total) {
             const int g = idx / n;
             const int k = idx - g * n;
-            const float2 Y = buf[g * n + k];
-            const float2 Yr = (k == 0) ? make_float2(0.0f, 0.0f) : buf[g * n + n - k];
+            const float2 Y = buf[lds_slot(g * n + k)];
+            const float2 Yr = (k == 0) ? make_float2(0.0f, 0.0f) : buf[lds_slot(g * n + n - k)];
             const float2 wc = cconj(dtw[k]);
             const float2 Va = cmul(wc, make_float2(Y.x, -Yr.x));
             const float2 Vb = cmul(wc, make_float2(Y.y, -Yr.y));
@@ -383,15 +416,15 @@ __global__ __launch_bounds__(kBlock) void dct_rows_inv_kernel(const float* __res
 #pragma unroll
     for (int i = 0; i < FFT_EPT; ++i) {
         const int idx = threadIdx.x + i * kBlock;
-        if (idx < total) buf[idx] = keep[i];
+        if (idx < total) buf[lds_slot(idx)] = keep[i];
     }
     __syncthreads();
-    lds_fft<1>(buf, fd, G, tw);
+    lds_fft<1>(buf, fd, G, seq_shift, tw);
     for (int idx = threadIdx.x; idx < total; idx += kBlock) {
         const int g = idx / n;
         const int x = idx - g * n;
         const size_t ra = (size_t)(row0 + 2 * g) * n;
-        const float2 v = buf[g * n + dct_perm(x, n)];
+        const float2 v = buf[lds_slot(g * n + dct_perm(x, n))];
         dst[ra + x] = v.x;
         dst[ra + n + x] = v.y;
     }
@@ -434,6 +467,16 @@ __global__ __launch_bounds__(kBlock) void pad_psf_kernel(const float* __restrict
 // launch helpers
 // ---------------------------------------------------------------------------
 
+// threads per sequence = kBlock / batch (batch a power of two)
+static int seq_shift_for(int batch) {
+    int sh = 8;  // log2(kBlock)
+    while (batch > 1) {
+        batch >>= 1;
+        --sh;
+    }
+    return sh;
+}
+
 static int pick_pairs_per_block(int n) {
     // two rows per pair; stay within the LDS budget; keep >= ~512 workgroups
     int target = n >= 2048 ? 2 : 1;
@@ -443,71 +486,75 @@ static int pick_pairs_per_block(int n) {
 }
 
 static int pick_cols_per_block(int n) {
-    int cc = 1024 / n;
-    if (cc < 1) cc = 1;
-    while (cc * n > FFT_MAX_ELEMS) cc /= 2;
+    int cc = 1;  // largest power of two with cc * n <= min(4096, FFT_MAX_ELEMS)
+    while ((cc * 2) * n <= FFT_MAX_ELEMS && (cc * 2) * n <= 4096) cc *= 2;
     return cc;
 }
 
-hipError_t launch_fft_rows_r2c(const float* src, int n, float2* T, const FftDesc& fd, const float2* tw,
+hipError_t launch_fft_rows_r2c(const float* src, int n, float2* T, int ts, const FftDesc& fd, const float2* tw,
                                hipStream_t s) {
     const int G = pick_pairs_per_block(n);
-    const size_t lds = (size_t)G * n * sizeof(float2);
-    hipLaunchKernelGGL(fft_rows_r2c_kernel, dim3(n / (2 * G)), dim3(kBlock), lds, s, src, n, T, fd, tw, G);
+    const size_t lds = lds_bytes(G * n, n);
+    hipLaunchKernelGGL(fft_rows_r2c_kernel, dim3(n / (2 * G)), dim3(kBlock), lds, s, src, n, T, ts, fd, tw, G,
+                       seq_shift_for(G));
     return hipGetLastError();
 }
 
-hipError_t launch_fft_cols_filter(float2* T, int n, const float* spec, float alpha, float inv, const FftDesc& fd,
-                                  const float2* tw, hipStream_t s) {
+hipError_t launch_fft_cols_filter(float2* T, int n, int ts, const float* spec, float alpha, float inv,
+                                  const FftDesc& fd, const float2* tw, hipStream_t s) {
     const int CC = pick_cols_per_block(n);
     const int half = n / 2 + 1;
-    const size_t lds = (size_t)CC * n * sizeof(float2);
-    hipLaunchKernelGGL(fft_cols_kernel, dim3((half + CC - 1) / CC), dim3(kBlock), lds, s, T, n, spec, alpha,
-                       inv, fd, tw, CC, 0, (float*)nullptr);
+    const size_t lds = lds_bytes(CC * n, n);
+    hipLaunchKernelGGL(fft_cols_kernel, dim3((half + CC - 1) / CC), dim3(kBlock), lds, s, T, n, ts, spec, alpha,
+                       inv, fd, tw, CC, 0, (float*)nullptr, seq_shift_for(CC));
     return hipGetLastError();
 }
 
-hipError_t launch_fft_cols_power(const float2* T, int n, float* spec, const FftDesc& fd, const float2* tw,
-                                 hipStream_t s) {
+hipError_t launch_fft_cols_power(const float2* T, int n, int ts, float* spec, const FftDesc& fd,
+                                 const float2* tw, hipStream_t s) {
     const int CC = pick_cols_per_block(n);
     const int half = n / 2 + 1;
-    const size_t lds = (size_t)CC * n * sizeof(float2);
+    const size_t lds = lds_bytes(CC * n, n);
     hipLaunchKernelGGL(fft_cols_kernel, dim3((half + CC - 1) / CC), dim3(kBlock), lds, s,
-                       const_cast<float2*>(T), n, (const float*)nullptr, 0.0f, 1.0f, fd, tw, CC, 1, spec);
+                       const_cast<float2*>(T), n, ts, (const float*)nullptr, 0.0f, 1.0f, fd, tw, CC, 1, spec,
+                       seq_shift_for(CC));
     return hipGetLastError();
 }
 
-hipError_t launch_fft_rows_c2r(const float2* T, int n, float* dst, const FftDesc& fd, const float2* tw,
+hipError_t launch_fft_rows_c2r(const float2* T, int n, int ts, float* dst, const FftDesc& fd, const float2* tw,
                                hipStream_t s) {
     const int G = pick_pairs_per_block(n);
-    const size_t lds = (size_t)G * n * sizeof(float2);
-    hipLaunchKernelGGL(fft_rows_c2r_kernel, dim3(n / (2 * G)), dim3(kBlock), lds, s, T, n, dst, fd, tw, G);
+    const size_t lds = lds_bytes(G * n, n);
+    hipLaunchKernelGGL(fft_rows_c2r_kernel, dim3(n / (2 * G)), dim3(kBlock), lds, s, T, n, ts, dst, fd, tw, G,
+                       seq_shift_for(G));
     return hipGetLastError();
 }
 
-hipError_t launch_dct_rows_fwd(const float* src, int n, float* Tr, const FftDesc& fd, const float2* tw,
+hipError_t launch_dct_rows_fwd(const float* src, int n, float* Tr, int ts, const FftDesc& fd, const float2* tw,
                                const float2* dtw, hipStream_t s) {
     const int G = pick_pairs_per_block(n);
-    const size_t lds = (size_t)G * n * sizeof(float2);
-    hipLaunchKernelGGL(dct_rows_fwd_kernel, dim3(n / (2 * G)), dim3(kBlock), lds, s, src, n, Tr, fd, tw, dtw, G);
+    const size_t lds = lds_bytes(G * n, n);
+    hipLaunchKernelGGL(dct_rows_fwd_kernel, dim3(n / (2 * G)), dim3(kBlock), lds, s, src, n, Tr, ts, fd, tw, dtw, G,
+                       seq_shift_for(G));
     return hipGetLastError();
 }
 
-hipError_t launch_dct_cols_filter(float* Tr, int n, const float* spec, float alpha, float inv, const FftDesc& fd,
-                                  const float2* tw, const float2* dtw, hipStream_t s) {
+hipError_t launch_dct_cols_filter(float* Tr, int n, int ts, const float* spec, float alpha, float inv,
+                                  const FftDesc& fd, const float2* tw, const float2* dtw, hipStream_t s) {
     int CP = pick_cols_per_block(n);
     const int pairs = n / 2;
-    const size_t lds = (size_t)CP * n * sizeof(float2);
-    hipLaunchKernelGGL(dct_cols_filter_kernel, dim3((pairs + CP - 1) / CP), dim3(kBlock), lds, s, Tr, n, spec,
-                       alpha, inv, fd, tw, dtw, CP);
+    const size_t lds = lds_bytes(CP * n, n);
+    hipLaunchKernelGGL(dct_cols_filter_kernel, dim3((pairs + CP - 1) / CP), dim3(kBlock), lds, s, Tr, n, ts, spec,
+                       alpha, inv, fd, tw, dtw, CP, seq_shift_for(CP));
     return hipGetLastError();
 }
 
-hipError_t launch_dct_rows_inv(const float* Tr, int n, float* dst, const FftDesc& fd, const float2* tw,
+hipError_t launch_dct_rows_inv(const float* Tr, int n, int ts, float* dst, const FftDesc& fd, const float2* tw,
                                const float2* dtw, hipStream_t s) {
     const int G = pick_pairs_per_block(n);
-    const size_t lds = (size_t)G * n * sizeof(float2);
-    hipLaunchKernelGGL(dct_rows_inv_kernel, dim3(n / (2 * G)), dim3(kBlock), lds, s, Tr, n, dst, fd, tw, dtw, G);
+    const size_t lds = lds_bytes(G * n, n);
+    hipLaunchKernelGGL(dct_rows_inv_kernel, dim3(n / (2 * G)), dim3(kBlock), lds, s, Tr, n, ts, dst, fd, tw, dtw, G,
+                       seq_shift_for(G));
     return hipGetLastError();
 }
 

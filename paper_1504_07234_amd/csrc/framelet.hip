@@ -4,12 +4,15 @@
 // (b1 oriented as the rows of the matrix printed in section 6.1).  Band (i,j)
 // applies b_i along x and b_j along y under half-sample reflective extension.
 //
-// Data layout: one thread per column of a 16-row strip.  A workgroup covers
-// 256 - 2d output columns plus a d-column halo on each side; every thread
-// streams its column (16 + 2d rows, coalesced across the wavefront) through
-// registers, applies the y-direction filters there, parks the three
-// y-filtered columns in LDS, and after one barrier applies the x-direction
-// filters from LDS for the interior columns.
+// Analysis + Bregman update: one thread per column and 8-row strip, no LDS;
+// the x-direction taps at x-d and x+d are read from memory (cache hits) and
+// every old coefficient of the strip is loaded before the first store.
+// Synthesis: one thread per column of an 8-row strip; a workgroup covers 256
+// - 2d output columns plus a d-column halo on each side.  Every thread
+// streams its column of each of the 9 inputs (8 + 2d rows, coalesced across
+// the wavefront) through registers, applies the y-direction transposes there,
+// parks the three partial sums in LDS and, after one barrier, applies the
+// x-direction transposes for the interior columns.
 //
 // The transpose (synthesis) uses the fact that for a symmetric mask the
 // reflective operator's transpose is the mirrored mask applied to the
@@ -22,66 +25,79 @@
 
 namespace mlba {
 
-constexpr int FR_TY = 16;
+constexpr int FR_TY = 8;
 constexpr float kB1 = 0.35355339059327376f;  // sqrt(2) / 4
 
 // pair (i, j) != (0, 0) -> position in the level's band block
 __host__ __device__ constexpr int pair_slot(int i, int j) { return i * 3 + j - 1; }
+
+// Analysis of one level: one thread per column, AN_TY rows per thread.  The
+// x-direction filters read the two neighbouring columns straight from memory
+// (cache hits); every old coefficient of the strip is loaded before the first
+// store so that 9 * AN_TY independent loads are in flight per thread.
+constexpr int AN_TY = 8;
 
 template <int D>
 __global__ __launch_bounds__(kBlock) void analysis_level_kernel(const float* __restrict__ v, int N,
                                                                 float* __restrict__ zlev,
                                                                 float* __restrict__ low,
                                                                 int accum_bands, int accum_low) {
-    constexpr int IW = kBlock - 2 * D;
-    __shared__ float gy[3][FR_TY][kBlock];
-    const int x0 = blockIdx.x * IW;
-    const int y0 = blockIdx.y * FR_TY;
-    const int c = threadIdx.x;
-    const int gx = reflect_index(x0 - D + c, N);
-
-    float col[FR_TY + 2 * D];
-#pragma unroll
-    for (int q = 0; q < FR_TY + 2 * D; ++q) col[q] = v[(size_t)reflect_index(y0 - D + q, N) * N + gx];
-#pragma unroll
-    for (int r = 0; r < FR_TY; ++r) {
-        const float a = col[r], b = col[r + D], e = col[r + 2 * D];  // v[y-d], v[y], v[y+d]
-        gy[0][r][c] = 0.25f * a + 0.5f * b + 0.25f * e;
-        gy[1][r][c] = kB1 * (e - a);
-        gy[2][r][c] = -0.25f * a + 0.5f * b - 0.25f * e;
-    }
-    __syncthreads();
-
-    if (c < D || c >= kBlock - D) return;
-    const int x = x0 + c - D;
+    const int x = blockIdx.x * kBlock + threadIdx.x;
+    const int y0 = blockIdx.y * AN_TY;
     if (x >= N) return;
     const size_t NN = (size_t)N * N;
-    for (int r = 0; r < FR_TY; ++r) {
-        const int y = y0 + r;
-        if (y >= N) break;
-        const size_t o = (size_t)y * N + x;
+    const int rows = min(AN_TY, N - y0);
+
+    // old values of the 8 bands and the low-pass output for this strip
+    float old[AN_TY][9];
+    if (accum_bands) {
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const float l = gy[j][r][c - D], m = gy[j][r][c], rr = gy[j][r][c + D];
-            const float h0 = 0.25f * l + 0.5f * m + 0.25f * rr;
-            const float h1 = kB1 * (rr - l);
-            const float h2 = -0.25f * l + 0.5f * m - 0.25f * rr;
-            if (j == 0) {
-                if (accum_low) low[o] += h0; else low[o] = h0;
-            } else {
-                float* p0 = zlev + pair_slot(0, j) * NN + o;
-                if (accum_bands) *p0 += h0; else *p0 = h0;
-            }
-            float* p1 = zlev + pair_slot(1, j) * NN + o;
-            float* p2 = zlev + pair_slot(2, j) * NN + o;
-            if (accum_bands) {
-                *p1 += h1;
-                *p2 += h2;
-            } else {
-                *p1 = h1;
-                *p2 = h2;
+        for (int r = 0; r < AN_TY; ++r) {
+            if (r < rows) {
+                const size_t o = (size_t)(y0 + r) * N + x;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) old[r][q] = zlev[q * NN + o];
+                old[r][8] = accum_low ? low[o] : 0.0f;
             }
         }
+    }
+
+    // x-direction filters h_i on the rows y0-D .. y0+AN_TY-1+D
+    const int xl = reflect_index(x - D, N), xr = reflect_index(x + D, N);
+    float h0[AN_TY + 2 * D], h1[AN_TY + 2 * D], h2[AN_TY + 2 * D];
+#pragma unroll
+    for (int q = 0; q < AN_TY + 2 * D; ++q) {
+        const float* row = v + (size_t)reflect_index(y0 - D + q, N) * N;
+        const float a = row[xl], b = row[x], e = row[xr];
+        h0[q] = 0.25f * a + 0.5f * b + 0.25f * e;
+        h1[q] = kB1 * (e - a);
+        h2[q] = -0.25f * a + 0.5f * b - 0.25f * e;
+    }
+
+#pragma unroll
+    for (int r = 0; r < AN_TY; ++r) {
+        if (r >= rows) break;
+        const size_t o = (size_t)(y0 + r) * N + x;
+        float out[9];
+        // band (i, j) = b_j along y of h_i; slot 8 holds (0, 0)
+        const float* hh[3] = {h0, h1, h2};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const float a = hh[i][r], b = hh[i][r + D], e = hh[i][r + 2 * D];
+            const float y0v = 0.25f * a + 0.5f * b + 0.25f * e;
+            const float y1v = kB1 * (e - a);
+            const float y2v = -0.25f * a + 0.5f * b - 0.25f * e;
+            if (i == 0) out[8] = y0v; else out[pair_slot(i, 0)] = y0v;
+            out[pair_slot(i, 1)] = y1v;
+            out[pair_slot(i, 2)] = y2v;
+        }
+        if (accum_bands) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) out[q] += old[r][q];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) zlev[q * NN + o] = out[q];
+        low[o] = out[8];
     }
 }
 
@@ -174,8 +190,7 @@ __global__ __launch_bounds__(kBlock) void synthesis_level_kernel(const float* __
 
 template <int D>
 static hipError_t launch_an(const float* v, int N, float* zlev, float* low, int ab, int al, hipStream_t s) {
-    constexpr int IW = kBlock - 2 * D;
-    dim3 grid((N + IW - 1) / IW, (N + FR_TY - 1) / FR_TY);
+    dim3 grid((N + kBlock - 1) / kBlock, (N + AN_TY - 1) / AN_TY);
     hipLaunchKernelGGL((analysis_level_kernel<D>), grid, dim3(kBlock), 0, s, v, N, zlev, low, ab, al);
     return hipGetLastError();
 }

@@ -52,25 +52,26 @@ hipError_t launch_soft_threshold(const float* z, float* x, int bands, size_t ban
                                  BandMu mu, float delta, hipStream_t s);
 
 // ---- spectral preconditioner --------------------------------------------
-// BCCB: rows r2c -> T (half spectrum, transposed [n/2+1][n] complex)
-hipError_t launch_fft_rows_r2c(const float* src, int n, float2* T, const FftDesc& fd,
+// BCCB: rows r2c -> T (half spectrum, transposed [n/2+1][ts] complex; the row
+// stride ts = n + 16 keeps the transposed accesses off a single memory channel)
+hipError_t launch_fft_rows_r2c(const float* src, int n, float2* T, int ts, const FftDesc& fd,
                                const float2* tw, hipStream_t s);
 // columns: forward FFT, scale by inv / (spec + alpha), inverse FFT (in place)
-hipError_t launch_fft_cols_filter(float2* T, int n, const float* spec, float alpha, float inv,
+hipError_t launch_fft_cols_filter(float2* T, int n, int ts, const float* spec, float alpha, float inv,
                                   const FftDesc& fd, const float2* tw, hipStream_t s);
 // columns: forward FFT, write spec = |.|^2 (same transposed layout)
-hipError_t launch_fft_cols_power(const float2* T, int n, float* spec, const FftDesc& fd,
+hipError_t launch_fft_cols_power(const float2* T, int n, int ts, float* spec, const FftDesc& fd,
                                  const float2* tw, hipStream_t s);
-hipError_t launch_fft_rows_c2r(const float2* T, int n, float* dst, const FftDesc& fd,
+hipError_t launch_fft_rows_c2r(const float2* T, int n, int ts, float* dst, const FftDesc& fd,
                                const float2* tw, hipStream_t s);
 // DCT: rows DCT-II -> Tr (transposed, real [n][n]); columns DCT-II, filter,
 // DCT-III; rows DCT-III -> dst.  Unnormalised transforms; `inv` carries 1/n^2.
-hipError_t launch_dct_rows_fwd(const float* src, int n, float* Tr, const FftDesc& fd,
+hipError_t launch_dct_rows_fwd(const float* src, int n, float* Tr, int ts, const FftDesc& fd,
                                const float2* tw, const float2* dtw, hipStream_t s);
-hipError_t launch_dct_cols_filter(float* Tr, int n, const float* spec, float alpha, float inv,
+hipError_t launch_dct_cols_filter(float* Tr, int n, int ts, const float* spec, float alpha, float inv,
                                   const FftDesc& fd, const float2* tw, const float2* dtw,
                                   hipStream_t s);
-hipError_t launch_dct_rows_inv(const float* Tr, int n, float* dst, const FftDesc& fd,
+hipError_t launch_dct_rows_inv(const float* Tr, int n, int ts, float* dst, const FftDesc& fd,
                                const float2* tw, const float2* dtw, hipStream_t s);
 // spec[kx][ky] = lambda[ky][kx]^2 for the symmetrised PSF (Algorithm 3)
 hipError_t launch_dct_spectrum(const float* psf, int p, int n, float* spec, const float* costab,

@@ -51,6 +51,7 @@ bool factor_23(int n, int* a, int* b) {
 struct mlba_plan_s {
     int n = 0, p = 0, c = 0, N = 0, bc = 0, precond = 0, levels = 0, bands = 0;
     FftDesc fd{};
+    int ts = 0;                // row stride of the transposed spectral workspace
     float* psf = nullptr;
     float* spec = nullptr;     // BCCB: [n/2+1][n] |Lambda|^2 (transposed); DCT: [n][n] lambda^2
     float2* tw = nullptr;      // exp(-2 pi i q / n)
@@ -71,6 +72,10 @@ struct mlba_plan_s {
     double* rn = nullptr;      // ||r^k||^2 history ring
     int rn_cap = 0;
     std::vector<void*> allocs;
+    // phase timing
+    std::vector<hipEvent_t> prof_ev;  // (MLBA_NPHASES + 1) per recorded iteration
+    int prof_cap = 0, prof_used = 0;
+    int prof_launch[MLBA_NPHASES] = {0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -95,7 +100,14 @@ int dalloc_t(mlba_plan_s* P, T** ptr, size_t count) {
     return st;
 }
 
+void release_events(mlba_plan_s* P) {
+    for (hipEvent_t e : P->prof_ev) hipEventDestroy(e);
+    P->prof_ev.clear();
+    P->prof_cap = P->prof_used = 0;
+}
+
 void free_plan(mlba_plan_s* P) {
+    release_events(P);
     for (void* a : P->allocs) hipFree(a);
     P->allocs.clear();
     delete P;
@@ -144,14 +156,14 @@ int do_precond(mlba_plan_s* P, const float* r, float* t, double alpha, hipStream
     const float inv = (float)(1.0 / ((double)n * (double)n));
     if (P->precond == MLBA_PRECOND_BCCB) {
         float2* T = (float2*)P->swork;
-        HIPCHK(launch_fft_rows_r2c(r, n, T, P->fd, P->tw, s));
-        HIPCHK(launch_fft_cols_filter(T, n, P->spec, (float)alpha, inv, P->fd, P->tw, s));
-        HIPCHK(launch_fft_rows_c2r(T, n, t, P->fd, P->tw, s));
+        HIPCHK(launch_fft_rows_r2c(r, n, T, P->ts, P->fd, P->tw, s));
+        HIPCHK(launch_fft_cols_filter(T, n, P->ts, P->spec, (float)alpha, inv, P->fd, P->tw, s));
+        HIPCHK(launch_fft_rows_c2r(T, n, P->ts, t, P->fd, P->tw, s));
     } else if (P->precond == MLBA_PRECOND_DCT) {
         float* Tr = (float*)P->swork;
-        HIPCHK(launch_dct_rows_fwd(r, n, Tr, P->fd, P->tw, P->dtw, s));
-        HIPCHK(launch_dct_cols_filter(Tr, n, P->spec, (float)alpha, inv, P->fd, P->tw, P->dtw, s));
-        HIPCHK(launch_dct_rows_inv(Tr, n, t, P->fd, P->tw, P->dtw, s));
+        HIPCHK(launch_dct_rows_fwd(r, n, Tr, P->ts, P->fd, P->tw, P->dtw, s));
+        HIPCHK(launch_dct_cols_filter(Tr, n, P->ts, P->spec, (float)alpha, inv, P->fd, P->tw, P->dtw, s));
+        HIPCHK(launch_dct_rows_inv(Tr, n, P->ts, t, P->fd, P->tw, P->dtw, s));
     } else if (r != t) {
         HIPCHK(hipMemcpyAsync(t, r, (size_t)n * n * sizeof(float), hipMemcpyDeviceToDevice, s));
     }
@@ -162,8 +174,8 @@ int compute_spectrum(mlba_plan_s* P, hipStream_t s) {
     const int n = P->n;
     if (P->precond == MLBA_PRECOND_BCCB) {
         HIPCHK(launch_pad_psf(P->psf, P->p, P->r, n, s));
-        HIPCHK(launch_fft_rows_r2c(P->r, n, (float2*)P->swork, P->fd, P->tw, s));
-        HIPCHK(launch_fft_cols_power((const float2*)P->swork, n, P->spec, P->fd, P->tw, s));
+        HIPCHK(launch_fft_rows_r2c(P->r, n, (float2*)P->swork, P->ts, P->fd, P->tw, s));
+        HIPCHK(launch_fft_cols_power((const float2*)P->swork, n, P->ts, P->spec, P->fd, P->tw, s));
     } else if (P->precond == MLBA_PRECOND_DCT) {
         HIPCHK(launch_dct_spectrum(P->psf, P->p, n, P->spec, P->costab, s));
     }
@@ -288,6 +300,7 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
     if (!plan || !psf) return MLBA_EINVAL;
     *plan = nullptr;
     if (n < 2 || p < 1 || (p % 2) == 0 || p > n) return MLBA_EINVAL;
+    if (p > 49) return MLBA_EUNSUPPORTED;  // the blur's LDS window
     if (bc < MLBA_BC_RECT || bc > MLBA_BC_ZERO) return MLBA_EINVAL;
     if (precond < MLBA_PRECOND_BCCB || precond > MLBA_PRECOND_NONE) return MLBA_EINVAL;
     if (levels < 1 || levels > 4) return MLBA_EINVAL;
@@ -295,7 +308,7 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
     if ((1 << (levels - 1)) >= N) return MLBA_EINVAL;
     int a2 = 0, b3 = 0;
     if (precond != MLBA_PRECOND_NONE) {
-        if (!factor_23(n, &a2, &b3) || a2 < 1 || n < 8 || n > 4096) return MLBA_EUNSUPPORTED;
+        if (!factor_23(n, &a2, &b3) || a2 < 1 || n < 8 || n > 2048) return MLBA_EUNSUPPORTED;
     }
 
     mlba_plan_s* P = new (std::nothrow) mlba_plan_s();
@@ -364,14 +377,16 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
         ALLOC(P->dtw, (size_t)n);
         ALLOC(P->costab, (size_t)2 * n);
         if (precond == MLBA_PRECOND_BCCB) {
+            P->ts = n + 16;
             ALLOC(P->spec, (size_t)(n / 2 + 1) * n);
             float2* T = nullptr;
-            ALLOC(T, (size_t)(n / 2 + 1) * n);
+            ALLOC(T, (size_t)(n / 2 + 1) * P->ts);
             P->swork = T;
         } else {
+            P->ts = n + 32;
             ALLOC(P->spec, obs);
             float* Tr = nullptr;
-            ALLOC(Tr, obs);
+            ALLOC(Tr, (size_t)n * P->ts);
             P->swork = Tr;
         }
 #undef ALLOC
@@ -542,13 +557,23 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
         return MLBA_OK;
     };
 
+    const int launches[MLBA_NPHASES] = {
+        P->levels, 2, P->precond == MLBA_PRECOND_NONE ? 1 : 3, P->bc == MLBA_BC_REFLECT ? 2 : 1, P->levels};
     for (int i = 0; i < iters; ++i) {
         if (i - ring_base >= P->rn_cap) {
             if (track) STCHK(drain(i));
             ring_base = i;
         }
+        hipEvent_t* ev = nullptr;
+        if (P->prof_used < P->prof_cap) {
+            ev = P->prof_ev.data() + (size_t)P->prof_used * (MLBA_NPHASES + 1);
+            ++P->prof_used;
+            for (int q = 0; q < MLBA_NPHASES; ++q) P->prof_launch[q] += launches[q];
+        }
+        if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_SYNTHESIS], s));
         STCHK(do_synthesis(P, z, P->u, true, mub, (float)delta[i], s));
         int np = 0;
+        if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_BLUR], s));
         STCHK(do_blur(P, P->u, g, P->r, true, &np, s));
         HIPCHK(launch_sum_partials(P->partials, np, P->rn + (i - ring_base), s));
         if (stop && (i % stop->check_every) == 0) {
@@ -561,9 +586,13 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
                 break;
             }
         }
+        if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_PRECOND], s));
         STCHK(do_precond(P, P->r, P->t, alpha[i], s));
+        if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_BLUR_T], s));
         STCHK(do_blurT(P, P->t, P->w, s));
+        if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_ANALYSIS], s));
         STCHK(do_analysis(P, P->w, z, true, s));
+        if (ev) HIPCHK(hipEventRecord(ev[MLBA_NPHASES], s));
         done = i + 1;
     }
     if (!stopped) STCHK(do_synthesis(P, z, f_out, true, mub, (float)delta[done], s));
@@ -582,6 +611,46 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
         if (iters_done) *iters_done = done;
     }
     return status;
+}
+
+int mlba_profile_begin(mlba_plan_t P, int max_iters) {
+    if (!P || max_iters < 1 || max_iters > (1 << 20)) return MLBA_EINVAL;
+    release_events(P);
+    for (int q = 0; q < MLBA_NPHASES; ++q) P->prof_launch[q] = 0;
+    const size_t count = (size_t)max_iters * (MLBA_NPHASES + 1);
+    P->prof_ev.reserve(count);
+    for (size_t i = 0; i < count; ++i) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) {
+            g_last_hip = (int)err;
+            release_events(P);
+            return MLBA_EHIP;
+        }
+        P->prof_ev.push_back(e);
+    }
+    P->prof_cap = max_iters;
+    P->prof_used = 0;
+    return MLBA_OK;
+}
+
+int mlba_profile_end(mlba_plan_t P, double* ms, int* launches, int* iters) {
+    if (!P || !ms) return MLBA_EINVAL;
+    for (int q = 0; q < MLBA_NPHASES; ++q) ms[q] = 0.0;
+    for (int it = 0; it < P->prof_used; ++it) {
+        hipEvent_t* ev = P->prof_ev.data() + (size_t)it * (MLBA_NPHASES + 1);
+        HIPCHK(hipEventSynchronize(ev[MLBA_NPHASES]));
+        for (int q = 0; q < MLBA_NPHASES; ++q) {
+            float t = 0.0f;
+            HIPCHK(hipEventElapsedTime(&t, ev[q], ev[q + 1]));
+            ms[q] += (double)t;
+        }
+    }
+    if (launches)
+        for (int q = 0; q < MLBA_NPHASES; ++q) launches[q] = P->prof_launch[q];
+    if (iters) *iters = P->prof_used;
+    release_events(P);
+    return MLBA_OK;
 }
 
 }  // extern "C"

@@ -151,6 +151,18 @@ class Plan:
                                                  _stream(stream)), "mlba_threshold_synthesis")
         return out
 
+    # -- phase timing --------------------------------------------------------
+    def profile_begin(self, max_iters: int):
+        check(self._lib.mlba_profile_begin(self._h, int(max_iters)), "mlba_profile_begin")
+
+    def profile_end(self):
+        """{phase: (milliseconds summed, kernel launches)} and the iteration count."""
+        ms = (ctypes.c_double * len(_lib.PHASES))()
+        launches = (ctypes.c_int * len(_lib.PHASES))()
+        iters = ctypes.c_int()
+        check(self._lib.mlba_profile_end(self._h, ms, launches, ctypes.byref(iters)), "mlba_profile_end")
+        return {ph: (ms[i], launches[i]) for i, ph in enumerate(_lib.PHASES)}, iters.value
+
     # -- restoration -------------------------------------------------------
     def restore(self, g, *, alpha=0.05, alpha_kind: int = _lib.ALPHA_CONST, alpha_ratio: float = 1.0,
                 alpha_floor: float = 0.0, alpha_table=None, mu=1e-3, delta: float = 0.0, delta_table=None,

@@ -59,6 +59,8 @@ def test_status_strings():
     (64, 9, 0, 0, 5, _lib.EINVAL),        # too many levels
     (70, 9, 0, 0, 1, _lib.EUNSUPPORTED),  # 70 = 2 * 5 * 7 has no 2/3-smooth FFT
     (5000, 9, 0, 0, 1, _lib.EUNSUPPORTED),
+    (4096, 9, 0, 0, 1, _lib.EUNSUPPORTED),   # beyond the one-workgroup transform
+    (256, 51, 0, 0, 1, _lib.EUNSUPPORTED),   # PSF window beyond the blur's LDS tile
 ])
 def test_plan_create_rejects_bad_arguments(n, p, bc, pc, levels, expect):
     """Validation happens before any device call, so it runs on the CPU."""
