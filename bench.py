@@ -77,6 +77,62 @@ def cpu_baseline(w, g64, delta, iters):
     }
 
 
+def batched_section(count: int = 64, iters: int = 100):
+    """64 uneven images (sides 128..1024, Gaussian PSFs 9..25, own alpha and
+    noise), 2 levels, `iters` iterations: one batched hipGraph replay against
+    64 sequential single-image restorations on the same stream."""
+    import torch
+
+    import synth
+    from paper_1504_07234_amd import mlba
+
+    ws = synth.batched_workloads(count=count, iters=iters)
+    plans, gs, alphas, deltas = [], [], [], []
+    for w in ws:
+        pl = mlba.Plan(w.n, w.p, mlba.RECT, mlba.BCCB, w.levels, torch.as_tensor(w.psf, dtype=torch.float32).cuda())
+        b = pl.apply_A(torch.as_tensor(w.truth, dtype=torch.float32).cuda())
+        xi = torch.as_tensor(w.xi, dtype=torch.float32).cuda()
+        g = (b + (w.noise_level * b.double().norm() / xi.double().norm()).float() * xi).contiguous()
+        plans.append(pl)
+        gs.append(g)
+        alphas.append(w.alpha0)
+        deltas.append(0.9 / max(pl.opnorm(w.alpha0, 50), 0.9))
+    outs = [torch.empty(pl.N, pl.N, device="cuda") for pl in plans]
+    torch.cuda.synchronize()
+    # 64 sequential plain solves (eager launches)
+    for pl, g, a, d, o in zip(plans, gs, alphas, deltas, outs):  # warm-up
+        pl.restore(g, alpha=a, mu=1e-3, delta=d, iters=2, out=o, track=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for pl, g, a, d, o in zip(plans, gs, alphas, deltas, outs):
+        pl.restore(g, alpha=a, mu=1e-3, delta=d, iters=iters, out=o, track=False)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    seq_ref = [o.clone() for o in outs]
+    # batched: capture once, then time a replay
+    batch = mlba.Batch(plans, max_iters=iters)
+    batch.restore(gs, alpha=alphas, mu=1e-3, delta=deltas, iters=iters, outs=outs, use_graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.restore(gs, alpha=alphas, mu=1e-3, delta=deltas, iters=iters, outs=outs, use_graph=True)
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    identical = all(torch.equal(a, b) for a, b in zip(outs, seq_ref))
+    px = sum(w.n * w.n for w in ws)
+    batch.close()
+    for pl in plans:
+        pl.close()
+    return {
+        "images": count, "iters": iters, "observed_pixels": px,
+        "sides": sorted({w.n for w in ws}),
+        "batched_graph_s": round(t_bat, 5), "sequential_s": round(t_seq, 5),
+        "speedup": round(t_seq / t_bat, 3),
+        "batched_Mpx_it_s": round(px * iters / t_bat / 1e6, 1),
+        "sequential_Mpx_it_s": round(px * iters / t_seq / 1e6, 1),
+        "identical_to_sequential": identical,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +141,7 @@ def main() -> int:
     ap.add_argument("--workload", default="rect-bccb-2048")
     ap.add_argument("--cpu-iters", type=int, default=3, help="oracle iterations for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-sequential section")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -170,7 +227,11 @@ def main() -> int:
         return r
 
     # dominant kernel: the longest single launch of an iteration
-    dom = max(phases, key=lambda ph: phases[ph][0] / max(1, (1 if ph == "blur" else phases[ph][1])))
+    def launch_ms(ph):
+        per_iter = max(1, phases[ph][1] // max(rec, 1))
+        return phases[ph][0] / max(rec, 1) / (1 if ph == "blur" else per_iter)
+
+    dom = max(phases, key=launch_ms)
     roof = roofline_of(dom)
     roof_hbm = roofline_of("analysis")
     total_bytes = sum(m["bytes"] for m in model.values())
@@ -197,11 +258,13 @@ def main() -> int:
         "roofline": roof,
         "roofline_hbm": roof_hbm,
     }
+    plan.close()
+    if not args.no_batched:
+        out["batched"] = batched_section()
     if not args.no_cpu:
         from oracle import blur as oblur
         g64 = synth.add_noise(oblur.blur(w.truth, w.psf, oblur.RECT), w.xi, w.noise_level)
         out["cpu_baseline"] = cpu_baseline(w, g64, delta, args.cpu_iters)
-    plan.close()
     print(json.dumps(out), flush=True)
     return 0
 

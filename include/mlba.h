@@ -171,6 +171,38 @@ int mlba_restore(mlba_plan_t plan, const float* g, const mlba_params* params,
                  float* f_out, float* z_state, double* rnorm_out, int* iters_done,
                  hipStream_t stream);
 
+/* ---- batched restoration ------------------------------------------------
+ * A batch advances many images of uneven sizes, each with its own plan (PSF,
+ * boundary model, sizes), alpha, mu and step, through eq. (MLBA2) together:
+ * every phase of an iteration is one launch covering the tiles of all images,
+ * and each image follows exactly the arithmetic of its own plan.
+ *
+ * mlba_batch_create: count plans (host array of distinct plans sharing
+ * `levels` and the preconditioner kind); the batch uses each plan's workspace
+ * and state buffer, so those plans must not run other work while the batch
+ * runs.  max_iters bounds the iteration count of one call.  Allocates the
+ * batch's descriptor table, tile maps and norm buffers (synchronous).
+ *
+ * mlba_batch_restore: g, f_out: host arrays of `count` device pointers
+ * (image i: n_i x n_i input, N_i x N_i output).  alpha, delta: host arrays of
+ * `count` values (delta <= 0: automatic step per image, see mlba_params).
+ * mu: host array of count * n_mu values (n_mu = 1 or bands).  z_state: NULL
+ * to start every image from z = 0 in its plan's state buffer, or a host array
+ * of `count` device pointers ([bands][N_i][N_i], in/out).  rnorm_out:
+ * optional host array of count * iters residual norms (synchronous; returns
+ * MLBA_WARN_DIVERGED as mlba_restore does).  use_graph != 0: the whole
+ * sequence for this iteration count is captured once into a hipGraph on a
+ * private stream (first call; instantiation allocates) and replayed on
+ * `stream`; later calls with the same count and state mode only update the
+ * descriptor table and replay. */
+typedef struct mlba_batch_s* mlba_batch_t;
+int mlba_batch_create(mlba_batch_t* batch, int count, const mlba_plan_t* plans, int max_iters,
+                      hipStream_t stream);
+int mlba_batch_destroy(mlba_batch_t batch);
+int mlba_batch_restore(mlba_batch_t batch, const float* const* g, const double* alpha, const double* mu,
+                       int n_mu, const double* delta, int iters, float* const* f_out, float* const* z_state,
+                       double* rnorm_out, int use_graph, hipStream_t stream);
+
 /* ---- phase timing (profiling aid) ----------------------------------------
  * Phases of one iteration of eq. (MLBA2) as the library runs them. */
 #define MLBA_PHASE_SYNTHESIS 0  /* x = delta S_mu(z), u = W^T x (levels launches)   */

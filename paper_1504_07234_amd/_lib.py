@@ -59,6 +59,10 @@ SIGNATURES = {
     "mlba_soft_threshold": (c_int, [c_void_p, c_void_p, c_int, c_size_t, c_dbl_p, c_int, c_double, c_void_p]),
     "mlba_restore": (c_int, [c_void_p, c_void_p, ctypes.POINTER(Params), c_void_p, c_void_p, c_dbl_p, c_int_p,
                              c_void_p]),
+    "mlba_batch_create": (c_int, [ctypes.POINTER(c_void_p), c_int, ctypes.POINTER(c_void_p), c_int, c_void_p]),
+    "mlba_batch_destroy": (c_int, [c_void_p]),
+    "mlba_batch_restore": (c_int, [c_void_p, ctypes.POINTER(c_void_p), c_dbl_p, c_dbl_p, c_int, c_dbl_p, c_int,
+                                   ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_dbl_p, c_int, c_void_p]),
     "mlba_profile_begin": (c_int, [c_void_p, c_int]),
     "mlba_profile_end": (c_int, [c_void_p, c_dbl_p, c_int_p, c_int_p]),
 }

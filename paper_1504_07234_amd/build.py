@@ -28,12 +28,15 @@ COMMON_FLAGS = [
     "-fPIC",
     "-std=c++17",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are fused only inside one source expression, so a device
+    # body inlined into different kernels rounds identically everywhere
+    "-ffp-contract=on",
     "-Wno-unused-command-line-argument",
     f"-I{INCLUDE}",
     f"-I{CSRC}",
 ]
 
-SOURCES = ["conv.hip", "framelet.hip", "fft.hip", "reduce.hip", "mlba.hip"]
+SOURCES = ["conv.hip", "framelet.hip", "fft.hip", "reduce.hip", "mlba.hip", "batch.hip"]
 
 
 def _compile(src: str) -> str:

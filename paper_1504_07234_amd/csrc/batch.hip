@@ -1,0 +1,277 @@
+// Batched restoration: many images of uneven sizes, each with its own PSF, alpha,
+// mu and step, advanced together.  Every phase of an iteration of eq. (MLBA2)
+// is one launch whose workgroups cover the tiles of all images (per-phase maps
+// workgroup -> (image, tile)); each tile runs the same device body as the
+// single-image path, so every image follows exactly the arithmetic of its own
+// plan.  The K-iteration sequence can be captured once into a hipGraph on a
+// private stream and replayed on the caller's stream; per-call data (image
+// pointers, alpha, mu, delta) live in a device descriptor table that the graph
+// reads at run time.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "mlba.h"
+#include "plan.hpp"
+
+using namespace mlba;
+
+namespace {
+
+struct Map {
+    int nblocks = 0;
+    int* bmap = nullptr;    // device: workgroup -> image
+    int* bfirst = nullptr;  // device: image -> first workgroup
+};
+
+}  // namespace
+
+struct mlba_batch_s {
+    int count = 0, levels = 0, precond = 0, pmax = 1, nmax = 8;
+    bool any_reflect = false;
+    std::vector<mlba_plan_t> plans;
+    std::vector<BatchImage> host;
+    BatchImage* imgs = nullptr;
+    int* maps = nullptr;  // one device buffer holding every map
+    Map conv_a, conv_at, fold, fill, pre[3], syn[5], ana[5];
+    double* partials = nullptr;
+    int* pcount = nullptr;
+    double* rn = nullptr;
+    int rn_cap = 0;
+    hipStream_t cap = nullptr;  // private stream for graph capture
+    hipGraphExec_t exec = nullptr;
+    int exec_iters = -1, exec_fill = -1;
+};
+
+namespace {
+
+void destroy_batch(mlba_batch_s* B) {
+    if (B->exec) hipGraphExecDestroy(B->exec);
+    if (B->cap) hipStreamDestroy(B->cap);
+    hipFree(B->imgs);
+    hipFree(B->maps);
+    hipFree(B->partials);
+    hipFree(B->pcount);
+    hipFree(B->rn);
+    delete B;
+}
+
+// Build the workgroup -> image map of one phase from per-image tile counts.
+void build_map(const std::vector<int>& tiles, std::vector<int>& host_maps, std::vector<size_t>& offs, Map& m) {
+    m.nblocks = 0;
+    for (int t : tiles) m.nblocks += t;
+    offs.push_back(host_maps.size());  // bmap offset
+    for (size_t i = 0; i < tiles.size(); ++i)
+        for (int t = 0; t < tiles[i]; ++t) host_maps.push_back((int)i);
+    offs.push_back(host_maps.size());  // bfirst offset
+    int acc = 0;
+    for (int t : tiles) {
+        host_maps.push_back(acc);
+        acc += t;
+    }
+}
+
+int enqueue(mlba_batch_s* B, int iters, bool fill_state, hipStream_t s) {
+    const BatchImage* I = B->imgs;
+    if (fill_state) HIPCHK(launch_fill_batched(I, B->fill.bmap, B->fill.bfirst, B->fill.nblocks, s));
+    for (int k = 0; k < iters; ++k) {
+        for (int lev = B->levels; lev >= 1; --lev) {
+            const Map& m = B->syn[lev];
+            HIPCHK(launch_synthesis_batched(I, m.bmap, m.bfirst, m.nblocks, lev, 1 << (lev - 1), 0, s));
+        }
+        HIPCHK(launch_conv_batched(I, B->conv_a.bmap, B->conv_a.bfirst, B->conv_a.nblocks, 1, B->pmax, B->partials,
+                                   s));
+        HIPCHK(launch_sum_partials_batched(I, B->partials, B->pcount, B->count, k, s));
+        if (B->precond != MLBA_PRECOND_NONE)
+            for (int pass = 0; pass < 3; ++pass)
+                HIPCHK(launch_precond_batched(I, B->pre[pass].bmap, B->pre[pass].bfirst, B->pre[pass].nblocks, pass,
+                                              B->precond, B->nmax, s));
+        HIPCHK(launch_conv_batched(I, B->conv_at.bmap, B->conv_at.bfirst, B->conv_at.nblocks, 0, B->pmax, nullptr,
+                                   s));
+        if (B->any_reflect) HIPCHK(launch_fold_batched(I, B->fold.bmap, B->fold.bfirst, B->fold.nblocks, s));
+        for (int lev = 1; lev <= B->levels; ++lev) {
+            const Map& m = B->ana[lev];
+            HIPCHK(launch_analysis_batched(I, m.bmap, m.bfirst, m.nblocks, lev, 1 << (lev - 1), s));
+        }
+    }
+    for (int lev = B->levels; lev >= 1; --lev) {
+        const Map& m = B->syn[lev];
+        HIPCHK(launch_synthesis_batched(I, m.bmap, m.bfirst, m.nblocks, lev, 1 << (lev - 1), 1, s));
+    }
+    return MLBA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mlba_batch_create(mlba_batch_t* batch, int count, const mlba_plan_t* plans, int max_iters, hipStream_t s) {
+    if (!batch || !plans || count < 1 || max_iters < 1) return MLBA_EINVAL;
+    *batch = nullptr;
+    for (int i = 0; i < count; ++i) {
+        if (!plans[i]) return MLBA_EINVAL;
+        if (plans[i]->levels != plans[0]->levels || plans[i]->precond != plans[0]->precond) return MLBA_EINVAL;
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == plans[i]) return MLBA_EINVAL;  // one image per plan (the plan holds its buffers)
+    }
+    mlba_batch_s* B = new (std::nothrow) mlba_batch_s();
+    if (!B) return MLBA_ENOMEM;
+    B->count = count;
+    B->levels = plans[0]->levels;
+    B->precond = plans[0]->precond;
+    B->plans.assign(plans, plans + count);
+    B->rn_cap = max_iters;
+    B->host.resize(count);
+    int pbase = 0;
+    std::vector<int> pcount(count);
+    for (int i = 0; i < count; ++i) {
+        B->host[i] = plan_desc(plans[i]);
+        B->pmax = std::max(B->pmax, plans[i]->p);
+        B->nmax = std::max(B->nmax, plans[i]->n);
+        B->any_reflect = B->any_reflect || plans[i]->bc == MLBA_BC_REFLECT;
+        B->host[i].pbase = pbase;
+        pcount[i] = conv_batched_tiles(B->host[i], 1);
+        pbase += pcount[i];
+    }
+    // phase maps
+    std::vector<int> hm;
+    std::vector<size_t> offs;
+    std::vector<Map*> order;
+    auto add = [&](Map& m, const std::vector<int>& tiles) {
+        build_map(tiles, hm, offs, m);
+        order.push_back(&m);
+    };
+    std::vector<int> t(count);
+    for (int i = 0; i < count; ++i) t[i] = conv_batched_tiles(B->host[i], 1);
+    add(B->conv_a, t);
+    for (int i = 0; i < count; ++i) t[i] = conv_batched_tiles(B->host[i], 0);
+    add(B->conv_at, t);
+    for (int i = 0; i < count; ++i) t[i] = B->host[i].bc == MLBA_BC_REFLECT ? B->host[i].n : 0;
+    add(B->fold, t);
+    for (int i = 0; i < count; ++i) t[i] = fill_tiles(B->host[i]);
+    add(B->fill, t);
+    for (int pass = 0; pass < 3; ++pass) {
+        for (int i = 0; i < count; ++i) t[i] = precond_pass_tiles(B->host[i], pass);
+        add(B->pre[pass], t);
+    }
+    for (int lev = 1; lev <= B->levels; ++lev) {
+        for (int i = 0; i < count; ++i) t[i] = synthesis_level_tiles(B->host[i].N, 1 << (lev - 1));
+        add(B->syn[lev], t);
+        for (int i = 0; i < count; ++i) t[i] = analysis_level_tiles(B->host[i].N, 1 << (lev - 1));
+        add(B->ana[lev], t);
+    }
+    hipError_t e = hipMalloc(&B->maps, hm.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&B->imgs, count * sizeof(BatchImage));
+    if (e == hipSuccess) e = hipMalloc(&B->partials, (size_t)std::max(pbase, 1) * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&B->pcount, count * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&B->rn, (size_t)count * max_iters * sizeof(double));
+    if (e != hipSuccess) {
+        mlba_internal_set_hip(e);
+        destroy_batch(B);
+        return MLBA_ENOMEM;
+    }
+    for (size_t q = 0; q < order.size(); ++q) {
+        order[q]->bmap = B->maps + offs[2 * q];
+        order[q]->bfirst = B->maps + offs[2 * q + 1];
+    }
+    for (int i = 0; i < count; ++i) B->host[i].rn = B->rn + (size_t)i * max_iters;
+    e = hipMemcpyAsync(B->maps, hm.data(), hm.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(B->pcount, pcount.data(), count * sizeof(int), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        mlba_internal_set_hip(e);
+        destroy_batch(B);
+        return MLBA_EHIP;
+    }
+    *batch = B;
+    return MLBA_OK;
+}
+
+int mlba_batch_destroy(mlba_batch_t B) {
+    if (!B) return MLBA_EINVAL;
+    hipDeviceSynchronize();
+    destroy_batch(B);
+    return MLBA_OK;
+}
+
+int mlba_batch_restore(mlba_batch_t B, const float* const* g, const double* alpha, const double* mu, int n_mu,
+                       const double* delta, int iters, float* const* f_out, float* const* z_state, double* rnorm_out,
+                       int use_graph, hipStream_t s) {
+    if (!B || !g || !alpha || !mu || !delta || !f_out || iters < 0 || iters > B->rn_cap) return MLBA_EINVAL;
+    const int count = B->count;
+    const int bands = 8 * B->levels + 1;
+    if (n_mu != 1 && n_mu != bands) return MLBA_EINVAL;
+    for (int i = 0; i < count; ++i) {
+        BatchImage& d = B->host[i];
+        if (!g[i] || !f_out[i]) return MLBA_EINVAL;
+        if (B->precond != MLBA_PRECOND_NONE && !(alpha[i] > 0.0)) return MLBA_EINVAL;
+        double dl = delta[i];
+        if (!(dl > 0.0)) {
+            double nrm = 0.0;
+            STCHK(mlba_internal_opnorm(B->plans[i], alpha[i], 50, &nrm, s));
+            dl = 0.9 / (nrm > 0.9 ? nrm : 0.9);
+        }
+        d.alpha = (float)alpha[i];
+        d.delta = (float)dl;
+        for (int b = 0; b < bands; ++b) {
+            const double m = mu[(size_t)i * n_mu + (n_mu == 1 ? 0 : b)];
+            if (!(m >= 0.0) || !isfinite(m)) return MLBA_EINVAL;
+            d.mu[b] = (float)m;
+        }
+        d.g = g[i];
+        d.f = f_out[i];
+        d.z = z_state ? z_state[i] : B->plans[i]->z;
+        if (!d.z) return MLBA_EINVAL;
+    }
+    HIPCHK(hipMemcpyAsync(B->imgs, B->host.data(), count * sizeof(BatchImage), hipMemcpyHostToDevice, s));
+    const bool fill_state = z_state == nullptr;
+    if (use_graph) {
+        if (!B->exec || B->exec_iters != iters || B->exec_fill != (int)fill_state) {
+            if (B->exec) {
+                HIPCHK(hipGraphExecDestroy(B->exec));
+                B->exec = nullptr;
+            }
+            hipGraph_t graph = nullptr;
+            HIPCHK(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+            const int st = enqueue(B, iters, fill_state, B->cap);
+            hipError_t e = hipStreamEndCapture(B->cap, &graph);
+            if (st < 0) {
+                if (graph) hipGraphDestroy(graph);
+                return st;
+            }
+            HIPCHK(e);
+            e = hipGraphInstantiate(&B->exec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            HIPCHK(e);
+            B->exec_iters = iters;
+            B->exec_fill = (int)fill_state;
+        }
+        HIPCHK(hipGraphLaunch(B->exec, s));
+    } else {
+        STCHK(enqueue(B, iters, fill_state, s));
+    }
+    if (rnorm_out && iters > 0) {
+        std::vector<double> buf((size_t)count * B->rn_cap);
+        HIPCHK(hipMemcpyAsync(buf.data(), B->rn, buf.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        int status = MLBA_OK;
+        for (int i = 0; i < count; ++i) {
+            const double first = sqrt(buf[(size_t)i * B->rn_cap]);
+            for (int k = 0; k < iters; ++k) {
+                const double v = sqrt(buf[(size_t)i * B->rn_cap + k]);
+                rnorm_out[(size_t)i * iters + k] = v;
+                if (!isfinite(v) || v > 1e3 * first) status = MLBA_WARN_DIVERGED;
+            }
+        }
+        return status;
+    }
+    return MLBA_OK;
+}
+
+}  // extern "C"

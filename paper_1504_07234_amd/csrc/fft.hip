@@ -175,11 +175,10 @@ __device__ void lds_fft(float2* buf, const FftDesc& fd, int nseq, int seq_shift,
 // ---------------------------------------------------------------------------
 
 // G row pairs per workgroup -> T[k][row], k = 0..n/2 (row stride ts complex)
-__global__ __launch_bounds__(kBlock) void fft_rows_r2c_kernel(const float* __restrict__ src, int n,
-                                                              float2* __restrict__ T, int ts, FftDesc fd,
-                                                              const float2* __restrict__ tw, int G, int seq_shift) {
-    extern __shared__ float2 buf[];
-    const int row0 = blockIdx.x * 2 * G;
+__device__ __forceinline__ void fft_rows_r2c_body(const float* __restrict__ src, int n,
+                                                              float2* __restrict__ T, int ts, const FftDesc& fd,
+                                                              const float2* __restrict__ tw, int G, int seq_shift, int blk, float2* buf) {
+    const int row0 = blk * 2 * G;
     for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
         const int g = idx / n;
         const int x = idx - g * n;
@@ -204,14 +203,13 @@ __global__ __launch_bounds__(kBlock) void fft_rows_r2c_kernel(const float* __res
 // CC rows of T per workgroup: forward FFT along the column index, then either
 // the filter inv / (spec + alpha) and the inverse FFT (mode 0), or |.|^2 into
 // `power` (mode 1).
-__global__ __launch_bounds__(kBlock) void fft_cols_kernel(float2* __restrict__ T, int n, int ts,
+__device__ __forceinline__ void fft_cols_body(float2* __restrict__ T, int n, int ts,
                                                           const float* __restrict__ spec, float alpha,
-                                                          float inv, FftDesc fd,
+                                                          float inv, const FftDesc& fd,
                                                           const float2* __restrict__ tw, int CC, int mode,
-                                                          float* __restrict__ power, int seq_shift) {
-    extern __shared__ float2 buf[];
+                                                          float* __restrict__ power, int seq_shift, int blk, float2* buf) {
     const int half = n / 2 + 1;
-    const int k0 = blockIdx.x * CC;
+    const int k0 = blk * CC;
     const int cc = min(CC, half - k0);
     const size_t base = (size_t)k0 * n;  // dense [n/2+1][n] spectrum
     for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
@@ -237,11 +235,10 @@ __global__ __launch_bounds__(kBlock) void fft_cols_kernel(float2* __restrict__ T
     }
 }
 
-__global__ __launch_bounds__(kBlock) void fft_rows_c2r_kernel(const float2* __restrict__ T, int n, int ts,
-                                                              float* __restrict__ dst, FftDesc fd,
-                                                              const float2* __restrict__ tw, int G, int seq_shift) {
-    extern __shared__ float2 buf[];
-    const int row0 = blockIdx.x * 2 * G;
+__device__ __forceinline__ void fft_rows_c2r_body(const float2* __restrict__ T, int n, int ts,
+                                                              float* __restrict__ dst, const FftDesc& fd,
+                                                              const float2* __restrict__ tw, int G, int seq_shift, int blk, float2* buf) {
+    const int row0 = blk * 2 * G;
     const int half = n / 2 + 1;
     for (int idx = threadIdx.x; idx < G * half; idx += kBlock) {
         const int k = idx / G;
@@ -278,12 +275,11 @@ __device__ __forceinline__ int dct_perm(int l, int n) { return (l & 1) ? n - 1 -
 __device__ __forceinline__ float re_mul(float2 w, float2 v) { return w.x * v.x - w.y * v.y; }
 
 // G row pairs -> Tr[k][row] (real, row stride ts), k = 0..n-1
-__global__ __launch_bounds__(kBlock) void dct_rows_fwd_kernel(const float* __restrict__ src, int n,
-                                                              float* __restrict__ Tr, int ts, FftDesc fd,
+__device__ __forceinline__ void dct_rows_fwd_body(const float* __restrict__ src, int n,
+                                                              float* __restrict__ Tr, int ts, const FftDesc& fd,
                                                               const float2* __restrict__ tw,
-                                                              const float2* __restrict__ dtw, int G, int seq_shift) {
-    extern __shared__ float2 buf[];
-    const int row0 = blockIdx.x * 2 * G;
+                                                              const float2* __restrict__ dtw, int G, int seq_shift, int blk, float2* buf) {
+    const int row0 = blk * 2 * G;
     for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
         const int g = idx / n;
         const int x = idx - g * n;
@@ -307,14 +303,13 @@ __global__ __launch_bounds__(kBlock) void dct_rows_fwd_kernel(const float* __res
 
 // CP pairs of Tr rows per workgroup: DCT-II along the row, multiply by
 // inv / (spec + alpha), DCT-III back.
-__global__ __launch_bounds__(kBlock) void dct_cols_filter_kernel(float* __restrict__ Tr, int n, int ts,
+__device__ __forceinline__ void dct_cols_filter_body(float* __restrict__ Tr, int n, int ts,
                                                                  const float* __restrict__ spec, float alpha,
-                                                                 float inv, FftDesc fd,
+                                                                 float inv, const FftDesc& fd,
                                                                  const float2* __restrict__ tw,
-                                                                 const float2* __restrict__ dtw, int CP, int seq_shift) {
-    extern __shared__ float2 buf[];
+                                                                 const float2* __restrict__ dtw, int CP, int seq_shift, int blk, float2* buf) {
     const int pairs = n / 2;
-    const int p0 = blockIdx.x * CP;
+    const int p0 = blk * CP;
     const int cp = min(CP, pairs - p0);
     const int total = cp * n;
     for (int idx = threadIdx.x; idx < total; idx += kBlock) {
@@ -384,12 +379,11 @@ __global__ __launch_bounds__(kBlock) void dct_cols_filter_kernel(float* __restri
     }
 }
 
-__global__ __launch_bounds__(kBlock) void dct_rows_inv_kernel(const float* __restrict__ Tr, int n, int ts,
-                                                              float* __restrict__ dst, FftDesc fd,
+__device__ __forceinline__ void dct_rows_inv_body(const float* __restrict__ Tr, int n, int ts,
+                                                              float* __restrict__ dst, const FftDesc& fd,
                                                               const float2* __restrict__ tw,
-                                                              const float2* __restrict__ dtw, int G, int seq_shift) {
-    extern __shared__ float2 buf[];
-    const int row0 = blockIdx.x * 2 * G;
+                                                              const float2* __restrict__ dtw, int G, int seq_shift, int blk, float2* buf) {
+    const int row0 = blk * 2 * G;
     const int total = G * n;
     for (int idx = threadIdx.x; idx < total; idx += kBlock) {
         const int k = idx / G;
@@ -428,6 +422,56 @@ __global__ __launch_bounds__(kBlock) void dct_rows_inv_kernel(const float* __res
         dst[ra + x] = v.x;
         dst[ra + n + x] = v.y;
     }
+}
+
+// ---- single-image kernels ------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void fft_rows_r2c_kernel(const float* __restrict__ src, int n,
+                                                              float2* __restrict__ T, int ts, FftDesc fd,
+                                                              const float2* __restrict__ tw, int G, int seq_shift) {
+    extern __shared__ float2 buf[];
+    fft_rows_r2c_body(src, n, T, ts, fd, tw, G, seq_shift, blockIdx.x, buf);
+}
+
+__global__ __launch_bounds__(kBlock) void fft_cols_kernel(float2* __restrict__ T, int n, int ts,
+                                                          const float* __restrict__ spec, float alpha,
+                                                          float inv, FftDesc fd,
+                                                          const float2* __restrict__ tw, int CC, int mode,
+                                                          float* __restrict__ power, int seq_shift) {
+    extern __shared__ float2 buf[];
+    fft_cols_body(T, n, ts, spec, alpha, inv, fd, tw, CC, mode, power, seq_shift, blockIdx.x, buf);
+}
+
+__global__ __launch_bounds__(kBlock) void fft_rows_c2r_kernel(const float2* __restrict__ T, int n, int ts,
+                                                              float* __restrict__ dst, FftDesc fd,
+                                                              const float2* __restrict__ tw, int G, int seq_shift) {
+    extern __shared__ float2 buf[];
+    fft_rows_c2r_body(T, n, ts, dst, fd, tw, G, seq_shift, blockIdx.x, buf);
+}
+
+__global__ __launch_bounds__(kBlock) void dct_rows_fwd_kernel(const float* __restrict__ src, int n,
+                                                              float* __restrict__ Tr, int ts, FftDesc fd,
+                                                              const float2* __restrict__ tw,
+                                                              const float2* __restrict__ dtw, int G, int seq_shift) {
+    extern __shared__ float2 buf[];
+    dct_rows_fwd_body(src, n, Tr, ts, fd, tw, dtw, G, seq_shift, blockIdx.x, buf);
+}
+
+__global__ __launch_bounds__(kBlock) void dct_cols_filter_kernel(float* __restrict__ Tr, int n, int ts,
+                                                                 const float* __restrict__ spec, float alpha,
+                                                                 float inv, FftDesc fd,
+                                                                 const float2* __restrict__ tw,
+                                                                 const float2* __restrict__ dtw, int CP, int seq_shift) {
+    extern __shared__ float2 buf[];
+    dct_cols_filter_body(Tr, n, ts, spec, alpha, inv, fd, tw, dtw, CP, seq_shift, blockIdx.x, buf);
+}
+
+__global__ __launch_bounds__(kBlock) void dct_rows_inv_kernel(const float* __restrict__ Tr, int n, int ts,
+                                                              float* __restrict__ dst, FftDesc fd,
+                                                              const float2* __restrict__ tw,
+                                                              const float2* __restrict__ dtw, int G, int seq_shift) {
+    extern __shared__ float2 buf[];
+    dct_rows_inv_body(Tr, n, ts, dst, fd, tw, dtw, G, seq_shift, blockIdx.x, buf);
 }
 
 // lambda of the reflective blur of the symmetrised PSF:
@@ -489,6 +533,68 @@ static int pick_cols_per_block(int n) {
     int cc = 1;  // largest power of two with cc * n <= min(4096, FFT_MAX_ELEMS)
     while ((cc * 2) * n <= FFT_MAX_ELEMS && (cc * 2) * n <= 4096) cc *= 2;
     return cc;
+}
+
+int fft_rows_batch(int n) { return pick_pairs_per_block(n); }
+int fft_cols_batch(int n) { return pick_cols_per_block(n); }
+int fft_seq_shift(int batch) { return seq_shift_for(batch); }
+
+// ---- batched preconditioner passes ---------------------------------------
+// Workgroup b serves image bmap[b], block b - bfirst[img] of the given pass.
+
+int precond_pass_tiles(const BatchImage& I, int pass) {
+    if (I.precond == 2) return 0;  // P = I: the descriptor aliases t to r
+    if (pass != 1) return I.n / (2 * I.fft_rows_g);
+    if (I.precond == 0) return (I.n / 2 + 1 + I.fft_cols_c - 1) / I.fft_cols_c;
+    return (I.n / 2 + I.fft_cols_c - 1) / I.fft_cols_c;
+}
+
+template <int PASS, int PRECOND>
+__global__ __launch_bounds__(kBlock) void precond_batched_kernel(const BatchImage* __restrict__ imgs,
+                                                                 const int* __restrict__ bmap,
+                                                                 const int* __restrict__ bfirst) {
+    extern __shared__ float2 buf[];
+    const int im = bmap[blockIdx.x];
+    const BatchImage& I = imgs[im];
+    const int blk = blockIdx.x - bfirst[im];
+    const int n = I.n;
+    const float inv = (float)(1.0 / ((double)n * (double)n));
+    if (PRECOND == 0) {
+        float2* T = (float2*)I.swork;
+        if (PASS == 0) fft_rows_r2c_body(I.r, n, T, I.ts, I.fd, I.tw, I.fft_rows_g, I.fft_rows_shift, blk, buf);
+        if (PASS == 1)
+            fft_cols_body(T, n, I.ts, I.spec, I.alpha, inv, I.fd, I.tw, I.fft_cols_c, 0, nullptr, I.fft_cols_shift,
+                          blk, buf);
+        if (PASS == 2) fft_rows_c2r_body(T, n, I.ts, I.t, I.fd, I.tw, I.fft_rows_g, I.fft_rows_shift, blk, buf);
+    } else {
+        float* Tr = (float*)I.swork;
+        if (PASS == 0)
+            dct_rows_fwd_body(I.r, n, Tr, I.ts, I.fd, I.tw, I.dtw, I.fft_rows_g, I.fft_rows_shift, blk, buf);
+        if (PASS == 1)
+            dct_cols_filter_body(Tr, n, I.ts, I.spec, I.alpha, inv, I.fd, I.tw, I.dtw, I.fft_cols_c,
+                                 I.fft_cols_shift, blk, buf);
+        if (PASS == 2)
+            dct_rows_inv_body(Tr, n, I.ts, I.t, I.fd, I.tw, I.dtw, I.fft_rows_g, I.fft_rows_shift, blk, buf);
+    }
+}
+
+hipError_t launch_precond_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks, int pass,
+                                  int precond, int nmax, hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    const size_t lds = lds_bytes(FFT_MAX_ELEMS, nmax);
+#define MLBA_PB(PA, PC) \
+    hipLaunchKernelGGL((precond_batched_kernel<PA, PC>), dim3(nblocks), dim3(kBlock), lds, s, imgs, bmap, bfirst)
+    if (precond == 0) {
+        if (pass == 0) MLBA_PB(0, 0);
+        else if (pass == 1) MLBA_PB(1, 0);
+        else MLBA_PB(2, 0);
+    } else {
+        if (pass == 0) MLBA_PB(0, 1);
+        else if (pass == 1) MLBA_PB(1, 1);
+        else MLBA_PB(2, 1);
+    }
+#undef MLBA_PB
+    return hipGetLastError();
 }
 
 hipError_t launch_fft_rows_r2c(const float* src, int n, float2* T, int ts, const FftDesc& fd, const float2* tw,

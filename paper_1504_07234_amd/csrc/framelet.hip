@@ -38,12 +38,11 @@ __host__ __device__ constexpr int pair_slot(int i, int j) { return i * 3 + j - 1
 constexpr int AN_TY = 8;
 
 template <int D>
-__global__ __launch_bounds__(kBlock) void analysis_level_kernel(const float* __restrict__ v, int N,
-                                                                float* __restrict__ zlev,
-                                                                float* __restrict__ low,
-                                                                int accum_bands, int accum_low) {
-    const int x = blockIdx.x * kBlock + threadIdx.x;
-    const int y0 = blockIdx.y * AN_TY;
+__device__ __forceinline__ void analysis_tile(const float* __restrict__ v, int N, float* __restrict__ zlev,
+                                              float* __restrict__ low, int accum_bands, int accum_low, int bx,
+                                              int by) {
+    const int x = bx * kBlock + threadIdx.x;
+    const int y0 = by * AN_TY;
     if (x >= N) return;
     const size_t NN = (size_t)N * N;
     const int rows = min(AN_TY, N - y0);
@@ -69,9 +68,9 @@ __global__ __launch_bounds__(kBlock) void analysis_level_kernel(const float* __r
     for (int q = 0; q < AN_TY + 2 * D; ++q) {
         const float* row = v + (size_t)reflect_index(y0 - D + q, N) * N;
         const float a = row[xl], b = row[x], e = row[xr];
-        h0[q] = 0.25f * a + 0.5f * b + 0.25f * e;
+        h0[q] = fmaf(0.25f, a + e, 0.5f * b);
         h1[q] = kB1 * (e - a);
-        h2[q] = -0.25f * a + 0.5f * b - 0.25f * e;
+        h2[q] = fmaf(-0.25f, a + e, 0.5f * b);
     }
 
 #pragma unroll
@@ -84,9 +83,9 @@ __global__ __launch_bounds__(kBlock) void analysis_level_kernel(const float* __r
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             const float a = hh[i][r], b = hh[i][r + D], e = hh[i][r + 2 * D];
-            const float y0v = 0.25f * a + 0.5f * b + 0.25f * e;
+            const float y0v = fmaf(0.25f, a + e, 0.5f * b);
             const float y1v = kB1 * (e - a);
-            const float y2v = -0.25f * a + 0.5f * b - 0.25f * e;
+            const float y2v = fmaf(-0.25f, a + e, 0.5f * b);
             if (i == 0) out[8] = y0v; else out[pair_slot(i, 0)] = y0v;
             out[pair_slot(i, 1)] = y1v;
             out[pair_slot(i, 2)] = y2v;
@@ -102,14 +101,21 @@ __global__ __launch_bounds__(kBlock) void analysis_level_kernel(const float* __r
 }
 
 template <int D>
-__global__ __launch_bounds__(kBlock) void synthesis_level_kernel(const float* __restrict__ zlev,
-                                                                 const float* __restrict__ low, int N,
-                                                                 float* __restrict__ out, LevelMu mu,
-                                                                 float delta, int thr_low, int thr_bands) {
+__global__ __launch_bounds__(kBlock) void analysis_level_kernel(const float* __restrict__ v, int N,
+                                                                float* __restrict__ zlev,
+                                                                float* __restrict__ low,
+                                                                int accum_bands, int accum_low) {
+    analysis_tile<D>(v, N, zlev, low, accum_bands, accum_low, blockIdx.x, blockIdx.y);
+}
+
+template <int D>
+__device__ __forceinline__ void synthesis_tile(const float* __restrict__ zlev, const float* __restrict__ low,
+                                               int N, float* __restrict__ out, const LevelMu& mu, float delta,
+                                               int thr_low, int thr_bands, int bx, int by,
+                                               float (*ys)[FR_TY][kBlock]) {
     constexpr int IW = kBlock - 2 * D;
-    __shared__ float ys[3][FR_TY][kBlock];
-    const int x0 = blockIdx.x * IW;
-    const int y0 = blockIdx.y * FR_TY;
+    const int x0 = bx * IW;
+    const int y0 = by * FR_TY;
     const int c = threadIdx.x;
     bool fx;
     const int gx = reflect_index(x0 - D + c, N, &fx);
@@ -140,10 +146,13 @@ __global__ __launch_bounds__(kBlock) void synthesis_level_kernel(const float* __
             const bool thr = is_low ? (thr_low != 0) : (thr_bands != 0);
             const float m = is_low ? mu.low : mu.band[pair_slot(i, j)];
             const float sx = (i == 1 && fx) ? -1.0f : 1.0f;
+            // issue the whole column's loads before using any of them
             float col[FR_TY + 2 * D];
 #pragma unroll
+            for (int q = 0; q < FR_TY + 2 * D; ++q) col[q] = src[(size_t)rowi[q] * N + gx];
+#pragma unroll
             for (int q = 0; q < FR_TY + 2 * D; ++q) {
-                float val = src[(size_t)rowi[q] * N + gx];
+                float val = col[q];
                 if (thr) val = shrink(val, m, delta);
                 const float sy = (j == 1 && rowf[q]) ? -1.0f : 1.0f;
                 col[q] = sx * sy * val;
@@ -152,9 +161,9 @@ __global__ __launch_bounds__(kBlock) void synthesis_level_kernel(const float* __
 #pragma unroll
             for (int r = 0; r < FR_TY; ++r) {
                 const float wm = col[r], w0 = col[r + D], wp = col[r + 2 * D];  // y-d, y, y+d
-                if (j == 0) acc[i][r] += 0.25f * wp + 0.5f * w0 + 0.25f * wm;
-                else if (j == 1) acc[i][r] += kB1 * (wm - wp);
-                else acc[i][r] += -0.25f * wp + 0.5f * w0 - 0.25f * wm;
+                if (j == 0) acc[i][r] += fmaf(0.25f, wp + wm, 0.5f * w0);
+                else if (j == 1) acc[i][r] = fmaf(kB1, wm - wp, acc[i][r]);
+                else acc[i][r] += fmaf(-0.25f, wp + wm, 0.5f * w0);
             }
         }
     }
@@ -174,18 +183,27 @@ __global__ __launch_bounds__(kBlock) void synthesis_level_kernel(const float* __
         float s = 0.0f;
         {
             const float l = ys[0][r][c - D], m = ys[0][r][c], rr = ys[0][r][c + D];
-            s += 0.25f * rr + 0.5f * m + 0.25f * l;
+            s += fmaf(0.25f, rr + l, 0.5f * m);
         }
         {
             const float l = ys[1][r][c - D], rr = ys[1][r][c + D];
-            s += kB1 * (l - rr);
+            s = fmaf(kB1, l - rr, s);
         }
         {
             const float l = ys[2][r][c - D], m = ys[2][r][c], rr = ys[2][r][c + D];
-            s += -0.25f * rr + 0.5f * m - 0.25f * l;
+            s += fmaf(-0.25f, rr + l, 0.5f * m);
         }
         out[(size_t)y * N + x] = s;
     }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void synthesis_level_kernel(const float* __restrict__ zlev,
+                                                                 const float* __restrict__ low, int N,
+                                                                 float* __restrict__ out, LevelMu mu,
+                                                                 float delta, int thr_low, int thr_bands) {
+    __shared__ float ys[3][FR_TY][kBlock];
+    synthesis_tile<D>(zlev, low, N, out, mu, delta, thr_low, thr_bands, blockIdx.x, blockIdx.y, ys);
 }
 
 template <int D>
@@ -225,6 +243,110 @@ hipError_t launch_synthesis_level(const float* zlev, const float* low, int N, in
         case 8: return launch_syn<8>(zlev, low, N, out, mu, delta, thr_low, thr_bands, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+// ---- batched levels: workgroup b serves image bmap[b], tile b - bfirst[img] ----
+
+int synthesis_level_tiles(int N, int d) {
+    const int IW = kBlock - 2 * d;
+    return ((N + IW - 1) / IW) * ((N + FR_TY - 1) / FR_TY);
+}
+
+int analysis_level_tiles(int N, int d) { return ((N + kBlock - 1) / kBlock) * ((N + AN_TY - 1) / AN_TY); }
+
+// level `lev` of W^T (delta S_mu(z)) for image I, exactly as the single-image
+// path sequences it: level L reads the thresholded low-pass z_0, lower levels
+// the previous level's output; level 1 writes u (or f for the final image).
+template <int D>
+__global__ __launch_bounds__(kBlock) void synthesis_batched_kernel(const BatchImage* __restrict__ imgs,
+                                                                   const int* __restrict__ bmap,
+                                                                   const int* __restrict__ bfirst, int lev,
+                                                                   int final_out) {
+    __shared__ float ys[3][FR_TY][kBlock];
+    const int im = bmap[blockIdx.x];
+    const BatchImage& I = imgs[im];
+    const size_t nn = (size_t)I.N * I.N;
+    const float* zlev = I.z + (size_t)(1 + 8 * (lev - 1)) * nn;
+    const bool top = lev == I.levels;
+    const float* low = top ? I.z : ((lev + 1) & 1 ? I.tmp1 : I.tmp0);
+    float* out = lev == 1 ? (final_out ? I.f : I.u) : ((lev & 1) ? I.tmp1 : I.tmp0);
+    LevelMu mu;
+    mu.low = I.mu[0];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) mu.band[q] = I.mu[1 + 8 * (lev - 1) + q];
+    const int IW = kBlock - 2 * D;
+    const int gx = (I.N + IW - 1) / IW;
+    const int local = blockIdx.x - bfirst[im];
+    const int by = local / gx;
+    synthesis_tile<D>(zlev, low, I.N, out, mu, I.delta, top ? 1 : 0, 1, local - by * gx, by, ys);
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void analysis_batched_kernel(const BatchImage* __restrict__ imgs,
+                                                                  const int* __restrict__ bmap,
+                                                                  const int* __restrict__ bfirst, int lev) {
+    const int im = bmap[blockIdx.x];
+    const BatchImage& I = imgs[im];
+    const size_t nn = (size_t)I.N * I.N;
+    const float* in = lev == 1 ? I.w : (((lev - 1) & 1) ? I.tmp1 : I.tmp0);
+    const bool last = lev == I.levels;
+    float* low = last ? I.z : ((lev & 1) ? I.tmp1 : I.tmp0);
+    float* zlev = I.z + (size_t)(1 + 8 * (lev - 1)) * nn;
+    const int gx = (I.N + kBlock - 1) / kBlock;
+    const int local = blockIdx.x - bfirst[im];
+    const int by = local / gx;
+    analysis_tile<D>(in, I.N, zlev, low, 1, last ? 1 : 0, local - by * gx, by);
+}
+
+hipError_t launch_synthesis_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks,
+                                    int lev, int d, int final_out, hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    switch (d) {
+        case 1: hipLaunchKernelGGL(synthesis_batched_kernel<1>, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst, lev, final_out); break;
+        case 2: hipLaunchKernelGGL(synthesis_batched_kernel<2>, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst, lev, final_out); break;
+        case 4: hipLaunchKernelGGL(synthesis_batched_kernel<4>, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst, lev, final_out); break;
+        case 8: hipLaunchKernelGGL(synthesis_batched_kernel<8>, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst, lev, final_out); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_analysis_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks,
+                                   int lev, int d, hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    switch (d) {
+        case 1: hipLaunchKernelGGL(analysis_batched_kernel<1>, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst, lev); break;
+        case 2: hipLaunchKernelGGL(analysis_batched_kernel<2>, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst, lev); break;
+        case 4: hipLaunchKernelGGL(analysis_batched_kernel<4>, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst, lev); break;
+        case 8: hipLaunchKernelGGL(analysis_batched_kernel<8>, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst, lev); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+constexpr int FILL_CHUNK = kBlock * 1024;
+
+int fill_tiles(const BatchImage& I) {
+    const size_t count = (size_t)I.bands * I.N * I.N;
+    return (int)((count + FILL_CHUNK - 1) / FILL_CHUNK);
+}
+
+__global__ __launch_bounds__(kBlock) void fill_batched_kernel(const BatchImage* __restrict__ imgs,
+                                                              const int* __restrict__ bmap,
+                                                              const int* __restrict__ bfirst) {
+    const int im = bmap[blockIdx.x];
+    const BatchImage& I = imgs[im];
+    const size_t count = (size_t)I.bands * I.N * I.N;
+    const size_t beg = (size_t)(blockIdx.x - bfirst[im]) * FILL_CHUNK;
+    const size_t end = beg + FILL_CHUNK < count ? beg + FILL_CHUNK : count;
+    for (size_t i = beg + threadIdx.x; i < end; i += kBlock) I.z[i] = 0.0f;
+}
+
+hipError_t launch_fill_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks,
+                               hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_batched_kernel, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst);
+    return hipGetLastError();
 }
 
 __global__ __launch_bounds__(kBlock) void soft_threshold_kernel(const float* __restrict__ z,

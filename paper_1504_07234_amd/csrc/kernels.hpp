@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 
+#include "common.hpp"
+
 namespace mlba {
 
 // Mixed-radix plan of a length-n complex FFT (n = 2^a 3^b).
@@ -26,6 +28,84 @@ struct BandMu {
     float v[64];
 };
 
+// One blur: dst[y][x] = (g ? g[y][x] - s : s) over D x D outputs,
+// s = sum_{a,b} K[a][b] src_ext[y+org+a][x+org+b] (src S x S, extension ext).
+struct ConvJob {
+    const float* src;
+    int S, ext, org;
+    float* dst;
+    int D;
+    const float* g;
+    const float* psf;
+};
+
+// Per-image descriptor of a batch (device memory): sizes, model, parameters
+// and the plan's buffers.  All images of a batch share the framelet depth.
+struct BatchImage {
+    int n, p, c, N, bc, precond, levels, bands, ts;
+    int fft_rows_g, fft_cols_c, fft_rows_shift, fft_cols_shift;  // transform batching
+    int pbase;  // first residual-norm partial of this image
+    float alpha, delta;
+    float mu[33];
+    const float* g;
+    float* f;
+    float* z;
+    float* u;
+    float* r;
+    float* t;
+    float* w;
+    float* wext;
+    float* tmp0;
+    float* tmp1;
+    const float* psf;
+    const float* spec;
+    void* swork;
+    const float2* tw;
+    const float2* dtw;
+    double* rn;  // ||r^k||^2 per iteration
+    FftDesc fd;
+};
+
+__host__ __device__ inline int ext_of_bc(int bc) {
+    return bc == 1 ? EXT_REFLECT : (bc == 2 ? EXT_PERIODIC : EXT_ZERO);  // REFLECT, PERIODIC, else zero
+}
+
+// r = g - A u  (section 2: valid convolution of the (extended) unknown)
+__host__ __device__ inline ConvJob blur_job(const BatchImage& I) {
+    ConvJob j;
+    j.src = I.u;
+    j.S = I.N;
+    j.ext = ext_of_bc(I.bc);
+    j.org = I.bc == 0 ? 0 : -I.c;
+    j.dst = I.r;
+    j.D = I.n;
+    j.g = I.g;
+    j.psf = I.psf;
+    return j;
+}
+
+// w = A^T t (full correlation; the reflective model writes the padded grid
+// wext, folded afterwards)
+__host__ __device__ inline ConvJob blurT_job(const BatchImage& I) {
+    ConvJob j;
+    j.src = I.t;
+    j.S = I.n;
+    j.g = nullptr;
+    j.psf = I.psf;
+    if (I.bc == 0 || I.bc == 1) {
+        j.ext = EXT_ZERO;
+        j.org = -(I.p - 1);
+        j.dst = I.bc == 0 ? I.w : I.wext;
+        j.D = I.n + I.p - 1;
+    } else {
+        j.ext = I.bc == 2 ? EXT_PERIODIC : EXT_ZERO;
+        j.org = -I.c;
+        j.dst = I.w;
+        j.D = I.n;
+    }
+    return j;
+}
+
 // ---- blur (direct convolution) -------------------------------------------
 // dst[y][x] = (g ? g[y][x] - s : s),  s = sum_{a,b} K[a][b] src_ext[y+org+a][x+org+b]
 // with K = H rotated by 180 degrees (flip = 1, the blur A) or K = H
@@ -34,7 +114,18 @@ struct BandMu {
 hipError_t launch_conv(const float* src, int S, int ext, int org, float* dst, int D,
                        const float* g, const float* psf, int p, int flip, double* partials,
                        int* n_partials, hipStream_t s);
+// ry: output rows per thread (1 or 2; other values pick by occupancy)
+hipError_t launch_conv_job(const ConvJob& j, int p, int flip, int ry, double* partials, int* n_partials,
+                           hipStream_t s);
 int conv_partials_count(int D);
+int conv_default_rows(int D, int p);
+int conv_tiles(int D, int ry);
+// batched: tiles of every image in one launch (flip = 1: residual, 0: A^T)
+int conv_batched_tiles(const BatchImage& I, int flip);
+hipError_t launch_conv_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks,
+                               int flip, int pmax, double* partials, hipStream_t s);
+hipError_t launch_fold_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks,
+                               hipStream_t s);
 
 // Transpose of the reflective padding: w[y][x] = sum of wext over the
 // positions of the (n+2c)^2 padded grid that copy pixel (y, x).
@@ -50,6 +141,18 @@ hipError_t launch_synthesis_level(const float* zlev, const float* low, int N, in
                                   hipStream_t s);
 hipError_t launch_soft_threshold(const float* z, float* x, int bands, size_t band_elems,
                                  BandMu mu, float delta, hipStream_t s);
+// batched framelet levels (all images share `levels`); tiles per image:
+int synthesis_level_tiles(int N, int d);
+int analysis_level_tiles(int N, int d);
+// synthesis of level `lev` with thresholds; final_out: level 1 writes f, else u
+hipError_t launch_synthesis_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks,
+                                    int lev, int d, int final_out, hipStream_t s);
+// z += W w, level `lev`
+hipError_t launch_analysis_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks,
+                                   int lev, int d, hipStream_t s);
+hipError_t launch_fill_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks,
+                               hipStream_t s);  // z = 0, 256 * 1024 elements per workgroup
+int fill_tiles(const BatchImage& I);
 
 // ---- spectral preconditioner --------------------------------------------
 // BCCB: rows r2c -> T (half spectrum, transposed [n/2+1][ts] complex; the row
@@ -78,6 +181,14 @@ hipError_t launch_dct_spectrum(const float* psf, int p, int n, float* spec, cons
                                hipStream_t s);
 // place the PSF in the top-left corner of a zeroed n x n image
 hipError_t launch_pad_psf(const float* psf, int p, float* dst, int n, hipStream_t s);
+// transform batching chosen for size n (row pairs / columns per workgroup)
+int fft_rows_batch(int n);
+int fft_cols_batch(int n);
+int fft_seq_shift(int batch);
+// batched preconditioner passes: pass 0 rows forward, 1 columns, 2 rows inverse
+int precond_pass_tiles(const BatchImage& I, int pass);
+hipError_t launch_precond_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks,
+                                  int pass, int precond, int nmax, hipStream_t s);
 
 // ---- reductions and small helpers ---------------------------------------
 // out[0] = sum of partials[0..count) in a fixed order (double)
@@ -90,5 +201,8 @@ hipError_t launch_scale(float* x, size_t count, const double* inv_norm_sq_or_nul
 hipError_t launch_fill_hash(float* x, size_t count, unsigned seed, hipStream_t s);
 hipError_t launch_fill(float* x, size_t count, float value, hipStream_t s);
 int reduce_partials_cap();
+// rn[image][k] = sum of that image's residual-norm partials (one workgroup per image)
+hipError_t launch_sum_partials_batched(const BatchImage* imgs, const double* partials, const int* pcount,
+                                       int count, int k, hipStream_t s);
 
 }  // namespace mlba

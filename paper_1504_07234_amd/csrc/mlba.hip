@@ -10,27 +10,18 @@
 #include "common.hpp"
 #include "kernels.hpp"
 #include "mlba.h"
+#include "plan.hpp"
 
 using namespace mlba;
 
 namespace {
-
 thread_local int g_last_hip = 0;
+}
 
-#define HIPCHK(expr)                          \
-    do {                                      \
-        hipError_t e_ = (expr);               \
-        if (e_ != hipSuccess) {               \
-            g_last_hip = (int)e_;             \
-            return MLBA_EHIP;                 \
-        }                                     \
-    } while (0)
+int mlba_internal_last_hip() { return g_last_hip; }
+void mlba_internal_set_hip(hipError_t e) { g_last_hip = (int)e; }
 
-#define STCHK(expr)              \
-    do {                         \
-        int st_ = (expr);        \
-        if (st_ < 0) return st_; \
-    } while (0)
+namespace {
 
 bool factor_23(int n, int* a, int* b) {
     *a = 0;
@@ -48,43 +39,13 @@ bool factor_23(int n, int* a, int* b) {
 
 }  // namespace
 
-struct mlba_plan_s {
-    int n = 0, p = 0, c = 0, N = 0, bc = 0, precond = 0, levels = 0, bands = 0;
-    FftDesc fd{};
-    int ts = 0;                // row stride of the transposed spectral workspace
-    float* psf = nullptr;
-    float* spec = nullptr;     // BCCB: [n/2+1][n] |Lambda|^2 (transposed); DCT: [n][n] lambda^2
-    float2* tw = nullptr;      // exp(-2 pi i q / n)
-    float2* dtw = nullptr;     // exp(-i pi k / (2n))
-    float* costab = nullptr;   // cos(pi q / n), q < 2n
-    void* swork = nullptr;     // spectral workspace
-    float* u = nullptr;        // N x N synthesis output
-    float* r = nullptr;        // n x n residual
-    float* t = nullptr;        // n x n preconditioned residual
-    float* w = nullptr;        // N x N A^T t
-    float* wext = nullptr;     // m x m full correlation (reflective boundary)
-    float* tmp[2] = {nullptr, nullptr};  // N x N level intermediates
-    float* pv = nullptr;       // N x N power-iteration vector
-    float* z = nullptr;        // [bands][N][N] state when the caller passes none
-    double* partials = nullptr;
-    int partials_cap = 0;
-    double* scal = nullptr;    // device scalars
-    double* rn = nullptr;      // ||r^k||^2 history ring
-    int rn_cap = 0;
-    std::vector<void*> allocs;
-    // phase timing
-    std::vector<hipEvent_t> prof_ev;  // (MLBA_NPHASES + 1) per recorded iteration
-    int prof_cap = 0, prof_used = 0;
-    int prof_launch[MLBA_NPHASES] = {0, 0, 0, 0, 0};
-};
-
 namespace {
 
 int dalloc(mlba_plan_s* P, void** ptr, size_t bytes) {
     if (bytes == 0) bytes = 16;
     hipError_t e = hipMalloc(ptr, bytes);
     if (e != hipSuccess) {
-        g_last_hip = (int)e;
+        mlba_internal_set_hip(e);
         *ptr = nullptr;
         return MLBA_ENOMEM;
     }
@@ -115,39 +76,24 @@ void free_plan(mlba_plan_s* P) {
 
 size_t NN(const mlba_plan_s* P) { return (size_t)P->N * P->N; }
 
-int ext_of_bc(int bc) {
-    return bc == MLBA_BC_REFLECT ? EXT_REFLECT : (bc == MLBA_BC_PERIODIC ? EXT_PERIODIC : EXT_ZERO);
-}
-
 // r = g - A u (g may be null: y = A u); partial sums of r^2 into P->partials
 int do_blur(mlba_plan_s* P, const float* u, const float* g, float* y, bool want_norm, int* nparts,
             hipStream_t s) {
-    const int org = P->bc == MLBA_BC_RECT ? 0 : -P->c;
-    HIPCHK(launch_conv(u, P->N, ext_of_bc(P->bc), org, y, P->n, g, P->psf, P->p, 1,
-                       want_norm ? P->partials : nullptr, nparts, s));
+    BatchImage d = plan_desc(P);
+    d.u = const_cast<float*>(u);
+    d.g = g;
+    d.r = y;
+    HIPCHK(launch_conv_job(blur_job(d), P->p, 1, P->conv_rows[0], want_norm ? P->partials : nullptr, nparts, s));
     return MLBA_OK;
 }
 
+// w = A^T y (+ fold of the reflective padding)
 int do_blurT(mlba_plan_s* P, const float* y, float* w, hipStream_t s) {
-    switch (P->bc) {
-        case MLBA_BC_RECT:
-            HIPCHK(launch_conv(y, P->n, EXT_ZERO, -(P->p - 1), w, P->N, nullptr, P->psf, P->p, 0, nullptr,
-                               nullptr, s));
-            break;
-        case MLBA_BC_REFLECT: {
-            const int m = P->n + P->p - 1;
-            HIPCHK(launch_conv(y, P->n, EXT_ZERO, -(P->p - 1), P->wext, m, nullptr, P->psf, P->p, 0, nullptr,
-                               nullptr, s));
-            HIPCHK(launch_fold_reflect(P->wext, m, w, P->n, P->c, s));
-            break;
-        }
-        case MLBA_BC_PERIODIC:
-            HIPCHK(launch_conv(y, P->n, EXT_PERIODIC, -P->c, w, P->n, nullptr, P->psf, P->p, 0, nullptr, nullptr,
-                               s));
-            break;
-        default:
-            HIPCHK(launch_conv(y, P->n, EXT_ZERO, -P->c, w, P->n, nullptr, P->psf, P->p, 0, nullptr, nullptr, s));
-    }
+    BatchImage d = plan_desc(P);
+    d.t = const_cast<float*>(y);
+    d.w = w;
+    HIPCHK(launch_conv_job(blurT_job(d), P->p, 0, P->conv_rows[1], nullptr, nullptr, s));
+    if (P->bc == MLBA_BC_REFLECT) HIPCHK(launch_fold_reflect(P->wext, P->n + P->p - 1, w, P->n, P->c, s));
     return MLBA_OK;
 }
 
@@ -233,7 +179,9 @@ int expand_mu(const mlba_plan_s* P, const double* mu, int n_mu, float* out) {
     return MLBA_OK;
 }
 
-int opnorm_impl(mlba_plan_s* P, double alpha, int iters, double* out, hipStream_t s) {
+}  // namespace
+
+int mlba_internal_opnorm(mlba_plan_s* P, double alpha, int iters, double* out, hipStream_t s) {
     const size_t nn = NN(P);
     float* v = P->pv;
     float* w = P->u;  // the synthesis buffer is free while estimating
@@ -261,6 +209,8 @@ int opnorm_impl(mlba_plan_s* P, double alpha, int iters, double* out, hipStream_
     *out = host[1];
     return MLBA_OK;
 }
+
+namespace {
 
 double alpha_at(const mlba_alpha_schedule& a, int k) {
     switch (a.kind) {
@@ -291,7 +241,7 @@ const char* mlba_status_string(int status) {
     }
 }
 
-int mlba_last_hip_error(void) { return g_last_hip; }
+int mlba_last_hip_error(void) { return mlba_internal_last_hip(); }
 
 int mlba_version(void) { return 1; }
 
@@ -396,7 +346,7 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
             e = hipMemcpyAsync(P->costab, cost.data(), 2 * n * sizeof(float), hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);  // host tables go out of scope
         if (e != hipSuccess) {
-            g_last_hip = (int)e;
+            mlba_internal_set_hip(e);
             free_plan(P);
             return MLBA_EHIP;
         }
@@ -434,7 +384,7 @@ int mlba_plan_dims(mlba_plan_t P, int* n, int* p, int* N, int* bands) {
 
 int mlba_plan_opnorm(mlba_plan_t P, double alpha, int iters, double* out, hipStream_t s) {
     if (!P || !out || iters < 1 || !(alpha > 0.0 || P->precond == MLBA_PRECOND_NONE)) return MLBA_EINVAL;
-    return opnorm_impl(P, alpha, iters, out, s);
+    return mlba_internal_opnorm(P, alpha, iters, out, s);
 }
 
 int mlba_apply_A(mlba_plan_t P, const float* u, float* y, hipStream_t s) {
@@ -526,7 +476,7 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
             while (j < seen_a.size() && seen_a[j] != alpha[i]) ++j;
             if (j == seen_a.size()) {
                 double nrm = 0.0;
-                STCHK(opnorm_impl(P, alpha[i], 50, &nrm, s));
+                STCHK(mlba_internal_opnorm(P, alpha[i], 50, &nrm, s));
                 seen_a.push_back(alpha[i]);
                 seen_d.push_back(0.9 / (nrm > 0.9 ? nrm : 0.9));
             }
@@ -623,7 +573,7 @@ int mlba_profile_begin(mlba_plan_t P, int max_iters) {
         hipEvent_t e;
         hipError_t err = hipEventCreate(&e);
         if (err != hipSuccess) {
-            g_last_hip = (int)err;
+            mlba_internal_set_hip(err);
             release_events(P);
             return MLBA_EHIP;
         }

@@ -1,0 +1,94 @@
+// Internal plan layout shared by the library's host translation units.
+#pragma once
+
+#include <vector>
+
+#include "kernels.hpp"
+#include "mlba.h"
+
+int mlba_internal_last_hip();
+void mlba_internal_set_hip(hipError_t e);
+
+#define HIPCHK(expr)                         \
+    do {                                     \
+        hipError_t e_ = (expr);              \
+        if (e_ != hipSuccess) {              \
+            mlba_internal_set_hip(e_);       \
+            return MLBA_EHIP;                \
+        }                                    \
+    } while (0)
+
+#define STCHK(expr)              \
+    do {                         \
+        int st_ = (expr);        \
+        if (st_ < 0) return st_; \
+    } while (0)
+
+struct mlba_plan_s {
+    int n = 0, p = 0, c = 0, N = 0, bc = 0, precond = 0, levels = 0, bands = 0;
+    mlba::FftDesc fd{};
+    int ts = 0;                // row stride of the transposed spectral workspace
+    int conv_rows[2] = {0, 0}; // output rows per thread of the A / A^T blur (0: by occupancy)
+    float* psf = nullptr;
+    float* spec = nullptr;     // BCCB: [n/2+1][n] |Lambda|^2 (transposed); DCT: [n][n] lambda^2
+    float2* tw = nullptr;      // exp(-2 pi i q / n)
+    float2* dtw = nullptr;     // exp(-i pi k / (2n))
+    float* costab = nullptr;   // cos(pi q / n), q < 2n
+    void* swork = nullptr;     // spectral workspace
+    float* u = nullptr;        // N x N synthesis output
+    float* r = nullptr;        // n x n residual
+    float* t = nullptr;        // n x n preconditioned residual
+    float* w = nullptr;        // N x N A^T t
+    float* wext = nullptr;     // m x m full correlation (reflective boundary)
+    float* tmp[2] = {nullptr, nullptr};  // N x N level intermediates
+    float* pv = nullptr;       // N x N power-iteration vector
+    float* z = nullptr;        // [bands][N][N] state when the caller passes none
+    double* partials = nullptr;
+    int partials_cap = 0;
+    double* scal = nullptr;    // device scalars
+    double* rn = nullptr;      // ||r^k||^2 history ring
+    int rn_cap = 0;
+    std::vector<void*> allocs;
+    // phase timing
+    std::vector<hipEvent_t> prof_ev;  // (MLBA_NPHASES + 1) per recorded iteration
+    int prof_cap = 0, prof_used = 0;
+    int prof_launch[MLBA_NPHASES] = {0, 0, 0, 0, 0};
+};
+
+int mlba_internal_opnorm(mlba_plan_s* P, double alpha, int iters, double* out, hipStream_t s);
+
+// Descriptor of a plan's sizes and buffers (the per-image record of a batch;
+// the single-image path builds the same record so both run identical jobs).
+inline mlba::BatchImage plan_desc(const mlba_plan_s* P) {
+    mlba::BatchImage d{};
+    d.n = P->n;
+    d.p = P->p;
+    d.c = P->c;
+    d.N = P->N;
+    d.bc = P->bc;
+    d.precond = P->precond;
+    d.levels = P->levels;
+    d.bands = P->bands;
+    d.ts = P->ts;
+    d.u = P->u;
+    d.r = P->r;
+    d.t = P->precond == MLBA_PRECOND_NONE ? P->r : P->t;
+    d.w = P->w;
+    d.wext = P->wext;
+    d.tmp0 = P->tmp[0];
+    d.tmp1 = P->tmp[1];
+    d.z = P->z;
+    d.psf = P->psf;
+    d.spec = P->spec;
+    d.swork = P->swork;
+    d.tw = P->tw;
+    d.dtw = P->dtw;
+    d.fd = P->fd;
+    if (P->precond != MLBA_PRECOND_NONE) {
+        d.fft_rows_g = mlba::fft_rows_batch(P->n);
+        d.fft_cols_c = mlba::fft_cols_batch(P->n);
+        d.fft_rows_shift = mlba::fft_seq_shift(d.fft_rows_g);
+        d.fft_cols_shift = mlba::fft_seq_shift(d.fft_cols_c);
+    }
+    return d;
+}

@@ -24,6 +24,27 @@ hipError_t launch_sum_partials(const double* partials, int count, double* out, h
     return hipGetLastError();
 }
 
+// one workgroup per image: rn[k] = sum of the image's partials, fixed order
+__global__ __launch_bounds__(kBlock) void sum_partials_batched_kernel(const BatchImage* __restrict__ imgs,
+                                                                      const double* __restrict__ partials,
+                                                                      const int* __restrict__ pcount, int k) {
+    __shared__ double red[kBlock / 64];
+    const BatchImage& I = imgs[blockIdx.x];
+    const double* p = partials + I.pbase;
+    const int count = pcount[blockIdx.x];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < count; i += kBlock) s += p[i];
+    const double t = block_sum(s, red);
+    if (threadIdx.x == 0) I.rn[k] = t;
+}
+
+hipError_t launch_sum_partials_batched(const BatchImage* imgs, const double* partials, const int* pcount, int count,
+                                       int k, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sum_partials_batched_kernel, dim3(count), dim3(kBlock), 0, s, imgs, partials, pcount, k);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(kBlock) void dot_partials_kernel(const float* __restrict__ a,
                                                               const float* __restrict__ b, size_t count,
                                                               double* __restrict__ partials) {

@@ -226,3 +226,69 @@ def soft_threshold(z: torch.Tensor, mu, delta: float = 1.0, out=None, stream=Non
     check(lib.mlba_soft_threshold(_dev(z, "z"), _dev(out, "out", tuple(z.shape)), bands, elems, ptr, len(mus),
                                   float(delta), _stream(stream)), "mlba_soft_threshold")
     return out
+
+
+class Batch:
+    """Many restorations advanced together (one launch per phase covering all
+    images), optionally replayed from a captured hipGraph.  The batch uses the
+    given plans' workspaces; keep the plans alive and idle while it runs."""
+
+    def __init__(self, plans, max_iters: int, stream=None):
+        self._lib = _lib.load()
+        self.plans = list(plans)
+        self._h = ctypes.c_void_p()
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        check(self._lib.mlba_batch_create(ctypes.byref(self._h), len(self.plans), arr, int(max_iters),
+                                          _stream(stream)), "mlba_batch_create")
+        self.max_iters = int(max_iters)
+
+    def close(self):
+        if self._h:
+            torch.cuda.synchronize()
+            self._lib.mlba_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def restore(self, gs, *, alpha, mu=1e-3, delta=None, iters: int = 100, outs=None, zs=None,
+                use_graph: bool = True, track: bool = False, stream=None):
+        """Returns (list of restored images, residual norms [count][iters] or None)."""
+        count = len(self.plans)
+        if len(gs) != count:
+            raise ValueError("one observed image per plan")
+        outs = [self.plans[i]._new(self.plans[i].N, self.plans[i].N) for i in range(count)] if outs is None else outs
+        gp = (ctypes.c_void_p * count)(*[_dev(g, "g", (p.n, p.n)).value for g, p in zip(gs, self.plans)])
+        fp = (ctypes.c_void_p * count)(*[_dev(f, "f", (p.N, p.N)).value for f, p in zip(outs, self.plans)])
+        zp = None
+        if zs is not None:
+            zp = (ctypes.c_void_p * count)(*[_dev(z, "z", (p.bands, p.N, p.N)).value for z, p in zip(zs, self.plans)])
+        alphas = [alpha] * count if isinstance(alpha, (int, float)) else list(alpha)
+        deltas = [0.0] * count if delta is None else ([delta] * count if isinstance(delta, (int, float)) else list(delta))
+        if isinstance(mu, (int, float)):
+            mus, n_mu = [mu] * count, 1
+        else:
+            rows = [list(m) if hasattr(m, "__len__") else [m] for m in mu]
+            n_mu = len(rows[0])
+            mus = [v for r in rows for v in r]
+        aarr, ap = _dbl_array(alphas)
+        marr, mp = _dbl_array(mus)
+        darr, dp = _dbl_array(deltas)
+        rn = (ctypes.c_double * (count * max(iters, 1)))() if track else None
+        st = self._lib.mlba_batch_restore(self._h, gp, ap, mp, n_mu, dp, int(iters), fp, zp,
+                                          ctypes.cast(rn, _lib.c_dbl_p) if track else None, int(bool(use_graph)),
+                                          _stream(stream))
+        check(st, "mlba_batch_restore")
+        norms = None
+        if track:
+            norms = [list(rn[i * iters:(i + 1) * iters]) for i in range(count)]
+        return outs, norms

@@ -1,0 +1,167 @@
+"""Batched restoration (many uneven images per launch, hipGraph replay).
+
+Each image of a batch runs the same tile bodies as its own plan's
+single-image path, so the batched result must equal the per-image result bit
+for bit; the per-image path is itself pinned to the FP64 oracle, and one
+batch is also compared with the oracle directly.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import blur as oblur
+from oracle import mlba as omlba
+from tests._util import announce, cuda, host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mlba():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1504_07234_amd import mlba as m
+    return m
+
+
+def _problem(n, p, seed, bc=0):
+    gen = synth.rng(seed)
+    truth = synth.shapes_image(n + p - 1, gen, n_rect=6, n_disk=3, n_bumps=3)
+    H = synth.gaussian_psf(p, gen.uniform(1.0, 4.0))
+    g = synth.add_noise(oblur.blur(truth, H, 0), synth.white_noise((n, n), gen), gen.uniform(0.005, 0.02))
+    return g, H
+
+
+SIZES = [(64, 9), (96, 13), (128, 25), (192, 11), (256, 17), (72, 5), (384, 21), (144, 15)]
+
+
+def _make(mlba, specs, levels=2, precond=0, bcs=None):
+    plans, gs, Hs = [], [], []
+    for i, (n, p) in enumerate(specs):
+        bc = 0 if bcs is None else bcs[i]
+        g, H = _problem(n, p, 4000 + i)
+        plans.append(mlba.Plan(n, p, bc, precond, levels, cuda(H)))
+        gs.append(g)
+        Hs.append(H)
+    return plans, gs, Hs
+
+
+def test_batched_equals_per_image(mlba):
+    import torch
+    announce("batched == per-image (eager and graph)")
+    plans, gs, _ = _make(mlba, SIZES)
+    iters = 15
+    alphas = [0.02 + 0.02 * i for i in range(len(plans))]
+    deltas = [0.2 + 0.01 * i for i in range(len(plans))]
+    mus = [1e-3 * (1 + i % 3) for i in range(len(plans))]
+    gdev = [cuda(g) for g in gs]
+    ref = []
+    for pl, g, a, d, m in zip(plans, gdev, alphas, deltas, mus):
+        f, info = pl.restore(g, alpha=a, mu=m, delta=d, iters=iters)
+        ref.append((f.clone(), info.rnorm))
+    with mlba.Batch(plans, max_iters=iters) as batch:
+        for use_graph in (False, True):
+            outs, norms = batch.restore(gdev, alpha=alphas, mu=mus, delta=deltas, iters=iters,
+                                        use_graph=use_graph, track=True)
+            torch.cuda.synchronize()
+            for i, (f_ref, rn_ref) in enumerate(ref):
+                assert torch.equal(outs[i], f_ref), (use_graph, i)
+                assert np.allclose(norms[i], rn_ref, rtol=1e-12, atol=0), (use_graph, i)
+    for pl in plans:
+        pl.close()
+
+
+def test_graph_replays_with_eager_work_between(mlba):
+    """Every replay of the captured graph equals the eager batched result, with
+    unrelated eager GPU work and synchronisations between the replays."""
+    import torch
+    announce("graph replays")
+    plans, gs, _ = _make(mlba, SIZES[:5])
+    iters = 10
+    gdev = [cuda(g) for g in gs]
+    with mlba.Batch(plans, max_iters=iters) as batch:
+        eager, _ = batch.restore(gdev, alpha=0.05, mu=1e-3, delta=0.25, iters=iters, use_graph=False)
+        eager = [e.clone() for e in eager]
+        for rep in range(4):
+            junk = torch.randn(1 << 20, device="cuda").cumsum(0)
+            _ = plans[0].apply_A(torch.rand(plans[0].N, plans[0].N, device="cuda"))
+            torch.cuda.synchronize()
+            outs, _ = batch.restore(gdev, alpha=0.05, mu=1e-3, delta=0.25, iters=iters, use_graph=True)
+            torch.cuda.synchronize()
+            for i in range(len(plans)):
+                assert torch.equal(outs[i], eager[i]), (rep, i)
+            del junk
+    for pl in plans:
+        pl.close()
+
+
+def test_batched_reflective_dct(mlba):
+    import torch
+    announce("batched reflective + DCT")
+    specs = [(64, 9), (96, 7), (128, 15), (192, 9)]
+    plans, gs, _ = _make(mlba, specs, levels=3, precond=1, bcs=[1, 0, 1, 3])
+    iters = 12
+    gdev = [cuda(g) for g in gs]
+    ref = [pl.restore(g, alpha=0.1, mu=2e-3, delta=0.3, iters=iters)[0].clone() for pl, g in zip(plans, gdev)]
+    with mlba.Batch(plans, max_iters=iters) as batch:
+        outs, _ = batch.restore(gdev, alpha=0.1, mu=2e-3, delta=0.3, iters=iters, use_graph=True)
+        torch.cuda.synchronize()
+        for i in range(len(plans)):
+            assert torch.equal(outs[i], ref[i]), i
+    for pl in plans:
+        pl.close()
+
+
+def test_batched_against_oracle(mlba):
+    announce("batched vs FP64 oracle")
+    specs = [(64, 9), (96, 17), (192, 11)]
+    plans, gs, Hs = _make(mlba, specs)
+    iters = 30
+    alphas = [0.05, 0.1, 0.03]
+    deltas = [omlba.delta_auto(omlba.opnorm(H, n, 0, 0, a, tol=1e-6)) for (n, p), H, a in zip(specs, Hs, alphas)]
+    with mlba.Batch(plans, max_iters=iters) as batch:
+        outs, norms = batch.restore([cuda(g) for g in gs], alpha=alphas, mu=1e-3, delta=deltas, iters=iters,
+                                    use_graph=True, track=True)
+        outs = [host(o) for o in outs]
+    for i, ((n, p), H, g) in enumerate(zip(specs, Hs, gs)):
+        ref = omlba.mlba(g, H, 0, 0, 2, np.full(iters, alphas[i]), np.full(iters + 1, deltas[i]), 1e-3, iters)
+        assert rel_err(outs[i], ref["f"]) < 1e-4
+        assert rel_err(norms[i], ref["rnorm"]) < 1e-4
+    for pl in plans:
+        pl.close()
+
+
+def test_batched_resume_state(mlba):
+    """Caller-owned states: 4 + 6 batched iterations equal 10."""
+    import torch
+    announce("batched resume")
+    plans, gs, _ = _make(mlba, SIZES[:3])
+    gdev = [cuda(g) for g in gs]
+    with mlba.Batch(plans, max_iters=10) as batch:
+        full, _ = batch.restore(gdev, alpha=0.05, mu=1e-3, delta=0.3, iters=10, use_graph=False)
+        full = [f.clone() for f in full]
+        zs = [torch.zeros(p.bands, p.N, p.N, device="cuda") for p in plans]
+        batch.restore(gdev, alpha=0.05, mu=1e-3, delta=0.3, iters=4, zs=zs, use_graph=True)
+        outs, _ = batch.restore(gdev, alpha=0.05, mu=1e-3, delta=0.3, iters=6, zs=zs, use_graph=True)
+        torch.cuda.synchronize()
+        for i in range(3):
+            assert torch.equal(outs[i], full[i])
+    for pl in plans:
+        pl.close()
+
+
+def test_batch_rejects_mixed_levels(mlba):
+    from paper_1504_07234_amd import _lib
+    announce("batch argument checks")
+    a = mlba.Plan(64, 9, 0, 0, 2, cuda(synth.gaussian_psf(9, 2.0)))
+    b = mlba.Plan(64, 9, 0, 0, 3, cuda(synth.gaussian_psf(9, 2.0)))
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_void_p * 2)(a._h.value, b._h.value)
+    assert lib.mlba_batch_create(ctypes.byref(h), 2, arr, 10, None) == _lib.EINVAL
+    arr = (ctypes.c_void_p * 2)(a._h.value, a._h.value)
+    assert lib.mlba_batch_create(ctypes.byref(h), 2, arr, 10, None) == _lib.EINVAL
+    a.close()
+    b.close()
