@@ -18,7 +18,7 @@ Modules
   mlba      soft threshold, the iteration (MLBA2), schedules, ||A^T P A||
   adjoint   reverse-mode gradient of K unrolled iterations
 """
-from . import blur, framelet, precond, mlba  # noqa: F401
+from . import adjoint, blur, framelet, precond, mlba  # noqa: F401
 
 RECT, REFLECT, PERIODIC, ZERO = blur.RECT, blur.REFLECT, blur.PERIODIC, blur.ZERO
 BCCB, DCT, NONE = precond.BCCB, precond.DCT, precond.NONE
