@@ -13,7 +13,10 @@ scene, PSF and noise) and resident in HBM before the timed region starts.
 Prints one JSON line: Mpixel-iter/s over the observed pixels, the
 per-phase breakdown measured with HIP events on the library's stream during
 the timed region, the roofline of the dominant kernel, and the FP64 oracle
-timed on the host cores over a bounded sample of the same workload.
+timed on the host cores over a bounded sample of the same workload.  Two
+sections follow: 64 uneven images batched under a hipGraph against 64
+sequential solves, and the forward / backward time of 30 unrolled
+iterations over 16 images of 256^2 with their gradients.
 """
 from __future__ import annotations
 
@@ -133,6 +136,61 @@ def batched_section(count: int = 64, iters: int = 100):
     }
 
 
+def unrolled_section(reps: int = 5):
+    """Differentiable unrolled MLBA: 16 images of 256^2, 15 x 15 Gaussian PSF
+    (sigma 2.5), 2 levels (17 thresholds), K = 30 iterations, checkpoints every
+    5; loss ||f - f_true||^2.  Forward (with checkpoints) and backward (segment
+    recompute + reverse sweep, gradients for mu, alpha, PSF and g) timed with
+    HIP events on the library's stream, averaged over `reps` calls."""
+    import torch
+
+    import synth
+    from paper_1504_07234_amd import mlba
+
+    ws = synth.unrolled_workloads()
+    w0 = ws[0]
+    K, ce = w0.iters, w0.extra["ckpt_every"]
+    psf = torch.as_tensor(w0.psf, dtype=torch.float32).cuda()
+    U = mlba.Unrolled([w.n for w in ws], w0.p, w0.levels, psf, K, ce)
+    gs, truths = [], []
+    for w, pl in zip(ws, U.plans):
+        truth = torch.as_tensor(w.truth, dtype=torch.float32).cuda()
+        b = pl.apply_A(truth)
+        xi = torch.as_tensor(w.xi, dtype=torch.float32).cuda()
+        gs.append((b + (w.noise_level * b.double().norm() / xi.double().norm()).float() * xi).contiguous())
+        truths.append(truth)
+    delta = 0.9 / max(U.plans[0].opnorm(w0.alpha0, 50), 0.9)
+    mu = [w0.mu] * U.bands
+    fs, ck = U.forward(gs, alpha=w0.alpha0, mu=mu, delta=delta)
+    dfs = [(2.0 * (f - t)).contiguous() for f, t in zip(fs, truths)]
+    res = U.backward(gs, dfs, ck, alpha=w0.alpha0, mu=mu, delta=delta)  # warm-up
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_f = t_b = 0.0
+    for _ in range(reps):
+        ev[0].record()
+        U.forward(gs, alpha=w0.alpha0, mu=mu, delta=delta, ckpts=ck, outs=fs)
+        ev[1].record()
+        res = U.backward(gs, dfs, ck, alpha=w0.alpha0, mu=mu, delta=delta)
+        ev[2].record()
+        torch.cuda.synchronize()
+        t_f += ev[0].elapsed_time(ev[1])
+        t_b += ev[1].elapsed_time(ev[2])
+    t_f /= reps
+    t_b /= reps
+    finite = bool(torch.isfinite(res["mu"]).all() and torch.isfinite(res["psf"]).all()
+                  and torch.isfinite(res["alpha"]))
+    px = sum(w.n * w.n for w in ws)
+    U.close()
+    return {
+        "images": len(ws), "n": w0.n, "p": w0.p, "levels": w0.levels, "bands": 8 * w0.levels + 1,
+        "iters": K, "ckpt_every": ce, "alpha": w0.alpha0, "mu": w0.mu, "delta": round(delta, 6),
+        "forward_ms": round(t_f, 4), "backward_ms": round(t_b, 4), "bwd_fwd_ratio": round(t_b / t_f, 3),
+        "forward_Mpx_it_s": round(px * K / (t_f * 1e-3) / 1e6, 1),
+        "grads": ["mu[17]", "alpha", "psf[15x15]", "g"], "grads_finite": finite,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +200,7 @@ def main() -> int:
     ap.add_argument("--cpu-iters", type=int, default=3, help="oracle iterations for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-sequential section")
+    ap.add_argument("--no-unrolled", action="store_true", help="skip the unrolled forward/backward section")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -261,6 +320,8 @@ def main() -> int:
     plan.close()
     if not args.no_batched:
         out["batched"] = batched_section()
+    if not args.no_unrolled:
+        out["unrolled"] = unrolled_section()
     if not args.no_cpu:
         from oracle import blur as oblur
         g64 = synth.add_noise(oblur.blur(w.truth, w.psf, oblur.RECT), w.xi, w.noise_level)

@@ -31,7 +31,9 @@
  *     owns its workspace (allocated by mlba_plan_create), so one plan must
  *     not be used by two streams at the same time.  Entry points other than
  *     mlba_plan_create / mlba_plan_destroy / mlba_batch_create /
- *     mlba_batch_destroy allocate no device memory.
+ *     mlba_batch_destroy / mlba_unrolled_create / mlba_unrolled_destroy
+ *     allocate no device memory (graph instantiation aside, see
+ *     mlba_batch_restore).
  *   - Errors: every call returns an int status.  Negative values are
  *     errors (nothing was enqueued), MLBA_WARN_DIVERGED is a warning.
  *     No C++ exception crosses this interface.
@@ -202,6 +204,53 @@ int mlba_batch_destroy(mlba_batch_t batch);
 int mlba_batch_restore(mlba_batch_t batch, const float* const* g, const double* alpha, const double* mu,
                        int n_mu, const double* delta, int iters, float* const* f_out, float* const* z_state,
                        double* rnorm_out, int use_graph, hipStream_t stream);
+
+/* ---- differentiable unrolled MLBA -----------------------------------------
+ * K iterations of eq. (MLBA2) from z = 0, f = W^T(delta S_mu(z^K)), for a
+ * batch of images with the rectangular blur (section 2.1) and the BCCB
+ * preconditioner (Algorithm 1), and the exact reverse-mode gradient of a loss
+ * l(f) with respect to the per-band thresholds mu (eq. soft), alpha
+ * (Algorithm 1), the PSF entries and the observations g.  The soft threshold
+ * is differentiated almost everywhere: dS/dz = 1{|z| > mu} and
+ * dS/dmu = -sgn(z) 1{|z| > mu}, taken as 0 at the kink |z| = mu.  delta is a
+ * constant.  All images share alpha, mu, delta and the PSF side p; the
+ * gradients returned are sums over the images, i.e. the gradient with respect
+ * to parameters shared by the batch.
+ *
+ * mlba_unrolled_create: count distinct plans (MLBA_BC_RECT, MLBA_PRECOND_BCCB,
+ * otherwise MLBA_EUNSUPPORTED; equal levels and p, otherwise MLBA_EINVAL),
+ * iters = K >= 1, 1 <= ckpt_every <= K.  The object uses each plan's
+ * workspace and PSF/spectrum (so those plans must not run other work
+ * meanwhile) and allocates its own segment storage: per image
+ * (ckpt_every + 2) states of bands*N*N floats plus ckpt_every images of each
+ * of u, t and the half spectrum (synchronous).
+ * mlba_unrolled_dims: number of checkpoint segments J = ceil(K / ckpt_every)
+ * and, per image (host array of count values, optional), the checkpoint
+ * buffer length J * bands * N_i * N_i in floats.
+ *
+ * mlba_unrolled_forward: g, f: host arrays of count device pointers (n_i x n_i
+ * in, N_i x N_i out).  ckpt: host array of count device pointers to caller
+ * buffers of the length above; slot j receives z^{j*ckpt_every}.  alpha > 0,
+ * delta > 0; mu: host, n_mu = 1 or bands values >= 0.  Asynchronous.
+ *
+ * mlba_unrolled_backward: the same g, alpha, mu, delta and the checkpoints
+ * written by the forward call (read only); df: host array of count device
+ * pointers to dl/df (N_i x N_i).  Writes dmu (device, bands doubles), dalpha
+ * (device, one double), dpsf (device, p*p doubles, row-major like the PSF)
+ * and, when dg is not NULL, dg[i] = dl/dg_i (device n_i x n_i floats).  Each
+ * checkpoint segment is recomputed once.  Results are deterministic (fixed
+ * reduction order).  Asynchronous.  One object must not run two calls at
+ * the same time. */
+typedef struct mlba_unrolled_s* mlba_unrolled_t;
+int mlba_unrolled_create(mlba_unrolled_t* unrolled, int count, const mlba_plan_t* plans, int iters,
+                         int ckpt_every, hipStream_t stream);
+int mlba_unrolled_destroy(mlba_unrolled_t unrolled);
+int mlba_unrolled_dims(mlba_unrolled_t unrolled, int* segments, size_t* ckpt_elems_per_image);
+int mlba_unrolled_forward(mlba_unrolled_t unrolled, const float* const* g, double alpha, const double* mu,
+                          int n_mu, double delta, float* const* ckpt, float* const* f, hipStream_t stream);
+int mlba_unrolled_backward(mlba_unrolled_t unrolled, const float* const* g, double alpha, const double* mu,
+                           int n_mu, double delta, float* const* ckpt, const float* const* df, double* dmu,
+                           double* dalpha, double* dpsf, float* const* dg, hipStream_t stream);
 
 /* ---- phase timing (profiling aid) ----------------------------------------
  * Phases of one iteration of eq. (MLBA2) as the library runs them. */

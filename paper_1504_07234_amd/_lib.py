@@ -63,6 +63,15 @@ SIGNATURES = {
     "mlba_batch_destroy": (c_int, [c_void_p]),
     "mlba_batch_restore": (c_int, [c_void_p, ctypes.POINTER(c_void_p), c_dbl_p, c_dbl_p, c_int, c_dbl_p, c_int,
                                    ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_dbl_p, c_int, c_void_p]),
+    "mlba_unrolled_create": (c_int, [ctypes.POINTER(c_void_p), c_int, ctypes.POINTER(c_void_p), c_int, c_int,
+                                     c_void_p]),
+    "mlba_unrolled_destroy": (c_int, [c_void_p]),
+    "mlba_unrolled_dims": (c_int, [c_void_p, c_int_p, ctypes.POINTER(c_size_t)]),
+    "mlba_unrolled_forward": (c_int, [c_void_p, ctypes.POINTER(c_void_p), c_double, c_dbl_p, c_int, c_double,
+                                      ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_void_p]),
+    "mlba_unrolled_backward": (c_int, [c_void_p, ctypes.POINTER(c_void_p), c_double, c_dbl_p, c_int, c_double,
+                                       ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_void_p, c_void_p,
+                                       c_void_p, ctypes.POINTER(c_void_p), c_void_p]),
     "mlba_profile_begin": (c_int, [c_void_p, c_int]),
     "mlba_profile_end": (c_int, [c_void_p, c_dbl_p, c_int_p, c_int_p]),
 }

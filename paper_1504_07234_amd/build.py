@@ -36,7 +36,8 @@ COMMON_FLAGS = [
     f"-I{CSRC}",
 ]
 
-SOURCES = ["conv.hip", "framelet.hip", "fft.hip", "reduce.hip", "mlba.hip", "batch.hip"]
+SOURCES = ["conv.hip", "framelet.hip", "fft.hip", "reduce.hip", "psfgrad.hip", "mlba.hip", "batch.hip",
+           "unrolled.hip"]
 
 
 def _compile(src: str) -> str:

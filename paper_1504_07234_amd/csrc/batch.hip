@@ -227,6 +227,7 @@ int mlba_batch_restore(mlba_batch_t B, const float* const* g, const double* alph
         d.g = g[i];
         d.f = f_out[i];
         d.z = z_state ? z_state[i] : B->plans[i]->z;
+        d.zin = d.z;
         if (!d.z) return MLBA_EINVAL;
     }
     HIPCHK(hipMemcpyAsync(B->imgs, B->host.data(), count * sizeof(BatchImage), hipMemcpyHostToDevice, s));

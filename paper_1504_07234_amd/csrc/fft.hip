@@ -207,7 +207,10 @@ __device__ __forceinline__ void fft_cols_body(float2* __restrict__ T, int n, int
                                                           const float* __restrict__ spec, float alpha,
                                                           float inv, const FftDesc& fd,
                                                           const float2* __restrict__ tw, int CC, int mode,
-                                                          float* __restrict__ power, int seq_shift, int blk, float2* buf) {
+                                                          float* __restrict__ power, int seq_shift, int blk, float2* buf,
+                                                          float2* __restrict__ sstore = nullptr,
+                                                          const float2* __restrict__ sfwd = nullptr,
+                                                          float* __restrict__ eacc = nullptr) {
     const int half = n / 2 + 1;
     const int k0 = blk * CC;
     const int cc = min(CC, half - k0);
@@ -227,6 +230,35 @@ __device__ __forceinline__ void fft_cols_body(float2* __restrict__ T, int n, int
     }
     for (int idx = threadIdx.x; idx < cc * n; idx += kBlock)
         buf[lds_slot(idx)] = cscale(buf[lds_slot(idx)], inv / (spec[base + idx] + alpha));
+    if (sstore || eacc) {  // reverse sweep of unrolled iterations (same thread owns each slot)
+        for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
+            const float2 v = buf[lds_slot(idx)];
+            if (sstore) sstore[base + idx] = v;
+            if (eacc) {
+                const float2 f = sfwd[base + idx];
+                eacc[base + idx] += fmaf(v.x, f.x, v.y * f.y);
+            }
+        }
+    }
+    __syncthreads();
+    lds_fft<1>(buf, fd, cc, seq_shift, tw);
+    for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
+        const int q = idx / n;
+        T[(size_t)(k0 + q) * ts + (idx - q * n)] = buf[lds_slot(idx)];
+    }
+}
+
+// CC rows of T per workgroup: inverse FFT along the column index of the real
+// dense spectrum e ([n/2+1][n]), written to T.
+__device__ __forceinline__ void fft_cols_inverse_real_body(const float* __restrict__ e, float2* __restrict__ T,
+                                                           int n, int ts, const FftDesc& fd,
+                                                           const float2* __restrict__ tw, int CC, int seq_shift,
+                                                           int blk, float2* buf) {
+    const int half = n / 2 + 1;
+    const int k0 = blk * CC;
+    const int cc = min(CC, half - k0);
+    const size_t base = (size_t)k0 * n;
+    for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) buf[lds_slot(idx)] = make_float2(e[base + idx], 0.0f);
     __syncthreads();
     lds_fft<1>(buf, fd, cc, seq_shift, tw);
     for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
@@ -544,6 +576,7 @@ int fft_seq_shift(int batch) { return seq_shift_for(batch); }
 
 int precond_pass_tiles(const BatchImage& I, int pass) {
     if (I.precond == 2) return 0;  // P = I: the descriptor aliases t to r
+    if (pass == 3) pass = 1;
     if (pass != 1) return I.n / (2 * I.fft_rows_g);
     if (I.precond == 0) return (I.n / 2 + 1 + I.fft_cols_c - 1) / I.fft_cols_c;
     return (I.n / 2 + I.fft_cols_c - 1) / I.fft_cols_c;
@@ -564,8 +597,10 @@ __global__ __launch_bounds__(kBlock) void precond_batched_kernel(const BatchImag
         if (PASS == 0) fft_rows_r2c_body(I.r, n, T, I.ts, I.fd, I.tw, I.fft_rows_g, I.fft_rows_shift, blk, buf);
         if (PASS == 1)
             fft_cols_body(T, n, I.ts, I.spec, I.alpha, inv, I.fd, I.tw, I.fft_cols_c, 0, nullptr, I.fft_cols_shift,
-                          blk, buf);
+                          blk, buf, I.sstore, I.sfwd, I.eacc);
         if (PASS == 2) fft_rows_c2r_body(T, n, I.ts, I.t, I.fd, I.tw, I.fft_rows_g, I.fft_rows_shift, blk, buf);
+        if (PASS == 3)
+            fft_cols_inverse_real_body(I.eacc, T, n, I.ts, I.fd, I.tw, I.fft_cols_c, I.fft_cols_shift, blk, buf);
     } else {
         float* Tr = (float*)I.swork;
         if (PASS == 0)
@@ -587,8 +622,10 @@ hipError_t launch_precond_batched(const BatchImage* imgs, const int* bmap, const
     if (precond == 0) {
         if (pass == 0) MLBA_PB(0, 0);
         else if (pass == 1) MLBA_PB(1, 0);
-        else MLBA_PB(2, 0);
+        else if (pass == 2) MLBA_PB(2, 0);
+        else MLBA_PB(3, 0);
     } else {
+        if (pass == 3) return hipErrorInvalidValue;
         if (pass == 0) MLBA_PB(0, 1);
         else if (pass == 1) MLBA_PB(1, 1);
         else MLBA_PB(2, 1);

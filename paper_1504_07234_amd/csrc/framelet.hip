@@ -37,10 +37,45 @@ __host__ __device__ constexpr int pair_slot(int i, int j) { return i * 3 + j - 1
 // store so that 9 * AN_TY independent loads are in flight per thread.
 constexpr int AN_TY = 8;
 
+// x-direction filters h_i at column x on the rows y0-D .. y0+AN_TY-1+D
 template <int D>
-__device__ __forceinline__ void analysis_tile(const float* __restrict__ v, int N, float* __restrict__ zlev,
-                                              float* __restrict__ low, int accum_bands, int accum_low, int bx,
-                                              int by) {
+__device__ __forceinline__ void analysis_xfilter(const float* __restrict__ v, int N, int x, int y0,
+                                                 float* h0, float* h1, float* h2) {
+    const int xl = reflect_index(x - D, N), xr = reflect_index(x + D, N);
+#pragma unroll
+    for (int q = 0; q < AN_TY + 2 * D; ++q) {
+        const float* row = v + (size_t)reflect_index(y0 - D + q, N) * N;
+        const float a = row[xl], b = row[x], e = row[xr];
+        h0[q] = fmaf(0.25f, a + e, 0.5f * b);
+        h1[q] = kB1 * (e - a);
+        h2[q] = fmaf(-0.25f, a + e, 0.5f * b);
+    }
+}
+
+// y-direction filters of strip row r: the eight bands (slot pair_slot(i, j))
+// and the low-pass (slot 8)
+template <int D>
+__device__ __forceinline__ void analysis_yfilter(const float* h0, const float* h1, const float* h2, int r,
+                                                 float* out) {
+    const float* hh[3] = {h0, h1, h2};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float a = hh[i][r], b = hh[i][r + D], e = hh[i][r + 2 * D];
+        const float y0v = fmaf(0.25f, a + e, 0.5f * b);
+        const float y1v = kB1 * (e - a);
+        const float y2v = fmaf(-0.25f, a + e, 0.5f * b);
+        if (i == 0) out[8] = y0v; else out[pair_slot(i, 0)] = y0v;
+        out[pair_slot(i, 1)] = y1v;
+        out[pair_slot(i, 2)] = y2v;
+    }
+}
+
+// Old coefficients come from zin_lev / low_in (the same arrays as zlev / low
+// for an in-place update; a new state slot otherwise).
+template <int D>
+__device__ __forceinline__ void analysis_tile(const float* __restrict__ v, int N, const float* zin_lev,
+                                              const float* low_in, float* zlev, float* low, int accum_bands,
+                                              int accum_low, int bx, int by) {
     const int x = bx * kBlock + threadIdx.x;
     const int y0 = by * AN_TY;
     if (x >= N) return;
@@ -55,41 +90,21 @@ __device__ __forceinline__ void analysis_tile(const float* __restrict__ v, int N
             if (r < rows) {
                 const size_t o = (size_t)(y0 + r) * N + x;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) old[r][q] = zlev[q * NN + o];
-                old[r][8] = accum_low ? low[o] : 0.0f;
+                for (int q = 0; q < 8; ++q) old[r][q] = zin_lev[q * NN + o];
+                old[r][8] = accum_low ? low_in[o] : 0.0f;
             }
         }
     }
 
-    // x-direction filters h_i on the rows y0-D .. y0+AN_TY-1+D
-    const int xl = reflect_index(x - D, N), xr = reflect_index(x + D, N);
     float h0[AN_TY + 2 * D], h1[AN_TY + 2 * D], h2[AN_TY + 2 * D];
-#pragma unroll
-    for (int q = 0; q < AN_TY + 2 * D; ++q) {
-        const float* row = v + (size_t)reflect_index(y0 - D + q, N) * N;
-        const float a = row[xl], b = row[x], e = row[xr];
-        h0[q] = fmaf(0.25f, a + e, 0.5f * b);
-        h1[q] = kB1 * (e - a);
-        h2[q] = fmaf(-0.25f, a + e, 0.5f * b);
-    }
+    analysis_xfilter<D>(v, N, x, y0, h0, h1, h2);
 
 #pragma unroll
     for (int r = 0; r < AN_TY; ++r) {
         if (r >= rows) break;
         const size_t o = (size_t)(y0 + r) * N + x;
         float out[9];
-        // band (i, j) = b_j along y of h_i; slot 8 holds (0, 0)
-        const float* hh[3] = {h0, h1, h2};
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const float a = hh[i][r], b = hh[i][r + D], e = hh[i][r + 2 * D];
-            const float y0v = fmaf(0.25f, a + e, 0.5f * b);
-            const float y1v = kB1 * (e - a);
-            const float y2v = fmaf(-0.25f, a + e, 0.5f * b);
-            if (i == 0) out[8] = y0v; else out[pair_slot(i, 0)] = y0v;
-            out[pair_slot(i, 1)] = y1v;
-            out[pair_slot(i, 2)] = y2v;
-        }
+        analysis_yfilter<D>(h0, h1, h2, r, out);
         if (accum_bands) {
 #pragma unroll
             for (int q = 0; q < 9; ++q) out[q] += old[r][q];
@@ -105,7 +120,59 @@ __global__ __launch_bounds__(kBlock) void analysis_level_kernel(const float* __r
                                                                 float* __restrict__ zlev,
                                                                 float* __restrict__ low,
                                                                 int accum_bands, int accum_low) {
-    analysis_tile<D>(v, N, zlev, low, accum_bands, accum_low, blockIdx.x, blockIdx.y);
+    analysis_tile<D>(v, N, zlev, low, zlev, low, accum_bands, accum_low, blockIdx.x, blockIdx.y);
+}
+
+// Reverse-sweep level: the filters of analysis_tile, and for every band value
+// v the cotangent update under the active set of the forward state zk (the
+// a.e. derivative of the soft threshold: 1{|zk| > mu}, 0 at the kink).  psum
+// collects the thread's contribution to the threshold gradient per slot.
+template <int D>
+__device__ __forceinline__ void analysis_adjoint_tile(const float* __restrict__ v, int N,
+                                                      const float* __restrict__ zk_lev, float* zb_lev,
+                                                      const float* __restrict__ zk_low, float* zb_low,
+                                                      float* __restrict__ low_out, const LevelMu& mu,
+                                                      float delta, int init, int bx, int by, float* psum) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) psum[q] = 0.0f;
+    const int x = bx * kBlock + threadIdx.x;
+    const int y0 = by * AN_TY;
+    if (x >= N) return;
+    const size_t NN = (size_t)N * N;
+    const int rows = min(AN_TY, N - y0);
+    const float sd = init ? delta : -delta;  // change of zbar per unit of v where active
+
+    float zkv[AN_TY][9];
+#pragma unroll
+    for (int r = 0; r < AN_TY; ++r) {
+        if (r < rows) {
+            const size_t o = (size_t)(y0 + r) * N + x;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) zkv[r][q] = zk_lev[q * NN + o];
+            zkv[r][8] = zk_low ? zk_low[o] : 0.0f;
+        }
+    }
+    float h0[AN_TY + 2 * D], h1[AN_TY + 2 * D], h2[AN_TY + 2 * D];
+    analysis_xfilter<D>(v, N, x, y0, h0, h1, h2);
+
+#pragma unroll
+    for (int r = 0; r < AN_TY; ++r) {
+        if (r >= rows) break;
+        const size_t o = (size_t)(y0 + r) * N + x;
+        float out[9];
+        analysis_yfilter<D>(h0, h1, h2, r, out);
+        if (!zk_low) low_out[o] = out[8];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            if (q == 8 && !zk_low) continue;
+            float* zb = q < 8 ? zb_lev + q * NN : zb_low;
+            const float m = q < 8 ? mu.band[q] : mu.low;
+            const float old = init ? 0.0f : zb[o];
+            const bool act = fabsf(zkv[r][q]) > m;
+            zb[o] = act ? fmaf(sd, out[q], old) : old;
+            if (act) psum[q] -= sd * (zkv[r][q] > 0.0f ? out[q] : -out[q]);
+        }
+    }
 }
 
 template <int D>
@@ -261,14 +328,14 @@ template <int D>
 __global__ __launch_bounds__(kBlock) void synthesis_batched_kernel(const BatchImage* __restrict__ imgs,
                                                                    const int* __restrict__ bmap,
                                                                    const int* __restrict__ bfirst, int lev,
-                                                                   int final_out) {
+                                                                   int final_out, int thr) {
     __shared__ float ys[3][FR_TY][kBlock];
     const int im = bmap[blockIdx.x];
     const BatchImage& I = imgs[im];
     const size_t nn = (size_t)I.N * I.N;
-    const float* zlev = I.z + (size_t)(1 + 8 * (lev - 1)) * nn;
+    const float* zlev = I.zin + (size_t)(1 + 8 * (lev - 1)) * nn;
     const bool top = lev == I.levels;
-    const float* low = top ? I.z : ((lev + 1) & 1 ? I.tmp1 : I.tmp0);
+    const float* low = top ? I.zin : ((lev + 1) & 1 ? I.tmp1 : I.tmp0);
     float* out = lev == 1 ? (final_out ? I.f : I.u) : ((lev & 1) ? I.tmp1 : I.tmp0);
     LevelMu mu;
     mu.low = I.mu[0];
@@ -278,7 +345,8 @@ __global__ __launch_bounds__(kBlock) void synthesis_batched_kernel(const BatchIm
     const int gx = (I.N + IW - 1) / IW;
     const int local = blockIdx.x - bfirst[im];
     const int by = local / gx;
-    synthesis_tile<D>(zlev, low, I.N, out, mu, I.delta, top ? 1 : 0, 1, local - by * gx, by, ys);
+    synthesis_tile<D>(zlev, low, I.N, out, mu, thr ? I.delta : 1.0f, (thr && top) ? 1 : 0, thr, local - by * gx,
+                      by, ys);
 }
 
 template <int D>
@@ -292,20 +360,74 @@ __global__ __launch_bounds__(kBlock) void analysis_batched_kernel(const BatchIma
     const bool last = lev == I.levels;
     float* low = last ? I.z : ((lev & 1) ? I.tmp1 : I.tmp0);
     float* zlev = I.z + (size_t)(1 + 8 * (lev - 1)) * nn;
+    const float* zin_lev = I.zin + (size_t)(1 + 8 * (lev - 1)) * nn;
     const int gx = (I.N + kBlock - 1) / kBlock;
     const int local = blockIdx.x - bfirst[im];
     const int by = local / gx;
-    analysis_tile<D>(in, I.N, zlev, low, 1, last ? 1 : 0, local - by * gx, by);
+    analysis_tile<D>(in, I.N, zin_lev, last ? I.zin : low, zlev, low, 1, last ? 1 : 0, local - by * gx, by);
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void analysis_adjoint_batched_kernel(const BatchImage* __restrict__ imgs,
+                                                                          const int* __restrict__ bmap,
+                                                                          const int* __restrict__ bfirst, int lev,
+                                                                          int init, double* __restrict__ part) {
+    __shared__ double red[9][kBlock / 64];
+    const int im = bmap[blockIdx.x];
+    const BatchImage& I = imgs[im];
+    const size_t nn = (size_t)I.N * I.N;
+    const float* in = lev == 1 ? I.w : (((lev - 1) & 1) ? I.tmp1 : I.tmp0);
+    const bool last = lev == I.levels;
+    const size_t lo = (size_t)(1 + 8 * (lev - 1)) * nn;
+    LevelMu mu;
+    mu.low = I.mu[0];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) mu.band[q] = I.mu[1 + 8 * (lev - 1) + q];
+    const int gx = (I.N + kBlock - 1) / kBlock;
+    const int local = blockIdx.x - bfirst[im];
+    const int by = local / gx;
+    float ps[9];
+    analysis_adjoint_tile<D>(in, I.N, I.zk + lo, I.zbar + lo, last ? I.zk : nullptr, last ? I.zbar : nullptr,
+                             last ? nullptr : ((lev & 1) ? I.tmp1 : I.tmp0), mu, I.delta, init, local - by * gx, by,
+                             ps);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        double v = (double)ps[q];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) red[q][wid] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 9) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) t += red[threadIdx.x][w];
+        part[(size_t)blockIdx.x * 9 + threadIdx.x] += t;
+    }
+}
+
+int analysis_adjoint_tiles(int N, int d) { return analysis_level_tiles(N, d); }
+
+hipError_t launch_analysis_adjoint_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks,
+                                           int lev, int d, int init, double* part, hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    switch (d) {
+        case 1: hipLaunchKernelGGL(analysis_adjoint_batched_kernel<1>, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst, lev, init, part); break;
+        case 2: hipLaunchKernelGGL(analysis_adjoint_batched_kernel<2>, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst, lev, init, part); break;
+        case 4: hipLaunchKernelGGL(analysis_adjoint_batched_kernel<4>, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst, lev, init, part); break;
+        case 8: hipLaunchKernelGGL(analysis_adjoint_batched_kernel<8>, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst, lev, init, part); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_synthesis_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks,
-                                    int lev, int d, int final_out, hipStream_t s) {
+                                    int lev, int d, int final_out, hipStream_t s, int thr) {
     if (nblocks <= 0) return hipSuccess;
     switch (d) {
-        case 1: hipLaunchKernelGGL(synthesis_batched_kernel<1>, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst, lev, final_out); break;
-        case 2: hipLaunchKernelGGL(synthesis_batched_kernel<2>, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst, lev, final_out); break;
-        case 4: hipLaunchKernelGGL(synthesis_batched_kernel<4>, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst, lev, final_out); break;
-        case 8: hipLaunchKernelGGL(synthesis_batched_kernel<8>, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst, lev, final_out); break;
+        case 1: hipLaunchKernelGGL(synthesis_batched_kernel<1>, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst, lev, final_out, thr); break;
+        case 2: hipLaunchKernelGGL(synthesis_batched_kernel<2>, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst, lev, final_out, thr); break;
+        case 4: hipLaunchKernelGGL(synthesis_batched_kernel<4>, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst, lev, final_out, thr); break;
+        case 8: hipLaunchKernelGGL(synthesis_batched_kernel<8>, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst, lev, final_out, thr); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

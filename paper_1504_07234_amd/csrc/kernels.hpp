@@ -49,7 +49,8 @@ struct BatchImage {
     float mu[33];
     const float* g;
     float* f;
-    float* z;
+    float* z;          // state written by the analysis update
+    const float* zin;  // state read by the synthesis and by the update (z unless a step writes a new slot)
     float* u;
     float* r;
     float* t;
@@ -63,6 +64,15 @@ struct BatchImage {
     const float2* tw;
     const float2* dtw;
     double* rn;  // ||r^k||^2 per iteration
+    // reverse sweep of unrolled iterations (null elsewhere)
+    float2* sstore;      // the preconditioner's filtered spectrum is stored here ([n/2+1][n])
+    const float2* sfwd;  // filtered spectrum of the forward step being reversed
+    float* eacc;         // += Re(conj(filtered) * sfwd), dense [n/2+1][n]
+    const float* zk;     // forward state z_k: its active set masks the cotangent update
+    float* zbar;         // state cotangent [bands][N][N]
+    const float* tk;     // forward t_k = P r_k (n x n)
+    const float* uk;     // forward u_k = W^T(delta S_mu(z_k)) (N x N)
+    float* dg;           // gradient of the observation (n x n)
     FftDesc fd;
 };
 
@@ -144,15 +154,25 @@ hipError_t launch_soft_threshold(const float* z, float* x, int bands, size_t ban
 // batched framelet levels (all images share `levels`); tiles per image:
 int synthesis_level_tiles(int N, int d);
 int analysis_level_tiles(int N, int d);
-// synthesis of level `lev` with thresholds; final_out: level 1 writes f, else u
+// synthesis of level `lev` (thresholded input when thr, else plain W^T); final_out:
+// level 1 writes f, else u
 hipError_t launch_synthesis_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks,
-                                    int lev, int d, int final_out, hipStream_t s);
+                                    int lev, int d, int final_out, hipStream_t s, int thr = 1);
 // z += W w, level `lev`
 hipError_t launch_analysis_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks,
                                    int lev, int d, hipStream_t s);
 hipError_t launch_fill_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks,
                                hipStream_t s);  // z = 0, 256 * 1024 elements per workgroup
 int fill_tiles(const BatchImage& I);
+// Reverse sweep, level `lev` of v = W w with the cotangent update applied to
+// every band it produces (the low-pass of inner levels goes to tmp as usual):
+//   init:  zbar_b  = delta 1{|zk_b| > mu_b} v_b,  part += -delta sgn(zk) 1{..} v
+//   else:  zbar_b -= delta 1{|zk_b| > mu_b} v_b,  part += +delta sgn(zk) 1{..} v
+// Input: w (level 1), else the previous level's low-pass.
+// part: running per-workgroup band sums [nblocks][9] (slot 8 = low-pass).
+int analysis_adjoint_tiles(int N, int d);
+hipError_t launch_analysis_adjoint_batched(const BatchImage* imgs, const int* bmap, const int* bfirst,
+                                           int nblocks, int lev, int d, int init, double* part, hipStream_t s);
 
 // ---- spectral preconditioner --------------------------------------------
 // BCCB: rows r2c -> T (half spectrum, transposed [n/2+1][ts] complex; the row
@@ -187,8 +207,32 @@ int fft_cols_batch(int n);
 int fft_seq_shift(int batch);
 // batched preconditioner passes: pass 0 rows forward, 1 columns, 2 rows inverse
 int precond_pass_tiles(const BatchImage& I, int pass);
+// pass 3: columns, inverse FFT only, of the real dense spectrum I.eacc (into swork)
 hipError_t launch_precond_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks,
                                   int pass, int precond, int nmax, hipStream_t s);
+
+// ---- PSF correlations of the reverse sweep ---------------------------------
+// Per tile of the n x n grid, running sums over the steps of
+//   part[b][a*p+q] += sum_{y,x} tk[y][x] u[y+p-1-a][x+p-1-q] - t[y][x] uk[y+p-1-a][x+p-1-q]
+//   apart[b]       -= sum_{y,x} t[y][x] tk[y][x]
+//   dg             (+)= t   (written at the first step)
+// with u = W^T zbar and t = rbar of the descriptor.
+int psf_corr_tiles(const BatchImage& I);
+hipError_t launch_psf_corr_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks,
+                                   int p, int first, double* part, double* apart, hipStream_t s);
+// spec[i][a*p+q] = -2 n^2 sum_{a',q'} H[a'][q'] e[(a'-a) mod n][(q'-q) mod n], e = I.t (one workgroup per image)
+hipError_t launch_psf_spectral_batched(const BatchImage* imgs, int count, int p, double* spec, hipStream_t s);
+// Running partials of the reverse sweep and their final reduction into
+// dmu[bands], dalpha and dpsf[p*p] (all device doubles, written).
+struct UnrolledSums {
+    int bands, levels, p, count, corr_blocks;
+    int mu_blocks[4];
+    const double* mu_part[4];  // per level [blocks][9]
+    const double* alpha_part;  // [corr_blocks]
+    const double* corr_part;   // [corr_blocks][p*p]
+    const double* spec;        // [count][p*p]
+};
+hipError_t launch_unrolled_reduce(const UnrolledSums& S, double* dmu, double* dalpha, double* dpsf, hipStream_t s);
 
 // ---- reductions and small helpers ---------------------------------------
 // out[0] = sum of partials[0..count) in a fixed order (double)

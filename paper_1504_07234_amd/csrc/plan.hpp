@@ -78,6 +78,7 @@ inline mlba::BatchImage plan_desc(const mlba_plan_s* P) {
     d.tmp0 = P->tmp[0];
     d.tmp1 = P->tmp[1];
     d.z = P->z;
+    d.zin = P->z;
     d.psf = P->psf;
     d.spec = P->spec;
     d.swork = P->swork;

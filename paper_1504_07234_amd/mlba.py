@@ -292,3 +292,139 @@ class Batch:
         if track:
             norms = [list(rn[i * iters:(i + 1) * iters]) for i in range(count)]
         return outs, norms
+
+
+class Unrolled:
+    """K unrolled iterations of eq. (MLBA2) for a batch of images (rectangular
+    blur, BCCB preconditioner, one shared PSF, alpha, mu and delta) and their
+    reverse-mode gradient, checkpointing z every `ckpt_every` iterations.
+    Owns one plan per image."""
+
+    def __init__(self, sizes, p: int, levels: int, psf: torch.Tensor, iters: int, ckpt_every: int = 5,
+                 stream=None):
+        self._lib = _lib.load()
+        self.sizes = [int(n) for n in sizes]
+        self.p, self.levels, self.iters, self.ckpt_every = int(p), int(levels), int(iters), int(ckpt_every)
+        self.plans = [Plan(n, p, RECT, BCCB, levels, psf, stream) for n in self.sizes]
+        self.bands = self.plans[0].bands
+        self._h = ctypes.c_void_p()
+        arr = (ctypes.c_void_p * len(self.plans))(*[pl._h.value for pl in self.plans])
+        check(self._lib.mlba_unrolled_create(ctypes.byref(self._h), len(self.plans), arr, self.iters,
+                                             self.ckpt_every, _stream(stream)), "mlba_unrolled_create")
+        seg = ctypes.c_int()
+        elems = (ctypes.c_size_t * len(self.plans))()
+        check(self._lib.mlba_unrolled_dims(self._h, ctypes.byref(seg), elems), "mlba_unrolled_dims")
+        self.segments = seg.value
+        self.ckpt_elems = list(elems)
+
+    def close(self):
+        if self._h:
+            torch.cuda.synchronize()
+            self._lib.mlba_unrolled_destroy(self._h)
+            self._h = ctypes.c_void_p()
+        for pl in getattr(self, "plans", []):
+            pl.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_psf(self, psf: torch.Tensor, stream=None):
+        for pl in self.plans:
+            pl.set_psf(psf, stream)
+
+    def _ptrs(self, ts, name, shape_of):
+        if len(ts) != len(self.plans):
+            raise ValueError(f"{name}: one tensor per image")
+        return (ctypes.c_void_p * len(ts))(*[_dev(t, name, shape_of(pl)).value for t, pl in zip(ts, self.plans)])
+
+    def _mu(self, mu):
+        mus = [float(mu)] if isinstance(mu, (int, float)) else [float(v) for v in mu]
+        return _dbl_array(mus) + (len(mus),)
+
+    def new_checkpoints(self):
+        dev = torch.device("cuda", torch.cuda.current_device())
+        return [torch.empty(e, device=dev, dtype=torch.float32) for e in self.ckpt_elems]
+
+    def forward(self, gs, *, alpha: float, mu, delta: float, ckpts=None, outs=None, stream=None):
+        """Returns (list of f_i, list of checkpoint buffers)."""
+        ckpts = self.new_checkpoints() if ckpts is None else ckpts
+        outs = [pl._new(pl.N, pl.N) for pl in self.plans] if outs is None else outs
+        gp = self._ptrs(gs, "g", lambda pl: (pl.n, pl.n))
+        fp = self._ptrs(outs, "f", lambda pl: (pl.N, pl.N))
+        cp = (ctypes.c_void_p * len(ckpts))(*[_dev(c, "ckpt", (e,)).value for c, e in zip(ckpts, self.ckpt_elems)])
+        marr, mp, n_mu = self._mu(mu)
+        check(self._lib.mlba_unrolled_forward(self._h, gp, float(alpha), mp, n_mu, float(delta), cp, fp,
+                                              _stream(stream)), "mlba_unrolled_forward")
+        return outs, ckpts
+
+    def backward(self, gs, dfs, ckpts, *, alpha: float, mu, delta: float, want_dg: bool = True, stream=None):
+        """Gradients of a loss with dl/df_i = dfs[i]: dict with 'mu' (bands,),
+        'alpha' (), 'psf' (p, p) float64 device tensors and 'g' (list of
+        n_i x n_i float32, or None)."""
+        dev = torch.device("cuda", torch.cuda.current_device())
+        gp = self._ptrs(gs, "g", lambda pl: (pl.n, pl.n))
+        dp = self._ptrs(dfs, "df", lambda pl: (pl.N, pl.N))
+        cp = (ctypes.c_void_p * len(ckpts))(*[_dev(c, "ckpt", (e,)).value for c, e in zip(ckpts, self.ckpt_elems)])
+        dmu = torch.empty(self.bands, device=dev, dtype=torch.float64)
+        dal = torch.empty((), device=dev, dtype=torch.float64)
+        dpsf = torch.empty(self.p, self.p, device=dev, dtype=torch.float64)
+        dgs = [pl._new(pl.n, pl.n) for pl in self.plans] if want_dg else None
+        dgp = self._ptrs(dgs, "dg", lambda pl: (pl.n, pl.n)) if want_dg else None
+        marr, mp, n_mu = self._mu(mu)
+        check(self._lib.mlba_unrolled_backward(self._h, gp, float(alpha), mp, n_mu, float(delta), cp, dp,
+                                               ctypes.c_void_p(dmu.data_ptr()), ctypes.c_void_p(dal.data_ptr()),
+                                               ctypes.c_void_p(dpsf.data_ptr()), dgp, _stream(stream)),
+              "mlba_unrolled_backward")
+        return {"mu": dmu, "alpha": dal, "psf": dpsf, "g": dgs}
+
+
+class UnrolledMLBA(torch.autograd.Function):
+    """f = unrolled MLBA(g; psf, alpha, mu) over a batch of equal-size images.
+
+    g: (B, n, n) float32; psf: (p, p) float32; alpha: 0-d tensor; mu: (bands,)
+    tensor; returns f: (B, N, N).  `engine` is an Unrolled built for B images
+    of side n (its PSF is replaced by `psf` on every call); delta is a float.
+    The backward pass recomputes each checkpoint segment once."""
+
+    @staticmethod
+    def forward(ctx, g, psf, alpha, mu, engine, delta):
+        B = g.shape[0]
+        g = g.detach().contiguous()
+        psf_d = psf.detach().contiguous()
+        engine.set_psf(psf_d)
+        a = float(alpha)
+        m = [float(v) for v in mu.detach().reshape(-1).cpu()]
+        N = engine.plans[0].N
+        f = torch.empty(B, N, N, device=g.device, dtype=torch.float32)
+        outs, ckpts = engine.forward([g[i] for i in range(B)], alpha=a, mu=m, delta=delta,
+                                     outs=[f[i] for i in range(B)])
+        ctx.engine, ctx.delta, ctx.alpha, ctx.mu, ctx.ckpts = engine, delta, a, m, ckpts
+        ctx.save_for_backward(g, psf_d)
+        return f
+
+    @staticmethod
+    def backward(ctx, df):
+        g, psf = ctx.saved_tensors
+        engine = ctx.engine
+        engine.set_psf(psf)
+        B = g.shape[0]
+        df = df.contiguous()
+        res = engine.backward([g[i] for i in range(B)], [df[i] for i in range(B)], ctx.ckpts, alpha=ctx.alpha,
+                              mu=ctx.mu, delta=ctx.delta, want_dg=ctx.needs_input_grad[0])
+        dg = torch.stack(res["g"]) if res["g"] is not None else None
+        return (dg, res["psf"].to(psf.dtype), res["alpha"].to(torch.float32), res["mu"].to(torch.float32),
+                None, None)
+
+
+def unrolled_mlba(g, psf, alpha, mu, engine: Unrolled, delta: float):
+    """Differentiable K-iteration MLBA restoration (see UnrolledMLBA)."""
+    return UnrolledMLBA.apply(g, psf, alpha, mu, engine, delta)
