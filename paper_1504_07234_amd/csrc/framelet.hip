@@ -37,13 +37,13 @@ __host__ __device__ constexpr int pair_slot(int i, int j) { return i * 3 + j - 1
 // store so that 9 * AN_TY independent loads are in flight per thread.
 constexpr int AN_TY = 8;
 
-// x-direction filters h_i at column x on the rows y0-D .. y0+AN_TY-1+D
-template <int D>
+// x-direction filters h_i at column x on the rows y0-D .. y0+TY-1+D
+template <int D, int TY = AN_TY>
 __device__ __forceinline__ void analysis_xfilter(const float* __restrict__ v, int N, int x, int y0,
                                                  float* h0, float* h1, float* h2) {
     const int xl = reflect_index(x - D, N), xr = reflect_index(x + D, N);
 #pragma unroll
-    for (int q = 0; q < AN_TY + 2 * D; ++q) {
+    for (int q = 0; q < TY + 2 * D; ++q) {
         const float* row = v + (size_t)reflect_index(y0 - D + q, N) * N;
         const float a = row[xl], b = row[x], e = row[xr];
         h0[q] = fmaf(0.25f, a + e, 0.5f * b);
@@ -127,49 +127,62 @@ __global__ __launch_bounds__(kBlock) void analysis_level_kernel(const float* __r
 // v the cotangent update under the active set of the forward state zk (the
 // a.e. derivative of the soft threshold: 1{|zk| > mu}, 0 at the kink).  psum
 // collects the thread's contribution to the threshold gradient per slot.
+// A wave covers 64 columns x ADJ_TY rows and a workgroup four such strips
+// stacked in y; the forward state and the old cotangent of the strip are
+// loaded before the first store.
+constexpr int ADJ_TY = 4;
+constexpr int ADJ_TX = 64;
+
 template <int D>
 __device__ __forceinline__ void analysis_adjoint_tile(const float* __restrict__ v, int N,
-                                                      const float* __restrict__ zk_lev, float* zb_lev,
-                                                      const float* __restrict__ zk_low, float* zb_low,
+                                                      const float* __restrict__ zk_lev,
+                                                      float* __restrict__ zb_lev,
+                                                      const float* __restrict__ zk_low,
+                                                      float* __restrict__ zb_low,
                                                       float* __restrict__ low_out, const LevelMu& mu,
                                                       float delta, int init, int bx, int by, float* psum) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) psum[q] = 0.0f;
-    const int x = bx * kBlock + threadIdx.x;
-    const int y0 = by * AN_TY;
-    if (x >= N) return;
+    const int x = bx * ADJ_TX + (threadIdx.x & (ADJ_TX - 1));
+    const int y0 = (by * (kBlock / ADJ_TX) + (threadIdx.x / ADJ_TX)) * ADJ_TY;
+    if (x >= N || y0 >= N) return;
     const size_t NN = (size_t)N * N;
-    const int rows = min(AN_TY, N - y0);
+    const int rows = min(ADJ_TY, N - y0);
+    const bool last = zk_low != nullptr;
     const float sd = init ? delta : -delta;  // change of zbar per unit of v where active
 
-    float zkv[AN_TY][9];
+    float zkv[ADJ_TY][9], zbv[ADJ_TY][9];
 #pragma unroll
-    for (int r = 0; r < AN_TY; ++r) {
+    for (int r = 0; r < ADJ_TY; ++r) {
         if (r < rows) {
             const size_t o = (size_t)(y0 + r) * N + x;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) zkv[r][q] = zk_lev[q * NN + o];
-            zkv[r][8] = zk_low ? zk_low[o] : 0.0f;
+            for (int q = 0; q < 8; ++q) {
+                zkv[r][q] = zk_lev[q * NN + o];
+                zbv[r][q] = init ? 0.0f : zb_lev[q * NN + o];
+            }
+            zkv[r][8] = last ? zk_low[o] : 0.0f;
+            zbv[r][8] = (last && !init) ? zb_low[o] : 0.0f;
         }
     }
-    float h0[AN_TY + 2 * D], h1[AN_TY + 2 * D], h2[AN_TY + 2 * D];
-    analysis_xfilter<D>(v, N, x, y0, h0, h1, h2);
+    float h0[ADJ_TY + 2 * D], h1[ADJ_TY + 2 * D], h2[ADJ_TY + 2 * D];
+    analysis_xfilter<D, ADJ_TY>(v, N, x, y0, h0, h1, h2);
 
 #pragma unroll
-    for (int r = 0; r < AN_TY; ++r) {
+    for (int r = 0; r < ADJ_TY; ++r) {
         if (r >= rows) break;
         const size_t o = (size_t)(y0 + r) * N + x;
         float out[9];
         analysis_yfilter<D>(h0, h1, h2, r, out);
-        if (!zk_low) low_out[o] = out[8];
+        if (!last) low_out[o] = out[8];
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-            if (q == 8 && !zk_low) continue;
-            float* zb = q < 8 ? zb_lev + q * NN : zb_low;
+            if (q == 8 && !last) continue;
             const float m = q < 8 ? mu.band[q] : mu.low;
-            const float old = init ? 0.0f : zb[o];
             const bool act = fabsf(zkv[r][q]) > m;
-            zb[o] = act ? fmaf(sd, out[q], old) : old;
+            const float nv = act ? fmaf(sd, out[q], zbv[r][q]) : zbv[r][q];
+            if (q < 8) zb_lev[q * NN + o] = nv;
+            else zb_low[o] = nv;
             if (act) psum[q] -= sd * (zkv[r][q] > 0.0f ? out[q] : -out[q]);
         }
     }
@@ -383,7 +396,7 @@ __global__ __launch_bounds__(kBlock) void analysis_adjoint_batched_kernel(const 
     mu.low = I.mu[0];
 #pragma unroll
     for (int q = 0; q < 8; ++q) mu.band[q] = I.mu[1 + 8 * (lev - 1) + q];
-    const int gx = (I.N + kBlock - 1) / kBlock;
+    const int gx = (I.N + ADJ_TX - 1) / ADJ_TX;
     const int local = blockIdx.x - bfirst[im];
     const int by = local / gx;
     float ps[9];
@@ -405,7 +418,10 @@ __global__ __launch_bounds__(kBlock) void analysis_adjoint_batched_kernel(const 
     }
 }
 
-int analysis_adjoint_tiles(int N, int d) { return analysis_level_tiles(N, d); }
+int analysis_adjoint_tiles(int N, int d) {
+    constexpr int rows = (kBlock / ADJ_TX) * ADJ_TY;
+    return ((N + ADJ_TX - 1) / ADJ_TX) * ((N + rows - 1) / rows);
+}
 
 hipError_t launch_analysis_adjoint_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks,
                                            int lev, int d, int init, double* part, hipStream_t s) {

@@ -62,7 +62,7 @@ struct mlba_unrolled_s {
     std::vector<ImgBufs> bufs;
     std::vector<void*> allocs;
     int* maps = nullptr;
-    Map conv_a, conv_at, pre[3], syn[5], ana[5], corr, fill;
+    Map conv_a, conv_at, pre[3], syn[5], ana[5], adj[5], corr, fill;
     double* dblock = nullptr;  // running partials (doubles), zeroed per backward
     size_t dcount = 0;
     float* eblock = nullptr;   // eacc of every image, zeroed per backward
@@ -256,8 +256,10 @@ int mlba_unrolled_create(mlba_unrolled_t* out, int count, const mlba_plan_t* pla
     for (int lev = 1; lev <= U->levels; ++lev) {
         for (int i = 0; i < count; ++i) t[i] = synthesis_level_tiles(U->base[i].N, 1 << (lev - 1));
         add(U->syn[lev]);
-        for (int i = 0; i < count; ++i) t[i] = analysis_adjoint_tiles(U->base[i].N, 1 << (lev - 1));
+        for (int i = 0; i < count; ++i) t[i] = analysis_level_tiles(U->base[i].N, 1 << (lev - 1));
         add(U->ana[lev]);
+        for (int i = 0; i < count; ++i) t[i] = analysis_adjoint_tiles(U->base[i].N, 1 << (lev - 1));
+        add(U->adj[lev]);
     }
     for (int i = 0; i < count; ++i) t[i] = psf_corr_tiles(U->base[i]);
     add(U->corr);
@@ -274,7 +276,7 @@ int mlba_unrolled_create(mlba_unrolled_t* out, int count, const mlba_plan_t* pla
     U->dcount = 0;
     for (int lev = 1; lev <= U->levels; ++lev) {
         off[lev - 1] = U->dcount;
-        U->dcount += (size_t)U->ana[lev].nblocks * 9;
+        U->dcount += (size_t)U->adj[lev].nblocks * 9;
     }
     off[4] = U->dcount;
     U->dcount += U->corr.nblocks;
@@ -424,7 +426,7 @@ int mlba_unrolled_backward(mlba_unrolled_t U, const float* const* g, double alph
         for (int k = 0; k < L; ++k) STCHK(enqueue_step(U, table(U, t_rec[j][k]), s));
         if (j == J - 1)
             for (int lev = 1; lev <= U->levels; ++lev) {
-                const Map& m = U->ana[lev];
+                const Map& m = U->adj[lev];
                 HIPCHK(launch_analysis_adjoint_batched(table(U, t_init), m.bmap, m.bfirst, m.nblocks, lev,
                                                        1 << (lev - 1), 1, U->mu_part[lev - 1], s));
             }
@@ -441,7 +443,7 @@ int mlba_unrolled_backward(mlba_unrolled_t U, const float* const* g, double alph
             HIPCHK(launch_conv_batched(T, U->conv_at.bmap, U->conv_at.bfirst, U->conv_at.nblocks, 0, U->p, nullptr,
                                        s));
             for (int lev = 1; lev <= U->levels; ++lev) {
-                const Map& m = U->ana[lev];
+                const Map& m = U->adj[lev];
                 HIPCHK(launch_analysis_adjoint_batched(T, m.bmap, m.bfirst, m.nblocks, lev, 1 << (lev - 1), 0,
                                                        U->mu_part[lev - 1], s));
             }
@@ -464,7 +466,7 @@ int mlba_unrolled_backward(mlba_unrolled_t U, const float* const* g, double alph
     S.count = U->count;
     S.corr_blocks = U->corr.nblocks;
     for (int lev = 1; lev <= U->levels; ++lev) {
-        S.mu_blocks[lev - 1] = U->ana[lev].nblocks;
+        S.mu_blocks[lev - 1] = U->adj[lev].nblocks;
         S.mu_part[lev - 1] = U->mu_part[lev - 1];
     }
     S.alpha_part = U->alpha_part;
