@@ -205,6 +205,37 @@ int mlba_batch_restore(mlba_batch_t batch, const float* const* g, const double* 
                        int n_mu, const double* delta, int iters, float* const* f_out, float* const* z_state,
                        double* rnorm_out, int use_graph, hipStream_t stream);
 
+/* Autotuner of the batch's tile shapes.  Times every candidate of each
+ * tunable phase on the batch's own images, `reps` launches each after one
+ * untimed launch (HIP events on `stream`, synchronous), and keeps the fastest:
+ *   - the blur A and the adjoint blur A^T: one or two output rows per thread
+ *     (32- or 64-row tiles; PSFs with p > 33 always use 64-row tiles);
+ *   - the preconditioner's row passes: at most 1, 2 or 4 row pairs per
+ *     workgroup, or the built-in choice per size (cap 0);
+ *   - its column pass: at most 1, 2, 4, 8 or 16 columns per workgroup, or
+ *     the built-in choice (cap 0).
+ * The timed launches only write the plans' scratch buffers (residual,
+ * spectral workspace, A^T output), never a state.  A captured graph is
+ * dropped and re-captured by the next graph restore.  Results do not depend on
+ * the tile shapes: every choice computes each output with the same
+ * arithmetic.  out (host, optional) receives the choices and the timings. */
+#define MLBA_TUNE_ROWS 4
+#define MLBA_TUNE_COLS 6
+typedef struct mlba_batch_tuning {
+    int conv_rows[2];                 /* chosen rows per thread: A, A^T          */
+    int fft_rows_cap, fft_cols_cap;   /* chosen caps (0: built-in choice)        */
+    double conv_ms[2][2];             /* [A / A^T][1 / 2 rows] mean ms per launch */
+    double rows_ms[MLBA_TUNE_ROWS];   /* caps 0, 1, 2, 4: both row passes        */
+    double cols_ms[MLBA_TUNE_COLS];   /* caps 0, 1, 2, 4, 8, 16                  */
+} mlba_batch_tuning;
+int mlba_batch_autotune(mlba_batch_t batch, int reps, mlba_batch_tuning* out, hipStream_t stream);
+/* Sets the tile shapes directly from choice->conv_rows (each 1 or 2),
+ * choice->fft_rows_cap and choice->fft_cols_cap (>= 0; a cap is rounded down
+ * to a valid power of two per image size); the timings are ignored.  Lets a
+ * caller reuse tuned choices for another batch of the same shapes
+ * (synchronous). */
+int mlba_batch_set_tiles(mlba_batch_t batch, const mlba_batch_tuning* choice, hipStream_t stream);
+
 /* ---- differentiable unrolled MLBA -----------------------------------------
  * K iterations of eq. (MLBA2) from z = 0, f = W^T(delta S_mu(z^K)), for a
  * batch of images with the rectangular blur (section 2.1) and the BCCB

@@ -32,6 +32,11 @@ class Stop(ctypes.Structure):
     _fields_ = [("noise_norm", c_double), ("gamma", c_double), ("check_every", c_int)]
 
 
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("conv_rows", c_int * 2), ("fft_rows_cap", c_int), ("fft_cols_cap", c_int),
+                ("conv_ms", (c_double * 2) * 2), ("rows_ms", c_double * 4), ("cols_ms", c_double * 6)]
+
+
 class Params(ctypes.Structure):
     _fields_ = [("alpha", AlphaSchedule), ("mu", c_dbl_p), ("n_mu", c_int), ("delta", c_double),
                 ("delta_table", c_dbl_p), ("iters", c_int), ("k0", c_int),
@@ -63,6 +68,8 @@ SIGNATURES = {
     "mlba_batch_destroy": (c_int, [c_void_p]),
     "mlba_batch_restore": (c_int, [c_void_p, ctypes.POINTER(c_void_p), c_dbl_p, c_dbl_p, c_int, c_dbl_p, c_int,
                                    ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_dbl_p, c_int, c_void_p]),
+    "mlba_batch_autotune": (c_int, [c_void_p, c_int, ctypes.POINTER(BatchTuning), c_void_p]),
+    "mlba_batch_set_tiles": (c_int, [c_void_p, ctypes.POINTER(BatchTuning), c_void_p]),
     "mlba_unrolled_create": (c_int, [ctypes.POINTER(c_void_p), c_int, ctypes.POINTER(c_void_p), c_int, c_int,
                                      c_void_p]),
     "mlba_unrolled_destroy": (c_int, [c_void_p]),

@@ -39,6 +39,9 @@ struct mlba_batch_s {
     BatchImage* imgs = nullptr;
     int* maps = nullptr;  // one device buffer holding every map
     Map conv_a, conv_at, fold, fill, pre[3], syn[5], ana[5];
+    // tile choices (set by mlba_batch_autotune)
+    int conv_ry[2] = {1, 1};          // output rows per thread of the A and A^T launches
+    int rows_want = 0, cols_want = 0;  // transform batching caps (0: built-in choice per size)
     double* partials = nullptr;
     int* pcount = nullptr;
     double* rn = nullptr;
@@ -76,6 +79,77 @@ void build_map(const std::vector<int>& tiles, std::vector<int>& host_maps, std::
     }
 }
 
+// Applies the batch's tile choices: per-image transform batching and residual
+// partial offsets, every phase map (device buffer rebuilt), descriptors and
+// partial counts uploaded.  Drops a captured graph (its maps are stale).
+int configure(mlba_batch_s* B, hipStream_t s) {
+    const int count = B->count;
+    int pbase = 0;
+    std::vector<int> pcount(count);
+    for (int i = 0; i < count; ++i) {
+        BatchImage& d = B->host[i];
+        if (d.precond != MLBA_PRECOND_NONE) {
+            d.fft_rows_g = B->rows_want ? fft_rows_batch_at_most(d.n, B->rows_want) : fft_rows_batch(d.n);
+            d.fft_cols_c = B->cols_want ? fft_cols_batch_at_most(d.n, B->cols_want) : fft_cols_batch(d.n);
+            d.fft_rows_shift = fft_seq_shift(d.fft_rows_g);
+            d.fft_cols_shift = fft_seq_shift(d.fft_cols_c);
+        }
+        d.pbase = pbase;
+        pcount[i] = conv_batched_tiles(d, 1, B->conv_ry[0]);
+        pbase += pcount[i];
+    }
+    std::vector<int> hm;
+    std::vector<size_t> offs;
+    std::vector<Map*> order;
+    auto add = [&](Map& m, const std::vector<int>& tiles) {
+        build_map(tiles, hm, offs, m);
+        order.push_back(&m);
+    };
+    std::vector<int> t(count);
+    for (int i = 0; i < count; ++i) t[i] = conv_batched_tiles(B->host[i], 1, B->conv_ry[0]);
+    add(B->conv_a, t);
+    for (int i = 0; i < count; ++i) t[i] = conv_batched_tiles(B->host[i], 0, B->conv_ry[1]);
+    add(B->conv_at, t);
+    for (int i = 0; i < count; ++i) t[i] = B->host[i].bc == MLBA_BC_REFLECT ? B->host[i].n : 0;
+    add(B->fold, t);
+    for (int i = 0; i < count; ++i) t[i] = fill_tiles(B->host[i]);
+    add(B->fill, t);
+    for (int pass = 0; pass < 3; ++pass) {
+        for (int i = 0; i < count; ++i) t[i] = precond_pass_tiles(B->host[i], pass);
+        add(B->pre[pass], t);
+    }
+    for (int lev = 1; lev <= B->levels; ++lev) {
+        for (int i = 0; i < count; ++i) t[i] = synthesis_level_tiles(B->host[i].N, 1 << (lev - 1));
+        add(B->syn[lev], t);
+        for (int i = 0; i < count; ++i) t[i] = analysis_level_tiles(B->host[i].N, 1 << (lev - 1));
+        add(B->ana[lev], t);
+    }
+    if (B->exec) {
+        HIPCHK(hipGraphExecDestroy(B->exec));
+        B->exec = nullptr;
+    }
+    if (B->maps) {
+        HIPCHK(hipStreamSynchronize(s));  // work still reading the old maps
+        HIPCHK(hipFree(B->maps));
+        B->maps = nullptr;
+    }
+    hipError_t e = hipMalloc(&B->maps, hm.size() * sizeof(int));
+    if (e != hipSuccess) {
+        mlba_internal_set_hip(e);
+        B->maps = nullptr;
+        return MLBA_ENOMEM;
+    }
+    for (size_t q = 0; q < order.size(); ++q) {
+        order[q]->bmap = B->maps + offs[2 * q];
+        order[q]->bfirst = B->maps + offs[2 * q + 1];
+    }
+    HIPCHK(hipMemcpyAsync(B->maps, hm.data(), hm.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(B->pcount, pcount.data(), count * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(B->imgs, B->host.data(), count * sizeof(BatchImage), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return MLBA_OK;
+}
+
 int enqueue(mlba_batch_s* B, int iters, bool fill_state, hipStream_t s) {
     const BatchImage* I = B->imgs;
     if (fill_state) HIPCHK(launch_fill_batched(I, B->fill.bmap, B->fill.bfirst, B->fill.nblocks, s));
@@ -85,14 +159,14 @@ int enqueue(mlba_batch_s* B, int iters, bool fill_state, hipStream_t s) {
             HIPCHK(launch_synthesis_batched(I, m.bmap, m.bfirst, m.nblocks, lev, 1 << (lev - 1), 0, s));
         }
         HIPCHK(launch_conv_batched(I, B->conv_a.bmap, B->conv_a.bfirst, B->conv_a.nblocks, 1, B->pmax, B->partials,
-                                   s));
+                                   s, B->conv_ry[0]));
         HIPCHK(launch_sum_partials_batched(I, B->partials, B->pcount, B->count, k, s));
         if (B->precond != MLBA_PRECOND_NONE)
             for (int pass = 0; pass < 3; ++pass)
                 HIPCHK(launch_precond_batched(I, B->pre[pass].bmap, B->pre[pass].bfirst, B->pre[pass].nblocks, pass,
                                               B->precond, B->nmax, s));
         HIPCHK(launch_conv_batched(I, B->conv_at.bmap, B->conv_at.bfirst, B->conv_at.nblocks, 0, B->pmax, nullptr,
-                                   s));
+                                   s, B->conv_ry[1]));
         if (B->any_reflect) HIPCHK(launch_fold_batched(I, B->fold.bmap, B->fold.bfirst, B->fold.nblocks, s));
         for (int lev = 1; lev <= B->levels; ++lev) {
             const Map& m = B->ana[lev];
@@ -104,6 +178,40 @@ int enqueue(mlba_batch_s* B, int iters, bool fill_state, hipStream_t s) {
         HIPCHK(launch_synthesis_batched(I, m.bmap, m.bfirst, m.nblocks, lev, 1 << (lev - 1), 1, s));
     }
     return MLBA_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Mean milliseconds of `reps` launches of `phase` after one untimed launch.
+template <class F>
+int time_phase(F phase, int reps, hipStream_t s, double* ms) {
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    hipError_t err = hipEventCreate(&e1);
+    if (err != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        mlba_internal_set_hip(err);
+        return MLBA_EHIP;
+    }
+    int st = phase();
+    if (st >= 0) {
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps && st >= 0; ++r) st = phase();
+        (void)hipEventRecord(e1, s);
+        err = hipEventSynchronize(e1);
+        float t = 0.0f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+        if (err != hipSuccess) {
+            mlba_internal_set_hip(err);
+            st = MLBA_EHIP;
+        }
+        *ms = (double)t / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
 }
 
 }  // namespace
@@ -127,47 +235,16 @@ int mlba_batch_create(mlba_batch_t* batch, int count, const mlba_plan_t* plans, 
     B->plans.assign(plans, plans + count);
     B->rn_cap = max_iters;
     B->host.resize(count);
-    int pbase = 0;
-    std::vector<int> pcount(count);
+    int pmax_parts = 0;  // residual partials with one row per thread (the most tiles)
     for (int i = 0; i < count; ++i) {
         B->host[i] = plan_desc(plans[i]);
         B->pmax = std::max(B->pmax, plans[i]->p);
         B->nmax = std::max(B->nmax, plans[i]->n);
         B->any_reflect = B->any_reflect || plans[i]->bc == MLBA_BC_REFLECT;
-        B->host[i].pbase = pbase;
-        pcount[i] = conv_batched_tiles(B->host[i], 1);
-        pbase += pcount[i];
+        pmax_parts += conv_batched_tiles(B->host[i], 1, 1);
     }
-    // phase maps
-    std::vector<int> hm;
-    std::vector<size_t> offs;
-    std::vector<Map*> order;
-    auto add = [&](Map& m, const std::vector<int>& tiles) {
-        build_map(tiles, hm, offs, m);
-        order.push_back(&m);
-    };
-    std::vector<int> t(count);
-    for (int i = 0; i < count; ++i) t[i] = conv_batched_tiles(B->host[i], 1);
-    add(B->conv_a, t);
-    for (int i = 0; i < count; ++i) t[i] = conv_batched_tiles(B->host[i], 0);
-    add(B->conv_at, t);
-    for (int i = 0; i < count; ++i) t[i] = B->host[i].bc == MLBA_BC_REFLECT ? B->host[i].n : 0;
-    add(B->fold, t);
-    for (int i = 0; i < count; ++i) t[i] = fill_tiles(B->host[i]);
-    add(B->fill, t);
-    for (int pass = 0; pass < 3; ++pass) {
-        for (int i = 0; i < count; ++i) t[i] = precond_pass_tiles(B->host[i], pass);
-        add(B->pre[pass], t);
-    }
-    for (int lev = 1; lev <= B->levels; ++lev) {
-        for (int i = 0; i < count; ++i) t[i] = synthesis_level_tiles(B->host[i].N, 1 << (lev - 1));
-        add(B->syn[lev], t);
-        for (int i = 0; i < count; ++i) t[i] = analysis_level_tiles(B->host[i].N, 1 << (lev - 1));
-        add(B->ana[lev], t);
-    }
-    hipError_t e = hipMalloc(&B->maps, hm.size() * sizeof(int));
-    if (e == hipSuccess) e = hipMalloc(&B->imgs, count * sizeof(BatchImage));
-    if (e == hipSuccess) e = hipMalloc(&B->partials, (size_t)std::max(pbase, 1) * sizeof(double));
+    hipError_t e = hipMalloc(&B->imgs, count * sizeof(BatchImage));
+    if (e == hipSuccess) e = hipMalloc(&B->partials, (size_t)std::max(pmax_parts, 1) * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&B->pcount, count * sizeof(int));
     if (e == hipSuccess) e = hipMalloc(&B->rn, (size_t)count * max_iters * sizeof(double));
     if (e != hipSuccess) {
@@ -175,15 +252,13 @@ int mlba_batch_create(mlba_batch_t* batch, int count, const mlba_plan_t* plans, 
         destroy_batch(B);
         return MLBA_ENOMEM;
     }
-    for (size_t q = 0; q < order.size(); ++q) {
-        order[q]->bmap = B->maps + offs[2 * q];
-        order[q]->bfirst = B->maps + offs[2 * q + 1];
-    }
     for (int i = 0; i < count; ++i) B->host[i].rn = B->rn + (size_t)i * max_iters;
-    e = hipMemcpyAsync(B->maps, hm.data(), hm.size() * sizeof(int), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(B->pcount, pcount.data(), count * sizeof(int), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking);
+    int st = configure(B, s);
+    if (st < 0) {
+        destroy_batch(B);
+        return st;
+    }
+    e = hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
         mlba_internal_set_hip(e);
         destroy_batch(B);
@@ -191,6 +266,96 @@ int mlba_batch_create(mlba_batch_t* batch, int count, const mlba_plan_t* plans, 
     }
     *batch = B;
     return MLBA_OK;
+}
+
+int mlba_batch_autotune(mlba_batch_t B, int reps, mlba_batch_tuning* out, hipStream_t s) {
+    if (!B || reps < 1) return MLBA_EINVAL;
+    const BatchImage* I = B->imgs;
+    // A and A^T: one or two output rows per thread
+    for (int which = 0; which < 2; ++which) {
+        double best = 1e300;
+        int best_ry = 1;
+        for (int ry = 1; ry <= 2; ++ry) {
+            B->conv_ry[which] = ry;
+            STCHK(configure(B, s));
+            const Map& m = which == 0 ? B->conv_a : B->conv_at;
+            double ms = 0.0;
+            STCHK(time_phase([&]() -> int {
+                HIPCHK(launch_conv_batched(I, m.bmap, m.bfirst, m.nblocks, which == 0 ? 1 : 0, B->pmax, nullptr, s,
+                                           ry));
+                return MLBA_OK;
+            }, reps, s, &ms));
+            if (out) out->conv_ms[which][ry - 1] = ms;
+            if (ms < best) {
+                best = ms;
+                best_ry = ry;
+            }
+        }
+        B->conv_ry[which] = best_ry;
+    }
+    if (B->precond != MLBA_PRECOND_NONE) {
+        // row passes (forward and inverse): caps on the row pairs per workgroup
+        static const int rows_cand[MLBA_TUNE_ROWS] = {0, 1, 2, 4};
+        double best = 1e300;
+        int best_w = 0;
+        for (int c = 0; c < MLBA_TUNE_ROWS; ++c) {
+            B->rows_want = rows_cand[c];
+            STCHK(configure(B, s));
+            double ms = 0.0;
+            STCHK(time_phase([&]() -> int {
+                for (int pass = 0; pass < 3; pass += 2)
+                    HIPCHK(launch_precond_batched(I, B->pre[pass].bmap, B->pre[pass].bfirst, B->pre[pass].nblocks,
+                                                  pass, B->precond, B->nmax, s));
+                return MLBA_OK;
+            }, reps, s, &ms));
+            if (out) out->rows_ms[c] = ms;
+            if (ms < best) {
+                best = ms;
+                best_w = rows_cand[c];
+            }
+        }
+        B->rows_want = best_w;
+        // column pass: caps on the columns per workgroup
+        static const int cols_cand[MLBA_TUNE_COLS] = {0, 1, 2, 4, 8, 16};
+        best = 1e300;
+        best_w = 0;
+        for (int c = 0; c < MLBA_TUNE_COLS; ++c) {
+            B->cols_want = cols_cand[c];
+            STCHK(configure(B, s));
+            double ms = 0.0;
+            STCHK(time_phase([&]() -> int {
+                HIPCHK(launch_precond_batched(I, B->pre[1].bmap, B->pre[1].bfirst, B->pre[1].nblocks, 1, B->precond,
+                                              B->nmax, s));
+                return MLBA_OK;
+            }, reps, s, &ms));
+            if (out) out->cols_ms[c] = ms;
+            if (ms < best) {
+                best = ms;
+                best_w = cols_cand[c];
+            }
+        }
+        B->cols_want = best_w;
+    }
+    STCHK(configure(B, s));
+    if (out) {
+        out->conv_rows[0] = B->conv_ry[0];
+        out->conv_rows[1] = B->conv_ry[1];
+        out->fft_rows_cap = B->rows_want;
+        out->fft_cols_cap = B->cols_want;
+    }
+    return MLBA_OK;
+}
+
+int mlba_batch_set_tiles(mlba_batch_t B, const mlba_batch_tuning* choice, hipStream_t s) {
+    if (!B || !choice) return MLBA_EINVAL;
+    for (int w = 0; w < 2; ++w)
+        if (choice->conv_rows[w] != 1 && choice->conv_rows[w] != 2) return MLBA_EINVAL;
+    if (choice->fft_rows_cap < 0 || choice->fft_cols_cap < 0) return MLBA_EINVAL;
+    B->conv_ry[0] = choice->conv_rows[0];
+    B->conv_ry[1] = choice->conv_rows[1];
+    B->rows_want = choice->fft_rows_cap;
+    B->cols_want = choice->fft_cols_cap;
+    return configure(B, s);
 }
 
 int mlba_batch_destroy(mlba_batch_t B) {

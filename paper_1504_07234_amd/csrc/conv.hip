@@ -251,12 +251,12 @@ hipError_t launch_conv_job(const ConvJob& j, int p, int flip, int ry, double* pa
 // FLIP: r = g - A u with the residual-norm partial of the tile written to
 // partials[pbase + local tile]; otherwise the A^T correlation.
 
-template <bool FLIP>
+template <bool FLIP, int RY>
 __device__ __forceinline__ double conv_tile_dispatch(const ConvJob& j, int p, int bx, int by, float* lds) {
     switch (p) {
 #define MLBA_CONV_DISPATCH(PP) \
     case PP:                   \
-        return conv_tile<PP, FLIP, 1>(j, bx, by, lds);
+        return conv_tile<PP, FLIP, RY>(j, bx, by, lds);
         MLBA_CONV_DISPATCH(1)
         MLBA_CONV_DISPATCH(3)
         MLBA_CONV_DISPATCH(5)
@@ -280,9 +280,11 @@ __device__ __forceinline__ double conv_tile_dispatch(const ConvJob& j, int p, in
     }
 }
 
-static int batched_rows(int p) { return p > 33 ? 2 : 1; }
+// rows per thread of an image's tiles: the launch's choice, or the generic
+// body's 64-row tiles for p > 33
+static int batched_rows(int p, int ry) { return p > 33 ? 2 : ry; }
 
-template <bool FLIP>
+template <bool FLIP, int RY>
 __global__ __launch_bounds__(kBlock) void conv_batched_kernel(const BatchImage* __restrict__ imgs,
                                                               const int* __restrict__ bmap,
                                                               const int* __restrict__ bfirst,
@@ -296,31 +298,39 @@ __global__ __launch_bounds__(kBlock) void conv_batched_kernel(const BatchImage* 
     const int gx = (j.D + CONV_TX - 1) / CONV_TX;
     const int by = local / gx;
     const int bx = local - by * gx;
-    const double ss = conv_tile_dispatch<FLIP>(j, I.p, bx, by, smem);
+    const double ss = conv_tile_dispatch<FLIP, RY>(j, I.p, bx, by, smem);
     if (FLIP && partials) conv_partial(ss, red, partials + I.pbase + local);
 }
 
-int conv_batched_tiles(const BatchImage& I, int flip) {
+int conv_batched_tiles(const BatchImage& I, int flip, int ry) {
     const ConvJob j = flip ? blur_job(I) : blurT_job(I);
-    return conv_tiles(j.D, batched_rows(I.p));
+    return conv_tiles(j.D, batched_rows(I.p, ry));
 }
 
-static size_t conv_batched_lds(int pmax) {
-    return pmax > 33 ? conv_generic_lds(pmax) : (size_t)conv_lds_floats(pmax, 1) * sizeof(float);
+static size_t conv_batched_lds(int pmax, int ry) {
+    const size_t fixed = (size_t)conv_lds_floats(pmax < 33 ? pmax : 33, ry) * sizeof(float);
+    if (pmax <= 33) return fixed;
+    const size_t gen = conv_generic_lds(pmax);
+    return gen > fixed ? gen : fixed;
+}
+
+template <bool FLIP, int RY>
+static hipError_t launch_cb(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks, int pmax,
+                            double* partials, hipStream_t s) {
+    const size_t lds = conv_batched_lds(pmax, RY);
+    if (lds > 64 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((conv_batched_kernel<FLIP, RY>), dim3(nblocks), dim3(kBlock), lds, s, imgs, bmap, bfirst,
+                       partials);
+    return hipGetLastError();
 }
 
 hipError_t launch_conv_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks, int flip,
-                               int pmax, double* partials, hipStream_t s) {
+                               int pmax, double* partials, hipStream_t s, int ry) {
     if (nblocks <= 0) return hipSuccess;
-    const size_t lds = conv_batched_lds(pmax);
-    if (lds > 64 * 1024) return hipErrorInvalidValue;
-    if (flip)
-        hipLaunchKernelGGL(conv_batched_kernel<true>, dim3(nblocks), dim3(kBlock), lds, s, imgs, bmap, bfirst,
-                           partials);
-    else
-        hipLaunchKernelGGL(conv_batched_kernel<false>, dim3(nblocks), dim3(kBlock), lds, s, imgs, bmap, bfirst,
-                           (double*)nullptr);
-    return hipGetLastError();
+    if (flip) return ry == 2 ? launch_cb<true, 2>(imgs, bmap, bfirst, nblocks, pmax, partials, s)
+                             : launch_cb<true, 1>(imgs, bmap, bfirst, nblocks, pmax, partials, s);
+    return ry == 2 ? launch_cb<false, 2>(imgs, bmap, bfirst, nblocks, pmax, nullptr, s)
+                   : launch_cb<false, 1>(imgs, bmap, bfirst, nblocks, pmax, nullptr, s);
 }
 
 // ---- transpose of the reflective padding ---------------------------------

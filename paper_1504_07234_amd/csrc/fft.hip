@@ -568,6 +568,18 @@ static int pick_cols_per_block(int n) {
 }
 
 int fft_rows_batch(int n) { return pick_pairs_per_block(n); }
+
+int fft_rows_batch_at_most(int n, int want) {
+    int G = 1;
+    while (G * 2 <= want && (G * 2) * n <= FFT_MAX_ELEMS && ((n / 2) % (G * 2)) == 0) G *= 2;
+    return G;
+}
+
+int fft_cols_batch_at_most(int n, int want) {
+    int cc = 1;
+    while (cc * 2 <= want && (cc * 2) * n <= FFT_MAX_ELEMS) cc *= 2;
+    return cc;
+}
 int fft_cols_batch(int n) { return pick_cols_per_block(n); }
 int fft_seq_shift(int batch) { return seq_shift_for(batch); }
 

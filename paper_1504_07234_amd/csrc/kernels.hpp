@@ -130,10 +130,11 @@ hipError_t launch_conv_job(const ConvJob& j, int p, int flip, int ry, double* pa
 int conv_partials_count(int D);
 int conv_default_rows(int D, int p);
 int conv_tiles(int D, int ry);
-// batched: tiles of every image in one launch (flip = 1: residual, 0: A^T)
-int conv_batched_tiles(const BatchImage& I, int flip);
+// batched: tiles of every image in one launch (flip = 1: residual, 0: A^T);
+// ry = output rows per thread (1 or 2) of the images with p <= 33
+int conv_batched_tiles(const BatchImage& I, int flip, int ry = 1);
 hipError_t launch_conv_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks,
-                               int flip, int pmax, double* partials, hipStream_t s);
+                               int flip, int pmax, double* partials, hipStream_t s, int ry = 1);
 hipError_t launch_fold_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks,
                                hipStream_t s);
 
@@ -205,6 +206,9 @@ hipError_t launch_pad_psf(const float* psf, int p, float* dst, int n, hipStream_
 int fft_rows_batch(int n);
 int fft_cols_batch(int n);
 int fft_seq_shift(int batch);
+// the largest valid batching <= want (a power of two) for size n
+int fft_rows_batch_at_most(int n, int want);
+int fft_cols_batch_at_most(int n, int want);
 // batched preconditioner passes: pass 0 rows forward, 1 columns, 2 rows inverse
 int precond_pass_tiles(const BatchImage& I, int pass);
 // pass 3: columns, inverse FFT only, of the real dense spectrum I.eacc (into swork)

@@ -260,6 +260,22 @@ class Batch:
     def __exit__(self, *exc):
         self.close()
 
+    def autotune(self, reps: int = 5, stream=None) -> dict:
+        """Times the candidate tile shapes of the tunable phases on this batch and
+        keeps the fastest (see mlba_batch_autotune); returns the choices and timings."""
+        t = _lib.BatchTuning()
+        check(self._lib.mlba_batch_autotune(self._h, int(reps), ctypes.byref(t), _stream(stream)),
+              "mlba_batch_autotune")
+        return {"conv_rows": list(t.conv_rows), "fft_rows_cap": t.fft_rows_cap, "fft_cols_cap": t.fft_cols_cap,
+                "conv_ms": [list(r) for r in t.conv_ms], "rows_ms": list(t.rows_ms), "cols_ms": list(t.cols_ms)}
+
+    def set_tiles(self, conv_rows=(1, 1), fft_rows_cap: int = 0, fft_cols_cap: int = 0, stream=None):
+        """Sets the tile shapes directly (see mlba_batch_set_tiles)."""
+        t = _lib.BatchTuning()
+        t.conv_rows[0], t.conv_rows[1] = int(conv_rows[0]), int(conv_rows[1])
+        t.fft_rows_cap, t.fft_cols_cap = int(fft_rows_cap), int(fft_cols_cap)
+        check(self._lib.mlba_batch_set_tiles(self._h, ctypes.byref(t), _stream(stream)), "mlba_batch_set_tiles")
+
     def restore(self, gs, *, alpha, mu=1e-3, delta=None, iters: int = 100, outs=None, zs=None,
                 use_graph: bool = True, track: bool = False, stream=None):
         """Returns (list of restored images, residual norms [count][iters] or None)."""

@@ -165,3 +165,35 @@ def test_batch_rejects_mixed_levels(mlba):
     assert lib.mlba_batch_create(ctypes.byref(h), 2, arr, 10, None) == _lib.EINVAL
     a.close()
     b.close()
+
+
+def test_tile_choices_do_not_change_results(mlba):
+    """Every tile shape the autotuner can pick computes each output with the
+    same arithmetic: results are bit-identical across choices, including the
+    autotuner's own pick (graph re-captured after each change)."""
+    import torch
+    announce("batched tile choices bitwise")
+    plans, gs, _ = _make(mlba, SIZES)
+    iters = 6
+    gdev = [cuda(g) for g in gs]
+    with mlba.Batch(plans, max_iters=iters) as batch:
+        ref, _ = batch.restore(gdev, alpha=0.05, mu=1e-3, delta=0.25, iters=iters, use_graph=True)
+        ref = [r.clone() for r in ref]
+        choices = [((2, 1), 0, 0), ((1, 2), 0, 0), ((2, 2), 0, 0)]
+        choices += [((1, 1), c, 0) for c in (1, 2, 4)]
+        choices += [((1, 1), 0, c) for c in (1, 2, 4, 8, 16)]
+        for conv_rows, rc, cc in choices:
+            batch.set_tiles(conv_rows, rc, cc)
+            outs, _ = batch.restore(gdev, alpha=0.05, mu=1e-3, delta=0.25, iters=iters, use_graph=True)
+            torch.cuda.synchronize()
+            for i in range(len(plans)):
+                assert torch.equal(outs[i], ref[i]), (conv_rows, rc, cc, i)
+        tuned = batch.autotune(reps=2)
+        assert tuned["conv_rows"][0] in (1, 2) and tuned["conv_rows"][1] in (1, 2)
+        assert all(t > 0 for t in tuned["rows_ms"] + tuned["cols_ms"])
+        outs, _ = batch.restore(gdev, alpha=0.05, mu=1e-3, delta=0.25, iters=iters, use_graph=True)
+        torch.cuda.synchronize()
+        for i in range(len(plans)):
+            assert torch.equal(outs[i], ref[i]), ("tuned", i)
+    for pl in plans:
+        pl.close()
