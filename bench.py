@@ -36,22 +36,38 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, non-packed FP32
 
 
-def phase_model(n, p, N, B):
+def phase_model(n, p, N, B, L, implicit):
     """Algorithmic bytes and flops of each phase of one iteration (float32).
 
-    synthesis : read z (B N^2), write u (N^2)
-    blur      : read u (N^2), read g (n^2), write r (n^2); 2 p^2 n^2 flops
-    precond   : read r (n^2), write t (n^2)
-    blur_t    : read t (n^2), write w (N^2); 2 p^2 n^2 flops
-    analysis  : read w (N^2), read and write z (2 B N^2)
+    Explicit state z ([B][N][N]):
+      synthesis : read z (B N^2), write u (N^2)
+      blur_t    : read t (n^2), write w (N^2); 2 p^2 n^2 flops
+      analysis  : read w (N^2), read and write z (2 B N^2)
+    Implicit state omega (N x N, z = W omega):
+      synthesis : L-1 low-pass levels (read + write N^2 each), then L levels
+                  (read the level's low-pass, read the level above's output
+                  except at the top, write N^2)
+      blur_t    : read t (n^2), read and write omega (2 N^2); 2 p^2 n^2 flops
+      analysis  : none
+    Both:
+      blur      : read u (N^2), read g (n^2), write r (n^2); 2 p^2 n^2 flops
+      precond   : read r (n^2), write t (n^2)
     """
     f4 = 4.0
+    if implicit:
+        syn = f4 * N * N * (2 * (L - 1) + 2 + 3 * (L - 1))
+        bt = f4 * (n * n + 2 * N * N)
+        ana = 0.0
+    else:
+        syn = f4 * (B * N * N + N * N)
+        bt = f4 * (n * n + N * N)
+        ana = f4 * (N * N + 2 * B * N * N)
     return {
-        "synthesis": {"bytes": f4 * (B * N * N + N * N), "flops": 0.0},
+        "synthesis": {"bytes": syn, "flops": 0.0},
         "blur": {"bytes": f4 * (N * N + 2 * n * n), "flops": 2.0 * p * p * n * n},
         "precond": {"bytes": f4 * (2 * n * n), "flops": 0.0},
-        "blur_t": {"bytes": f4 * (n * n + N * N), "flops": 2.0 * p * p * n * n},
-        "analysis": {"bytes": f4 * (N * N + 2 * B * N * N), "flops": 0.0},
+        "blur_t": {"bytes": bt, "flops": 2.0 * p * p * n * n},
+        "analysis": {"bytes": ana, "flops": 0.0},
     }
 
 
@@ -205,6 +221,10 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-sequential section")
     ap.add_argument("--no-unrolled", action="store_true", help="skip the unrolled forward/backward section")
+    ap.add_argument("--state", choices=("implicit", "explicit"), default="implicit",
+                    help="iteration state: omega (z = W omega recomputed) or the frame coefficients z")
+    ap.add_argument("--compare-steps", type=int, default=20,
+                    help="iterations timed with the other state, for comparison (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -236,30 +256,41 @@ def main() -> int:
     g = g.contiguous()
     opn = plan.opnorm(w.alpha0, 50)
     delta = 0.9 / max(opn, 0.9)
-    z = torch.zeros((B, N, N), dtype=torch.float32, device="cuda")
     f = torch.empty((N, N), dtype=torch.float32, device="cuda")
-    torch.cuda.synchronize()
 
-    # ---- warmup ---------------------------------------------------------
-    plan.restore(g, alpha=w.alpha0, mu=w.mu, delta=delta, iters=args.warmup, z=z, out=f, track=False)
-    torch.cuda.synchronize()
+    def run(implicit, steps, warmup, profile):
+        st = torch.zeros((N, N) if implicit else (B, N, N), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        plan.restore(g, alpha=w.alpha0, mu=w.mu, delta=delta, iters=warmup, z=st, out=f, track=False,
+                     implicit=implicit)
+        torch.cuda.synchronize()
+        if profile:
+            plan.profile_begin(steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.restore(g, alpha=w.alpha0, mu=w.mu, delta=delta, iters=steps, k0=warmup, z=st, out=f, track=False,
+                     implicit=implicit)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ph = plan.profile_end() if profile else None
+        _, info = plan.restore(g, alpha=w.alpha0, mu=w.mu, delta=delta, iters=1, k0=warmup + steps, z=st, out=f,
+                               track=True, implicit=implicit)
+        assert np.isfinite(info.rnorm[0]), "non-finite residual"
+        return el, ph
 
-    # ---- timed region: K iterations, phase events on the library stream --
-    plan.profile_begin(args.steps)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan.restore(g, alpha=w.alpha0, mu=w.mu, delta=delta, iters=args.steps, k0=args.warmup, z=z, out=f,
-                 track=False)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    phases, rec = plan.profile_end()
-    _, info = plan.restore(g, alpha=w.alpha0, mu=w.mu, delta=delta, iters=1, k0=args.warmup + args.steps, z=z,
-                           out=f, track=True)
-    assert np.isfinite(info.rnorm[0]), "non-finite residual"
+    implicit = args.state == "implicit"
+    # ---- warmup, then the timed region: K iterations, phase events on the library stream --
+    elapsed, (phases, rec) = run(implicit, args.steps, args.warmup, True)
+    compare = None
+    if args.compare_steps > 0:
+        el2, _ = run(not implicit, args.compare_steps, 3, False)
+        compare = {"state": "explicit z" if implicit else "implicit omega", "steps": args.compare_steps,
+                   "ms_per_step": round(el2 * 1e3 / args.compare_steps, 5),
+                   "Mpx_it_s": round(n * n * args.compare_steps / el2 / 1e6, 2)}
 
     ms_per_step = elapsed * 1e3 / args.steps
     value = n * n * args.steps / elapsed / 1e6
-    model = phase_model(n, p, N, B)
+    model = phase_model(n, p, N, B, w.levels, implicit)
     phase_out = {}
     for ph, (ms, launches) in phases.items():
         per_iter_ms = ms / max(rec, 1)
@@ -267,7 +298,7 @@ def main() -> int:
         phase_out[ph] = {
             "ms_per_iter": round(per_iter_ms, 4),
             "launches_per_iter": launches // max(rec, 1),
-            "GBs": round(b / (per_iter_ms * 1e-3) / 1e9, 1) if per_iter_ms > 0 else None,
+            "GBs": round(b / (per_iter_ms * 1e-3) / 1e9, 1) if per_iter_ms > 0 and b > 0 else None,
             "TFLOPs": round(fl / (per_iter_ms * 1e-3) / 1e12, 2) if fl and per_iter_ms > 0 else None,
         }
     def roofline_of(ph):
@@ -292,11 +323,13 @@ def main() -> int:
     # dominant kernel: the longest single launch of an iteration
     def launch_ms(ph):
         per_iter = max(1, phases[ph][1] // max(rec, 1))
+        if phases[ph][1] == 0:
+            return 0.0
         return phases[ph][0] / max(rec, 1) / (1 if ph == "blur" else per_iter)
 
     dom = max(phases, key=launch_ms)
     roof = roofline_of(dom)
-    roof_hbm = roofline_of("analysis")
+    roof_hbm = roofline_of("synthesis" if implicit else "analysis")
     total_bytes = sum(m["bytes"] for m in model.values())
     hbm_frac = (total_bytes / (HBM_PEAK_GBS * 1e9)) / (ms_per_step * 1e-3)
 
@@ -315,11 +348,12 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": w.name, "n": n, "p": p, "N": N, "levels": w.levels, "bands": B,
                    "boundary": "rect", "precond": "bccb", "alpha": w.alpha0, "mu": w.mu,
-                   "delta": round(delta, 6), "state": "explicit z"},
+                   "delta": round(delta, 6), "state": "implicit omega (z = W omega)" if implicit else "explicit z"},
         "hbm_roofline_frac_whole_step": round(hbm_frac, 4),
         "phases": phase_out,
         "roofline": roof,
         "roofline_hbm": roof_hbm,
+        "other_state": compare,
     }
     plan.close()
     if not args.no_batched:

@@ -106,7 +106,19 @@ typedef struct mlba_params {
     int iters;                 /* iterations to run                           */
     int k0;                    /* global index of the first iteration (resume) */
     const mlba_stop* stop;     /* optional discrepancy stop (NULL: fixed iters) */
+    int state;                 /* MLBA_STATE_EXPLICIT or MLBA_STATE_IMPLICIT    */
 } mlba_params;
+
+/* State kept between iterations.  Explicit: the frame coefficients z
+ * ([bands][N][N]), updated by z += W A^T t.  Implicit: since z^0 = 0 and every
+ * update of eq. (MLBA2) is W applied to A^T t, z^k = W omega^k with
+ * omega^{k+1} = omega^k + A^T t_k; only omega (N x N) is kept and the
+ * synthesis recomputes W omega level by level.  Both compute the same
+ * iteration (they differ by floating-point rounding only); the implicit state
+ * moves about 6x fewer bytes per iteration.  An explicit state can be made from
+ * an implicit one with mlba_framelet_analysis (z = W omega). */
+#define MLBA_STATE_EXPLICIT 0
+#define MLBA_STATE_IMPLICIT 1
 
 typedef struct mlba_plan_s* mlba_plan_t;
 
@@ -158,10 +170,17 @@ int mlba_threshold_synthesis(mlba_plan_t plan, const float* z, const double* mu,
 int mlba_soft_threshold(const float* z, float* x, int bands, size_t band_elems,
                         const double* mu, int n_mu, double delta, hipStream_t stream);
 
+/* f = W^T(delta S_mu(W omega)): the synthesis step of the implicit state, one
+ * launch per level plus levels - 1 low-pass launches.  omega, f: device N x N
+ * (must not alias).  mu: host, n_mu = 1 or bands values. */
+int mlba_shrink_synthesis(mlba_plan_t plan, const float* omega, const double* mu, int n_mu, double delta,
+                          float* f, hipStream_t stream);
+
 /* ---- restoration --------------------------------------------------------
  * Runs params->iters iterations of eq. (MLBA2) from the state z_state
- * (device [bands][N][N], in/out; pass NULL to start from z = 0 in the plan's
- * own state buffer) and writes f_out = W^T(delta_K S_mu(z^K)) (device N x N).
+ * (device, in/out: [bands][N][N] for the explicit state, N x N omega for the
+ * implicit one; pass NULL to start from zero in the plan's own state buffer)
+ * and writes f_out = W^T(delta_K S_mu(z^K)) (device N x N).
  * g: device n x n.  rnorm_out: optional host array receiving ||r^k|| for each
  * iteration run (synchronous copy at the end).  iters_done: optional host
  * int receiving the number of iterations run (smaller than iters only when

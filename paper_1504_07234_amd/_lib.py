@@ -17,6 +17,7 @@ OK, WARN_DIVERGED, EINVAL, EUNSUPPORTED, EHIP, ENOMEM = 0, 1, -1, -2, -3, -4
 BC_RECT, BC_REFLECT, BC_PERIODIC, BC_ZERO = 0, 1, 2, 3
 PRECOND_BCCB, PRECOND_DCT, PRECOND_NONE = 0, 1, 2
 ALPHA_CONST, ALPHA_GEOMETRIC, ALPHA_TABLE = 0, 1, 2
+STATE_EXPLICIT, STATE_IMPLICIT = 0, 1
 
 c_int, c_double, c_size_t, c_void_p = ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
 c_dbl_p = ctypes.POINTER(ctypes.c_double)
@@ -40,7 +41,7 @@ class BatchTuning(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("alpha", AlphaSchedule), ("mu", c_dbl_p), ("n_mu", c_int), ("delta", c_double),
                 ("delta_table", c_dbl_p), ("iters", c_int), ("k0", c_int),
-                ("stop", ctypes.POINTER(Stop))]
+                ("stop", ctypes.POINTER(Stop)), ("state", c_int)]
 
 
 # name -> (restype, argtypes); every symbol declared in include/mlba.h
@@ -61,6 +62,7 @@ SIGNATURES = {
     "mlba_analysis_update": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "mlba_framelet_synthesis": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "mlba_threshold_synthesis": (c_int, [c_void_p, c_void_p, c_dbl_p, c_int, c_double, c_void_p, c_void_p]),
+    "mlba_shrink_synthesis": (c_int, [c_void_p, c_void_p, c_dbl_p, c_int, c_double, c_void_p, c_void_p]),
     "mlba_soft_threshold": (c_int, [c_void_p, c_void_p, c_int, c_size_t, c_dbl_p, c_int, c_double, c_void_p]),
     "mlba_restore": (c_int, [c_void_p, c_void_p, ctypes.POINTER(Params), c_void_p, c_void_p, c_dbl_p, c_int_p,
                              c_void_p]),

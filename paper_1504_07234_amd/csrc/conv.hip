@@ -70,6 +70,8 @@ __device__ __forceinline__ double conv_store(const ConvJob& j, int oy0, int ox0,
                     if (j.g) {
                         v = j.g[(size_t)y * j.D + x] - v;
                         ss += (double)v * (double)v;
+                    } else if (j.acc) {
+                        v = j.dst[(size_t)y * j.D + x] + v;
                     }
                     j.dst[(size_t)y * j.D + x] = v;
                 }
@@ -346,25 +348,25 @@ __device__ __forceinline__ int pad_preimages(int k, int n, int c, int* pre) {
 }
 
 __device__ __forceinline__ void fold_pixel(const float* __restrict__ wext, int m, float* __restrict__ w, int n,
-                                           int c, int y, int x) {
+                                           int c, int y, int x, int accum = 0) {
     int py[3], px[3];
     const int cy = pad_preimages(y, n, c, py);
     const int cx = pad_preimages(x, n, c, px);
     float acc = 0.0f;
     for (int i = 0; i < cy; ++i)
         for (int k = 0; k < cx; ++k) acc += wext[(size_t)py[i] * m + px[k]];
-    w[(size_t)y * n + x] = acc;
+    w[(size_t)y * n + x] = accum ? w[(size_t)y * n + x] + acc : acc;
 }
 
 __global__ __launch_bounds__(kBlock) void fold_reflect_kernel(const float* __restrict__ wext, int m,
-                                                              float* __restrict__ w, int n, int c) {
+                                                              float* __restrict__ w, int n, int c, int accum) {
     const int x = blockIdx.x * kBlock + threadIdx.x;
-    if (x < n) fold_pixel(wext, m, w, n, c, blockIdx.y, x);
+    if (x < n) fold_pixel(wext, m, w, n, c, blockIdx.y, x, accum);
 }
 
-hipError_t launch_fold_reflect(const float* wext, int m, float* w, int n, int c, hipStream_t s) {
+hipError_t launch_fold_reflect(const float* wext, int m, float* w, int n, int c, hipStream_t s, int accum) {
     dim3 grid((n + kBlock - 1) / kBlock, n);
-    hipLaunchKernelGGL(fold_reflect_kernel, grid, dim3(kBlock), 0, s, wext, m, w, n, c);
+    hipLaunchKernelGGL(fold_reflect_kernel, grid, dim3(kBlock), 0, s, wext, m, w, n, c, accum);
     return hipGetLastError();
 }
 

@@ -286,6 +286,183 @@ __global__ __launch_bounds__(kBlock) void synthesis_level_kernel(const float* __
     synthesis_tile<D>(zlev, low, N, out, mu, delta, thr_low, thr_bands, blockIdx.x, blockIdx.y, ys);
 }
 
+// ---- implicit state: z = W omega is never stored -------------------------
+// Every update of eq. (MLBA2) is W applied to A^T t, so z^k = W omega^k with
+// omega^{k+1} = omega^k + A^T t_k (one N x N plane).  u = W^T(delta S_mu(W omega))
+// is evaluated level by level from the low-pass chain low_0 = omega,
+// low_l = (b0 x b0) low_{l-1}: the synthesis of level l recomputes that level's
+// eight bands from low_{l-1} instead of reading them.
+//
+// Extension: with the half-sample symmetric extension of low_{l-1}, a
+// symmetric mask (b0, b2) yields a symmetrically extended band and the
+// antisymmetric b1 an antisymmetrically extended one; the soft threshold is
+// odd, so it keeps both.  Evaluating the bands at extended positions from the
+// extended low-pass therefore gives exactly the signed extension that the
+// synthesis transposes need (the sign flips of synthesis_tile come out of the
+// arithmetic), and no other boundary logic is required.
+
+// low_out = (b0 x b0) v with dilation D: the (0,0) band of analysis_tile
+template <int D>
+__global__ __launch_bounds__(kBlock) void lowpass_level_kernel(const float* __restrict__ v, int N,
+                                                               float* __restrict__ out) {
+    const int x = blockIdx.x * kBlock + threadIdx.x;
+    const int y0 = blockIdx.y * AN_TY;
+    if (x >= N) return;
+    const int rows = min(AN_TY, N - y0);
+    const int xl = reflect_index(x - D, N), xr = reflect_index(x + D, N);
+    float h0[AN_TY + 2 * D];
+#pragma unroll
+    for (int q = 0; q < AN_TY + 2 * D; ++q) {
+        const float* row = v + (size_t)reflect_index(y0 - D + q, N) * N;
+        h0[q] = fmaf(0.25f, row[xl] + row[xr], 0.5f * row[x]);
+    }
+#pragma unroll
+    for (int r = 0; r < AN_TY; ++r) {
+        if (r >= rows) break;
+        out[(size_t)(y0 + r) * N + x] = fmaf(0.25f, h0[r] + h0[r + 2 * D], 0.5f * h0[r + D]);
+    }
+}
+
+// Level with dilation D of W^T(delta S_mu(.)) fed by low = low_{l-1}: the
+// eight bands of the level are computed from low, thresholded and transposed;
+// the (0,0) input is the thresholded low-pass (s_in == null: top level) or
+// s_in, the output of the level above.  Same workgroup geometry as
+// synthesis_tile: one thread per column of an FR_TY-row strip, 256 - 2D
+// output columns per workgroup.
+template <int D>
+__device__ __forceinline__ void shrink_synthesis_tile(const float* __restrict__ low, const float* __restrict__ s_in,
+                                                      int N, float* __restrict__ out, const LevelMu& mu,
+                                                      float delta, int bx, int by,
+                                                      float (*ys)[FR_TY][kBlock]) {
+    constexpr int IW = kBlock - 2 * D;
+    constexpr int HR = FR_TY + 4 * D;  // rows of x-filtered low: y0-2D .. y0+FR_TY+2D-1
+    constexpr int BR = FR_TY + 2 * D;  // rows of bands: y0-D .. y0+FR_TY+D-1
+    const int x0 = bx * IW;
+    const int y0 = by * FR_TY;
+    const int c = threadIdx.x;
+    const int xe = x0 - D + c;  // extended column of this thread
+    const int xm = reflect_index(xe, N), xl = reflect_index(xe - D, N), xr = reflect_index(xe + D, N);
+
+    int rowo[HR];  // row offsets of the x-filtered rows (reflected)
+#pragma unroll
+    for (int q = 0; q < HR; ++q) rowo[q] = reflect_index(y0 - 2 * D + q, N) * N;
+    float sc[BR];
+    if (s_in) {
+#pragma unroll
+        for (int q = 0; q < BR; ++q) sc[q] = s_in[(size_t)reflect_index(y0 - D + q, N) * N + xm];
+    }
+
+    float acc[3][FR_TY];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int r = 0; r < FR_TY; ++r) acc[i][r] = 0.0f;
+
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        // x-filter h_i of low at this column (re-read per i from cache)
+        float hh[HR];
+#pragma unroll
+        for (int q = 0; q < HR; ++q) {
+            const float* row = low + rowo[q];
+            const float a = row[xl], b = row[xm], e = row[xr];
+            if (i == 0) hh[q] = fmaf(0.25f, a + e, 0.5f * b);
+            else if (i == 1) hh[q] = kB1 * (e - a);
+            else hh[q] = fmaf(-0.25f, a + e, 0.5f * b);
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const bool is_low = (i == 0 && j == 0);
+            const float m = is_low ? mu.low : mu.band[pair_slot(i, j)];
+            float col[BR];
+#pragma unroll
+            for (int q = 0; q < BR; ++q) {
+                const float a = hh[q], b = hh[q + D], e = hh[q + 2 * D];
+                float v;
+                if (j == 0) v = fmaf(0.25f, a + e, 0.5f * b);
+                else if (j == 1) v = kB1 * (e - a);
+                else v = fmaf(-0.25f, a + e, 0.5f * b);
+                col[q] = (is_low && s_in) ? sc[q] : shrink(v, m, delta);
+            }
+#pragma unroll
+            for (int r = 0; r < FR_TY; ++r) {
+                const float wm = col[r], w0 = col[r + D], wp = col[r + 2 * D];  // y-d, y, y+d
+                if (j == 0) acc[i][r] += fmaf(0.25f, wp + wm, 0.5f * w0);
+                else if (j == 1) acc[i][r] = fmaf(kB1, wm - wp, acc[i][r]);
+                else acc[i][r] += fmaf(-0.25f, wp + wm, 0.5f * w0);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int r = 0; r < FR_TY; ++r) ys[i][r][c] = acc[i][r];
+    __syncthreads();
+
+    if (c < D || c >= kBlock - D) return;
+    const int x = x0 + c - D;
+    if (x >= N) return;
+    for (int r = 0; r < FR_TY; ++r) {
+        const int y = y0 + r;
+        if (y >= N) break;
+        float sum = 0.0f;
+        {
+            const float l = ys[0][r][c - D], mm = ys[0][r][c], rr = ys[0][r][c + D];
+            sum += fmaf(0.25f, rr + l, 0.5f * mm);
+        }
+        {
+            const float l = ys[1][r][c - D], rr = ys[1][r][c + D];
+            sum = fmaf(kB1, l - rr, sum);
+        }
+        {
+            const float l = ys[2][r][c - D], mm = ys[2][r][c], rr = ys[2][r][c + D];
+            sum += fmaf(-0.25f, rr + l, 0.5f * mm);
+        }
+        out[(size_t)y * N + x] = sum;
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void shrink_synthesis_kernel(const float* __restrict__ low,
+                                                                  const float* __restrict__ s_in, int N,
+                                                                  float* __restrict__ out, LevelMu mu,
+                                                                  float delta) {
+    __shared__ float ys[3][FR_TY][kBlock];
+    shrink_synthesis_tile<D>(low, s_in, N, out, mu, delta, blockIdx.x, blockIdx.y, ys);
+}
+
+hipError_t launch_lowpass_level(const float* v, int N, int d, float* out, hipStream_t s) {
+    dim3 grid((N + kBlock - 1) / kBlock, (N + AN_TY - 1) / AN_TY);
+    switch (d) {
+        case 1: hipLaunchKernelGGL(lowpass_level_kernel<1>, grid, dim3(kBlock), 0, s, v, N, out); break;
+        case 2: hipLaunchKernelGGL(lowpass_level_kernel<2>, grid, dim3(kBlock), 0, s, v, N, out); break;
+        case 4: hipLaunchKernelGGL(lowpass_level_kernel<4>, grid, dim3(kBlock), 0, s, v, N, out); break;
+        case 8: hipLaunchKernelGGL(lowpass_level_kernel<8>, grid, dim3(kBlock), 0, s, v, N, out); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int D>
+static hipError_t launch_ss(const float* low, const float* s_in, int N, float* out, LevelMu mu, float delta,
+                            hipStream_t s) {
+    constexpr int IW = kBlock - 2 * D;
+    dim3 grid((N + IW - 1) / IW, (N + FR_TY - 1) / FR_TY);
+    hipLaunchKernelGGL((shrink_synthesis_kernel<D>), grid, dim3(kBlock), 0, s, low, s_in, N, out, mu, delta);
+    return hipGetLastError();
+}
+
+hipError_t launch_shrink_synthesis_level(const float* low, const float* s_in, int N, int d, float* out,
+                                         LevelMu mu, float delta, hipStream_t s) {
+    switch (d) {
+        case 1: return launch_ss<1>(low, s_in, N, out, mu, delta, s);
+        case 2: return launch_ss<2>(low, s_in, N, out, mu, delta, s);
+        case 4: return launch_ss<4>(low, s_in, N, out, mu, delta, s);
+        case 8: return launch_ss<8>(low, s_in, N, out, mu, delta, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <int D>
 static hipError_t launch_an(const float* v, int N, float* zlev, float* low, int ab, int al, hipStream_t s) {
     dim3 grid((N + kBlock - 1) / kBlock, (N + AN_TY - 1) / AN_TY);

@@ -28,8 +28,8 @@ struct BandMu {
     float v[64];
 };
 
-// One blur: dst[y][x] = (g ? g[y][x] - s : s) over D x D outputs,
-// s = sum_{a,b} K[a][b] src_ext[y+org+a][x+org+b] (src S x S, extension ext).
+// One blur: dst[y][x] = (g ? g[y][x] - s : (acc ? dst[y][x] + s : s)) over D x D
+// outputs, s = sum_{a,b} K[a][b] src_ext[y+org+a][x+org+b] (src S x S, extension ext).
 struct ConvJob {
     const float* src;
     int S, ext, org;
@@ -37,6 +37,7 @@ struct ConvJob {
     int D;
     const float* g;
     const float* psf;
+    int acc;
 };
 
 // Per-image descriptor of a batch (device memory): sizes, model, parameters
@@ -91,6 +92,7 @@ __host__ __device__ inline ConvJob blur_job(const BatchImage& I) {
     j.D = I.n;
     j.g = I.g;
     j.psf = I.psf;
+    j.acc = 0;
     return j;
 }
 
@@ -102,6 +104,7 @@ __host__ __device__ inline ConvJob blurT_job(const BatchImage& I) {
     j.S = I.n;
     j.g = nullptr;
     j.psf = I.psf;
+    j.acc = 0;
     if (I.bc == 0 || I.bc == 1) {
         j.ext = EXT_ZERO;
         j.org = -(I.p - 1);
@@ -140,7 +143,7 @@ hipError_t launch_fold_batched(const BatchImage* imgs, const int* bmap, const in
 
 // Transpose of the reflective padding: w[y][x] = sum of wext over the
 // positions of the (n+2c)^2 padded grid that copy pixel (y, x).
-hipError_t launch_fold_reflect(const float* wext, int m, float* w, int n, int c, hipStream_t s);
+hipError_t launch_fold_reflect(const float* wext, int m, float* w, int n, int c, hipStream_t s, int accum = 0);
 
 // ---- framelet -----------------------------------------------------------
 // analysis level with dilation d: bands (+)= B_i B_j v, low (+)= B_0 B_0 v
@@ -152,6 +155,12 @@ hipError_t launch_synthesis_level(const float* zlev, const float* low, int N, in
                                   hipStream_t s);
 hipError_t launch_soft_threshold(const float* z, float* x, int bands, size_t band_elems,
                                  BandMu mu, float delta, hipStream_t s);
+// implicit state (z = W omega): low-pass of one level, out = (b0 x b0) v
+hipError_t launch_lowpass_level(const float* v, int N, int d, float* out, hipStream_t s);
+// one level of W^T(delta S_mu(W omega)) from low = low_{l-1}; s_in = output of
+// the level above, or null at the top level (thresholded low-pass)
+hipError_t launch_shrink_synthesis_level(const float* low, const float* s_in, int N, int d, float* out,
+                                         LevelMu mu, float delta, hipStream_t s);
 // batched framelet levels (all images share `levels`); tiles per image:
 int synthesis_level_tiles(int N, int d);
 int analysis_level_tiles(int N, int d);

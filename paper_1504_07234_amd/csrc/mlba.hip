@@ -169,6 +169,36 @@ int do_synthesis(mlba_plan_s* P, const float* z, float* f, bool thr, const float
     return MLBA_OK;
 }
 
+// f = W^T (delta S_mu(W omega)) (implicit state): low-pass chain, then one
+// shrink-synthesis launch per level from the top
+int do_shrink_synthesis(mlba_plan_s* P, const float* omega, float* f, const float* mub, float delta,
+                        hipStream_t s) {
+    const float* low[4] = {omega, P->lows[0], P->lows[1], P->lows[2]};
+    for (int l = 1; l < P->levels; ++l)
+        HIPCHK(launch_lowpass_level(low[l - 1], P->N, 1 << (l - 1), P->lows[l - 1], s));
+    const float* s_in = nullptr;
+    for (int lev = P->levels; lev >= 1; --lev) {
+        float* out = lev == 1 ? f : P->tmp[lev & 1];
+        HIPCHK(launch_shrink_synthesis_level(low[lev - 1], s_in, P->N, 1 << (lev - 1), out, level_mu(mub, lev),
+                                             delta, s));
+        s_in = out;
+    }
+    return MLBA_OK;
+}
+
+// omega += A^T y (implicit state: the Bregman update of eq. (MLBA2) before W)
+int do_blurT_acc(mlba_plan_s* P, const float* y, float* omega, hipStream_t s) {
+    BatchImage d = plan_desc(P);
+    d.t = const_cast<float*>(y);
+    d.w = omega;
+    ConvJob j = blurT_job(d);
+    const bool fold = P->bc == MLBA_BC_REFLECT;
+    j.acc = fold ? 0 : 1;
+    HIPCHK(launch_conv_job(j, P->p, 0, P->conv_rows[1], nullptr, nullptr, s));
+    if (fold) HIPCHK(launch_fold_reflect(P->wext, P->n + P->p - 1, omega, P->n, P->c, s, 1));
+    return MLBA_OK;
+}
+
 int expand_mu(const mlba_plan_s* P, const double* mu, int n_mu, float* out) {
     if (!mu || (n_mu != 1 && n_mu != P->bands)) return MLBA_EINVAL;
     for (int b = 0; b < P->bands; ++b) {
@@ -295,6 +325,8 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
     ALLOC(P->tmp[1], nn);
     ALLOC(P->pv, nn);
     ALLOC(P->z, nn * P->bands);
+    ALLOC(P->omega, nn);
+    for (int l = 0; l < levels - 1; ++l) ALLOC(P->lows[l], nn);
     ALLOC(P->partials, (size_t)P->partials_cap);
     ALLOC(P->scal, 8);
     ALLOC(P->rn, (size_t)P->rn_cap);
@@ -431,6 +463,14 @@ int mlba_threshold_synthesis(mlba_plan_t P, const float* z, const double* mu, in
     return do_synthesis(P, z, f, true, mub, (float)delta, s);
 }
 
+int mlba_shrink_synthesis(mlba_plan_t P, const float* omega, const double* mu, int n_mu, double delta, float* f,
+                          hipStream_t s) {
+    if (!P || !omega || !f || omega == f || !isfinite(delta)) return MLBA_EINVAL;
+    float mub[64];
+    STCHK(expand_mu(P, mu, n_mu, mub));
+    return do_shrink_synthesis(P, omega, f, mub, (float)delta, s);
+}
+
 int mlba_soft_threshold(const float* z, float* x, int bands, size_t band_elems, const double* mu, int n_mu,
                         double delta, hipStream_t s) {
     if (!z || !x || !mu || bands < 1 || bands > 64 || (n_mu != 1 && n_mu != bands) || !isfinite(delta))
@@ -456,6 +496,8 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
     if (as.kind == MLBA_ALPHA_GEOMETRIC && !(as.ratio > 0.0)) return MLBA_EINVAL;
     const mlba_stop* stop = prm->stop;
     if (stop && (stop->check_every < 1 || !(stop->noise_norm >= 0.0))) return MLBA_EINVAL;
+    if (prm->state != MLBA_STATE_EXPLICIT && prm->state != MLBA_STATE_IMPLICIT) return MLBA_EINVAL;
+    const bool implicit = prm->state == MLBA_STATE_IMPLICIT;
     float mub[64];
     STCHK(expand_mu(P, prm->mu, prm->n_mu, mub));
 
@@ -487,8 +529,8 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
         if (!isfinite(delta[i])) return MLBA_EINVAL;
 
     const size_t nn = NN(P);
-    float* z = z_state ? z_state : P->z;
-    if (!z_state) HIPCHK(launch_fill(z, nn * P->bands, 0.0f, s));
+    float* z = z_state ? z_state : (implicit ? P->omega : P->z);
+    if (!z_state) HIPCHK(launch_fill(z, implicit ? nn : nn * P->bands, 0.0f, s));
 
     const bool track = rnorm_out || iters_done || stop;
     std::vector<double> rn_host;
@@ -508,7 +550,8 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
     };
 
     const int launches[MLBA_NPHASES] = {
-        P->levels, 2, P->precond == MLBA_PRECOND_NONE ? 1 : 3, P->bc == MLBA_BC_REFLECT ? 2 : 1, P->levels};
+        implicit ? 2 * P->levels - 1 : P->levels, 2, P->precond == MLBA_PRECOND_NONE ? 1 : 3,
+        P->bc == MLBA_BC_REFLECT ? 2 : 1, implicit ? 0 : P->levels};
     for (int i = 0; i < iters; ++i) {
         if (i - ring_base >= P->rn_cap) {
             if (track) STCHK(drain(i));
@@ -521,7 +564,8 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
             for (int q = 0; q < MLBA_NPHASES; ++q) P->prof_launch[q] += launches[q];
         }
         if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_SYNTHESIS], s));
-        STCHK(do_synthesis(P, z, P->u, true, mub, (float)delta[i], s));
+        if (implicit) STCHK(do_shrink_synthesis(P, z, P->u, mub, (float)delta[i], s));
+        else STCHK(do_synthesis(P, z, P->u, true, mub, (float)delta[i], s));
         int np = 0;
         if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_BLUR], s));
         STCHK(do_blur(P, P->u, g, P->r, true, &np, s));
@@ -539,13 +583,21 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
         if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_PRECOND], s));
         STCHK(do_precond(P, P->r, P->t, alpha[i], s));
         if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_BLUR_T], s));
-        STCHK(do_blurT(P, P->t, P->w, s));
-        if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_ANALYSIS], s));
-        STCHK(do_analysis(P, P->w, z, true, s));
+        if (implicit) {
+            STCHK(do_blurT_acc(P, P->t, z, s));
+            if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_ANALYSIS], s));
+        } else {
+            STCHK(do_blurT(P, P->t, P->w, s));
+            if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_ANALYSIS], s));
+            STCHK(do_analysis(P, P->w, z, true, s));
+        }
         if (ev) HIPCHK(hipEventRecord(ev[MLBA_NPHASES], s));
         done = i + 1;
     }
-    if (!stopped) STCHK(do_synthesis(P, z, f_out, true, mub, (float)delta[done], s));
+    if (!stopped) {
+        if (implicit) STCHK(do_shrink_synthesis(P, z, f_out, mub, (float)delta[done], s));
+        else STCHK(do_synthesis(P, z, f_out, true, mub, (float)delta[done], s));
+    }
 
     int status = MLBA_OK;
     if (track) {

@@ -43,6 +43,8 @@ struct mlba_plan_s {
     float* tmp[2] = {nullptr, nullptr};  // N x N level intermediates
     float* pv = nullptr;       // N x N power-iteration vector
     float* z = nullptr;        // [bands][N][N] state when the caller passes none
+    float* omega = nullptr;    // N x N implicit state (z = W omega) when the caller passes none
+    float* lows[3] = {nullptr, nullptr, nullptr};  // low-pass chain low_1 .. low_{levels-1} (N x N)
     double* partials = nullptr;
     int partials_cap = 0;
     double* scal = nullptr;    // device scalars

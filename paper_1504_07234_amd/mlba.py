@@ -152,6 +152,16 @@ class Plan:
         return out
 
     # -- phase timing --------------------------------------------------------
+    def shrink_synthesis(self, omega, mu, delta: float, out=None, stream=None):
+        """f = W^T(delta S_mu(W omega)) (the implicit state's synthesis)."""
+        out = self._new(self.N, self.N) if out is None else out
+        mus = [mu] if isinstance(mu, (int, float)) else list(mu)
+        arr, ptr = _dbl_array(mus)
+        check(self._lib.mlba_shrink_synthesis(self._h, _dev(omega, "omega", (self.N, self.N)), ptr, len(mus),
+                                              float(delta), _dev(out, "out", (self.N, self.N)), _stream(stream)),
+              "mlba_shrink_synthesis")
+        return out
+
     def profile_begin(self, max_iters: int):
         check(self._lib.mlba_profile_begin(self._h, int(max_iters)), "mlba_profile_begin")
 
@@ -166,10 +176,14 @@ class Plan:
     # -- restoration -------------------------------------------------------
     def restore(self, g, *, alpha=0.05, alpha_kind: int = _lib.ALPHA_CONST, alpha_ratio: float = 1.0,
                 alpha_floor: float = 0.0, alpha_table=None, mu=1e-3, delta: float = 0.0, delta_table=None,
-                iters: int = 50, k0: int = 0, z=None, out=None, stop=None, track: bool = True, stream=None):
+                iters: int = 50, k0: int = 0, z=None, out=None, stop=None, track: bool = True,
+                implicit: bool = False, stream=None):
         """Run `iters` iterations of eq. (MLBA2); returns (f, RestoreInfo).
 
-        z: optional state tensor [bands, N, N] (in/out, resume with k0).
+        implicit: keep the state as omega (z = W omega, one N x N plane) instead
+        of the frame coefficients z.
+        z: optional state tensor, [bands, N, N] or [N, N] when implicit (in/out,
+        resume with k0).
         stop: optional (noise_norm, gamma, check_every) discrepancy stop.
         track: read back the residual norms (synchronises at the end)."""
         out = self._new(self.N, self.N) if out is None else out
@@ -203,7 +217,9 @@ class Plan:
             st = _lib.Stop(float(stop[0]), float(stop[1]), int(stop[2]))
             keep.append(st)
             prm.stop = ctypes.pointer(st)
-        zp = ctypes.c_void_p() if z is None else _dev(z, "z", (self.bands, self.N, self.N))
+        prm.state = _lib.STATE_IMPLICIT if implicit else _lib.STATE_EXPLICIT
+        zshape = (self.N, self.N) if implicit else (self.bands, self.N, self.N)
+        zp = ctypes.c_void_p() if z is None else _dev(z, "z", zshape)
         rn = (ctypes.c_double * max(1, iters))() if track else None
         done = ctypes.c_int(iters)
         status = self._lib.mlba_restore(self._h, _dev(g, "g", (self.n, self.n)), ctypes.byref(prm),
