@@ -35,6 +35,35 @@ METRIC = "MLBA Mpixel-iter/s at 2048² FP32 (% HBM roofline); batched vs plain; 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, non-packed FP32
 
+# HBM traffic of the dominant kernel per launch, from two rocprofv3 --pmc passes
+# (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) over `python bench.py
+# --traffic-probe`, each scaled by what the counter reads for a plain 256 MiB
+# copy on the same run (FETCH_SIZE 131,084 KiB -> x2.000, WRITE_SIZE
+# 262,144 KiB -> x1.000).  The figure belongs to the kernel sources it was
+# taken with: when their hash differs it is reported as null.
+TRAFFIC = {
+    ("blur_t", "implicit"): {"fetch_kib": 32405.1, "write_kib": 18425.5, "fetch_scale": 2.0, "write_scale": 1.0,
+                             "sources_sha256": "e3c4154046c17a4c04bf4e23f9f6db2bba583e11da333d7ee67982946b8e3e09"},
+}
+TRAFFIC_SOURCES = ("paper_1504_07234_amd/csrc/conv.hip", "paper_1504_07234_amd/csrc/common.hpp",
+                   "paper_1504_07234_amd/csrc/kernels.hpp")
+
+
+def measured_traffic(phase: str, state: str):
+    """Bytes per launch from the recorded counter passes, or None when none
+    were taken for this kernel or its sources changed since."""
+    import hashlib
+    rec = TRAFFIC.get((phase, state))
+    if rec is None:
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])
+
 
 def phase_model(n, p, N, B, L, implicit):
     """Algorithmic bytes and flops of each phase of one iteration (float32).
@@ -225,6 +254,10 @@ def main() -> int:
                     help="iteration state: omega (z = W omega recomputed) or the frame coefficients z")
     ap.add_argument("--compare-steps", type=int, default=20,
                     help="iterations timed with the other state, for comparison (0: skip)")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run only two 256 MiB device copies x3 (counter calibration: the runtime copy and "
+                         "a one-float-per-lane copy) and 3 iterations of the workload, for rocprofv3 --pmc "
+                         "FETCH_SIZE / WRITE_SIZE passes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -279,6 +312,19 @@ def main() -> int:
         return el, ph
 
     implicit = args.state == "implicit"
+    if args.traffic_probe:
+        src = torch.rand(64 << 20, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)  # runtime copy (wide requests)
+        for _ in range(3):
+            mlba.soft_threshold(src, 0.0, 1.0, out=dst)  # one float per lane: x = S_0(z) = z
+        torch.cuda.synchronize()
+        st = torch.zeros((N, N) if implicit else (B, N, N), dtype=torch.float32, device="cuda")
+        plan.restore(g, alpha=w.alpha0, mu=w.mu, delta=delta, iters=3, z=st, out=f, track=False, implicit=implicit)
+        torch.cuda.synchronize()
+        print("traffic probe done", flush=True)
+        return 0
     # ---- warmup, then the timed region: K iterations, phase events on the library stream --
     elapsed, (phases, rec) = run(implicit, args.steps, args.warmup, True)
     compare = None
@@ -311,13 +357,14 @@ def main() -> int:
         if model[ph]["flops"] > 0:
             ach = model[ph]["flops"] / nl / (launch_ms * 1e-3) / 1e12
             r = {"bound": "alu", "achieved": round(ach, 2), "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                 "frac": round(ach / FP32_VALU_PEAK_TFLOPS, 4), "traffic": None}
+                 "frac": round(ach / FP32_VALU_PEAK_TFLOPS, 4), "traffic": measured_traffic(ph, args.state)}
         else:
             ach = model[ph]["bytes"] / nl / (launch_ms * 1e-3) / 1e9
             r = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(ph, args.state)}
         r["kernel_phase"] = ph
         r["launch_ms"] = round(launch_ms, 4)
+        r["algorithmic_bytes"] = round(model[ph]["bytes"] / nl)
         return r
 
     # dominant kernel: the longest single launch of an iteration
