@@ -72,6 +72,13 @@ extern "C" {
 #define MLBA_ALPHA_CONST      0  /* alpha_k = alpha0                              */
 #define MLBA_ALPHA_GEOMETRIC  1  /* alpha_k = max(alpha0 * ratio^k, alpha_floor)  */
 #define MLBA_ALPHA_TABLE      2  /* alpha_k = table[k] (host, >= k0+iters values) */
+#define MLBA_ALPHA_NS         3  /* Algorithm 4-NS (MLBA_METHOD_ALG4, BCCB only): alpha_n solves
+                                    alpha_n ||(C C^T + alpha_n I)^{-1} r^n|| = q_n ||r^n||,
+                                    q_n = max{ns_q, 2 ns_rho + (1 + ns_rho) / tau_n},
+                                    tau_n = ||r^n|| / noise (eq. Alg4_rev_7); the run stops at
+                                    the first n with ||r^n|| <= tau noise, tau = (1 + 2 ns_rho) /
+                                    (1 - 2 ns_rho) (eq. Alg4_rev_12); noise = stop->noise_norm
+                                    (required); alpha0 is the first Newton start */
 
 typedef struct mlba_alpha_schedule {
     int kind;
@@ -80,7 +87,17 @@ typedef struct mlba_alpha_schedule {
     double alpha_floor;
     const double* table;  /* host; used when kind == MLBA_ALPHA_TABLE */
     int table_len;
+    double ns_q;          /* MLBA_ALPHA_NS: q in (2 rho, 1) (the paper's runs: 0.5)  */
+    double ns_rho;        /* MLBA_ALPHA_NS: rho in (0, 1/2) (the paper's runs: 1e-4) */
 } mlba_alpha_schedule;
+
+/* Update direction (section 5).  MLBA: eq. (MLBA2), z += W A^T P_alpha r with
+ * the preconditioner of the plan.  ALG4: eq. (Alg4), z += W C^T (C C^T +
+ * alpha I)^{-1} r, C the periodic (BCCB plan) or reflective-of-the-symmetrised-
+ * PSF (DCT plan) blur: no A^T product; square boundary models only (plans
+ * with MLBA_BC_RECT return MLBA_EUNSUPPORTED), preconditioner BCCB or DCT. */
+#define MLBA_METHOD_MLBA 0
+#define MLBA_METHOD_ALG4 1
 
 /* Discrepancy-principle stop, eq. (discrpr): stop at the first k with
  * ||r^k|| <= gamma * noise_norm.  Checked every `check_every` iterations
@@ -107,6 +124,9 @@ typedef struct mlba_params {
     int k0;                    /* global index of the first iteration (resume) */
     const mlba_stop* stop;     /* optional discrepancy stop (NULL: fixed iters) */
     int state;                 /* MLBA_STATE_EXPLICIT or MLBA_STATE_IMPLICIT    */
+    int method;                /* MLBA_METHOD_MLBA or MLBA_METHOD_ALG4          */
+    double* alpha_out;         /* host, optional: the alpha_k of each iteration run
+                                  (iters values; synchronous copy at the end)   */
 } mlba_params;
 
 /* State kept between iterations.  Explicit: the frame coefficients z
@@ -155,6 +175,11 @@ int mlba_residual(mlba_plan_t plan, const float* g, const float* u, float* r, hi
 int mlba_apply_At(mlba_plan_t plan, const float* y, float* w, hipStream_t stream);
 /* t = P_alpha r.  r, t: device n x n, may alias (section 4, Algorithms 1 / 3). */
 int mlba_apply_P(mlba_plan_t plan, const float* r, float* t, double alpha, hipStream_t stream);
+/* t = C^T (C C^T + alpha I)^{-1} r: the direction of eq. (Alg4) before W, with
+ * C the periodic-boundary blur of the PSF (BCCB plan) or the reflective blur of
+ * the symmetrised PSF (DCT plan).  r, t: device n x n, must not alias.  Square
+ * models only (MLBA_EUNSUPPORTED for MLBA_BC_RECT or MLBA_PRECOND_NONE). */
+int mlba_apply_CtP(mlba_plan_t plan, const float* r, float* t, double alpha, hipStream_t stream);
 /* z = W f.  f: device N x N, z: device [bands][N][N] (section 6.1). */
 int mlba_framelet_analysis(mlba_plan_t plan, const float* f, float* z, hipStream_t stream);
 /* z += W w: the Bregman update of eq. (MLBA2).  w: device N x N. */

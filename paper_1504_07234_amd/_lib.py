@@ -16,7 +16,8 @@ OK, WARN_DIVERGED, EINVAL, EUNSUPPORTED, EHIP, ENOMEM = 0, 1, -1, -2, -3, -4
 # boundary models / preconditioners / schedules
 BC_RECT, BC_REFLECT, BC_PERIODIC, BC_ZERO = 0, 1, 2, 3
 PRECOND_BCCB, PRECOND_DCT, PRECOND_NONE = 0, 1, 2
-ALPHA_CONST, ALPHA_GEOMETRIC, ALPHA_TABLE = 0, 1, 2
+ALPHA_CONST, ALPHA_GEOMETRIC, ALPHA_TABLE, ALPHA_NS = 0, 1, 2, 3
+METHOD_MLBA, METHOD_ALG4 = 0, 1
 STATE_EXPLICIT, STATE_IMPLICIT = 0, 1
 
 c_int, c_double, c_size_t, c_void_p = ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
@@ -26,7 +27,7 @@ c_int_p = ctypes.POINTER(ctypes.c_int)
 
 class AlphaSchedule(ctypes.Structure):
     _fields_ = [("kind", c_int), ("alpha0", c_double), ("ratio", c_double), ("alpha_floor", c_double),
-                ("table", c_dbl_p), ("table_len", c_int)]
+                ("table", c_dbl_p), ("table_len", c_int), ("ns_q", c_double), ("ns_rho", c_double)]
 
 
 class Stop(ctypes.Structure):
@@ -41,7 +42,7 @@ class BatchTuning(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("alpha", AlphaSchedule), ("mu", c_dbl_p), ("n_mu", c_int), ("delta", c_double),
                 ("delta_table", c_dbl_p), ("iters", c_int), ("k0", c_int),
-                ("stop", ctypes.POINTER(Stop)), ("state", c_int)]
+                ("stop", ctypes.POINTER(Stop)), ("state", c_int), ("method", c_int), ("alpha_out", c_dbl_p)]
 
 
 # name -> (restype, argtypes); every symbol declared in include/mlba.h
@@ -58,6 +59,7 @@ SIGNATURES = {
     "mlba_residual": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "mlba_apply_At": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "mlba_apply_P": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_void_p]),
+    "mlba_apply_CtP": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_void_p]),
     "mlba_framelet_analysis": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "mlba_analysis_update": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "mlba_framelet_synthesis": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),

@@ -200,9 +200,14 @@ __device__ __forceinline__ void fft_rows_r2c_body(const float* __restrict__ src,
     }
 }
 
-// CC rows of T per workgroup: forward FFT along the column index, then either
-// the filter inv / (spec + alpha) and the inverse FFT (mode 0), or |.|^2 into
-// `power` (mode 1).
+// CC rows of T per workgroup, along the column index:
+//   mode 0: forward FFT, filter inv / (spec + alpha) (times conj(lamc) when
+//           lamc is given: C^T (C C^T + alpha I)^{-1} of Algorithm 4), inverse FFT;
+//   mode 1: forward FFT, |.|^2 into `power`;
+//   mode 2: forward FFT, the complex values into `cspec`;
+//   mode 3: forward FFT only, written back to T;
+//   mode 4: filter of mode 0 on the spectrum already in T, inverse FFT.
+// alpha_dev (optional) replaces alpha by a value computed on the device.
 __device__ __forceinline__ void fft_cols_body(float2* __restrict__ T, int n, int ts,
                                                           const float* __restrict__ spec, float alpha,
                                                           float inv, const FftDesc& fd,
@@ -210,7 +215,10 @@ __device__ __forceinline__ void fft_cols_body(float2* __restrict__ T, int n, int
                                                           float* __restrict__ power, int seq_shift, int blk, float2* buf,
                                                           float2* __restrict__ sstore = nullptr,
                                                           const float2* __restrict__ sfwd = nullptr,
-                                                          float* __restrict__ eacc = nullptr) {
+                                                          float* __restrict__ eacc = nullptr,
+                                                          const float2* __restrict__ lamc = nullptr,
+                                                          const double* __restrict__ alpha_dev = nullptr,
+                                                          float2* __restrict__ cspec = nullptr) {
     const int half = n / 2 + 1;
     const int k0 = blk * CC;
     const int cc = min(CC, half - k0);
@@ -220,7 +228,7 @@ __device__ __forceinline__ void fft_cols_body(float2* __restrict__ T, int n, int
         buf[lds_slot(idx)] = T[(size_t)(k0 + q) * ts + (idx - q * n)];
     }
     __syncthreads();
-    lds_fft<-1>(buf, fd, cc, seq_shift, tw);
+    if (mode != 4) lds_fft<-1>(buf, fd, cc, seq_shift, tw);
     if (mode == 1) {
         for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
             const float2 v = buf[lds_slot(idx)];
@@ -228,8 +236,23 @@ __device__ __forceinline__ void fft_cols_body(float2* __restrict__ T, int n, int
         }
         return;
     }
-    for (int idx = threadIdx.x; idx < cc * n; idx += kBlock)
-        buf[lds_slot(idx)] = cscale(buf[lds_slot(idx)], inv / (spec[base + idx] + alpha));
+    if (mode == 2) {
+        for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) cspec[base + idx] = buf[lds_slot(idx)];
+        return;
+    }
+    if (mode == 3) {
+        for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
+            const int q = idx / n;
+            T[(size_t)(k0 + q) * ts + (idx - q * n)] = buf[lds_slot(idx)];
+        }
+        return;
+    }
+    if (alpha_dev) alpha = (float)*alpha_dev;
+    for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
+        float2 v = cscale(buf[lds_slot(idx)], inv / (spec[base + idx] + alpha));
+        if (lamc) v = cmul(v, cconj(lamc[base + idx]));
+        buf[lds_slot(idx)] = v;
+    }
     if (sstore || eacc) {  // reverse sweep of unrolled iterations (same thread owns each slot)
         for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
             const float2 v = buf[lds_slot(idx)];
@@ -269,7 +292,8 @@ __device__ __forceinline__ void fft_cols_inverse_real_body(const float* __restri
 
 __device__ __forceinline__ void fft_rows_c2r_body(const float2* __restrict__ T, int n, int ts,
                                                               float* __restrict__ dst, const FftDesc& fd,
-                                                              const float2* __restrict__ tw, int G, int seq_shift, int blk, float2* buf) {
+                                                              const float2* __restrict__ tw, int G, int seq_shift, int blk, float2* buf,
+                                                              int accum = 0) {
     const int row0 = blk * 2 * G;
     const int half = n / 2 + 1;
     for (int idx = threadIdx.x; idx < G * half; idx += kBlock) {
@@ -292,8 +316,13 @@ __device__ __forceinline__ void fft_rows_c2r_body(const float2* __restrict__ T, 
         const int x = idx - g * n;
         const size_t ra = (size_t)(row0 + 2 * g) * n;
         const float2 v = buf[lds_slot(idx)];
-        dst[ra + x] = v.x;
-        dst[ra + n + x] = v.y;
+        if (accum) {
+            dst[ra + x] += v.x;
+            dst[ra + n + x] += v.y;
+        } else {
+            dst[ra + x] = v.x;
+            dst[ra + n + x] = v.y;
+        }
     }
 }
 
@@ -339,7 +368,8 @@ __device__ __forceinline__ void dct_cols_filter_body(float* __restrict__ Tr, int
                                                                  const float* __restrict__ spec, float alpha,
                                                                  float inv, const FftDesc& fd,
                                                                  const float2* __restrict__ tw,
-                                                                 const float2* __restrict__ dtw, int CP, int seq_shift, int blk, float2* buf) {
+                                                                 const float2* __restrict__ dtw, int CP, int seq_shift, int blk, float2* buf,
+                                                                 const float* __restrict__ lamr = nullptr) {
     const int pairs = n / 2;
     const int p0 = blk * CP;
     const int cp = min(CP, pairs - p0);
@@ -367,8 +397,12 @@ __device__ __forceinline__ void dct_cols_filter_body(float* __restrict__ Tr, int
             const float2 V2 = make_float2(0.5f * D.y, -0.5f * D.x);
             const float2 w = dtw[l];
             const size_t s1 = (size_t)(2 * (p0 + q)) * n;  // dense [n][n] spectrum
-            const float f1 = inv / (spec[s1 + l] + alpha);
-            const float f2 = inv / (spec[s1 + n + l] + alpha);
+            float f1 = inv / (spec[s1 + l] + alpha);
+            float f2 = inv / (spec[s1 + n + l] + alpha);
+            if (lamr) {  // C^T (C C^T + alpha I)^{-1} of Algorithm 4
+                f1 *= lamr[s1 + l];
+                f2 *= lamr[s1 + n + l];
+            }
             keep[i] = make_float2(re_mul(w, V1) * f1, re_mul(w, V2) * f2);
         }
     }
@@ -414,7 +448,8 @@ __device__ __forceinline__ void dct_cols_filter_body(float* __restrict__ Tr, int
 __device__ __forceinline__ void dct_rows_inv_body(const float* __restrict__ Tr, int n, int ts,
                                                               float* __restrict__ dst, const FftDesc& fd,
                                                               const float2* __restrict__ tw,
-                                                              const float2* __restrict__ dtw, int G, int seq_shift, int blk, float2* buf) {
+                                                              const float2* __restrict__ dtw, int G, int seq_shift, int blk, float2* buf,
+                                                              int accum = 0) {
     const int row0 = blk * 2 * G;
     const int total = G * n;
     for (int idx = threadIdx.x; idx < total; idx += kBlock) {
@@ -451,8 +486,13 @@ __device__ __forceinline__ void dct_rows_inv_body(const float* __restrict__ Tr, 
         const int x = idx - g * n;
         const size_t ra = (size_t)(row0 + 2 * g) * n;
         const float2 v = buf[lds_slot(g * n + dct_perm(x, n))];
-        dst[ra + x] = v.x;
-        dst[ra + n + x] = v.y;
+        if (accum) {
+            dst[ra + x] += v.x;
+            dst[ra + n + x] += v.y;
+        } else {
+            dst[ra + x] = v.x;
+            dst[ra + n + x] = v.y;
+        }
     }
 }
 
@@ -469,16 +509,21 @@ __global__ __launch_bounds__(kBlock) void fft_cols_kernel(float2* __restrict__ T
                                                           const float* __restrict__ spec, float alpha,
                                                           float inv, FftDesc fd,
                                                           const float2* __restrict__ tw, int CC, int mode,
-                                                          float* __restrict__ power, int seq_shift) {
+                                                          float* __restrict__ power, int seq_shift,
+                                                          const float2* __restrict__ lamc,
+                                                          const double* __restrict__ alpha_dev,
+                                                          float2* __restrict__ cspec) {
     extern __shared__ float2 buf[];
-    fft_cols_body(T, n, ts, spec, alpha, inv, fd, tw, CC, mode, power, seq_shift, blockIdx.x, buf);
+    fft_cols_body(T, n, ts, spec, alpha, inv, fd, tw, CC, mode, power, seq_shift, blockIdx.x, buf, nullptr, nullptr,
+                  nullptr, lamc, alpha_dev, cspec);
 }
 
 __global__ __launch_bounds__(kBlock) void fft_rows_c2r_kernel(const float2* __restrict__ T, int n, int ts,
                                                               float* __restrict__ dst, FftDesc fd,
-                                                              const float2* __restrict__ tw, int G, int seq_shift) {
+                                                              const float2* __restrict__ tw, int G, int seq_shift,
+                                                              int accum) {
     extern __shared__ float2 buf[];
-    fft_rows_c2r_body(T, n, ts, dst, fd, tw, G, seq_shift, blockIdx.x, buf);
+    fft_rows_c2r_body(T, n, ts, dst, fd, tw, G, seq_shift, blockIdx.x, buf, accum);
 }
 
 __global__ __launch_bounds__(kBlock) void dct_rows_fwd_kernel(const float* __restrict__ src, int n,
@@ -493,17 +538,19 @@ __global__ __launch_bounds__(kBlock) void dct_cols_filter_kernel(float* __restri
                                                                  const float* __restrict__ spec, float alpha,
                                                                  float inv, FftDesc fd,
                                                                  const float2* __restrict__ tw,
-                                                                 const float2* __restrict__ dtw, int CP, int seq_shift) {
+                                                                 const float2* __restrict__ dtw, int CP, int seq_shift,
+                                                                 const float* __restrict__ lamr) {
     extern __shared__ float2 buf[];
-    dct_cols_filter_body(Tr, n, ts, spec, alpha, inv, fd, tw, dtw, CP, seq_shift, blockIdx.x, buf);
+    dct_cols_filter_body(Tr, n, ts, spec, alpha, inv, fd, tw, dtw, CP, seq_shift, blockIdx.x, buf, lamr);
 }
 
 __global__ __launch_bounds__(kBlock) void dct_rows_inv_kernel(const float* __restrict__ Tr, int n, int ts,
                                                               float* __restrict__ dst, FftDesc fd,
                                                               const float2* __restrict__ tw,
-                                                              const float2* __restrict__ dtw, int G, int seq_shift) {
+                                                              const float2* __restrict__ dtw, int G, int seq_shift,
+                                                              int accum) {
     extern __shared__ float2 buf[];
-    dct_rows_inv_body(Tr, n, ts, dst, fd, tw, dtw, G, seq_shift, blockIdx.x, buf);
+    dct_rows_inv_body(Tr, n, ts, dst, fd, tw, dtw, G, seq_shift, blockIdx.x, buf, accum);
 }
 
 // lambda of the reflective blur of the symmetrised PSF:
@@ -511,7 +558,8 @@ __global__ __launch_bounds__(kBlock) void dct_rows_inv_kernel(const float* __res
 // written squared into spec[kx][ky]; costab[q] = cos(pi q / n), q < 2n.
 __global__ __launch_bounds__(kBlock) void dct_spectrum_kernel(const float* __restrict__ psf, int p, int n,
                                                               float* __restrict__ spec,
-                                                              const float* __restrict__ costab) {
+                                                              const float* __restrict__ costab,
+                                                              float* __restrict__ lam) {
     const int ky = blockIdx.x * kBlock + threadIdx.x;
     const int kx = blockIdx.y;
     if (ky >= n) return;
@@ -529,6 +577,19 @@ __global__ __launch_bounds__(kBlock) void dct_spectrum_kernel(const float* __res
         acc += cy * row;
     }
     spec[(size_t)kx * n + ky] = acc * acc;
+    if (lam) lam[(size_t)kx * n + ky] = acc;
+}
+
+// the PSF centred at the origin of a zeroed n x n image: H[a][b] at
+// ((a - c) mod n, (b - c) mod n) -- the kernel of the periodic-boundary blur
+__global__ __launch_bounds__(kBlock) void pad_psf_centred_kernel(const float* __restrict__ psf, int p,
+                                                                 float* __restrict__ dst, int n) {
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= (size_t)n * n) return;
+    const int y = (int)(i / n), x = (int)(i % n);
+    const int c = (p - 1) / 2;
+    const int a = (y + c) % n, b = (x + c) % n;  // inverse of the shift
+    dst[i] = (a < p && b < p) ? psf[a * p + b] : 0.0f;
 }
 
 __global__ __launch_bounds__(kBlock) void pad_psf_kernel(const float* __restrict__ psf, int p,
@@ -538,6 +599,139 @@ __global__ __launch_bounds__(kBlock) void pad_psf_kernel(const float* __restrict
     const int y = (int)(i / n), x = (int)(i % n);
     dst[i] = (y < p && x < p) ? psf[y * p + x] : 0.0f;
 }
+
+// ---------------------------------------------------------------------------
+// Algorithm 4-NS: alpha_n with alpha_n ||(C C^T + alpha_n I)^{-1} r|| = q_n ||r||
+// (eq. Alg4_rev_7), solved on the device from the half spectrum of r (T after
+// a forward column pass) and s = |Lambda|^2.  By Parseval the equation reads
+// h(alpha) = alpha^2 S0(alpha) = q_n^2 R with S0 = sum w / (s + alpha)^2,
+// R = sum w, w = |F r|^2 (each x-frequency other than 0 and n/2 stands for
+// itself and its conjugate twin, weight 2).  h increases with alpha; Newton on
+// log h against log alpha (slope d log h / d log alpha = 2 S1 / S0,
+// S1 = sum w s / (s + alpha)^3) with a bracket [lo, hi] that every step
+// narrows, falling back to bisection of log alpha when a step leaves it.
+// state (device doubles): [0] alpha, [1] log lo, [2] log hi, [3] q_n.
+// ---------------------------------------------------------------------------
+constexpr int NS_BLOCKS = 256;
+
+__global__ __launch_bounds__(kBlock) void ns_partials_kernel(const float2* __restrict__ T, int n, int ts,
+                                                             const float* __restrict__ spec,
+                                                             const double* __restrict__ state,
+                                                             double* __restrict__ part) {
+    __shared__ double red[3][kBlock / 64];
+    const float a = (float)state[0];
+    const int half = n / 2 + 1;
+    const size_t total = (size_t)half * n;
+    double s0 = 0.0, s1 = 0.0, rr = 0.0;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (size_t)gridDim.x * kBlock) {
+        const int kx = (int)(i / n);
+        const int ky = (int)(i - (size_t)kx * n);
+        const float2 v = T[(size_t)kx * ts + ky];
+        const float w = ((kx == 0 || 2 * kx == n) ? 1.0f : 2.0f) * (v.x * v.x + v.y * v.y);
+        const float sk = spec[i];
+        const float id = 1.0f / (sk + a);
+        const float t0 = w * id * id;
+        s0 += (double)t0;
+        s1 += (double)(t0 * sk * id);
+        rr += (double)w;
+    }
+    double v[3] = {s0, s1, rr};
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        double x = v[q];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) red[q][wid] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) t += red[threadIdx.x][w];
+        part[(size_t)blockIdx.x * 3 + threadIdx.x] = t;
+    }
+}
+
+// q_n from ||r^n||^2 (rn_sq) and the noise level; bracket [hi 1e-14, hi] with
+// hi = q_n smax / (1 - q_n), smax = (sum |H|)^2 >= max |Lambda|^2 (there
+// alpha / (s + alpha) >= q_n for every s); start from the previous alpha when
+// it lies inside, else from hi / 2.
+__global__ void ns_init_kernel(double* __restrict__ state, const double* __restrict__ rn_sq,
+                               const float* __restrict__ psf, int p, double noise, double q, double rho,
+                               double alpha_first, int first) {
+    double l1 = 0.0;
+    for (int i = 0; i < p * p; ++i) l1 += fabs((double)psf[i]);
+    const double smax = l1 * l1;
+    const double tau_n = sqrt(*rn_sq) / noise;
+    const double qn = fmax(q, 2.0 * rho + (1.0 + rho) / tau_n);
+    const double hi = qn * smax / (1.0 - qn) * 1.0001 + 1e-30;
+    const double lo = hi * 1e-14;
+    double a = first ? alpha_first : state[0];
+    if (!(a > lo && a < hi)) a = 0.5 * hi;
+    state[0] = a;
+    state[1] = log(lo);
+    state[2] = log(hi);
+    state[3] = qn;
+}
+
+__global__ __launch_bounds__(kBlock) void ns_update_kernel(const double* __restrict__ part, int nparts,
+                                                           double* __restrict__ state, double* __restrict__ hist) {
+    __shared__ double red[3][kBlock / 64];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nparts; b += kBlock)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) v[q] += part[(size_t)b * 3 + q];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        double x = v[q];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) red[q][wid] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double S0 = 0.0, S1 = 0.0, R = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+        S0 += red[0][w];
+        S1 += red[1][w];
+        R += red[2][w];
+    }
+    const double a = state[0], la = log(a);
+    double lo = state[1], hi = state[2];
+    const double qn = state[3];
+    const double h = a * a * S0, target = qn * qn * R;
+    double t;
+    const double g = log(h) - log(target);
+    if (R <= 0.0 || fabs(g) < 1e-13) {
+        t = la;  // r = 0 (nothing to solve), or solved to rounding: stay
+    } else {
+        if (g > 0.0) hi = la; else lo = la;
+        const double slope = 2.0 * S1 / S0;
+        t = (slope > 0.0 && isfinite(g)) ? la - g / slope : 0.5 * (lo + hi);
+        // a Newton point on the bracket's closed interval is kept (it sits on
+        // the end just moved when g is near rounding); outside it, bisect
+        if (!(t >= lo && t <= hi)) t = 0.5 * (lo + hi);
+    }
+    state[0] = exp(t);
+    state[1] = lo;
+    state[2] = hi;
+    if (hist) *hist = state[0];
+}
+
+hipError_t launch_ns_alpha(const float2* T, int n, int ts, const float* spec, double* state, double* part,
+                           const double* rn_sq, const float* psf, int p, double noise, double q, double rho,
+                           double alpha_first, int first, int steps, double* hist, hipStream_t s) {
+    hipLaunchKernelGGL(ns_init_kernel, dim3(1), dim3(1), 0, s, state, rn_sq, psf, p, noise, q, rho, alpha_first,
+                       first);
+    for (int k = 0; k < steps; ++k) {
+        hipLaunchKernelGGL(ns_partials_kernel, dim3(NS_BLOCKS), dim3(kBlock), 0, s, T, n, ts, spec,
+                           (const double*)state, part);
+        hipLaunchKernelGGL(ns_update_kernel, dim3(1), dim3(kBlock), 0, s, (const double*)part, NS_BLOCKS, state,
+                           k == steps - 1 ? hist : (double*)nullptr);
+    }
+    return hipGetLastError();
+}
+
+int ns_partials_needed() { return 3 * NS_BLOCKS; }
 
 // ---------------------------------------------------------------------------
 // launch helpers
@@ -655,33 +849,50 @@ hipError_t launch_fft_rows_r2c(const float* src, int n, float2* T, int ts, const
     return hipGetLastError();
 }
 
-hipError_t launch_fft_cols_filter(float2* T, int n, int ts, const float* spec, float alpha, float inv,
-                                  const FftDesc& fd, const float2* tw, hipStream_t s) {
+static hipError_t launch_cols(float2* T, int n, int ts, const float* spec, float alpha, float inv, const FftDesc& fd,
+                              const float2* tw, int mode, float* power, const float2* lamc, const double* alpha_dev,
+                              float2* cspec, hipStream_t s) {
     const int CC = pick_cols_per_block(n);
     const int half = n / 2 + 1;
     const size_t lds = lds_bytes(CC * n, n);
     hipLaunchKernelGGL(fft_cols_kernel, dim3((half + CC - 1) / CC), dim3(kBlock), lds, s, T, n, ts, spec, alpha,
-                       inv, fd, tw, CC, 0, (float*)nullptr, seq_shift_for(CC));
+                       inv, fd, tw, CC, mode, power, seq_shift_for(CC), lamc, alpha_dev, cspec);
     return hipGetLastError();
+}
+
+hipError_t launch_fft_cols_filter(float2* T, int n, int ts, const float* spec, float alpha, float inv,
+                                  const FftDesc& fd, const float2* tw, hipStream_t s, const float2* lamc) {
+    return launch_cols(T, n, ts, spec, alpha, inv, fd, tw, 0, nullptr, lamc, nullptr, nullptr, s);
+}
+
+hipError_t launch_fft_cols_forward(float2* T, int n, int ts, const FftDesc& fd, const float2* tw, hipStream_t s) {
+    return launch_cols(T, n, ts, nullptr, 0.0f, 1.0f, fd, tw, 3, nullptr, nullptr, nullptr, nullptr, s);
+}
+
+hipError_t launch_fft_cols_filter_inverse(float2* T, int n, int ts, const float* spec, const double* alpha_dev,
+                                          float inv, const float2* lamc, const FftDesc& fd, const float2* tw,
+                                          hipStream_t s) {
+    return launch_cols(T, n, ts, spec, 0.0f, inv, fd, tw, 4, nullptr, lamc, alpha_dev, nullptr, s);
+}
+
+hipError_t launch_fft_cols_complex(const float2* T, int n, int ts, float2* cspec, const FftDesc& fd,
+                                   const float2* tw, hipStream_t s) {
+    return launch_cols(const_cast<float2*>(T), n, ts, nullptr, 0.0f, 1.0f, fd, tw, 2, nullptr, nullptr, nullptr, cspec,
+                       s);
 }
 
 hipError_t launch_fft_cols_power(const float2* T, int n, int ts, float* spec, const FftDesc& fd,
                                  const float2* tw, hipStream_t s) {
-    const int CC = pick_cols_per_block(n);
-    const int half = n / 2 + 1;
-    const size_t lds = lds_bytes(CC * n, n);
-    hipLaunchKernelGGL(fft_cols_kernel, dim3((half + CC - 1) / CC), dim3(kBlock), lds, s,
-                       const_cast<float2*>(T), n, ts, (const float*)nullptr, 0.0f, 1.0f, fd, tw, CC, 1, spec,
-                       seq_shift_for(CC));
-    return hipGetLastError();
+    return launch_cols(const_cast<float2*>(T), n, ts, nullptr, 0.0f, 1.0f, fd, tw, 1, spec, nullptr, nullptr, nullptr,
+                       s);
 }
 
 hipError_t launch_fft_rows_c2r(const float2* T, int n, int ts, float* dst, const FftDesc& fd, const float2* tw,
-                               hipStream_t s) {
+                               hipStream_t s, int accum) {
     const int G = pick_pairs_per_block(n);
     const size_t lds = lds_bytes(G * n, n);
     hipLaunchKernelGGL(fft_rows_c2r_kernel, dim3(n / (2 * G)), dim3(kBlock), lds, s, T, n, ts, dst, fd, tw, G,
-                       seq_shift_for(G));
+                       seq_shift_for(G), accum);
     return hipGetLastError();
 }
 
@@ -695,27 +906,36 @@ hipError_t launch_dct_rows_fwd(const float* src, int n, float* Tr, int ts, const
 }
 
 hipError_t launch_dct_cols_filter(float* Tr, int n, int ts, const float* spec, float alpha, float inv,
-                                  const FftDesc& fd, const float2* tw, const float2* dtw, hipStream_t s) {
+                                  const FftDesc& fd, const float2* tw, const float2* dtw, hipStream_t s,
+                                  const float* lamr) {
     int CP = pick_cols_per_block(n);
     const int pairs = n / 2;
     const size_t lds = lds_bytes(CP * n, n);
     hipLaunchKernelGGL(dct_cols_filter_kernel, dim3((pairs + CP - 1) / CP), dim3(kBlock), lds, s, Tr, n, ts, spec,
-                       alpha, inv, fd, tw, dtw, CP, seq_shift_for(CP));
+                       alpha, inv, fd, tw, dtw, CP, seq_shift_for(CP), lamr);
     return hipGetLastError();
 }
 
 hipError_t launch_dct_rows_inv(const float* Tr, int n, int ts, float* dst, const FftDesc& fd, const float2* tw,
-                               const float2* dtw, hipStream_t s) {
+                               const float2* dtw, hipStream_t s, int accum) {
     const int G = pick_pairs_per_block(n);
     const size_t lds = lds_bytes(G * n, n);
     hipLaunchKernelGGL(dct_rows_inv_kernel, dim3(n / (2 * G)), dim3(kBlock), lds, s, Tr, n, ts, dst, fd, tw, dtw, G,
-                       seq_shift_for(G));
+                       seq_shift_for(G), accum);
     return hipGetLastError();
 }
 
-hipError_t launch_dct_spectrum(const float* psf, int p, int n, float* spec, const float* costab, hipStream_t s) {
+hipError_t launch_dct_spectrum(const float* psf, int p, int n, float* spec, const float* costab, hipStream_t s,
+                               float* lam) {
     dim3 grid((n + kBlock - 1) / kBlock, n);
-    hipLaunchKernelGGL(dct_spectrum_kernel, grid, dim3(kBlock), 0, s, psf, p, n, spec, costab);
+    hipLaunchKernelGGL(dct_spectrum_kernel, grid, dim3(kBlock), 0, s, psf, p, n, spec, costab, lam);
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_psf_centred(const float* psf, int p, float* dst, int n, hipStream_t s) {
+    const size_t tot = (size_t)n * n;
+    hipLaunchKernelGGL(pad_psf_centred_kernel, dim3((unsigned)((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, psf,
+                       p, dst, n);
     return hipGetLastError();
 }
 

@@ -189,28 +189,46 @@ hipError_t launch_analysis_adjoint_batched(const BatchImage* imgs, const int* bm
 // stride ts = n + 16 keeps the transposed accesses off a single memory channel)
 hipError_t launch_fft_rows_r2c(const float* src, int n, float2* T, int ts, const FftDesc& fd,
                                const float2* tw, hipStream_t s);
-// columns: forward FFT, scale by inv / (spec + alpha), inverse FFT (in place)
+// columns: forward FFT, scale by inv / (spec + alpha) (times conj(lamc) when
+// given: the C^T (C C^T + alpha I)^{-1} of Algorithm 4), inverse FFT (in place)
 hipError_t launch_fft_cols_filter(float2* T, int n, int ts, const float* spec, float alpha, float inv,
-                                  const FftDesc& fd, const float2* tw, hipStream_t s);
+                                  const FftDesc& fd, const float2* tw, hipStream_t s, const float2* lamc = nullptr);
+// columns: forward FFT only (T then holds the 2-D half spectrum)
+hipError_t launch_fft_cols_forward(float2* T, int n, int ts, const FftDesc& fd, const float2* tw, hipStream_t s);
+// columns: the filter of launch_fft_cols_filter with alpha read on the device, inverse FFT
+hipError_t launch_fft_cols_filter_inverse(float2* T, int n, int ts, const float* spec, const double* alpha_dev,
+                                          float inv, const float2* lamc, const FftDesc& fd, const float2* tw,
+                                          hipStream_t s);
+// columns: forward FFT, complex values into cspec (dense [n/2+1][n])
+hipError_t launch_fft_cols_complex(const float2* T, int n, int ts, float2* cspec, const FftDesc& fd,
+                                   const float2* tw, hipStream_t s);
+// Algorithm 4-NS: alpha_n on the device (state, hist: device doubles; part: >= ns_partials_needed())
+hipError_t launch_ns_alpha(const float2* T, int n, int ts, const float* spec, double* state, double* part,
+                           const double* rn_sq, const float* psf, int p, double noise, double q, double rho,
+                           double alpha_first, int first, int steps, double* hist, hipStream_t s);
+int ns_partials_needed();
 // columns: forward FFT, write spec = |.|^2 (same transposed layout)
 hipError_t launch_fft_cols_power(const float2* T, int n, int ts, float* spec, const FftDesc& fd,
                                  const float2* tw, hipStream_t s);
 hipError_t launch_fft_rows_c2r(const float2* T, int n, int ts, float* dst, const FftDesc& fd,
-                               const float2* tw, hipStream_t s);
+                               const float2* tw, hipStream_t s, int accum = 0);  // accum: dst +=
 // DCT: rows DCT-II -> Tr (transposed, real [n][n]); columns DCT-II, filter,
 // DCT-III; rows DCT-III -> dst.  Unnormalised transforms; `inv` carries 1/n^2.
 hipError_t launch_dct_rows_fwd(const float* src, int n, float* Tr, int ts, const FftDesc& fd,
                                const float2* tw, const float2* dtw, hipStream_t s);
 hipError_t launch_dct_cols_filter(float* Tr, int n, int ts, const float* spec, float alpha, float inv,
                                   const FftDesc& fd, const float2* tw, const float2* dtw,
-                                  hipStream_t s);
+                                  hipStream_t s, const float* lamr = nullptr);  // lamr: times lambda (Alg. 4)
 hipError_t launch_dct_rows_inv(const float* Tr, int n, int ts, float* dst, const FftDesc& fd,
-                               const float2* tw, const float2* dtw, hipStream_t s);
-// spec[kx][ky] = lambda[ky][kx]^2 for the symmetrised PSF (Algorithm 3)
+                               const float2* tw, const float2* dtw, hipStream_t s, int accum = 0);
+// spec[kx][ky] = lambda[ky][kx]^2 for the symmetrised PSF (Algorithm 3), and
+// lambda itself into lam when given
 hipError_t launch_dct_spectrum(const float* psf, int p, int n, float* spec, const float* costab,
-                               hipStream_t s);
+                               hipStream_t s, float* lam = nullptr);
 // place the PSF in the top-left corner of a zeroed n x n image
 hipError_t launch_pad_psf(const float* psf, int p, float* dst, int n, hipStream_t s);
+// the PSF centred at the origin (kernel of the periodic-boundary blur)
+hipError_t launch_pad_psf_centred(const float* psf, int p, float* dst, int n, hipStream_t s);
 // transform batching chosen for size n (row pairs / columns per workgroup)
 int fft_rows_batch(int n);
 int fft_cols_batch(int n);

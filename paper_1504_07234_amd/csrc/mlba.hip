@@ -122,9 +122,48 @@ int compute_spectrum(mlba_plan_s* P, hipStream_t s) {
         HIPCHK(launch_pad_psf(P->psf, P->p, P->r, n, s));
         HIPCHK(launch_fft_rows_r2c(P->r, n, (float2*)P->swork, P->ts, P->fd, P->tw, s));
         HIPCHK(launch_fft_cols_power((const float2*)P->swork, n, P->ts, P->spec, P->fd, P->tw, s));
+        if (P->lamc) {  // Algorithm 4: eigenvalues of the periodic blur (PSF centred at the origin)
+            HIPCHK(launch_pad_psf_centred(P->psf, P->p, P->r, n, s));
+            HIPCHK(launch_fft_rows_r2c(P->r, n, (float2*)P->swork, P->ts, P->fd, P->tw, s));
+            HIPCHK(launch_fft_cols_complex((const float2*)P->swork, n, P->ts, P->lamc, P->fd, P->tw, s));
+        }
     } else if (P->precond == MLBA_PRECOND_DCT) {
-        HIPCHK(launch_dct_spectrum(P->psf, P->p, n, P->spec, P->costab, s));
+        HIPCHK(launch_dct_spectrum(P->psf, P->p, n, P->spec, P->costab, s, P->lamr));
     }
+    return MLBA_OK;
+}
+
+// t = C^T (C C^T + alpha I)^{-1} r (Algorithm 4), or accumulated into t (accum)
+int do_ct_precond(mlba_plan_s* P, const float* r, float* t, double alpha, int accum, hipStream_t s) {
+    const int n = P->n;
+    const float inv = (float)(1.0 / ((double)n * (double)n));
+    if (P->precond == MLBA_PRECOND_BCCB) {
+        float2* T = (float2*)P->swork;
+        HIPCHK(launch_fft_rows_r2c(r, n, T, P->ts, P->fd, P->tw, s));
+        HIPCHK(launch_fft_cols_filter(T, n, P->ts, P->spec, (float)alpha, inv, P->fd, P->tw, s, P->lamc));
+        HIPCHK(launch_fft_rows_c2r(T, n, P->ts, t, P->fd, P->tw, s, accum));
+    } else {
+        float* Tr = (float*)P->swork;
+        HIPCHK(launch_dct_rows_fwd(r, n, Tr, P->ts, P->fd, P->tw, P->dtw, s));
+        HIPCHK(launch_dct_cols_filter(Tr, n, P->ts, P->spec, (float)alpha, inv, P->fd, P->tw, P->dtw, s, P->lamr));
+        HIPCHK(launch_dct_rows_inv(Tr, n, P->ts, t, P->fd, P->tw, P->dtw, s, accum));
+    }
+    return MLBA_OK;
+}
+
+// Algorithm 4-NS step (BCCB): alpha_n solved on the device from the spectrum
+// of r (rn_sq = ||r||^2 on the device), then t (+)= C^T (C C^T + alpha_n I)^{-1} r
+int do_ct_precond_ns(mlba_plan_s* P, const float* r, float* t, const double* rn_sq, double noise, double q,
+                     double rho, double alpha_first, int first, double* hist, int accum, hipStream_t s) {
+    const int n = P->n;
+    const float inv = (float)(1.0 / ((double)n * (double)n));
+    float2* T = (float2*)P->swork;
+    HIPCHK(launch_fft_rows_r2c(r, n, T, P->ts, P->fd, P->tw, s));
+    HIPCHK(launch_fft_cols_forward(T, n, P->ts, P->fd, P->tw, s));
+    HIPCHK(launch_ns_alpha(T, n, P->ts, P->spec, P->ns, P->partials, rn_sq, P->psf, P->p, noise, q, rho,
+                           alpha_first, first, 12, hist, s));
+    HIPCHK(launch_fft_cols_filter_inverse(T, n, P->ts, P->spec, P->ns, inv, P->lamc, P->fd, P->tw, s));
+    HIPCHK(launch_fft_rows_c2r(T, n, P->ts, t, P->fd, P->tw, s, accum));
     return MLBA_OK;
 }
 
@@ -307,6 +346,7 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
     const int m = n + p - 1;
     P->partials_cap = conv_partials_count(n);
     if (P->partials_cap < reduce_partials_cap()) P->partials_cap = reduce_partials_cap();
+    if (P->partials_cap < ns_partials_needed()) P->partials_cap = ns_partials_needed();
     P->rn_cap = 1 << 16;
 #define ALLOC(ptr, count)                                  \
     do {                                                   \
@@ -330,6 +370,7 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
     ALLOC(P->partials, (size_t)P->partials_cap);
     ALLOC(P->scal, 8);
     ALLOC(P->rn, (size_t)P->rn_cap);
+    ALLOC(P->ahist, (size_t)P->rn_cap);
     if (bc == MLBA_BC_REFLECT) ALLOC(P->wext, (size_t)m * m);
 
     if (precond != MLBA_PRECOND_NONE) {
@@ -358,15 +399,18 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
         ALLOC(P->tw, (size_t)n);
         ALLOC(P->dtw, (size_t)n);
         ALLOC(P->costab, (size_t)2 * n);
+        ALLOC(P->ns, 8);
         if (precond == MLBA_PRECOND_BCCB) {
             P->ts = n + 16;
             ALLOC(P->spec, (size_t)(n / 2 + 1) * n);
+            if (bc != MLBA_BC_RECT) ALLOC(P->lamc, (size_t)(n / 2 + 1) * n);
             float2* T = nullptr;
             ALLOC(T, (size_t)(n / 2 + 1) * P->ts);
             P->swork = T;
         } else {
             P->ts = n + 32;
             ALLOC(P->spec, obs);
+            if (bc != MLBA_BC_RECT) ALLOC(P->lamr, obs);
             float* Tr = nullptr;
             ALLOC(Tr, (size_t)n * P->ts);
             P->swork = Tr;
@@ -440,6 +484,12 @@ int mlba_apply_P(mlba_plan_t P, const float* r, float* t, double alpha, hipStrea
     return do_precond(P, r, t, alpha, s);
 }
 
+int mlba_apply_CtP(mlba_plan_t P, const float* r, float* t, double alpha, hipStream_t s) {
+    if (!P || !r || !t || r == t || !(alpha > 0.0)) return MLBA_EINVAL;
+    if (P->bc == MLBA_BC_RECT || P->precond == MLBA_PRECOND_NONE) return MLBA_EUNSUPPORTED;
+    return do_ct_precond(P, r, t, alpha, 0, s);
+}
+
 int mlba_framelet_analysis(mlba_plan_t P, const float* f, float* z, hipStream_t s) {
     if (!P || !f || !z) return MLBA_EINVAL;
     return do_analysis(P, f, z, false, s);
@@ -491,13 +541,29 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
     const int iters = prm->iters, k0 = prm->k0;
     if (iters < 0 || k0 < 0) return MLBA_EINVAL;
     const mlba_alpha_schedule& as = prm->alpha;
-    if (as.kind < MLBA_ALPHA_CONST || as.kind > MLBA_ALPHA_TABLE) return MLBA_EINVAL;
+    if (as.kind < MLBA_ALPHA_CONST || as.kind > MLBA_ALPHA_NS) return MLBA_EINVAL;
     if (as.kind == MLBA_ALPHA_TABLE && (!as.table || as.table_len < k0 + iters)) return MLBA_EINVAL;
     if (as.kind == MLBA_ALPHA_GEOMETRIC && !(as.ratio > 0.0)) return MLBA_EINVAL;
     const mlba_stop* stop = prm->stop;
     if (stop && (stop->check_every < 1 || !(stop->noise_norm >= 0.0))) return MLBA_EINVAL;
     if (prm->state != MLBA_STATE_EXPLICIT && prm->state != MLBA_STATE_IMPLICIT) return MLBA_EINVAL;
     const bool implicit = prm->state == MLBA_STATE_IMPLICIT;
+    if (prm->method != MLBA_METHOD_MLBA && prm->method != MLBA_METHOD_ALG4) return MLBA_EINVAL;
+    const bool alg4 = prm->method == MLBA_METHOD_ALG4;
+    if (alg4 && (P->bc == MLBA_BC_RECT || P->precond == MLBA_PRECOND_NONE)) return MLBA_EUNSUPPORTED;
+    const bool ns = as.kind == MLBA_ALPHA_NS;
+    mlba_stop ns_stop{};
+    if (ns) {
+        if (prm->alpha_out && iters > P->rn_cap) return MLBA_EINVAL;  // the device history is one ring
+        if (!alg4 || P->precond != MLBA_PRECOND_BCCB) return MLBA_EUNSUPPORTED;
+        if (!stop || !(stop->noise_norm > 0.0) || !(as.ns_rho > 0.0 && as.ns_rho < 0.5) ||
+            !(as.ns_q > 2.0 * as.ns_rho && as.ns_q < 1.0) || !(as.alpha0 > 0.0))
+            return MLBA_EINVAL;
+        ns_stop.noise_norm = stop->noise_norm;
+        ns_stop.gamma = (1.0 + 2.0 * as.ns_rho) / (1.0 - 2.0 * as.ns_rho);  // tau of eq. (Alg4_rev_12)
+        ns_stop.check_every = 1;
+        stop = &ns_stop;
+    }
     float mub[64];
     STCHK(expand_mu(P, prm->mu, prm->n_mu, mub));
 
@@ -511,6 +577,8 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
         for (int i = 0; i <= iters; ++i) delta[i] = prm->delta_table[k0 + i];
     } else if (prm->delta > 0.0) {
         for (int i = 0; i <= iters; ++i) delta[i] = prm->delta;
+    } else if (alg4) {
+        for (int i = 0; i <= iters; ++i) delta[i] = 1.0;  // eq. (Alg4) uses the unit step
     } else {
         std::vector<double> seen_a, seen_d;
         for (int i = 0; i <= iters; ++i) {
@@ -550,8 +618,8 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
     };
 
     const int launches[MLBA_NPHASES] = {
-        implicit ? 2 * P->levels - 1 : P->levels, 2, P->precond == MLBA_PRECOND_NONE ? 1 : 3,
-        P->bc == MLBA_BC_REFLECT ? 2 : 1, implicit ? 0 : P->levels};
+        implicit ? 2 * P->levels - 1 : P->levels, 2, P->precond == MLBA_PRECOND_NONE ? 1 : (ns ? 4 + 1 + 24 : 3),
+        alg4 ? 0 : (P->bc == MLBA_BC_REFLECT ? 2 : 1), implicit ? 0 : P->levels};
     for (int i = 0; i < iters; ++i) {
         if (i - ring_base >= P->rn_cap) {
             if (track) STCHK(drain(i));
@@ -581,6 +649,23 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
             }
         }
         if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_PRECOND], s));
+        if (alg4) {
+            // eq. (Alg4): the direction C^T (C C^T + alpha I)^{-1} r, no A^T product
+            float* dst = implicit ? z : P->t;
+            if (ns) {
+                STCHK(do_ct_precond_ns(P, P->r, dst, P->rn + (i - ring_base), stop->noise_norm, as.ns_q,
+                                       as.ns_rho, as.alpha0, i == 0 ? 1 : 0, P->ahist + (i - ring_base),
+                                       implicit ? 1 : 0, s));
+            } else {
+                STCHK(do_ct_precond(P, P->r, dst, alpha[i], implicit ? 1 : 0, s));
+            }
+            if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_BLUR_T], s));
+            if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_ANALYSIS], s));
+            if (!implicit) STCHK(do_analysis(P, P->t, z, true, s));
+            if (ev) HIPCHK(hipEventRecord(ev[MLBA_NPHASES], s));
+            done = i + 1;
+            continue;
+        }
         STCHK(do_precond(P, P->r, P->t, alpha[i], s));
         if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_BLUR_T], s));
         if (implicit) {
@@ -599,6 +684,14 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
         else STCHK(do_synthesis(P, z, f_out, true, mub, (float)delta[done], s));
     }
 
+    if (prm->alpha_out && done > 0) {
+        if (ns) {
+            HIPCHK(hipMemcpyAsync(prm->alpha_out, P->ahist, (size_t)done * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        } else {
+            for (int i = 0; i < done; ++i) prm->alpha_out[i] = alpha[i];
+        }
+    }
     int status = MLBA_OK;
     if (track) {
         STCHK(drain(done));

@@ -31,6 +31,10 @@ struct mlba_plan_s {
     int conv_rows[2] = {0, 0}; // output rows per thread of the A / A^T blur (0: by occupancy)
     float* psf = nullptr;
     float* spec = nullptr;     // BCCB: [n/2+1][n] |Lambda|^2 (transposed); DCT: [n][n] lambda^2
+    float2* lamc = nullptr;    // square models, BCCB: Lambda_c of the centred PSF (layout of spec)
+    float* lamr = nullptr;     // square models, DCT: lambda (layout of spec)
+    double* ns = nullptr;      // Algorithm 4-NS device state
+    double* ahist = nullptr;   // alpha_k used (ring like rn)
     float2* tw = nullptr;      // exp(-2 pi i q / n)
     float2* dtw = nullptr;     // exp(-i pi k / (2n))
     float* costab = nullptr;   // cos(pi q / n), q < 2n

@@ -16,6 +16,7 @@ from ._lib import check
 
 RECT, REFLECT, PERIODIC, ZERO = _lib.BC_RECT, _lib.BC_REFLECT, _lib.BC_PERIODIC, _lib.BC_ZERO
 BCCB, DCT, NONE = _lib.PRECOND_BCCB, _lib.PRECOND_DCT, _lib.PRECOND_NONE
+MLBA, ALG4 = _lib.METHOD_MLBA, _lib.METHOD_ALG4
 
 
 def _stream(stream=None) -> ctypes.c_void_p:
@@ -45,6 +46,7 @@ class RestoreInfo:
     status: int
     iters_done: int
     rnorm: list
+    alphas: list = None
 
 
 class Plan:
@@ -152,6 +154,13 @@ class Plan:
         return out
 
     # -- phase timing --------------------------------------------------------
+    def apply_CtP(self, r, alpha: float, out=None, stream=None):
+        """t = C^T (C C^T + alpha I)^{-1} r (the direction of Algorithm 4)."""
+        out = self._new(self.n, self.n) if out is None else out
+        check(self._lib.mlba_apply_CtP(self._h, _dev(r, "r", (self.n, self.n)), _dev(out, "out", (self.n, self.n)),
+                                       float(alpha), _stream(stream)), "mlba_apply_CtP")
+        return out
+
     def shrink_synthesis(self, omega, mu, delta: float, out=None, stream=None):
         """f = W^T(delta S_mu(W omega)) (the implicit state's synthesis)."""
         out = self._new(self.N, self.N) if out is None else out
@@ -177,8 +186,14 @@ class Plan:
     def restore(self, g, *, alpha=0.05, alpha_kind: int = _lib.ALPHA_CONST, alpha_ratio: float = 1.0,
                 alpha_floor: float = 0.0, alpha_table=None, mu=1e-3, delta: float = 0.0, delta_table=None,
                 iters: int = 50, k0: int = 0, z=None, out=None, stop=None, track: bool = True,
-                implicit: bool = False, stream=None):
-        """Run `iters` iterations of eq. (MLBA2); returns (f, RestoreInfo).
+                implicit: bool = False, method: int = _lib.METHOD_MLBA, ns=None, stream=None):
+        """Run `iters` iterations of eq. (MLBA2) (method METHOD_MLBA) or eq. (Alg4)
+        (METHOD_ALG4, square models); returns (f, RestoreInfo).
+
+        ns: (q, rho) selects Algorithm 4-NS (alpha_n solved per iteration, alpha is
+        the first Newton start; needs stop=(noise_norm, ., .), whose gamma is
+        replaced by tau = (1 + 2 rho) / (1 - 2 rho)).  RestoreInfo.alphas holds the
+        alpha_k used.
 
         implicit: keep the state as omega (z = W omega, one N x N plane) instead
         of the frame coefficients z.
@@ -218,6 +233,12 @@ class Plan:
             keep.append(st)
             prm.stop = ctypes.pointer(st)
         prm.state = _lib.STATE_IMPLICIT if implicit else _lib.STATE_EXPLICIT
+        prm.method = int(method)
+        if ns is not None:
+            prm.alpha.kind = _lib.ALPHA_NS
+            prm.alpha.ns_q, prm.alpha.ns_rho = float(ns[0]), float(ns[1])
+        aout = (ctypes.c_double * max(1, iters))() if track else None
+        prm.alpha_out = ctypes.cast(aout, _lib.c_dbl_p) if track else None
         zshape = (self.N, self.N) if implicit else (self.bands, self.N, self.N)
         zp = ctypes.c_void_p() if z is None else _dev(z, "z", zshape)
         rn = (ctypes.c_double * max(1, iters))() if track else None
@@ -227,7 +248,8 @@ class Plan:
                                         ctypes.cast(rn, _lib.c_dbl_p) if track else None,
                                         ctypes.byref(done) if track else None, _stream(stream))
         check(status, "mlba_restore")
-        info = RestoreInfo(status, done.value, list(rn[:done.value]) if track else [])
+        info = RestoreInfo(status, done.value, list(rn[:done.value]) if track else [],
+                           list(aout[:done.value]) if track else [])
         return out, info
 
 
