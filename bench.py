@@ -240,6 +240,44 @@ def unrolled_section(reps: int = 5):
     }
 
 
+def alg4_section(w, g, noise, steps: int = 30):
+    """Algorithm 4 (section 5) on the 2048^2 observation as a square model:
+    periodic boundary conditions, C^T (C C^T + alpha I)^{-1} by FFT (no A^T
+    product), implicit state, alpha = 0.02, unit step, `steps` timed
+    iterations; and Algorithm 4-NS (q = 0.5, rho = 1e-4) run to its
+    discrepancy stop."""
+    import torch
+
+    from paper_1504_07234_amd import mlba
+
+    psf = torch.as_tensor(w.psf, dtype=torch.float32).cuda()
+    n = w.n
+    out = {"model": "periodic", "precond": "bccb", "alpha": 0.02, "levels": w.levels, "state": "implicit omega"}
+    with mlba.Plan(n, w.p, mlba.PERIODIC, mlba.BCCB, w.levels, psf) as plan:
+        f = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        om = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+        plan.restore(g, alpha=0.02, mu=w.mu, delta=1.0, iters=3, z=om, out=f, track=False, implicit=True,
+                     method=mlba.ALG4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.restore(g, alpha=0.02, mu=w.mu, delta=1.0, iters=steps, k0=3, z=om, out=f, track=False,
+                     implicit=True, method=mlba.ALG4)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out.update({"steps": steps, "ms_per_step": round(el * 1e3 / steps, 5),
+                    "Mpx_it_s": round(n * n * steps / el / 1e6, 2)})
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = plan.restore(g, alpha=0.5, mu=w.mu, delta=1.0, iters=500, out=f, implicit=True,
+                               method=mlba.ALG4, ns=(0.5, 1e-4), stop=(noise, 0.0, 1))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out["ns"] = {"q": 0.5, "rho": 1e-4, "iters_to_stop": info.iters_done, "s_total": round(el, 5),
+                     "ms_per_step": round(el * 1e3 / max(info.iters_done, 1), 5),
+                     "last_alpha": info.alphas[-1] if info.alphas else None}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -250,6 +288,7 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-sequential section")
     ap.add_argument("--no-unrolled", action="store_true", help="skip the unrolled forward/backward section")
+    ap.add_argument("--no-alg4", action="store_true", help="skip the Algorithm 4 / 4-NS section")
     ap.add_argument("--state", choices=("implicit", "explicit"), default="implicit",
                     help="iteration state: omega (z = W omega recomputed) or the frame coefficients z")
     ap.add_argument("--compare-steps", type=int, default=20,
@@ -407,6 +446,8 @@ def main() -> int:
         out["batched"] = batched_section()
     if not args.no_unrolled:
         out["unrolled"] = unrolled_section()
+    if not args.no_alg4:
+        out["alg4"] = alg4_section(w, g, float(w.noise_level * blurred.double().norm()))
     if not args.no_cpu:
         from oracle import blur as oblur
         g64 = synth.add_noise(oblur.blur(w.truth, w.psf, oblur.RECT), w.xi, w.noise_level)
