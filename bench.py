@@ -351,6 +351,12 @@ def main() -> int:
         return el, ph
 
     implicit = args.state == "implicit"
+    blur_choice = None
+    if not args.traffic_probe:
+        # what the plan autotuner measures for the blur (direct taps vs FFT grid); the
+        # timed run keeps the direct blur, whose VALU roofline is reported below
+        blur_choice = plan.autotune(reps=5)
+        plan.set_blur(mlba.BLUR_DIRECT)
     if args.traffic_probe:
         src = torch.rand(64 << 20, device="cuda")
         dst = torch.empty_like(src)
@@ -440,6 +446,7 @@ def main() -> int:
         "roofline": roof,
         "roofline_hbm": roof_hbm,
         "other_state": compare,
+        "blur_autotune": blur_choice,
     }
     plan.close()
     if not args.no_batched:

@@ -160,12 +160,27 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
 /* Replace the PSF (same p) and recompute the spectrum. psf: device p x p. */
 int mlba_plan_set_psf(mlba_plan_t plan, const float* psf, hipStream_t stream);
 int mlba_plan_destroy(mlba_plan_t plan);
+/* How the rectangular model's blur A and its transpose are computed:
+ * MLBA_BLUR_DIRECT (default): LDS-tiled direct convolution, p^2 taps per
+ * output; MLBA_BLUR_FFT: circular convolution on an M x M grid, M >= N,
+ * M = 2^a 3^b (section 2.1's FFT evaluation), three transform passes per
+ * product.  mlba_plan_set_blur: MLBA_BLUR_FFT allocates the grid's workspace
+ * and PSF spectrum on first use (synchronous) and returns MLBA_EUNSUPPORTED for
+ * imposed boundary models or when M would exceed 3072.  mlba_plan_autotune:
+ * times both on the plan's own scratch buffers (`reps` calls each, HIP events,
+ * synchronous), keeps the faster pair, writes the mean ms per call to ms_out
+ * (host, optional: direct A, direct A^T, FFT A, FFT A^T; -1 where unavailable)
+ * and returns the chosen mode (>= 0) or an error. */
+#define MLBA_BLUR_DIRECT 0
+#define MLBA_BLUR_FFT    1
+int mlba_plan_set_blur(mlba_plan_t plan, int mode, hipStream_t stream);
+int mlba_plan_autotune(mlba_plan_t plan, int reps, double* ms_out, hipStream_t stream);
 /* Sizes: observed side n, PSF side p, unknown side N, number of bands. */
 int mlba_plan_dims(mlba_plan_t plan, int* n, int* p, int* N, int* bands);
 /* ||A^T P_alpha A|| by `iters` power iterations (synchronous; result on host). */
 int mlba_plan_opnorm(mlba_plan_t plan, double alpha, int iters, double* out, hipStream_t stream);
 
-/* ---- operators (each one device pass, asynchronous) --------------------- */
+/* ---- operators (asynchronous) ---------------------------------------------- */
 /* y = A u.   u: device N x N, y: device n x n (section 2, eq. Arect / Table 1). */
 int mlba_apply_A(mlba_plan_t plan, const float* u, float* y, hipStream_t stream);
 /* r = g - A u.  g, r: device n x n, u: device N x N. */

@@ -18,6 +18,7 @@ BC_RECT, BC_REFLECT, BC_PERIODIC, BC_ZERO = 0, 1, 2, 3
 PRECOND_BCCB, PRECOND_DCT, PRECOND_NONE = 0, 1, 2
 ALPHA_CONST, ALPHA_GEOMETRIC, ALPHA_TABLE, ALPHA_NS = 0, 1, 2, 3
 METHOD_MLBA, METHOD_ALG4 = 0, 1
+BLUR_DIRECT, BLUR_FFT = 0, 1
 STATE_EXPLICIT, STATE_IMPLICIT = 0, 1
 
 c_int, c_double, c_size_t, c_void_p = ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
@@ -53,6 +54,8 @@ SIGNATURES = {
     "mlba_plan_create": (c_int, [ctypes.POINTER(c_void_p), c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p]),
     "mlba_plan_set_psf": (c_int, [c_void_p, c_void_p, c_void_p]),
     "mlba_plan_destroy": (c_int, [c_void_p]),
+    "mlba_plan_set_blur": (c_int, [c_void_p, c_int, c_void_p]),
+    "mlba_plan_autotune": (c_int, [c_void_p, c_int, c_dbl_p, c_void_p]),
     "mlba_plan_dims": (c_int, [c_void_p, c_int_p, c_int_p, c_int_p, c_int_p]),
     "mlba_plan_opnorm": (c_int, [c_void_p, c_double, c_int, c_dbl_p, c_void_p]),
     "mlba_apply_A": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),

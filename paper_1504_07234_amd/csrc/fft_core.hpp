@@ -1,0 +1,163 @@
+// In-LDS mixed-radix (8, 4, 2, 3) Stockham autosort FFT shared by the
+// spectral preconditioners and the FFT blur.  Every thread carries up to EPT
+// complex values per stage in registers between the read and the write
+// barrier; twiddles come from a table of exp(-2 pi i q / n) computed in
+// double precision on the host.
+#pragma once
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mlba {
+
+constexpr int FFT_EPT = 8;  // complex values per thread per stage (max)
+constexpr int FFT_MAX_ELEMS = FFT_EPT * kBlock;  // complex values per workgroup (16 KB of LDS)
+
+// LDS slot of element i: one padding slot after every 8 elements, so that the
+// power-of-two strides of the Stockham writes do not pile onto one bank.
+__host__ __device__ __forceinline__ int lds_slot(int i) { return i + (i >> 3); }
+__host__ __device__ constexpr int lds_data_slots(int elems) { return elems + elems / 8 + 1; }
+__host__ __device__ constexpr size_t lds_bytes(int elems, int n) { return (size_t)lds_data_slots(elems) * 8 + 0 * n; }
+
+template <int DIR>
+__device__ __forceinline__ float2 twiddle(const float2* __restrict__ tw, int q) {
+    const float2 w = tw[q];
+    return DIR < 0 ? w : make_float2(w.x, -w.y);
+}
+
+// w[r] = W^(r*e) for r = 1..R-1, W = exp(DIR 2 pi i / n), e = jm * step.
+// Powers 1, 2, 4 come from the table; the others are one product away.
+template <int R, int DIR>
+__device__ __forceinline__ void twiddle_powers(const float2* __restrict__ tw, int e, int n, float2* w) {
+    w[1] = twiddle<DIR>(tw, e);
+    if constexpr (R >= 3) w[2] = twiddle<DIR>(tw, 2 * e);
+    if constexpr (R >= 4) w[3] = cmul(w[1], w[2]);
+    if constexpr (R == 8) {
+        w[4] = twiddle<DIR>(tw, 4 * e);
+        w[5] = cmul(w[1], w[4]);
+        w[6] = cmul(w[2], w[4]);
+        w[7] = cmul(w[3], w[4]);
+    }
+}
+
+// a * (DIR i)
+template <int DIR>
+__device__ __forceinline__ float2 mul_i(float2 a) {
+    return DIR < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft4(float2* v) {
+    const float2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    const float2 s13 = cadd(v[1], v[3]), d13 = mul_i<DIR>(csub(v[1], v[3]));
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, d13);
+    v[3] = csub(d02, d13);
+}
+
+template <int R, int DIR>
+__device__ __forceinline__ void dft(float2* v) {
+    if constexpr (R == 2) {
+        const float2 t = v[0];
+        v[0] = cadd(t, v[1]);
+        v[1] = csub(t, v[1]);
+    } else if constexpr (R == 3) {
+        const float s3 = 0.86602540378443865f;  // sqrt(3)/2
+        const float2 t = cadd(v[1], v[2]);
+        const float2 d = cscale(mul_i<DIR>(csub(v[1], v[2])), s3);
+        const float2 m = make_float2(v[0].x - 0.5f * t.x, v[0].y - 0.5f * t.y);
+        v[0] = cadd(v[0], t);
+        v[1] = cadd(m, d);
+        v[2] = csub(m, d);
+    } else if constexpr (R == 4) {
+        dft4<DIR>(v);
+    } else {  // R == 8: two length-4 transforms and the eighth-root twiddles
+        float2 e[4] = {v[0], v[2], v[4], v[6]};
+        float2 o[4] = {v[1], v[3], v[5], v[7]};
+        dft4<DIR>(e);
+        dft4<DIR>(o);
+        const float h = 0.70710678118654752f;
+        const float sg = (float)DIR;
+        const float2 o1 = make_float2(h * (o[1].x - sg * o[1].y), h * (o[1].y + sg * o[1].x));
+        const float2 o2 = mul_i<DIR>(o[2]);
+        const float2 o3 = make_float2(h * (-o[3].x - sg * o[3].y), h * (-o[3].y + sg * o[3].x));
+        v[0] = cadd(e[0], o[0]);
+        v[4] = csub(e[0], o[0]);
+        v[1] = cadd(e[1], o1);
+        v[5] = csub(e[1], o1);
+        v[2] = cadd(e[2], o2);
+        v[6] = csub(e[2], o2);
+        v[3] = cadd(e[3], o3);
+        v[7] = csub(e[3], o3);
+    }
+}
+
+// One Stockham stage of radix R.  The workgroup holds up to kBlock >> seq_shift
+// sequences of length n back to back in `buf`; sequence b is owned by the
+// 2^seq_shift threads with threadIdx.x >> seq_shift == b (only the first nseq
+// sequences are live).  Ns is the product of the radices already applied;
+// ns_shift = log2(Ns) when Ns is a power of two (every radix-2/4/8 stage,
+// since radix-3 stages run last), -1 otherwise.
+template <int R, int DIR, int EPT = FFT_EPT>
+__device__ __forceinline__ void stockham_stage(float2* buf, int n, int nseq, int seq_shift, int Ns,
+                                               int ns_shift, const float2* __restrict__ tw) {
+    constexpr int MAXB = (EPT + R - 1) / R;
+    const int nb = n / R;
+    const int nthr = 1 << seq_shift;
+    const int b = threadIdx.x >> seq_shift;
+    const int tl = threadIdx.x & (nthr - 1);
+    const bool live = b < nseq;
+    const int step = n / (Ns * R);
+    const int base0 = b * n;
+    float2 v[MAXB][R];
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int j = tl + i * nthr;
+        if (live && j < nb) {
+            const int jm = ns_shift >= 0 ? (j & (Ns - 1)) : (j % Ns);
+            float2 w[R];
+            if (jm > 0) twiddle_powers<R, DIR>(tw, jm * step, n, w);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float2 x = buf[lds_slot(base0 + j + r * nb)];
+                if (r > 0 && jm > 0) x = cmul(x, w[r]);
+                v[i][r] = x;
+            }
+            dft<R, DIR>(v[i]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int j = tl + i * nthr;
+        if (live && j < nb) {
+            const int jm = ns_shift >= 0 ? (j & (Ns - 1)) : (j % Ns);
+            const int dst = base0 + (j - jm) * R + jm;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[lds_slot(dst + r * Ns)] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+// In-LDS transform of nseq sequences; DIR = -1 forward, +1 inverse
+// (unnormalised).  Each sequence's 2^seq_shift threads carry at most EPT
+// complex values per stage, so n <= EPT << seq_shift.  The caller synchronises
+// before the call.
+template <int DIR, int EPT = FFT_EPT>
+__device__ void lds_fft(float2* buf, const FftDesc& fd, int nseq, int seq_shift, const float2* __restrict__ tw) {
+    int Ns = 1, ns_shift = 0;
+    for (int s = 0; s < fd.nst; ++s) {
+        const int R = fd.radix[s];
+        if (R == 8) stockham_stage<8, DIR, EPT>(buf, fd.n, nseq, seq_shift, Ns, ns_shift, tw);
+        else if (R == 4) stockham_stage<4, DIR, EPT>(buf, fd.n, nseq, seq_shift, Ns, ns_shift, tw);
+        else if (R == 2) stockham_stage<2, DIR, EPT>(buf, fd.n, nseq, seq_shift, Ns, ns_shift, tw);
+        else stockham_stage<3, DIR, EPT>(buf, fd.n, nseq, seq_shift, Ns, ns_shift, tw);
+        Ns *= R;
+        ns_shift = (R == 3 || ns_shift < 0) ? -1 : ns_shift + (R == 8 ? 3 : (R == 4 ? 2 : 1));
+    }
+}
+
+
+}  // namespace mlba

@@ -1,0 +1,247 @@
+// The blur of the rectangular model by FFTs (section 2.1: A and A^T computed
+// with FFTs of a grid that holds the whole unknown), an alternative to the
+// direct convolution for large PSFs.
+//
+// On an M x M grid (M >= N = n + p - 1, M = 2^a 3^b) the circular convolution
+// with H (placed at the origin) has no wrap-around on the outputs that matter:
+//   A u   = crop_{[p-1, N)^2} F^{-1}[ F(pad u) * F(pad H) ] / M^2
+//   A^T t = crop_{[0, N)^2}   F^{-1}[ F(t placed at (p-1, p-1)) * conj(F(pad H)) ] / M^2
+// (the second is the circular correlation, the transpose of the first).
+//
+// Three passes like the preconditioner: rows (two real rows packed into one
+// complex FFT, written transposed as a half spectrum), columns (forward FFT,
+// product with the PSF spectrum, inverse FFT), rows (inverse, with the crop
+// and the epilogue: residual g - . with its squared-norm partials, plain
+// write, or accumulation).  Rows that are zero in the padded input are skipped
+// by the row pass and read as zero by the column pass.  Transforms of up to
+// 3072 points use 12 values per thread.
+#include "common.hpp"
+#include "fft_core.hpp"
+#include "kernels.hpp"
+
+namespace mlba {
+
+constexpr int FC_EPT = 12;
+constexpr int FC_MAX = FC_EPT * kBlock;
+
+int fftconv_max_size() { return FC_MAX; }
+
+static int fc_pairs_per_block(int M) {
+    int G = 1;
+    while ((G * 2) * M <= FC_MAX && ((M / 2) % (G * 2)) == 0 && G * 2 <= 4) G *= 2;
+    return G;
+}
+
+static int fc_cols_per_block(int M) {
+    int cc = 1;
+    while ((cc * 2) * M <= FC_MAX) cc *= 2;
+    return cc;
+}
+
+static int fc_seq_shift(int batch) {
+    int sh = 8;
+    while (batch > 1) {
+        batch >>= 1;
+        --sh;
+    }
+    return sh;
+}
+
+// Rows pass: row pairs pair0 + blk*G + g of the M grid; entry (Y, X) is
+// src[Y - off][X - off] inside the S x S box at (off, off), else 0.
+__global__ __launch_bounds__(kBlock) void fc_rows_fwd_kernel(const float* __restrict__ src, int S, int off, int M,
+                                                             float2* __restrict__ T, int ts, FftDesc fd,
+                                                             const float2* __restrict__ tw, int G, int seq_shift,
+                                                             int pair0, int pair_end) {
+    extern __shared__ float2 buf[];
+    const int pb = pair0 + blockIdx.x * G;
+    for (int idx = threadIdx.x; idx < G * M; idx += kBlock) {
+        const int g = idx / M;
+        const int X = idx - g * M;
+        const int Y = 2 * (pb + g);
+        const int x = X - off;
+        float a = 0.0f, b = 0.0f;
+        if (pb + g < pair_end && x >= 0 && x < S) {
+            const int y0 = Y - off, y1 = Y + 1 - off;
+            if (y0 >= 0 && y0 < S) a = src[(size_t)y0 * S + x];
+            if (y1 >= 0 && y1 < S) b = src[(size_t)y1 * S + x];
+        }
+        buf[lds_slot(idx)] = make_float2(a, b);
+    }
+    __syncthreads();
+    lds_fft<-1, FC_EPT>(buf, fd, G, seq_shift, tw);
+    const int half = M / 2 + 1;
+    for (int idx = threadIdx.x; idx < G * half; idx += kBlock) {
+        const int k = idx / G;
+        const int g = idx - k * G;
+        if (pb + g >= pair_end) continue;
+        const float2 Z = buf[lds_slot(g * M + k)];
+        const float2 Zc = cconj(buf[lds_slot(g * M + (k == 0 ? 0 : M - k))]);
+        const float2 Xa = cscale(cadd(Z, Zc), 0.5f);
+        const float2 D = csub(Z, Zc);
+        const float2 Xb = make_float2(0.5f * D.y, -0.5f * D.x);
+        *reinterpret_cast<float4*>(T + (size_t)k * ts + 2 * (pb + g)) = make_float4(Xa.x, Xa.y, Xb.x, Xb.y);
+    }
+}
+
+// Columns pass over CC half-spectrum rows per workgroup; rows outside
+// [y_lo, y_hi) of the input are zero.  mode 0: forward FFT, times Hs (or
+// conj(Hs)) * inv, inverse FFT, written back; mode 1: forward FFT into cspec.
+__global__ __launch_bounds__(kBlock) void fc_cols_kernel(float2* __restrict__ T, int M, int ts,
+                                                         const float2* __restrict__ Hs, int conj_h, float inv,
+                                                         int y_lo, int y_hi, int mode, float2* __restrict__ cspec,
+                                                         FftDesc fd, const float2* __restrict__ tw, int CC,
+                                                         int seq_shift) {
+    extern __shared__ float2 buf[];
+    const int half = M / 2 + 1;
+    const int k0 = blockIdx.x * CC;
+    const int cc = min(CC, half - k0);
+    for (int idx = threadIdx.x; idx < cc * M; idx += kBlock) {
+        const int q = idx / M;
+        const int y = idx - q * M;
+        buf[lds_slot(idx)] = (y >= y_lo && y < y_hi) ? T[(size_t)(k0 + q) * ts + y] : make_float2(0.0f, 0.0f);
+    }
+    __syncthreads();
+    lds_fft<-1, FC_EPT>(buf, fd, cc, seq_shift, tw);
+    const size_t base = (size_t)k0 * M;
+    if (mode == 1) {
+        for (int idx = threadIdx.x; idx < cc * M; idx += kBlock) cspec[base + idx] = buf[lds_slot(idx)];
+        return;
+    }
+    for (int idx = threadIdx.x; idx < cc * M; idx += kBlock) {
+        float2 h = Hs[base + idx];
+        if (conj_h) h = cconj(h);
+        buf[lds_slot(idx)] = cscale(cmul(buf[lds_slot(idx)], h), inv);
+    }
+    __syncthreads();
+    lds_fft<1, FC_EPT>(buf, fd, cc, seq_shift, tw);
+    for (int idx = threadIdx.x; idx < cc * M; idx += kBlock) {
+        const int q = idx / M;
+        T[(size_t)(k0 + q) * ts + (idx - q * M)] = buf[lds_slot(idx)];
+    }
+}
+
+// Inverse rows pass over row pairs pair0 + blk*G + g; output (Y, X) of the M
+// grid inside [oy, oy + D) x [ox, ox + D) goes to dst[Y - oy][X - ox]:
+// g ? g - v (squared-norm partial per workgroup) : (accum ? dst + v : v).
+__global__ __launch_bounds__(kBlock) void fc_rows_inv_kernel(const float2* __restrict__ T, int M, int ts,
+                                                             FftDesc fd, const float2* __restrict__ tw, int G,
+                                                             int seq_shift, int pair0, int pair_end, int oy, int ox,
+                                                             int D, float* __restrict__ dst,
+                                                             const float* __restrict__ g, int accum,
+                                                             double* __restrict__ partials) {
+    extern __shared__ float2 buf[];
+    __shared__ double red[kBlock / 64];
+    const int pb = pair0 + blockIdx.x * G;
+    const int half = M / 2 + 1;
+    for (int idx = threadIdx.x; idx < G * half; idx += kBlock) {
+        const int k = idx / G;
+        const int gg = idx - k * G;
+        float2 Xa = make_float2(0.0f, 0.0f), Xb = Xa;
+        if (pb + gg < pair_end) {
+            const float4 q = *reinterpret_cast<const float4*>(T + (size_t)k * ts + 2 * (pb + gg));
+            Xa = make_float2(q.x, q.y);
+            Xb = make_float2(q.z, q.w);
+        }
+        const bool edge = (k == 0) || (2 * k == M);
+        if (edge) {
+            Xa.y = 0.0f;
+            Xb.y = 0.0f;
+        }
+        buf[lds_slot(gg * M + k)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
+        if (!edge) buf[lds_slot(gg * M + M - k)] = make_float2(Xa.x + Xb.y, -Xa.y + Xb.x);
+    }
+    __syncthreads();
+    lds_fft<1, FC_EPT>(buf, fd, G, seq_shift, tw);
+    double ss = 0.0;
+    for (int idx = threadIdx.x; idx < G * M; idx += kBlock) {
+        const int gg = idx / M;
+        const int X = idx - gg * M;
+        if (pb + gg >= pair_end) continue;
+        const int x = X - ox;
+        if (x < 0 || x >= D) continue;
+        const float2 v = buf[lds_slot(idx)];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int y = 2 * (pb + gg) + h - oy;
+            if (y < 0 || y >= D) continue;
+            const size_t o = (size_t)y * D + x;
+            float val = h == 0 ? v.x : v.y;
+            if (g) {
+                val = g[o] - val;
+                ss += (double)val * (double)val;
+            } else if (accum) {
+                val = dst[o] + val;
+            }
+            dst[o] = val;
+        }
+    }
+    if (partials) {
+        const double t = block_sum(ss, red);
+        if (threadIdx.x == 0) partials[blockIdx.x] = t;
+    }
+}
+
+// ---- launchers ------------------------------------------------------------
+
+static hipError_t fc_rows_fwd(const FftConv& c, const float* src, int S, int off, int y_lo, int y_hi,
+                              hipStream_t s) {
+    const int G = fc_pairs_per_block(c.M);
+    const int p0 = y_lo / 2, p1 = (y_hi + 1) / 2;
+    const int blocks = (p1 - p0 + G - 1) / G;
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fc_rows_fwd_kernel, dim3(blocks), dim3(kBlock), lds_bytes(G * c.M, c.M), s, src, S, off, c.M,
+                       c.T, c.ts, c.fd, c.tw, G, fc_seq_shift(G), p0, p1);
+    return hipGetLastError();
+}
+
+static hipError_t fc_cols(const FftConv& c, int conj_h, int y_lo, int y_hi, int mode, float2* cspec, hipStream_t s) {
+    const int CC = fc_cols_per_block(c.M);
+    const int half = c.M / 2 + 1;
+    const float inv = (float)(1.0 / ((double)c.M * (double)c.M));
+    hipLaunchKernelGGL(fc_cols_kernel, dim3((half + CC - 1) / CC), dim3(kBlock), lds_bytes(CC * c.M, c.M), s, c.T,
+                       c.M, c.ts, (const float2*)c.H, conj_h, inv, y_lo, y_hi, mode, cspec, c.fd, c.tw, CC,
+                       fc_seq_shift(CC));
+    return hipGetLastError();
+}
+
+static hipError_t fc_rows_inv(const FftConv& c, int oy, int ox, int D, float* dst, const float* g, int accum,
+                              double* partials, int* n_partials, hipStream_t s) {
+    const int G = fc_pairs_per_block(c.M);
+    const int p0 = oy / 2, p1 = (oy + D + 1) / 2;
+    const int blocks = (p1 - p0 + G - 1) / G;
+    if (n_partials) *n_partials = blocks;
+    hipLaunchKernelGGL(fc_rows_inv_kernel, dim3(blocks), dim3(kBlock), lds_bytes(G * c.M, c.M), s, (const float2*)c.T,
+                       c.M, c.ts, c.fd, c.tw, G, fc_seq_shift(G), p0, p1, oy, ox, D, dst, g, accum, partials);
+    return hipGetLastError();
+}
+
+int fftconv_partials_count(int M, int n) {
+    const int G = fc_pairs_per_block(M);
+    return (n / 2 + 1 + G) / G + 1;
+}
+
+hipError_t launch_fftconv_spectrum(const FftConv& c, const float* psf, int p, hipStream_t s) {
+    hipError_t e = fc_rows_fwd(c, psf, p, 0, 0, p, s);
+    if (e != hipSuccess) return e;
+    return fc_cols(c, 0, 0, p, 1, c.H, s);
+}
+
+hipError_t launch_fftconv_blur(const FftConv& c, const float* u, int n, int p, const float* g, float* r,
+                               double* partials, int* n_partials, hipStream_t s) {
+    const int N = n + p - 1;
+    hipError_t e = fc_rows_fwd(c, u, N, 0, 0, N, s);
+    if (e == hipSuccess) e = fc_cols(c, 0, 0, N, 0, nullptr, s);
+    if (e == hipSuccess) e = fc_rows_inv(c, p - 1, p - 1, n, r, g, 0, g ? partials : nullptr, n_partials, s);
+    return e;
+}
+
+hipError_t launch_fftconv_blurT(const FftConv& c, const float* t, int n, int p, float* w, int accum, hipStream_t s) {
+    const int N = n + p - 1;
+    hipError_t e = fc_rows_fwd(c, t, n, p - 1, p - 1, N, s);
+    if (e == hipSuccess) e = fc_cols(c, 1, p - 1, N, 0, nullptr, s);
+    if (e == hipSuccess) e = fc_rows_inv(c, 0, 0, N, w, nullptr, accum, nullptr, nullptr, s);
+    return e;
+}
+
+}  // namespace mlba

@@ -145,6 +145,26 @@ hipError_t launch_fold_batched(const BatchImage* imgs, const int* bmap, const in
 // positions of the (n+2c)^2 padded grid that copy pixel (y, x).
 hipError_t launch_fold_reflect(const float* wext, int m, float* w, int n, int c, hipStream_t s, int accum = 0);
 
+// ---- blur by FFTs (rectangular model) -------------------------------------
+// M x M grid, M >= N = n + p - 1, M = 2^a 3^b <= fftconv_max_size(); T: half
+// spectrum workspace [M/2+1][ts], H: spectrum of the PSF at the origin
+// (dense [M/2+1][M]).
+struct FftConv {
+    int M, ts;
+    FftDesc fd;
+    const float2* tw;
+    float2* T;
+    float2* H;
+};
+int fftconv_max_size();
+int fftconv_partials_count(int M, int n);
+hipError_t launch_fftconv_spectrum(const FftConv& c, const float* psf, int p, hipStream_t s);
+// r = g - A u (partials: squared-norm per workgroup, count in *n_partials) or y = A u (g null)
+hipError_t launch_fftconv_blur(const FftConv& c, const float* u, int n, int p, const float* g, float* r,
+                               double* partials, int* n_partials, hipStream_t s);
+// w = A^T t, or w += A^T t (accum)
+hipError_t launch_fftconv_blurT(const FftConv& c, const float* t, int n, int p, float* w, int accum, hipStream_t s);
+
 // ---- framelet -----------------------------------------------------------
 // analysis level with dilation d: bands (+)= B_i B_j v, low (+)= B_0 B_0 v
 hipError_t launch_analysis_level(const float* v, int N, int d, float* zlev, float* low,

@@ -79,6 +79,10 @@ size_t NN(const mlba_plan_s* P) { return (size_t)P->N * P->N; }
 // r = g - A u (g may be null: y = A u); partial sums of r^2 into P->partials
 int do_blur(mlba_plan_s* P, const float* u, const float* g, float* y, bool want_norm, int* nparts,
             hipStream_t s) {
+    if (P->blur_fft) {
+        HIPCHK(launch_fftconv_blur(P->fc, u, P->n, P->p, g, y, want_norm ? P->partials : nullptr, nparts, s));
+        return MLBA_OK;
+    }
     BatchImage d = plan_desc(P);
     d.u = const_cast<float*>(u);
     d.g = g;
@@ -89,6 +93,10 @@ int do_blur(mlba_plan_s* P, const float* u, const float* g, float* y, bool want_
 
 // w = A^T y (+ fold of the reflective padding)
 int do_blurT(mlba_plan_s* P, const float* y, float* w, hipStream_t s) {
+    if (P->blur_fft) {
+        HIPCHK(launch_fftconv_blurT(P->fc, y, P->n, P->p, w, 0, s));
+        return MLBA_OK;
+    }
     BatchImage d = plan_desc(P);
     d.t = const_cast<float*>(y);
     d.w = w;
@@ -227,6 +235,10 @@ int do_shrink_synthesis(mlba_plan_s* P, const float* omega, float* f, const floa
 
 // omega += A^T y (implicit state: the Bregman update of eq. (MLBA2) before W)
 int do_blurT_acc(mlba_plan_s* P, const float* y, float* omega, hipStream_t s) {
+    if (P->blur_fft) {
+        HIPCHK(launch_fftconv_blurT(P->fc, y, P->n, P->p, omega, 1, s));
+        return MLBA_OK;
+    }
     BatchImage d = plan_desc(P);
     d.t = const_cast<float*>(y);
     d.w = omega;
@@ -439,7 +451,127 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
 int mlba_plan_set_psf(mlba_plan_t P, const float* psf, hipStream_t s) {
     if (!P || !psf) return MLBA_EINVAL;
     HIPCHK(hipMemcpyAsync(P->psf, psf, (size_t)P->p * P->p * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if (P->fc.H) HIPCHK(launch_fftconv_spectrum(P->fc, P->psf, P->p, s));
     return compute_spectrum(P, s);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Smallest M = 2^a 3^b (a >= 1) with M >= N, or 0 above the transform limit.
+int fft_grid_size(int N) {
+    int best = 0;
+    for (int a = 1; (1 << a) <= fftconv_max_size(); ++a)
+        for (long m = 1L << a; m <= fftconv_max_size(); m *= 3)
+            if (m >= N && (best == 0 || m < best)) best = (int)m;
+    return best;
+}
+
+// Allocates the FFT blur of a rectangular plan (first use) and computes the
+// PSF spectrum on that grid.
+int ensure_fftconv(mlba_plan_s* P, hipStream_t s) {
+    if (P->fc.H) return MLBA_OK;
+    if (P->bc != MLBA_BC_RECT) return MLBA_EUNSUPPORTED;
+    const int M = fft_grid_size(P->N);
+    if (M == 0) return MLBA_EUNSUPPORTED;
+    if (fftconv_partials_count(M, P->n) > P->partials_cap) return MLBA_EUNSUPPORTED;
+    FftConv c{};
+    c.M = M;
+    c.ts = M + 16;
+    int a2 = 0, b3 = 0;
+    factor_23(M, &a2, &b3);
+    c.fd.n = M;
+    c.fd.nst = 0;
+    int a = a2;
+    while (a >= 3) {
+        c.fd.radix[c.fd.nst++] = 8;
+        a -= 3;
+    }
+    if (a == 2) c.fd.radix[c.fd.nst++] = 4;
+    if (a == 1) c.fd.radix[c.fd.nst++] = 2;
+    for (int i = 0; i < b3; ++i) c.fd.radix[c.fd.nst++] = 3;
+    std::vector<float2> tw(M);
+    const double pi = 3.14159265358979323846;
+    for (int q = 0; q < M; ++q) {
+        const double ang = -2.0 * pi * (double)q / (double)M;
+        tw[q] = make_float2((float)cos(ang), (float)sin(ang));
+    }
+    float2 *twd = nullptr, *T = nullptr, *H = nullptr;
+    STCHK(dalloc_t(P, &twd, (size_t)M));
+    STCHK(dalloc_t(P, &T, (size_t)(M / 2 + 1) * c.ts));
+    STCHK(dalloc_t(P, &H, (size_t)(M / 2 + 1) * M));
+    HIPCHK(hipMemcpyAsync(twd, tw.data(), M * sizeof(float2), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));  // the host table goes out of scope
+    c.tw = twd;
+    c.T = T;
+    c.H = H;
+    HIPCHK(launch_fftconv_spectrum(c, P->psf, P->p, s));
+    P->fc = c;
+    return MLBA_OK;
+}
+
+// mean ms of `reps` calls of f after one untimed call
+template <class F>
+int time_ms(F f, int reps, hipStream_t s, double* ms) {
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    hipError_t err = hipEventCreate(&e1);
+    if (err != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        mlba_internal_set_hip(err);
+        return MLBA_EHIP;
+    }
+    int st = f();
+    if (st >= 0) {
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps && st >= 0; ++r) st = f();
+        (void)hipEventRecord(e1, s);
+        err = hipEventSynchronize(e1);
+        float t = 0.0f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+        if (err != hipSuccess) {
+            mlba_internal_set_hip(err);
+            st = MLBA_EHIP;
+        }
+        *ms = (double)t / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mlba_plan_set_blur(mlba_plan_t P, int mode, hipStream_t s) {
+    if (!P || mode < MLBA_BLUR_DIRECT || mode > MLBA_BLUR_FFT) return MLBA_EINVAL;
+    if (mode == MLBA_BLUR_FFT) STCHK(ensure_fftconv(P, s));
+    P->blur_fft = mode == MLBA_BLUR_FFT ? 1 : 0;
+    return MLBA_OK;
+}
+
+int mlba_plan_autotune(mlba_plan_t P, int reps, double* ms_out, hipStream_t s) {
+    if (!P || reps < 1) return MLBA_EINVAL;
+    double t[2][2] = {{0.0, 0.0}, {-1.0, -1.0}};  // [direct / fft][A / A^T]
+    const int keep = P->blur_fft;
+    const int have_fft = P->bc == MLBA_BC_RECT ? ensure_fftconv(P, s) : MLBA_EUNSUPPORTED;
+    if (have_fft < 0 && have_fft != MLBA_EUNSUPPORTED) return have_fft;
+    for (int mode = 0; mode < (have_fft == MLBA_OK ? 2 : 1); ++mode) {
+        P->blur_fft = mode;
+        // scratch only: u -> r and t -> w of the plan
+        int st = time_ms([&]() { return do_blur(P, P->u, nullptr, P->r, false, nullptr, s); }, reps, s, &t[mode][0]);
+        if (st >= 0) st = time_ms([&]() { return do_blurT(P, P->t, P->w, s); }, reps, s, &t[mode][1]);
+        if (st < 0) {
+            P->blur_fft = keep;
+            return st;
+        }
+    }
+    P->blur_fft = (have_fft == MLBA_OK && t[1][0] + t[1][1] < t[0][0] + t[0][1]) ? 1 : 0;
+    if (ms_out)
+        for (int i = 0; i < 4; ++i) ms_out[i] = t[i / 2][i % 2];
+    return P->blur_fft ? MLBA_BLUR_FFT : MLBA_BLUR_DIRECT;
 }
 
 int mlba_plan_destroy(mlba_plan_t P) {

@@ -29,6 +29,8 @@ struct mlba_plan_s {
     mlba::FftDesc fd{};
     int ts = 0;                // row stride of the transposed spectral workspace
     int conv_rows[2] = {0, 0}; // output rows per thread of the A / A^T blur (0: by occupancy)
+    int blur_fft = 0;          // rectangular model: A and A^T by FFTs of an M x M grid
+    mlba::FftConv fc{};        // its plan and buffers (allocated on first use)
     float* psf = nullptr;
     float* spec = nullptr;     // BCCB: [n/2+1][n] |Lambda|^2 (transposed); DCT: [n][n] lambda^2
     float2* lamc = nullptr;    // square models, BCCB: Lambda_c of the centred PSF (layout of spec)

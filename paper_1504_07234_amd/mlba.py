@@ -17,6 +17,7 @@ from ._lib import check
 RECT, REFLECT, PERIODIC, ZERO = _lib.BC_RECT, _lib.BC_REFLECT, _lib.BC_PERIODIC, _lib.BC_ZERO
 BCCB, DCT, NONE = _lib.PRECOND_BCCB, _lib.PRECOND_DCT, _lib.PRECOND_NONE
 MLBA, ALG4 = _lib.METHOD_MLBA, _lib.METHOD_ALG4
+BLUR_DIRECT, BLUR_FFT = _lib.BLUR_DIRECT, _lib.BLUR_FFT
 
 
 def _stream(stream=None) -> ctypes.c_void_p:
@@ -92,6 +93,17 @@ class Plan:
         psf = psf.contiguous()
         check(self._lib.mlba_plan_set_psf(self._h, _dev(psf, "psf", (self.p, self.p)), _stream(stream)),
               "mlba_plan_set_psf")
+
+    def set_blur(self, mode: int, stream=None):
+        """BLUR_DIRECT or BLUR_FFT for A and A^T (rectangular model)."""
+        check(self._lib.mlba_plan_set_blur(self._h, int(mode), _stream(stream)), "mlba_plan_set_blur")
+
+    def autotune(self, reps: int = 5, stream=None) -> dict:
+        """Times the direct and the FFT blur and keeps the faster (see mlba_plan_autotune)."""
+        ms = (ctypes.c_double * 4)()
+        mode = check(self._lib.mlba_plan_autotune(self._h, int(reps), ms, _stream(stream)), "mlba_plan_autotune")
+        return {"blur": "fft" if mode == _lib.BLUR_FFT else "direct",
+                "direct_ms": [ms[0], ms[1]], "fft_ms": [ms[2], ms[3]] if ms[2] >= 0 else None}
 
     def opnorm(self, alpha: float, iters: int = 50, stream=None) -> float:
         out = ctypes.c_double()
