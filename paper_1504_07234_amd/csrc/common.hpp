@@ -54,6 +54,26 @@ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8), each with its own L2.  Renumbering so that every XCD processes one
+// contiguous range of logical blocks keeps neighbouring blocks (which share
+// cache lines or halos) in the same L2.  A bijection of [0, nb).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int per = nb / kXcds, rem = nb % kXcds;
+    const int x = b % kXcds, s = b / kXcds;
+    return x * per + min(x, rem) + s;
+}
+
+// The (x, y) tile of a 2-D grid after the XCD renumbering of the linear block
+// index (row-major tiles: each XCD takes a band of consecutive tile rows).
+__device__ __forceinline__ void xcd_tile(int* bx, int* by) {
+    const int gx = (int)gridDim.x;
+    const int l = xcd_block((int)(blockIdx.y * gridDim.x + blockIdx.x), (int)(gridDim.x * gridDim.y));
+    *by = l / gx;
+    *bx = l - *by * gx;
+}
+
 // Wave-level then workgroup-level sum of a double (blockDim.x == kBlock).
 __device__ __forceinline__ double block_sum(double v, double* smem /* >= kBlock/64 */) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

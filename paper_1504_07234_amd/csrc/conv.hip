@@ -164,7 +164,9 @@ template <int P, bool FLIP, int RY>
 __global__ __launch_bounds__(kBlock) void conv_kernel(ConvJob j, double* __restrict__ partials) {
     __shared__ float tile[conv_lds_floats(P, RY)];
     __shared__ double red[kBlock / 64];
-    const double ss = conv_tile<P, FLIP, RY>(j, blockIdx.x, blockIdx.y, tile);
+    int bx, by;
+    xcd_tile(&bx, &by);
+    const double ss = conv_tile<P, FLIP, RY>(j, bx, by, tile);
     if (partials) conv_partial(ss, red, partials + blockIdx.y * gridDim.x + blockIdx.x);
 }
 
@@ -172,7 +174,9 @@ __global__ __launch_bounds__(kBlock) void conv_kernel_generic(ConvJob j, int P, 
                                                               double* __restrict__ partials) {
     extern __shared__ float smem[];
     __shared__ double red[kBlock / 64];
-    const double ss = conv_tile_generic(j, P, flip, blockIdx.x, blockIdx.y, smem);
+    int bx, by;
+    xcd_tile(&bx, &by);
+    const double ss = conv_tile_generic(j, P, flip, bx, by, smem);
     if (partials) conv_partial(ss, red, partials + blockIdx.y * gridDim.x + blockIdx.x);
 }
 

@@ -356,7 +356,7 @@ __global__ __launch_bounds__(kBlock) void fft_rows_r2c_kernel(const float* __res
                                                               float2* __restrict__ T, int ts, FftDesc fd,
                                                               const float2* __restrict__ tw, int G, int seq_shift) {
     extern __shared__ float2 buf[];
-    fft_rows_r2c_body(src, n, T, ts, fd, tw, G, seq_shift, blockIdx.x, buf);
+    fft_rows_r2c_body(src, n, T, ts, fd, tw, G, seq_shift, xcd_block(blockIdx.x, gridDim.x), buf);
 }
 
 __global__ __launch_bounds__(kBlock) void fft_cols_kernel(float2* __restrict__ T, int n, int ts,
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(kBlock) void fft_rows_c2r_kernel(const float2* __re
                                                               const float2* __restrict__ tw, int G, int seq_shift,
                                                               int accum) {
     extern __shared__ float2 buf[];
-    fft_rows_c2r_body(T, n, ts, dst, fd, tw, G, seq_shift, blockIdx.x, buf, accum);
+    fft_rows_c2r_body(T, n, ts, dst, fd, tw, G, seq_shift, xcd_block(blockIdx.x, gridDim.x), buf, accum);
 }
 
 __global__ __launch_bounds__(kBlock) void dct_rows_fwd_kernel(const float* __restrict__ src, int n,
@@ -385,7 +385,7 @@ __global__ __launch_bounds__(kBlock) void dct_rows_fwd_kernel(const float* __res
                                                               const float2* __restrict__ tw,
                                                               const float2* __restrict__ dtw, int G, int seq_shift) {
     extern __shared__ float2 buf[];
-    dct_rows_fwd_body(src, n, Tr, ts, fd, tw, dtw, G, seq_shift, blockIdx.x, buf);
+    dct_rows_fwd_body(src, n, Tr, ts, fd, tw, dtw, G, seq_shift, xcd_block(blockIdx.x, gridDim.x), buf);
 }
 
 __global__ __launch_bounds__(kBlock) void dct_cols_filter_kernel(float* __restrict__ Tr, int n, int ts,
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void dct_rows_inv_kernel(const float* __res
                                                               const float2* __restrict__ dtw, int G, int seq_shift,
                                                               int accum) {
     extern __shared__ float2 buf[];
-    dct_rows_inv_body(Tr, n, ts, dst, fd, tw, dtw, G, seq_shift, blockIdx.x, buf, accum);
+    dct_rows_inv_body(Tr, n, ts, dst, fd, tw, dtw, G, seq_shift, xcd_block(blockIdx.x, gridDim.x), buf, accum);
 }
 
 // lambda of the reflective blur of the symmetrised PSF:

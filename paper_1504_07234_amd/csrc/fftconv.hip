@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kBlock) void fc_rows_fwd_kernel(const float* __rest
                                                              const float2* __restrict__ tw, int G, int seq_shift,
                                                              int pair0, int pair_end) {
     extern __shared__ float2 buf[];
-    const int pb = pair0 + blockIdx.x * G;
+    const int pb = pair0 + xcd_block(blockIdx.x, gridDim.x) * G;
     for (int idx = threadIdx.x; idx < G * M; idx += kBlock) {
         const int g = idx / M;
         const int X = idx - g * M;
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void fc_rows_inv_kernel(const float2* __res
                                                              double* __restrict__ partials) {
     extern __shared__ float2 buf[];
     __shared__ double red[kBlock / 64];
-    const int pb = pair0 + blockIdx.x * G;
+    const int pb = pair0 + xcd_block(blockIdx.x, gridDim.x) * G;
     const int half = M / 2 + 1;
     for (int idx = threadIdx.x; idx < G * half; idx += kBlock) {
         const int k = idx / G;
