@@ -17,9 +17,10 @@ Modules
   precond   spectral Tikhonov preconditioners (Algorithms 1 and 3)
   mlba      soft threshold, the iteration (MLBA2), schedules, ||A^T P A||
   adjoint   reverse-mode gradient of K unrolled iterations
+  alg2      Algorithm 2, the PCG-approximated preconditioner (section 4.2)
   alg4      Algorithm 4 and Algorithm 4-NS (section 5)
 """
-from . import adjoint, alg4, blur, framelet, precond, mlba  # noqa: F401
+from . import adjoint, alg2, alg4, blur, framelet, precond, mlba  # noqa: F401
 
 RECT, REFLECT, PERIODIC, ZERO = blur.RECT, blur.REFLECT, blur.PERIODIC, blur.ZERO
 BCCB, DCT, NONE = precond.BCCB, precond.DCT, precond.NONE
