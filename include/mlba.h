@@ -98,6 +98,13 @@ typedef struct mlba_alpha_schedule {
  * with MLBA_BC_RECT return MLBA_EUNSUPPORTED), preconditioner BCCB or DCT. */
 #define MLBA_METHOD_MLBA 0
 #define MLBA_METHOD_ALG4 1
+/* ALG2: eq. (Alg2), z += W A^T t with t ~ (A A^T + alpha I)^{-1} r from
+ * beta_n = min{pcg_max, beta_tol} steps of CG preconditioned by the plan's
+ * (C C^T + alpha I)^{-1} (BCCB or DCT), started from zero; beta_tol is the first
+ * step whose preconditioned relative residual sqrt(res^T M^-1 res / r^T M^-1 r)
+ * is at most pcg_tol (eq. bet; the paper: 5 and 1e-3).  One scalar is read
+ * back per CG step. */
+#define MLBA_METHOD_ALG2 2
 
 /* Discrepancy-principle stop, eq. (discrpr): stop at the first k with
  * ||r^k|| <= gamma * noise_norm.  Checked every `check_every` iterations
@@ -127,6 +134,9 @@ typedef struct mlba_params {
     int method;                /* MLBA_METHOD_MLBA or MLBA_METHOD_ALG4          */
     double* alpha_out;         /* host, optional: the alpha_k of each iteration run
                                   (iters values; synchronous copy at the end)   */
+    int pcg_max;               /* MLBA_METHOD_ALG2: step cap (0: 5)            */
+    double pcg_tol;            /* MLBA_METHOD_ALG2: tolerance (0: 1e-3)         */
+    int* pcg_steps_out;        /* host, optional: beta_n of each iteration run  */
 } mlba_params;
 
 /* State kept between iterations.  Explicit: the frame coefficients z

@@ -17,7 +17,7 @@ OK, WARN_DIVERGED, EINVAL, EUNSUPPORTED, EHIP, ENOMEM = 0, 1, -1, -2, -3, -4
 BC_RECT, BC_REFLECT, BC_PERIODIC, BC_ZERO = 0, 1, 2, 3
 PRECOND_BCCB, PRECOND_DCT, PRECOND_NONE = 0, 1, 2
 ALPHA_CONST, ALPHA_GEOMETRIC, ALPHA_TABLE, ALPHA_NS = 0, 1, 2, 3
-METHOD_MLBA, METHOD_ALG4 = 0, 1
+METHOD_MLBA, METHOD_ALG4, METHOD_ALG2 = 0, 1, 2
 BLUR_DIRECT, BLUR_FFT = 0, 1
 STATE_EXPLICIT, STATE_IMPLICIT = 0, 1
 
@@ -43,7 +43,8 @@ class BatchTuning(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("alpha", AlphaSchedule), ("mu", c_dbl_p), ("n_mu", c_int), ("delta", c_double),
                 ("delta_table", c_dbl_p), ("iters", c_int), ("k0", c_int),
-                ("stop", ctypes.POINTER(Stop)), ("state", c_int), ("method", c_int), ("alpha_out", c_dbl_p)]
+                ("stop", ctypes.POINTER(Stop)), ("state", c_int), ("method", c_int), ("alpha_out", c_dbl_p),
+                ("pcg_max", c_int), ("pcg_tol", c_double), ("pcg_steps_out", c_int_p)]
 
 
 # name -> (restype, argtypes); every symbol declared in include/mlba.h

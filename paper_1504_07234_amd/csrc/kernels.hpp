@@ -296,6 +296,13 @@ hipError_t launch_scale(float* x, size_t count, const double* inv_norm_sq_or_nul
 hipError_t launch_fill_hash(float* x, size_t count, unsigned seed, hipStream_t s);
 hipError_t launch_fill(float* x, size_t count, float value, hipStream_t s);
 int reduce_partials_cap();
+// preconditioned CG of Algorithm 2: t += a d, res -= a q with a = *rho / *pq
+hipError_t launch_pcg_update(float* t, float* res, const float* d, const float* q, size_t count, const double* rho,
+                             const double* pq, hipStream_t s);
+// d = z + (*rho_new / *rho) d
+hipError_t launch_pcg_dir(float* d, const float* z, size_t count, const double* rho_new, const double* rho,
+                          hipStream_t s);
+hipError_t launch_axpy(float* y, const float* x, size_t count, float a, hipStream_t s);  // y += a x
 // rn[image][k] = sum of that image's residual-norm partials (one workgroup per image)
 hipError_t launch_sum_partials_batched(const BatchImage* imgs, const double* partials, const int* pcount,
                                        int count, int k, hipStream_t s);

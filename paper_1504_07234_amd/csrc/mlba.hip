@@ -250,6 +250,52 @@ int do_blurT_acc(mlba_plan_s* P, const float* y, float* omega, hipStream_t s) {
     return MLBA_OK;
 }
 
+// Algorithm 2: P->pcg[0 .. n^2) <- t ~ (A A^T + alpha I)^{-1} r (r = P->r, used
+// as the CG residual and overwritten) by preconditioned CG from t = 0, at most
+// max_steps steps, stopping at the first step with sqrt(rho_j / rho_0) <= tol,
+// rho_j = res_j^T M^{-1} res_j (eq. bet).  *steps_out = beta_n.
+int do_pcg(mlba_plan_s* P, double alpha, int max_steps, double tol, int* steps_out, hipStream_t s) {
+    const size_t nn = (size_t)P->n * P->n;
+    float* t = P->pcg;
+    float* zc = P->pcg + nn;
+    float* d = P->pcg + 2 * nn;
+    float* q = P->pcg + 3 * nn;
+    float* res = P->r;
+    double* rho[2] = {P->pcgs, P->pcgs + 1};
+    double* pq = P->pcgs + 2;
+    int np = 0;
+    HIPCHK(launch_fill(t, nn, 0.0f, s));
+    STCHK(do_precond(P, res, zc, alpha, s));
+    HIPCHK(hipMemcpyAsync(d, zc, nn * sizeof(float), hipMemcpyDeviceToDevice, s));
+    HIPCHK(launch_dot_partials(res, zc, nn, P->partials, &np, s));
+    HIPCHK(launch_sum_partials(P->partials, np, rho[0], s));
+    double rho0 = 0.0;
+    HIPCHK(hipMemcpyAsync(&rho0, rho[0], sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *steps_out = 0;
+    if (!(rho0 > 0.0)) return MLBA_OK;  // r = 0: t = 0
+    for (int j = 1; j <= max_steps; ++j) {
+        double* rc = rho[(j - 1) & 1];
+        double* rn = rho[j & 1];
+        STCHK(do_blurT(P, d, P->w, s));                 // q = (A A^T + alpha I) d
+        STCHK(do_blur(P, P->w, nullptr, q, false, nullptr, s));
+        HIPCHK(launch_axpy(q, d, nn, (float)alpha, s));
+        HIPCHK(launch_dot_partials(d, q, nn, P->partials, &np, s));
+        HIPCHK(launch_sum_partials(P->partials, np, pq, s));
+        HIPCHK(launch_pcg_update(t, res, d, q, nn, rc, pq, s));
+        STCHK(do_precond(P, res, zc, alpha, s));
+        HIPCHK(launch_dot_partials(res, zc, nn, P->partials, &np, s));
+        HIPCHK(launch_sum_partials(P->partials, np, rn, s));
+        double rho_j = 0.0;
+        HIPCHK(hipMemcpyAsync(&rho_j, rn, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        *steps_out = j;
+        if (sqrt(rho_j / rho0) <= tol || j == max_steps) break;
+        HIPCHK(launch_pcg_dir(d, zc, nn, rn, rc, s));
+    }
+    return MLBA_OK;
+}
+
 int expand_mu(const mlba_plan_s* P, const double* mu, int n_mu, float* out) {
     if (!mu || (n_mu != 1 && n_mu != P->bands)) return MLBA_EINVAL;
     for (int b = 0; b < P->bands; ++b) {
@@ -383,6 +429,10 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
     ALLOC(P->scal, 8);
     ALLOC(P->rn, (size_t)P->rn_cap);
     ALLOC(P->ahist, (size_t)P->rn_cap);
+    if (precond != MLBA_PRECOND_NONE) {
+        ALLOC(P->pcg, 4 * obs);
+        ALLOC(P->pcgs, 8);
+    }
     if (bc == MLBA_BC_REFLECT) ALLOC(P->wext, (size_t)m * m);
 
     if (precond != MLBA_PRECOND_NONE) {
@@ -680,8 +730,13 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
     if (stop && (stop->check_every < 1 || !(stop->noise_norm >= 0.0))) return MLBA_EINVAL;
     if (prm->state != MLBA_STATE_EXPLICIT && prm->state != MLBA_STATE_IMPLICIT) return MLBA_EINVAL;
     const bool implicit = prm->state == MLBA_STATE_IMPLICIT;
-    if (prm->method != MLBA_METHOD_MLBA && prm->method != MLBA_METHOD_ALG4) return MLBA_EINVAL;
+    if (prm->method < MLBA_METHOD_MLBA || prm->method > MLBA_METHOD_ALG2) return MLBA_EINVAL;
     const bool alg4 = prm->method == MLBA_METHOD_ALG4;
+    const bool alg2 = prm->method == MLBA_METHOD_ALG2;
+    if (alg2 && P->precond == MLBA_PRECOND_NONE) return MLBA_EUNSUPPORTED;
+    const int pcg_max = prm->pcg_max > 0 ? prm->pcg_max : 5;
+    const double pcg_tol = prm->pcg_tol > 0.0 ? prm->pcg_tol : 1e-3;
+    if (alg2 && (pcg_max > 1000 || !isfinite(pcg_tol))) return MLBA_EINVAL;
     if (alg4 && (P->bc == MLBA_BC_RECT || P->precond == MLBA_PRECOND_NONE)) return MLBA_EUNSUPPORTED;
     const bool ns = as.kind == MLBA_ALPHA_NS;
     mlba_stop ns_stop{};
@@ -794,6 +849,24 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
             if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_BLUR_T], s));
             if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_ANALYSIS], s));
             if (!implicit) STCHK(do_analysis(P, P->t, z, true, s));
+            if (ev) HIPCHK(hipEventRecord(ev[MLBA_NPHASES], s));
+            done = i + 1;
+            continue;
+        }
+        if (alg2) {
+            int steps = 0;
+            STCHK(do_pcg(P, alpha[i], pcg_max, pcg_tol, &steps, s));
+            if (prm->pcg_steps_out) prm->pcg_steps_out[i] = steps;
+            if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_BLUR_T], s));
+            float* tsol = P->pcg;  // the CG solution t
+            if (implicit) {
+                STCHK(do_blurT_acc(P, tsol, z, s));
+                if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_ANALYSIS], s));
+            } else {
+                STCHK(do_blurT(P, tsol, P->w, s));
+                if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_ANALYSIS], s));
+                STCHK(do_analysis(P, P->w, z, true, s));
+            }
             if (ev) HIPCHK(hipEventRecord(ev[MLBA_NPHASES], s));
             done = i + 1;
             continue;

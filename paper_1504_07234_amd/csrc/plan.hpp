@@ -37,6 +37,8 @@ struct mlba_plan_s {
     float* lamr = nullptr;     // square models, DCT: lambda (layout of spec)
     double* ns = nullptr;      // Algorithm 4-NS device state
     double* ahist = nullptr;   // alpha_k used (ring like rn)
+    float* pcg = nullptr;      // Algorithm 2: t, z, d, q (n x n each)
+    double* pcgs = nullptr;    // Algorithm 2 scalars: rho (two slots), pq, rho0
     float2* tw = nullptr;      // exp(-2 pi i q / n)
     float2* dtw = nullptr;     // exp(-i pi k / (2n))
     float* costab = nullptr;   // cos(pi q / n), q < 2n

@@ -116,4 +116,58 @@ hipError_t launch_fill(float* x, size_t count, float value, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ---- preconditioned CG of Algorithm 2 (device scalars, no host round trip) ----
+// t += a d, res -= a q with a = rho / pq (both device doubles)
+__global__ __launch_bounds__(kBlock) void pcg_update_kernel(float* __restrict__ t, float* __restrict__ res,
+                                                            const float* __restrict__ d, const float* __restrict__ q,
+                                                            size_t count, const double* __restrict__ rho,
+                                                            const double* __restrict__ pq) {
+    const float a = (float)(*rho / *pq);
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (size_t)gridDim.x * kBlock) {
+        t[i] = fmaf(a, d[i], t[i]);
+        res[i] = fmaf(-a, q[i], res[i]);
+    }
+}
+
+// d = z + (rho_new / rho) d
+__global__ __launch_bounds__(kBlock) void pcg_dir_kernel(float* __restrict__ d, const float* __restrict__ z,
+                                                         size_t count, const double* __restrict__ rho_new,
+                                                         const double* __restrict__ rho) {
+    const float b = (float)(*rho_new / *rho);
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (size_t)gridDim.x * kBlock)
+        d[i] = fmaf(b, d[i], z[i]);
+}
+
+// y += a x
+__global__ __launch_bounds__(kBlock) void axpy_kernel(float* __restrict__ y, const float* __restrict__ x, size_t count,
+                                                      float a) {
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (size_t)gridDim.x * kBlock)
+        y[i] = fmaf(a, x[i], y[i]);
+}
+
+static unsigned elementwise_blocks(size_t count) {
+    size_t b = (count + kBlock - 1) / kBlock;
+    if (b > 4096) b = 4096;
+    return (unsigned)(b ? b : 1);
+}
+
+hipError_t launch_pcg_update(float* t, float* res, const float* d, const float* q, size_t count, const double* rho,
+                             const double* pq, hipStream_t s) {
+    hipLaunchKernelGGL(pcg_update_kernel, dim3(elementwise_blocks(count)), dim3(kBlock), 0, s, t, res, d, q, count,
+                       rho, pq);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_dir(float* d, const float* z, size_t count, const double* rho_new, const double* rho,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(pcg_dir_kernel, dim3(elementwise_blocks(count)), dim3(kBlock), 0, s, d, z, count, rho_new,
+                       rho);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy(float* y, const float* x, size_t count, float a, hipStream_t s) {
+    hipLaunchKernelGGL(axpy_kernel, dim3(elementwise_blocks(count)), dim3(kBlock), 0, s, y, x, count, a);
+    return hipGetLastError();
+}
+
 }  // namespace mlba

@@ -16,7 +16,7 @@ from ._lib import check
 
 RECT, REFLECT, PERIODIC, ZERO = _lib.BC_RECT, _lib.BC_REFLECT, _lib.BC_PERIODIC, _lib.BC_ZERO
 BCCB, DCT, NONE = _lib.PRECOND_BCCB, _lib.PRECOND_DCT, _lib.PRECOND_NONE
-MLBA, ALG4 = _lib.METHOD_MLBA, _lib.METHOD_ALG4
+MLBA, ALG4, ALG2 = _lib.METHOD_MLBA, _lib.METHOD_ALG4, _lib.METHOD_ALG2
 BLUR_DIRECT, BLUR_FFT = _lib.BLUR_DIRECT, _lib.BLUR_FFT
 
 
@@ -48,6 +48,7 @@ class RestoreInfo:
     iters_done: int
     rnorm: list
     alphas: list = None
+    pcg_steps: list = None
 
 
 class Plan:
@@ -198,7 +199,7 @@ class Plan:
     def restore(self, g, *, alpha=0.05, alpha_kind: int = _lib.ALPHA_CONST, alpha_ratio: float = 1.0,
                 alpha_floor: float = 0.0, alpha_table=None, mu=1e-3, delta: float = 0.0, delta_table=None,
                 iters: int = 50, k0: int = 0, z=None, out=None, stop=None, track: bool = True,
-                implicit: bool = False, method: int = _lib.METHOD_MLBA, ns=None, stream=None):
+                implicit: bool = False, method: int = _lib.METHOD_MLBA, ns=None, pcg=None, stream=None):
         """Run `iters` iterations of eq. (MLBA2) (method METHOD_MLBA) or eq. (Alg4)
         (METHOD_ALG4, square models); returns (f, RestoreInfo).
 
@@ -206,6 +207,8 @@ class Plan:
         the first Newton start; needs stop=(noise_norm, ., .), whose gamma is
         replaced by tau = (1 + 2 rho) / (1 - 2 rho)).  RestoreInfo.alphas holds the
         alpha_k used.
+        pcg: (max steps, tolerance) of Algorithm 2 (method ALG2; default (5, 1e-3));
+        RestoreInfo.pcg_steps holds beta_n.
 
         implicit: keep the state as omega (z = W omega, one N x N plane) instead
         of the frame coefficients z.
@@ -251,6 +254,10 @@ class Plan:
             prm.alpha.ns_q, prm.alpha.ns_rho = float(ns[0]), float(ns[1])
         aout = (ctypes.c_double * max(1, iters))() if track else None
         prm.alpha_out = ctypes.cast(aout, _lib.c_dbl_p) if track else None
+        if pcg is not None:
+            prm.pcg_max, prm.pcg_tol = int(pcg[0]), float(pcg[1])
+        bout = (ctypes.c_int * max(1, iters))() if track else None
+        prm.pcg_steps_out = ctypes.cast(bout, _lib.c_int_p) if track else None
         zshape = (self.N, self.N) if implicit else (self.bands, self.N, self.N)
         zp = ctypes.c_void_p() if z is None else _dev(z, "z", zshape)
         rn = (ctypes.c_double * max(1, iters))() if track else None
@@ -261,7 +268,8 @@ class Plan:
                                         ctypes.byref(done) if track else None, _stream(stream))
         check(status, "mlba_restore")
         info = RestoreInfo(status, done.value, list(rn[:done.value]) if track else [],
-                           list(aout[:done.value]) if track else [])
+                           list(aout[:done.value]) if track else [],
+                           list(bout[:done.value]) if (track and method == _lib.METHOD_ALG2) else [])
         return out, info
 
 
