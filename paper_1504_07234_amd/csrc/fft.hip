@@ -28,10 +28,15 @@ namespace mlba {
 // BCCB (Algorithm 1)
 // ---------------------------------------------------------------------------
 
-// G row pairs per workgroup -> T[k][row], k = 0..n/2 (row stride ts complex)
-__device__ __forceinline__ void fft_rows_r2c_body(const float* __restrict__ src, int n,
-                                                              float2* __restrict__ T, int ts, const FftDesc& fd,
-                                                              const float2* __restrict__ tw, int G, int seq_shift, int blk, float2* buf) {
+// G row pairs per workgroup -> T[k][row], k = 0..n/2 (row stride ts complex).
+// NT > 0: n == NT and one row pair per workgroup (fixed-size transform).
+template <int NT = 0>
+__device__ __forceinline__ void fft_rows_r2c_body(const float* __restrict__ src, int n_,
+                                                  float2* __restrict__ T, int ts, const FftDesc& fd,
+                                                  const float2* __restrict__ tw, int G_, int seq_shift, int blk,
+                                                  float2* buf) {
+    const int n = NT > 0 ? NT : n_;
+    const int G = NT > 0 ? 1 : G_;
     const int row0 = blk * 2 * G;
     for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
         const int g = idx / n;
@@ -40,7 +45,7 @@ __device__ __forceinline__ void fft_rows_r2c_body(const float* __restrict__ src,
         buf[lds_slot(idx)] = make_float2(src[ra + x], src[ra + n + x]);
     }
     __syncthreads();
-    lds_fft<-1>(buf, fd, G, seq_shift, tw);
+    lds_fft_any<-1, NT>(buf, fd, G, seq_shift, tw);
     const int half = n / 2 + 1;
     for (int idx = threadIdx.x; idx < G * half; idx += kBlock) {
         const int k = idx / G;
@@ -62,10 +67,11 @@ __device__ __forceinline__ void fft_rows_r2c_body(const float* __restrict__ src,
 //   mode 3: forward FFT only, written back to T;
 //   mode 4: filter of mode 0 on the spectrum already in T, inverse FFT.
 // alpha_dev (optional) replaces alpha by a value computed on the device.
-__device__ __forceinline__ void fft_cols_body(float2* __restrict__ T, int n, int ts,
+template <int NT = 0>
+__device__ __forceinline__ void fft_cols_body(float2* __restrict__ T, int n_, int ts,
                                                           const float* __restrict__ spec, float alpha,
                                                           float inv, const FftDesc& fd,
-                                                          const float2* __restrict__ tw, int CC, int mode,
+                                                          const float2* __restrict__ tw, int CC_, int mode,
                                                           float* __restrict__ power, int seq_shift, int blk, float2* buf,
                                                           float2* __restrict__ sstore = nullptr,
                                                           const float2* __restrict__ sfwd = nullptr,
@@ -73,6 +79,8 @@ __device__ __forceinline__ void fft_cols_body(float2* __restrict__ T, int n, int
                                                           const float2* __restrict__ lamc = nullptr,
                                                           const double* __restrict__ alpha_dev = nullptr,
                                                           float2* __restrict__ cspec = nullptr) {
+    const int n = NT > 0 ? NT : n_;
+    const int CC = NT > 0 ? 1 : CC_;
     const int half = n / 2 + 1;
     const int k0 = blk * CC;
     const int cc = min(CC, half - k0);
@@ -82,7 +90,7 @@ __device__ __forceinline__ void fft_cols_body(float2* __restrict__ T, int n, int
         buf[lds_slot(idx)] = T[(size_t)(k0 + q) * ts + (idx - q * n)];
     }
     __syncthreads();
-    if (mode != 4) lds_fft<-1>(buf, fd, cc, seq_shift, tw);
+    if (mode != 4) lds_fft_any<-1, NT>(buf, fd, cc, seq_shift, tw);
     if (mode == 1) {
         for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
             const float2 v = buf[lds_slot(idx)];
@@ -118,7 +126,7 @@ __device__ __forceinline__ void fft_cols_body(float2* __restrict__ T, int n, int
         }
     }
     __syncthreads();
-    lds_fft<1>(buf, fd, cc, seq_shift, tw);
+    lds_fft_any<1, NT>(buf, fd, cc, seq_shift, tw);
     for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
         const int q = idx / n;
         T[(size_t)(k0 + q) * ts + (idx - q * n)] = buf[lds_slot(idx)];
@@ -144,10 +152,13 @@ __device__ __forceinline__ void fft_cols_inverse_real_body(const float* __restri
     }
 }
 
-__device__ __forceinline__ void fft_rows_c2r_body(const float2* __restrict__ T, int n, int ts,
-                                                              float* __restrict__ dst, const FftDesc& fd,
-                                                              const float2* __restrict__ tw, int G, int seq_shift, int blk, float2* buf,
-                                                              int accum = 0) {
+template <int NT = 0>
+__device__ __forceinline__ void fft_rows_c2r_body(const float2* __restrict__ T, int n_, int ts,
+                                                  float* __restrict__ dst, const FftDesc& fd,
+                                                  const float2* __restrict__ tw, int G_, int seq_shift, int blk,
+                                                  float2* buf, int accum = 0) {
+    const int n = NT > 0 ? NT : n_;
+    const int G = NT > 0 ? 1 : G_;
     const int row0 = blk * 2 * G;
     const int half = n / 2 + 1;
     for (int idx = threadIdx.x; idx < G * half; idx += kBlock) {
@@ -164,7 +175,7 @@ __device__ __forceinline__ void fft_rows_c2r_body(const float2* __restrict__ T, 
         if (!edge) buf[lds_slot(g * n + n - k)] = make_float2(Xa.x + Xb.y, -Xa.y + Xb.x);  // conj(Xa) + i conj(Xb)
     }
     __syncthreads();
-    lds_fft<1>(buf, fd, G, seq_shift, tw);
+    lds_fft_any<1, NT>(buf, fd, G, seq_shift, tw);
     for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
         const int g = idx / n;
         const int x = idx - g * n;
@@ -352,13 +363,15 @@ __device__ __forceinline__ void dct_rows_inv_body(const float* __restrict__ Tr, 
 
 // ---- single-image kernels ------------------------------------------------
 
+template <int NT>
 __global__ __launch_bounds__(kBlock) void fft_rows_r2c_kernel(const float* __restrict__ src, int n,
                                                               float2* __restrict__ T, int ts, FftDesc fd,
                                                               const float2* __restrict__ tw, int G, int seq_shift) {
     extern __shared__ float2 buf[];
-    fft_rows_r2c_body(src, n, T, ts, fd, tw, G, seq_shift, xcd_block(blockIdx.x, gridDim.x), buf);
+    fft_rows_r2c_body<NT>(src, n, T, ts, fd, tw, G, seq_shift, xcd_block(blockIdx.x, gridDim.x), buf);
 }
 
+template <int NT>
 __global__ __launch_bounds__(kBlock) void fft_cols_kernel(float2* __restrict__ T, int n, int ts,
                                                           const float* __restrict__ spec, float alpha,
                                                           float inv, FftDesc fd,
@@ -368,16 +381,17 @@ __global__ __launch_bounds__(kBlock) void fft_cols_kernel(float2* __restrict__ T
                                                           const double* __restrict__ alpha_dev,
                                                           float2* __restrict__ cspec) {
     extern __shared__ float2 buf[];
-    fft_cols_body(T, n, ts, spec, alpha, inv, fd, tw, CC, mode, power, seq_shift, blockIdx.x, buf, nullptr, nullptr,
-                  nullptr, lamc, alpha_dev, cspec);
+    fft_cols_body<NT>(T, n, ts, spec, alpha, inv, fd, tw, CC, mode, power, seq_shift, blockIdx.x, buf, nullptr,
+                      nullptr, nullptr, lamc, alpha_dev, cspec);
 }
 
+template <int NT>
 __global__ __launch_bounds__(kBlock) void fft_rows_c2r_kernel(const float2* __restrict__ T, int n, int ts,
                                                               float* __restrict__ dst, FftDesc fd,
                                                               const float2* __restrict__ tw, int G, int seq_shift,
                                                               int accum) {
     extern __shared__ float2 buf[];
-    fft_rows_c2r_body(T, n, ts, dst, fd, tw, G, seq_shift, xcd_block(blockIdx.x, gridDim.x), buf, accum);
+    fft_rows_c2r_body<NT>(T, n, ts, dst, fd, tw, G, seq_shift, xcd_block(blockIdx.x, gridDim.x), buf, accum);
 }
 
 __global__ __launch_bounds__(kBlock) void dct_rows_fwd_kernel(const float* __restrict__ src, int n,
@@ -592,6 +606,9 @@ int ns_partials_needed() { return 3 * NS_BLOCKS; }
 // ---------------------------------------------------------------------------
 
 // threads per sequence = kBlock / batch (batch a power of two)
+// Length with a compiled fixed-size transform (one sequence per workgroup).
+constexpr int kFixedN = 2048;
+
 static int seq_shift_for(int batch) {
     int sh = 8;  // log2(kBlock)
     while (batch > 1) {
@@ -698,8 +715,12 @@ hipError_t launch_fft_rows_r2c(const float* src, int n, float2* T, int ts, const
                                hipStream_t s) {
     const int G = pick_pairs_per_block(n);
     const size_t lds = lds_bytes(G * n, n);
-    hipLaunchKernelGGL(fft_rows_r2c_kernel, dim3(n / (2 * G)), dim3(kBlock), lds, s, src, n, T, ts, fd, tw, G,
-                       seq_shift_for(G));
+    if (n == kFixedN && G == 1)
+        hipLaunchKernelGGL(fft_rows_r2c_kernel<kFixedN>, dim3(n / 2), dim3(kBlock), lds, s, src, n, T, ts, fd, tw, 1,
+                           seq_shift_for(1));
+    else
+        hipLaunchKernelGGL(fft_rows_r2c_kernel<0>, dim3(n / (2 * G)), dim3(kBlock), lds, s, src, n, T, ts, fd, tw, G,
+                           seq_shift_for(G));
     return hipGetLastError();
 }
 
@@ -709,8 +730,12 @@ static hipError_t launch_cols(float2* T, int n, int ts, const float* spec, float
     const int CC = pick_cols_per_block(n);
     const int half = n / 2 + 1;
     const size_t lds = lds_bytes(CC * n, n);
-    hipLaunchKernelGGL(fft_cols_kernel, dim3((half + CC - 1) / CC), dim3(kBlock), lds, s, T, n, ts, spec, alpha,
-                       inv, fd, tw, CC, mode, power, seq_shift_for(CC), lamc, alpha_dev, cspec);
+    if (n == kFixedN && CC == 1)
+        hipLaunchKernelGGL(fft_cols_kernel<kFixedN>, dim3(half), dim3(kBlock), lds, s, T, n, ts, spec, alpha, inv, fd,
+                           tw, 1, mode, power, seq_shift_for(1), lamc, alpha_dev, cspec);
+    else
+        hipLaunchKernelGGL(fft_cols_kernel<0>, dim3((half + CC - 1) / CC), dim3(kBlock), lds, s, T, n, ts, spec,
+                           alpha, inv, fd, tw, CC, mode, power, seq_shift_for(CC), lamc, alpha_dev, cspec);
     return hipGetLastError();
 }
 
@@ -745,8 +770,12 @@ hipError_t launch_fft_rows_c2r(const float2* T, int n, int ts, float* dst, const
                                hipStream_t s, int accum) {
     const int G = pick_pairs_per_block(n);
     const size_t lds = lds_bytes(G * n, n);
-    hipLaunchKernelGGL(fft_rows_c2r_kernel, dim3(n / (2 * G)), dim3(kBlock), lds, s, T, n, ts, dst, fd, tw, G,
-                       seq_shift_for(G), accum);
+    if (n == kFixedN && G == 1)
+        hipLaunchKernelGGL(fft_rows_c2r_kernel<kFixedN>, dim3(n / 2), dim3(kBlock), lds, s, T, n, ts, dst, fd, tw, 1,
+                           seq_shift_for(1), accum);
+    else
+        hipLaunchKernelGGL(fft_rows_c2r_kernel<0>, dim3(n / (2 * G)), dim3(kBlock), lds, s, T, n, ts, dst, fd, tw, G,
+                           seq_shift_for(G), accum);
     return hipGetLastError();
 }
 

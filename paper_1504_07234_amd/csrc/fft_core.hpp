@@ -159,5 +159,96 @@ __device__ void lds_fft(float2* buf, const FftDesc& fd, int nseq, int seq_shift,
     }
 }
 
+// ---- fixed-size transforms ------------------------------------------------
+// The same stages with the length known at compile time and one sequence per
+// workgroup (kBlock threads): every index, stride and loop bound folds to a
+// constant.  The radix order and the arithmetic of each butterfly are those
+// of lds_fft with the plan built on the host (8s, then 4 or 2, then 3s), so
+// both give bit-identical results.
+struct FixedPlan {
+    int nst;
+    int radix[24];
+    int ns[24];
+};
+
+__host__ __device__ constexpr FixedPlan fixed_plan(int n) {
+    FixedPlan p{};
+    int a = 0, b = 0, m = n;
+    while (m % 2 == 0) {
+        m /= 2;
+        ++a;
+    }
+    while (m % 3 == 0) {
+        m /= 3;
+        ++b;
+    }
+    while (a >= 3) {
+        p.radix[p.nst++] = 8;
+        a -= 3;
+    }
+    if (a == 2) p.radix[p.nst++] = 4;
+    if (a == 1) p.radix[p.nst++] = 2;
+    for (int i = 0; i < b; ++i) p.radix[p.nst++] = 3;
+    int ns = 1;
+    for (int s = 0; s < p.nst; ++s) {
+        p.ns[s] = ns;
+        ns *= p.radix[s];
+    }
+    return p;
+}
+
+template <int R, int DIR, int N, int NS>
+__device__ __forceinline__ void stockham_stage_fixed(float2* buf, const float2* __restrict__ tw) {
+    constexpr int nb = N / R;
+    constexpr int MAXB = (nb + kBlock - 1) / kBlock;
+    constexpr int step = N / (NS * R);
+    float2 v[MAXB][R];
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int j = (int)threadIdx.x + i * kBlock;
+        if (nb % kBlock == 0 || j < nb) {
+            const int jm = j % NS;
+            float2 w[R];
+            if (jm > 0) twiddle_powers<R, DIR>(tw, jm * step, N, w);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float2 x = buf[lds_slot(j + r * nb)];
+                if (r > 0 && jm > 0) x = cmul(x, w[r]);
+                v[i][r] = x;
+            }
+            dft<R, DIR>(v[i]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int j = (int)threadIdx.x + i * kBlock;
+        if (nb % kBlock == 0 || j < nb) {
+            const int jm = j % NS;
+            const int dst = (j - jm) * R + jm;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[lds_slot(dst + r * NS)] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <int DIR, int N, int S = 0>
+__device__ __forceinline__ void lds_fft_fixed(float2* buf, const float2* __restrict__ tw) {
+    constexpr FixedPlan P = fixed_plan(N);
+    if constexpr (S < P.nst) {
+        stockham_stage_fixed<P.radix[S], DIR, N, P.ns[S]>(buf, tw);
+        lds_fft_fixed<DIR, N, S + 1>(buf, tw);
+    }
+}
+
+// NT > 0: the fixed transform of length NT (one sequence per workgroup);
+// NT == 0: the run-time plan fd over nseq sequences.
+template <int DIR, int NT, int EPT = FFT_EPT>
+__device__ __forceinline__ void lds_fft_any(float2* buf, const FftDesc& fd, int nseq, int seq_shift,
+                                            const float2* __restrict__ tw) {
+    if constexpr (NT > 0) lds_fft_fixed<DIR, NT>(buf, tw);
+    else lds_fft<DIR, EPT>(buf, fd, nseq, seq_shift, tw);
+}
 
 }  // namespace mlba

@@ -47,13 +47,22 @@ static int fc_seq_shift(int batch) {
     return sh;
 }
 
+// Grid side with a compiled fixed-size transform (one sequence per
+// workgroup): the smallest admissible grid for the 2048 observation with PSFs
+// of 17..227 taps.
+constexpr int kFixedM = 2304;
+
 // Rows pass: row pairs pair0 + blk*G + g of the M grid; entry (Y, X) is
 // src[Y - off][X - off] inside the S x S box at (off, off), else 0.
-__global__ __launch_bounds__(kBlock) void fc_rows_fwd_kernel(const float* __restrict__ src, int S, int off, int M,
+// NT > 0: M == NT and G == 1.
+template <int NT>
+__global__ __launch_bounds__(kBlock) void fc_rows_fwd_kernel(const float* __restrict__ src, int S, int off, int M_,
                                                              float2* __restrict__ T, int ts, FftDesc fd,
-                                                             const float2* __restrict__ tw, int G, int seq_shift,
+                                                             const float2* __restrict__ tw, int G_, int seq_shift,
                                                              int pair0, int pair_end) {
     extern __shared__ float2 buf[];
+    const int M = NT > 0 ? NT : M_;
+    const int G = NT > 0 ? 1 : G_;
     const int pb = pair0 + xcd_block(blockIdx.x, gridDim.x) * G;
     for (int idx = threadIdx.x; idx < G * M; idx += kBlock) {
         const int g = idx / M;
@@ -69,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void fc_rows_fwd_kernel(const float* __rest
         buf[lds_slot(idx)] = make_float2(a, b);
     }
     __syncthreads();
-    lds_fft<-1, FC_EPT>(buf, fd, G, seq_shift, tw);
+    lds_fft_any<-1, NT, FC_EPT>(buf, fd, G, seq_shift, tw);
     const int half = M / 2 + 1;
     for (int idx = threadIdx.x; idx < G * half; idx += kBlock) {
         const int k = idx / G;
@@ -87,12 +96,15 @@ __global__ __launch_bounds__(kBlock) void fc_rows_fwd_kernel(const float* __rest
 // Columns pass over CC half-spectrum rows per workgroup; rows outside
 // [y_lo, y_hi) of the input are zero.  mode 0: forward FFT, times Hs (or
 // conj(Hs)) * inv, inverse FFT, written back; mode 1: forward FFT into cspec.
-__global__ __launch_bounds__(kBlock) void fc_cols_kernel(float2* __restrict__ T, int M, int ts,
+template <int NT>
+__global__ __launch_bounds__(kBlock) void fc_cols_kernel(float2* __restrict__ T, int M_, int ts,
                                                          const float2* __restrict__ Hs, int conj_h, float inv,
                                                          int y_lo, int y_hi, int mode, float2* __restrict__ cspec,
-                                                         FftDesc fd, const float2* __restrict__ tw, int CC,
+                                                         FftDesc fd, const float2* __restrict__ tw, int CC_,
                                                          int seq_shift) {
     extern __shared__ float2 buf[];
+    const int M = NT > 0 ? NT : M_;
+    const int CC = NT > 0 ? 1 : CC_;
     const int half = M / 2 + 1;
     const int k0 = blockIdx.x * CC;
     const int cc = min(CC, half - k0);
@@ -102,7 +114,7 @@ __global__ __launch_bounds__(kBlock) void fc_cols_kernel(float2* __restrict__ T,
         buf[lds_slot(idx)] = (y >= y_lo && y < y_hi) ? T[(size_t)(k0 + q) * ts + y] : make_float2(0.0f, 0.0f);
     }
     __syncthreads();
-    lds_fft<-1, FC_EPT>(buf, fd, cc, seq_shift, tw);
+    lds_fft_any<-1, NT, FC_EPT>(buf, fd, cc, seq_shift, tw);
     const size_t base = (size_t)k0 * M;
     if (mode == 1) {
         for (int idx = threadIdx.x; idx < cc * M; idx += kBlock) cspec[base + idx] = buf[lds_slot(idx)];
@@ -114,7 +126,7 @@ __global__ __launch_bounds__(kBlock) void fc_cols_kernel(float2* __restrict__ T,
         buf[lds_slot(idx)] = cscale(cmul(buf[lds_slot(idx)], h), inv);
     }
     __syncthreads();
-    lds_fft<1, FC_EPT>(buf, fd, cc, seq_shift, tw);
+    lds_fft_any<1, NT, FC_EPT>(buf, fd, cc, seq_shift, tw);
     for (int idx = threadIdx.x; idx < cc * M; idx += kBlock) {
         const int q = idx / M;
         T[(size_t)(k0 + q) * ts + (idx - q * M)] = buf[lds_slot(idx)];
@@ -124,14 +136,17 @@ __global__ __launch_bounds__(kBlock) void fc_cols_kernel(float2* __restrict__ T,
 // Inverse rows pass over row pairs pair0 + blk*G + g; output (Y, X) of the M
 // grid inside [oy, oy + D) x [ox, ox + D) goes to dst[Y - oy][X - ox]:
 // g ? g - v (squared-norm partial per workgroup) : (accum ? dst + v : v).
-__global__ __launch_bounds__(kBlock) void fc_rows_inv_kernel(const float2* __restrict__ T, int M, int ts,
-                                                             FftDesc fd, const float2* __restrict__ tw, int G,
+template <int NT>
+__global__ __launch_bounds__(kBlock) void fc_rows_inv_kernel(const float2* __restrict__ T, int M_, int ts,
+                                                             FftDesc fd, const float2* __restrict__ tw, int G_,
                                                              int seq_shift, int pair0, int pair_end, int oy, int ox,
                                                              int D, float* __restrict__ dst,
                                                              const float* __restrict__ g, int accum,
                                                              double* __restrict__ partials) {
     extern __shared__ float2 buf[];
     __shared__ double red[kBlock / 64];
+    const int M = NT > 0 ? NT : M_;
+    const int G = NT > 0 ? 1 : G_;
     const int pb = pair0 + xcd_block(blockIdx.x, gridDim.x) * G;
     const int half = M / 2 + 1;
     for (int idx = threadIdx.x; idx < G * half; idx += kBlock) {
@@ -152,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void fc_rows_inv_kernel(const float2* __res
         if (!edge) buf[lds_slot(gg * M + M - k)] = make_float2(Xa.x + Xb.y, -Xa.y + Xb.x);
     }
     __syncthreads();
-    lds_fft<1, FC_EPT>(buf, fd, G, seq_shift, tw);
+    lds_fft_any<1, NT, FC_EPT>(buf, fd, G, seq_shift, tw);
     double ss = 0.0;
     for (int idx = threadIdx.x; idx < G * M; idx += kBlock) {
         const int gg = idx / M;
@@ -190,8 +205,12 @@ static hipError_t fc_rows_fwd(const FftConv& c, const float* src, int S, int off
     const int p0 = y_lo / 2, p1 = (y_hi + 1) / 2;
     const int blocks = (p1 - p0 + G - 1) / G;
     if (blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fc_rows_fwd_kernel, dim3(blocks), dim3(kBlock), lds_bytes(G * c.M, c.M), s, src, S, off, c.M,
-                       c.T, c.ts, c.fd, c.tw, G, fc_seq_shift(G), p0, p1);
+    if (c.M == kFixedM && G == 1)
+        hipLaunchKernelGGL(fc_rows_fwd_kernel<kFixedM>, dim3(blocks), dim3(kBlock), lds_bytes(c.M, c.M), s, src, S,
+                           off, c.M, c.T, c.ts, c.fd, c.tw, 1, fc_seq_shift(1), p0, p1);
+    else
+        hipLaunchKernelGGL(fc_rows_fwd_kernel<0>, dim3(blocks), dim3(kBlock), lds_bytes(G * c.M, c.M), s, src, S, off,
+                           c.M, c.T, c.ts, c.fd, c.tw, G, fc_seq_shift(G), p0, p1);
     return hipGetLastError();
 }
 
@@ -199,9 +218,13 @@ static hipError_t fc_cols(const FftConv& c, int conj_h, int y_lo, int y_hi, int 
     const int CC = fc_cols_per_block(c.M);
     const int half = c.M / 2 + 1;
     const float inv = (float)(1.0 / ((double)c.M * (double)c.M));
-    hipLaunchKernelGGL(fc_cols_kernel, dim3((half + CC - 1) / CC), dim3(kBlock), lds_bytes(CC * c.M, c.M), s, c.T,
-                       c.M, c.ts, (const float2*)c.H, conj_h, inv, y_lo, y_hi, mode, cspec, c.fd, c.tw, CC,
-                       fc_seq_shift(CC));
+    if (c.M == kFixedM && CC == 1)
+        hipLaunchKernelGGL(fc_cols_kernel<kFixedM>, dim3(half), dim3(kBlock), lds_bytes(c.M, c.M), s, c.T, c.M, c.ts,
+                           (const float2*)c.H, conj_h, inv, y_lo, y_hi, mode, cspec, c.fd, c.tw, 1, fc_seq_shift(1));
+    else
+        hipLaunchKernelGGL(fc_cols_kernel<0>, dim3((half + CC - 1) / CC), dim3(kBlock), lds_bytes(CC * c.M, c.M), s,
+                           c.T, c.M, c.ts, (const float2*)c.H, conj_h, inv, y_lo, y_hi, mode, cspec, c.fd, c.tw, CC,
+                           fc_seq_shift(CC));
     return hipGetLastError();
 }
 
@@ -211,8 +234,14 @@ static hipError_t fc_rows_inv(const FftConv& c, int oy, int ox, int D, float* ds
     const int p0 = oy / 2, p1 = (oy + D + 1) / 2;
     const int blocks = (p1 - p0 + G - 1) / G;
     if (n_partials) *n_partials = blocks;
-    hipLaunchKernelGGL(fc_rows_inv_kernel, dim3(blocks), dim3(kBlock), lds_bytes(G * c.M, c.M), s, (const float2*)c.T,
-                       c.M, c.ts, c.fd, c.tw, G, fc_seq_shift(G), p0, p1, oy, ox, D, dst, g, accum, partials);
+    if (c.M == kFixedM && G == 1)
+        hipLaunchKernelGGL(fc_rows_inv_kernel<kFixedM>, dim3(blocks), dim3(kBlock), lds_bytes(c.M, c.M), s,
+                           (const float2*)c.T, c.M, c.ts, c.fd, c.tw, 1, fc_seq_shift(1), p0, p1, oy, ox, D, dst, g,
+                           accum, partials);
+    else
+        hipLaunchKernelGGL(fc_rows_inv_kernel<0>, dim3(blocks), dim3(kBlock), lds_bytes(G * c.M, c.M), s,
+                           (const float2*)c.T, c.M, c.ts, c.fd, c.tw, G, fc_seq_shift(G), p0, p1, oy, ox, D, dst, g,
+                           accum, partials);
     return hipGetLastError();
 }
 
