@@ -10,10 +10,12 @@ scene, PSF and noise) and resident in HBM before the timed region starts.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-Prints one JSON line: Mpixel-iter/s over the observed pixels, the
-per-phase breakdown measured with HIP events on the library's stream during
-the timed region, the roofline of the dominant kernel, and the FP64 oracle
-timed on the host cores over a bounded sample of the same workload.  Two
+The blur is the one the plan autotuner picks (direct taps or the FFT grid).
+Prints one JSON line: Mpixel-iter/s over the observed pixels, the per-kernel
+and per-phase breakdown measured with HIP events on the library's stream on
+every 4th iteration of the timed region, the roofline of the dominant kernel
+(the one with the largest share of the iteration), and the FP64 oracle timed
+on the host cores over a bounded sample of the same workload.  Two
 sections follow: 64 uneven images batched under a hipGraph against 64
 sequential solves, and the forward / backward time of 30 unrolled
 iterations over 16 images of 256^2 with their gradients.
@@ -34,70 +36,120 @@ if ROOT not in sys.path:
 METRIC = "MLBA Mpixel-iter/s at 2048² FP32 (% HBM roofline); batched vs plain; bwd/fwd ratio"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, non-packed FP32
+PROFILE_EVERY = 4              # kernel events on every 4th timed iteration (their overhead stays below 1 %)
 
-# HBM traffic of the dominant kernel per launch, from two rocprofv3 --pmc passes
-# (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) over `python bench.py
-# --traffic-probe`, each scaled by what the counter reads for a plain 256 MiB
-# copy on the same run (FETCH_SIZE 131,084 KiB -> x2.000, WRITE_SIZE
-# 262,144 KiB -> x1.000).  The figure belongs to the kernel sources it was
-# taken with: when their hash differs it is reported as null.
-TRAFFIC = {
-    ("blur_t", "implicit"): {"fetch_kib": 17573.7, "write_kib": 16878.0, "fetch_scale": 2.0, "write_scale": 1.0,
-                             "sources_sha256": "fc757902bc5c941b6e9070e111ccee7e6f5d1340d05ffa7944585ad07c031ca3"},
+# HBM traffic of the dominant kernel per iteration, from two rocprofv3 --pmc
+# passes (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, summed over the
+# kernel's launches in one iteration) over `python bench.py --traffic-probe`,
+# each scaled by what the counter reads for a plain 256 MiB copy on the same run
+# (FETCH_SIZE x2.000, WRITE_SIZE x1.000).  A figure belongs to the kernel sources
+# it was taken with: when their hash differs it is reported as null.
+TRAFFIC = {}
+TRAFFIC_SOURCES = {
+    "shrink_synthesis": ("framelet.hip", "common.hpp", "kernels.hpp"),
+    "lowpass_level": ("framelet.hip", "common.hpp", "kernels.hpp"),
+    "conv_blur_t": ("conv.hip", "common.hpp", "kernels.hpp"),
+    "conv_blur": ("conv.hip", "common.hpp", "kernels.hpp"),
+    "fc_cols": ("fftconv.hip", "fft_core.hpp", "common.hpp", "kernels.hpp"),
+    "fc_rows_fwd": ("fftconv.hip", "fft_core.hpp", "common.hpp", "kernels.hpp"),
+    "fc_rows_inv": ("fftconv.hip", "fft_core.hpp", "common.hpp", "kernels.hpp"),
+    "fc_residual_precond_rows": ("fftconv.hip", "fft_core.hpp", "common.hpp", "kernels.hpp"),
+    "precond_rows_fc_fwd": ("fftconv.hip", "fft_core.hpp", "common.hpp", "kernels.hpp"),
+    "fft_cols": ("fft.hip", "fft_core.hpp", "common.hpp", "kernels.hpp"),
 }
-TRAFFIC_SOURCES = ("paper_1504_07234_amd/csrc/conv.hip", "paper_1504_07234_amd/csrc/common.hpp",
-                   "paper_1504_07234_amd/csrc/kernels.hpp")
 
 
-def measured_traffic(phase: str, state: str):
-    """Bytes per launch from the recorded counter passes, or None when none
-    were taken for this kernel or its sources changed since."""
+def sources_hash(kernel: str):
     import hashlib
-    rec = TRAFFIC.get((phase, state))
-    if rec is None:
+    files = TRAFFIC_SOURCES.get(kernel)
+    if files is None:
         return None
     h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
+    for f in files:
+        with open(os.path.join(ROOT, "paper_1504_07234_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != rec["sources_sha256"]:
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, key: str):
+    """HBM bytes per launch from the recorded counter passes, or None when none
+    were taken for this kernel and configuration or its sources changed since."""
+    rec = TRAFFIC.get((kernel, key))
+    if rec is None or sources_hash(kernel) != rec["sources_sha256"]:
         return None
-    return 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])
+    per_iter = 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])
+    return per_iter / rec["launches"]
 
 
-def phase_model(n, p, N, B, L, implicit):
-    """Algorithmic bytes and flops of each phase of one iteration (float32).
+def fft_grid(N: int) -> int:
+    """Side of the FFT-blur grid: the smallest even 2^a 3^b >= N (at most 3072)."""
+    best = 0
+    a = 1
+    while (1 << a) <= 3072:
+        m = 1 << a
+        while m <= 3072:
+            if m >= N and (best == 0 or m < best):
+                best = m
+            m *= 3
+        a += 1
+    return best
 
-    Explicit state z ([B][N][N]):
-      synthesis : read z (B N^2), write u (N^2)
-      blur_t    : read t (n^2), write w (N^2); 2 p^2 n^2 flops
-      analysis  : read w (N^2), read and write z (2 B N^2)
-    Implicit state omega (N x N, z = W omega):
-      synthesis : L-1 low-pass levels (read + write N^2 each), then L levels
-                  (read the level's low-pass, read the level above's output
-                  except at the top, write N^2)
-      blur_t    : read t (n^2), read and write omega (2 N^2); 2 p^2 n^2 flops
-      analysis  : none
-    Both:
-      blur      : read u (N^2), read g (n^2), write r (n^2); 2 p^2 n^2 flops
-      precond   : read r (n^2), write t (n^2)
+
+def kernel_model(n, p, N, L, implicit, fft_blur):
+    """Algorithmic bytes and flops of each kernel per iteration (float32
+    values, complex = 8 bytes), and the roof that bounds it.
+
+      synthesis_level   (z)     level: read 8 bands + low-pass, write N^2
+      lowpass_level     (omega) level: read + write N^2
+      shrink_synthesis  (omega) level: read the level's low-pass and the level
+                                above's output (not at the top), write N^2;
+                                119 flops per pixel (FMA = 2): x-analysis 10,
+                                y-analysis 30, 9 thresholds 27, y-synthesis 39,
+                                x-synthesis 13
+      conv_blur                 read u (N^2) and g, write r; 2 p^2 n^2 flops
+      conv_blur_t               read t, write w (omega: read + write); 2 p^2 n^2
+      fft_rows_fwd / _inv       n^2 reals <-> (n/2+1) n complex (transposed)
+      fft_cols                  read + write (n/2+1) n complex, read the filter
+      fc_rows_fwd (A)           read u (N^2), write (M/2+1) N complex
+      fc_cols (A, A^T)          read the nonzero rows ((M/2+1) N, (M/2+1) n),
+                                read the PSF spectrum and write (M/2+1) M
+      fc_rows_inv (A^T)         read (M/2+1) N complex, write w (omega: +read)
+      fc_residual_precond_rows  read (M/2+1) n complex and g, write (n/2+1) n
+      precond_rows_fc_fwd       read (n/2+1) n complex, write (M/2+1) n
+      analysis_level    (z)     read v, read + write 8 bands, write low-pass
     """
-    f4 = 4.0
+    f4, c8 = 4.0, 8.0
+    nn, NN = n * n, N * N
+    hp = (n // 2 + 1) * n
+    conv_fl = 2.0 * p * p * n * n
+    m = {}
     if implicit:
-        syn = f4 * N * N * (2 * (L - 1) + 2 + 3 * (L - 1))
-        bt = f4 * (n * n + 2 * N * N)
-        ana = 0.0
+        m["lowpass_level"] = {"bytes": f4 * 2 * NN * (L - 1), "flops": 8.0 * NN * (L - 1), "launches": L - 1}
+        m["shrink_synthesis"] = {"bytes": f4 * NN * (3 * L - 1), "flops": 119.0 * NN * L, "launches": L}
     else:
-        syn = f4 * (B * N * N + N * N)
-        bt = f4 * (n * n + N * N)
-        ana = f4 * (N * N + 2 * B * N * N)
-    return {
-        "synthesis": {"bytes": syn, "flops": 0.0},
-        "blur": {"bytes": f4 * (N * N + 2 * n * n), "flops": 2.0 * p * p * n * n},
-        "precond": {"bytes": f4 * (2 * n * n), "flops": 0.0},
-        "blur_t": {"bytes": bt, "flops": 2.0 * p * p * n * n},
-        "analysis": {"bytes": ana, "flops": 0.0},
-    }
+        m["synthesis_level"] = {"bytes": f4 * 10 * NN * L, "flops": 90.0 * NN * L, "launches": L}
+        m["analysis_level"] = {"bytes": f4 * NN * (18 * L + 1), "flops": 60.0 * NN * L, "launches": L}
+    if fft_blur:
+        M = fft_grid(N)
+        hm = M // 2 + 1
+        m["fc_rows_fwd"] = {"bytes": f4 * NN + c8 * hm * N, "flops": 0.0, "launches": 1}
+        m["fc_cols"] = {"bytes": c8 * hm * (N + n) + 2 * 2 * c8 * hm * M, "flops": 0.0, "launches": 2}
+        m["fc_residual_precond_rows"] = {"bytes": c8 * hm * n + f4 * nn + c8 * hp, "flops": 0.0, "launches": 1}
+        m["fft_cols"] = {"bytes": 2 * c8 * hp + f4 * hp, "flops": 0.0, "launches": 1}
+        m["precond_rows_fc_fwd"] = {"bytes": c8 * hp + c8 * hm * n, "flops": 0.0, "launches": 1}
+        m["fc_rows_inv"] = {"bytes": c8 * hm * N + f4 * NN * (2 if implicit else 1), "flops": 0.0, "launches": 1}
+    else:
+        m["conv_blur"] = {"bytes": f4 * (NN + 2 * nn), "flops": conv_fl, "launches": 1}
+        m["fft_rows_fwd"] = {"bytes": f4 * nn + c8 * hp, "flops": 0.0, "launches": 1}
+        m["fft_cols"] = {"bytes": 2 * c8 * hp + f4 * hp, "flops": 0.0, "launches": 1}
+        m["fft_rows_inv"] = {"bytes": c8 * hp + f4 * nn, "flops": 0.0, "launches": 1}
+        m["conv_blur_t"] = {"bytes": f4 * (nn + (2 if implicit else 1) * NN), "flops": conv_fl, "launches": 1}
+    m["reduce"] = {"bytes": 0.0, "flops": 0.0, "launches": 1}
+    for k, v in m.items():
+        t_hbm = v["bytes"] / (HBM_PEAK_GBS * 1e9)
+        t_alu = v["flops"] / (FP32_VALU_PEAK_TFLOPS * 1e12)
+        v["bound"] = "alu" if t_alu > t_hbm else "hbm"
+    return m
 
 
 def cpu_baseline(w, g64, delta, iters):
@@ -321,6 +373,8 @@ def main() -> int:
                     help="iteration state: omega (z = W omega recomputed) or the frame coefficients z")
     ap.add_argument("--compare-steps", type=int, default=20,
                     help="iterations timed with the other state, for comparison (0: skip)")
+    ap.add_argument("--traffic-blur", choices=("fft", "direct"), default="fft",
+                    help="blur used by --traffic-probe")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only two 256 MiB device copies x3 (counter calibration: the runtime copy and "
                          "a one-float-per-lane copy) and 3 iterations of the workload, for rocprofv3 --pmc "
@@ -365,26 +419,30 @@ def main() -> int:
                      implicit=implicit)
         torch.cuda.synchronize()
         if profile:
-            plan.profile_begin(steps)
+            plan.profile_begin(steps, every=PROFILE_EVERY)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         plan.restore(g, alpha=w.alpha0, mu=w.mu, delta=delta, iters=steps, k0=warmup, z=st, out=f, track=False,
                      implicit=implicit)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        ph = plan.profile_end() if profile else None
+        prof = None
+        if profile:
+            phases, rec = plan.profile_end()
+            prof = (phases, plan.profile_kernels(), rec)
         _, info = plan.restore(g, alpha=w.alpha0, mu=w.mu, delta=delta, iters=1, k0=warmup + steps, z=st, out=f,
                                track=True, implicit=implicit)
         assert np.isfinite(info.rnorm[0]), "non-finite residual"
-        return el, ph
+        return el, prof
 
     implicit = args.state == "implicit"
     blur_choice = None
     if not args.traffic_probe:
-        # what the plan autotuner measures for the blur (direct taps vs FFT grid); the
-        # timed run keeps the direct blur, whose VALU roofline is reported below
+        # the plan autotuner times the direct blur against the FFT grid and keeps the faster
         blur_choice = plan.autotune(reps=5)
-        plan.set_blur(mlba.BLUR_DIRECT)
+    else:
+        plan.set_blur(mlba.BLUR_FFT if args.traffic_blur == "fft" else mlba.BLUR_DIRECT)
+    fft_blur = (blur_choice["blur"] == "fft") if blur_choice is not None else args.traffic_blur == "fft"
     if args.traffic_probe:
         src = torch.rand(64 << 20, device="cuda")
         dst = torch.empty_like(src)
@@ -398,8 +456,8 @@ def main() -> int:
         torch.cuda.synchronize()
         print("traffic probe done", flush=True)
         return 0
-    # ---- warmup, then the timed region: K iterations, phase events on the library stream --
-    elapsed, (phases, rec) = run(implicit, args.steps, args.warmup, True)
+    # ---- warmup, then the timed region: K iterations, kernel events on the library stream --
+    elapsed, (phases, kernels, rec) = run(implicit, args.steps, args.warmup, True)
     compare = None
     alt_blur = None
     if args.compare_steps > 0:
@@ -408,58 +466,56 @@ def main() -> int:
                    "ms_per_step": round(el2 * 1e3 / args.compare_steps, 5),
                    "Mpx_it_s": round(n * n * args.compare_steps / el2 / 1e6, 2)}
         if blur_choice is not None and blur_choice["fft_ms"] is not None:
-            # the same iteration with A and A^T evaluated on the FFT grid
-            plan.set_blur(mlba.BLUR_FFT)
+            # the same iteration with the blur the autotuner did not pick
+            plan.set_blur(mlba.BLUR_DIRECT if fft_blur else mlba.BLUR_FFT)
             el3, _ = run(implicit, args.compare_steps, 3, False)
-            plan.set_blur(mlba.BLUR_DIRECT)
-            alt_blur = {"blur": "fft", "steps": args.compare_steps,
+            plan.set_blur(mlba.BLUR_FFT if fft_blur else mlba.BLUR_DIRECT)
+            alt_blur = {"blur": "direct" if fft_blur else "fft", "steps": args.compare_steps,
                         "ms_per_step": round(el3 * 1e3 / args.compare_steps, 5),
                         "Mpx_it_s": round(n * n * args.compare_steps / el3 / 1e6, 2)}
 
     ms_per_step = elapsed * 1e3 / args.steps
     value = n * n * args.steps / elapsed / 1e6
-    model = phase_model(n, p, N, B, w.levels, implicit)
-    phase_out = {}
-    for ph, (ms, launches) in phases.items():
-        per_iter_ms = ms / max(rec, 1)
-        b, fl = model[ph]["bytes"], model[ph]["flops"]
-        phase_out[ph] = {
-            "ms_per_iter": round(per_iter_ms, 4),
-            "launches_per_iter": launches // max(rec, 1),
-            "GBs": round(b / (per_iter_ms * 1e-3) / 1e9, 1) if per_iter_ms > 0 and b > 0 else None,
-            "TFLOPs": round(fl / (per_iter_ms * 1e-3) / 1e12, 2) if fl and per_iter_ms > 0 else None,
-        }
-    def roofline_of(ph):
-        """Roofline of the phase's main kernel from the live event times."""
-        ms_iter = phases[ph][0] / max(rec, 1)
-        nl = max(1, phases[ph][1] // max(rec, 1))
-        if ph == "blur":  # conv + one tiny reduction launch: the conv is the kernel
-            nl = 1
-        launch_ms = ms_iter / nl
-        if model[ph]["flops"] > 0:
-            ach = model[ph]["flops"] / nl / (launch_ms * 1e-3) / 1e12
-            r = {"bound": "alu", "achieved": round(ach, 2), "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                 "frac": round(ach / FP32_VALU_PEAK_TFLOPS, 4), "traffic": measured_traffic(ph, args.state)}
-        else:
-            ach = model[ph]["bytes"] / nl / (launch_ms * 1e-3) / 1e9
-            r = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(ph, args.state)}
-        r["kernel_phase"] = ph
-        r["launch_ms"] = round(launch_ms, 4)
-        r["algorithmic_bytes"] = round(model[ph]["bytes"] / nl)
-        return r
+    model = kernel_model(n, p, N, w.levels, implicit, fft_blur)
+    key = f"{'fft' if fft_blur else 'direct'}-{'implicit' if implicit else 'explicit'}"
+    rec = max(rec, 1)
+    kern_out = {}
+    for k, (ms, nl) in kernels.items():
+        us_iter = ms * 1e3 / rec
+        mk = model.get(k)
+        e = {"us_per_iter": round(us_iter, 2), "launches_per_iter": round(nl / rec, 2),
+             "us_per_launch": round(ms * 1e3 / nl, 2)}
+        if mk is not None and us_iter > 0:
+            e["GBs"] = round(mk["bytes"] / (us_iter * 1e-6) / 1e9, 1)
+            e["TFLOPs"] = round(mk["flops"] / (us_iter * 1e-6) / 1e12, 2) if mk["flops"] else None
+            e["bound"] = mk["bound"]
+            e["frac"] = round(e["GBs"] / HBM_PEAK_GBS if mk["bound"] == "hbm" else
+                              e["TFLOPs"] / FP32_VALU_PEAK_TFLOPS, 4)
+        kern_out[k] = e
+    phase_out = {ph: {"us_per_iter": round(ms * 1e3 / rec, 2), "launches_per_iter": round(nl / rec, 2)}
+                 for ph, (ms, nl) in phases.items()}
 
-    # dominant kernel: the longest single launch of an iteration
-    def launch_ms(ph):
-        per_iter = max(1, phases[ph][1] // max(rec, 1))
-        if phases[ph][1] == 0:
-            return 0.0
-        return phases[ph][0] / max(rec, 1) / (1 if ph == "blur" else per_iter)
-
-    dom = max(phases, key=launch_ms)
-    roof = roofline_of(dom)
-    roof_hbm = roofline_of("synthesis" if implicit else "analysis")
-    total_bytes = sum(m["bytes"] for m in model.values())
+    # dominant kernel: the one that takes the largest share of the iteration
+    dom = max((k for k in kernels if k in model), key=lambda k: kernels[k][0])
+    mk = model[dom]
+    ms, nl = kernels[dom]
+    launch_s = ms * 1e-3 / nl
+    per_launch_bytes = mk["bytes"] / mk["launches"]
+    per_launch_flops = mk["flops"] / mk["launches"]
+    if mk["bound"] == "alu":
+        ach = per_launch_flops / launch_s / 1e12
+        roof = {"bound": "alu", "achieved": round(ach, 2), "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / FP32_VALU_PEAK_TFLOPS, 4)}
+    else:
+        ach = per_launch_bytes / launch_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4)}
+    roof["traffic"] = measured_traffic(dom, key)
+    roof.update({"kernel": dom, "launch_us": round(launch_s * 1e6, 2), "launches_per_iter": mk["launches"],
+                 "algorithmic_bytes_per_launch": round(per_launch_bytes),
+                 "algorithmic_flops_per_launch": round(per_launch_flops),
+                 "iterations_sampled": rec, "sampled_every": PROFILE_EVERY})
+    total_bytes = sum(v["bytes"] for v in model.values())
     hbm_frac = (total_bytes / (HBM_PEAK_GBS * 1e9)) / (ms_per_step * 1e-3)
 
     out = {
@@ -477,14 +533,15 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": w.name, "n": n, "p": p, "N": N, "levels": w.levels, "bands": B,
                    "boundary": "rect", "precond": "bccb", "alpha": w.alpha0, "mu": w.mu,
-                   "delta": round(delta, 6), "state": "implicit omega (z = W omega)" if implicit else "explicit z"},
+                   "delta": round(delta, 6), "state": "implicit omega (z = W omega)" if implicit else "explicit z",
+                   "blur": f"fft grid {fft_grid(N)}" if fft_blur else "direct taps"},
         "hbm_roofline_frac_whole_step": round(hbm_frac, 4),
-        "phases": phase_out,
         "roofline": roof,
-        "roofline_hbm": roof_hbm,
+        "kernels": kern_out,
+        "phases": phase_out,
         "other_state": compare,
         "blur_autotune": blur_choice,
-        "fft_blur_iteration": alt_blur,
+        "other_blur": alt_blur,
     }
     plan.close()
     if not args.no_batched:

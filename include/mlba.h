@@ -352,23 +352,59 @@ int mlba_unrolled_backward(mlba_unrolled_t unrolled, const float* const* g, doub
                            int n_mu, double delta, float* const* ckpt, const float* const* df, double* dmu,
                            double* dalpha, double* dpsf, float* const* dg, hipStream_t stream);
 
-/* ---- phase timing (profiling aid) ----------------------------------------
+/* ---- phase and kernel timing (profiling aid) -----------------------------
  * Phases of one iteration of eq. (MLBA2) as the library runs them. */
-#define MLBA_PHASE_SYNTHESIS 0  /* x = delta S_mu(z), u = W^T x (levels launches)   */
-#define MLBA_PHASE_BLUR      1  /* r = g - A u and ||r||^2                           */
-#define MLBA_PHASE_PRECOND   2  /* t = P_alpha r (three transform passes)            */
-#define MLBA_PHASE_BLUR_T    3  /* w = A^T t                                         */
-#define MLBA_PHASE_ANALYSIS  4  /* z += W w (levels launches)                        */
+#define MLBA_PHASE_SYNTHESIS 0  /* x = delta S_mu(z), u = W^T x                        */
+#define MLBA_PHASE_BLUR      1  /* r = g - A u and ||r||^2 (with the FFT blur and the
+                                   BCCB preconditioner also the preconditioner's
+                                   forward row pass, fused with the residual's)     */
+#define MLBA_PHASE_PRECOND   2  /* t = P_alpha r (the transform passes)              */
+#define MLBA_PHASE_BLUR_T    3  /* w = A^T t (fused FFT path: from the
+                                   preconditioner's inverse row pass on)            */
+#define MLBA_PHASE_ANALYSIS  4  /* z += W w                                          */
 #define MLBA_NPHASES         5
-/* mlba_profile_begin: the following mlba_restore calls on this plan record a
- * HIP event on their stream before each phase and after the last, for at most
- * max_iters iterations in total (host-side event objects, no device memory).
+/* Kernels (one launch each unless noted). */
+#define MLBA_KERNEL_SYNTHESIS_LEVEL   0  /* thresholded synthesis of one level (z state) */
+#define MLBA_KERNEL_LOWPASS_LEVEL     1  /* low-pass of one level (omega state)          */
+#define MLBA_KERNEL_SHRINK_SYNTHESIS  2  /* bands, threshold, synthesis of one level     */
+#define MLBA_KERNEL_CONV_BLUR         3  /* direct r = g - A u                           */
+#define MLBA_KERNEL_CONV_BLUR_T       4  /* direct A^T t (accumulating for omega)        */
+#define MLBA_KERNEL_FOLD_REFLECT      5  /* fold of the reflective padding               */
+#define MLBA_KERNEL_REDUCE            6  /* sum of the ||r||^2 partials                  */
+#define MLBA_KERNEL_FFT_ROWS_FWD      7  /* preconditioner: forward row pass             */
+#define MLBA_KERNEL_FFT_COLS          8  /* preconditioner: column pass with the filter  */
+#define MLBA_KERNEL_FFT_ROWS_INV      9  /* preconditioner: inverse row pass             */
+#define MLBA_KERNEL_FC_ROWS_FWD      10  /* FFT blur: forward row pass                   */
+#define MLBA_KERNEL_FC_COLS          11  /* FFT blur: column pass                        */
+#define MLBA_KERNEL_FC_ROWS_INV      12  /* FFT blur: inverse row pass                   */
+#define MLBA_KERNEL_FC_RESIDUAL_PRECOND_ROWS 13  /* fused residual rows + preconditioner
+                                                    forward rows                        */
+#define MLBA_KERNEL_PRECOND_ROWS_FC_FWD      14  /* fused preconditioner inverse rows +
+                                                    A^T forward rows                    */
+#define MLBA_KERNEL_ANALYSIS_LEVEL   15  /* analysis + Bregman update of one level       */
+#define MLBA_KERNEL_OTHER            16  /* launch sequences timed as one: the 4-NS
+                                            Newton steps, the PCG of Algorithm 2, copies */
+#define MLBA_NKERNELS                17
+/* mlba_profile_begin: the following mlba_restore calls on this plan record HIP
+ * events on their stream (one at the start of an iteration and one after each
+ * launch or launch sequence of the table above) for at most max_iters
+ * iterations in total (host-side event objects, no device memory).
  * mlba_profile_end: waits for those events and writes, per phase, the summed
  * milliseconds (ms[MLBA_NPHASES], host) and the number of kernel launches
  * (launches[MLBA_NPHASES], host, optional), plus the number of iterations
- * recorded (iters, optional); then releases the events. */
+ * recorded (iters, optional); keeps the per-kernel sums for
+ * mlba_profile_kernels and releases the events.
+ * mlba_profile_kernels: the per-kernel milliseconds (ms[MLBA_NKERNELS]) and
+ * launch counts (launches[MLBA_NKERNELS], optional) of the last
+ * mlba_profile_end (zero before one). */
 int mlba_profile_begin(mlba_plan_t plan, int max_iters);
+/* mlba_profile_every: after mlba_profile_begin, record only every stride-th
+ * iteration (stride >= 1; the default 1 records every one), counting from the
+ * first iteration after this call.  The recorded iterations still count
+ * against max_iters. */
+int mlba_profile_every(mlba_plan_t plan, int stride);
 int mlba_profile_end(mlba_plan_t plan, double* ms, int* launches, int* iters);
+int mlba_profile_kernels(mlba_plan_t plan, double* ms, int* launches);
 
 #ifdef __cplusplus
 }

@@ -89,9 +89,15 @@ SIGNATURES = {
                                        c_void_p, ctypes.POINTER(c_void_p), c_void_p]),
     "mlba_profile_begin": (c_int, [c_void_p, c_int]),
     "mlba_profile_end": (c_int, [c_void_p, c_dbl_p, c_int_p, c_int_p]),
+    "mlba_profile_kernels": (c_int, [c_void_p, c_dbl_p, c_int_p]),
+    "mlba_profile_every": (c_int, [c_void_p, c_int]),
 }
 
 PHASES = ("synthesis", "blur", "precond", "blur_t", "analysis")
+# MLBA_KERNEL_* in order
+KERNELS = ("synthesis_level", "lowpass_level", "shrink_synthesis", "conv_blur", "conv_blur_t", "fold_reflect",
+           "reduce", "fft_rows_fwd", "fft_cols", "fft_rows_inv", "fc_rows_fwd", "fc_cols", "fc_rows_inv",
+           "fc_residual_precond_rows", "precond_rows_fc_fwd", "analysis_level", "other")
 
 _lib = None
 

@@ -606,9 +606,6 @@ int ns_partials_needed() { return 3 * NS_BLOCKS; }
 // ---------------------------------------------------------------------------
 
 // threads per sequence = kBlock / batch (batch a power of two)
-// Length with a compiled fixed-size transform (one sequence per workgroup).
-constexpr int kFixedN = 2048;
-
 static int seq_shift_for(int batch) {
     int sh = 8;  // log2(kBlock)
     while (batch > 1) {

@@ -11,6 +11,12 @@
 namespace mlba {
 
 constexpr int FFT_EPT = 8;  // complex values per thread per stage (max)
+
+// Lengths with a compiled fixed-size transform (one sequence per workgroup):
+// the preconditioner of the 2048 observation, and the FFT-blur grid of that
+// observation (the smallest admissible grid for PSFs of 17..227 taps).
+constexpr int kFixedN = 2048;
+constexpr int kFixedM = 2304;
 constexpr int FFT_MAX_ELEMS = FFT_EPT * kBlock;  // complex values per workgroup (16 KB of LDS)
 
 // LDS slot of element i: one padding slot after every 8 elements, so that the

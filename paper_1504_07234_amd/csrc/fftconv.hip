@@ -47,11 +47,6 @@ static int fc_seq_shift(int batch) {
     return sh;
 }
 
-// Grid side with a compiled fixed-size transform (one sequence per
-// workgroup): the smallest admissible grid for the 2048 observation with PSFs
-// of 17..227 taps.
-constexpr int kFixedM = 2304;
-
 // Rows pass: row pairs pair0 + blk*G + g of the M grid; entry (Y, X) is
 // src[Y - off][X - off] inside the S x S box at (off, off), else 0.
 // NT > 0: M == NT and G == 1.
@@ -197,9 +192,147 @@ __global__ __launch_bounds__(kBlock) void fc_rows_inv_kernel(const float2* __res
     }
 }
 
+// ---- row passes fused with the preconditioner's ---------------------------
+// The residual's inverse row pass (FFT-blur grid) and the preconditioner's
+// forward row pass both run over the same two observed rows, so one
+// workgroup does both: inverse transform of the grid pair, crop and residual
+// (with its squared-norm partial), then the forward transform of the two
+// residual rows, split and written transposed into the preconditioner's half
+// spectrum.  The arithmetic of every value is that of the separate passes.
+template <int NTM, int NTN>
+__global__ __launch_bounds__(kBlock) void fc_residual_precond_kernel(
+    const float2* __restrict__ Tc, int M_, int tsc, FftDesc fdm, const float2* __restrict__ twm, int pair0, int n_,
+    int off, const float* __restrict__ g, float* __restrict__ r_out, double* __restrict__ partials,
+    float2* __restrict__ Tp, int tsp, FftDesc fdn, const float2* __restrict__ twn) {
+    extern __shared__ float2 buf[];
+    __shared__ double red[kBlock / 64];
+    const int M = NTM > 0 ? NTM : M_;
+    const int n = NTN > 0 ? NTN : n_;
+    const int q = xcd_block(blockIdx.x, gridDim.x);  // observed rows 2q, 2q + 1
+    const int pb = pair0 + q;                        // the same rows of the grid
+    const int half = M / 2 + 1;
+    for (int k = threadIdx.x; k < half; k += kBlock) {
+        const float4 v = *reinterpret_cast<const float4*>(Tc + (size_t)k * tsc + 2 * pb);
+        float2 Xa = make_float2(v.x, v.y), Xb = make_float2(v.z, v.w);
+        const bool edge = (k == 0) || (2 * k == M);
+        if (edge) {
+            Xa.y = 0.0f;
+            Xb.y = 0.0f;
+        }
+        buf[lds_slot(k)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
+        if (!edge) buf[lds_slot(M - k)] = make_float2(Xa.x + Xb.y, -Xa.y + Xb.x);
+    }
+    __syncthreads();
+    lds_fft_any<1, NTM, FC_EPT>(buf, fdm, 1, 8, twm);
+    float2 rr[FC_EPT];
+    double ss = 0.0;
+    const size_t ra = (size_t)(2 * q) * n;
+#pragma unroll
+    for (int j = 0; j < FC_EPT; ++j) {
+        rr[j] = make_float2(0.0f, 0.0f);
+        const int X = (int)threadIdx.x + j * kBlock;
+        const int x = X - off;
+        if (X < M && x >= 0 && x < n) {
+            const float2 v = buf[lds_slot(X)];
+            const float a = g[ra + x] - v.x;
+            ss += (double)a * (double)a;
+            const float b = g[ra + n + x] - v.y;
+            ss += (double)b * (double)b;
+            rr[j] = make_float2(a, b);
+            if (r_out) {
+                r_out[ra + x] = a;
+                r_out[ra + n + x] = b;
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < FC_EPT; ++j) {
+        const int X = (int)threadIdx.x + j * kBlock;
+        const int x = X - off;
+        if (X < M && x >= 0 && x < n) buf[lds_slot(x)] = rr[j];
+    }
+    __syncthreads();
+    lds_fft_any<-1, NTN, FFT_EPT>(buf, fdn, 1, 8, twn);
+    const int hn = n / 2 + 1;
+    for (int k = threadIdx.x; k < hn; k += kBlock) {
+        const float2 Z = buf[lds_slot(k)];
+        const float2 Zc = cconj(buf[lds_slot(k == 0 ? 0 : n - k)]);
+        const float2 Xa = cscale(cadd(Z, Zc), 0.5f);
+        const float2 D = csub(Z, Zc);
+        const float2 Xb = make_float2(0.5f * D.y, -0.5f * D.x);  // D / (2i)
+        *reinterpret_cast<float4*>(Tp + (size_t)k * tsp + 2 * q) = make_float4(Xa.x, Xa.y, Xb.x, Xb.y);
+    }
+    if (partials) {
+        const double t = block_sum(ss, red);
+        if (threadIdx.x == 0) partials[blockIdx.x] = t;
+    }
+}
+
+// The preconditioner's inverse row pass (t = P r, two observed rows) and the
+// forward row pass of A^T on the FFT-blur grid, where those rows sit at
+// (y + off, x + off), in one workgroup.
+template <int NTN, int NTM>
+__global__ __launch_bounds__(kBlock) void precond_fc_blurT_kernel(
+    const float2* __restrict__ Tp, int n_, int tsp, FftDesc fdn, const float2* __restrict__ twn,
+    float* __restrict__ t_out, int off, float2* __restrict__ Tc, int M_, int tsc, FftDesc fdm,
+    const float2* __restrict__ twm, int pair0) {
+    extern __shared__ float2 buf[];
+    const int M = NTM > 0 ? NTM : M_;
+    const int n = NTN > 0 ? NTN : n_;
+    const int q = xcd_block(blockIdx.x, gridDim.x);
+    const int hn = n / 2 + 1;
+    for (int k = threadIdx.x; k < hn; k += kBlock) {
+        const float4 v = *reinterpret_cast<const float4*>(Tp + (size_t)k * tsp + 2 * q);
+        float2 Xa = make_float2(v.x, v.y), Xb = make_float2(v.z, v.w);
+        const bool edge = (k == 0) || (2 * k == n);
+        if (edge) {  // spectra of real rows are real at DC and Nyquist
+            Xa.y = 0.0f;
+            Xb.y = 0.0f;
+        }
+        buf[lds_slot(k)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
+        if (!edge) buf[lds_slot(n - k)] = make_float2(Xa.x + Xb.y, -Xa.y + Xb.x);
+    }
+    __syncthreads();
+    lds_fft_any<1, NTN, FFT_EPT>(buf, fdn, 1, 8, twn);
+    if (t_out) {
+        const size_t ra = (size_t)(2 * q) * n;
+        for (int x = threadIdx.x; x < n; x += kBlock) {
+            const float2 v = buf[lds_slot(x)];
+            t_out[ra + x] = v.x;
+            t_out[ra + n + x] = v.y;
+        }
+    }
+    float2 e[FC_EPT];
+#pragma unroll
+    for (int j = 0; j < FC_EPT; ++j) {
+        const int X = (int)threadIdx.x + j * kBlock;
+        const int x = X - off;
+        e[j] = (X < M && x >= 0 && x < n) ? buf[lds_slot(x)] : make_float2(0.0f, 0.0f);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < FC_EPT; ++j) {
+        const int X = (int)threadIdx.x + j * kBlock;
+        if (X < M) buf[lds_slot(X)] = e[j];
+    }
+    __syncthreads();
+    lds_fft_any<-1, NTM, FC_EPT>(buf, fdm, 1, 8, twm);
+    const int half = M / 2 + 1;
+    const int pb = pair0 + q;
+    for (int k = threadIdx.x; k < half; k += kBlock) {
+        const float2 Z = buf[lds_slot(k)];
+        const float2 Zc = cconj(buf[lds_slot(k == 0 ? 0 : M - k)]);
+        const float2 Xa = cscale(cadd(Z, Zc), 0.5f);
+        const float2 D = csub(Z, Zc);
+        const float2 Xb = make_float2(0.5f * D.y, -0.5f * D.x);
+        *reinterpret_cast<float4*>(Tc + (size_t)k * tsc + 2 * pb) = make_float4(Xa.x, Xa.y, Xb.x, Xb.y);
+    }
+}
+
 // ---- launchers ------------------------------------------------------------
 
-static hipError_t fc_rows_fwd(const FftConv& c, const float* src, int S, int off, int y_lo, int y_hi,
+hipError_t launch_fc_rows_fwd(const FftConv& c, const float* src, int S, int off, int y_lo, int y_hi,
                               hipStream_t s) {
     const int G = fc_pairs_per_block(c.M);
     const int p0 = y_lo / 2, p1 = (y_hi + 1) / 2;
@@ -214,7 +347,7 @@ static hipError_t fc_rows_fwd(const FftConv& c, const float* src, int S, int off
     return hipGetLastError();
 }
 
-static hipError_t fc_cols(const FftConv& c, int conj_h, int y_lo, int y_hi, int mode, float2* cspec, hipStream_t s) {
+hipError_t launch_fc_cols(const FftConv& c, int conj_h, int y_lo, int y_hi, int mode, float2* cspec, hipStream_t s) {
     const int CC = fc_cols_per_block(c.M);
     const int half = c.M / 2 + 1;
     const float inv = (float)(1.0 / ((double)c.M * (double)c.M));
@@ -228,7 +361,7 @@ static hipError_t fc_cols(const FftConv& c, int conj_h, int y_lo, int y_hi, int 
     return hipGetLastError();
 }
 
-static hipError_t fc_rows_inv(const FftConv& c, int oy, int ox, int D, float* dst, const float* g, int accum,
+hipError_t launch_fc_rows_inv(const FftConv& c, int oy, int ox, int D, float* dst, const float* g, int accum,
                               double* partials, int* n_partials, hipStream_t s) {
     const int G = fc_pairs_per_block(c.M);
     const int p0 = oy / 2, p1 = (oy + D + 1) / 2;
@@ -251,26 +384,61 @@ int fftconv_partials_count(int M, int n) {
 }
 
 hipError_t launch_fftconv_spectrum(const FftConv& c, const float* psf, int p, hipStream_t s) {
-    hipError_t e = fc_rows_fwd(c, psf, p, 0, 0, p, s);
+    hipError_t e = launch_fc_rows_fwd(c, psf, p, 0, 0, p, s);
     if (e != hipSuccess) return e;
-    return fc_cols(c, 0, 0, p, 1, c.H, s);
+    return launch_fc_cols(c, 0, 0, p, 1, c.H, s);
 }
 
 hipError_t launch_fftconv_blur(const FftConv& c, const float* u, int n, int p, const float* g, float* r,
                                double* partials, int* n_partials, hipStream_t s) {
     const int N = n + p - 1;
-    hipError_t e = fc_rows_fwd(c, u, N, 0, 0, N, s);
-    if (e == hipSuccess) e = fc_cols(c, 0, 0, N, 0, nullptr, s);
-    if (e == hipSuccess) e = fc_rows_inv(c, p - 1, p - 1, n, r, g, 0, g ? partials : nullptr, n_partials, s);
+    hipError_t e = launch_fc_rows_fwd(c, u, N, 0, 0, N, s);
+    if (e == hipSuccess) e = launch_fc_cols(c, 0, 0, N, 0, nullptr, s);
+    if (e == hipSuccess) e = launch_fc_rows_inv(c, p - 1, p - 1, n, r, g, 0, g ? partials : nullptr, n_partials, s);
     return e;
 }
 
 hipError_t launch_fftconv_blurT(const FftConv& c, const float* t, int n, int p, float* w, int accum, hipStream_t s) {
     const int N = n + p - 1;
-    hipError_t e = fc_rows_fwd(c, t, n, p - 1, p - 1, N, s);
-    if (e == hipSuccess) e = fc_cols(c, 1, p - 1, N, 0, nullptr, s);
-    if (e == hipSuccess) e = fc_rows_inv(c, 0, 0, N, w, nullptr, accum, nullptr, nullptr, s);
+    hipError_t e = launch_fc_rows_fwd(c, t, n, p - 1, p - 1, N, s);
+    if (e == hipSuccess) e = launch_fc_cols(c, 1, p - 1, N, 0, nullptr, s);
+    if (e == hipSuccess) e = launch_fc_rows_inv(c, 0, 0, N, w, nullptr, accum, nullptr, nullptr, s);
     return e;
+}
+
+hipError_t launch_fc_residual_precond_rows(const FftConv& c, int n, int p, const float* g, float* r_out,
+                                           double* partials, int* n_partials, const PrecondRows& pr, hipStream_t s) {
+    if (!fftconv_fusable(c, n, pr)) return hipErrorInvalidValue;
+    const int blocks = n / 2;
+    if (n_partials) *n_partials = blocks;
+    const size_t lds = lds_bytes(c.M > n ? c.M : n, 0);
+    if (c.M == kFixedM && n == kFixedN)
+        hipLaunchKernelGGL((fc_residual_precond_kernel<kFixedM, kFixedN>), dim3(blocks), dim3(kBlock), lds, s,
+                           (const float2*)c.T, c.M, c.ts, c.fd, c.tw, (p - 1) / 2, n, p - 1, g, r_out, partials, pr.T,
+                           pr.ts, pr.fd, pr.tw);
+    else
+        hipLaunchKernelGGL((fc_residual_precond_kernel<0, 0>), dim3(blocks), dim3(kBlock), lds, s, (const float2*)c.T,
+                           c.M, c.ts, c.fd, c.tw, (p - 1) / 2, n, p - 1, g, r_out, partials, pr.T, pr.ts, pr.fd,
+                           pr.tw);
+    return hipGetLastError();
+}
+
+hipError_t launch_precond_rows_fc_fwd(const FftConv& c, int n, int p, const PrecondRows& pr, float* t_out,
+                                      hipStream_t s) {
+    if (!fftconv_fusable(c, n, pr)) return hipErrorInvalidValue;
+    const size_t lds = lds_bytes(c.M > n ? c.M : n, 0);
+    if (c.M == kFixedM && n == kFixedN)
+        hipLaunchKernelGGL((precond_fc_blurT_kernel<kFixedN, kFixedM>), dim3(n / 2), dim3(kBlock), lds, s,
+                           (const float2*)pr.T, n, pr.ts, pr.fd, pr.tw, t_out, p - 1, c.T, c.M, c.ts, c.fd, c.tw,
+                           (p - 1) / 2);
+    else
+        hipLaunchKernelGGL((precond_fc_blurT_kernel<0, 0>), dim3(n / 2), dim3(kBlock), lds, s, (const float2*)pr.T, n,
+                           pr.ts, pr.fd, pr.tw, t_out, p - 1, c.T, c.M, c.ts, c.fd, c.tw, (p - 1) / 2);
+    return hipGetLastError();
+}
+
+bool fftconv_fusable(const FftConv& c, int n, const PrecondRows& pr) {
+    return c.T && n % 2 == 0 && n <= FFT_MAX_ELEMS && pr.T && pr.fd.n == n;
 }
 
 }  // namespace mlba

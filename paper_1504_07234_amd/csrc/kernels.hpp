@@ -165,6 +165,36 @@ hipError_t launch_fftconv_blur(const FftConv& c, const float* u, int n, int p, c
 // w = A^T t, or w += A^T t (accum)
 hipError_t launch_fftconv_blurT(const FftConv& c, const float* t, int n, int p, float* w, int accum, hipStream_t s);
 
+// The transposed half spectrum of the BCCB preconditioner (n x n, row stride
+// ts complex) and its transform plan, for the passes fused with the FFT blur.
+struct PrecondRows {
+    float2* T;
+    int ts;
+    FftDesc fd;
+    const float2* tw;
+};
+// The three passes of the FFT blur, one launch each: forward rows of the
+// S x S image placed at (off, off) (rows outside [y_lo, y_hi) are zero),
+// columns (mode 0: product with the PSF spectrum or its conjugate and the
+// inverse; mode 1: forward only into cspec), inverse rows cropped to the
+// D x D window at (oy, ox) with the epilogue g - . (partials) / plain / +=.
+hipError_t launch_fc_rows_fwd(const FftConv& c, const float* src, int S, int off, int y_lo, int y_hi, hipStream_t s);
+hipError_t launch_fc_cols(const FftConv& c, int conj_h, int y_lo, int y_hi, int mode, float2* cspec, hipStream_t s);
+hipError_t launch_fc_rows_inv(const FftConv& c, int oy, int ox, int D, float* dst, const float* g, int accum,
+                              double* partials, int* n_partials, hipStream_t s);
+// Row passes fused with the preconditioner's (n even, n <= 2048):
+// the residual rows r = g - A u (after launch_fc_cols of u) with their
+// squared-norm partials, then the preconditioner's forward row transform of r
+// into pr.T (r written only when r_out is given);
+hipError_t launch_fc_residual_precond_rows(const FftConv& c, int n, int p, const float* g, float* r_out,
+                                           double* partials, int* n_partials, const PrecondRows& pr, hipStream_t s);
+// the preconditioner's inverse row transform of pr.T (t = P r, written to
+// t_out when given), then the forward rows of A^T t on the grid (followed by
+// launch_fc_cols with the conjugate spectrum and launch_fc_rows_inv).
+hipError_t launch_precond_rows_fc_fwd(const FftConv& c, int n, int p, const PrecondRows& pr, float* t_out,
+                                      hipStream_t s);
+bool fftconv_fusable(const FftConv& c, int n, const PrecondRows& pr);
+
 // ---- framelet -----------------------------------------------------------
 // analysis level with dilation d: bands (+)= B_i B_j v, low (+)= B_0 B_0 v
 hipError_t launch_analysis_level(const float* v, int N, int d, float* zlev, float* low,

@@ -64,8 +64,42 @@ int dalloc_t(mlba_plan_s* P, T** ptr, size_t count) {
 void release_events(mlba_plan_s* P) {
     for (hipEvent_t e : P->prof_ev) hipEventDestroy(e);
     P->prof_ev.clear();
+    P->prof_phase.clear();
+    P->prof_kernel.clear();
+    P->prof_nl.clear();
+    P->prof_nm.clear();
     P->prof_cap = P->prof_used = 0;
+    P->prof_cur = -1;
 }
+
+constexpr int kMarks = mlba_plan_s::kMaxMarks;
+
+// Start of a profiled iteration (while event slots remain).
+int prof_iter_begin(mlba_plan_s* P, hipStream_t s) {
+    P->prof_cur = -1;
+    if (P->prof_used >= P->prof_cap) return MLBA_OK;
+    if ((P->prof_seen++ % P->prof_stride) != 0) return MLBA_OK;
+    const int it = P->prof_used++;
+    P->prof_cur = it;
+    P->prof_nm[it] = 1;
+    HIPCHK(hipEventRecord(P->prof_ev[(size_t)it * kMarks], s));
+    return MLBA_OK;
+}
+
+// The time since the previous event belongs to `launches` launches of `kernel`
+// in `phase` (no-op outside a profiled iteration).
+int prof_mark(mlba_plan_s* P, int phase, int kernel, int launches, hipStream_t s) {
+    const int it = P->prof_cur;
+    if (it < 0 || P->prof_nm[it] >= kMarks) return MLBA_OK;
+    const size_t i = (size_t)it * kMarks + P->prof_nm[it]++;
+    P->prof_phase[i] = phase;
+    P->prof_kernel[i] = kernel;
+    P->prof_nl[i] = launches;
+    HIPCHK(hipEventRecord(P->prof_ev[i], s));
+    return MLBA_OK;
+}
+
+#define MARK(ph, k) STCHK(prof_mark(P, MLBA_PHASE_##ph, MLBA_KERNEL_##k, 1, s))
 
 void free_plan(mlba_plan_s* P) {
     release_events(P);
@@ -80,7 +114,14 @@ size_t NN(const mlba_plan_s* P) { return (size_t)P->N * P->N; }
 int do_blur(mlba_plan_s* P, const float* u, const float* g, float* y, bool want_norm, int* nparts,
             hipStream_t s) {
     if (P->blur_fft) {
-        HIPCHK(launch_fftconv_blur(P->fc, u, P->n, P->p, g, y, want_norm ? P->partials : nullptr, nparts, s));
+        const int n = P->n, p = P->p, N = n + p - 1;
+        HIPCHK(launch_fc_rows_fwd(P->fc, u, N, 0, 0, N, s));
+        MARK(BLUR, FC_ROWS_FWD);
+        HIPCHK(launch_fc_cols(P->fc, 0, 0, N, 0, nullptr, s));
+        MARK(BLUR, FC_COLS);
+        HIPCHK(launch_fc_rows_inv(P->fc, p - 1, p - 1, n, y, g, 0, g && want_norm ? P->partials : nullptr, nparts,
+                                  s));
+        MARK(BLUR, FC_ROWS_INV);
         return MLBA_OK;
     }
     BatchImage d = plan_desc(P);
@@ -88,20 +129,74 @@ int do_blur(mlba_plan_s* P, const float* u, const float* g, float* y, bool want_
     d.g = g;
     d.r = y;
     HIPCHK(launch_conv_job(blur_job(d), P->p, 1, P->conv_rows[0], want_norm ? P->partials : nullptr, nparts, s));
+    MARK(BLUR, CONV_BLUR);
+    return MLBA_OK;
+}
+
+// The preconditioner's half spectrum and transform plan (BCCB plans).
+PrecondRows precond_rows(const mlba_plan_s* P) {
+    PrecondRows pr{};
+    pr.T = (float2*)P->swork;
+    pr.ts = P->ts;
+    pr.fd = P->fd;
+    pr.tw = P->tw;
+    return pr;
+}
+
+// FFT blur with the BCCB preconditioner: the residual's inverse row pass and
+// the preconditioner's forward row pass run as one launch (as do the
+// preconditioner's inverse row pass and the forward row pass of A^T).
+bool fused_fft_path(const mlba_plan_s* P) {
+    return P->blur_fft && P->precond == MLBA_PRECOND_BCCB && fftconv_fusable(P->fc, P->n, precond_rows(P));
+}
+
+// r = g - A u with its partials and the preconditioner's forward row pass of r
+int do_blur_residual_precond_rows(mlba_plan_s* P, const float* u, const float* g, int* nparts, hipStream_t s) {
+    const int n = P->n, p = P->p, N = n + p - 1;
+    HIPCHK(launch_fc_rows_fwd(P->fc, u, N, 0, 0, N, s));
+    MARK(BLUR, FC_ROWS_FWD);
+    HIPCHK(launch_fc_cols(P->fc, 0, 0, N, 0, nullptr, s));
+    MARK(BLUR, FC_COLS);
+    HIPCHK(launch_fc_residual_precond_rows(P->fc, n, p, g, nullptr, P->partials, nparts, precond_rows(P), s));
+    MARK(BLUR, FC_RESIDUAL_PRECOND_ROWS);
+    return MLBA_OK;
+}
+
+// the preconditioner's inverse row pass, then w (+)= A^T t
+int do_precond_rows_blurT(mlba_plan_s* P, float* w, int accum, hipStream_t s) {
+    const int n = P->n, p = P->p, N = n + p - 1;
+    HIPCHK(launch_precond_rows_fc_fwd(P->fc, n, p, precond_rows(P), nullptr, s));
+    MARK(BLUR_T, PRECOND_ROWS_FC_FWD);
+    HIPCHK(launch_fc_cols(P->fc, 1, p - 1, N, 0, nullptr, s));
+    MARK(BLUR_T, FC_COLS);
+    HIPCHK(launch_fc_rows_inv(P->fc, 0, 0, N, w, nullptr, accum, nullptr, nullptr, s));
+    MARK(BLUR_T, FC_ROWS_INV);
     return MLBA_OK;
 }
 
 // w = A^T y (+ fold of the reflective padding)
+int do_blurT_fft(mlba_plan_s* P, const float* y, float* w, int accum, hipStream_t s) {
+    const int n = P->n, p = P->p, N = n + p - 1;
+    HIPCHK(launch_fc_rows_fwd(P->fc, y, n, p - 1, p - 1, N, s));
+    MARK(BLUR_T, FC_ROWS_FWD);
+    HIPCHK(launch_fc_cols(P->fc, 1, p - 1, N, 0, nullptr, s));
+    MARK(BLUR_T, FC_COLS);
+    HIPCHK(launch_fc_rows_inv(P->fc, 0, 0, N, w, nullptr, accum, nullptr, nullptr, s));
+    MARK(BLUR_T, FC_ROWS_INV);
+    return MLBA_OK;
+}
+
 int do_blurT(mlba_plan_s* P, const float* y, float* w, hipStream_t s) {
-    if (P->blur_fft) {
-        HIPCHK(launch_fftconv_blurT(P->fc, y, P->n, P->p, w, 0, s));
-        return MLBA_OK;
-    }
+    if (P->blur_fft) return do_blurT_fft(P, y, w, 0, s);
     BatchImage d = plan_desc(P);
     d.t = const_cast<float*>(y);
     d.w = w;
     HIPCHK(launch_conv_job(blurT_job(d), P->p, 0, P->conv_rows[1], nullptr, nullptr, s));
-    if (P->bc == MLBA_BC_REFLECT) HIPCHK(launch_fold_reflect(P->wext, P->n + P->p - 1, w, P->n, P->c, s));
+    MARK(BLUR_T, CONV_BLUR_T);
+    if (P->bc == MLBA_BC_REFLECT) {
+        HIPCHK(launch_fold_reflect(P->wext, P->n + P->p - 1, w, P->n, P->c, s));
+        MARK(BLUR_T, FOLD_REFLECT);
+    }
     return MLBA_OK;
 }
 
@@ -111,15 +206,22 @@ int do_precond(mlba_plan_s* P, const float* r, float* t, double alpha, hipStream
     if (P->precond == MLBA_PRECOND_BCCB) {
         float2* T = (float2*)P->swork;
         HIPCHK(launch_fft_rows_r2c(r, n, T, P->ts, P->fd, P->tw, s));
+        MARK(PRECOND, FFT_ROWS_FWD);
         HIPCHK(launch_fft_cols_filter(T, n, P->ts, P->spec, (float)alpha, inv, P->fd, P->tw, s));
+        MARK(PRECOND, FFT_COLS);
         HIPCHK(launch_fft_rows_c2r(T, n, P->ts, t, P->fd, P->tw, s));
+        MARK(PRECOND, FFT_ROWS_INV);
     } else if (P->precond == MLBA_PRECOND_DCT) {
         float* Tr = (float*)P->swork;
         HIPCHK(launch_dct_rows_fwd(r, n, Tr, P->ts, P->fd, P->tw, P->dtw, s));
+        MARK(PRECOND, FFT_ROWS_FWD);
         HIPCHK(launch_dct_cols_filter(Tr, n, P->ts, P->spec, (float)alpha, inv, P->fd, P->tw, P->dtw, s));
+        MARK(PRECOND, FFT_COLS);
         HIPCHK(launch_dct_rows_inv(Tr, n, P->ts, t, P->fd, P->tw, P->dtw, s));
+        MARK(PRECOND, FFT_ROWS_INV);
     } else if (r != t) {
         HIPCHK(hipMemcpyAsync(t, r, (size_t)n * n * sizeof(float), hipMemcpyDeviceToDevice, s));
+        MARK(PRECOND, OTHER);
     }
     return MLBA_OK;
 }
@@ -148,13 +250,19 @@ int do_ct_precond(mlba_plan_s* P, const float* r, float* t, double alpha, int ac
     if (P->precond == MLBA_PRECOND_BCCB) {
         float2* T = (float2*)P->swork;
         HIPCHK(launch_fft_rows_r2c(r, n, T, P->ts, P->fd, P->tw, s));
+        MARK(PRECOND, FFT_ROWS_FWD);
         HIPCHK(launch_fft_cols_filter(T, n, P->ts, P->spec, (float)alpha, inv, P->fd, P->tw, s, P->lamc));
+        MARK(PRECOND, FFT_COLS);
         HIPCHK(launch_fft_rows_c2r(T, n, P->ts, t, P->fd, P->tw, s, accum));
+        MARK(PRECOND, FFT_ROWS_INV);
     } else {
         float* Tr = (float*)P->swork;
         HIPCHK(launch_dct_rows_fwd(r, n, Tr, P->ts, P->fd, P->tw, P->dtw, s));
+        MARK(PRECOND, FFT_ROWS_FWD);
         HIPCHK(launch_dct_cols_filter(Tr, n, P->ts, P->spec, (float)alpha, inv, P->fd, P->tw, P->dtw, s, P->lamr));
+        MARK(PRECOND, FFT_COLS);
         HIPCHK(launch_dct_rows_inv(Tr, n, P->ts, t, P->fd, P->tw, P->dtw, s, accum));
+        MARK(PRECOND, FFT_ROWS_INV);
     }
     return MLBA_OK;
 }
@@ -167,11 +275,16 @@ int do_ct_precond_ns(mlba_plan_s* P, const float* r, float* t, const double* rn_
     const float inv = (float)(1.0 / ((double)n * (double)n));
     float2* T = (float2*)P->swork;
     HIPCHK(launch_fft_rows_r2c(r, n, T, P->ts, P->fd, P->tw, s));
+    MARK(PRECOND, FFT_ROWS_FWD);
     HIPCHK(launch_fft_cols_forward(T, n, P->ts, P->fd, P->tw, s));
+    MARK(PRECOND, FFT_COLS);
     HIPCHK(launch_ns_alpha(T, n, P->ts, P->spec, P->ns, P->partials, rn_sq, P->psf, P->p, noise, q, rho,
                            alpha_first, first, 12, hist, s));
+    STCHK(prof_mark(P, MLBA_PHASE_PRECOND, MLBA_KERNEL_OTHER, 1 + 2 * 12, s));
     HIPCHK(launch_fft_cols_filter_inverse(T, n, P->ts, P->spec, P->ns, inv, P->lamc, P->fd, P->tw, s));
+    MARK(PRECOND, FFT_COLS);
     HIPCHK(launch_fft_rows_c2r(T, n, P->ts, t, P->fd, P->tw, s, accum));
+    MARK(PRECOND, FFT_ROWS_INV);
     return MLBA_OK;
 }
 
@@ -192,6 +305,7 @@ int do_analysis(mlba_plan_s* P, const float* v, float* z, bool accum, hipStream_
         const bool last = lev == P->levels;
         float* low = last ? z : P->tmp[lev & 1];
         HIPCHK(launch_analysis_level(in, P->N, d, zlev, low, accum ? 1 : 0, (accum && last) ? 1 : 0, s));
+        MARK(ANALYSIS, ANALYSIS_LEVEL);
         in = low;
     }
     return MLBA_OK;
@@ -211,6 +325,7 @@ int do_synthesis(mlba_plan_s* P, const float* z, float* f, bool thr, const float
         const bool top = lev == P->levels;
         HIPCHK(launch_synthesis_level(zlev, low, P->N, d, out, level_mu(mu, lev), thr ? delta : 1.0f,
                                       (thr && top) ? 1 : 0, thr ? 1 : 0, s));
+        MARK(SYNTHESIS, SYNTHESIS_LEVEL);
         low = out;
     }
     return MLBA_OK;
@@ -221,13 +336,16 @@ int do_synthesis(mlba_plan_s* P, const float* z, float* f, bool thr, const float
 int do_shrink_synthesis(mlba_plan_s* P, const float* omega, float* f, const float* mub, float delta,
                         hipStream_t s) {
     const float* low[4] = {omega, P->lows[0], P->lows[1], P->lows[2]};
-    for (int l = 1; l < P->levels; ++l)
+    for (int l = 1; l < P->levels; ++l) {
         HIPCHK(launch_lowpass_level(low[l - 1], P->N, 1 << (l - 1), P->lows[l - 1], s));
+        MARK(SYNTHESIS, LOWPASS_LEVEL);
+    }
     const float* s_in = nullptr;
     for (int lev = P->levels; lev >= 1; --lev) {
         float* out = lev == 1 ? f : P->tmp[lev & 1];
         HIPCHK(launch_shrink_synthesis_level(low[lev - 1], s_in, P->N, 1 << (lev - 1), out, level_mu(mub, lev),
                                              delta, s));
+        MARK(SYNTHESIS, SHRINK_SYNTHESIS);
         s_in = out;
     }
     return MLBA_OK;
@@ -235,10 +353,7 @@ int do_shrink_synthesis(mlba_plan_s* P, const float* omega, float* f, const floa
 
 // omega += A^T y (implicit state: the Bregman update of eq. (MLBA2) before W)
 int do_blurT_acc(mlba_plan_s* P, const float* y, float* omega, hipStream_t s) {
-    if (P->blur_fft) {
-        HIPCHK(launch_fftconv_blurT(P->fc, y, P->n, P->p, omega, 1, s));
-        return MLBA_OK;
-    }
+    if (P->blur_fft) return do_blurT_fft(P, y, omega, 1, s);
     BatchImage d = plan_desc(P);
     d.t = const_cast<float*>(y);
     d.w = omega;
@@ -246,7 +361,11 @@ int do_blurT_acc(mlba_plan_s* P, const float* y, float* omega, hipStream_t s) {
     const bool fold = P->bc == MLBA_BC_REFLECT;
     j.acc = fold ? 0 : 1;
     HIPCHK(launch_conv_job(j, P->p, 0, P->conv_rows[1], nullptr, nullptr, s));
-    if (fold) HIPCHK(launch_fold_reflect(P->wext, P->n + P->p - 1, omega, P->n, P->c, s, 1));
+    MARK(BLUR_T, CONV_BLUR_T);
+    if (fold) {
+        HIPCHK(launch_fold_reflect(P->wext, P->n + P->p - 1, omega, P->n, P->c, s, 1));
+        MARK(BLUR_T, FOLD_REFLECT);
+    }
     return MLBA_OK;
 }
 
@@ -804,27 +923,25 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
         return MLBA_OK;
     };
 
-    const int launches[MLBA_NPHASES] = {
-        implicit ? 2 * P->levels - 1 : P->levels, 2, P->precond == MLBA_PRECOND_NONE ? 1 : (ns ? 4 + 1 + 24 : 3),
-        alg4 ? 0 : (P->bc == MLBA_BC_REFLECT ? 2 : 1), implicit ? 0 : P->levels};
+    // marks are recorded only inside profiled iterations; every exit path clears them
+    struct ProfGuard {
+        mlba_plan_s* P;
+        ~ProfGuard() { P->prof_cur = -1; }
+    } prof_guard{P};
+    const bool fused = !alg4 && !alg2 && fused_fft_path(P);
     for (int i = 0; i < iters; ++i) {
         if (i - ring_base >= P->rn_cap) {
             if (track) STCHK(drain(i));
             ring_base = i;
         }
-        hipEvent_t* ev = nullptr;
-        if (P->prof_used < P->prof_cap) {
-            ev = P->prof_ev.data() + (size_t)P->prof_used * (MLBA_NPHASES + 1);
-            ++P->prof_used;
-            for (int q = 0; q < MLBA_NPHASES; ++q) P->prof_launch[q] += launches[q];
-        }
-        if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_SYNTHESIS], s));
+        STCHK(prof_iter_begin(P, s));
         if (implicit) STCHK(do_shrink_synthesis(P, z, P->u, mub, (float)delta[i], s));
         else STCHK(do_synthesis(P, z, P->u, true, mub, (float)delta[i], s));
         int np = 0;
-        if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_BLUR], s));
-        STCHK(do_blur(P, P->u, g, P->r, true, &np, s));
+        if (fused) STCHK(do_blur_residual_precond_rows(P, P->u, g, &np, s));
+        else STCHK(do_blur(P, P->u, g, P->r, true, &np, s));
         HIPCHK(launch_sum_partials(P->partials, np, P->rn + (i - ring_base), s));
+        MARK(BLUR, REDUCE);
         if (stop && (i % stop->check_every) == 0) {
             STCHK(drain(i + 1));
             if (sqrt(rn_host.back()) <= stop->gamma * stop->noise_norm) {
@@ -835,7 +952,6 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
                 break;
             }
         }
-        if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_PRECOND], s));
         if (alg4) {
             // eq. (Alg4): the direction C^T (C C^T + alpha I)^{-1} r, no A^T product
             float* dst = implicit ? z : P->t;
@@ -846,44 +962,51 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
             } else {
                 STCHK(do_ct_precond(P, P->r, dst, alpha[i], implicit ? 1 : 0, s));
             }
-            if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_BLUR_T], s));
-            if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_ANALYSIS], s));
             if (!implicit) STCHK(do_analysis(P, P->t, z, true, s));
-            if (ev) HIPCHK(hipEventRecord(ev[MLBA_NPHASES], s));
+            P->prof_cur = -1;
             done = i + 1;
             continue;
         }
         if (alg2) {
             int steps = 0;
+            const int cur = P->prof_cur;  // the PCG is timed as one sequence
+            P->prof_cur = -1;
             STCHK(do_pcg(P, alpha[i], pcg_max, pcg_tol, &steps, s));
+            P->prof_cur = cur;
+            STCHK(prof_mark(P, MLBA_PHASE_PRECOND, MLBA_KERNEL_OTHER, 1, s));
             if (prm->pcg_steps_out) prm->pcg_steps_out[i] = steps;
-            if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_BLUR_T], s));
             float* tsol = P->pcg;  // the CG solution t
             if (implicit) {
                 STCHK(do_blurT_acc(P, tsol, z, s));
-                if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_ANALYSIS], s));
             } else {
                 STCHK(do_blurT(P, tsol, P->w, s));
-                if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_ANALYSIS], s));
                 STCHK(do_analysis(P, P->w, z, true, s));
             }
-            if (ev) HIPCHK(hipEventRecord(ev[MLBA_NPHASES], s));
+            P->prof_cur = -1;
             done = i + 1;
             continue;
         }
-        STCHK(do_precond(P, P->r, P->t, alpha[i], s));
-        if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_BLUR_T], s));
-        if (implicit) {
-            STCHK(do_blurT_acc(P, P->t, z, s));
-            if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_ANALYSIS], s));
+        if (fused) {
+            // the column pass of P; its inverse row pass runs with A^T's forward one
+            const float inv = (float)(1.0 / ((double)P->n * (double)P->n));
+            HIPCHK(launch_fft_cols_filter((float2*)P->swork, P->n, P->ts, P->spec, (float)alpha[i], inv, P->fd,
+                                          P->tw, s));
+            MARK(PRECOND, FFT_COLS);
+            STCHK(do_precond_rows_blurT(P, implicit ? z : P->w, implicit ? 1 : 0, s));
+            if (!implicit) STCHK(do_analysis(P, P->w, z, true, s));
         } else {
-            STCHK(do_blurT(P, P->t, P->w, s));
-            if (ev) HIPCHK(hipEventRecord(ev[MLBA_PHASE_ANALYSIS], s));
-            STCHK(do_analysis(P, P->w, z, true, s));
+            STCHK(do_precond(P, P->r, P->t, alpha[i], s));
+            if (implicit) {
+                STCHK(do_blurT_acc(P, P->t, z, s));
+            } else {
+                STCHK(do_blurT(P, P->t, P->w, s));
+                STCHK(do_analysis(P, P->w, z, true, s));
+            }
         }
-        if (ev) HIPCHK(hipEventRecord(ev[MLBA_NPHASES], s));
+        P->prof_cur = -1;
         done = i + 1;
     }
+    P->prof_cur = -1;
     if (!stopped) {
         if (implicit) STCHK(do_shrink_synthesis(P, z, f_out, mub, (float)delta[done], s));
         else STCHK(do_synthesis(P, z, f_out, true, mub, (float)delta[done], s));
@@ -914,14 +1037,14 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
 }
 
 int mlba_profile_begin(mlba_plan_t P, int max_iters) {
-    if (!P || max_iters < 1 || max_iters > (1 << 20)) return MLBA_EINVAL;
+    if (!P || max_iters < 1 || max_iters > (1 << 16)) return MLBA_EINVAL;
     release_events(P);
-    for (int q = 0; q < MLBA_NPHASES; ++q) P->prof_launch[q] = 0;
-    const size_t count = (size_t)max_iters * (MLBA_NPHASES + 1);
+    const size_t count = (size_t)max_iters * kMarks;
     P->prof_ev.reserve(count);
     for (size_t i = 0; i < count; ++i) {
         hipEvent_t e;
-        hipError_t err = hipEventCreate(&e);
+        // timestamps only: no system-scope fence when the event completes
+        hipError_t err = hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
         if (err != hipSuccess) {
             mlba_internal_set_hip(err);
             release_events(P);
@@ -929,27 +1052,61 @@ int mlba_profile_begin(mlba_plan_t P, int max_iters) {
         }
         P->prof_ev.push_back(e);
     }
+    P->prof_phase.assign(count, 0);
+    P->prof_kernel.assign(count, 0);
+    P->prof_nl.assign(count, 0);
+    P->prof_nm.assign((size_t)max_iters, 0);
     P->prof_cap = max_iters;
     P->prof_used = 0;
+    P->prof_cur = -1;
+    P->prof_seen = 0;
+    P->prof_stride = 1;
+    return MLBA_OK;
+}
+
+int mlba_profile_every(mlba_plan_t P, int stride) {
+    if (!P || stride < 1) return MLBA_EINVAL;
+    P->prof_stride = stride;
+    P->prof_seen = 0;
     return MLBA_OK;
 }
 
 int mlba_profile_end(mlba_plan_t P, double* ms, int* launches, int* iters) {
     if (!P || !ms) return MLBA_EINVAL;
-    for (int q = 0; q < MLBA_NPHASES; ++q) ms[q] = 0.0;
+    for (int q = 0; q < MLBA_NPHASES; ++q) {
+        ms[q] = 0.0;
+        if (launches) launches[q] = 0;
+    }
+    for (int k = 0; k < MLBA_NKERNELS; ++k) {
+        P->prof_kms[k] = 0.0;
+        P->prof_kl[k] = 0;
+    }
     for (int it = 0; it < P->prof_used; ++it) {
-        hipEvent_t* ev = P->prof_ev.data() + (size_t)it * (MLBA_NPHASES + 1);
-        HIPCHK(hipEventSynchronize(ev[MLBA_NPHASES]));
-        for (int q = 0; q < MLBA_NPHASES; ++q) {
+        const size_t b = (size_t)it * kMarks;
+        const int nm = P->prof_nm[it];
+        if (nm < 2) continue;
+        HIPCHK(hipEventSynchronize(P->prof_ev[b + nm - 1]));
+        for (int m = 1; m < nm; ++m) {
             float t = 0.0f;
-            HIPCHK(hipEventElapsedTime(&t, ev[q], ev[q + 1]));
-            ms[q] += (double)t;
+            HIPCHK(hipEventElapsedTime(&t, P->prof_ev[b + m - 1], P->prof_ev[b + m]));
+            const int ph = P->prof_phase[b + m], k = P->prof_kernel[b + m], nl = P->prof_nl[b + m];
+            ms[ph] += (double)t;
+            if (launches) launches[ph] += nl;
+            P->prof_kms[k] += (double)t;
+            P->prof_kl[k] += nl;
         }
     }
-    if (launches)
-        for (int q = 0; q < MLBA_NPHASES; ++q) launches[q] = P->prof_launch[q];
     if (iters) *iters = P->prof_used;
     release_events(P);
+    return MLBA_OK;
+}
+
+int mlba_profile_kernels(mlba_plan_t P, double* ms, int* launches) {
+    if (!P || !ms) return MLBA_EINVAL;
+    for (int k = 0; k < MLBA_NKERNELS; ++k) {
+        ms[k] = P->prof_kms[k];
+        if (launches) launches[k] = P->prof_kl[k];
+    }
     return MLBA_OK;
 }
 

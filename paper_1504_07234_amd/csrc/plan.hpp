@@ -59,10 +59,17 @@ struct mlba_plan_s {
     double* rn = nullptr;      // ||r^k||^2 history ring
     int rn_cap = 0;
     std::vector<void*> allocs;
-    // phase timing
-    std::vector<hipEvent_t> prof_ev;  // (MLBA_NPHASES + 1) per recorded iteration
-    int prof_cap = 0, prof_used = 0;
-    int prof_launch[MLBA_NPHASES] = {0, 0, 0, 0, 0};
+    // kernel timing (mlba_profile_begin / end): per profiled iteration one
+    // start event and up to kMaxMarks - 1 marks, each an event recorded after
+    // a launch (or a launch sequence) and labelled with the phase and kernel
+    // whose time since the previous event it measures
+    static constexpr int kMaxMarks = 48;
+    std::vector<hipEvent_t> prof_ev;
+    std::vector<int> prof_phase, prof_kernel, prof_nl, prof_nm;
+    int prof_cap = 0, prof_used = 0, prof_cur = -1;
+    int prof_stride = 1, prof_seen = 0;  // record every prof_stride-th iteration
+    double prof_kms[MLBA_NKERNELS] = {};  // per kernel, from the last mlba_profile_end
+    int prof_kl[MLBA_NKERNELS] = {};
 };
 
 int mlba_internal_opnorm(mlba_plan_s* P, double alpha, int iters, double* out, hipStream_t s);

@@ -184,8 +184,11 @@ class Plan:
               "mlba_shrink_synthesis")
         return out
 
-    def profile_begin(self, max_iters: int):
+    def profile_begin(self, max_iters: int, every: int = 1):
+        """Record HIP events in the next restorations: every `every`-th iteration, at most `max_iters`."""
         check(self._lib.mlba_profile_begin(self._h, int(max_iters)), "mlba_profile_begin")
+        if every != 1:
+            check(self._lib.mlba_profile_every(self._h, int(every)), "mlba_profile_every")
 
     def profile_end(self):
         """{phase: (milliseconds summed, kernel launches)} and the iteration count."""
@@ -194,6 +197,13 @@ class Plan:
         iters = ctypes.c_int()
         check(self._lib.mlba_profile_end(self._h, ms, launches, ctypes.byref(iters)), "mlba_profile_end")
         return {ph: (ms[i], launches[i]) for i, ph in enumerate(_lib.PHASES)}, iters.value
+
+    def profile_kernels(self):
+        """{kernel: (milliseconds summed, launches)} of the last profile_end (kernels that ran)."""
+        ms = (ctypes.c_double * len(_lib.KERNELS))()
+        launches = (ctypes.c_int * len(_lib.KERNELS))()
+        check(self._lib.mlba_profile_kernels(self._h, ms, launches), "mlba_profile_kernels")
+        return {k: (ms[i], launches[i]) for i, k in enumerate(_lib.KERNELS) if launches[i] > 0}
 
     # -- restoration -------------------------------------------------------
     def restore(self, g, *, alpha=0.05, alpha_kind: int = _lib.ALPHA_CONST, alpha_ratio: float = 1.0,

@@ -42,6 +42,22 @@ def test_binding_covers_every_declared_symbol():
     assert set(declared_symbols()) <= set(_lib.SIGNATURES)
 
 
+def _header_defines(prefix):
+    text = open(os.path.join(ROOT, "include", "mlba.h")).read()
+    return {m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+(" + prefix + r"\w*)\s+(\d+)", text)}
+
+
+def test_phase_and_kernel_tables_match_the_header():
+    ph = _header_defines("MLBA_PHASE_")
+    assert len(_lib.PHASES) == _header_defines("MLBA_NPHASES")["MLBA_NPHASES"]
+    for name, idx in ph.items():
+        assert _lib.PHASES[idx] == name[len("MLBA_PHASE_"):].lower()
+    ks = _header_defines("MLBA_KERNEL_")
+    assert len(_lib.KERNELS) == _header_defines("MLBA_NKERNELS")["MLBA_NKERNELS"] == len(ks)
+    for name, idx in ks.items():
+        assert _lib.KERNELS[idx] == name[len("MLBA_KERNEL_"):].lower()
+
+
 def test_status_strings():
     lib = _lib.load()
     assert lib.mlba_status_string(0) == b"ok"

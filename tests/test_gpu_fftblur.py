@@ -97,3 +97,63 @@ def test_autotune_picks_a_working_blur(mlba):
         assert t["blur"] in ("fft", "direct") and t["fft_ms"] is not None
         u = synth.rng(3).standard_normal((plan.N, plan.N))
         assert rel_err(host(plan.apply_A(cuda(u))), ob.blur(u, w.psf, ob.RECT)) < 1e-5
+
+
+@pytest.mark.parametrize("n,p,pc,implicit", [(97, 9, 2, False), (96, 9, 1, True), (96, 9, 0, True),
+                                             (96, 9, 0, False)])
+def test_restore_small_fft_blur_and_kernel_profile(mlba, n, p, pc, implicit):
+    """Without the BCCB preconditioner (P = I, or the DCT of Algorithm 3) the
+    FFT blur runs its three passes; with it, the residual row pass is fused
+    with the preconditioner's forward row pass and the preconditioner's
+    inverse row pass with the forward row pass of A^T.  Both against the
+    oracle, and the kernel profile of the iteration."""
+    announce(f"restore n={n} p={p} precond={pc} FFT blur implicit={implicit}")
+    gen = synth.rng(4400 + n + pc)
+    H = synth.gaussian_psf(p, 1.5)
+    N = n + p - 1
+    truth = synth.shapes_image(N, gen, n_rect=6, n_disk=3)
+    b = ob.blur(truth, H, ob.RECT)
+    g = synth.add_noise(b, synth.white_noise((n, n), gen), 0.01)
+    iters = 25
+    alphas = np.full(iters + 1, 0.05)
+    deltas = omlba.delta_table(H, n, ob.RECT, pc, alphas, 0.0, iters + 1)
+    with mlba.Plan(n, p, mlba.RECT, pc, 2, cuda(H)) as plan:
+        plan.set_blur(mlba.BLUR_FFT)
+        plan.profile_begin(iters)
+        f, info = plan.restore(cuda(g), alpha_table=alphas[:iters], mu=1e-3, delta_table=deltas, iters=iters,
+                               implicit=implicit)
+        phases, rec = plan.profile_end()
+        kern = plan.profile_kernels()
+        f = host(f)
+    ref = omlba.mlba(g, H, ob.RECT, pc, 2, alphas[:iters], deltas, 1e-3, iters)
+    print(f"  image {rel_err(f, ref['f']):.2e} rnorm {rel_err(info.rnorm, ref['rnorm']):.2e}", flush=True)
+    assert rel_err(f, ref["f"]) < 1e-4
+    assert rel_err(info.rnorm, ref["rnorm"]) < 1e-4
+    assert rec == iters
+    fused = pc == 0
+    assert kern["fc_cols"][1] == 2 * iters
+    assert kern.get("fc_residual_precond_rows", (0, 0))[1] == (iters if fused else 0)
+    assert kern.get("precond_rows_fc_fwd", (0, 0))[1] == (iters if fused else 0)
+    assert kern.get("fc_rows_fwd", (0, 0))[1] == (1 if fused else 2) * iters
+    assert kern.get("fft_cols", (0, 0))[1] == (0 if pc == 2 else iters)
+    assert kern.get("fft_rows_fwd", (0, 0))[1] == (iters if pc == 1 else 0)
+    assert kern["shrink_synthesis" if implicit else "synthesis_level"][1] == 2 * iters
+    assert ("analysis_level" in kern) == (not implicit)
+    # every launch of an iteration is accounted to one phase
+    assert sum(v[1] for v in phases.values()) == sum(v[1] for v in kern.values())
+    assert abs(sum(v[0] for v in phases.values()) - sum(v[0] for v in kern.values())) < 1e-6
+
+
+def test_profile_every(mlba):
+    """Recording every k-th iteration: the count and the per-launch averages."""
+    announce("profile every 3rd iteration")
+    n, p = 64, 9
+    H = synth.gaussian_psf(p, 1.5)
+    g = synth.rng(5).random((n, n))
+    with mlba.Plan(n, p, mlba.RECT, mlba.BCCB, 2, cuda(H)) as plan:
+        plan.profile_begin(100, every=3)
+        plan.restore(cuda(g), alpha=0.05, mu=1e-3, delta=0.3, iters=10, implicit=True)
+        _, rec = plan.profile_end()
+        kern = plan.profile_kernels()
+    assert rec == 4  # iterations 0, 3, 6, 9
+    assert kern["conv_blur"][1] == 4 and kern["conv_blur"][0] > 0.0

@@ -90,23 +90,33 @@ def test_512_workloads_200_iterations(mlba, name):
 
 def test_full_size_iterations(mlba):
     """2048 x 2048 observed, 31 x 31 disk, 3 levels: the bench workload, a few
-    iterations compared in full (state z and image)."""
+    iterations compared in full (state z and image), with the direct blur and
+    with the FFT blur (whose residual and A^T row passes run fused with the
+    preconditioner's row passes), in both states."""
     w = synth.make_workload("rect-bccb-2048")
     iters = 3
     announce(f"restore rect-bccb-2048 {iters} iterations")
     g, _ = observed(w, oblur)
     alphas = np.full(iters, w.alpha0)
     deltas = np.full(iters + 1, 0.3)
-    with mlba.Plan(w.n, w.p, w.bc, w.precond, w.levels, cuda(w.psf)) as plan:
-        import torch
-        z = torch.zeros((plan.bands, plan.N, plan.N), dtype=torch.float32, device="cuda")
-        f, info = plan.restore(cuda(g), alpha_table=alphas, mu=w.mu, delta_table=deltas, iters=iters, z=z)
-        f, z = host(f), host(z)
     ref = omlba.mlba(g, w.psf, w.bc, w.precond, w.levels, alphas, deltas, w.mu, iters)
-    print(f"  image {rel_err(f, ref['f']):.2e} state {rel_err(z, ref['z']):.2e}", flush=True)
-    assert rel_err(f, ref["f"]) < 1e-5
-    assert rel_err(z, ref["z"]) < 1e-5
-    assert rel_err(info.rnorm, ref["rnorm"]) < 1e-6
+    import torch
+    for blur, implicit in ((mlba.BLUR_DIRECT, False), (mlba.BLUR_FFT, False), (mlba.BLUR_FFT, True)):
+        announce(f"  blur={'fft' if blur == mlba.BLUR_FFT else 'direct'} implicit={implicit}")
+        with mlba.Plan(w.n, w.p, w.bc, w.precond, w.levels, cuda(w.psf)) as plan:
+            plan.set_blur(blur)
+            shape = (plan.N, plan.N) if implicit else (plan.bands, plan.N, plan.N)
+            z = torch.zeros(shape, dtype=torch.float32, device="cuda")
+            f, info = plan.restore(cuda(g), alpha_table=alphas, mu=w.mu, delta_table=deltas, iters=iters, z=z,
+                                   implicit=implicit)
+            if implicit:
+                z = plan.analysis(z)  # z = W omega
+            f, z = host(f), host(z)
+        print(f"  image {rel_err(f, ref['f']):.2e} state {rel_err(z, ref['z']):.2e} "
+              f"rnorm {rel_err(info.rnorm, ref['rnorm']):.2e}", flush=True)
+        assert rel_err(f, ref["f"]) < 1e-5
+        assert rel_err(z, ref["z"]) < 1e-5
+        assert rel_err(info.rnorm, ref["rnorm"]) < 1e-6
 
 
 @pytest.mark.parametrize("n,p,bc,pc,L", [(96, 17, 0, 0, 2), (96, 17, 1, 1, 3), (192, 11, 3, 0, 2),
