@@ -20,13 +20,19 @@ __device__ __forceinline__ int mod_pos(int x, int m) {
 }
 
 // Reflected index; *flipped is set when the position lands on a mirrored copy.
+// Positions within one length of the image (the usual halos) need no modulo.
 __device__ __forceinline__ int reflect_index(int x, int S, bool* flipped) {
+    if (x >= -S && x < 2 * S) {
+        *flipped = x < 0 || x >= S;
+        return x < 0 ? -1 - x : (x >= S ? 2 * S - 1 - x : x);
+    }
     int s = mod_pos(x, 2 * S);
     *flipped = s >= S;
     return *flipped ? 2 * S - 1 - s : s;
 }
 
 __device__ __forceinline__ int reflect_index(int x, int S) {
+    if (x >= -S && x < 2 * S) return x < 0 ? -1 - x : (x >= S ? 2 * S - 1 - x : x);
     int s = mod_pos(x, 2 * S);
     return s >= S ? 2 * S - 1 - s : s;
 }
@@ -39,11 +45,12 @@ __device__ __forceinline__ float fetch_ext(const float* __restrict__ src, int S,
     return src[(size_t)reflect_index(y, S) * S + reflect_index(x, S)];
 }
 
-// Soft threshold of eq. (soft), scaled: delta * sgn(v) * max(|v| - mu, 0).
-// A tie |v| == mu gives 0.
+// Soft threshold of eq. (soft), scaled: delta * sgn(v) * max(|v| - mu, 0),
+// written as delta * (v - median(-mu, v, mu)): the same value in every case
+// (v - mu and v + mu are the differences the sign form rounds), and a tie
+// |v| == mu gives 0.
 __device__ __forceinline__ float shrink(float v, float mu, float delta) {
-    float a = fabsf(v) - mu;
-    return a > 0.0f ? copysignf(a * delta, v) : 0.0f;
+    return (v - __builtin_amdgcn_fmed3f(v, -mu, mu)) * delta;
 }
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {

@@ -329,106 +329,156 @@ __global__ __launch_bounds__(kBlock) void lowpass_level_kernel(const float* __re
 // s_in, the output of the level above.  Same workgroup geometry as
 // synthesis_tile: one thread per column of an FR_TY-row strip, 256 - 2D
 // output columns per workgroup.
-template <int D>
+template <int D, int TY>
+struct SsTile {
+    static constexpr int IW = kBlock - 2 * D;  // output columns per workgroup
+    static constexpr int HR = TY + 4 * D;      // low-pass rows: y0-2D .. y0+TY+2D-1
+    static constexpr int BR = TY + 2 * D;      // band rows: y0-D .. y0+TY+D-1
+    static constexpr int LW = kBlock + 2 * D;  // low-pass columns: x0-2D .. x0+kBlock-1
+    static constexpr int LOW_FLOATS = HR * LW;
+    static constexpr int YS_FLOATS = 3 * TY * kBlock;
+    static constexpr int LDS_FLOATS = LOW_FLOATS > YS_FLOATS ? LOW_FLOATS : YS_FLOATS;
+};
+
+// The low-pass tile is staged in LDS once (coalesced rows, reflected
+// indices); each thread then filters its extended column from LDS.  The LDS
+// is reused for the three x-synthesis inputs after the last x-filter.
+//
+// Arithmetic: the masks are applied unnormalised, b0 = [1 2 1] / 4,
+// b1 = [-1 0 1] sqrt(2)/4, b2 = [-1 2 -1] / 4, i.e. b_i = c_i m_i with
+// c = (1/4, sqrt(2)/4, 1/4); the three x (and y) filters then share a + e and
+// 2b.  Band (i, j) computed with the unnormalised masks is the band divided by
+// c_i c_j, and S_mu(c v) = c S_{mu/c}(v) for c > 0, so it is thresholded at
+// mu / (c_i c_j); its synthesis with the unnormalised transposes is weighted
+// by F_ij = delta (c_i c_j)^2 (both scale factors and the step).  Below the top
+// level the (0, 0) input is the level above's output itself, weighted by
+// c_0^2 only.
+// Per band (i, j): the threshold of the unnormalised coefficient and its
+// synthesis weight (computed on the host).
+struct SsCoef {
+    float thr[3][3];
+    float wgt[3][3];
+};
+
+template <int D, int TY, bool SIN>
 __device__ __forceinline__ void shrink_synthesis_tile(const float* __restrict__ low, const float* __restrict__ s_in,
-                                                      int N, float* __restrict__ out, const LevelMu& mu,
-                                                      float delta, int bx, int by,
-                                                      float (*ys)[FR_TY][kBlock]) {
-    constexpr int IW = kBlock - 2 * D;
-    constexpr int HR = FR_TY + 4 * D;  // rows of x-filtered low: y0-2D .. y0+FR_TY+2D-1
-    constexpr int BR = FR_TY + 2 * D;  // rows of bands: y0-D .. y0+FR_TY+D-1
-    const int x0 = bx * IW;
-    const int y0 = by * FR_TY;
+                                                      int N, float* __restrict__ out, const SsCoef& cf, int bx,
+                                                      int by, float* lds) {
+    using G = SsTile<D, TY>;
+    constexpr int HR = G::HR, BR = G::BR, LW = G::LW;
+    const int x0 = bx * G::IW;
+    const int y0 = by * TY;
     const int c = threadIdx.x;
     const int xe = x0 - D + c;  // extended column of this thread
-    const int xm = reflect_index(xe, N), xl = reflect_index(xe - D, N), xr = reflect_index(xe + D, N);
-
-    int rowo[HR];  // row offsets of the x-filtered rows (reflected)
+    float* L = lds;             // [HR][LW]
+    // row offsets first (uniform), so that every load of a column is in flight at once
+    size_t rowo[HR];
 #pragma unroll
-    for (int q = 0; q < HR; ++q) rowo[q] = reflect_index(y0 - 2 * D + q, N) * N;
-    float sc[BR];
-    if (s_in) {
+    for (int q = 0; q < HR; ++q) rowo[q] = (size_t)reflect_index(y0 - 2 * D + q, N) * N;
 #pragma unroll
-        for (int q = 0; q < BR; ++q) sc[q] = s_in[(size_t)reflect_index(y0 - D + q, N) * N + xm];
+    for (int k0 = 0; k0 < LW; k0 += kBlock) {
+        const int k = k0 + c;
+        if (k0 + kBlock <= LW || k < LW) {
+            const int col = reflect_index(x0 - 2 * D + k, N);
+            float v[HR];
+#pragma unroll
+            for (int q = 0; q < HR; ++q) v[q] = low[rowo[q] + col];
+#pragma unroll
+            for (int q = 0; q < HR; ++q) L[q * LW + k] = v[q];
+        }
     }
+    float sc[BR];
+    if constexpr (SIN) {
+        const int xm = reflect_index(xe, N);
+#pragma unroll
+        for (int q = 0; q < BR; ++q) sc[q] = s_in[rowo[q + D] + xm];
+    }
+    __syncthreads();
 
-    float acc[3][FR_TY];
+    float acc[3][TY];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int r = 0; r < FR_TY; ++r) acc[i][r] = 0.0f;
+        for (int r = 0; r < TY; ++r) acc[i][r] = 0.0f;
 
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        // x-filter h_i of low at this column (re-read per i from cache)
+        // one filter pass at a time: keeps the three passes' loads from piling up in registers
+        __builtin_amdgcn_sched_barrier(0);
+        // unnormalised x-filter m_i of low at this column
         float hh[HR];
 #pragma unroll
         for (int q = 0; q < HR; ++q) {
-            const float* row = low + rowo[q];
-            const float a = row[xl], b = row[xm], e = row[xr];
-            if (i == 0) hh[q] = fmaf(0.25f, a + e, 0.5f * b);
-            else if (i == 1) hh[q] = kB1 * (e - a);
-            else hh[q] = fmaf(-0.25f, a + e, 0.5f * b);
+            const float a = L[q * LW + c], b = L[q * LW + c + D], e = L[q * LW + c + 2 * D];
+            if (i == 0) hh[q] = fmaf(2.0f, b, a + e);
+            else if (i == 1) hh[q] = e - a;
+            else hh[q] = fmaf(2.0f, b, -(a + e));
         }
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            const bool is_low = (i == 0 && j == 0);
-            const float m = is_low ? mu.low : mu.band[pair_slot(i, j)];
+            const bool from_above = SIN && i == 0 && j == 0;  // folds once the loops unroll
+            const float m = cf.thr[i][j];
             float col[BR];
 #pragma unroll
             for (int q = 0; q < BR; ++q) {
-                const float a = hh[q], b = hh[q + D], e = hh[q + 2 * D];
-                float v;
-                if (j == 0) v = fmaf(0.25f, a + e, 0.5f * b);
-                else if (j == 1) v = kB1 * (e - a);
-                else v = fmaf(-0.25f, a + e, 0.5f * b);
-                col[q] = (is_low && s_in) ? sc[q] : shrink(v, m, delta);
+                if (from_above) {
+                    col[q] = sc[q];
+                } else {
+                    const float a = hh[q], b = hh[q + D], e = hh[q + 2 * D];
+                    float v;
+                    if (j == 0) v = fmaf(2.0f, b, a + e);
+                    else if (j == 1) v = e - a;
+                    else v = fmaf(2.0f, b, -(a + e));
+                    col[q] = v - __builtin_amdgcn_fmed3f(v, -m, m);
+                }
             }
+            const float f = cf.wgt[i][j];
 #pragma unroll
-            for (int r = 0; r < FR_TY; ++r) {
+            for (int r = 0; r < TY; ++r) {
                 const float wm = col[r], w0 = col[r + D], wp = col[r + 2 * D];  // y-d, y, y+d
-                if (j == 0) acc[i][r] += fmaf(0.25f, wp + wm, 0.5f * w0);
-                else if (j == 1) acc[i][r] = fmaf(kB1, wm - wp, acc[i][r]);
-                else acc[i][r] += fmaf(-0.25f, wp + wm, 0.5f * w0);
+                float t;
+                if (j == 0) t = fmaf(2.0f, w0, wp + wm);
+                else if (j == 1) t = wm - wp;
+                else t = fmaf(2.0f, w0, -(wp + wm));
+                acc[i][r] = fmaf(f, t, acc[i][r]);
             }
         }
     }
+    __syncthreads();  // the low-pass tile is no longer read
+    float* ys = lds;  // [3][TY][kBlock]
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int r = 0; r < FR_TY; ++r) ys[i][r][c] = acc[i][r];
+        for (int r = 0; r < TY; ++r) ys[(i * TY + r) * kBlock + c] = acc[i][r];
     __syncthreads();
 
     if (c < D || c >= kBlock - D) return;
     const int x = x0 + c - D;
     if (x >= N) return;
-    for (int r = 0; r < FR_TY; ++r) {
+#pragma unroll
+    for (int r = 0; r < TY; ++r) {
         const int y = y0 + r;
         if (y >= N) break;
-        float sum = 0.0f;
-        {
-            const float l = ys[0][r][c - D], mm = ys[0][r][c], rr = ys[0][r][c + D];
-            sum += fmaf(0.25f, rr + l, 0.5f * mm);
-        }
-        {
-            const float l = ys[1][r][c - D], rr = ys[1][r][c + D];
-            sum = fmaf(kB1, l - rr, sum);
-        }
-        {
-            const float l = ys[2][r][c - D], mm = ys[2][r][c], rr = ys[2][r][c + D];
-            sum += fmaf(-0.25f, rr + l, 0.5f * mm);
-        }
+        const float* y0r = ys + (0 * TY + r) * kBlock;
+        const float* y1r = ys + (1 * TY + r) * kBlock;
+        const float* y2r = ys + (2 * TY + r) * kBlock;
+        float sum = fmaf(2.0f, y0r[c], y0r[c + D] + y0r[c - D]);
+        sum += y1r[c - D] - y1r[c + D];
+        sum += fmaf(2.0f, y2r[c], -(y2r[c + D] + y2r[c - D]));
         out[(size_t)y * N + x] = sum;
     }
 }
 
+// rows per strip of the shrink-synthesis of dilation D
 template <int D>
+constexpr int ss_rows() { return 8; }
+
+template <int D, bool SIN>
 __global__ __launch_bounds__(kBlock) void shrink_synthesis_kernel(const float* __restrict__ low,
                                                                   const float* __restrict__ s_in, int N,
-                                                                  float* __restrict__ out, LevelMu mu,
-                                                                  float delta) {
-    __shared__ float ys[3][FR_TY][kBlock];
-    shrink_synthesis_tile<D>(low, s_in, N, out, mu, delta, blockIdx.x, blockIdx.y, ys);
+                                                                  float* __restrict__ out, SsCoef cf) {
+    __shared__ float lds[SsTile<D, ss_rows<D>()>::LDS_FLOATS];
+    shrink_synthesis_tile<D, ss_rows<D>(), SIN>(low, s_in, N, out, cf, blockIdx.x, blockIdx.y, lds);
 }
 
 hipError_t launch_lowpass_level(const float* v, int N, int d, float* out, hipStream_t s) {
@@ -447,8 +497,23 @@ template <int D>
 static hipError_t launch_ss(const float* low, const float* s_in, int N, float* out, LevelMu mu, float delta,
                             hipStream_t s) {
     constexpr int IW = kBlock - 2 * D;
-    dim3 grid((N + IW - 1) / IW, (N + FR_TY - 1) / FR_TY);
-    hipLaunchKernelGGL((shrink_synthesis_kernel<D>), grid, dim3(kBlock), 0, s, low, s_in, N, out, mu, delta);
+    constexpr int TY = ss_rows<D>();
+    const double cs[3] = {0.25, 0.35355339059327376, 0.25};  // c_i of b_i = c_i m_i
+    SsCoef cf;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const double cc = cs[i] * cs[j];
+            const double m = (i == 0 && j == 0) ? mu.low : mu.band[pair_slot(i, j)];
+            cf.thr[i][j] = (float)(m / cc);
+            cf.wgt[i][j] = (float)(delta * cc * cc);
+        }
+    dim3 grid((N + IW - 1) / IW, (N + TY - 1) / TY);
+    if (s_in) {
+        cf.wgt[0][0] = 0.0625f;  // c_0^2: the level above's output enters unthresholded
+        hipLaunchKernelGGL((shrink_synthesis_kernel<D, true>), grid, dim3(kBlock), 0, s, low, s_in, N, out, cf);
+    } else {
+        hipLaunchKernelGGL((shrink_synthesis_kernel<D, false>), grid, dim3(kBlock), 0, s, low, s_in, N, out, cf);
+    }
     return hipGetLastError();
 }
 
