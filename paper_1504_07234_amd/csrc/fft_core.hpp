@@ -38,11 +38,17 @@ __device__ __forceinline__ void twiddle_powers(const float2* __restrict__ tw, in
     w[1] = twiddle<DIR>(tw, e);
     if constexpr (R >= 3) w[2] = twiddle<DIR>(tw, 2 * e);
     if constexpr (R >= 4) w[3] = cmul(w[1], w[2]);
-    if constexpr (R == 8) {
+    if constexpr (R >= 8) {
         w[4] = twiddle<DIR>(tw, 4 * e);
         w[5] = cmul(w[1], w[4]);
         w[6] = cmul(w[2], w[4]);
         w[7] = cmul(w[3], w[4]);
+    }
+    if constexpr (R == 9) w[8] = twiddle<DIR>(tw, 8 * e);
+    if constexpr (R == 16) {
+        w[8] = twiddle<DIR>(tw, 8 * e);
+#pragma unroll
+        for (int r = 9; r < 16; ++r) w[r] = cmul(w[r - 8], w[8]);
     }
 }
 
@@ -62,9 +68,81 @@ __device__ __forceinline__ void dft4(float2* v) {
     v[3] = csub(d02, d13);
 }
 
+template <int DIR>
+__device__ __forceinline__ void dft3(float2& a, float2& b, float2& c) {
+    const float s3 = 0.86602540378443865f;  // sqrt(3)/2
+    const float2 t = cadd(b, c);
+    const float2 d = cscale(mul_i<DIR>(csub(b, c)), s3);
+    const float2 m = make_float2(a.x - 0.5f * t.x, a.y - 0.5f * t.y);
+    a = cadd(a, t);
+    b = cadd(m, d);
+    c = csub(m, d);
+}
+
+// exp(DIR 2 pi i q / 16) and exp(DIR 2 pi i q / 9)
+template <int DIR>
+__device__ __forceinline__ float2 w16(int q) {
+    const float c1 = 0.92387953251128676f, s1 = 0.38268343236508977f, h = 0.70710678118654752f;
+    const float sg = (float)DIR;
+    switch (q) {
+        case 1: return make_float2(c1, sg * s1);
+        case 2: return make_float2(h, sg * h);
+        case 3: return make_float2(s1, sg * c1);
+        case 4: return make_float2(0.0f, sg);
+        case 6: return make_float2(-h, sg * h);
+        default: return make_float2(-c1, -sg * s1);  // q == 9
+    }
+}
+
+template <int DIR>
+__device__ __forceinline__ float2 w9(int q) {
+    const float sg = (float)DIR;
+    switch (q) {
+        case 1: return make_float2(0.76604444311897804f, sg * 0.64278760968653933f);
+        case 2: return make_float2(0.17364817766693035f, sg * 0.98480775301220806f);
+        default: return make_float2(-0.93969262078590838f, sg * 0.34202014332566873f);  // q == 4
+    }
+}
+
 template <int R, int DIR>
 __device__ __forceinline__ void dft(float2* v) {
-    if constexpr (R == 2) {
+    if constexpr (R == 16) {
+        // 4 x 4: n = k1 + 4 n2, k = m + 4 j
+        float2 y[4][4];
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            float2 t[4] = {v[k1], v[k1 + 4], v[k1 + 8], v[k1 + 12]};
+            dft4<DIR>(t);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) y[k1][m] = (k1 == 0 || m == 0) ? t[m] : cmul(t[m], w16<DIR>(k1 * m));
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            float2 t[4] = {y[0][m], y[1][m], y[2][m], y[3][m]};
+            dft4<DIR>(t);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[m + 4 * j] = t[j];
+        }
+    } else if constexpr (R == 9) {
+        // 3 x 3: n = k1 + 3 n2, k = m + 3 j
+        float2 y[3][3];
+#pragma unroll
+        for (int k1 = 0; k1 < 3; ++k1) {
+            float2 a = v[k1], b = v[k1 + 3], c = v[k1 + 6];
+            dft3<DIR>(a, b, c);
+            y[k1][0] = a;
+            y[k1][1] = k1 == 0 ? b : cmul(b, w9<DIR>(k1));
+            y[k1][2] = k1 == 0 ? c : cmul(c, w9<DIR>(2 * k1));
+        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            float2 a = y[0][m], b = y[1][m], c = y[2][m];
+            dft3<DIR>(a, b, c);
+            v[m] = a;
+            v[m + 3] = b;
+            v[m + 6] = c;
+        }
+    } else if constexpr (R == 2) {
         const float2 t = v[0];
         v[0] = cadd(t, v[1]);
         v[1] = csub(t, v[1]);
@@ -166,17 +244,18 @@ __device__ void lds_fft(float2* buf, const FftDesc& fd, int nseq, int seq_shift,
 }
 
 // ---- fixed-size transforms ------------------------------------------------
-// The same stages with the length known at compile time and one sequence per
-// workgroup (kBlock threads): every index, stride and loop bound folds to a
-// constant.  The radix order and the arithmetic of each butterfly are those
-// of lds_fft with the plan built on the host (8s, then 4 or 2, then 3s), so
-// both give bit-identical results.
+// The same Stockham stages with the length known at compile time and one
+// sequence per workgroup (kBlock threads): every index, stride and loop bound
+// folds to a constant, and the plan may use radix-16 and radix-9 butterflies
+// (fewer passes through LDS than the run-time plan's 8/4/2/3).
 struct FixedPlan {
     int nst;
     int radix[24];
     int ns[24];
 };
 
+// Radices 16 (then 8, 4, 2) for the power of two and 9 (then 3) for the
+// power of three: the fewest passes through LDS.
 __host__ __device__ constexpr FixedPlan fixed_plan(int n) {
     FixedPlan p{};
     int a = 0, b = 0, m = n;
@@ -188,13 +267,21 @@ __host__ __device__ constexpr FixedPlan fixed_plan(int n) {
         m /= 3;
         ++b;
     }
+    while (a >= 4 && a != 5 && a != 6) {  // 32 = 8 4 and 64 = 8 8 keep two balanced stages
+        p.radix[p.nst++] = 16;
+        a -= 4;
+    }
     while (a >= 3) {
         p.radix[p.nst++] = 8;
         a -= 3;
     }
     if (a == 2) p.radix[p.nst++] = 4;
     if (a == 1) p.radix[p.nst++] = 2;
-    for (int i = 0; i < b; ++i) p.radix[p.nst++] = 3;
+    while (b >= 2) {
+        p.radix[p.nst++] = 9;
+        b -= 2;
+    }
+    if (b == 1) p.radix[p.nst++] = 3;
     int ns = 1;
     for (int s = 0; s < p.nst; ++s) {
         p.ns[s] = ns;
