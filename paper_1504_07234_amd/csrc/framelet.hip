@@ -323,6 +323,61 @@ __global__ __launch_bounds__(kBlock) void lowpass_level_kernel(const float* __re
     }
 }
 
+// low_1 = (b0 x b0) v (dilation 1) and low_2 = (b0 x b0) low_1 (dilation 2)
+// in one pass over v.  Thread c holds the extended column xe = x0 - 2 + c;
+// low_1 is computed there for the strip rows and a 2-row halo straight from
+// v (b0 is symmetric, so at a reflected position it equals low_1 at the
+// mirrored one, with the same additions), kept in LDS for the dilation-2
+// filter, and written for the strip's own rows and columns.
+constexpr int LP2_TY = 8;
+
+__global__ __launch_bounds__(kBlock) void lowpass_two_levels_kernel(const float* __restrict__ v, int N,
+                                                                    float* __restrict__ low1,
+                                                                    float* __restrict__ low2) {
+    constexpr int IW = kBlock - 4;
+    constexpr int HR = LP2_TY + 4;  // low_1 rows y0-2 .. y0+TY+1
+    __shared__ float l1[HR][kBlock];
+    const int x0 = blockIdx.x * IW;
+    const int y0 = blockIdx.y * LP2_TY;
+    const int c = threadIdx.x;
+    const int xe = x0 - 2 + c;
+    const int xm = reflect_index(xe, N), xl = reflect_index(xe - 1, N), xr = reflect_index(xe + 1, N);
+    size_t rowo[HR + 2];
+#pragma unroll
+    for (int q = 0; q < HR + 2; ++q) rowo[q] = (size_t)reflect_index(y0 - 3 + q, N) * N;
+    float h[HR + 2];
+#pragma unroll
+    for (int q = 0; q < HR + 2; ++q) {
+        const float* row = v + rowo[q];
+        h[q] = fmaf(0.25f, row[xl] + row[xr], 0.5f * row[xm]);
+    }
+#pragma unroll
+    for (int q = 0; q < HR; ++q) l1[q][c] = fmaf(0.25f, h[q] + h[q + 2], 0.5f * h[q + 1]);
+    const bool own = c >= 2 && c < kBlock - 2 && xe < N;
+    if (own) {
+#pragma unroll
+        for (int r = 0; r < LP2_TY; ++r) {
+            if (y0 + r < N) low1[(size_t)(y0 + r) * N + xe] = l1[r + 2][c];
+        }
+    }
+    __syncthreads();
+    if (!own) return;
+    float g[HR];
+#pragma unroll
+    for (int q = 0; q < HR; ++q) g[q] = fmaf(0.25f, l1[q][c - 2] + l1[q][c + 2], 0.5f * l1[q][c]);
+#pragma unroll
+    for (int r = 0; r < LP2_TY; ++r) {
+        if (y0 + r >= N) break;
+        low2[(size_t)(y0 + r) * N + xe] = fmaf(0.25f, g[r] + g[r + 4], 0.5f * g[r + 2]);
+    }
+}
+
+hipError_t launch_lowpass_two_levels(const float* v, int N, float* low1, float* low2, hipStream_t s) {
+    dim3 grid((N + kBlock - 5) / (kBlock - 4), (N + LP2_TY - 1) / LP2_TY);
+    hipLaunchKernelGGL(lowpass_two_levels_kernel, grid, dim3(kBlock), 0, s, v, N, low1, low2);
+    return hipGetLastError();
+}
+
 // Level with dilation D of W^T(delta S_mu(.)) fed by low = low_{l-1}: the
 // eight bands of the level are computed from low, thresholded and transposed;
 // the (0,0) input is the thresholded low-pass (s_in == null: top level) or

@@ -209,6 +209,8 @@ hipError_t launch_soft_threshold(const float* z, float* x, int bands, size_t ban
 hipError_t launch_lowpass_level(const float* v, int N, int d, float* out, hipStream_t s);
 // one level of W^T(delta S_mu(W omega)) from low = low_{l-1}; s_in = output of
 // the level above, or null at the top level (thresholded low-pass)
+// low1 = (b0 x b0) v, low2 = (b0 x b0) low1 (dilations 1 and 2) in one pass
+hipError_t launch_lowpass_two_levels(const float* v, int N, float* low1, float* low2, hipStream_t s);
 hipError_t launch_shrink_synthesis_level(const float* low, const float* s_in, int N, int d, float* out,
                                          LevelMu mu, float delta, hipStream_t s);
 // batched framelet levels (all images share `levels`); tiles per image:

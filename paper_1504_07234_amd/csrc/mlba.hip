@@ -336,7 +336,13 @@ int do_synthesis(mlba_plan_s* P, const float* z, float* f, bool thr, const float
 int do_shrink_synthesis(mlba_plan_s* P, const float* omega, float* f, const float* mub, float delta,
                         hipStream_t s) {
     const float* low[4] = {omega, P->lows[0], P->lows[1], P->lows[2]};
-    for (int l = 1; l < P->levels; ++l) {
+    int l = 1;
+    if (P->levels >= 3) {  // the first two levels of the chain in one pass
+        HIPCHK(launch_lowpass_two_levels(omega, P->N, P->lows[0], P->lows[1], s));
+        MARK(SYNTHESIS, LOWPASS_LEVEL);
+        l = 3;
+    }
+    for (; l < P->levels; ++l) {
         HIPCHK(launch_lowpass_level(low[l - 1], P->N, 1 << (l - 1), P->lows[l - 1], s));
         MARK(SYNTHESIS, LOWPASS_LEVEL);
     }
