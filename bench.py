@@ -45,17 +45,18 @@ PROFILE_EVERY = 4              # kernel events on every 4th timed iteration (the
 # (FETCH_SIZE x2.000, WRITE_SIZE x1.000).  A figure belongs to the kernel sources
 # it was taken with: when their hash differs it is reported as null.
 TRAFFIC = {}
+# the sources that define each kernel's device code
 TRAFFIC_SOURCES = {
-    "shrink_synthesis": ("framelet.hip", "common.hpp", "kernels.hpp"),
-    "lowpass_level": ("framelet.hip", "common.hpp", "kernels.hpp"),
+    "shrink_synthesis": ("framelet.hip", "common.hpp"),
+    "lowpass_level": ("framelet.hip", "common.hpp"),
     "conv_blur_t": ("conv.hip", "common.hpp", "kernels.hpp"),
     "conv_blur": ("conv.hip", "common.hpp", "kernels.hpp"),
-    "fc_cols": ("fftconv.hip", "fft_core.hpp", "common.hpp", "kernels.hpp"),
-    "fc_rows_fwd": ("fftconv.hip", "fft_core.hpp", "common.hpp", "kernels.hpp"),
-    "fc_rows_inv": ("fftconv.hip", "fft_core.hpp", "common.hpp", "kernels.hpp"),
-    "fc_residual_precond_rows": ("fftconv.hip", "fft_core.hpp", "common.hpp", "kernels.hpp"),
-    "precond_rows_fc_fwd": ("fftconv.hip", "fft_core.hpp", "common.hpp", "kernels.hpp"),
-    "fft_cols": ("fft.hip", "fft_core.hpp", "common.hpp", "kernels.hpp"),
+    "fc_cols": ("fftconv.hip", "fft_core.hpp", "common.hpp"),
+    "fc_rows_fwd": ("fftconv.hip", "fft_core.hpp", "common.hpp"),
+    "fc_rows_inv": ("fftconv.hip", "fft_core.hpp", "common.hpp"),
+    "fc_residual_precond_rows": ("fftconv.hip", "fft_core.hpp", "common.hpp"),
+    "precond_rows_fc_fwd": ("fftconv.hip", "fft_core.hpp", "common.hpp"),
+    "fft_cols": ("fft.hip", "fft_core.hpp", "common.hpp"),
 }
 
 
@@ -373,8 +374,8 @@ def main() -> int:
                     help="iteration state: omega (z = W omega recomputed) or the frame coefficients z")
     ap.add_argument("--compare-steps", type=int, default=20,
                     help="iterations timed with the other state, for comparison (0: skip)")
-    ap.add_argument("--traffic-blur", choices=("fft", "direct"), default="fft",
-                    help="blur used by --traffic-probe")
+    ap.add_argument("--blur", choices=("auto", "fft", "direct"), default="auto",
+                    help="A and A^T: the plan autotuner's choice (default), the FFT grid or the direct taps")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only two 256 MiB device copies x3 (counter calibration: the runtime copy and "
                          "a one-float-per-lane copy) and 3 iterations of the workload, for rocprofv3 --pmc "
@@ -440,9 +441,14 @@ def main() -> int:
     if not args.traffic_probe:
         # the plan autotuner times the direct blur against the FFT grid and keeps the faster
         blur_choice = plan.autotune(reps=5)
+    if args.blur != "auto":
+        plan.set_blur(mlba.BLUR_FFT if args.blur == "fft" else mlba.BLUR_DIRECT)
+    if args.blur == "auto":
+        fft_blur = blur_choice is None or blur_choice["blur"] == "fft"
+        if blur_choice is None:
+            plan.set_blur(mlba.BLUR_FFT)
     else:
-        plan.set_blur(mlba.BLUR_FFT if args.traffic_blur == "fft" else mlba.BLUR_DIRECT)
-    fft_blur = (blur_choice["blur"] == "fft") if blur_choice is not None else args.traffic_blur == "fft"
+        fft_blur = args.blur == "fft"
     if args.traffic_probe:
         src = torch.rand(64 << 20, device="cuda")
         dst = torch.empty_like(src)
@@ -465,7 +471,7 @@ def main() -> int:
         compare = {"state": "explicit z" if implicit else "implicit omega", "steps": args.compare_steps,
                    "ms_per_step": round(el2 * 1e3 / args.compare_steps, 5),
                    "Mpx_it_s": round(n * n * args.compare_steps / el2 / 1e6, 2)}
-        if blur_choice is not None and blur_choice["fft_ms"] is not None:
+        if args.blur == "auto" and blur_choice is not None and blur_choice["fft_ms"] is not None:
             # the same iteration with the blur the autotuner did not pick
             plan.set_blur(mlba.BLUR_DIRECT if fft_blur else mlba.BLUR_FFT)
             el3, _ = run(implicit, args.compare_steps, 3, False)
