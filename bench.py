@@ -101,7 +101,8 @@ def kernel_model(n, p, N, L, implicit, fft_blur):
     values, complex = 8 bytes), and the roof that bounds it.
 
       synthesis_level   (z)     level: read 8 bands + low-pass, write N^2
-      lowpass_level     (omega) level: read + write N^2
+      lowpass_level     (omega) level: read + write N^2; levels 1 and 2 in one
+                                launch (read omega, write both planes)
       shrink_synthesis  (omega) level: read the level's low-pass and the level
                                 above's output (not at the top), write N^2;
                                 119 flops per pixel (FMA = 2): x-analysis 10,
@@ -125,7 +126,10 @@ def kernel_model(n, p, N, L, implicit, fft_blur):
     conv_fl = 2.0 * p * p * n * n
     m = {}
     if implicit:
-        m["lowpass_level"] = {"bytes": f4 * 2 * NN * (L - 1), "flops": 8.0 * NN * (L - 1), "launches": L - 1}
+        if L >= 3:  # levels 1 and 2 in one pass (read omega, write two planes), then one launch per level
+            m["lowpass_level"] = {"bytes": f4 * NN * (3 + 2 * (L - 3)), "flops": 8.0 * NN * (L - 1), "launches": L - 2}
+        else:
+            m["lowpass_level"] = {"bytes": f4 * 2 * NN, "flops": 8.0 * NN, "launches": 1}
         m["shrink_synthesis"] = {"bytes": f4 * NN * (3 * L - 1), "flops": 119.0 * NN * L, "launches": L}
     else:
         m["synthesis_level"] = {"bytes": f4 * 10 * NN * L, "flops": 90.0 * NN * L, "launches": L}

@@ -337,8 +337,10 @@ __global__ __launch_bounds__(kBlock) void lowpass_two_levels_kernel(const float*
     constexpr int IW = kBlock - 4;
     constexpr int HR = LP2_TY + 4;  // low_1 rows y0-2 .. y0+TY+1
     __shared__ float l1[HR][kBlock];
-    const int x0 = blockIdx.x * IW;
-    const int y0 = blockIdx.y * LP2_TY;
+    int bx, by;
+    xcd_tile(&bx, &by);
+    const int x0 = bx * IW;
+    const int y0 = by * LP2_TY;
     const int c = threadIdx.x;
     const int xe = x0 - 2 + c;
     const int xm = reflect_index(xe, N), xl = reflect_index(xe - 1, N), xr = reflect_index(xe + 1, N);
@@ -533,7 +535,9 @@ __global__ __launch_bounds__(kBlock) void shrink_synthesis_kernel(const float* _
                                                                   const float* __restrict__ s_in, int N,
                                                                   float* __restrict__ out, SsCoef cf) {
     __shared__ float lds[SsTile<D, ss_rows<D>()>::LDS_FLOATS];
-    shrink_synthesis_tile<D, ss_rows<D>(), SIN>(low, s_in, N, out, cf, blockIdx.x, blockIdx.y, lds);
+    int bx, by;
+    xcd_tile(&bx, &by);  // each XCD takes a band of strips: the row halos stay in its L2
+    shrink_synthesis_tile<D, ss_rows<D>(), SIN>(low, s_in, N, out, cf, bx, by, lds);
 }
 
 hipError_t launch_lowpass_level(const float* v, int N, int d, float* out, hipStream_t s) {
