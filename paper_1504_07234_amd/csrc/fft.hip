@@ -371,6 +371,8 @@ __global__ __launch_bounds__(kBlock) void fft_rows_r2c_kernel(const float* __res
     fft_rows_r2c_body<NT>(src, n, T, ts, fd, tw, G, seq_shift, xcd_block(blockIdx.x, gridDim.x), buf);
 }
 
+// red_out (optional): workgroup 0 first sums red_count partials of the
+// previous launch into *red_out, in the order of the separate reduction.
 template <int NT>
 __global__ __launch_bounds__(kBlock) void fft_cols_kernel(float2* __restrict__ T, int n, int ts,
                                                           const float* __restrict__ spec, float alpha,
@@ -379,8 +381,17 @@ __global__ __launch_bounds__(kBlock) void fft_cols_kernel(float2* __restrict__ T
                                                           float* __restrict__ power, int seq_shift,
                                                           const float2* __restrict__ lamc,
                                                           const double* __restrict__ alpha_dev,
-                                                          float2* __restrict__ cspec) {
+                                                          float2* __restrict__ cspec,
+                                                          const double* __restrict__ red_in, int red_count,
+                                                          double* __restrict__ red_out) {
     extern __shared__ float2 buf[];
+    if (red_out && blockIdx.x == 0) {
+        __shared__ double red[kBlock / 64];
+        double acc = 0.0;
+        for (int i = threadIdx.x; i < red_count; i += kBlock) acc += red_in[i];
+        const double t = block_sum(acc, red);
+        if (threadIdx.x == 0) *red_out = t;
+    }
     fft_cols_body<NT>(T, n, ts, spec, alpha, inv, fd, tw, CC, mode, power, seq_shift, blockIdx.x, buf, nullptr,
                       nullptr, nullptr, lamc, alpha_dev, cspec);
 }
@@ -723,22 +734,26 @@ hipError_t launch_fft_rows_r2c(const float* src, int n, float2* T, int ts, const
 
 static hipError_t launch_cols(float2* T, int n, int ts, const float* spec, float alpha, float inv, const FftDesc& fd,
                               const float2* tw, int mode, float* power, const float2* lamc, const double* alpha_dev,
-                              float2* cspec, hipStream_t s) {
+                              float2* cspec, hipStream_t s, const double* red_in = nullptr, int red_count = 0,
+                              double* red_out = nullptr) {
     const int CC = pick_cols_per_block(n);
     const int half = n / 2 + 1;
     const size_t lds = lds_bytes(CC * n, n);
     if (n == kFixedN && CC == 1)
         hipLaunchKernelGGL(fft_cols_kernel<kFixedN>, dim3(half), dim3(kBlock), lds, s, T, n, ts, spec, alpha, inv, fd,
-                           tw, 1, mode, power, seq_shift_for(1), lamc, alpha_dev, cspec);
+                           tw, 1, mode, power, seq_shift_for(1), lamc, alpha_dev, cspec, red_in, red_count, red_out);
     else
         hipLaunchKernelGGL(fft_cols_kernel<0>, dim3((half + CC - 1) / CC), dim3(kBlock), lds, s, T, n, ts, spec,
-                           alpha, inv, fd, tw, CC, mode, power, seq_shift_for(CC), lamc, alpha_dev, cspec);
+                           alpha, inv, fd, tw, CC, mode, power, seq_shift_for(CC), lamc, alpha_dev, cspec, red_in,
+                           red_count, red_out);
     return hipGetLastError();
 }
 
 hipError_t launch_fft_cols_filter(float2* T, int n, int ts, const float* spec, float alpha, float inv,
-                                  const FftDesc& fd, const float2* tw, hipStream_t s, const float2* lamc) {
-    return launch_cols(T, n, ts, spec, alpha, inv, fd, tw, 0, nullptr, lamc, nullptr, nullptr, s);
+                                  const FftDesc& fd, const float2* tw, hipStream_t s, const float2* lamc,
+                                  const double* red_in, int red_count, double* red_out) {
+    return launch_cols(T, n, ts, spec, alpha, inv, fd, tw, 0, nullptr, lamc, nullptr, nullptr, s, red_in, red_count,
+                       red_out);
 }
 
 hipError_t launch_fft_cols_forward(float2* T, int n, int ts, const FftDesc& fd, const float2* tw, hipStream_t s) {

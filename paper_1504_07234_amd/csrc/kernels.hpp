@@ -242,9 +242,12 @@ hipError_t launch_analysis_adjoint_batched(const BatchImage* imgs, const int* bm
 hipError_t launch_fft_rows_r2c(const float* src, int n, float2* T, int ts, const FftDesc& fd,
                                const float2* tw, hipStream_t s);
 // columns: forward FFT, scale by inv / (spec + alpha) (times conj(lamc) when
-// given: the C^T (C C^T + alpha I)^{-1} of Algorithm 4), inverse FFT (in place)
+// given: the C^T (C C^T + alpha I)^{-1} of Algorithm 4), inverse FFT (in place);
+// red_out (optional): the first workgroup also writes the sum of red_count
+// partials (the previous launch's) to *red_out
 hipError_t launch_fft_cols_filter(float2* T, int n, int ts, const float* spec, float alpha, float inv,
-                                  const FftDesc& fd, const float2* tw, hipStream_t s, const float2* lamc = nullptr);
+                                  const FftDesc& fd, const float2* tw, hipStream_t s, const float2* lamc = nullptr,
+                                  const double* red_in = nullptr, int red_count = 0, double* red_out = nullptr);
 // columns: forward FFT only (T then holds the 2-D half spectrum)
 hipError_t launch_fft_cols_forward(float2* T, int n, int ts, const FftDesc& fd, const float2* tw, hipStream_t s);
 // columns: the filter of launch_fft_cols_filter with alpha read on the device, inverse FFT

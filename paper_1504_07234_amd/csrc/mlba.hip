@@ -944,19 +944,45 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
         if (implicit) STCHK(do_shrink_synthesis(P, z, P->u, mub, (float)delta[i], s));
         else STCHK(do_synthesis(P, z, P->u, true, mub, (float)delta[i], s));
         int np = 0;
-        if (fused) STCHK(do_blur_residual_precond_rows(P, P->u, g, &np, s));
-        else STCHK(do_blur(P, P->u, g, P->r, true, &np, s));
-        HIPCHK(launch_sum_partials(P->partials, np, P->rn + (i - ring_base), s));
-        MARK(BLUR, REDUCE);
-        if (stop && (i % stop->check_every) == 0) {
+        // the discrepancy stop after ||r^k||^2 is on the device: returns W^T x^k when it holds
+        auto check_stop = [&](bool* hit) -> int {
+            *hit = false;
+            if (!stop || (i % stop->check_every) != 0) return MLBA_OK;
             STCHK(drain(i + 1));
             if (sqrt(rn_host.back()) <= stop->gamma * stop->noise_norm) {
-                // x^k already satisfies the discrepancy principle: return W^T x^k
                 rn_host.pop_back();
                 HIPCHK(hipMemcpyAsync(f_out, P->u, nn * sizeof(float), hipMemcpyDeviceToDevice, s));
+                *hit = true;
+            }
+            return MLBA_OK;
+        };
+        bool hit = false;
+        if (fused) {
+            // r = g - A u with P's forward row pass; the partials are summed by P's column pass
+            STCHK(do_blur_residual_precond_rows(P, P->u, g, &np, s));
+            const float inv = (float)(1.0 / ((double)P->n * (double)P->n));
+            HIPCHK(launch_fft_cols_filter((float2*)P->swork, P->n, P->ts, P->spec, (float)alpha[i], inv, P->fd,
+                                          P->tw, s, nullptr, P->partials, np, P->rn + (i - ring_base)));
+            MARK(PRECOND, FFT_COLS);
+            STCHK(check_stop(&hit));
+            if (hit) {
                 stopped = true;
                 break;
             }
+            // P's inverse row pass runs with A^T's forward one
+            STCHK(do_precond_rows_blurT(P, implicit ? z : P->w, implicit ? 1 : 0, s));
+            if (!implicit) STCHK(do_analysis(P, P->w, z, true, s));
+            P->prof_cur = -1;
+            done = i + 1;
+            continue;
+        }
+        STCHK(do_blur(P, P->u, g, P->r, true, &np, s));
+        HIPCHK(launch_sum_partials(P->partials, np, P->rn + (i - ring_base), s));
+        MARK(BLUR, REDUCE);
+        STCHK(check_stop(&hit));
+        if (hit) {
+            stopped = true;
+            break;
         }
         if (alg4) {
             // eq. (Alg4): the direction C^T (C C^T + alpha I)^{-1} r, no A^T product
@@ -992,22 +1018,12 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
             done = i + 1;
             continue;
         }
-        if (fused) {
-            // the column pass of P; its inverse row pass runs with A^T's forward one
-            const float inv = (float)(1.0 / ((double)P->n * (double)P->n));
-            HIPCHK(launch_fft_cols_filter((float2*)P->swork, P->n, P->ts, P->spec, (float)alpha[i], inv, P->fd,
-                                          P->tw, s));
-            MARK(PRECOND, FFT_COLS);
-            STCHK(do_precond_rows_blurT(P, implicit ? z : P->w, implicit ? 1 : 0, s));
-            if (!implicit) STCHK(do_analysis(P, P->w, z, true, s));
+        STCHK(do_precond(P, P->r, P->t, alpha[i], s));
+        if (implicit) {
+            STCHK(do_blurT_acc(P, P->t, z, s));
         } else {
-            STCHK(do_precond(P, P->r, P->t, alpha[i], s));
-            if (implicit) {
-                STCHK(do_blurT_acc(P, P->t, z, s));
-            } else {
-                STCHK(do_blurT(P, P->t, P->w, s));
-                STCHK(do_analysis(P, P->w, z, true, s));
-            }
+            STCHK(do_blurT(P, P->t, P->w, s));
+            STCHK(do_analysis(P, P->w, z, true, s));
         }
         P->prof_cur = -1;
         done = i + 1;

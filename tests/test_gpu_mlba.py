@@ -161,10 +161,13 @@ def test_resume_and_determinism(mlba):
         assert i1.rnorm == ia.rnorm + ib.rnorm == i3.rnorm
 
 
-def test_discrepancy_stop(mlba):
-    """eq. (discrpr): stop at the first k with ||r^k|| <= gamma * ||eta||."""
+@pytest.mark.parametrize("fft_blur", [False, True])
+def test_discrepancy_stop(mlba, fft_blur):
+    """eq. (discrpr): stop at the first k with ||r^k|| <= gamma * ||eta||; with
+    the FFT blur the residual norm is summed by the preconditioner's column
+    pass before the check."""
     w = synth.make_workload("plain-fp64-72")
-    announce("discrepancy stop")
+    announce(f"discrepancy stop fft_blur={fft_blur}")
     g, nn = observed(w, oblur)
     it = 50
     alphas = np.full(it, 0.05)
@@ -175,6 +178,8 @@ def test_discrepancy_stop(mlba):
     k_star = int(np.argmax(ref["rnorm"] <= gamma * nn))
     assert ref["rnorm"][k_star] <= gamma * nn and k_star > 0
     with mlba.Plan(w.n, w.p, 0, 0, 1, cuda(w.psf)) as plan:
+        if fft_blur:
+            plan.set_blur(mlba.BLUR_FFT)
         f, info = plan.restore(cuda(g), alpha_table=alphas, mu=w.mu, delta_table=deltas, iters=it,
                                stop=(nn, gamma, 1))
         f = host(f)
