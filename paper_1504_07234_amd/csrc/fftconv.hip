@@ -90,13 +90,14 @@ __global__ __launch_bounds__(kBlock) void fc_rows_fwd_kernel(const float* __rest
 
 // Columns pass over CC half-spectrum rows per workgroup; rows outside
 // [y_lo, y_hi) of the input are zero.  mode 0: forward FFT, times Hs (or
-// conj(Hs)) * inv, inverse FFT, written back; mode 1: forward FFT into cspec.
+// conj(Hs)) * inv, inverse FFT, written back for the rows [o_lo, o_hi) that the
+// inverse row pass reads; mode 1: forward FFT into cspec.
 template <int NT>
 __global__ __launch_bounds__(kBlock) void fc_cols_kernel(float2* __restrict__ T, int M_, int ts,
                                                          const float2* __restrict__ Hs, int conj_h, float inv,
                                                          int y_lo, int y_hi, int mode, float2* __restrict__ cspec,
                                                          FftDesc fd, const float2* __restrict__ tw, int CC_,
-                                                         int seq_shift) {
+                                                         int seq_shift, int o_lo, int o_hi) {
     extern __shared__ float2 buf[];
     const int M = NT > 0 ? NT : M_;
     const int CC = NT > 0 ? 1 : CC_;
@@ -124,7 +125,8 @@ __global__ __launch_bounds__(kBlock) void fc_cols_kernel(float2* __restrict__ T,
     lds_fft_any<1, NT, FC_EPT>(buf, fd, cc, seq_shift, tw);
     for (int idx = threadIdx.x; idx < cc * M; idx += kBlock) {
         const int q = idx / M;
-        T[(size_t)(k0 + q) * ts + (idx - q * M)] = buf[lds_slot(idx)];
+        const int y = idx - q * M;
+        if (y >= o_lo && y < o_hi) T[(size_t)(k0 + q) * ts + y] = buf[lds_slot(idx)];
     }
 }
 
@@ -347,17 +349,19 @@ hipError_t launch_fc_rows_fwd(const FftConv& c, const float* src, int S, int off
     return hipGetLastError();
 }
 
-hipError_t launch_fc_cols(const FftConv& c, int conj_h, int y_lo, int y_hi, int mode, float2* cspec, hipStream_t s) {
+hipError_t launch_fc_cols(const FftConv& c, int conj_h, int y_lo, int y_hi, int mode, float2* cspec, hipStream_t s,
+                          int o_lo, int o_hi) {
     const int CC = fc_cols_per_block(c.M);
     const int half = c.M / 2 + 1;
     const float inv = (float)(1.0 / ((double)c.M * (double)c.M));
     if (c.M == kFixedM && CC == 1)
         hipLaunchKernelGGL(fc_cols_kernel<kFixedM>, dim3(half), dim3(kBlock), lds_bytes(c.M, c.M), s, c.T, c.M, c.ts,
-                           (const float2*)c.H, conj_h, inv, y_lo, y_hi, mode, cspec, c.fd, c.tw, 1, fc_seq_shift(1));
+                           (const float2*)c.H, conj_h, inv, y_lo, y_hi, mode, cspec, c.fd, c.tw, 1, fc_seq_shift(1), o_lo,
+                           o_hi);
     else
         hipLaunchKernelGGL(fc_cols_kernel<0>, dim3((half + CC - 1) / CC), dim3(kBlock), lds_bytes(CC * c.M, c.M), s,
                            c.T, c.M, c.ts, (const float2*)c.H, conj_h, inv, y_lo, y_hi, mode, cspec, c.fd, c.tw, CC,
-                           fc_seq_shift(CC));
+                           fc_seq_shift(CC), o_lo, o_hi);
     return hipGetLastError();
 }
 
@@ -386,14 +390,14 @@ int fftconv_partials_count(int M, int n) {
 hipError_t launch_fftconv_spectrum(const FftConv& c, const float* psf, int p, hipStream_t s) {
     hipError_t e = launch_fc_rows_fwd(c, psf, p, 0, 0, p, s);
     if (e != hipSuccess) return e;
-    return launch_fc_cols(c, 0, 0, p, 1, c.H, s);
+    return launch_fc_cols(c, 0, 0, p, 1, c.H, s, 0, c.M);
 }
 
 hipError_t launch_fftconv_blur(const FftConv& c, const float* u, int n, int p, const float* g, float* r,
                                double* partials, int* n_partials, hipStream_t s) {
     const int N = n + p - 1;
     hipError_t e = launch_fc_rows_fwd(c, u, N, 0, 0, N, s);
-    if (e == hipSuccess) e = launch_fc_cols(c, 0, 0, N, 0, nullptr, s);
+    if (e == hipSuccess) e = launch_fc_cols(c, 0, 0, N, 0, nullptr, s, p - 1, p - 1 + n + (n & 1));
     if (e == hipSuccess) e = launch_fc_rows_inv(c, p - 1, p - 1, n, r, g, 0, g ? partials : nullptr, n_partials, s);
     return e;
 }
@@ -401,7 +405,7 @@ hipError_t launch_fftconv_blur(const FftConv& c, const float* u, int n, int p, c
 hipError_t launch_fftconv_blurT(const FftConv& c, const float* t, int n, int p, float* w, int accum, hipStream_t s) {
     const int N = n + p - 1;
     hipError_t e = launch_fc_rows_fwd(c, t, n, p - 1, p - 1, N, s);
-    if (e == hipSuccess) e = launch_fc_cols(c, 1, p - 1, N, 0, nullptr, s);
+    if (e == hipSuccess) e = launch_fc_cols(c, 1, p - 1, N, 0, nullptr, s, 0, N + (N & 1));
     if (e == hipSuccess) e = launch_fc_rows_inv(c, 0, 0, N, w, nullptr, accum, nullptr, nullptr, s);
     return e;
 }

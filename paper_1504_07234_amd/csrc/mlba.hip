@@ -117,7 +117,7 @@ int do_blur(mlba_plan_s* P, const float* u, const float* g, float* y, bool want_
         const int n = P->n, p = P->p, N = n + p - 1;
         HIPCHK(launch_fc_rows_fwd(P->fc, u, N, 0, 0, N, s));
         MARK(BLUR, FC_ROWS_FWD);
-        HIPCHK(launch_fc_cols(P->fc, 0, 0, N, 0, nullptr, s));
+        HIPCHK(launch_fc_cols(P->fc, 0, 0, N, 0, nullptr, s, p - 1, p - 1 + n + (n & 1)));
         MARK(BLUR, FC_COLS);
         HIPCHK(launch_fc_rows_inv(P->fc, p - 1, p - 1, n, y, g, 0, g && want_norm ? P->partials : nullptr, nparts,
                                   s));
@@ -155,7 +155,7 @@ int do_blur_residual_precond_rows(mlba_plan_s* P, const float* u, const float* g
     const int n = P->n, p = P->p, N = n + p - 1;
     HIPCHK(launch_fc_rows_fwd(P->fc, u, N, 0, 0, N, s));
     MARK(BLUR, FC_ROWS_FWD);
-    HIPCHK(launch_fc_cols(P->fc, 0, 0, N, 0, nullptr, s));
+    HIPCHK(launch_fc_cols(P->fc, 0, 0, N, 0, nullptr, s, p - 1, p - 1 + n + (n & 1)));
     MARK(BLUR, FC_COLS);
     HIPCHK(launch_fc_residual_precond_rows(P->fc, n, p, g, nullptr, P->partials, nparts, precond_rows(P), s));
     MARK(BLUR, FC_RESIDUAL_PRECOND_ROWS);
@@ -167,7 +167,7 @@ int do_precond_rows_blurT(mlba_plan_s* P, float* w, int accum, hipStream_t s) {
     const int n = P->n, p = P->p, N = n + p - 1;
     HIPCHK(launch_precond_rows_fc_fwd(P->fc, n, p, precond_rows(P), nullptr, s));
     MARK(BLUR_T, PRECOND_ROWS_FC_FWD);
-    HIPCHK(launch_fc_cols(P->fc, 1, p - 1, N, 0, nullptr, s));
+    HIPCHK(launch_fc_cols(P->fc, 1, p - 1, N, 0, nullptr, s, 0, N + (N & 1)));
     MARK(BLUR_T, FC_COLS);
     HIPCHK(launch_fc_rows_inv(P->fc, 0, 0, N, w, nullptr, accum, nullptr, nullptr, s));
     MARK(BLUR_T, FC_ROWS_INV);
@@ -179,7 +179,7 @@ int do_blurT_fft(mlba_plan_s* P, const float* y, float* w, int accum, hipStream_
     const int n = P->n, p = P->p, N = n + p - 1;
     HIPCHK(launch_fc_rows_fwd(P->fc, y, n, p - 1, p - 1, N, s));
     MARK(BLUR_T, FC_ROWS_FWD);
-    HIPCHK(launch_fc_cols(P->fc, 1, p - 1, N, 0, nullptr, s));
+    HIPCHK(launch_fc_cols(P->fc, 1, p - 1, N, 0, nullptr, s, 0, N + (N & 1)));
     MARK(BLUR_T, FC_COLS);
     HIPCHK(launch_fc_rows_inv(P->fc, 0, 0, N, w, nullptr, accum, nullptr, nullptr, s));
     MARK(BLUR_T, FC_ROWS_INV);
