@@ -44,7 +44,16 @@ PROFILE_EVERY = 4              # kernel events on every 4th timed iteration (the
 # each scaled by what the counter reads for a plain 256 MiB copy on the same run
 # (FETCH_SIZE x2.000, WRITE_SIZE x1.000).  A figure belongs to the kernel sources
 # it was taken with: when their hash differs it is reported as null.
-TRAFFIC = {}
+TRAFFIC = {
+    # 2078^2, 3 levels: the three shrink-synthesis launches of one iteration (d = 4, 2, 1)
+    ("shrink_synthesis", "fft-implicit"): {
+        "fetch_kib": 43465.875, "write_kib": 50610.46875, "fetch_scale": 2.0, "write_scale": 1.0, "launches": 3,
+        "sources_sha256": "ff2e3996f89ded4922cd9284f46e6d2b2643bf57cb27278751c142eba3660221"},
+    # the direct A^T accumulating into omega (p = 31), one launch per iteration
+    ("conv_blur_t", "direct-implicit"): {
+        "fetch_kib": 17582.0625, "write_kib": 16878.03125, "fetch_scale": 2.0, "write_scale": 1.0, "launches": 1,
+        "sources_sha256": "43d78d16d9400d3d95f3d0c85e8c6e849352bd703b6d3b2e8cd2006152541baa"},
+}
 # the sources that define each kernel's device code
 TRAFFIC_SOURCES = {
     "shrink_synthesis": ("framelet.hip", "common.hpp"),
