@@ -120,7 +120,9 @@ __global__ __launch_bounds__(kBlock) void analysis_level_kernel(const float* __r
                                                                 float* __restrict__ zlev,
                                                                 float* __restrict__ low,
                                                                 int accum_bands, int accum_low) {
-    analysis_tile<D>(v, N, zlev, low, zlev, low, accum_bands, accum_low, blockIdx.x, blockIdx.y);
+    int bx, by;
+    xcd_tile(&bx, &by);  // row halos of adjacent strips in one L2
+    analysis_tile<D>(v, N, zlev, low, zlev, low, accum_bands, accum_low, bx, by);
 }
 
 // Reverse-sweep level: the filters of analysis_tile, and for every band value
@@ -283,7 +285,9 @@ __global__ __launch_bounds__(kBlock) void synthesis_level_kernel(const float* __
                                                                  float* __restrict__ out, LevelMu mu,
                                                                  float delta, int thr_low, int thr_bands) {
     __shared__ float ys[3][FR_TY][kBlock];
-    synthesis_tile<D>(zlev, low, N, out, mu, delta, thr_low, thr_bands, blockIdx.x, blockIdx.y, ys);
+    int bx, by;
+    xcd_tile(&bx, &by);  // row halos of adjacent strips in one L2
+    synthesis_tile<D>(zlev, low, N, out, mu, delta, thr_low, thr_bands, bx, by, ys);
 }
 
 // ---- implicit state: z = W omega is never stored -------------------------
