@@ -109,7 +109,9 @@ def kernel_model(n, p, N, L, implicit, fft_blur):
     """Algorithmic bytes and flops of each kernel per iteration (float32
     values, complex = 8 bytes), and the roof that bounds it.
 
-      synthesis_level   (z)     level: read 8 bands + low-pass, write N^2
+      synthesis_level   (z)     level: read 8 bands + low-pass, write N^2; 79 flops
+                                per pixel: 9 thresholds 27, y-synthesis 39,
+                                x-synthesis 13
       lowpass_level     (omega) level: read + write N^2; levels 1 and 2 in one
                                 launch (read omega, write both planes)
       shrink_synthesis  (omega) level: read the level's low-pass and the level
@@ -127,7 +129,9 @@ def kernel_model(n, p, N, L, implicit, fft_blur):
       fc_rows_inv (A^T)         read (M/2+1) N complex, write w (omega: +read)
       fc_residual_precond_rows  read (M/2+1) n complex and g, write (n/2+1) n
       precond_rows_fc_fwd       read (n/2+1) n complex, write (M/2+1) n
-      analysis_level    (z)     read v, read + write 8 bands, write low-pass
+      analysis_level    (z)     read v, read + write 8 bands, write low-pass; 48
+                                flops per pixel: x-filters 10, y-filters 30,
+                                8 accumulations
     """
     f4, c8 = 4.0, 8.0
     nn, NN = n * n, N * N
@@ -141,8 +145,8 @@ def kernel_model(n, p, N, L, implicit, fft_blur):
             m["lowpass_level"] = {"bytes": f4 * 2 * NN, "flops": 8.0 * NN, "launches": 1}
         m["shrink_synthesis"] = {"bytes": f4 * NN * (3 * L - 1), "flops": 119.0 * NN * L, "launches": L}
     else:
-        m["synthesis_level"] = {"bytes": f4 * 10 * NN * L, "flops": 90.0 * NN * L, "launches": L}
-        m["analysis_level"] = {"bytes": f4 * NN * (18 * L + 1), "flops": 60.0 * NN * L, "launches": L}
+        m["synthesis_level"] = {"bytes": f4 * 10 * NN * L, "flops": 79.0 * NN * L, "launches": L}
+        m["analysis_level"] = {"bytes": f4 * NN * (18 * L + 1), "flops": 48.0 * NN * L, "launches": L}
     if fft_blur:
         M = fft_grid(N)
         hm = M // 2 + 1
