@@ -352,7 +352,8 @@ def alg2_section(w, g, delta, steps: int = 10):
     """Algorithm 2 (section 4.2) on the 2048^2 rectangular workload: the
     preconditioner replaced by at most 5 PCG steps (tolerance 1e-3) on
     (A A^T + alpha I) t = r, preconditioned by the BCCB (C C^T + alpha I)^{-1};
-    implicit state, `steps` timed iterations (one host read per PCG step)."""
+    implicit state, the autotuned blur, `steps` timed iterations (one host read
+    per PCG step)."""
     import torch
 
     from paper_1504_07234_amd import mlba
@@ -361,6 +362,7 @@ def alg2_section(w, g, delta, steps: int = 10):
     n = w.n
     with mlba.Plan(n, w.p, w.bc, w.precond, w.levels, psf) as plan:
         N = plan.N
+        blur = plan.autotune(reps=3)["blur"]  # each PCG step is one A A^T product
         f = torch.empty((N, N), dtype=torch.float32, device="cuda")
         om = torch.zeros((N, N), dtype=torch.float32, device="cuda")
         plan.restore(g, alpha=w.alpha0, mu=w.mu, delta=delta, iters=2, z=om, out=f, track=False, implicit=True,
@@ -371,7 +373,7 @@ def alg2_section(w, g, delta, steps: int = 10):
                                implicit=True, method=mlba.ALG2)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-    return {"model": "rect", "precond": "bccb", "alpha": w.alpha0, "pcg": [5, 1e-3], "steps": steps,
+    return {"model": "rect", "precond": "bccb", "blur": blur, "alpha": w.alpha0, "pcg": [5, 1e-3], "steps": steps,
             "ms_per_step": round(el * 1e3 / steps, 5), "Mpx_it_s": round(n * n * steps / el / 1e6, 2),
             "pcg_steps": info.pcg_steps}
 
