@@ -51,6 +51,29 @@ def test_alg2_against_oracle(mlba, n, p, bc, pc, L, alpha, pcg, implicit):
     assert rel_err(info.rnorm, ref["rnorm"]) < 1e-4
 
 
+@pytest.mark.parametrize("implicit", [False, True])
+def test_alg2_with_the_fft_blur(mlba, implicit):
+    """The PCG's A A^T products and the final A^T evaluated on the FFT grid."""
+    n, p, L, alpha, pcg = 96, 9, 2, 0.05, (5, 0.05)
+    announce(f"Alg2 FFT blur n={n} p={p} implicit={implicit}")
+    gen = synth.rng(n + p + 11)
+    truth = synth.shapes_image(n + p - 1, gen, n_rect=6, n_disk=3, n_bumps=3)
+    H = synth.motion_psf(p, p - 2.0, gen.uniform(0, np.pi))
+    g = synth.add_noise(ob.blur(truth, H, ob.RECT), synth.white_noise((n, n), gen), 0.01)
+    iters = 20
+    ref = oa2.alg2(g, H, ob.RECT, 0, L, np.full(iters, alpha), np.full(iters + 1, 0.8), 1e-3, iters,
+                   beta_max=pcg[0], tol=pcg[1])
+    with mlba.Plan(n, p, ob.RECT, 0, L, cuda(H)) as plan:
+        plan.set_blur(mlba.BLUR_FFT)
+        f, info = plan.restore(cuda(g), alpha=alpha, mu=1e-3, delta=0.8, iters=iters, method=mlba.ALG2, pcg=pcg,
+                               implicit=implicit)
+        f = host(f)
+    print(f"  betas gpu {info.pcg_steps} oracle {ref['betas'].tolist()}; image {rel_err(f, ref['f']):.2e}",
+          flush=True)
+    assert info.pcg_steps == ref["betas"].tolist()
+    assert rel_err(f, ref["f"]) < 1e-4
+
+
 def test_alg2_exact_preconditioner_takes_one_step(mlba):
     """Periodic model, BCCB plan: the preconditioner is exact, every beta_n = 1,
     and the run equals the plain preconditioned MLBA."""
