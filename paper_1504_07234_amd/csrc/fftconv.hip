@@ -393,23 +393,6 @@ hipError_t launch_fftconv_spectrum(const FftConv& c, const float* psf, int p, hi
     return launch_fc_cols(c, 0, 0, p, 1, c.H, s, 0, c.M);
 }
 
-hipError_t launch_fftconv_blur(const FftConv& c, const float* u, int n, int p, const float* g, float* r,
-                               double* partials, int* n_partials, hipStream_t s) {
-    const int N = n + p - 1;
-    hipError_t e = launch_fc_rows_fwd(c, u, N, 0, 0, N, s);
-    if (e == hipSuccess) e = launch_fc_cols(c, 0, 0, N, 0, nullptr, s, p - 1, p - 1 + n + (n & 1));
-    if (e == hipSuccess) e = launch_fc_rows_inv(c, p - 1, p - 1, n, r, g, 0, g ? partials : nullptr, n_partials, s);
-    return e;
-}
-
-hipError_t launch_fftconv_blurT(const FftConv& c, const float* t, int n, int p, float* w, int accum, hipStream_t s) {
-    const int N = n + p - 1;
-    hipError_t e = launch_fc_rows_fwd(c, t, n, p - 1, p - 1, N, s);
-    if (e == hipSuccess) e = launch_fc_cols(c, 1, p - 1, N, 0, nullptr, s, 0, N + (N & 1));
-    if (e == hipSuccess) e = launch_fc_rows_inv(c, 0, 0, N, w, nullptr, accum, nullptr, nullptr, s);
-    return e;
-}
-
 hipError_t launch_fc_residual_precond_rows(const FftConv& c, int n, int p, const float* g, float* r_out,
                                            double* partials, int* n_partials, const PrecondRows& pr, hipStream_t s) {
     if (!fftconv_fusable(c, n, pr)) return hipErrorInvalidValue;

@@ -159,11 +159,6 @@ struct FftConv {
 int fftconv_max_size();
 int fftconv_partials_count(int M, int n);
 hipError_t launch_fftconv_spectrum(const FftConv& c, const float* psf, int p, hipStream_t s);
-// r = g - A u (partials: squared-norm per workgroup, count in *n_partials) or y = A u (g null)
-hipError_t launch_fftconv_blur(const FftConv& c, const float* u, int n, int p, const float* g, float* r,
-                               double* partials, int* n_partials, hipStream_t s);
-// w = A^T t, or w += A^T t (accum)
-hipError_t launch_fftconv_blurT(const FftConv& c, const float* t, int n, int p, float* w, int accum, hipStream_t s);
 
 // The transposed half spectrum of the BCCB preconditioner (n x n, row stride
 // ts complex) and its transform plan, for the passes fused with the FFT blur.
