@@ -542,6 +542,9 @@ def main() -> int:
                  "iterations_sampled": rec, "sampled_every": PROFILE_EVERY})
     total_bytes = sum(v["bytes"] for v in model.values())
     hbm_frac = (total_bytes / (HBM_PEAK_GBS * 1e9)) / (ms_per_step * 1e-3)
+    # every kernel at its own roof: sum_k max(bytes_k / HBM peak, flops_k / VALU peak)
+    t_roof = sum(max(v["bytes"] / (HBM_PEAK_GBS * 1e9), v["flops"] / (FP32_VALU_PEAK_TFLOPS * 1e12))
+                 for v in model.values())
 
     out = {
         "metric": METRIC,
@@ -561,6 +564,8 @@ def main() -> int:
                    "delta": round(delta, 6), "state": "implicit omega (z = W omega)" if implicit else "explicit z",
                    "blur": f"fft grid {fft_grid(N)}" if fft_blur else "direct taps"},
         "hbm_roofline_frac_whole_step": round(hbm_frac, 4),
+        "roofline_frac_whole_step": {"t_roof_us": round(t_roof * 1e6, 2), "t_meas_us": round(ms_per_step * 1e3, 2),
+                                     "frac": round(t_roof / (ms_per_step * 1e-3), 4)},
         "roofline": roof,
         "kernels": kern_out,
         "phases": phase_out,
