@@ -56,8 +56,8 @@ TRAFFIC = {
 }
 # the sources that define each kernel's device code
 TRAFFIC_SOURCES = {
-    "shrink_synthesis": ("framelet.hip", "common.hpp"),
-    "lowpass_level": ("framelet.hip", "common.hpp"),
+    "shrink_synthesis": ("shrink.hip", "framelet.hpp", "common.hpp"),
+    "lowpass_level": ("shrink.hip", "framelet.hpp", "common.hpp"),
     "conv_blur_t": ("conv.hip", "common.hpp", "kernels.hpp"),
     "conv_blur": ("conv.hip", "common.hpp", "kernels.hpp"),
     "fc_cols": ("fftconv.hip", "fft_core.hpp", "common.hpp"),

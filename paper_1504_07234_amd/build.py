@@ -36,7 +36,7 @@ COMMON_FLAGS = [
     f"-I{CSRC}",
 ]
 
-SOURCES = ["conv.hip", "framelet.hip", "fft.hip", "fftconv.hip", "reduce.hip", "psfgrad.hip", "mlba.hip",
+SOURCES = ["conv.hip", "framelet.hip", "shrink.hip", "fft.hip", "fftconv.hip", "reduce.hip", "psfgrad.hip", "mlba.hip",
            "batch.hip", "unrolled.hip"]
 
 
