@@ -401,8 +401,9 @@ def main() -> int:
                          "FETCH_SIZE / WRITE_SIZE passes")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU decomposition is described in DESIGN.md, not built)", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the library has no multi-GPU path: independent images shard without communication, "
+              "a single image would need halo exchanges and a distributed transpose)", file=sys.stderr)
         return 2
 
     import numpy as np
