@@ -47,12 +47,12 @@ PROFILE_EVERY = 4              # kernel events on every 4th timed iteration (the
 TRAFFIC = {
     # 2078^2, 3 levels: the three shrink-synthesis launches of one iteration (d = 4, 2, 1)
     ("shrink_synthesis", "fft-implicit"): {
-        "fetch_kib": 43465.875, "write_kib": 50610.46875, "fetch_scale": 2.0, "write_scale": 1.0, "launches": 3,
-        "sources_sha256": "ff2e3996f89ded4922cd9284f46e6d2b2643bf57cb27278751c142eba3660221"},
+        "fetch_kib": 43467.875, "write_kib": 50610.46875, "fetch_scale": 2.0, "write_scale": 1.0, "launches": 3,
+        "sources_sha256": "8c65fed666594571d421301171dc91078bc98ff1bda518df2ed031f5377ae64a"},
     # the direct A^T accumulating into omega (p = 31), one launch per iteration
     ("conv_blur_t", "direct-implicit"): {
         "fetch_kib": 17582.0625, "write_kib": 16878.03125, "fetch_scale": 2.0, "write_scale": 1.0, "launches": 1,
-        "sources_sha256": "43d78d16d9400d3d95f3d0c85e8c6e849352bd703b6d3b2e8cd2006152541baa"},
+        "sources_sha256": "a645147298484ea7ed30d08d5d29b45515bd7037267cb7a977b7c5b52b4b25f2"},
 }
 # the sources that define each kernel's device code
 TRAFFIC_SOURCES = {
