@@ -672,9 +672,12 @@ __global__ __launch_bounds__(kBlock) void precond_batched_kernel(const BatchImag
                                                                  const int* __restrict__ bmap,
                                                                  const int* __restrict__ bfirst) {
     extern __shared__ float2 buf[];
-    const int im = bmap[blockIdx.x];
+    // row passes: consecutive row pairs of an image in one L2 (their transposed
+    // stores share cache lines); the column passes keep the launch order
+    const int xb = (PASS == 0 || PASS == 2) ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int im = bmap[xb];
     const BatchImage& I = imgs[im];
-    const int blk = blockIdx.x - bfirst[im];
+    const int blk = xb - bfirst[im];
     const int n = I.n;
     const float inv = (float)(1.0 / ((double)n * (double)n));
     if (PRECOND == 0) {

@@ -341,7 +341,8 @@ __global__ __launch_bounds__(kBlock) void synthesis_batched_kernel(const BatchIm
                                                                    const int* __restrict__ bfirst, int lev,
                                                                    int final_out, int thr) {
     __shared__ float ys[3][FR_TY][kBlock];
-    const int im = bmap[blockIdx.x];
+    const int xb = xcd_block(blockIdx.x, gridDim.x);  // adjacent tiles of an image in one L2
+    const int im = bmap[xb];
     const BatchImage& I = imgs[im];
     const size_t nn = (size_t)I.N * I.N;
     const float* zlev = I.zin + (size_t)(1 + 8 * (lev - 1)) * nn;
@@ -354,7 +355,7 @@ __global__ __launch_bounds__(kBlock) void synthesis_batched_kernel(const BatchIm
     for (int q = 0; q < 8; ++q) mu.band[q] = I.mu[1 + 8 * (lev - 1) + q];
     const int IW = kBlock - 2 * D;
     const int gx = (I.N + IW - 1) / IW;
-    const int local = blockIdx.x - bfirst[im];
+    const int local = xb - bfirst[im];
     const int by = local / gx;
     synthesis_tile<D>(zlev, low, I.N, out, mu, thr ? I.delta : 1.0f, (thr && top) ? 1 : 0, thr, local - by * gx,
                       by, ys);
@@ -364,7 +365,8 @@ template <int D>
 __global__ __launch_bounds__(kBlock) void analysis_batched_kernel(const BatchImage* __restrict__ imgs,
                                                                   const int* __restrict__ bmap,
                                                                   const int* __restrict__ bfirst, int lev) {
-    const int im = bmap[blockIdx.x];
+    const int xb = xcd_block(blockIdx.x, gridDim.x);  // adjacent tiles of an image in one L2
+    const int im = bmap[xb];
     const BatchImage& I = imgs[im];
     const size_t nn = (size_t)I.N * I.N;
     const float* in = lev == 1 ? I.w : (((lev - 1) & 1) ? I.tmp1 : I.tmp0);
@@ -373,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void analysis_batched_kernel(const BatchIma
     float* zlev = I.z + (size_t)(1 + 8 * (lev - 1)) * nn;
     const float* zin_lev = I.zin + (size_t)(1 + 8 * (lev - 1)) * nn;
     const int gx = (I.N + kBlock - 1) / kBlock;
-    const int local = blockIdx.x - bfirst[im];
+    const int local = xb - bfirst[im];
     const int by = local / gx;
     analysis_tile<D>(in, I.N, zin_lev, last ? I.zin : low, zlev, low, 1, last ? 1 : 0, local - by * gx, by);
 }
@@ -384,7 +386,8 @@ __global__ __launch_bounds__(kBlock) void analysis_adjoint_batched_kernel(const 
                                                                           const int* __restrict__ bfirst, int lev,
                                                                           int init, double* __restrict__ part) {
     __shared__ double red[9][kBlock / 64];
-    const int im = bmap[blockIdx.x];
+    const int xb = xcd_block(blockIdx.x, gridDim.x);  // adjacent tiles of an image in one L2
+    const int im = bmap[xb];
     const BatchImage& I = imgs[im];
     const size_t nn = (size_t)I.N * I.N;
     const float* in = lev == 1 ? I.w : (((lev - 1) & 1) ? I.tmp1 : I.tmp0);
@@ -395,7 +398,7 @@ __global__ __launch_bounds__(kBlock) void analysis_adjoint_batched_kernel(const 
 #pragma unroll
     for (int q = 0; q < 8; ++q) mu.band[q] = I.mu[1 + 8 * (lev - 1) + q];
     const int gx = (I.N + ADJ_TX - 1) / ADJ_TX;
-    const int local = blockIdx.x - bfirst[im];
+    const int local = xb - bfirst[im];
     const int by = local / gx;
     float ps[9];
     analysis_adjoint_tile<D>(in, I.N, I.zk + lo, I.zbar + lo, last ? I.zk : nullptr, last ? I.zbar : nullptr,
@@ -470,10 +473,11 @@ int fill_tiles(const BatchImage& I) {
 __global__ __launch_bounds__(kBlock) void fill_batched_kernel(const BatchImage* __restrict__ imgs,
                                                               const int* __restrict__ bmap,
                                                               const int* __restrict__ bfirst) {
-    const int im = bmap[blockIdx.x];
+    const int xb = xcd_block(blockIdx.x, gridDim.x);  // adjacent tiles of an image in one L2
+    const int im = bmap[xb];
     const BatchImage& I = imgs[im];
     const size_t count = (size_t)I.bands * I.N * I.N;
-    const size_t beg = (size_t)(blockIdx.x - bfirst[im]) * FILL_CHUNK;
+    const size_t beg = (size_t)(xb - bfirst[im]) * FILL_CHUNK;
     const size_t end = beg + FILL_CHUNK < count ? beg + FILL_CHUNK : count;
     for (size_t i = beg + threadIdx.x; i < end; i += kBlock) I.z[i] = 0.0f;
 }

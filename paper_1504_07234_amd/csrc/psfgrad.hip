@@ -63,12 +63,13 @@ __global__ __launch_bounds__(kBlock) void psf_corr_batched_kernel(const BatchIma
                                                                   double* __restrict__ apart) {
     extern __shared__ float smem[];
     __shared__ double red[kBlock / 64];
-    const int im = bmap[blockIdx.x];
+    const int xb = xcd_block(blockIdx.x, gridDim.x);  // adjacent tiles of an image in one L2
+    const int im = bmap[xb];
     const BatchImage& I = imgs[im];
     const int n = I.n, N = I.N, p = I.p;
     const CorrShape cs = corr_shape(p);
     const int gx = (n + PC_TX - 1) / PC_TX;
-    const int local = blockIdx.x - bfirst[im];
+    const int local = xb - bfirst[im];
     const int by = local / gx;
     const int oy0 = by * PC_TY, ox0 = (local - by * gx) * PC_TX;
 
