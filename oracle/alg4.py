@@ -11,7 +11,11 @@ approximation of the blur A:
     C^T (C C^T + alpha I)^{-1} r = F^{-1}[ conj(Lambda_c) F r / (|Lambda_c|^2 + alpha) ];
   * DCT: C is the reflective-boundary blur of the symmetrised PSF H~ (the
     matrix of Algorithm 3), symmetric and diagonalised by the orthonormal DCT-II:
-    C^T (C C^T + alpha I)^{-1} r = C2^T[ lambda C2 r / (lambda^2 + alpha) ].
+    C^T (C C^T + alpha I)^{-1} r = C2^T[ lambda C2 r / (lambda^2 + alpha) ];
+  * AR: C is the antireflective blur of H~ (sections 2.2 and 4.3), with C^T
+    read as the reblurring C' = C (H~ is unchanged by the 180-degree rotation):
+    C' (C C' + alpha I)^{-1} r = T[ lambda (T^-1 r) / (lambda^2 + alpha) ]
+    with T the antireflective transform along both axes.
 
 The method is only defined for square models (A imposes boundary conditions,
 so A and C have the same size).
@@ -39,7 +43,7 @@ from . import framelet as _fr
 from . import precond as _pc
 from .mlba import soft_threshold
 
-BCCB, DCT = _pc.BCCB, _pc.DCT
+BCCB, DCT, AR = _pc.BCCB, _pc.DCT, _pc.AR
 
 
 def centred_eigs(H: np.ndarray, n: int) -> np.ndarray:
@@ -64,7 +68,10 @@ def apply_ct_prec(r: np.ndarray, H: np.ndarray, alpha: float, kind: int) -> np.n
         lam = _pc.dct_eigs(_pc.symmetrize(H), n)
         c2 = scipy.fft.dctn(r, type=2, norm="ortho")
         return scipy.fft.idctn(lam * c2 / (lam * lam + alpha), type=2, norm="ortho")
-    raise ValueError("Algorithm 4 needs the BCCB or the DCT preconditioner")
+    if kind == AR:
+        lam = _pc.ar_eigs(_pc.symmetrize(H), n)
+        return _pc.ar_filter(r, lam / (lam * lam + alpha))
+    raise ValueError("Algorithm 4 needs the BCCB, DCT or antireflective preconditioner")
 
 
 def tikhonov_norm(r: np.ndarray, H: np.ndarray, alpha: float, kind: int) -> float:

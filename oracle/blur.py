@@ -6,11 +6,20 @@ rectangular n^2 x m^2 matrix A = M A_big keeps only the pixels of the field of
 view, i.e. A f is the *valid* part of the 2-D convolution of f with H, and
 A^T y is the *full* correlation of y with H.  Section 2.2 and Table 1: with an
 imposed boundary condition the unknown is n x n and f is first extended by c =
-(p-1)/2 pixels on every side (zero, periodic, or mirrored), then blurred in
-valid mode.  The transpose of a boundary-condition blur is the full correlation
-followed by the transpose of the extension (the pad contributions folded back
-onto the pixels they were copied from); the reblurring substitute of the paper
-is only used for antireflective conditions, which are not modelled here.
+(p-1)/2 pixels on every side (zero, periodic, mirrored or antireflected),
+then blurred in valid mode.  The transpose of a boundary-condition blur is the
+full correlation followed by the transpose of the extension (the pad
+contributions folded back onto the pixels they were copied from).
+
+Antireflective conditions (section 2.2): a pad pixel beyond an edge is twice
+the edge pixel minus the pixel mirrored about it (the extension keeps the
+normal derivative continuous); a corner pad pixel is antireflected in one
+direction and then in the other.  The extension is therefore linear but not a
+selection: row r of E holds 2 at the edge pixel and -1 at the mirrored one.
+With these conditions the paper replaces A^T by the reblurring matrix A': the
+same boundary conditions applied to the PSF rotated by 180 degrees.
+:func:`blurT` (the operator the iterations use) returns A' for them, while
+:func:`blurT_direct` and :func:`blurT_fft` stay the exact transposes.
 
 Index convention: images are row-major arrays f[y, x]; H[a, b] with centre
 (c, c).  With these conventions
@@ -30,8 +39,9 @@ import numpy as np
 import scipy.signal
 import scipy.sparse as sp
 
-RECT, REFLECT, PERIODIC, ZERO = 0, 1, 2, 3
-BC_NAMES = {RECT: "rect", REFLECT: "reflect", PERIODIC: "periodic", ZERO: "zero"}
+RECT, REFLECT, PERIODIC, ZERO, ANTIREFLECT = 0, 1, 2, 3, 4
+BC_NAMES = {RECT: "rect", REFLECT: "reflect", PERIODIC: "periodic", ZERO: "zero",
+            ANTIREFLECT: "antireflect"}
 
 
 def unknown_side(n: int, p: int, bc: int) -> int:
@@ -41,16 +51,32 @@ def unknown_side(n: int, p: int, bc: int) -> int:
 
 
 def extension_matrix(n: int, c: int, bc: int) -> sp.csr_matrix:
-    """(n + 2c) x n 0/1 matrix E with pad(f) = E f E^T along both axes.
+    """(n + 2c) x n matrix E with pad(f) = E f E^T along both axes.
 
     Row r (padded position r - c) selects the source pixel that Table 1 of the
     paper copies there: itself inside, its mirror image for reflective
     conditions (F_c, F_r: half-sample symmetric, position -1-i holds pixel i),
     its periodic image for periodic conditions, nothing for zero conditions.
+    For antireflective conditions (section 2.2) position -i holds
+    2 f[0] - f[i] and position n-1+i holds 2 f[n-1] - f[n-1-i] (1 <= i <= c,
+    c <= n - 1); applying E along both axes antireflects the corners first in
+    one direction and then in the other.
     """
-    rows, cols = [], []
+    rows, cols, vals = [], [], []
     for r in range(n + 2 * c):
         x = r - c
+        if bc == ANTIREFLECT:
+            if 0 <= x < n:
+                rows.append(r), cols.append(x), vals.append(1.0)
+            else:
+                edge = 0 if x < 0 else n - 1
+                mirror = 2 * edge - x
+                if not 0 <= mirror < n:
+                    raise ValueError("antireflective pad wider than the image")
+                rows += [r, r]
+                cols += [edge, mirror]
+                vals += [2.0, -1.0]
+            continue
         if bc == PERIODIC:
             src = x % n
         elif bc == REFLECT:
@@ -65,8 +91,8 @@ def extension_matrix(n: int, c: int, bc: int) -> sp.csr_matrix:
             raise ValueError("extension only defined for boundary conditions")
         rows.append(r)
         cols.append(src)
-    data = np.ones(len(rows))
-    return sp.csr_matrix((data, (rows, cols)), shape=(n + 2 * c, n))
+        vals.append(1.0)
+    return sp.csr_matrix((np.asarray(vals), (rows, cols)), shape=(n + 2 * c, n))
 
 
 def _extend(f: np.ndarray, c: int, bc: int) -> np.ndarray:
@@ -142,7 +168,17 @@ def blur(f, H, bc, method: str = "auto"):
     return blur_fft(f, H, bc)
 
 
+def reblur(y, H, bc, method: str = "auto"):
+    """A' y (section 2.2): the blur of y under the same boundary conditions
+    with the PSF rotated by 180 degrees."""
+    return blur(np.asarray(y, dtype=np.float64), np.asarray(H, dtype=np.float64)[::-1, ::-1], bc, method)
+
+
 def blurT(y, H, bc, method: str = "auto"):
+    """The transpose the iterations use: A^T, or the reblurring A' for
+    antireflective conditions (section 2.2)."""
+    if bc == ANTIREFLECT:
+        return reblur(y, H, bc, method)
     if method == "direct" or (method == "auto" and y.shape[0] <= 96):
         return blurT_direct(y, H, bc)
     return blurT_fft(y, H, bc)

@@ -18,7 +18,10 @@ Readings (recorded with the other readings of the paper):
   * mu may be one value or one value per band (band 0 is the low-pass);
   * the geometric schedule alpha_k = max(alpha_0 r^k, alpha_floor) is not
     the paper's; iteration k uses alpha_k and delta_k, and the returned image
-    is W^T (delta_K S_mu(z^K)).
+    is W^T (delta_K S_mu(z^K));
+  * with antireflective boundary conditions A^T stands for the reblurring
+    matrix A' throughout (section 2.2), so the update is W A' P r and the
+    norm of the step rule is the largest eigenvalue modulus of A' P A.
 """
 from __future__ import annotations
 
@@ -51,7 +54,8 @@ def alpha_table(kind: int, alpha0: float, count: int, ratio: float = 1.0,
 def opnorm(H: np.ndarray, n: int, bc: int, precond: int, alpha: float,
            tol: float = 1e-10) -> float:
     """||A^T P_alpha A|| (largest eigenvalue of the symmetric positive
-    semidefinite operator) by Lanczos."""
+    semidefinite operator) by Lanczos; for antireflective conditions the
+    largest eigenvalue modulus of A' P_alpha A by Arnoldi."""
     p = H.shape[0]
     N = _blur.unknown_side(n, p, bc)
 
@@ -63,6 +67,11 @@ def opnorm(H: np.ndarray, n: int, bc: int, precond: int, alpha: float,
 
     op = spla.LinearOperator((N * N, N * N), matvec=mv, dtype=np.float64)
     v0 = np.random.Generator(np.random.PCG64(12345)).standard_normal(N * N)
+    if bc == _blur.ANTIREFLECT:
+        # A' P A is not symmetric (section 2.2's reblurring): the largest
+        # eigenvalue modulus by Arnoldi instead of Lanczos
+        val = spla.eigs(op, k=1, which="LM", v0=v0, tol=tol, return_eigenvectors=False)
+        return float(abs(val[0]))
     val = spla.eigsh(op, k=1, which="LA", v0=v0, tol=tol, return_eigenvectors=False)
     return float(val[0])
 

@@ -18,13 +18,34 @@ reflective-boundary blur of H~, which the orthonormal 2-D DCT-II diagonalises
 
 ``NONE`` is P = I, which turns the iteration into the plain linearized
 Bregman iteration (eq. iterLinBreg).
+
+``AR`` is Algorithm 3 for antireflective boundary conditions (sections 2.2
+and 4.3): Q is the antireflective blur of H~.  For a PSF symmetric about its
+centre the antireflective extension of every vector of the basis
+
+    t_0[k] = 1 - k/(n-1),   t_j[k] = sin(pi j k / (n-1)) (0 < j < n-1),
+    t_{n-1}[k] = k/(n-1)
+
+is the vector itself continued (the sines are odd about both ends, the linear
+functions stay linear), so Q T = T Lambda with T = [t_0 .. t_{n-1}] along
+each axis (the antireflective transform: the sine transform with the two
+linear functions added) and
+
+    lambda[k, l] = sum_{a,b} H~[a, b] cos(w_k (a-c)) cos(w_l (b-c)),
+    w_j = pi j / (n-1) for the sines, w = 0 for the two linear functions.
+
+Read with the paper's convention that Q^T stands for the reblurring Q' (the
+antireflective blur of the rotated H~, i.e. Q itself), P = (Q Q' + alpha I)^-1
+= T (Lambda^2 + alpha)^-1 T^-1.  T is not orthogonal; the oracle builds it
+densely and applies T^-1 by solving with it.
 """
 from __future__ import annotations
 
 import numpy as np
 import scipy.fft
+import scipy.linalg
 
-BCCB, DCT, NONE = 0, 1, 2
+BCCB, DCT, NONE, AR = 0, 1, 2, 3
 
 
 def bccb_eigs_sq(H: np.ndarray, n: int) -> np.ndarray:
@@ -69,7 +90,47 @@ def apply_dct(r: np.ndarray, H: np.ndarray, alpha: float) -> np.ndarray:
     return scipy.fft.idctn(c2 / (lam * lam + alpha), type=2, norm="ortho")
 
 
+def ar_basis(n: int) -> np.ndarray:
+    """The n x n antireflective transform T (columns t_0 .. t_{n-1} above)."""
+    N = n - 1
+    k = np.arange(n, dtype=np.float64)
+    T = np.empty((n, n))
+    T[:, 0] = 1.0 - k / N
+    T[:, n - 1] = k / N
+    for j in range(1, n - 1):
+        T[:, j] = np.sin(np.pi * j * k / N)
+    return T
+
+
+def ar_eigs(Hs: np.ndarray, n: int) -> np.ndarray:
+    """lambda[k, l] of the antireflective blur of a quadrantally symmetric PSF
+    (closed form above)."""
+    Hs = np.asarray(Hs, dtype=np.float64)
+    p = Hs.shape[0]
+    c = (p - 1) // 2
+    w = np.pi * np.arange(n, dtype=np.float64) / (n - 1)
+    w[0] = w[n - 1] = 0.0
+    Cm = np.cos(w[:, None] * (np.arange(p) - c)[None, :])   # n x p
+    return Cm @ Hs @ Cm.T
+
+
+def ar_filter(r: np.ndarray, lam_filter: np.ndarray) -> np.ndarray:
+    """T (lam_filter * (T^-1 r T^-T)) T^T along both axes."""
+    T = ar_basis(r.shape[0])
+    lu = scipy.linalg.lu_factor(T)
+    coef = scipy.linalg.lu_solve(lu, scipy.linalg.lu_solve(lu, r).T).T
+    return T @ (coef * lam_filter) @ T.T
+
+
+def apply_ar(r: np.ndarray, H: np.ndarray, alpha: float) -> np.ndarray:
+    r = np.asarray(r, dtype=np.float64)
+    lam = ar_eigs(symmetrize(H), r.shape[0])
+    return ar_filter(r, 1.0 / (lam * lam + alpha))
+
+
 def apply(r: np.ndarray, H: np.ndarray, alpha: float, kind: int) -> np.ndarray:
+    if kind == AR:
+        return apply_ar(r, H, alpha)
     if kind == BCCB:
         return apply_bccb(r, H, alpha)
     if kind == DCT:
