@@ -378,6 +378,67 @@ def alg2_section(w, g, delta, steps: int = 10):
             "pcg_steps": info.pcg_steps}
 
 
+def antireflective_section(steps: int = 30, warmup: int = 3):
+    """Alg-BC3 of Example 4 at n = 1025: antireflective pad in the direct blur,
+    the reblur A' in place of A^T, the antireflective-transform preconditioner
+    (three passes of complex FFTs of length 2(n - 1) = 2048), 31 x 31
+    Gaussian, 3 levels, implicit state, automatic step; `steps` timed
+    iterations with the per-kernel profile.  Algorithmic bytes of the
+    transform passes: rows T^-1 read n^2 and write n^2 floats, columns read
+    n^2 and the n^2 filter and write n^2, rows T read n^2 and write n^2."""
+    import torch
+
+    import synth
+    from paper_1504_07234_amd import mlba
+
+    w = synth.make_workload("antireflect-ar-1025")
+    n, p = w.n, w.p
+    psf = torch.as_tensor(w.psf, dtype=torch.float32).cuda()
+    with mlba.Plan(n, p, mlba.RECT, mlba.NONE, 1, psf) as rect:
+        blurred = rect.apply_A(torch.as_tensor(w.truth, dtype=torch.float32).cuda())
+    xi = torch.as_tensor(w.xi, dtype=torch.float32).cuda()
+    g = (blurred + (w.noise_level * blurred.double().norm() / xi.double().norm()).float() * xi).contiguous()
+    names = {"fft_rows_fwd": "ar_rows_fwd", "fft_cols": "ar_cols_filter", "fft_rows_inv": "ar_rows_inv"}
+    with mlba.Plan(n, p, w.bc, w.precond, w.levels, psf) as plan:
+        N = plan.N
+        delta = 0.9 / max(plan.opnorm(w.alpha0, 50), 0.9)
+        f = torch.empty((N, N), dtype=torch.float32, device="cuda")
+        om = torch.zeros((N, N), dtype=torch.float32, device="cuda")
+        plan.restore(g, alpha=w.alpha0, mu=w.mu, delta=delta, iters=warmup, z=om, out=f, track=False,
+                     implicit=True)
+        plan.profile_begin(steps, every=PROFILE_EVERY)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.restore(g, alpha=w.alpha0, mu=w.mu, delta=delta, iters=steps, k0=warmup, z=om, out=f, track=False,
+                     implicit=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        _, rec = plan.profile_end()
+        kernels = plan.profile_kernels()
+    rec = max(rec, 1)
+    model = kernel_model(n, p, N, w.levels, True, False)
+    nn = 4.0 * n * n
+    model["fft_rows_fwd"] = {"bytes": 2 * nn, "flops": 0.0, "launches": 1, "bound": "hbm"}
+    model["fft_cols"] = {"bytes": 3 * nn, "flops": 0.0, "launches": 1, "bound": "hbm"}
+    model["fft_rows_inv"] = {"bytes": 2 * nn, "flops": 0.0, "launches": 1, "bound": "hbm"}
+    kern = {}
+    for k, (ms, nl) in kernels.items():
+        us = ms * 1e3 / rec
+        e = {"us_per_iter": round(us, 2), "launches_per_iter": round(nl / rec, 2)}
+        mk = model.get(k)
+        if mk is not None and us > 0:
+            e["GBs"] = round(mk["bytes"] / (us * 1e-6) / 1e9, 1)
+            e["bound"] = mk["bound"]
+            e["frac"] = round(e["GBs"] / HBM_PEAK_GBS if mk["bound"] == "hbm" else
+                              mk["flops"] / (us * 1e-6) / 1e12 / FP32_VALU_PEAK_TFLOPS, 4)
+        kern[names.get(k, k)] = e
+    return {"workload": w.name, "n": n, "p": p, "levels": w.levels, "boundary": "antireflective (A' = reblur)",
+            "precond": "antireflective transform (FFT length 2048)", "alpha": w.alpha0, "mu": w.mu,
+            "delta": round(delta, 6), "state": "implicit omega", "steps": steps,
+            "ms_per_step": round(el * 1e3 / steps, 5), "Mpx_it_s": round(n * n * steps / el / 1e6, 2),
+            "kernels": kern}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -389,6 +450,7 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-sequential section")
     ap.add_argument("--no-unrolled", action="store_true", help="skip the unrolled forward/backward section")
     ap.add_argument("--no-alg4", action="store_true", help="skip the Algorithm 4 / 4-NS and Algorithm 2 sections")
+    ap.add_argument("--no-ar", action="store_true", help="skip the antireflective (Alg-BC3) section")
     ap.add_argument("--state", choices=("implicit", "explicit"), default="implicit",
                     help="iteration state: omega (z = W omega recomputed) or the frame coefficients z")
     ap.add_argument("--compare-steps", type=int, default=20,
@@ -582,6 +644,8 @@ def main() -> int:
     if not args.no_alg4:
         out["alg4"] = alg4_section(w, g, float(w.noise_level * blurred.double().norm()))
         out["alg2"] = alg2_section(w, g, delta)
+    if not args.no_ar:
+        out["antireflective"] = antireflective_section()
     if not args.no_cpu:
         from oracle import blur as oblur
         g64 = synth.add_noise(oblur.blur(w.truth, w.psf, oblur.RECT), w.xi, w.noise_level)

@@ -61,12 +61,20 @@ extern "C" {
 #define MLBA_BC_REFLECT   1  /* reflective (half-sample symmetric) pad, Table 1 */
 #define MLBA_BC_PERIODIC  2  /* periodic pad, Table 1                          */
 #define MLBA_BC_ZERO      3  /* zero pad, Table 1                              */
+#define MLBA_BC_ANTIREFLECT 4  /* antireflective pad, section 2.2: position -i holds
+                                  2 f[0] - f[i] along each axis, corners antireflected
+                                  along one axis then the other; A^T is replaced by the
+                                  reblurring A' (the same pad, PSF rotated 180 degrees)
+                                  everywhere the method uses it                    */
 
 /* ---- preconditioners (section 4) ------------------------------------ */
 #define MLBA_PRECOND_BCCB 0  /* P = (C C^T + alpha I)^-1 by 2-D FFT, Algorithm 1 */
 #define MLBA_PRECOND_DCT  1  /* P = (Q Q^T + alpha I)^-1 by 2-D DCT of the
                                 symmetrised PSF, Algorithm 3                  */
 #define MLBA_PRECOND_NONE 2  /* P = I: plain linearized Bregman, eq. (iterLinBreg) */
+#define MLBA_PRECOND_AR   3  /* P = (Q Q' + alpha I)^-1, Q the antireflective blur of the
+                                symmetrised PSF, by the 2-D antireflective transform
+                                (sections 2.2, 4.3: Algorithm 3 for MLBA_BC_ANTIREFLECT) */
 
 /* ---- alpha schedules ------------------------------------------------- */
 #define MLBA_ALPHA_CONST      0  /* alpha_k = alpha0                              */
@@ -161,10 +169,13 @@ int mlba_version(void);
  * mlba_plan_create: n observed side, p odd PSF side (1 <= p <= n, p <= 49), bc one of
  * MLBA_BC_*, precond one of MLBA_PRECOND_*, levels in [1, 4] with
  * 2^(levels-1) < N.  The transforms of P need n = 2^a 3^b, a >= 1,
- * 8 <= n <= 2048 (MLBA_EUNSUPPORTED otherwise).  psf: device p x p.
+ * 8 <= n <= 2048 for MLBA_PRECOND_BCCB and MLBA_PRECOND_DCT, and
+ * 2(n - 1) = 2^a 3^b <= 2048 (n = 65, 97, 129, 193, 257, ..., 1025) for
+ * MLBA_PRECOND_AR (MLBA_EUNSUPPORTED otherwise).  psf: device p x p.
  * Allocates the workspace, copies the PSF and computes the spectrum of
  * (C C^T) or (Q Q^T) on `stream` (section 4.1 / 4.3).  The plan keeps no
- * reference to `psf`. */
+ * reference to `psf`.  With MLBA_BC_ANTIREFLECT every A^T below (operators,
+ * iterations, the norm of mlba_plan_opnorm) is the reblurring A'. */
 int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int levels,
                      const float* psf, hipStream_t stream);
 /* Replace the PSF (same p) and recompute the spectrum. psf: device p x p. */

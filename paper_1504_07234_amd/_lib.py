@@ -14,8 +14,8 @@ LIB_PATH = os.path.join(HERE, "libmlba.so")
 # status codes
 OK, WARN_DIVERGED, EINVAL, EUNSUPPORTED, EHIP, ENOMEM = 0, 1, -1, -2, -3, -4
 # boundary models / preconditioners / schedules
-BC_RECT, BC_REFLECT, BC_PERIODIC, BC_ZERO = 0, 1, 2, 3
-PRECOND_BCCB, PRECOND_DCT, PRECOND_NONE = 0, 1, 2
+BC_RECT, BC_REFLECT, BC_PERIODIC, BC_ZERO, BC_ANTIREFLECT = 0, 1, 2, 3, 4
+PRECOND_BCCB, PRECOND_DCT, PRECOND_NONE, PRECOND_AR = 0, 1, 2, 3
 ALPHA_CONST, ALPHA_GEOMETRIC, ALPHA_TABLE, ALPHA_NS = 0, 1, 2, 3
 METHOD_MLBA, METHOD_ALG4, METHOD_ALG2 = 0, 1, 2
 BLUR_DIRECT, BLUR_FFT = 0, 1

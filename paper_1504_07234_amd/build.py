@@ -36,8 +36,8 @@ COMMON_FLAGS = [
     f"-I{CSRC}",
 ]
 
-SOURCES = ["conv.hip", "framelet.hip", "shrink.hip", "fft.hip", "fftconv.hip", "reduce.hip", "psfgrad.hip", "mlba.hip",
-           "batch.hip", "unrolled.hip"]
+SOURCES = ["conv.hip", "framelet.hip", "shrink.hip", "fft.hip", "artrans.hip", "fftconv.hip", "reduce.hip",
+           "psfgrad.hip", "mlba.hip", "batch.hip", "unrolled.hip"]
 
 
 def _compile(src: str) -> str:

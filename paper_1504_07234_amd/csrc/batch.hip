@@ -224,6 +224,7 @@ int mlba_batch_create(mlba_batch_t* batch, int count, const mlba_plan_t* plans, 
     for (int i = 0; i < count; ++i) {
         if (!plans[i]) return MLBA_EINVAL;
         if (plans[i]->levels != plans[0]->levels || plans[i]->precond != plans[0]->precond) return MLBA_EINVAL;
+        if (plans[i]->precond == MLBA_PRECOND_AR) return MLBA_EUNSUPPORTED;  // batched passes: DFT and DCT only
         for (int j = 0; j < i; ++j)
             if (plans[j] == plans[i]) return MLBA_EINVAL;  // one image per plan (the plan holds its buffers)
     }

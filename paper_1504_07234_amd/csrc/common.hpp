@@ -12,7 +12,11 @@ constexpr int kBlock = 256;  // threads per workgroup for every kernel here
 //   EXT_ZERO     value 0
 //   EXT_REFLECT  half-sample mirror, position x -> s or 2S-1-s, s = x mod 2S
 //   EXT_PERIODIC position x -> x mod S
-enum Ext : int { EXT_ZERO = 0, EXT_REFLECT = 1, EXT_PERIODIC = 2 };
+//   EXT_ANTIREFLECT along each axis position -i -> 2 v[0] - v[i] and
+//                S-1+i -> 2 v[S-1] - v[S-1-i] (section 2.2); a corner is
+//                antireflected along one axis and then the other.  Positions
+//                further out than S-1 are clamped (they feed no output).
+enum Ext : int { EXT_ZERO = 0, EXT_REFLECT = 1, EXT_PERIODIC = 2, EXT_ANTIREFLECT = 3 };
 
 __device__ __forceinline__ int mod_pos(int x, int m) {
     int r = x % m;
@@ -37,11 +41,38 @@ __device__ __forceinline__ int reflect_index(int x, int S) {
     return s >= S ? 2 * S - 1 - s : s;
 }
 
+// One axis of the antireflective pad: the value at position x is
+// wa * v[ia] + wb * v[ib].
+__device__ __forceinline__ void antireflect_axis(int x, int S, int* ia, int* ib, float* wa, float* wb) {
+    if (x >= 0 && x < S) {
+        *ia = *ib = x;
+        *wa = 1.0f;
+        *wb = 0.0f;
+        return;
+    }
+    const int e = x < 0 ? 0 : S - 1;
+    *ia = e;
+    *ib = min(max(2 * e - x, 0), S - 1);
+    *wa = 2.0f;
+    *wb = -1.0f;
+}
+
+__device__ __forceinline__ float fetch_antireflect(const float* __restrict__ src, int S, int y, int x) {
+    int ya, yb, xa, xb;
+    float wya, wyb, wxa, wxb;
+    antireflect_axis(y, S, &ya, &yb, &wya, &wyb);
+    antireflect_axis(x, S, &xa, &xb, &wxa, &wxb);
+    const float* ra = src + (size_t)ya * S;
+    const float* rb = src + (size_t)yb * S;
+    return wya * (wxa * ra[xa] + wxb * ra[xb]) + wyb * (wxa * rb[xa] + wxb * rb[xb]);
+}
+
 // Read src[y][x] of an S x S image under extension `ext`.
 __device__ __forceinline__ float fetch_ext(const float* __restrict__ src, int S, int y, int x, int ext) {
     if (y >= 0 && y < S && x >= 0 && x < S) return src[(size_t)y * S + x];
     if (ext == EXT_ZERO) return 0.0f;
     if (ext == EXT_PERIODIC) return src[(size_t)mod_pos(y, S) * S + mod_pos(x, S)];
+    if (ext == EXT_ANTIREFLECT) return fetch_antireflect(src, S, y, x);
     return src[(size_t)reflect_index(y, S) * S + reflect_index(x, S)];
 }
 

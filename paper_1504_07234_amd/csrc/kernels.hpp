@@ -77,8 +77,8 @@ struct BatchImage {
     FftDesc fd;
 };
 
-__host__ __device__ inline int ext_of_bc(int bc) {
-    return bc == 1 ? EXT_REFLECT : (bc == 2 ? EXT_PERIODIC : EXT_ZERO);  // REFLECT, PERIODIC, else zero
+__host__ __device__ inline int ext_of_bc(int bc) {  // REFLECT, PERIODIC, ANTIREFLECT, else zero
+    return bc == 1 ? EXT_REFLECT : (bc == 2 ? EXT_PERIODIC : (bc == 4 ? EXT_ANTIREFLECT : EXT_ZERO));
 }
 
 // r = g - A u  (section 2: valid convolution of the (extended) unknown)
@@ -97,7 +97,10 @@ __host__ __device__ inline ConvJob blur_job(const BatchImage& I) {
 }
 
 // w = A^T t (full correlation; the reflective model writes the padded grid
-// wext, folded afterwards)
+// wext, folded afterwards).  Zero and periodic models: the correlation of the
+// extended t, which is their exact transpose.  Antireflective model: the same
+// correlation of the antireflected t, i.e. the reblurring A' (the blur with
+// the PSF rotated by 180 degrees, section 2.2) that replaces A^T there.
 __host__ __device__ inline ConvJob blurT_job(const BatchImage& I) {
     ConvJob j;
     j.src = I.t;
@@ -111,7 +114,7 @@ __host__ __device__ inline ConvJob blurT_job(const BatchImage& I) {
         j.dst = I.bc == 0 ? I.w : I.wext;
         j.D = I.n + I.p - 1;
     } else {
-        j.ext = I.bc == 2 ? EXT_PERIODIC : EXT_ZERO;
+        j.ext = ext_of_bc(I.bc);
         j.org = -I.c;
         j.dst = I.w;
         j.D = I.n;
@@ -277,6 +280,22 @@ hipError_t launch_dct_rows_inv(const float* Tr, int n, int ts, float* dst, const
 // lambda itself into lam when given
 hipError_t launch_dct_spectrum(const float* psf, int p, int n, float* spec, const float* costab,
                                hipStream_t s, float* lam = nullptr);
+// Antireflective transform (Algorithm 3 with antireflective boundaries): rows
+// T^-1 -> Tr (transposed, real, row stride ts = ar_workspace_stride(n), n
+// rows); columns T^-1, filter 1/(spec + alpha) (times lamr), T; rows T -> dst.
+// fd / tw describe the complex FFT of length 2(n - 1).
+bool ar_transform_supported(int n);
+int ar_workspace_stride(int n);
+hipError_t launch_ar_rows_fwd(const float* src, int n, float* Tr, int ts, const FftDesc& fd, const float2* tw,
+                              hipStream_t s);
+hipError_t launch_ar_cols_filter(float* Tr, int n, int ts, const float* spec, float alpha, const float* lamr,
+                                 const FftDesc& fd, const float2* tw, hipStream_t s);
+hipError_t launch_ar_rows_inv(const float* Tr, int n, int ts, float* dst, const FftDesc& fd, const float2* tw,
+                              hipStream_t s, int accum = 0);
+// spec[kx][ky] = lambda[ky][kx]^2 of the antireflective blur of the
+// symmetrised PSF, lambda into lam when given; costab[q] = cos(pi q / (n-1))
+hipError_t launch_ar_spectrum(const float* psf, int p, int n, float* spec, const float* costab, hipStream_t s,
+                              float* lam = nullptr);
 // place the PSF in the top-left corner of a zeroed n x n image
 hipError_t launch_pad_psf(const float* psf, int p, float* dst, int n, hipStream_t s);
 // the PSF centred at the origin (kernel of the periodic-boundary blur)

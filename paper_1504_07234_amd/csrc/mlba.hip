@@ -219,6 +219,14 @@ int do_precond(mlba_plan_s* P, const float* r, float* t, double alpha, hipStream
         MARK(PRECOND, FFT_COLS);
         HIPCHK(launch_dct_rows_inv(Tr, n, P->ts, t, P->fd, P->tw, P->dtw, s));
         MARK(PRECOND, FFT_ROWS_INV);
+    } else if (P->precond == MLBA_PRECOND_AR) {
+        float* Tr = (float*)P->swork;
+        HIPCHK(launch_ar_rows_fwd(r, n, Tr, P->ts, P->fd, P->tw, s));
+        MARK(PRECOND, FFT_ROWS_FWD);
+        HIPCHK(launch_ar_cols_filter(Tr, n, P->ts, P->spec, (float)alpha, nullptr, P->fd, P->tw, s));
+        MARK(PRECOND, FFT_COLS);
+        HIPCHK(launch_ar_rows_inv(Tr, n, P->ts, t, P->fd, P->tw, s));
+        MARK(PRECOND, FFT_ROWS_INV);
     } else if (r != t) {
         HIPCHK(hipMemcpyAsync(t, r, (size_t)n * n * sizeof(float), hipMemcpyDeviceToDevice, s));
         MARK(PRECOND, OTHER);
@@ -239,6 +247,8 @@ int compute_spectrum(mlba_plan_s* P, hipStream_t s) {
         }
     } else if (P->precond == MLBA_PRECOND_DCT) {
         HIPCHK(launch_dct_spectrum(P->psf, P->p, n, P->spec, P->costab, s, P->lamr));
+    } else if (P->precond == MLBA_PRECOND_AR) {
+        HIPCHK(launch_ar_spectrum(P->psf, P->p, n, P->spec, P->costab, s, P->lamr));
     }
     return MLBA_OK;
 }
@@ -254,6 +264,14 @@ int do_ct_precond(mlba_plan_s* P, const float* r, float* t, double alpha, int ac
         HIPCHK(launch_fft_cols_filter(T, n, P->ts, P->spec, (float)alpha, inv, P->fd, P->tw, s, P->lamc));
         MARK(PRECOND, FFT_COLS);
         HIPCHK(launch_fft_rows_c2r(T, n, P->ts, t, P->fd, P->tw, s, accum));
+        MARK(PRECOND, FFT_ROWS_INV);
+    } else if (P->precond == MLBA_PRECOND_AR) {
+        float* Tr = (float*)P->swork;
+        HIPCHK(launch_ar_rows_fwd(r, n, Tr, P->ts, P->fd, P->tw, s));
+        MARK(PRECOND, FFT_ROWS_FWD);
+        HIPCHK(launch_ar_cols_filter(Tr, n, P->ts, P->spec, (float)alpha, P->lamr, P->fd, P->tw, s));
+        MARK(PRECOND, FFT_COLS);
+        HIPCHK(launch_ar_rows_inv(Tr, n, P->ts, t, P->fd, P->tw, s, accum));
         MARK(PRECOND, FFT_ROWS_INV);
     } else {
         float* Tr = (float*)P->swork;
@@ -503,13 +521,16 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
     *plan = nullptr;
     if (n < 2 || p < 1 || (p % 2) == 0 || p > n) return MLBA_EINVAL;
     if (p > 49) return MLBA_EUNSUPPORTED;  // the blur's LDS window
-    if (bc < MLBA_BC_RECT || bc > MLBA_BC_ZERO) return MLBA_EINVAL;
-    if (precond < MLBA_PRECOND_BCCB || precond > MLBA_PRECOND_NONE) return MLBA_EINVAL;
+    if (bc < MLBA_BC_RECT || bc > MLBA_BC_ANTIREFLECT) return MLBA_EINVAL;
+    if (precond < MLBA_PRECOND_BCCB || precond > MLBA_PRECOND_AR) return MLBA_EINVAL;
     if (levels < 1 || levels > 4) return MLBA_EINVAL;
     const int N = bc == MLBA_BC_RECT ? n + p - 1 : n;
     if ((1 << (levels - 1)) >= N) return MLBA_EINVAL;
     int a2 = 0, b3 = 0;
-    if (precond != MLBA_PRECOND_NONE) {
+    if (precond == MLBA_PRECOND_AR) {  // complex FFTs of length 2(n - 1)
+        if (!ar_transform_supported(n)) return MLBA_EUNSUPPORTED;
+        factor_23(2 * (n - 1), &a2, &b3);
+    } else if (precond != MLBA_PRECOND_NONE) {
         if (!factor_23(n, &a2, &b3) || a2 < 1 || n < 8 || n > 2048) return MLBA_EUNSUPPORTED;
     }
 
@@ -561,8 +582,9 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
     if (bc == MLBA_BC_REFLECT) ALLOC(P->wext, (size_t)m * m);
 
     if (precond != MLBA_PRECOND_NONE) {
+        const int L = precond == MLBA_PRECOND_AR ? 2 * (n - 1) : n;  // transform length
         FftDesc& fd = P->fd;
-        fd.n = n;
+        fd.n = L;
         fd.nst = 0;
         int a = a2;
         while (a >= 3) {
@@ -573,21 +595,33 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
         if (a == 1) fd.radix[fd.nst++] = 2;
         for (int i = 0; i < b3; ++i) fd.radix[fd.nst++] = 3;
 
-        std::vector<float2> tw(n), dtw(n);
-        std::vector<float> cost(2 * n);
+        // the cosine table serves the eigenvalues: angles pi q / n (DCT) or
+        // pi q / (n - 1) (antireflective transform); BCCB does not read it
+        const int CN = precond == MLBA_PRECOND_AR ? n - 1 : n;
+        std::vector<float2> tw(L), dtw(n);
+        std::vector<float> cost(2 * CN);
         const double pi = 3.14159265358979323846;
-        for (int q = 0; q < n; ++q) {
-            const double ang = -2.0 * pi * (double)q / (double)n;
+        for (int q = 0; q < L; ++q) {
+            const double ang = -2.0 * pi * (double)q / (double)L;
             tw[q] = make_float2((float)cos(ang), (float)sin(ang));
+        }
+        for (int q = 0; q < n; ++q) {
             const double ang2 = -pi * (double)q / (2.0 * (double)n);
             dtw[q] = make_float2((float)cos(ang2), (float)sin(ang2));
         }
-        for (int q = 0; q < 2 * n; ++q) cost[q] = (float)cos(pi * (double)q / (double)n);
-        ALLOC(P->tw, (size_t)n);
+        for (int q = 0; q < 2 * CN; ++q) cost[q] = (float)cos(pi * (double)q / (double)CN);
+        ALLOC(P->tw, (size_t)L);
         ALLOC(P->dtw, (size_t)n);
-        ALLOC(P->costab, (size_t)2 * n);
+        ALLOC(P->costab, (size_t)2 * CN);
         ALLOC(P->ns, 8);
-        if (precond == MLBA_PRECOND_BCCB) {
+        if (precond == MLBA_PRECOND_AR) {
+            P->ts = ar_workspace_stride(n);
+            ALLOC(P->spec, obs);
+            if (bc != MLBA_BC_RECT) ALLOC(P->lamr, obs);
+            float* Tr = nullptr;
+            ALLOC(Tr, (size_t)n * P->ts);
+            P->swork = Tr;
+        } else if (precond == MLBA_PRECOND_BCCB) {
             P->ts = n + 16;
             ALLOC(P->spec, (size_t)(n / 2 + 1) * n);
             if (bc != MLBA_BC_RECT) ALLOC(P->lamc, (size_t)(n / 2 + 1) * n);
@@ -603,10 +637,10 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
             P->swork = Tr;
         }
 #undef ALLOC
-        hipError_t e = hipMemcpyAsync(P->tw, tw.data(), n * sizeof(float2), hipMemcpyHostToDevice, s);
+        hipError_t e = hipMemcpyAsync(P->tw, tw.data(), L * sizeof(float2), hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipMemcpyAsync(P->dtw, dtw.data(), n * sizeof(float2), hipMemcpyHostToDevice, s);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(P->costab, cost.data(), 2 * n * sizeof(float), hipMemcpyHostToDevice, s);
+            e = hipMemcpyAsync(P->costab, cost.data(), 2 * CN * sizeof(float), hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);  // host tables go out of scope
         if (e != hipSuccess) {
             mlba_internal_set_hip(e);

@@ -32,16 +32,16 @@ struct mlba_plan_s {
     int blur_fft = 0;          // rectangular model: A and A^T by FFTs of an M x M grid
     mlba::FftConv fc{};        // its plan and buffers (allocated on first use)
     float* psf = nullptr;
-    float* spec = nullptr;     // BCCB: [n/2+1][n] |Lambda|^2 (transposed); DCT: [n][n] lambda^2
+    float* spec = nullptr;     // BCCB: [n/2+1][n] |Lambda|^2 (transposed); DCT, AR: [n][n] lambda^2
     float2* lamc = nullptr;    // square models, BCCB: Lambda_c of the centred PSF (layout of spec)
-    float* lamr = nullptr;     // square models, DCT: lambda (layout of spec)
+    float* lamr = nullptr;     // square models, DCT and AR: lambda (layout of spec)
     double* ns = nullptr;      // Algorithm 4-NS device state
     double* ahist = nullptr;   // alpha_k used (ring like rn)
     float* pcg = nullptr;      // Algorithm 2: t, z, d, q (n x n each)
     double* pcgs = nullptr;    // Algorithm 2 scalars: rho (two slots), pq, rho0
-    float2* tw = nullptr;      // exp(-2 pi i q / n)
+    float2* tw = nullptr;      // exp(-2 pi i q / L), L = fd.n (n; 2(n-1) for AR)
     float2* dtw = nullptr;     // exp(-i pi k / (2n))
-    float* costab = nullptr;   // cos(pi q / n), q < 2n
+    float* costab = nullptr;   // cos(pi q / n), q < 2n (AR: cos(pi q / (n-1)), q < 2(n-1))
     void* swork = nullptr;     // spectral workspace
     float* u = nullptr;        // N x N synthesis output
     float* r = nullptr;        // n x n residual

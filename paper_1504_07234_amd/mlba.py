@@ -14,8 +14,9 @@ import torch
 from . import _lib
 from ._lib import check
 
-RECT, REFLECT, PERIODIC, ZERO = _lib.BC_RECT, _lib.BC_REFLECT, _lib.BC_PERIODIC, _lib.BC_ZERO
-BCCB, DCT, NONE = _lib.PRECOND_BCCB, _lib.PRECOND_DCT, _lib.PRECOND_NONE
+RECT, REFLECT, PERIODIC, ZERO, ANTIREFLECT = (_lib.BC_RECT, _lib.BC_REFLECT, _lib.BC_PERIODIC, _lib.BC_ZERO,
+                                             _lib.BC_ANTIREFLECT)
+BCCB, DCT, NONE, AR = _lib.PRECOND_BCCB, _lib.PRECOND_DCT, _lib.PRECOND_NONE, _lib.PRECOND_AR
 MLBA, ALG4, ALG2 = _lib.METHOD_MLBA, _lib.METHOD_ALG4, _lib.METHOD_ALG2
 BLUR_DIRECT, BLUR_FFT = _lib.BLUR_DIRECT, _lib.BLUR_FFT
 

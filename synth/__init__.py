@@ -35,8 +35,8 @@ __all__ = [
 ]
 
 # boundary / preconditioner codes (plain integers so both sides can use them)
-RECT, REFLECT, PERIODIC, ZERO = 0, 1, 2, 3
-BCCB, DCT, NONE = 0, 1, 2
+RECT, REFLECT, PERIODIC, ZERO, ANTIREFLECT = 0, 1, 2, 3, 4
+BCCB, DCT, NONE, AR = 0, 1, 2, 3
 
 
 def rng(seed: int) -> np.random.Generator:
@@ -271,12 +271,26 @@ def batched_workloads(seed: int = 4, count: int = 64, sides=(128, 192, 256, 384,
     return out
 
 
+def _cfg_ar(seed=6):
+    """Antireflective model with the antireflective-transform preconditioner
+    (Alg-BC3 of Example 4): 31 x 31 Gaussian PSF of standard deviation 2.5,
+    2 % noise, the observation the valid part of a larger scene."""
+    g = rng(seed)
+    n, p = 1025, 31
+    truth = shapes_image(n + p - 1, g, n_rect=20, n_disk=10, n_bumps=10, texture=0.2)
+    psf = gaussian_psf(p, 2.5)
+    xi = white_noise((n, n), g)
+    return Workload("antireflect-ar-1025", n, p, truth, psf, xi, 0.02, ANTIREFLECT, AR, 3,
+                    alpha0=0.01, mu=1e-3, delta=0.0, iters=50)
+
+
 WORKLOADS = {
     "plain-fp64-72": lambda: _cfg1(),
     "rect-bccb-512": lambda: _cfg2(1),
     "reflect-dct-512": lambda: _cfg2(2),
     "rect-bccb-geometric-512": lambda: _cfg2(3),
     "rect-bccb-2048": lambda: _cfg3(),
+    "antireflect-ar-1025": lambda: _cfg_ar(),
 }
 
 

@@ -192,3 +192,14 @@ def test_threshold_free_run_is_preconditioned_landweber(pc):
         u = u + delta * Ar @ Pm @ (gobs.ravel() - A @ u)
     out = mlba.mlba(gobs, H, AR, pc, L, np.full(K, alpha), np.full(K + 1, delta), 0.0, K)
     np.testing.assert_allclose(out["f"].ravel(), u, rtol=0, atol=1e-11)
+
+
+def test_opnorm_closed_form_for_a_symmetric_psf():
+    """Symmetric PSF with the antireflective preconditioner: A = A' = Q, so
+    A' P A = T Lambda^2 (Lambda^2 + alpha)^-1 T^-1 and its largest eigenvalue
+    is the largest lambda^2 / (lambda^2 + alpha)."""
+    n, p, alpha = 10, 5, 0.05
+    H = synth.gaussian_psf(p, 1.2)
+    lam = precond.ar_eigs(H, n)
+    want = (lam * lam / (lam * lam + alpha)).max()
+    assert mlba.opnorm(H, n, AR, precond.AR, alpha) == pytest.approx(want, rel=1e-6)
