@@ -44,6 +44,7 @@ __device__ __forceinline__ float ar_odd_detrended(At at, int k, int N, float inv
 }
 
 // G row pairs per workgroup -> Tr[j][y] (row stride ts >= n + 1, j = 0..N)
+template <int NT>
 __device__ __forceinline__ void ar_rows_fwd_body(const float* __restrict__ src, int n, float* __restrict__ Tr,
                                                  int ts, const FftDesc& fd, const float2* __restrict__ tw, int G,
                                                  int seq_shift, int blk, float2* buf) {
@@ -63,7 +64,7 @@ __device__ __forceinline__ void ar_rows_fwd_body(const float* __restrict__ src, 
         buf[lds_slot(idx)] = v;
     }
     __syncthreads();
-    lds_fft<-1>(buf, fd, G, seq_shift, tw);
+    lds_fft_any<-1, NT>(buf, fd, G, seq_shift, tw);
     for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
         const int j = idx / G;
         const int g = idx - j * G;
@@ -84,6 +85,7 @@ __device__ __forceinline__ void ar_rows_fwd_body(const float* __restrict__ src, 
 // CP pairs of Tr rows per workgroup: T^-1 along the row, filter, T back.
 // filter[j] = 1 / (spec + alpha), times lamr for Algorithm 4 (dense [n][n],
 // spec[jx][jy]).
+template <int NT>
 __device__ __forceinline__ void ar_cols_filter_body(float* __restrict__ Tr, int n, int ts,
                                                     const float* __restrict__ spec, float alpha,
                                                     const float* __restrict__ lamr, const FftDesc& fd,
@@ -121,7 +123,7 @@ __device__ __forceinline__ void ar_cols_filter_body(float* __restrict__ Tr, int 
         lin[2 * q + (threadIdx.x & 1)] = c;
     }
     __syncthreads();
-    lds_fft<-1>(buf, fd, cp, seq_shift, tw);
+    lds_fft_any<-1, NT>(buf, fd, cp, seq_shift, tw);
 
     // filtered sine coefficients j = 1..N-1, held in registers while the
     // sequence is rebuilt as their odd extension
@@ -163,7 +165,7 @@ __device__ __forceinline__ void ar_cols_filter_body(float* __restrict__ Tr, int 
         buf[lds_slot(q * L + ((threadIdx.x & 1) ? N : 0))] = make_float2(0.0f, 0.0f);
     }
     __syncthreads();
-    lds_fft<-1>(buf, fd, cp, seq_shift, tw);
+    lds_fft_any<-1, NT>(buf, fd, cp, seq_shift, tw);
     for (int idx = threadIdx.x; idx < cp * n; idx += kBlock) {
         const int q = idx / n;
         const int k = idx - q * n;
@@ -177,6 +179,7 @@ __device__ __forceinline__ void ar_cols_filter_body(float* __restrict__ Tr, int 
     }
 }
 
+template <int NT>
 __device__ __forceinline__ void ar_rows_inv_body(const float* __restrict__ Tr, int n, int ts,
                                                  float* __restrict__ dst, const FftDesc& fd,
                                                  const float2* __restrict__ tw, int G, int seq_shift, int blk,
@@ -197,7 +200,7 @@ __device__ __forceinline__ void ar_rows_inv_body(const float* __restrict__ Tr, i
         buf[lds_slot(g * L + k)] = v;
     }
     __syncthreads();
-    lds_fft<-1>(buf, fd, G, seq_shift, tw);
+    lds_fft_any<-1, NT>(buf, fd, G, seq_shift, tw);
     for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
         const int g = idx / n;
         const int x = idx - g * n;
@@ -220,13 +223,15 @@ __device__ __forceinline__ void ar_rows_inv_body(const float* __restrict__ Tr, i
     }
 }
 
+template <int NT>
 __global__ __launch_bounds__(kBlock) void ar_rows_fwd_kernel(const float* __restrict__ src, int n,
                                                              float* __restrict__ Tr, int ts, FftDesc fd,
                                                              const float2* __restrict__ tw, int G, int seq_shift) {
     extern __shared__ float2 buf[];
-    ar_rows_fwd_body(src, n, Tr, ts, fd, tw, G, seq_shift, xcd_block(blockIdx.x, gridDim.x), buf);
+    ar_rows_fwd_body<NT>(src, n, Tr, ts, fd, tw, G, seq_shift, xcd_block(blockIdx.x, gridDim.x), buf);
 }
 
+template <int NT>
 __global__ __launch_bounds__(kBlock) void ar_cols_filter_kernel(float* __restrict__ Tr, int n, int ts,
                                                                 const float* __restrict__ spec, float alpha,
                                                                 const float* __restrict__ lamr, FftDesc fd,
@@ -234,15 +239,16 @@ __global__ __launch_bounds__(kBlock) void ar_cols_filter_kernel(float* __restric
                                                                 int seq_shift) {
     extern __shared__ float2 buf[];
     __shared__ float2 lin[2 * kArMaxBatch];
-    ar_cols_filter_body(Tr, n, ts, spec, alpha, lamr, fd, tw, CP, seq_shift, blockIdx.x, buf, lin);
+    ar_cols_filter_body<NT>(Tr, n, ts, spec, alpha, lamr, fd, tw, CP, seq_shift, blockIdx.x, buf, lin);
 }
 
+template <int NT>
 __global__ __launch_bounds__(kBlock) void ar_rows_inv_kernel(const float* __restrict__ Tr, int n, int ts,
                                                              float* __restrict__ dst, FftDesc fd,
                                                              const float2* __restrict__ tw, int G, int seq_shift,
                                                              int accum) {
     extern __shared__ float2 buf[];
-    ar_rows_inv_body(Tr, n, ts, dst, fd, tw, G, seq_shift, xcd_block(blockIdx.x, gridDim.x), buf, accum);
+    ar_rows_inv_body<NT>(Tr, n, ts, dst, fd, tw, G, seq_shift, xcd_block(blockIdx.x, gridDim.x), buf, accum);
 }
 
 // lambda of the antireflective blur of the symmetrised PSF (closed form
@@ -305,27 +311,47 @@ bool ar_transform_supported(int n) {
 
 int ar_workspace_stride(int n) { return ((n + 1 + 15) / 16) * 16 + 16; }
 
+// the compiled fixed-size transform when the length is kFixedN with one
+// sequence per workgroup (n = 1025), the run-time plan otherwise
 hipError_t launch_ar_rows_fwd(const float* src, int n, float* Tr, int ts, const FftDesc& fd, const float2* tw,
                               hipStream_t s) {
     const int G = ar_batch(n), L = 2 * (n - 1), pairs = (n + 1) / 2;
-    hipLaunchKernelGGL(ar_rows_fwd_kernel, dim3((pairs + G - 1) / G), dim3(kBlock), lds_bytes(G * L, L), s, src, n,
-                       Tr, ts, fd, tw, G, ar_shift_for(G));
+    const dim3 grid((pairs + G - 1) / G);
+    const size_t lds = lds_bytes(G * L, L);
+    if (L == kFixedN && G == 1)
+        hipLaunchKernelGGL(ar_rows_fwd_kernel<kFixedN>, grid, dim3(kBlock), lds, s, src, n, Tr, ts, fd, tw, 1,
+                           ar_shift_for(1));
+    else
+        hipLaunchKernelGGL(ar_rows_fwd_kernel<0>, grid, dim3(kBlock), lds, s, src, n, Tr, ts, fd, tw, G,
+                           ar_shift_for(G));
     return hipGetLastError();
 }
 
 hipError_t launch_ar_cols_filter(float* Tr, int n, int ts, const float* spec, float alpha, const float* lamr,
                                  const FftDesc& fd, const float2* tw, hipStream_t s) {
     const int CP = ar_batch(n), L = 2 * (n - 1), pairs = (n + 1) / 2;
-    hipLaunchKernelGGL(ar_cols_filter_kernel, dim3((pairs + CP - 1) / CP), dim3(kBlock), lds_bytes(CP * L, L), s,
-                       Tr, n, ts, spec, alpha, lamr, fd, tw, CP, ar_shift_for(CP));
+    const dim3 grid((pairs + CP - 1) / CP);
+    const size_t lds = lds_bytes(CP * L, L);
+    if (L == kFixedN && CP == 1)
+        hipLaunchKernelGGL(ar_cols_filter_kernel<kFixedN>, grid, dim3(kBlock), lds, s, Tr, n, ts, spec, alpha, lamr,
+                           fd, tw, 1, ar_shift_for(1));
+    else
+        hipLaunchKernelGGL(ar_cols_filter_kernel<0>, grid, dim3(kBlock), lds, s, Tr, n, ts, spec, alpha, lamr, fd,
+                           tw, CP, ar_shift_for(CP));
     return hipGetLastError();
 }
 
 hipError_t launch_ar_rows_inv(const float* Tr, int n, int ts, float* dst, const FftDesc& fd, const float2* tw,
                               hipStream_t s, int accum) {
     const int G = ar_batch(n), L = 2 * (n - 1), pairs = (n + 1) / 2;
-    hipLaunchKernelGGL(ar_rows_inv_kernel, dim3((pairs + G - 1) / G), dim3(kBlock), lds_bytes(G * L, L), s, Tr, n,
-                       ts, dst, fd, tw, G, ar_shift_for(G), accum);
+    const dim3 grid((pairs + G - 1) / G);
+    const size_t lds = lds_bytes(G * L, L);
+    if (L == kFixedN && G == 1)
+        hipLaunchKernelGGL(ar_rows_inv_kernel<kFixedN>, grid, dim3(kBlock), lds, s, Tr, n, ts, dst, fd, tw, 1,
+                           ar_shift_for(1), accum);
+    else
+        hipLaunchKernelGGL(ar_rows_inv_kernel<0>, grid, dim3(kBlock), lds, s, Tr, n, ts, dst, fd, tw, G,
+                           ar_shift_for(G), accum);
     return hipGetLastError();
 }
 

@@ -48,13 +48,15 @@ static int fc_seq_shift(int batch) {
 }
 
 // Rows pass: row pairs pair0 + blk*G + g of the M grid; entry (Y, X) is
-// src[Y - off][X - off] inside the S x S box at (off, off), else 0.
+// src[Y - off][X - off] inside the S x S box at (off, off), else 0.  With
+// `ar`, the box is widened by off on every side and holds the source's
+// antireflective pad there (section 2.2): the grid then carries E src E^T.
 // NT > 0: M == NT and G == 1.
 template <int NT>
 __global__ __launch_bounds__(kBlock) void fc_rows_fwd_kernel(const float* __restrict__ src, int S, int off, int M_,
                                                              float2* __restrict__ T, int ts, FftDesc fd,
                                                              const float2* __restrict__ tw, int G_, int seq_shift,
-                                                             int pair0, int pair_end) {
+                                                             int pair0, int pair_end, int ar) {
     extern __shared__ float2 buf[];
     const int M = NT > 0 ? NT : M_;
     const int G = NT > 0 ? 1 : G_;
@@ -65,8 +67,13 @@ __global__ __launch_bounds__(kBlock) void fc_rows_fwd_kernel(const float* __rest
         const int Y = 2 * (pb + g);
         const int x = X - off;
         float a = 0.0f, b = 0.0f;
-        if (pb + g < pair_end && x >= 0 && x < S) {
-            const int y0 = Y - off, y1 = Y + 1 - off;
+        const int y0 = Y - off, y1 = Y + 1 - off;
+        if (ar) {
+            if (pb + g < pair_end && x >= -off && x < S + off) {
+                if (y0 >= -off && y0 < S + off) a = fetch_ext(src, S, y0, x, EXT_ANTIREFLECT);
+                if (y1 >= -off && y1 < S + off) b = fetch_ext(src, S, y1, x, EXT_ANTIREFLECT);
+            }
+        } else if (pb + g < pair_end && x >= 0 && x < S) {
             if (y0 >= 0 && y0 < S) a = src[(size_t)y0 * S + x];
             if (y1 >= 0 && y1 < S) b = src[(size_t)y1 * S + x];
         }
@@ -335,17 +342,17 @@ __global__ __launch_bounds__(kBlock) void precond_fc_blurT_kernel(
 // ---- launchers ------------------------------------------------------------
 
 hipError_t launch_fc_rows_fwd(const FftConv& c, const float* src, int S, int off, int y_lo, int y_hi,
-                              hipStream_t s) {
+                              hipStream_t s, int ar) {
     const int G = fc_pairs_per_block(c.M);
     const int p0 = y_lo / 2, p1 = (y_hi + 1) / 2;
     const int blocks = (p1 - p0 + G - 1) / G;
     if (blocks <= 0) return hipSuccess;
     if (c.M == kFixedM && G == 1)
         hipLaunchKernelGGL(fc_rows_fwd_kernel<kFixedM>, dim3(blocks), dim3(kBlock), lds_bytes(c.M, c.M), s, src, S,
-                           off, c.M, c.T, c.ts, c.fd, c.tw, 1, fc_seq_shift(1), p0, p1);
+                           off, c.M, c.T, c.ts, c.fd, c.tw, 1, fc_seq_shift(1), p0, p1, ar);
     else
         hipLaunchKernelGGL(fc_rows_fwd_kernel<0>, dim3(blocks), dim3(kBlock), lds_bytes(G * c.M, c.M), s, src, S, off,
-                           c.M, c.T, c.ts, c.fd, c.tw, G, fc_seq_shift(G), p0, p1);
+                           c.M, c.T, c.ts, c.fd, c.tw, G, fc_seq_shift(G), p0, p1, ar);
     return hipGetLastError();
 }
 

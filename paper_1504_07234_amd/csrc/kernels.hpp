@@ -172,12 +172,14 @@ struct PrecondRows {
     const float2* tw;
 };
 // The three passes of the FFT blur, one launch each: forward rows of the
-// S x S image placed at (off, off) (rows outside [y_lo, y_hi) are zero),
+// S x S image placed at (off, off) (rows outside [y_lo, y_hi) are zero; `ar`:
+// with its antireflective pad of width off around it, i.e. E src E^T at 0),
 // columns (mode 0: product with the PSF spectrum or its conjugate and the
 // inverse, stored for the rows [o_lo, o_hi) only, whole row pairs; mode 1:
 // forward only into cspec), inverse rows cropped to the
 // D x D window at (oy, ox) with the epilogue g - . (partials) / plain / +=.
-hipError_t launch_fc_rows_fwd(const FftConv& c, const float* src, int S, int off, int y_lo, int y_hi, hipStream_t s);
+hipError_t launch_fc_rows_fwd(const FftConv& c, const float* src, int S, int off, int y_lo, int y_hi, hipStream_t s,
+                              int ar = 0);
 hipError_t launch_fc_cols(const FftConv& c, int conj_h, int y_lo, int y_hi, int mode, float2* cspec, hipStream_t s,
                           int o_lo, int o_hi);
 hipError_t launch_fc_rows_inv(const FftConv& c, int oy, int ox, int D, float* dst, const float* g, int accum,

@@ -113,9 +113,12 @@ size_t NN(const mlba_plan_s* P) { return (size_t)P->N * P->N; }
 // r = g - A u (g may be null: y = A u); partial sums of r^2 into P->partials
 int do_blur(mlba_plan_s* P, const float* u, const float* g, float* y, bool want_norm, int* nparts,
             hipStream_t s) {
-    if (P->blur_fft) {
+    if (P->blur_fft) {  // the grid holds u (rectangular) or its antireflective extension, m x m at the origin
         const int n = P->n, p = P->p, N = n + p - 1;
-        HIPCHK(launch_fc_rows_fwd(P->fc, u, N, 0, 0, N, s));
+        if (P->bc == MLBA_BC_ANTIREFLECT)
+            HIPCHK(launch_fc_rows_fwd(P->fc, u, n, P->c, 0, N, s, 1));
+        else
+            HIPCHK(launch_fc_rows_fwd(P->fc, u, N, 0, 0, N, s));
         MARK(BLUR, FC_ROWS_FWD);
         HIPCHK(launch_fc_cols(P->fc, 0, 0, N, 0, nullptr, s, p - 1, p - 1 + n + (n & 1)));
         MARK(BLUR, FC_COLS);
@@ -147,7 +150,8 @@ PrecondRows precond_rows(const mlba_plan_s* P) {
 // the preconditioner's forward row pass run as one launch (as do the
 // preconditioner's inverse row pass and the forward row pass of A^T).
 bool fused_fft_path(const mlba_plan_s* P) {
-    return P->blur_fft && P->precond == MLBA_PRECOND_BCCB && fftconv_fusable(P->fc, P->n, precond_rows(P));
+    return P->blur_fft && P->bc == MLBA_BC_RECT && P->precond == MLBA_PRECOND_BCCB &&
+           fftconv_fusable(P->fc, P->n, precond_rows(P));
 }
 
 // r = g - A u with its partials and the preconditioner's forward row pass of r
@@ -174,9 +178,21 @@ int do_precond_rows_blurT(mlba_plan_s* P, float* w, int accum, hipStream_t s) {
     return MLBA_OK;
 }
 
-// w = A^T y (+ fold of the reflective padding)
+// w (+)= A^T y on the FFT grid: the circular correlation of y placed at
+// (p-1, p-1), cropped to [0, N)^2; antireflective model: the reblur A' y, the
+// circular correlation of y's antireflective extension (m x m at the origin)
+// cropped to [0, n)^2 (the valid part of its convolution with the rotated PSF)
 int do_blurT_fft(mlba_plan_s* P, const float* y, float* w, int accum, hipStream_t s) {
     const int n = P->n, p = P->p, N = n + p - 1;
+    if (P->bc == MLBA_BC_ANTIREFLECT) {
+        HIPCHK(launch_fc_rows_fwd(P->fc, y, n, P->c, 0, N, s, 1));
+        MARK(BLUR_T, FC_ROWS_FWD);
+        HIPCHK(launch_fc_cols(P->fc, 1, 0, N, 0, nullptr, s, 0, n + (n & 1)));
+        MARK(BLUR_T, FC_COLS);
+        HIPCHK(launch_fc_rows_inv(P->fc, 0, 0, n, w, nullptr, accum, nullptr, nullptr, s));
+        MARK(BLUR_T, FC_ROWS_INV);
+        return MLBA_OK;
+    }
     HIPCHK(launch_fc_rows_fwd(P->fc, y, n, p - 1, p - 1, N, s));
     MARK(BLUR_T, FC_ROWS_FWD);
     HIPCHK(launch_fc_cols(P->fc, 1, p - 1, N, 0, nullptr, s, 0, N + (N & 1)));
@@ -677,12 +693,12 @@ int fft_grid_size(int N) {
     return best;
 }
 
-// Allocates the FFT blur of a rectangular plan (first use) and computes the
-// PSF spectrum on that grid.
+// Allocates the FFT blur of a rectangular or antireflective plan (first use)
+// and computes the PSF spectrum on that grid.
 int ensure_fftconv(mlba_plan_s* P, hipStream_t s) {
     if (P->fc.H) return MLBA_OK;
-    if (P->bc != MLBA_BC_RECT) return MLBA_EUNSUPPORTED;
-    const int M = fft_grid_size(P->N);
+    if (P->bc != MLBA_BC_RECT && P->bc != MLBA_BC_ANTIREFLECT) return MLBA_EUNSUPPORTED;
+    const int M = fft_grid_size(P->n + P->p - 1);  // the (extended) unknown, m x m
     if (M == 0) return MLBA_EUNSUPPORTED;
     if (fftconv_partials_count(M, P->n) > P->partials_cap) return MLBA_EUNSUPPORTED;
     FftConv c{};
@@ -765,7 +781,7 @@ int mlba_plan_autotune(mlba_plan_t P, int reps, double* ms_out, hipStream_t s) {
     if (!P || reps < 1) return MLBA_EINVAL;
     double t[2][2] = {{0.0, 0.0}, {-1.0, -1.0}};  // [direct / fft][A / A^T]
     const int keep = P->blur_fft;
-    const int have_fft = P->bc == MLBA_BC_RECT ? ensure_fftconv(P, s) : MLBA_EUNSUPPORTED;
+    const int have_fft = ensure_fftconv(P, s);
     if (have_fft < 0 && have_fft != MLBA_EUNSUPPORTED) return have_fft;
     for (int mode = 0; mode < (have_fft == MLBA_OK ? 2 : 1); ++mode) {
         P->blur_fft = mode;

@@ -71,6 +71,34 @@ def test_blur_and_reblur(mlba, n, p, kind):
     assert rel_err(r, gi - ref_Au) < TOL_L2
 
 
+@pytest.mark.parametrize("n,p,kind", [
+    (64, 9, "gauss"),
+    (97, 31, "motion"),
+    (150, 17, "rand"),
+    (257, 41, "rand"),
+    (1025, 31, "gauss"),   # the antireflective workload's shapes (grid 1152)
+])
+def test_fft_grid_blur_and_reblur(mlba, n, p, kind):
+    """A and A' with the antireflective extension placed on the FFT grid."""
+    announce(f"antireflective FFT-grid blur/reblur n={n} p={p} {kind}")
+    H = _psf(kind, p, n + 5 * p)
+    g = synth.rng(4500 + n + p)
+    u = g.random((n, n))
+    y = g.standard_normal((n, n))
+    gi = g.random((n, n))
+    with mlba.Plan(n, p, mlba.ANTIREFLECT, mlba.NONE, 1, cuda(H)) as plan:
+        plan.set_blur(mlba.BLUR_FFT)
+        Au = host(plan.apply_A(cuda(u)))
+        Ary = host(plan.apply_At(cuda(y)))
+        r = host(plan.residual(cuda(gi), cuda(u)))
+    ref_Au = ob.blur(u, H, AR_BC)
+    ref_Ary = ob.reblur(y, H, AR_BC)
+    print(f"  A {rel_err(Au, ref_Au):.2e}  A' {rel_err(Ary, ref_Ary):.2e}", flush=True)
+    assert rel_err(Au, ref_Au) < TOL_L2 and max_err(Au, ref_Au) < TOL_MAX
+    assert rel_err(Ary, ref_Ary) < TOL_L2 and max_err(Ary, ref_Ary) < TOL_MAX
+    assert rel_err(r, gi - ref_Au) < TOL_L2
+
+
 def test_affine_image_is_blurred_exactly(mlba):
     """An affine image under a normalised symmetric PSF is left unchanged by
     the antireflective blur, borders included (the pad continues it)."""
@@ -200,6 +228,27 @@ def test_mlba_antireflective_against_oracle(mlba, n, p, pc, sym, L, alpha, iters
 
 
 @pytest.mark.parametrize("implicit", [False, True])
+@pytest.mark.parametrize("pc", [opc.AR, opc.BCCB])
+def test_mlba_antireflective_fft_blur(mlba, pc, implicit):
+    """Whole runs with A and A' on the FFT grid (no fused row passes for this
+    model) against the oracle."""
+    n, p, L, iters = (97, 31, 2, 30) if pc == opc.AR else (96, 25, 2, 30)
+    alpha = 0.02 if pc == opc.AR else 0.37
+    announce(f"MLBA antireflective FFT blur n={n} p={p} pc={pc} implicit={implicit}")
+    g, H = _problem(n, p, pc == opc.AR, 90 + n)
+    delta = omlba.delta_auto(omlba.opnorm(H, n, AR_BC, pc, alpha, tol=1e-6))
+    ref = omlba.mlba(g, H, AR_BC, pc, L, np.full(iters, alpha), np.full(iters + 1, delta), 1e-3, iters)
+    with mlba.Plan(n, p, mlba.ANTIREFLECT, pc, L, cuda(H)) as plan:
+        plan.set_blur(mlba.BLUR_FFT)
+        f, info = plan.restore(cuda(g), alpha=alpha, mu=1e-3, delta=delta, iters=iters, implicit=implicit)
+        f = host(f)
+    e = rel_err(f, ref["f"])
+    print(f"  image {e:.2e} rnorm {rel_err(info.rnorm, ref['rnorm']):.2e}", flush=True)
+    assert e < 1e-4
+    assert rel_err(info.rnorm, ref["rnorm"]) < 1e-4
+
+
+@pytest.mark.parametrize("implicit", [False, True])
 @pytest.mark.parametrize("n,p,pc,sym", [(97, 9, opc.AR, True), (96, 9, opc.DCT, True)])
 def test_alg4_antireflective_against_oracle(mlba, n, p, pc, sym, implicit):
     """Alg-BC4 of Example 4 (Gaussian PSF), with the antireflective transform
@@ -250,8 +299,10 @@ def test_full_size_antireflective(mlba):
     ref = omlba.mlba(g, w.psf, AR_BC, opc.AR, w.levels, np.full(iters, w.alpha0), np.full(iters + 1, d), w.mu,
                      iters)
     with mlba.Plan(w.n, w.p, mlba.ANTIREFLECT, mlba.AR, w.levels, cuda(w.psf)) as plan:
+        choice = plan.autotune(reps=3)["blur"]  # the blur the timed section runs
         f, info = plan.restore(cuda(g), alpha=w.alpha0, mu=w.mu, delta=d, iters=iters, implicit=True)
         f = host(f)
+    print(f"  blur {choice}", flush=True)
     e = rel_err(f, ref["f"])
     print(f"  delta {d:.6f} image {e:.2e} rnorm {rel_err(info.rnorm, ref['rnorm']):.2e}", flush=True)
     assert e < 1e-4
