@@ -379,13 +379,17 @@ def alg2_section(w, g, delta, steps: int = 10):
 
 
 def antireflective_section(steps: int = 30, warmup: int = 3):
-    """Alg-BC3 of Example 4 at n = 1025: antireflective pad in the direct blur,
-    the reblur A' in place of A^T, the antireflective-transform preconditioner
-    (three passes of complex FFTs of length 2(n - 1) = 2048), 31 x 31
-    Gaussian, 3 levels, implicit state, automatic step; `steps` timed
+    """Alg-BC3 of Example 4 at n = 1025: the antireflective model (its pad in
+    A, the reblur A' in place of A^T; the autotuner picks the direct taps or
+    the FFT grid, m = 1055 on a 1152 grid), the antireflective-transform
+    preconditioner (three passes of complex FFTs of length 2(n - 1) = 2048),
+    31 x 31 Gaussian, 3 levels, implicit state, automatic step; `steps` timed
     iterations with the per-kernel profile.  Algorithmic bytes of the
     transform passes: rows T^-1 read n^2 and write n^2 floats, columns read
-    n^2 and the n^2 filter and write n^2, rows T read n^2 and write n^2."""
+    n^2 and the n^2 filter and write n^2, rows T read n^2 and write n^2; of the
+    grid passes (two launches each, A and A'): rows read n^2 and write the
+    (M/2+1) x m half spectrum, columns read it and the PSF spectrum and write
+    the (M/2+1) x n rows kept, inverse rows read those and read + write n^2."""
     import torch
 
     import synth
@@ -401,6 +405,7 @@ def antireflective_section(steps: int = 30, warmup: int = 3):
     names = {"fft_rows_fwd": "ar_rows_fwd", "fft_cols": "ar_cols_filter", "fft_rows_inv": "ar_rows_inv"}
     with mlba.Plan(n, p, w.bc, w.precond, w.levels, psf) as plan:
         N = plan.N
+        tune = plan.autotune(reps=5)
         delta = 0.9 / max(plan.opnorm(w.alpha0, 50), 0.9)
         f = torch.empty((N, N), dtype=torch.float32, device="cuda")
         om = torch.zeros((N, N), dtype=torch.float32, device="cuda")
@@ -416,8 +421,18 @@ def antireflective_section(steps: int = 30, warmup: int = 3):
         _, rec = plan.profile_end()
         kernels = plan.profile_kernels()
     rec = max(rec, 1)
+    fft_blur = tune["blur"] == "fft"
     model = kernel_model(n, p, N, w.levels, True, False)
     nn = 4.0 * n * n
+    if fft_blur:
+        m_ = n + p - 1
+        M = fft_grid(m_)
+        hm = M // 2 + 1
+        for k in ("conv_blur", "conv_blur_t"):
+            model.pop(k)
+        model["fc_rows_fwd"] = {"bytes": 2 * (nn + 8.0 * hm * m_), "flops": 0.0, "launches": 2, "bound": "hbm"}
+        model["fc_cols"] = {"bytes": 2 * 8.0 * hm * (m_ + M + n), "flops": 0.0, "launches": 2, "bound": "hbm"}
+        model["fc_rows_inv"] = {"bytes": 2 * (8.0 * hm * n + 2 * nn), "flops": 0.0, "launches": 2, "bound": "hbm"}
     model["fft_rows_fwd"] = {"bytes": 2 * nn, "flops": 0.0, "launches": 1, "bound": "hbm"}
     model["fft_cols"] = {"bytes": 3 * nn, "flops": 0.0, "launches": 1, "bound": "hbm"}
     model["fft_rows_inv"] = {"bytes": 2 * nn, "flops": 0.0, "launches": 1, "bound": "hbm"}
@@ -435,6 +450,8 @@ def antireflective_section(steps: int = 30, warmup: int = 3):
     return {"workload": w.name, "n": n, "p": p, "levels": w.levels, "boundary": "antireflective (A' = reblur)",
             "precond": "antireflective transform (FFT length 2048)", "alpha": w.alpha0, "mu": w.mu,
             "delta": round(delta, 6), "state": "implicit omega", "steps": steps,
+            "blur": f"fft grid {fft_grid(n + p - 1)}" if fft_blur else "direct taps",
+            "blur_autotune": tune,
             "ms_per_step": round(el * 1e3 / steps, 5), "Mpx_it_s": round(n * n * steps / el / 1e6, 2),
             "kernels": kern}
 
@@ -451,6 +468,8 @@ def main() -> int:
     ap.add_argument("--no-unrolled", action="store_true", help="skip the unrolled forward/backward section")
     ap.add_argument("--no-alg4", action="store_true", help="skip the Algorithm 4 / 4-NS and Algorithm 2 sections")
     ap.add_argument("--no-ar", action="store_true", help="skip the antireflective (Alg-BC3) section")
+    ap.add_argument("--only-ar", action="store_true",
+                    help="run only the antireflective section and print its JSON (for profiling it alone)")
     ap.add_argument("--state", choices=("implicit", "explicit"), default="implicit",
                     help="iteration state: omega (z = W omega recomputed) or the frame coefficients z")
     ap.add_argument("--compare-steps", type=int, default=20,
@@ -478,6 +497,9 @@ def main() -> int:
         print("bench.py needs a HIP device", file=sys.stderr)
         return 1
     torch.cuda.set_device(0)
+    if args.only_ar:
+        print(json.dumps({"antireflective": antireflective_section()}), flush=True)
+        return 0
     w = synth.make_workload(args.workload)
     n, p = w.n, w.p
 
