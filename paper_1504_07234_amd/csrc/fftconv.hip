@@ -26,15 +26,18 @@ constexpr int FC_MAX = FC_EPT * kBlock;
 
 int fftconv_max_size() { return FC_MAX; }
 
+// Sequences per workgroup: more than one only while the grid still gives at
+// least 512 workgroups (two per CU), so that small grids hide the latency of
+// their LDS phases with several resident workgroups.
 static int fc_pairs_per_block(int M) {
     int G = 1;
-    while ((G * 2) * M <= FC_MAX && ((M / 2) % (G * 2)) == 0 && G * 2 <= 4) G *= 2;
+    while ((G * 2) * M <= FC_MAX && ((M / 2) % (G * 2)) == 0 && G * 2 <= 4 && M / 2 / (G * 2) >= 512) G *= 2;
     return G;
 }
 
 static int fc_cols_per_block(int M) {
     int cc = 1;
-    while ((cc * 2) * M <= FC_MAX) cc *= 2;
+    while ((cc * 2) * M <= FC_MAX && (M / 2 + 1) / (cc * 2) >= 512) cc *= 2;
     return cc;
 }
 
