@@ -47,12 +47,12 @@ PROFILE_EVERY = 4              # kernel events on every 4th timed iteration (the
 TRAFFIC = {
     # 2078^2, 3 levels: the three shrink-synthesis launches of one iteration (d = 4, 2, 1)
     ("shrink_synthesis", "fft-implicit"): {
-        "fetch_kib": 43467.875, "write_kib": 50610.46875, "fetch_scale": 2.0, "write_scale": 1.0, "launches": 3,
-        "sources_sha256": "8c65fed666594571d421301171dc91078bc98ff1bda518df2ed031f5377ae64a"},
+        "fetch_kib": 43467.9, "write_kib": 50610.6, "fetch_scale": 2.0, "write_scale": 1.0, "launches": 3,
+        "sources_sha256": "a237d0c15e056285c0bea0d625d66945f49d3e87471762849549583f839860e1"},
     # the direct A^T accumulating into omega (p = 31), one launch per iteration
     ("conv_blur_t", "direct-implicit"): {
-        "fetch_kib": 17582.0625, "write_kib": 16878.03125, "fetch_scale": 2.0, "write_scale": 1.0, "launches": 1,
-        "sources_sha256": "a645147298484ea7ed30d08d5d29b45515bd7037267cb7a977b7c5b52b4b25f2"},
+        "fetch_kib": 17582.1, "write_kib": 16878.0, "fetch_scale": 2.0, "write_scale": 1.0, "launches": 1,
+        "sources_sha256": "bdad7678dbdfaf64904f9ecef39c9604460abeb36135a8882153cfba1096e33b"},
 }
 # the sources that define each kernel's device code
 TRAFFIC_SOURCES = {
