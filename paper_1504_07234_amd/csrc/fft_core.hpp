@@ -17,6 +17,7 @@ constexpr int FFT_EPT = 8;  // complex values per thread per stage (max)
 // observation (the smallest admissible grid for PSFs of 17..227 taps).
 constexpr int kFixedN = 2048;
 constexpr int kFixedM = 2304;
+constexpr int kFixedM2 = 1152;  // the FFT-blur grid of ~1K images (unknowns of 1025..1152)
 constexpr int FFT_MAX_ELEMS = FFT_EPT * kBlock;  // complex values per workgroup (16 KB of LDS)
 
 // LDS slot of element i: one padding slot after every 8 elements, so that the

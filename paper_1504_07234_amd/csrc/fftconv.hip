@@ -353,6 +353,9 @@ hipError_t launch_fc_rows_fwd(const FftConv& c, const float* src, int S, int off
     if (c.M == kFixedM && G == 1)
         hipLaunchKernelGGL(fc_rows_fwd_kernel<kFixedM>, dim3(blocks), dim3(kBlock), lds_bytes(c.M, c.M), s, src, S,
                            off, c.M, c.T, c.ts, c.fd, c.tw, 1, fc_seq_shift(1), p0, p1, ar);
+    else if (c.M == kFixedM2 && G == 1)
+        hipLaunchKernelGGL(fc_rows_fwd_kernel<kFixedM2>, dim3(blocks), dim3(kBlock), lds_bytes(c.M, c.M), s, src, S,
+                           off, c.M, c.T, c.ts, c.fd, c.tw, 1, fc_seq_shift(1), p0, p1, ar);
     else
         hipLaunchKernelGGL(fc_rows_fwd_kernel<0>, dim3(blocks), dim3(kBlock), lds_bytes(G * c.M, c.M), s, src, S, off,
                            c.M, c.T, c.ts, c.fd, c.tw, G, fc_seq_shift(G), p0, p1, ar);
@@ -366,6 +369,10 @@ hipError_t launch_fc_cols(const FftConv& c, int conj_h, int y_lo, int y_hi, int 
     const float inv = (float)(1.0 / ((double)c.M * (double)c.M));
     if (c.M == kFixedM && CC == 1)
         hipLaunchKernelGGL(fc_cols_kernel<kFixedM>, dim3(half), dim3(kBlock), lds_bytes(c.M, c.M), s, c.T, c.M, c.ts,
+                           (const float2*)c.H, conj_h, inv, y_lo, y_hi, mode, cspec, c.fd, c.tw, 1, fc_seq_shift(1), o_lo,
+                           o_hi);
+    else if (c.M == kFixedM2 && CC == 1)
+        hipLaunchKernelGGL(fc_cols_kernel<kFixedM2>, dim3(half), dim3(kBlock), lds_bytes(c.M, c.M), s, c.T, c.M, c.ts,
                            (const float2*)c.H, conj_h, inv, y_lo, y_hi, mode, cspec, c.fd, c.tw, 1, fc_seq_shift(1), o_lo,
                            o_hi);
     else
@@ -383,6 +390,10 @@ hipError_t launch_fc_rows_inv(const FftConv& c, int oy, int ox, int D, float* ds
     if (n_partials) *n_partials = blocks;
     if (c.M == kFixedM && G == 1)
         hipLaunchKernelGGL(fc_rows_inv_kernel<kFixedM>, dim3(blocks), dim3(kBlock), lds_bytes(c.M, c.M), s,
+                           (const float2*)c.T, c.M, c.ts, c.fd, c.tw, 1, fc_seq_shift(1), p0, p1, oy, ox, D, dst, g,
+                           accum, partials);
+    else if (c.M == kFixedM2 && G == 1)
+        hipLaunchKernelGGL(fc_rows_inv_kernel<kFixedM2>, dim3(blocks), dim3(kBlock), lds_bytes(c.M, c.M), s,
                            (const float2*)c.T, c.M, c.ts, c.fd, c.tw, 1, fc_seq_shift(1), p0, p1, oy, ox, D, dst, g,
                            accum, partials);
     else

@@ -20,8 +20,9 @@ def mlba():
     return m
 
 
-# (n, p): ragged grids, odd N, the largest PSF, the 3072-point limit, the bench shape
-CASES = [(8, 1), (64, 9), (100, 17), (97, 5), (256, 49), (2048, 31), (3000, 49)]
+# (n, p): ragged grids, odd N, the largest PSF, the compiled 1152 grid, the
+# 3072-point limit, the bench shape (the compiled 2304 grid)
+CASES = [(8, 1), (64, 9), (100, 17), (97, 5), (256, 49), (1000, 49), (2048, 31), (3000, 49)]
 
 
 @pytest.mark.parametrize("n,p", CASES)
