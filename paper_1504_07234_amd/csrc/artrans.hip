@@ -251,35 +251,6 @@ __global__ __launch_bounds__(kBlock) void ar_rows_inv_kernel(const float* __rest
     ar_rows_inv_body<NT>(Tr, n, ts, dst, fd, tw, G, seq_shift, xcd_block(blockIdx.x, gridDim.x), buf, accum);
 }
 
-// lambda of the antireflective blur of the symmetrised PSF (closed form
-// above), written squared into spec[kx][ky] and, optionally, as is into lam;
-// costab[q] = cos(pi q / N), q < 2N.
-__global__ __launch_bounds__(kBlock) void ar_spectrum_kernel(const float* __restrict__ psf, int p, int n,
-                                                             float* __restrict__ spec,
-                                                             const float* __restrict__ costab,
-                                                             float* __restrict__ lam) {
-    const int ky = blockIdx.x * kBlock + threadIdx.x;
-    const int kx = blockIdx.y;
-    if (ky >= n) return;
-    const int N = n - 1;
-    const int c = (p - 1) / 2;
-    const int fy = ky == N ? 0 : ky;  // the linear functions take frequency 0
-    const int fx = kx == N ? 0 : kx;
-    float acc = 0.0f;
-    for (int a = 0; a < p; ++a) {
-        const float cy = costab[mod_pos(fy * (a - c), 2 * N)];
-        float row = 0.0f;
-        for (int b = 0; b < p; ++b) {
-            const float hs = 0.25f * (psf[a * p + b] + psf[(p - 1 - a) * p + b] + psf[a * p + (p - 1 - b)] +
-                                      psf[(p - 1 - a) * p + (p - 1 - b)]);
-            row += hs * costab[mod_pos(fx * (b - c), 2 * N)];
-        }
-        acc += cy * row;
-    }
-    spec[(size_t)kx * n + ky] = acc * acc;
-    if (lam) lam[(size_t)kx * n + ky] = acc;
-}
-
 // ---- launch helpers --------------------------------------------------------
 
 static int ar_shift_for(int batch) {
@@ -352,13 +323,6 @@ hipError_t launch_ar_rows_inv(const float* Tr, int n, int ts, float* dst, const 
     else
         hipLaunchKernelGGL(ar_rows_inv_kernel<0>, grid, dim3(kBlock), lds, s, Tr, n, ts, dst, fd, tw, G,
                            ar_shift_for(G), accum);
-    return hipGetLastError();
-}
-
-hipError_t launch_ar_spectrum(const float* psf, int p, int n, float* spec, const float* costab, hipStream_t s,
-                              float* lam) {
-    dim3 grid((n + kBlock - 1) / kBlock, n);
-    hipLaunchKernelGGL(ar_spectrum_kernel, grid, dim3(kBlock), 0, s, psf, p, n, spec, costab, lam);
     return hipGetLastError();
 }
 

@@ -432,31 +432,56 @@ __global__ __launch_bounds__(kBlock) void dct_rows_inv_kernel(const float* __res
     dct_rows_inv_body(Tr, n, ts, dst, fd, tw, dtw, G, seq_shift, xcd_block(blockIdx.x, gridDim.x), buf, accum);
 }
 
-// lambda of the reflective blur of the symmetrised PSF:
-//   lambda[ky][kx] = sum_{a,b} H~[a][b] cos(pi ky (a-c)/n) cos(pi kx (b-c)/n)
-// written squared into spec[kx][ky]; costab[q] = cos(pi q / n), q < 2n.
-__global__ __launch_bounds__(kBlock) void dct_spectrum_kernel(const float* __restrict__ psf, int p, int n,
-                                                              float* __restrict__ spec,
-                                                              const float* __restrict__ costab,
-                                                              float* __restrict__ lam) {
+// Cosine spectra of the symmetrised PSF H~ (reflective blur, Algorithm 3;
+// antireflective blur, with the two linear functions at frequency zero):
+//   lambda[ky][kx] = sum_a cos(w_ky (a-c)) rows[a][kx],
+//   rows[a][kx]    = sum_b H~[a][b] cos(w_kx (b-c)),
+// w_k = pi k / K (costab[q] = cos(pi q / K), q < 2K); with lin_last the last
+// frequency index K takes w = 0.  Two passes, O(n^2 p) instead of O(n^2 p^2).
+__device__ __forceinline__ int cos_freq(int k, int K, int lin_last) { return (lin_last && k == K) ? 0 : k; }
+
+__global__ __launch_bounds__(kBlock) void cos_spectrum_rows_kernel(const float* __restrict__ psf, int p, int n,
+                                                                   int K, int lin_last,
+                                                                   const float* __restrict__ costab,
+                                                                   float* __restrict__ rows) {
+    const int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= p * n) return;
+    const int a = idx / n;
+    const int fx = cos_freq(idx - a * n, K, lin_last);
+    const int c = (p - 1) / 2;
+    float row = 0.0f;
+    for (int b = 0; b < p; ++b) {
+        const float hs = 0.25f * (psf[a * p + b] + psf[(p - 1 - a) * p + b] + psf[a * p + (p - 1 - b)] +
+                                  psf[(p - 1 - a) * p + (p - 1 - b)]);
+        row += hs * costab[mod_pos(fx * (b - c), 2 * K)];
+    }
+    rows[idx] = row;
+}
+
+// written squared into spec[kx][ky] and, when given, as is into lam
+__global__ __launch_bounds__(kBlock) void cos_spectrum_cols_kernel(const float* __restrict__ rows, int p, int n,
+                                                                   int K, int lin_last,
+                                                                   const float* __restrict__ costab,
+                                                                   float* __restrict__ spec,
+                                                                   float* __restrict__ lam) {
     const int ky = blockIdx.x * kBlock + threadIdx.x;
     const int kx = blockIdx.y;
     if (ky >= n) return;
+    const int fy = cos_freq(ky, K, lin_last);
     const int c = (p - 1) / 2;
-    const int n2 = 2 * n;
     float acc = 0.0f;
-    for (int a = 0; a < p; ++a) {
-        const float cy = costab[mod_pos(ky * (a - c), n2)];
-        float row = 0.0f;
-        for (int b = 0; b < p; ++b) {
-            const float hs = 0.25f * (psf[a * p + b] + psf[(p - 1 - a) * p + b] + psf[a * p + (p - 1 - b)] +
-                                      psf[(p - 1 - a) * p + (p - 1 - b)]);
-            row += hs * costab[mod_pos(kx * (b - c), n2)];
-        }
-        acc += cy * row;
-    }
+    for (int a = 0; a < p; ++a) acc += costab[mod_pos(fy * (a - c), 2 * K)] * rows[a * n + kx];
     spec[(size_t)kx * n + ky] = acc * acc;
     if (lam) lam[(size_t)kx * n + ky] = acc;
+}
+
+hipError_t launch_cos_spectrum(const float* psf, int p, int n, int K, int lin_last, const float* costab, float* tmp,
+                               float* spec, float* lam, hipStream_t s) {
+    hipLaunchKernelGGL(cos_spectrum_rows_kernel, dim3((p * n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, psf, p, n,
+                       K, lin_last, costab, tmp);
+    hipLaunchKernelGGL(cos_spectrum_cols_kernel, dim3((n + kBlock - 1) / kBlock, n), dim3(kBlock), 0, s, tmp, p, n, K,
+                       lin_last, costab, spec, lam);
+    return hipGetLastError();
 }
 
 // the PSF centred at the origin of a zeroed n x n image: H[a][b] at
@@ -820,13 +845,6 @@ hipError_t launch_dct_rows_inv(const float* Tr, int n, int ts, float* dst, const
     const size_t lds = lds_bytes(G * n, n);
     hipLaunchKernelGGL(dct_rows_inv_kernel, dim3(n / (2 * G)), dim3(kBlock), lds, s, Tr, n, ts, dst, fd, tw, dtw, G,
                        seq_shift_for(G), accum);
-    return hipGetLastError();
-}
-
-hipError_t launch_dct_spectrum(const float* psf, int p, int n, float* spec, const float* costab, hipStream_t s,
-                               float* lam) {
-    dim3 grid((n + kBlock - 1) / kBlock, n);
-    hipLaunchKernelGGL(dct_spectrum_kernel, grid, dim3(kBlock), 0, s, psf, p, n, spec, costab, lam);
     return hipGetLastError();
 }
 

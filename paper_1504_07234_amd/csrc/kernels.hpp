@@ -278,10 +278,12 @@ hipError_t launch_dct_cols_filter(float* Tr, int n, int ts, const float* spec, f
                                   hipStream_t s, const float* lamr = nullptr);  // lamr: times lambda (Alg. 4)
 hipError_t launch_dct_rows_inv(const float* Tr, int n, int ts, float* dst, const FftDesc& fd,
                                const float2* tw, const float2* dtw, hipStream_t s, int accum = 0);
-// spec[kx][ky] = lambda[ky][kx]^2 for the symmetrised PSF (Algorithm 3), and
-// lambda itself into lam when given
-hipError_t launch_dct_spectrum(const float* psf, int p, int n, float* spec, const float* costab,
-                               hipStream_t s, float* lam = nullptr);
+// spec[kx][ky] = lambda[ky][kx]^2 of the symmetrised PSF's cosine spectrum,
+// lambda itself into lam when given: K = n with costab[q] = cos(pi q / n)
+// for the reflective blur (Algorithm 3); K = n - 1, costab[q] = cos(pi q /
+// (n-1)) and lin_last = 1 for the antireflective blur.  tmp: p x n floats.
+hipError_t launch_cos_spectrum(const float* psf, int p, int n, int K, int lin_last, const float* costab, float* tmp,
+                               float* spec, float* lam, hipStream_t s);
 // Antireflective transform (Algorithm 3 with antireflective boundaries): rows
 // T^-1 -> Tr (transposed, real, row stride ts = ar_workspace_stride(n), n
 // rows); columns T^-1, filter 1/(spec + alpha) (times lamr), T; rows T -> dst.
@@ -294,10 +296,6 @@ hipError_t launch_ar_cols_filter(float* Tr, int n, int ts, const float* spec, fl
                                  const FftDesc& fd, const float2* tw, hipStream_t s);
 hipError_t launch_ar_rows_inv(const float* Tr, int n, int ts, float* dst, const FftDesc& fd, const float2* tw,
                               hipStream_t s, int accum = 0);
-// spec[kx][ky] = lambda[ky][kx]^2 of the antireflective blur of the
-// symmetrised PSF, lambda into lam when given; costab[q] = cos(pi q / (n-1))
-hipError_t launch_ar_spectrum(const float* psf, int p, int n, float* spec, const float* costab, hipStream_t s,
-                              float* lam = nullptr);
 // place the PSF in the top-left corner of a zeroed n x n image
 hipError_t launch_pad_psf(const float* psf, int p, float* dst, int n, hipStream_t s);
 // the PSF centred at the origin (kernel of the periodic-boundary blur)

@@ -262,9 +262,9 @@ int compute_spectrum(mlba_plan_s* P, hipStream_t s) {
             HIPCHK(launch_fft_cols_complex((const float2*)P->swork, n, P->ts, P->lamc, P->fd, P->tw, s));
         }
     } else if (P->precond == MLBA_PRECOND_DCT) {
-        HIPCHK(launch_dct_spectrum(P->psf, P->p, n, P->spec, P->costab, s, P->lamr));
+        HIPCHK(launch_cos_spectrum(P->psf, P->p, n, n, 0, P->costab, P->r, P->spec, P->lamr, s));
     } else if (P->precond == MLBA_PRECOND_AR) {
-        HIPCHK(launch_ar_spectrum(P->psf, P->p, n, P->spec, P->costab, s, P->lamr));
+        HIPCHK(launch_cos_spectrum(P->psf, P->p, n, n - 1, 1, P->costab, P->r, P->spec, P->lamr, s));
     }
     return MLBA_OK;
 }
