@@ -37,6 +37,23 @@ bool factor_23(int n, int* a, int* b) {
     return n == 1;
 }
 
+// Run-time plan of a length-n transform (n = 2^a 3^b): radix 8 stages, one
+// radix 4 or 2 stage, then the radix 3 stages.  (Radix 16 and 9 stages, as in
+// the compiled plans, measured 3-6 % slower here: with several short
+// sequences per workgroup half the threads idle in them and the larger
+// butterflies cost occupancy.)
+FftDesc fft_desc(int n) {
+    FftDesc d{};
+    d.n = n;
+    int a = 0, b = 0;
+    factor_23(n, &a, &b);
+    for (; a >= 3; a -= 3) d.radix[d.nst++] = 8;
+    if (a == 2) d.radix[d.nst++] = 4;
+    if (a == 1) d.radix[d.nst++] = 2;
+    for (int i = 0; i < b; ++i) d.radix[d.nst++] = 3;
+    return d;
+}
+
 }  // namespace
 
 namespace {
@@ -545,7 +562,6 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
     int a2 = 0, b3 = 0;
     if (precond == MLBA_PRECOND_AR) {  // complex FFTs of length 2(n - 1)
         if (!ar_transform_supported(n)) return MLBA_EUNSUPPORTED;
-        factor_23(2 * (n - 1), &a2, &b3);
     } else if (precond != MLBA_PRECOND_NONE) {
         if (!factor_23(n, &a2, &b3) || a2 < 1 || n < 8 || n > 2048) return MLBA_EUNSUPPORTED;
     }
@@ -599,17 +615,7 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
 
     if (precond != MLBA_PRECOND_NONE) {
         const int L = precond == MLBA_PRECOND_AR ? 2 * (n - 1) : n;  // transform length
-        FftDesc& fd = P->fd;
-        fd.n = L;
-        fd.nst = 0;
-        int a = a2;
-        while (a >= 3) {
-            fd.radix[fd.nst++] = 8;
-            a -= 3;
-        }
-        if (a == 2) fd.radix[fd.nst++] = 4;
-        if (a == 1) fd.radix[fd.nst++] = 2;
-        for (int i = 0; i < b3; ++i) fd.radix[fd.nst++] = 3;
+        P->fd = fft_desc(L);
 
         // the cosine table serves the eigenvalues: angles pi q / n (DCT) or
         // pi q / (n - 1) (antireflective transform); BCCB does not read it
@@ -704,18 +710,7 @@ int ensure_fftconv(mlba_plan_s* P, hipStream_t s) {
     FftConv c{};
     c.M = M;
     c.ts = M + 16;
-    int a2 = 0, b3 = 0;
-    factor_23(M, &a2, &b3);
-    c.fd.n = M;
-    c.fd.nst = 0;
-    int a = a2;
-    while (a >= 3) {
-        c.fd.radix[c.fd.nst++] = 8;
-        a -= 3;
-    }
-    if (a == 2) c.fd.radix[c.fd.nst++] = 4;
-    if (a == 1) c.fd.radix[c.fd.nst++] = 2;
-    for (int i = 0; i < b3; ++i) c.fd.radix[c.fd.nst++] = 3;
+    c.fd = fft_desc(M);
     std::vector<float2> tw(M);
     const double pi = 3.14159265358979323846;
     for (int q = 0; q < M; ++q) {
