@@ -52,7 +52,7 @@ TRAFFIC = {
     # the direct A^T accumulating into omega (p = 31), one launch per iteration
     ("conv_blur_t", "direct-implicit"): {
         "fetch_kib": 17582.1, "write_kib": 16878.0, "fetch_scale": 2.0, "write_scale": 1.0, "launches": 1,
-        "sources_sha256": "bdad7678dbdfaf64904f9ecef39c9604460abeb36135a8882153cfba1096e33b"},
+        "sources_sha256": "0c603ebd312cd6d0532e262cfb295ffe4cb6eed830b37d6d8176d048ea45dfcd"},
 }
 # the sources that define each kernel's device code
 TRAFFIC_SOURCES = {
