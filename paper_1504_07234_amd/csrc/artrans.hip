@@ -23,7 +23,7 @@
 //   2. columns (rows of Tr): T^-1 along y, multiply by 1/(lambda^2 + alpha)
 //      (times lambda for Algorithm 4), T along y, all in LDS;
 //   3. rows: gather transposed, T along x, write the image rows.
-// The transform length 2N must be 2^a 3^b and at most FFT_MAX_ELEMS.
+// The transform length 2N must be 2^a 3^b 5^c and at most FFT_MAX_ELEMS.
 #include "common.hpp"
 #include "fft_core.hpp"
 #include "kernels.hpp"
@@ -277,6 +277,7 @@ bool ar_transform_supported(int n) {
     if (m > FFT_MAX_ELEMS) return false;
     while (m % 2 == 0) m /= 2;
     while (m % 3 == 0) m /= 3;
+    while (m % 5 == 0) m /= 5;
     return m == 1;
 }
 

@@ -10,7 +10,7 @@
 //      spectral filter, inverse transform, all in LDS in one kernel;
 //   3. rows: gather transposed, inverse transform, write rows.
 //
-// The complex FFT is a mixed-radix (8, 4, 2, 3) Stockham autosort transform
+// The complex FFT is a mixed-radix (8, 4, 2, 3, 5) Stockham autosort transform
 // held in LDS; every thread carries up to 8 complex values per stage in
 // registers between the read and the write barrier.  Twiddles come from a
 // table of exp(-2 pi i q / n) computed in double precision on the host.

@@ -1,4 +1,4 @@
-// In-LDS mixed-radix (8, 4, 2, 3) Stockham autosort FFT shared by the
+// In-LDS mixed-radix (8, 4, 2, 3, 5) Stockham autosort FFT shared by the
 // spectral preconditioners and the FFT blur.  Every thread carries up to EPT
 // complex values per stage in registers between the read and the write
 // barrier; twiddles come from a table of exp(-2 pi i q / n) computed in
@@ -39,6 +39,7 @@ __device__ __forceinline__ void twiddle_powers(const float2* __restrict__ tw, in
     w[1] = twiddle<DIR>(tw, e);
     if constexpr (R >= 3) w[2] = twiddle<DIR>(tw, 2 * e);
     if constexpr (R >= 4) w[3] = cmul(w[1], w[2]);
+    if constexpr (R == 5) w[4] = twiddle<DIR>(tw, 4 * e);
     if constexpr (R >= 8) {
         w[4] = twiddle<DIR>(tw, 4 * e);
         w[5] = cmul(w[1], w[4]);
@@ -157,6 +158,22 @@ __device__ __forceinline__ void dft(float2* v) {
         v[2] = csub(m, d);
     } else if constexpr (R == 4) {
         dft4<DIR>(v);
+    } else if constexpr (R == 5) {
+        // X_k = sum_j x_j W^{jk}, W = exp(DIR 2 pi i / 5): pair the inputs j and
+        // 5 - j (cosines on their sums, sines on their differences)
+        const float c1 = 0.30901699437494742f, s1 = 0.95105651629515357f;   // cos, sin(2 pi / 5)
+        const float c2 = -0.80901699437494742f, s2 = 0.58778525229247313f;  // cos, sin(4 pi / 5)
+        const float2 t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+        const float2 t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+        const float2 a1 = make_float2(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
+        const float2 a2 = make_float2(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
+        const float2 b1 = mul_i<DIR>(make_float2(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y));
+        const float2 b2 = mul_i<DIR>(make_float2(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y));
+        v[0] = cadd(v[0], cadd(t1, t2));
+        v[1] = cadd(a1, b1);
+        v[4] = csub(a1, b1);
+        v[2] = cadd(a2, b2);
+        v[3] = csub(a2, b2);
     } else {  // R == 8: two length-4 transforms and the eighth-root twiddles
         float2 e[4] = {v[0], v[2], v[4], v[6]};
         float2 o[4] = {v[1], v[3], v[5], v[7]};
@@ -183,7 +200,7 @@ __device__ __forceinline__ void dft(float2* v) {
 // 2^seq_shift threads with threadIdx.x >> seq_shift == b (only the first nseq
 // sequences are live).  Ns is the product of the radices already applied;
 // ns_shift = log2(Ns) when Ns is a power of two (every radix-2/4/8 stage,
-// since radix-3 stages run last), -1 otherwise.
+// since radix-3 and radix-5 stages run last), -1 otherwise.
 template <int R, int DIR, int EPT = FFT_EPT>
 __device__ __forceinline__ void stockham_stage(float2* buf, int n, int nseq, int seq_shift, int Ns,
                                                int ns_shift, const float2* __restrict__ tw) {
@@ -238,9 +255,10 @@ __device__ void lds_fft(float2* buf, const FftDesc& fd, int nseq, int seq_shift,
         if (R == 8) stockham_stage<8, DIR, EPT>(buf, fd.n, nseq, seq_shift, Ns, ns_shift, tw);
         else if (R == 4) stockham_stage<4, DIR, EPT>(buf, fd.n, nseq, seq_shift, Ns, ns_shift, tw);
         else if (R == 2) stockham_stage<2, DIR, EPT>(buf, fd.n, nseq, seq_shift, Ns, ns_shift, tw);
-        else stockham_stage<3, DIR, EPT>(buf, fd.n, nseq, seq_shift, Ns, ns_shift, tw);
+        else if (R == 3) stockham_stage<3, DIR, EPT>(buf, fd.n, nseq, seq_shift, Ns, ns_shift, tw);
+        else stockham_stage<5, DIR, EPT>(buf, fd.n, nseq, seq_shift, Ns, ns_shift, tw);
         Ns *= R;
-        ns_shift = (R == 3 || ns_shift < 0) ? -1 : ns_shift + (R == 8 ? 3 : (R == 4 ? 2 : 1));
+        ns_shift = (R == 3 || R == 5 || ns_shift < 0) ? -1 : ns_shift + (R == 8 ? 3 : (R == 4 ? 2 : 1));
     }
 }
 
@@ -248,7 +266,7 @@ __device__ void lds_fft(float2* buf, const FftDesc& fd, int nseq, int seq_shift,
 // The same Stockham stages with the length known at compile time and one
 // sequence per workgroup (kBlock threads): every index, stride and loop bound
 // folds to a constant, and the plan may use radix-16 and radix-9 butterflies
-// (fewer passes through LDS than the run-time plan's 8/4/2/3).
+// (fewer passes through LDS than the run-time plan's 8/4/2/3/5).
 struct FixedPlan {
     int nst;
     int radix[24];

@@ -10,7 +10,7 @@
 
 namespace mlba {
 
-// Mixed-radix plan of a length-n complex FFT (n = 2^a 3^b).
+// Mixed-radix plan of a length-n complex FFT (n = 2^a 3^b 5^c).
 struct FftDesc {
     int n;
     int nst;

@@ -23,34 +23,31 @@ void mlba_internal_set_hip(hipError_t e) { g_last_hip = (int)e; }
 
 namespace {
 
-bool factor_23(int n, int* a, int* b) {
-    *a = 0;
-    *b = 0;
-    while (n % 2 == 0) {
-        n /= 2;
-        ++*a;
-    }
-    while (n % 3 == 0) {
-        n /= 3;
-        ++*b;
-    }
+// n = 2^a 3^b 5^c?
+bool factor_235(int n, int* a, int* b, int* c) {
+    *a = *b = *c = 0;
+    if (n < 1) return false;
+    for (; n % 2 == 0; n /= 2) ++*a;
+    for (; n % 3 == 0; n /= 3) ++*b;
+    for (; n % 5 == 0; n /= 5) ++*c;
     return n == 1;
 }
 
-// Run-time plan of a length-n transform (n = 2^a 3^b): radix 8 stages, one
-// radix 4 or 2 stage, then the radix 3 stages.  (Radix 16 and 9 stages, as in
-// the compiled plans, measured 3-6 % slower here: with several short
-// sequences per workgroup half the threads idle in them and the larger
-// butterflies cost occupancy.)
+// Run-time plan of a length-n transform (n = 2^a 3^b 5^c): radix 8 stages,
+// one radix 4 or 2 stage, then the radix 3 and radix 5 stages.  (Radix 16 and
+// 9 stages, as in the compiled plans, measured 3-6 % slower here: with
+// several short sequences per workgroup half the threads idle in them and the
+// larger butterflies cost occupancy.)
 FftDesc fft_desc(int n) {
     FftDesc d{};
     d.n = n;
-    int a = 0, b = 0;
-    factor_23(n, &a, &b);
+    int a = 0, b = 0, c = 0;
+    factor_235(n, &a, &b, &c);
     for (; a >= 3; a -= 3) d.radix[d.nst++] = 8;
     if (a == 2) d.radix[d.nst++] = 4;
     if (a == 1) d.radix[d.nst++] = 2;
     for (int i = 0; i < b; ++i) d.radix[d.nst++] = 3;
+    for (int i = 0; i < c; ++i) d.radix[d.nst++] = 5;
     return d;
 }
 
@@ -559,11 +556,11 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
     if (levels < 1 || levels > 4) return MLBA_EINVAL;
     const int N = bc == MLBA_BC_RECT ? n + p - 1 : n;
     if ((1 << (levels - 1)) >= N) return MLBA_EINVAL;
-    int a2 = 0, b3 = 0;
+    int a2 = 0, b3 = 0, c5 = 0;
     if (precond == MLBA_PRECOND_AR) {  // complex FFTs of length 2(n - 1)
         if (!ar_transform_supported(n)) return MLBA_EUNSUPPORTED;
-    } else if (precond != MLBA_PRECOND_NONE) {
-        if (!factor_23(n, &a2, &b3) || a2 < 1 || n < 8 || n > 2048) return MLBA_EUNSUPPORTED;
+    } else if (precond != MLBA_PRECOND_NONE) {  // row pairs: n even
+        if (!factor_235(n, &a2, &b3, &c5) || a2 < 1 || n < 8 || n > 2048) return MLBA_EUNSUPPORTED;
     }
 
     mlba_plan_s* P = new (std::nothrow) mlba_plan_s();

@@ -73,7 +73,10 @@ def test_status_strings():
     (64, 9, 0, 5, 1, _lib.EINVAL),        # unknown preconditioner
     (64, 9, 0, 0, 0, _lib.EINVAL),        # no framelet level
     (64, 9, 0, 0, 5, _lib.EINVAL),        # too many levels
-    (70, 9, 0, 0, 1, _lib.EUNSUPPORTED),  # 70 = 2 * 5 * 7 has no 2/3-smooth FFT
+    (70, 9, 0, 0, 1, _lib.EUNSUPPORTED),  # 70 = 2 * 5 * 7: 7 is outside the radix 2/3/5 transforms
+    (125, 9, 0, 0, 1, _lib.EUNSUPPORTED),  # odd: the row passes pair rows
+    (196, 9, 4, 3, 1, _lib.EUNSUPPORTED),  # antireflective transform length 390 = 2 * 3 * 5 * 13
+    (2049, 9, 4, 3, 1, _lib.EUNSUPPORTED),  # antireflective transform length 4096: beyond one workgroup
     (5000, 9, 0, 0, 1, _lib.EUNSUPPORTED),
     (4096, 9, 0, 0, 1, _lib.EUNSUPPORTED),   # beyond the one-workgroup transform
     (256, 51, 0, 0, 1, _lib.EUNSUPPORTED),   # PSF window beyond the blur's LDS tile

@@ -112,7 +112,7 @@ def test_affine_image_is_blurred_exactly(mlba):
     assert np.abs(Af - f).max() < 2e-6
 
 
-AR_SIZES = [4, 10, 13, 65, 97, 193, 257, 433, 1025]
+AR_SIZES = [4, 6, 10, 11, 13, 51, 65, 97, 193, 226, 257, 433, 1025]  # transform lengths 2^a 3^b 5^c
 
 
 @pytest.mark.parametrize("n", AR_SIZES)
@@ -156,10 +156,11 @@ def test_ar_direction(mlba, n):
     assert rel_err(t, ref) < TOL_L2 and max_err(t, ref) < TOL_MAX
 
 
-@pytest.mark.parametrize("n", [226, 196, 2049, 3])
+@pytest.mark.parametrize("n", [196, 2049, 3, 15])
 def test_ar_sizes_outside_the_transform(mlba, n):
-    """2(n - 1) must be 2^a 3^b and at most 2048 (226 and 196 are the paper's
-    Examples 4 and 3 observation sides)."""
+    """2(n - 1) must be 2^a 3^b 5^c and at most 2048 (196, Example 3's
+    observation side, gives 390 = 2 * 3 * 5 * 13; Example 4's 226 is
+    supported)."""
     from paper_1504_07234_amd import _lib
     announce(f"antireflective transform size n={n}")
     with pytest.raises(_lib.MLBAError) as e:
@@ -220,6 +221,30 @@ def test_mlba_antireflective_against_oracle(mlba, n, p, pc, sym, L, alpha, iters
     ref = omlba.mlba(g, H, AR_BC, pc, L, np.full(iters, alpha), np.full(iters + 1, delta), mu, iters)
     with mlba.Plan(n, p, mlba.ANTIREFLECT, pc, L, cuda(H)) as plan:
         f, info = plan.restore(cuda(g), alpha=alpha, mu=mu, delta=delta, iters=iters, implicit=implicit)
+        f = host(f)
+    e = rel_err(f, ref["f"])
+    print(f"  image {e:.2e} rnorm {rel_err(info.rnorm, ref['rnorm']):.2e}", flush=True)
+    assert e < 1e-4
+    assert rel_err(info.rnorm, ref["rnorm"]) < 1e-4
+
+
+@pytest.mark.parametrize("blur", ["direct", "fft"])
+def test_example4_shape(mlba, blur):
+    """Example 4's shape: a 226 x 226 observation of a larger scene, 31 x 31
+    Gaussian of standard deviation 2.5, 2 % noise, antireflective conditions
+    with the antireflective-transform preconditioner (transform length 450 =
+    2 * 3^2 * 5^2), alpha = 0.01 (Table 4's Alg-BC3), automatic step."""
+    n, p, L, iters, alpha = 226, 31, 2, 20, 0.01
+    announce(f"Example 4 shape n={n} p={p} blur={blur}")
+    g0 = synth.rng(226)
+    truth = synth.shapes_image(n + p - 1, g0, n_rect=8, n_disk=4, n_bumps=3)
+    H = synth.gaussian_psf(p, 2.5)
+    g = synth.add_noise(ob.blur(truth, H, ob.RECT), synth.white_noise((n, n), g0), 0.02)
+    delta = omlba.delta_auto(_sym_opnorm(H, n, alpha))
+    ref = omlba.mlba(g, H, AR_BC, opc.AR, L, np.full(iters, alpha), np.full(iters + 1, delta), 1e-3, iters)
+    with mlba.Plan(n, p, mlba.ANTIREFLECT, mlba.AR, L, cuda(H)) as plan:
+        plan.set_blur(mlba.BLUR_FFT if blur == "fft" else mlba.BLUR_DIRECT)
+        f, info = plan.restore(cuda(g), alpha=alpha, mu=1e-3, delta=delta, iters=iters, implicit=True)
         f = host(f)
     e = rel_err(f, ref["f"])
     print(f"  image {e:.2e} rnorm {rel_err(info.rnorm, ref['rnorm']):.2e}", flush=True)
