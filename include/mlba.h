@@ -80,7 +80,7 @@ extern "C" {
 #define MLBA_ALPHA_CONST      0  /* alpha_k = alpha0                              */
 #define MLBA_ALPHA_GEOMETRIC  1  /* alpha_k = max(alpha0 * ratio^k, alpha_floor)  */
 #define MLBA_ALPHA_TABLE      2  /* alpha_k = table[k] (host, >= k0+iters values) */
-#define MLBA_ALPHA_NS         3  /* Algorithm 4-NS (MLBA_METHOD_ALG4, BCCB only): alpha_n solves
+#define MLBA_ALPHA_NS         3  /* Algorithm 4-NS (MLBA_METHOD_ALG4, BCCB or DCT plan): alpha_n solves
                                     alpha_n ||(C C^T + alpha_n I)^{-1} r^n|| = q_n ||r^n||,
                                     q_n = max{ns_q, 2 ns_rho + (1 + ns_rho) / tau_n},
                                     tau_n = ||r^n|| / noise (eq. Alg4_rev_7); the run stops at

@@ -227,48 +227,87 @@ __device__ __forceinline__ void dct_rows_fwd_body(const float* __restrict__ src,
     }
 }
 
-// CP pairs of Tr rows per workgroup: DCT-II along the row, multiply by
-// inv / (spec + alpha), DCT-III back.
+// CP pairs of Tr rows per workgroup.  mode 0: DCT-II along the row, multiply
+// by inv / (spec + alpha) (times lamr: C^T (C C^T + alpha I)^{-1} of
+// Algorithm 4), DCT-III back; mode 1: DCT-II only, the coefficients written
+// back (Algorithm 4-NS solves for alpha from them); mode 2: from those
+// coefficients, multiply by inv lamr / (spec + alpha_dev[0]), DCT-III back.
 __device__ __forceinline__ void dct_cols_filter_body(float* __restrict__ Tr, int n, int ts,
                                                                  const float* __restrict__ spec, float alpha,
                                                                  float inv, const FftDesc& fd,
                                                                  const float2* __restrict__ tw,
                                                                  const float2* __restrict__ dtw, int CP, int seq_shift, int blk, float2* buf,
-                                                                 const float* __restrict__ lamr = nullptr) {
+                                                                 const float* __restrict__ lamr = nullptr,
+                                                                 int mode = 0,
+                                                                 const double* __restrict__ alpha_dev = nullptr) {
     const int pairs = n / 2;
     const int p0 = blk * CP;
     const int cp = min(CP, pairs - p0);
     const int total = cp * n;
-    for (int idx = threadIdx.x; idx < total; idx += kBlock) {
-        const int q = idx / n;
-        const int l = idx - q * n;
-        const size_t r1 = (size_t)(2 * (p0 + q)) * ts;
-        buf[lds_slot(q * n + dct_perm(l, n))] = make_float2(Tr[r1 + l], Tr[r1 + ts + l]);
-    }
-    __syncthreads();
-    lds_fft<-1>(buf, fd, cp, seq_shift, tw);
-
     float2 keep[FFT_EPT];
+    if (mode == 2) {
+        const float a = (float)alpha_dev[0];
 #pragma unroll
-    for (int i = 0; i < FFT_EPT; ++i) {
-        const int idx = threadIdx.x + i * kBlock;
-        if (idx < total) {
+        for (int i = 0; i < FFT_EPT; ++i) {
+            const int idx = threadIdx.x + i * kBlock;
+            if (idx < total) {
+                const int q = idx / n;
+                const int l = idx - q * n;
+                const size_t r1 = (size_t)(2 * (p0 + q)) * ts;
+                const size_t s1 = (size_t)(2 * (p0 + q)) * n;
+                const float f1 = inv / (spec[s1 + l] + a) * lamr[s1 + l];
+                const float f2 = inv / (spec[s1 + n + l] + a) * lamr[s1 + n + l];
+                keep[i] = make_float2(Tr[r1 + l] * f1, Tr[r1 + ts + l] * f2);
+            }
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < total; idx += kBlock) {
             const int q = idx / n;
             const int l = idx - q * n;
-            const float2 Z = buf[lds_slot(q * n + l)];
-            const float2 Zc = cconj(buf[lds_slot(q * n + (l == 0 ? 0 : n - l))]);
-            const float2 V1 = cscale(cadd(Z, Zc), 0.5f);
-            const float2 D = csub(Z, Zc);
-            const float2 V2 = make_float2(0.5f * D.y, -0.5f * D.x);
-            const float2 w = dtw[l];
-            const size_t s1 = (size_t)(2 * (p0 + q)) * n;  // dense [n][n] spectrum
-            float f1 = inv / (spec[s1 + l] + alpha);
-            float f2 = inv / (spec[s1 + n + l] + alpha);
-            if (lamr) {  // C^T (C C^T + alpha I)^{-1} of Algorithm 4
-                f1 *= lamr[s1 + l];
-                f2 *= lamr[s1 + n + l];
+            const size_t r1 = (size_t)(2 * (p0 + q)) * ts;
+            buf[lds_slot(q * n + dct_perm(l, n))] = make_float2(Tr[r1 + l], Tr[r1 + ts + l]);
+        }
+        __syncthreads();
+        lds_fft<-1>(buf, fd, cp, seq_shift, tw);
+#pragma unroll
+        for (int i = 0; i < FFT_EPT; ++i) {
+            const int idx = threadIdx.x + i * kBlock;
+            if (idx < total) {
+                const int q = idx / n;
+                const int l = idx - q * n;
+                const float2 Z = buf[lds_slot(q * n + l)];
+                const float2 Zc = cconj(buf[lds_slot(q * n + (l == 0 ? 0 : n - l))]);
+                const float2 V1 = cscale(cadd(Z, Zc), 0.5f);
+                const float2 D = csub(Z, Zc);
+                const float2 V2 = make_float2(0.5f * D.y, -0.5f * D.x);
+                const float2 w = dtw[l];
+                if (mode == 1) {
+                    keep[i] = make_float2(re_mul(w, V1), re_mul(w, V2));
+                } else {
+                    const size_t s1 = (size_t)(2 * (p0 + q)) * n;  // dense [n][n] spectrum
+                    float f1 = inv / (spec[s1 + l] + alpha);
+                    float f2 = inv / (spec[s1 + n + l] + alpha);
+                    if (lamr) {
+                        f1 *= lamr[s1 + l];
+                        f2 *= lamr[s1 + n + l];
+                    }
+                    keep[i] = make_float2(re_mul(w, V1) * f1, re_mul(w, V2) * f2);
+                }
             }
-            keep[i] = make_float2(re_mul(w, V1) * f1, re_mul(w, V2) * f2);
+        }
+        if (mode == 1) {  // the coefficients over the rows this workgroup read
+#pragma unroll
+            for (int i = 0; i < FFT_EPT; ++i) {
+                const int idx = threadIdx.x + i * kBlock;
+                if (idx < total) {
+                    const int q = idx / n;
+                    const int l = idx - q * n;
+                    const size_t r1 = (size_t)(2 * (p0 + q)) * ts;
+                    Tr[r1 + l] = keep[i].x;
+                    Tr[r1 + ts + l] = keep[i].y;
+                }
+            }
+            return;
         }
     }
     __syncthreads();
@@ -418,9 +457,11 @@ __global__ __launch_bounds__(kBlock) void dct_cols_filter_kernel(float* __restri
                                                                  float inv, FftDesc fd,
                                                                  const float2* __restrict__ tw,
                                                                  const float2* __restrict__ dtw, int CP, int seq_shift,
-                                                                 const float* __restrict__ lamr) {
+                                                                 const float* __restrict__ lamr, int mode,
+                                                                 const double* __restrict__ alpha_dev) {
     extern __shared__ float2 buf[];
-    dct_cols_filter_body(Tr, n, ts, spec, alpha, inv, fd, tw, dtw, CP, seq_shift, blockIdx.x, buf, lamr);
+    dct_cols_filter_body(Tr, n, ts, spec, alpha, inv, fd, tw, dtw, CP, seq_shift, blockIdx.x, buf, lamr, mode,
+                         alpha_dev);
 }
 
 __global__ __launch_bounds__(kBlock) void dct_rows_inv_kernel(const float* __restrict__ Tr, int n, int ts,
@@ -518,20 +559,32 @@ __global__ __launch_bounds__(kBlock) void pad_psf_kernel(const float* __restrict
 // ---------------------------------------------------------------------------
 constexpr int NS_BLOCKS = 256;
 
-__global__ __launch_bounds__(kBlock) void ns_partials_kernel(const float2* __restrict__ T, int n, int ts,
+// REAL: the 2-D DCT-II coefficients Tr[kx][ky] (real, n rows) of the DCT
+// plan instead; with the unnormalised X_k = sum_j x_j cos(pi k (2j+1) / 2n)
+// the orthonormal coefficient is sqrt((2 - [k == 0]) / n) X_k along each axis,
+// so Parseval weighs X^2 by (kx ? 2 : 1)(ky ? 2 : 1) (the common 1/n^2
+// cancels in the equation).
+template <bool REAL>
+__global__ __launch_bounds__(kBlock) void ns_partials_kernel(const void* __restrict__ Tv, int n, int ts,
                                                              const float* __restrict__ spec,
                                                              const double* __restrict__ state,
                                                              double* __restrict__ part) {
     __shared__ double red[3][kBlock / 64];
     const float a = (float)state[0];
-    const int half = n / 2 + 1;
-    const size_t total = (size_t)half * n;
+    const int rows = REAL ? n : n / 2 + 1;
+    const size_t total = (size_t)rows * n;
     double s0 = 0.0, s1 = 0.0, rr = 0.0;
     for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (size_t)gridDim.x * kBlock) {
         const int kx = (int)(i / n);
         const int ky = (int)(i - (size_t)kx * n);
-        const float2 v = T[(size_t)kx * ts + ky];
-        const float w = ((kx == 0 || 2 * kx == n) ? 1.0f : 2.0f) * (v.x * v.x + v.y * v.y);
+        float w;
+        if constexpr (REAL) {
+            const float v = static_cast<const float*>(Tv)[(size_t)kx * ts + ky];
+            w = (kx == 0 ? 1.0f : 2.0f) * (ky == 0 ? 1.0f : 2.0f) * (v * v);
+        } else {
+            const float2 v = static_cast<const float2*>(Tv)[(size_t)kx * ts + ky];
+            w = ((kx == 0 || 2 * kx == n) ? 1.0f : 2.0f) * (v.x * v.x + v.y * v.y);
+        }
         const float sk = spec[i];
         const float id = 1.0f / (sk + a);
         const float t0 = w * id * id;
@@ -621,14 +674,18 @@ __global__ __launch_bounds__(kBlock) void ns_update_kernel(const double* __restr
     if (hist) *hist = state[0];
 }
 
-hipError_t launch_ns_alpha(const float2* T, int n, int ts, const float* spec, double* state, double* part,
+hipError_t launch_ns_alpha(const void* T, int real, int n, int ts, const float* spec, double* state, double* part,
                            const double* rn_sq, const float* psf, int p, double noise, double q, double rho,
                            double alpha_first, int first, int steps, double* hist, hipStream_t s) {
     hipLaunchKernelGGL(ns_init_kernel, dim3(1), dim3(1), 0, s, state, rn_sq, psf, p, noise, q, rho, alpha_first,
                        first);
     for (int k = 0; k < steps; ++k) {
-        hipLaunchKernelGGL(ns_partials_kernel, dim3(NS_BLOCKS), dim3(kBlock), 0, s, T, n, ts, spec,
-                           (const double*)state, part);
+        if (real)
+            hipLaunchKernelGGL(ns_partials_kernel<true>, dim3(NS_BLOCKS), dim3(kBlock), 0, s, T, n, ts, spec,
+                               (const double*)state, part);
+        else
+            hipLaunchKernelGGL(ns_partials_kernel<false>, dim3(NS_BLOCKS), dim3(kBlock), 0, s, T, n, ts, spec,
+                               (const double*)state, part);
         hipLaunchKernelGGL(ns_update_kernel, dim3(1), dim3(kBlock), 0, s, (const double*)part, NS_BLOCKS, state,
                            k == steps - 1 ? hist : (double*)nullptr);
     }
@@ -828,15 +885,32 @@ hipError_t launch_dct_rows_fwd(const float* src, int n, float* Tr, int ts, const
     return hipGetLastError();
 }
 
-hipError_t launch_dct_cols_filter(float* Tr, int n, int ts, const float* spec, float alpha, float inv,
+static hipError_t launch_dct_cols(float* Tr, int n, int ts, const float* spec, float alpha, float inv,
                                   const FftDesc& fd, const float2* tw, const float2* dtw, hipStream_t s,
-                                  const float* lamr) {
+                                  const float* lamr, int mode, const double* alpha_dev) {
     int CP = pick_cols_per_block(n);
     const int pairs = n / 2;
     const size_t lds = lds_bytes(CP * n, n);
     hipLaunchKernelGGL(dct_cols_filter_kernel, dim3((pairs + CP - 1) / CP), dim3(kBlock), lds, s, Tr, n, ts, spec,
-                       alpha, inv, fd, tw, dtw, CP, seq_shift_for(CP), lamr);
+                       alpha, inv, fd, tw, dtw, CP, seq_shift_for(CP), lamr, mode, alpha_dev);
     return hipGetLastError();
+}
+
+hipError_t launch_dct_cols_filter(float* Tr, int n, int ts, const float* spec, float alpha, float inv,
+                                  const FftDesc& fd, const float2* tw, const float2* dtw, hipStream_t s,
+                                  const float* lamr) {
+    return launch_dct_cols(Tr, n, ts, spec, alpha, inv, fd, tw, dtw, s, lamr, 0, nullptr);
+}
+
+hipError_t launch_dct_cols_forward(float* Tr, int n, int ts, const FftDesc& fd, const float2* tw, const float2* dtw,
+                                   hipStream_t s) {
+    return launch_dct_cols(Tr, n, ts, nullptr, 0.0f, 1.0f, fd, tw, dtw, s, nullptr, 1, nullptr);
+}
+
+hipError_t launch_dct_cols_filter_inverse(float* Tr, int n, int ts, const float* spec, const double* alpha_dev,
+                                          float inv, const float* lamr, const FftDesc& fd, const float2* tw,
+                                          const float2* dtw, hipStream_t s) {
+    return launch_dct_cols(Tr, n, ts, spec, 0.0f, inv, fd, tw, dtw, s, lamr, 2, alpha_dev);
 }
 
 hipError_t launch_dct_rows_inv(const float* Tr, int n, int ts, float* dst, const FftDesc& fd, const float2* tw,

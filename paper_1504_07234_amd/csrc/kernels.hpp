@@ -260,7 +260,8 @@ hipError_t launch_fft_cols_filter_inverse(float2* T, int n, int ts, const float*
 hipError_t launch_fft_cols_complex(const float2* T, int n, int ts, float2* cspec, const FftDesc& fd,
                                    const float2* tw, hipStream_t s);
 // Algorithm 4-NS: alpha_n on the device (state, hist: device doubles; part: >= ns_partials_needed())
-hipError_t launch_ns_alpha(const float2* T, int n, int ts, const float* spec, double* state, double* part,
+// from the BCCB half spectrum T (float2, real = 0) or the DCT coefficients (float, real = 1)
+hipError_t launch_ns_alpha(const void* T, int real, int n, int ts, const float* spec, double* state, double* part,
                            const double* rn_sq, const float* psf, int p, double noise, double q, double rho,
                            double alpha_first, int first, int steps, double* hist, hipStream_t s);
 int ns_partials_needed();
@@ -278,6 +279,13 @@ hipError_t launch_dct_cols_filter(float* Tr, int n, int ts, const float* spec, f
                                   hipStream_t s, const float* lamr = nullptr);  // lamr: times lambda (Alg. 4)
 hipError_t launch_dct_rows_inv(const float* Tr, int n, int ts, float* dst, const FftDesc& fd,
                                const float2* tw, const float2* dtw, hipStream_t s, int accum = 0);
+// columns: DCT-II only (Tr then holds the 2-D coefficients), and the filter
+// inv lamr / (spec + alpha_dev[0]) with the DCT-III from those coefficients (Algorithm 4-NS)
+hipError_t launch_dct_cols_forward(float* Tr, int n, int ts, const FftDesc& fd, const float2* tw, const float2* dtw,
+                                   hipStream_t s);
+hipError_t launch_dct_cols_filter_inverse(float* Tr, int n, int ts, const float* spec, const double* alpha_dev,
+                                          float inv, const float* lamr, const FftDesc& fd, const float2* tw,
+                                          const float2* dtw, hipStream_t s);
 // spec[kx][ky] = lambda[ky][kx]^2 of the symmetrised PSF's cosine spectrum,
 // lambda itself into lam when given: K = n with costab[q] = cos(pi q / n)
 // for the reflective blur (Algorithm 3); K = n - 1, costab[q] = cos(pi q /

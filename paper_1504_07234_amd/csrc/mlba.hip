@@ -315,18 +315,34 @@ int do_ct_precond(mlba_plan_s* P, const float* r, float* t, double alpha, int ac
     return MLBA_OK;
 }
 
-// Algorithm 4-NS step (BCCB): alpha_n solved on the device from the spectrum
-// of r (rn_sq = ||r||^2 on the device), then t (+)= C^T (C C^T + alpha_n I)^{-1} r
+// Algorithm 4-NS step (BCCB or DCT plan): alpha_n solved on the device from
+// the spectrum (or the DCT coefficients) of r (rn_sq = ||r||^2 on the device),
+// then t (+)= C^T (C C^T + alpha_n I)^{-1} r
 int do_ct_precond_ns(mlba_plan_s* P, const float* r, float* t, const double* rn_sq, double noise, double q,
                      double rho, double alpha_first, int first, double* hist, int accum, hipStream_t s) {
     const int n = P->n;
     const float inv = (float)(1.0 / ((double)n * (double)n));
+    if (P->precond == MLBA_PRECOND_DCT) {  // the same steps on the 2-D DCT-II coefficients
+        float* Tr = (float*)P->swork;
+        HIPCHK(launch_dct_rows_fwd(r, n, Tr, P->ts, P->fd, P->tw, P->dtw, s));
+        MARK(PRECOND, FFT_ROWS_FWD);
+        HIPCHK(launch_dct_cols_forward(Tr, n, P->ts, P->fd, P->tw, P->dtw, s));
+        MARK(PRECOND, FFT_COLS);
+        HIPCHK(launch_ns_alpha(Tr, 1, n, P->ts, P->spec, P->ns, P->partials, rn_sq, P->psf, P->p, noise, q, rho,
+                               alpha_first, first, 12, hist, s));
+        STCHK(prof_mark(P, MLBA_PHASE_PRECOND, MLBA_KERNEL_OTHER, 1 + 2 * 12, s));
+        HIPCHK(launch_dct_cols_filter_inverse(Tr, n, P->ts, P->spec, P->ns, inv, P->lamr, P->fd, P->tw, P->dtw, s));
+        MARK(PRECOND, FFT_COLS);
+        HIPCHK(launch_dct_rows_inv(Tr, n, P->ts, t, P->fd, P->tw, P->dtw, s, accum));
+        MARK(PRECOND, FFT_ROWS_INV);
+        return MLBA_OK;
+    }
     float2* T = (float2*)P->swork;
     HIPCHK(launch_fft_rows_r2c(r, n, T, P->ts, P->fd, P->tw, s));
     MARK(PRECOND, FFT_ROWS_FWD);
     HIPCHK(launch_fft_cols_forward(T, n, P->ts, P->fd, P->tw, s));
     MARK(PRECOND, FFT_COLS);
-    HIPCHK(launch_ns_alpha(T, n, P->ts, P->spec, P->ns, P->partials, rn_sq, P->psf, P->p, noise, q, rho,
+    HIPCHK(launch_ns_alpha(T, 0, n, P->ts, P->spec, P->ns, P->partials, rn_sq, P->psf, P->p, noise, q, rho,
                            alpha_first, first, 12, hist, s));
     STCHK(prof_mark(P, MLBA_PHASE_PRECOND, MLBA_KERNEL_OTHER, 1 + 2 * 12, s));
     HIPCHK(launch_fft_cols_filter_inverse(T, n, P->ts, P->spec, P->ns, inv, P->lamc, P->fd, P->tw, s));
@@ -909,7 +925,7 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
     mlba_stop ns_stop{};
     if (ns) {
         if (prm->alpha_out && iters > P->rn_cap) return MLBA_EINVAL;  // the device history is one ring
-        if (!alg4 || P->precond != MLBA_PRECOND_BCCB) return MLBA_EUNSUPPORTED;
+        if (!alg4 || (P->precond != MLBA_PRECOND_BCCB && P->precond != MLBA_PRECOND_DCT)) return MLBA_EUNSUPPORTED;
         if (!stop || !(stop->noise_norm > 0.0) || !(as.ns_rho > 0.0 && as.ns_rho < 0.5) ||
             !(as.ns_q > 2.0 * as.ns_rho && as.ns_q < 1.0) || !(as.alpha0 > 0.0))
             return MLBA_EINVAL;

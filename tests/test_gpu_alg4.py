@@ -80,7 +80,7 @@ def test_alg4_against_oracle(mlba, bc, kind, sym, alpha, iters, L, n, implicit):
     assert np.allclose(info.alphas, alpha)
 
 
-def _alpha_condition(g, H, bc, L, mu, alphas):
+def _alpha_condition(g, H, bc, L, mu, alphas, kind=None):
     """kappa_n = |d log alpha_n / d log q_n| along the oracle's 4-NS run.
 
     alpha_n solves alpha^2 S0(alpha) = q_n^2 R (S0 = sum w / (s + alpha)^2), so
@@ -89,31 +89,41 @@ def _alpha_condition(g, H, bc, L, mu, alphas):
     change of q_n (through ||r^n||) of 1e-7 then moves alpha_n by ~1e-7 kappa_n."""
     from oracle import framelet as ofr
     from oracle.mlba import soft_threshold
+    import scipy.fft
+    from oracle import precond as opc
+    kind = oa.BCCB if kind is None else kind
     n = g.shape[0]
-    s = np.abs(oa.centred_eigs(H, n)) ** 2
+    if kind == oa.BCCB:
+        s = np.abs(oa.centred_eigs(H, n)) ** 2
+    else:
+        s = opc.dct_eigs(opc.symmetrize(H), n) ** 2
     z = np.zeros((8 * L + 1, n, n))
     out = []
     for a in alphas:
         r = g - ob.blur(ofr.synthesis(soft_threshold(z, mu), L), H, bc)
-        w = np.abs(np.fft.fft2(r)) ** 2
+        w = np.abs(np.fft.fft2(r)) ** 2 if kind == oa.BCCB else scipy.fft.dctn(r, type=2, norm="ortho") ** 2
         S0 = np.sum(w / (s + a) ** 2)
         S1 = np.sum(w * s / (s + a) ** 3)
         out.append(S0 / S1)
-        z = z + ofr.analysis(oa.apply_ct_prec(r, H, a, oa.BCCB), L)
+        z = z + ofr.analysis(oa.apply_ct_prec(r, H, a, kind), L)
     return np.asarray(out)
 
 
 @pytest.mark.parametrize("implicit", [False, True])
-@pytest.mark.parametrize("bc,n,L", [(ob.ZERO, 128, 2), (ob.PERIODIC, 96, 1), (ob.REFLECT, 192, 2)])
-def test_alg4_ns_against_oracle(mlba, bc, n, L, implicit):
+@pytest.mark.parametrize("bc,n,L,kind", [(ob.ZERO, 128, 2, oa.BCCB), (ob.PERIODIC, 96, 1, oa.BCCB),
+                                         (ob.REFLECT, 192, 2, oa.BCCB), (ob.REFLECT, 128, 2, oa.DCT),
+                                         (ob.ANTIREFLECT, 96, 2, oa.DCT)])
+def test_alg4_ns_against_oracle(mlba, bc, n, L, kind, implicit):
+    """4-NS with the BCCB spectrum and with the DCT of the symmetrised PSF
+    (Alg-BC4-NS of Example 4: antireflective model, Gaussian PSF, DCT)."""
     p = 9
-    announce(f"Alg4-NS bc={bc} n={n} L={L} implicit={implicit}")
-    g, H, noise, _ = _problem(n, p, bc, False, 70 + bc)
+    announce(f"Alg4-NS bc={bc} n={n} L={L} kind={kind} implicit={implicit}")
+    g, H, noise, _ = _problem(n, p, bc, kind == oa.DCT, 70 + bc)
     mu = 1e-3
-    ref = oa.alg4_ns(g, H, bc, oa.BCCB, L, mu, noise, q=0.5, rho=1e-4, max_iters=300)
+    ref = oa.alg4_ns(g, H, bc, kind, L, mu, noise, q=0.5, rho=1e-4, max_iters=300)
     k = ref["iters"]
     assert 0 < k < 300
-    with mlba.Plan(n, p, bc, mlba.BCCB, L, cuda(H)) as plan:
+    with mlba.Plan(n, p, bc, kind, L, cuda(H)) as plan:
         f, info = plan.restore(cuda(g), alpha=0.5, mu=mu, delta=1.0, iters=300, method=mlba.ALG4,
                                implicit=implicit, ns=(0.5, 1e-4), stop=(noise, 0.0, 1))
         f = host(f)
@@ -121,7 +131,7 @@ def test_alg4_ns_against_oracle(mlba, bc, n, L, implicit):
           f"image {rel_err(f, ref['f']):.2e}", flush=True)
     assert info.iters_done == k
     # alpha_n within FP32 round-off carried through the condition of its equation
-    kappa = _alpha_condition(g, H, bc, L, mu, ref["alphas"])
+    kappa = _alpha_condition(g, H, bc, L, mu, ref["alphas"], kind)
     dev = np.abs(np.asarray(info.alphas) - ref["alphas"]) / ref["alphas"]
     print(f"  alpha rel dev {np.array2string(dev, precision=1)} kappa {np.array2string(kappa, precision=1)}",
           flush=True)
@@ -139,9 +149,10 @@ def test_alg4_rejections(mlba):
         with pytest.raises(_lib.MLBAError) as e:
             plan.restore(g, alpha=0.1, iters=2, method=mlba.ALG4)
         assert e.value.status == _lib.EUNSUPPORTED
-    with mlba.Plan(32, 5, mlba.REFLECT, mlba.DCT, 1, H) as plan:
-        with pytest.raises(_lib.MLBAError) as e:  # 4-NS needs the BCCB spectrum
-            plan.restore(g, alpha=0.1, iters=2, method=mlba.ALG4, ns=(0.5, 1e-4), stop=(1.0, 0.0, 1))
+    with mlba.Plan(33, 5, mlba.ANTIREFLECT, mlba.AR, 1, H) as plan:
+        with pytest.raises(_lib.MLBAError) as e:  # 4-NS needs an orthogonal transform (Parseval)
+            plan.restore(cuda(np.zeros((33, 33))), alpha=0.1, iters=2, method=mlba.ALG4, ns=(0.5, 1e-4),
+                         stop=(1.0, 0.0, 1))
         assert e.value.status == _lib.EUNSUPPORTED
     with mlba.Plan(32, 5, mlba.ZERO, mlba.BCCB, 1, H) as plan:
         with pytest.raises(_lib.MLBAError) as e:  # no noise level
