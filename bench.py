@@ -52,7 +52,7 @@ TRAFFIC = {
     # the direct A^T accumulating into omega (p = 31), one launch per iteration
     ("conv_blur_t", "direct-implicit"): {
         "fetch_kib": 17582.1, "write_kib": 16878.0, "fetch_scale": 2.0, "write_scale": 1.0, "launches": 1,
-        "sources_sha256": "ab7b83d263634987c2b01bebc5476b605c452f7f2dc8f184691aee96016ea55f"},
+        "sources_sha256": "fca4913313f0458db47a0f57d873789bf9eaaa77c44d52002f03c131abdef323"},
 }
 # the sources that define each kernel's device code
 TRAFFIC_SOURCES = {

@@ -312,6 +312,27 @@ def test_alg2_antireflective_against_oracle(mlba):
     assert rel_err(f, ref["f"]) < 1e-4
 
 
+def test_alg2_with_the_exact_antireflective_preconditioner(mlba):
+    """Example 4's remark: with a symmetric PSF the antireflective transform
+    preconditioner is (A A' + alpha I)^{-1} itself, so Algorithm 2 takes one
+    PCG step per iteration and equals Alg-BC3 (the MLBA with that
+    preconditioner); both against the oracle."""
+    n, p, L, alpha, delta, iters = 97, 9, 2, 0.05, 0.5, 15
+    announce("Alg2 with the exact antireflective preconditioner")
+    g, H = _problem(n, p, True, 83)
+    ref = oa2.alg2(g, H, AR_BC, opc.AR, L, np.full(iters, alpha), np.full(iters + 1, delta), 1e-3, iters,
+                   beta_max=5, tol=0.05)
+    assert ref["betas"].tolist() == [1] * iters
+    with mlba.Plan(n, p, mlba.ANTIREFLECT, mlba.AR, L, cuda(H)) as plan:
+        f2, i2 = plan.restore(cuda(g), alpha=alpha, mu=1e-3, delta=delta, iters=iters, method=mlba.ALG2,
+                              pcg=(5, 0.05))
+        f1, _ = plan.restore(cuda(g), alpha=alpha, mu=1e-3, delta=delta, iters=iters)
+        f1, f2 = host(f1), host(f2)
+    assert i2.pcg_steps == [1] * iters
+    assert rel_err(f2, ref["f"]) < 1e-4
+    assert rel_err(f2, f1) < 1e-5
+
+
 def test_full_size_antireflective(mlba):
     """The antireflective workload at its full size (n = 1025, 31 x 31
     Gaussian, 3 levels, automatic step) for a few iterations, the image and
