@@ -170,8 +170,8 @@ int mlba_version(void);
  * MLBA_BC_*, precond one of MLBA_PRECOND_*, levels in [1, 4] with
  * 2^(levels-1) < N.  The transforms of P need n = 2^a 3^b 5^c, a >= 1,
  * 8 <= n <= 2048 for MLBA_PRECOND_BCCB and MLBA_PRECOND_DCT, and
- * 2(n - 1) = 2^a 3^b 5^c <= 2048 (e.g. n = 65, 97, 226, 257, 1025) for
- * MLBA_PRECOND_AR (MLBA_EUNSUPPORTED otherwise).  psf: device p x p.
+ * 2(n - 1) = 2^a 3^b 5^c <= 2048 (e.g. n = 65, 97, 226, 257, 1025) and
+ * MLBA_BC_ANTIREFLECT for MLBA_PRECOND_AR (MLBA_EUNSUPPORTED otherwise).  psf: device p x p.
  * Allocates the workspace, copies the PSF and computes the spectrum of
  * (C C^T) or (Q Q^T) on `stream` (section 4.1 / 4.3).  The plan keeps no
  * reference to `psf`.  With MLBA_BC_ANTIREFLECT every A^T below (operators,

@@ -573,8 +573,8 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
     const int N = bc == MLBA_BC_RECT ? n + p - 1 : n;
     if ((1 << (levels - 1)) >= N) return MLBA_EINVAL;
     int a2 = 0, b3 = 0, c5 = 0;
-    if (precond == MLBA_PRECOND_AR) {  // complex FFTs of length 2(n - 1)
-        if (!ar_transform_supported(n)) return MLBA_EUNSUPPORTED;
+    if (precond == MLBA_PRECOND_AR) {  // complex FFTs of length 2(n - 1); Q antireflective like A
+        if (bc != MLBA_BC_ANTIREFLECT || !ar_transform_supported(n)) return MLBA_EUNSUPPORTED;
     } else if (precond != MLBA_PRECOND_NONE) {  // row pairs: n even
         if (!factor_235(n, &a2, &b3, &c5) || a2 < 1 || n < 8 || n > 2048) return MLBA_EUNSUPPORTED;
     }

@@ -77,6 +77,7 @@ def test_status_strings():
     (125, 9, 0, 0, 1, _lib.EUNSUPPORTED),  # odd: the row passes pair rows
     (196, 9, 4, 3, 1, _lib.EUNSUPPORTED),  # antireflective transform length 390 = 2 * 3 * 5 * 13
     (2049, 9, 4, 3, 1, _lib.EUNSUPPORTED),  # antireflective transform length 4096: beyond one workgroup
+    (65, 9, 1, 3, 1, _lib.EUNSUPPORTED),    # the antireflective transform goes with the antireflective model
     (5000, 9, 0, 0, 1, _lib.EUNSUPPORTED),
     (4096, 9, 0, 0, 1, _lib.EUNSUPPORTED),   # beyond the one-workgroup transform
     (256, 51, 0, 0, 1, _lib.EUNSUPPORTED),   # PSF window beyond the blur's LDS tile
