@@ -315,7 +315,8 @@ def alg4_section(w, g, noise, steps: int = 30):
     periodic boundary conditions, C^T (C C^T + alpha I)^{-1} by FFT (no A^T
     product), implicit state, alpha = 0.02, unit step, `steps` timed
     iterations; and Algorithm 4-NS (q = 0.5, rho = 1e-4) run to its
-    discrepancy stop."""
+    discrepancy stop, with that BCCB plan and with the DCT of the symmetrised
+    PSF on the reflective model."""
     import torch
 
     from paper_1504_07234_amd import mlba
@@ -345,6 +346,21 @@ def alg4_section(w, g, noise, steps: int = 30):
         out["ns"] = {"q": 0.5, "rho": 1e-4, "iters_to_stop": info.iters_done, "s_total": round(el, 5),
                      "ms_per_step": round(el * 1e3 / max(info.iters_done, 1), 5),
                      "last_alpha": info.alphas[-1] if info.alphas else None}
+    # 4-NS with the DCT of the symmetrised PSF on the reflective model (the DCT
+    # form of Example 4's Alg-BC4-NS)
+    with mlba.Plan(n, w.p, mlba.REFLECT, mlba.DCT, w.levels, psf) as plan:
+        f = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        plan.restore(g, alpha=0.5, mu=w.mu, delta=1.0, iters=2, out=f, implicit=True, method=mlba.ALG4,
+                     ns=(0.5, 1e-4), stop=(noise, 0.0, 1), track=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = plan.restore(g, alpha=0.5, mu=w.mu, delta=1.0, iters=500, out=f, implicit=True,
+                               method=mlba.ALG4, ns=(0.5, 1e-4), stop=(noise, 0.0, 1))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out["ns_dct"] = {"model": "reflective", "precond": "dct", "q": 0.5, "rho": 1e-4,
+                         "iters_to_stop": info.iters_done, "s_total": round(el, 5),
+                         "ms_per_step": round(el * 1e3 / max(info.iters_done, 1), 5)}
     return out
 
 
@@ -389,7 +405,9 @@ def antireflective_section(steps: int = 30, warmup: int = 3):
     n^2 and the n^2 filter and write n^2, rows T read n^2 and write n^2; of the
     grid passes (two launches each, A and A'): rows read n^2 and write the
     (M/2+1) x m half spectrum, columns read it and the PSF spectrum and write
-    the (M/2+1) x n rows kept, inverse rows read those and read + write n^2."""
+    the (M/2+1) x n rows kept, inverse rows read those and read + write n^2.
+    Alg-BC4 (Algorithm 4 with the same transform, no A' product) is timed on
+    the same plan."""
     import torch
 
     import synth
@@ -420,6 +438,15 @@ def antireflective_section(steps: int = 30, warmup: int = 3):
         el = time.perf_counter() - t0
         _, rec = plan.profile_end()
         kernels = plan.profile_kernels()
+        # Alg-BC4 on the same plan: Q' (Q Q' + alpha I)^-1 r by the transform, no A' product
+        plan.restore(g, alpha=w.alpha0, mu=w.mu, delta=1.0, iters=warmup, z=om, out=f, track=False,
+                     implicit=True, method=mlba.ALG4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.restore(g, alpha=w.alpha0, mu=w.mu, delta=1.0, iters=steps, k0=warmup, z=om, out=f, track=False,
+                     implicit=True, method=mlba.ALG4)
+        torch.cuda.synchronize()
+        el4 = time.perf_counter() - t0
     rec = max(rec, 1)
     fft_blur = tune["blur"] == "fft"
     model = kernel_model(n, p, N, w.levels, True, False)
@@ -453,6 +480,7 @@ def antireflective_section(steps: int = 30, warmup: int = 3):
             "blur": f"fft grid {fft_grid(n + p - 1)}" if fft_blur else "direct taps",
             "blur_autotune": tune,
             "ms_per_step": round(el * 1e3 / steps, 5), "Mpx_it_s": round(n * n * steps / el / 1e6, 2),
+            "alg4": {"ms_per_step": round(el4 * 1e3 / steps, 5), "Mpx_it_s": round(n * n * steps / el4 / 1e6, 2)},
             "kernels": kern}
 
 
