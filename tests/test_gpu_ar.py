@@ -48,6 +48,7 @@ def _psf(kind, p, seed):
     (96, 17, "motion"),
     (150, 31, "motion"),   # several tiles and a ragged tail
     (77, 35, "rand"),      # the generic tap loop
+    (100, 49, "rand"),     # the largest PSF (pad of 24)
     (33, 1, "rand"),
     (9, 9, "rand"),        # the pad as wide as the image allows (c = n - 1 - 4)
     (5, 3, "rand"),
@@ -76,6 +77,7 @@ def test_blur_and_reblur(mlba, n, p, kind):
     (97, 31, "motion"),
     (150, 17, "rand"),
     (257, 41, "rand"),
+    (200, 49, "rand"),     # the largest PSF
     (1025, 31, "gauss"),   # the antireflective workload's shapes (grid 1152)
 ])
 def test_fft_grid_blur_and_reblur(mlba, n, p, kind):
