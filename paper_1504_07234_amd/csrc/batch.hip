@@ -88,7 +88,10 @@ int configure(mlba_batch_s* B, hipStream_t s) {
     std::vector<int> pcount(count);
     for (int i = 0; i < count; ++i) {
         BatchImage& d = B->host[i];
-        if (d.precond != MLBA_PRECOND_NONE) {
+        if (d.precond == MLBA_PRECOND_AR) {  // one row pair per workgroup (the transform is 2(n-1) long)
+            d.fft_rows_g = d.fft_cols_c = 1;
+            d.fft_rows_shift = d.fft_cols_shift = fft_seq_shift(1);
+        } else if (d.precond != MLBA_PRECOND_NONE) {
             d.fft_rows_g = B->rows_want ? fft_rows_batch_at_most(d.n, B->rows_want) : fft_rows_batch(d.n);
             d.fft_cols_c = B->cols_want ? fft_cols_batch_at_most(d.n, B->cols_want) : fft_cols_batch(d.n);
             d.fft_rows_shift = fft_seq_shift(d.fft_rows_g);
@@ -224,7 +227,6 @@ int mlba_batch_create(mlba_batch_t* batch, int count, const mlba_plan_t* plans, 
     for (int i = 0; i < count; ++i) {
         if (!plans[i]) return MLBA_EINVAL;
         if (plans[i]->levels != plans[0]->levels || plans[i]->precond != plans[0]->precond) return MLBA_EINVAL;
-        if (plans[i]->precond == MLBA_PRECOND_AR) return MLBA_EUNSUPPORTED;  // batched passes: DFT and DCT only
         for (int j = 0; j < i; ++j)
             if (plans[j] == plans[i]) return MLBA_EINVAL;  // one image per plan (the plan holds its buffers)
     }

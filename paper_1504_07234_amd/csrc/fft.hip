@@ -18,6 +18,7 @@
 // samples followed by the reversed odd samples, with a quarter-sample
 // post-twiddle (Makhoul's reordering); DCT-III inverts those steps.
 // All transforms here are unnormalised; the filter carries the 1/n^2.
+#include "artrans.hpp"
 #include "common.hpp"
 #include "fft_core.hpp"
 #include "kernels.hpp"
@@ -743,6 +744,7 @@ int fft_seq_shift(int batch) { return seq_shift_for(batch); }
 
 int precond_pass_tiles(const BatchImage& I, int pass) {
     if (I.precond == 2) return 0;  // P = I: the descriptor aliases t to r
+    if (I.precond == 3) return pass == 3 ? 0 : (I.n + 1) / 2;  // antireflective: one row pair per workgroup
     if (pass == 3) pass = 1;
     if (pass != 1) return I.n / (2 * I.fft_rows_g);
     if (I.precond == 0) return (I.n / 2 + 1 + I.fft_cols_c - 1) / I.fft_cols_c;
@@ -762,6 +764,16 @@ __global__ __launch_bounds__(kBlock) void precond_batched_kernel(const BatchImag
     const int blk = xb - bfirst[im];
     const int n = I.n;
     const float inv = (float)(1.0 / ((double)n * (double)n));
+    if constexpr (PRECOND == 3) {  // antireflective transform, one row pair per workgroup
+        __shared__ float2 lin[2 * kArMaxBatch];
+        float* Tr = (float*)I.swork;
+        if (PASS == 0) ar_rows_fwd_body<0>(I.r, n, Tr, I.ts, I.fd, I.tw, 1, I.fft_rows_shift, blk, buf);
+        if (PASS == 1)
+            ar_cols_filter_body<0>(Tr, n, I.ts, I.spec, I.alpha, nullptr, I.fd, I.tw, 1, I.fft_cols_shift, blk, buf,
+                                   lin);
+        if (PASS == 2) ar_rows_inv_body<0>(Tr, n, I.ts, I.t, I.fd, I.tw, 1, I.fft_rows_shift, blk, buf, 0);
+        return;
+    }
     if (PRECOND == 0) {
         float2* T = (float2*)I.swork;
         if (PASS == 0) fft_rows_r2c_body(I.r, n, T, I.ts, I.fd, I.tw, I.fft_rows_g, I.fft_rows_shift, blk, buf);
@@ -794,11 +806,16 @@ hipError_t launch_precond_batched(const BatchImage* imgs, const int* bmap, const
         else if (pass == 1) MLBA_PB(1, 0);
         else if (pass == 2) MLBA_PB(2, 0);
         else MLBA_PB(3, 0);
-    } else {
+    } else if (precond == 1) {
         if (pass == 3) return hipErrorInvalidValue;
         if (pass == 0) MLBA_PB(0, 1);
         else if (pass == 1) MLBA_PB(1, 1);
         else MLBA_PB(2, 1);
+    } else {
+        if (pass == 3) return hipErrorInvalidValue;
+        if (pass == 0) MLBA_PB(0, 3);
+        else if (pass == 1) MLBA_PB(1, 3);
+        else MLBA_PB(2, 3);
     }
 #undef MLBA_PB
     return hipGetLastError();

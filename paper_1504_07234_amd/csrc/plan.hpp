@@ -102,7 +102,10 @@ inline mlba::BatchImage plan_desc(const mlba_plan_s* P) {
     d.tw = P->tw;
     d.dtw = P->dtw;
     d.fd = P->fd;
-    if (P->precond != MLBA_PRECOND_NONE) {
+    if (P->precond == MLBA_PRECOND_AR) {  // one row pair per workgroup
+        d.fft_rows_g = d.fft_cols_c = 1;
+        d.fft_rows_shift = d.fft_cols_shift = mlba::fft_seq_shift(1);
+    } else if (P->precond != MLBA_PRECOND_NONE) {
         d.fft_rows_g = mlba::fft_rows_batch(P->n);
         d.fft_cols_c = mlba::fft_cols_batch(P->n);
         d.fft_rows_shift = mlba::fft_seq_shift(d.fft_rows_g);
