@@ -135,6 +135,28 @@ def test_ar_preconditioner(mlba, n):
                 assert e2 < TOL_L2 and em < TOL_MAX
 
 
+def test_set_psf_recomputes_the_antireflective_spectra(mlba):
+    """A new PSF replaces the transform's eigenvalues and the FFT grid's
+    spectrum: P, A and A' follow it."""
+    n, p = 97, 9
+    announce("antireflective set_psf")
+    H1 = _psf("gauss", p, 1)
+    H2 = _psf("motion", p, 2)
+    g = synth.rng(7)
+    r = g.standard_normal((n, n))
+    u = g.random((n, n))
+    with mlba.Plan(n, p, mlba.ANTIREFLECT, mlba.AR, 1, cuda(H1)) as plan:
+        plan.set_blur(mlba.BLUR_FFT)
+        plan.apply_P(cuda(r), 0.05)
+        plan.set_psf(cuda(H2))
+        t = host(plan.apply_P(cuda(r), 0.05))
+        Au = host(plan.apply_A(cuda(u)))
+        Ary = host(plan.apply_At(cuda(r)))
+    assert rel_err(t, opc.apply_ar(r, H2, 0.05)) < TOL_L2
+    assert rel_err(Au, ob.blur(u, H2, AR_BC)) < TOL_L2
+    assert rel_err(Ary, ob.reblur(r, H2, AR_BC)) < TOL_L2
+
+
 def test_ar_preconditioner_in_place(mlba):
     n, p = 97, 7
     announce("antireflective preconditioner in place")
