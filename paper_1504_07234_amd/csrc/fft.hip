@@ -202,10 +202,15 @@ __device__ __forceinline__ int dct_perm(int l, int n) { return (l & 1) ? n - 1 -
 __device__ __forceinline__ float re_mul(float2 w, float2 v) { return w.x * v.x - w.y * v.y; }
 
 // G row pairs -> Tr[k][row] (real, row stride ts), k = 0..n-1
-__device__ __forceinline__ void dct_rows_fwd_body(const float* __restrict__ src, int n,
+// NT > 0 (here and in the two DCT bodies below): n == NT with one sequence per
+// workgroup, the compiled fixed-size transform.
+template <int NT = 0>
+__device__ __forceinline__ void dct_rows_fwd_body(const float* __restrict__ src, int n_,
                                                               float* __restrict__ Tr, int ts, const FftDesc& fd,
                                                               const float2* __restrict__ tw,
-                                                              const float2* __restrict__ dtw, int G, int seq_shift, int blk, float2* buf) {
+                                                              const float2* __restrict__ dtw, int G_, int seq_shift, int blk, float2* buf) {
+    const int n = NT > 0 ? NT : n_;
+    const int G = NT > 0 ? 1 : G_;
     const int row0 = blk * 2 * G;
     for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
         const int g = idx / n;
@@ -214,7 +219,7 @@ __device__ __forceinline__ void dct_rows_fwd_body(const float* __restrict__ src,
         buf[lds_slot(g * n + dct_perm(x, n))] = make_float2(src[ra + x], src[ra + n + x]);
     }
     __syncthreads();
-    lds_fft<-1>(buf, fd, G, seq_shift, tw);
+    lds_fft_any<-1, NT>(buf, fd, G, seq_shift, tw);
     for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
         const int k = idx / G;
         const int g = idx - k * G;
@@ -233,14 +238,17 @@ __device__ __forceinline__ void dct_rows_fwd_body(const float* __restrict__ src,
 // Algorithm 4), DCT-III back; mode 1: DCT-II only, the coefficients written
 // back (Algorithm 4-NS solves for alpha from them); mode 2: from those
 // coefficients, multiply by inv lamr / (spec + alpha_dev[0]), DCT-III back.
-__device__ __forceinline__ void dct_cols_filter_body(float* __restrict__ Tr, int n, int ts,
+template <int NT = 0>
+__device__ __forceinline__ void dct_cols_filter_body(float* __restrict__ Tr, int n_, int ts,
                                                                  const float* __restrict__ spec, float alpha,
                                                                  float inv, const FftDesc& fd,
                                                                  const float2* __restrict__ tw,
-                                                                 const float2* __restrict__ dtw, int CP, int seq_shift, int blk, float2* buf,
+                                                                 const float2* __restrict__ dtw, int CP_, int seq_shift, int blk, float2* buf,
                                                                  const float* __restrict__ lamr = nullptr,
                                                                  int mode = 0,
                                                                  const double* __restrict__ alpha_dev = nullptr) {
+    const int n = NT > 0 ? NT : n_;
+    const int CP = NT > 0 ? 1 : CP_;
     const int pairs = n / 2;
     const int p0 = blk * CP;
     const int cp = min(CP, pairs - p0);
@@ -269,7 +277,7 @@ __device__ __forceinline__ void dct_cols_filter_body(float* __restrict__ Tr, int
             buf[lds_slot(q * n + dct_perm(l, n))] = make_float2(Tr[r1 + l], Tr[r1 + ts + l]);
         }
         __syncthreads();
-        lds_fft<-1>(buf, fd, cp, seq_shift, tw);
+        lds_fft_any<-1, NT>(buf, fd, cp, seq_shift, tw);
 #pragma unroll
         for (int i = 0; i < FFT_EPT; ++i) {
             const int idx = threadIdx.x + i * kBlock;
@@ -339,7 +347,7 @@ __device__ __forceinline__ void dct_cols_filter_body(float* __restrict__ Tr, int
         if (idx < total) buf[lds_slot(idx)] = keep[i];
     }
     __syncthreads();
-    lds_fft<1>(buf, fd, cp, seq_shift, tw);
+    lds_fft_any<1, NT>(buf, fd, cp, seq_shift, tw);
     for (int idx = threadIdx.x; idx < total; idx += kBlock) {
         const int q = idx / n;
         const int l = idx - q * n;
@@ -350,11 +358,14 @@ __device__ __forceinline__ void dct_cols_filter_body(float* __restrict__ Tr, int
     }
 }
 
-__device__ __forceinline__ void dct_rows_inv_body(const float* __restrict__ Tr, int n, int ts,
+template <int NT = 0>
+__device__ __forceinline__ void dct_rows_inv_body(const float* __restrict__ Tr, int n_, int ts,
                                                               float* __restrict__ dst, const FftDesc& fd,
                                                               const float2* __restrict__ tw,
-                                                              const float2* __restrict__ dtw, int G, int seq_shift, int blk, float2* buf,
+                                                              const float2* __restrict__ dtw, int G_, int seq_shift, int blk, float2* buf,
                                                               int accum = 0) {
+    const int n = NT > 0 ? NT : n_;
+    const int G = NT > 0 ? 1 : G_;
     const int row0 = blk * 2 * G;
     const int total = G * n;
     for (int idx = threadIdx.x; idx < total; idx += kBlock) {
@@ -385,7 +396,7 @@ __device__ __forceinline__ void dct_rows_inv_body(const float* __restrict__ Tr, 
         if (idx < total) buf[lds_slot(idx)] = keep[i];
     }
     __syncthreads();
-    lds_fft<1>(buf, fd, G, seq_shift, tw);
+    lds_fft_any<1, NT>(buf, fd, G, seq_shift, tw);
     for (int idx = threadIdx.x; idx < total; idx += kBlock) {
         const int g = idx / n;
         const int x = idx - g * n;
@@ -445,14 +456,16 @@ __global__ __launch_bounds__(kBlock) void fft_rows_c2r_kernel(const float2* __re
     fft_rows_c2r_body<NT>(T, n, ts, dst, fd, tw, G, seq_shift, xcd_block(blockIdx.x, gridDim.x), buf, accum);
 }
 
+template <int NT>
 __global__ __launch_bounds__(kBlock) void dct_rows_fwd_kernel(const float* __restrict__ src, int n,
                                                               float* __restrict__ Tr, int ts, FftDesc fd,
                                                               const float2* __restrict__ tw,
                                                               const float2* __restrict__ dtw, int G, int seq_shift) {
     extern __shared__ float2 buf[];
-    dct_rows_fwd_body(src, n, Tr, ts, fd, tw, dtw, G, seq_shift, xcd_block(blockIdx.x, gridDim.x), buf);
+    dct_rows_fwd_body<NT>(src, n, Tr, ts, fd, tw, dtw, G, seq_shift, xcd_block(blockIdx.x, gridDim.x), buf);
 }
 
+template <int NT>
 __global__ __launch_bounds__(kBlock) void dct_cols_filter_kernel(float* __restrict__ Tr, int n, int ts,
                                                                  const float* __restrict__ spec, float alpha,
                                                                  float inv, FftDesc fd,
@@ -461,17 +474,18 @@ __global__ __launch_bounds__(kBlock) void dct_cols_filter_kernel(float* __restri
                                                                  const float* __restrict__ lamr, int mode,
                                                                  const double* __restrict__ alpha_dev) {
     extern __shared__ float2 buf[];
-    dct_cols_filter_body(Tr, n, ts, spec, alpha, inv, fd, tw, dtw, CP, seq_shift, blockIdx.x, buf, lamr, mode,
-                         alpha_dev);
+    dct_cols_filter_body<NT>(Tr, n, ts, spec, alpha, inv, fd, tw, dtw, CP, seq_shift, blockIdx.x, buf, lamr, mode,
+                             alpha_dev);
 }
 
+template <int NT>
 __global__ __launch_bounds__(kBlock) void dct_rows_inv_kernel(const float* __restrict__ Tr, int n, int ts,
                                                               float* __restrict__ dst, FftDesc fd,
                                                               const float2* __restrict__ tw,
                                                               const float2* __restrict__ dtw, int G, int seq_shift,
                                                               int accum) {
     extern __shared__ float2 buf[];
-    dct_rows_inv_body(Tr, n, ts, dst, fd, tw, dtw, G, seq_shift, xcd_block(blockIdx.x, gridDim.x), buf, accum);
+    dct_rows_inv_body<NT>(Tr, n, ts, dst, fd, tw, dtw, G, seq_shift, xcd_block(blockIdx.x, gridDim.x), buf, accum);
 }
 
 // Cosine spectra of the symmetrised PSF H~ (reflective blur, Algorithm 3;
@@ -897,8 +911,12 @@ hipError_t launch_dct_rows_fwd(const float* src, int n, float* Tr, int ts, const
                                const float2* dtw, hipStream_t s) {
     const int G = pick_pairs_per_block(n);
     const size_t lds = lds_bytes(G * n, n);
-    hipLaunchKernelGGL(dct_rows_fwd_kernel, dim3(n / (2 * G)), dim3(kBlock), lds, s, src, n, Tr, ts, fd, tw, dtw, G,
-                       seq_shift_for(G));
+    if (n == kFixedN && G == 1)
+        hipLaunchKernelGGL(dct_rows_fwd_kernel<kFixedN>, dim3(n / 2), dim3(kBlock), lds, s, src, n, Tr, ts, fd, tw,
+                           dtw, 1, seq_shift_for(1));
+    else
+        hipLaunchKernelGGL(dct_rows_fwd_kernel<0>, dim3(n / (2 * G)), dim3(kBlock), lds, s, src, n, Tr, ts, fd, tw,
+                           dtw, G, seq_shift_for(G));
     return hipGetLastError();
 }
 
@@ -908,8 +926,12 @@ static hipError_t launch_dct_cols(float* Tr, int n, int ts, const float* spec, f
     int CP = pick_cols_per_block(n);
     const int pairs = n / 2;
     const size_t lds = lds_bytes(CP * n, n);
-    hipLaunchKernelGGL(dct_cols_filter_kernel, dim3((pairs + CP - 1) / CP), dim3(kBlock), lds, s, Tr, n, ts, spec,
-                       alpha, inv, fd, tw, dtw, CP, seq_shift_for(CP), lamr, mode, alpha_dev);
+    if (n == kFixedN && CP == 1)
+        hipLaunchKernelGGL(dct_cols_filter_kernel<kFixedN>, dim3(pairs), dim3(kBlock), lds, s, Tr, n, ts, spec, alpha,
+                           inv, fd, tw, dtw, 1, seq_shift_for(1), lamr, mode, alpha_dev);
+    else
+        hipLaunchKernelGGL(dct_cols_filter_kernel<0>, dim3((pairs + CP - 1) / CP), dim3(kBlock), lds, s, Tr, n, ts,
+                           spec, alpha, inv, fd, tw, dtw, CP, seq_shift_for(CP), lamr, mode, alpha_dev);
     return hipGetLastError();
 }
 
@@ -934,8 +956,12 @@ hipError_t launch_dct_rows_inv(const float* Tr, int n, int ts, float* dst, const
                                const float2* dtw, hipStream_t s, int accum) {
     const int G = pick_pairs_per_block(n);
     const size_t lds = lds_bytes(G * n, n);
-    hipLaunchKernelGGL(dct_rows_inv_kernel, dim3(n / (2 * G)), dim3(kBlock), lds, s, Tr, n, ts, dst, fd, tw, dtw, G,
-                       seq_shift_for(G), accum);
+    if (n == kFixedN && G == 1)
+        hipLaunchKernelGGL(dct_rows_inv_kernel<kFixedN>, dim3(n / 2), dim3(kBlock), lds, s, Tr, n, ts, dst, fd, tw,
+                           dtw, 1, seq_shift_for(1), accum);
+    else
+        hipLaunchKernelGGL(dct_rows_inv_kernel<0>, dim3(n / (2 * G)), dim3(kBlock), lds, s, Tr, n, ts, dst, fd, tw,
+                           dtw, G, seq_shift_for(G), accum);
     return hipGetLastError();
 }
 

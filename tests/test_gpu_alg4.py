@@ -140,6 +140,28 @@ def test_alg4_ns_against_oracle(mlba, bc, n, L, kind, implicit):
     assert rel_err(info.rnorm, ref["rnorm"][:k]) < 1e-4
 
 
+@pytest.mark.parametrize("kind", [oa.BCCB, oa.DCT])
+def test_alg4_ns_first_steps_at_2048(mlba, kind):
+    """The 2048 observation (the compiled 2048-point transforms, including the
+    DCT's split column pass): the first three 4-NS steps, far from the stop
+    where alpha_n is well conditioned, against the oracle."""
+    n, p, L, iters = 2048, 9, 2, 3
+    bc = ob.REFLECT
+    announce(f"Alg4-NS first steps n={n} kind={kind}")
+    g, H, noise, _ = _problem(n, p, bc, True, 91 + kind)
+    ref = oa.alg4_ns(g, H, bc, kind, L, 1e-3, noise, q=0.5, rho=1e-4, max_iters=iters)
+    assert ref["iters"] == iters  # the stop does not fire this early
+    with mlba.Plan(n, p, bc, kind, L, cuda(H)) as plan:
+        f, info = plan.restore(cuda(g), alpha=0.5, mu=1e-3, delta=1.0, iters=iters, method=mlba.ALG4,
+                               implicit=True, ns=(0.5, 1e-4), stop=(noise, 0.0, 1))
+        f = host(f)
+    print(f"  alphas gpu {info.alphas} oracle {ref['alphas'].tolist()}; image {rel_err(f, ref['f']):.2e}",
+          flush=True)
+    assert info.iters_done == iters
+    assert rel_err(info.alphas, ref["alphas"]) < 1e-4
+    assert rel_err(f, ref["f"]) < 1e-4
+
+
 def test_alg4_rejections(mlba):
     from paper_1504_07234_amd import _lib
     announce("Alg4 argument checks")
