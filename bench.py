@@ -403,9 +403,11 @@ def antireflective_section(steps: int = 30, warmup: int = 3):
     iterations with the per-kernel profile.  Algorithmic bytes of the
     transform passes: rows T^-1 read n^2 and write n^2 floats, columns read
     n^2 and the n^2 filter and write n^2, rows T read n^2 and write n^2; of the
-    grid passes (two launches each, A and A'): rows read n^2 and write the
-    (M/2+1) x m half spectrum, columns read it and the PSF spectrum and write
-    the (M/2+1) x n rows kept, inverse rows read those and read + write n^2.
+    grid passes (A and A'): rows read n^2 and write the (M/2+1) x m half
+    spectrum, columns read it and the PSF spectrum and write the (M/2+1) x n
+    rows kept, inverse rows read those and read + write n^2 (on the grid the
+    residual's inverse rows and the transform's forward rows are one launch:
+    read the kept rows and g, write the n^2 transform rows).
     Alg-BC4 (Algorithm 4 with the same transform, no A' product) is timed on
     the same plan."""
     import torch
@@ -420,7 +422,8 @@ def antireflective_section(steps: int = 30, warmup: int = 3):
         blurred = rect.apply_A(torch.as_tensor(w.truth, dtype=torch.float32).cuda())
     xi = torch.as_tensor(w.xi, dtype=torch.float32).cuda()
     g = (blurred + (w.noise_level * blurred.double().norm() / xi.double().norm()).float() * xi).contiguous()
-    names = {"fft_rows_fwd": "ar_rows_fwd", "fft_cols": "ar_cols_filter", "fft_rows_inv": "ar_rows_inv"}
+    names = {"fft_rows_fwd": "ar_rows_fwd", "fft_cols": "ar_cols_filter", "fft_rows_inv": "ar_rows_inv",
+             "fc_residual_precond_rows": "fc_residual_ar_rows"}
     with mlba.Plan(n, p, w.bc, w.precond, w.levels, psf) as plan:
         N = plan.N
         tune = plan.autotune(reps=5)
@@ -451,6 +454,9 @@ def antireflective_section(steps: int = 30, warmup: int = 3):
     fft_blur = tune["blur"] == "fft"
     model = kernel_model(n, p, N, w.levels, True, False)
     nn = 4.0 * n * n
+    model["fft_rows_fwd"] = {"bytes": 2 * nn, "flops": 0.0, "launches": 1, "bound": "hbm"}
+    model["fft_cols"] = {"bytes": 3 * nn, "flops": 0.0, "launches": 1, "bound": "hbm"}
+    model["fft_rows_inv"] = {"bytes": 2 * nn, "flops": 0.0, "launches": 1, "bound": "hbm"}
     if fft_blur:
         m_ = n + p - 1
         M = fft_grid(m_)
@@ -459,10 +465,12 @@ def antireflective_section(steps: int = 30, warmup: int = 3):
             model.pop(k)
         model["fc_rows_fwd"] = {"bytes": 2 * (nn + 8.0 * hm * m_), "flops": 0.0, "launches": 2, "bound": "hbm"}
         model["fc_cols"] = {"bytes": 2 * 8.0 * hm * (m_ + M + n), "flops": 0.0, "launches": 2, "bound": "hbm"}
-        model["fc_rows_inv"] = {"bytes": 2 * (8.0 * hm * n + 2 * nn), "flops": 0.0, "launches": 2, "bound": "hbm"}
-    model["fft_rows_fwd"] = {"bytes": 2 * nn, "flops": 0.0, "launches": 1, "bound": "hbm"}
-    model["fft_cols"] = {"bytes": 3 * nn, "flops": 0.0, "launches": 1, "bound": "hbm"}
-    model["fft_rows_inv"] = {"bytes": 2 * nn, "flops": 0.0, "launches": 1, "bound": "hbm"}
+        # the residual's inverse rows fused with the transform's forward rows: read the
+        # kept half-spectrum rows and g, write Tr; the reblur's inverse rows into omega
+        model["fc_residual_precond_rows"] = {"bytes": 8.0 * hm * n + 2 * nn, "flops": 0.0, "launches": 1,
+                                             "bound": "hbm"}
+        model.pop("fft_rows_fwd")
+        model["fc_rows_inv"] = {"bytes": 8.0 * hm * n + 2 * nn, "flops": 0.0, "launches": 1, "bound": "hbm"}
     kern = {}
     for k, (ms, nl) in kernels.items():
         us = ms * 1e3 / rec

@@ -39,14 +39,24 @@ __global__ __launch_bounds__(kBlock) void ar_rows_fwd_kernel(const float* __rest
     ar_rows_fwd_body<NT>(src, n, Tr, ts, fd, tw, G, seq_shift, xcd_block(blockIdx.x, gridDim.x), buf);
 }
 
+// red_out (optional): workgroup 0 first sums red_count partials of the
+// previous launch (the residual's) into *red_out.
 template <int NT>
 __global__ __launch_bounds__(kBlock) void ar_cols_filter_kernel(float* __restrict__ Tr, int n, int ts,
                                                                 const float* __restrict__ spec, float alpha,
                                                                 const float* __restrict__ lamr, FftDesc fd,
                                                                 const float2* __restrict__ tw, int CP,
-                                                                int seq_shift) {
+                                                                int seq_shift, const double* __restrict__ red_in,
+                                                                int red_count, double* __restrict__ red_out) {
     extern __shared__ float2 buf[];
     __shared__ float2 lin[2 * kArMaxBatch];
+    if (red_out && blockIdx.x == 0) {
+        __shared__ double red[kBlock / 64];
+        double acc = 0.0;
+        for (int i = threadIdx.x; i < red_count; i += kBlock) acc += red_in[i];
+        const double t = block_sum(acc, red);
+        if (threadIdx.x == 0) *red_out = t;
+    }
     ar_cols_filter_body<NT>(Tr, n, ts, spec, alpha, lamr, fd, tw, CP, seq_shift, blockIdx.x, buf, lin);
 }
 
@@ -108,16 +118,17 @@ hipError_t launch_ar_rows_fwd(const float* src, int n, float* Tr, int ts, const 
 }
 
 hipError_t launch_ar_cols_filter(float* Tr, int n, int ts, const float* spec, float alpha, const float* lamr,
-                                 const FftDesc& fd, const float2* tw, hipStream_t s) {
+                                 const FftDesc& fd, const float2* tw, hipStream_t s, const double* red_in,
+                                 int red_count, double* red_out) {
     const int CP = ar_batch(n), L = 2 * (n - 1), pairs = (n + 1) / 2;
     const dim3 grid((pairs + CP - 1) / CP);
     const size_t lds = lds_bytes(CP * L, L);
     if (L == kFixedN && CP == 1)
         hipLaunchKernelGGL(ar_cols_filter_kernel<kFixedN>, grid, dim3(kBlock), lds, s, Tr, n, ts, spec, alpha, lamr,
-                           fd, tw, 1, ar_shift_for(1));
+                           fd, tw, 1, ar_shift_for(1), red_in, red_count, red_out);
     else
         hipLaunchKernelGGL(ar_cols_filter_kernel<0>, grid, dim3(kBlock), lds, s, Tr, n, ts, spec, alpha, lamr, fd,
-                           tw, CP, ar_shift_for(CP));
+                           tw, CP, ar_shift_for(CP), red_in, red_count, red_out);
     return hipGetLastError();
 }
 

@@ -15,6 +15,7 @@
 // write, or accumulation).  Rows that are zero in the padded input are skipped
 // by the row pass and read as zero by the column pass.  Transforms of up to
 // 3072 points use 12 values per thread.
+#include "artrans.hpp"
 #include "common.hpp"
 #include "fft_core.hpp"
 #include "kernels.hpp"
@@ -281,6 +282,108 @@ __global__ __launch_bounds__(kBlock) void fc_residual_precond_kernel(
     }
 }
 
+// The residual's inverse row pass on the FFT-blur grid (observed rows 2q and
+// 2q + 1; the second is absent for the last pair of an odd n) and the forward
+// row pass of the antireflective transform of those residual rows, in one
+// workgroup: inverse M-point row FFT, crop, g - . with the squared-norm
+// partial, then the odd extension of the detrended rows and its L-point FFT
+// (L = 2(n-1)), written transposed into Tr like ar_rows_fwd_body.
+template <int NTM, int NTL>
+__global__ __launch_bounds__(kBlock) void fc_residual_ar_kernel(
+    const float2* __restrict__ Tc, int M_, int tsc, FftDesc fdm, const float2* __restrict__ twm, int pair0, int n,
+    int off, const float* __restrict__ g, double* __restrict__ partials, float* __restrict__ Tr, int tsr,
+    FftDesc fdl, const float2* __restrict__ twl) {
+    extern __shared__ float2 buf[];
+    __shared__ double red[kBlock / 64];
+    __shared__ float2 ends[2];  // (r_a, r_b) at x = 0 and x = n - 1
+    const int M = NTM > 0 ? NTM : M_;
+    const int N = n - 1, L = NTL > 0 ? NTL : 2 * N;
+    const float invN = 1.0f / (float)N;
+    const int q = xcd_block(blockIdx.x, gridDim.x);
+    const int pb = pair0 + q;
+    const bool has_b = 2 * q + 1 < n;
+    const int half = M / 2 + 1;
+    for (int k = threadIdx.x; k < half; k += kBlock) {
+        const float4 v = *reinterpret_cast<const float4*>(Tc + (size_t)k * tsc + 2 * pb);
+        float2 Xa = make_float2(v.x, v.y), Xb = make_float2(v.z, v.w);
+        const bool edge = (k == 0) || (2 * k == M);
+        if (edge) {
+            Xa.y = 0.0f;
+            Xb.y = 0.0f;
+        }
+        buf[lds_slot(k)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
+        if (!edge) buf[lds_slot(M - k)] = make_float2(Xa.x + Xb.y, -Xa.y + Xb.x);
+    }
+    __syncthreads();
+    lds_fft_any<1, NTM, FC_EPT>(buf, fdm, 1, 8, twm);
+    float2 rr[FC_EPT];
+    double ss = 0.0;
+    const size_t ra = (size_t)(2 * q) * n;
+#pragma unroll
+    for (int j = 0; j < FC_EPT; ++j) {
+        rr[j] = make_float2(0.0f, 0.0f);
+        const int X = (int)threadIdx.x + j * kBlock;
+        const int x = X - off;
+        if (X < M && x >= 0 && x < n) {
+            const float2 v = buf[lds_slot(X)];
+            const float a = g[ra + x] - v.x;
+            ss += (double)a * (double)a;
+            float b = 0.0f;
+            if (has_b) {
+                b = g[ra + n + x] - v.y;
+                ss += (double)b * (double)b;
+            }
+            rr[j] = make_float2(a, b);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < FC_EPT; ++j) {
+        const int X = (int)threadIdx.x + j * kBlock;
+        const int x = X - off;
+        if (X < M && x >= 0 && x < n) {
+            buf[lds_slot(x)] = rr[j];
+            if (x == 0) ends[0] = rr[j];
+            if (x == N) ends[1] = rr[j];
+        }
+    }
+    __syncthreads();
+    // odd extension of the detrended residual rows (positions 0 and N zero)
+    constexpr int KE = FFT_MAX_ELEMS / kBlock;
+    float2 ext[KE];
+#pragma unroll
+    for (int j = 0; j < KE; ++j) {
+        const int k = (int)threadIdx.x + j * kBlock;
+        ext[j] = make_float2(0.0f, 0.0f);
+        if (k < L) {
+            ext[j].x = ar_odd_detrended([&](int i) { return buf[lds_slot(i)].x; }, k, N, invN);
+            ext[j].y = ar_odd_detrended([&](int i) { return buf[lds_slot(i)].y; }, k, N, invN);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < KE; ++j) {
+        const int k = (int)threadIdx.x + j * kBlock;
+        if (k < L) buf[lds_slot(k)] = ext[j];
+    }
+    __syncthreads();
+    lds_fft_any<-1, NTL, FFT_EPT>(buf, fdl, 1, 8, twl);
+    for (int jj = threadIdx.x; jj < n; jj += kBlock) {
+        float2 c;
+        if (jj == 0 || jj == N) {
+            c = ends[jj == 0 ? 0 : 1];
+        } else {
+            const float2 X = buf[lds_slot(jj)];
+            c = make_float2(-X.y * invN, X.x * invN);  // (2/N) DST-I
+        }
+        *reinterpret_cast<float2*>(Tr + (size_t)jj * tsr + 2 * q) = c;
+    }
+    if (partials) {
+        const double t = block_sum(ss, red);
+        if (threadIdx.x == 0) partials[blockIdx.x] = t;
+    }
+}
+
 // The preconditioner's inverse row pass (t = P r, two observed rows) and the
 // forward row pass of A^T on the FFT-blur grid, where those rows sit at
 // (y + off, x + off), in one workgroup.
@@ -428,6 +531,27 @@ hipError_t launch_fc_residual_precond_rows(const FftConv& c, int n, int p, const
         hipLaunchKernelGGL((fc_residual_precond_kernel<0, 0>), dim3(blocks), dim3(kBlock), lds, s, (const float2*)c.T,
                            c.M, c.ts, c.fd, c.tw, (p - 1) / 2, n, p - 1, g, r_out, partials, pr.T, pr.ts, pr.fd,
                            pr.tw);
+    return hipGetLastError();
+}
+
+bool fftconv_ar_fusable(const FftConv& c, int n, const FftDesc& fdl) {
+    return c.M <= FC_MAX && fdl.n == 2 * (n - 1) && fdl.n <= FFT_MAX_ELEMS;
+}
+
+hipError_t launch_fc_residual_ar_rows(const FftConv& c, int n, int p, const float* g, double* partials,
+                                     int* n_partials, float* Tr, int tsr, const FftDesc& fdl, const float2* twl,
+                                     hipStream_t s) {
+    if (!fftconv_ar_fusable(c, n, fdl)) return hipErrorInvalidValue;
+    const int blocks = (n + 1) / 2;
+    if (n_partials) *n_partials = blocks;
+    const size_t lds = lds_bytes(c.M > fdl.n ? c.M : fdl.n, 0);
+    if (c.M == kFixedM2 && fdl.n == kFixedN)
+        hipLaunchKernelGGL((fc_residual_ar_kernel<kFixedM2, kFixedN>), dim3(blocks), dim3(kBlock), lds, s,
+                           (const float2*)c.T, c.M, c.ts, c.fd, c.tw, (p - 1) / 2, n, p - 1, g, partials, Tr, tsr, fdl,
+                           twl);
+    else
+        hipLaunchKernelGGL((fc_residual_ar_kernel<0, 0>), dim3(blocks), dim3(kBlock), lds, s, (const float2*)c.T,
+                           c.M, c.ts, c.fd, c.tw, (p - 1) / 2, n, p - 1, g, partials, Tr, tsr, fdl, twl);
     return hipGetLastError();
 }
 

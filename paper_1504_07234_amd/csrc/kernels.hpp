@@ -196,6 +196,14 @@ hipError_t launch_fc_residual_precond_rows(const FftConv& c, int n, int p, const
 hipError_t launch_precond_rows_fc_fwd(const FftConv& c, int n, int p, const PrecondRows& pr, float* t_out,
                                       hipStream_t s);
 bool fftconv_fusable(const FftConv& c, int n, const PrecondRows& pr);
+// Antireflective model with the antireflective transform: the residual's
+// inverse row pass and the transform's forward row pass in one launch (one
+// observed row pair per workgroup, (n + 1) / 2 partials of ||r||^2); fdl / twl
+// describe the transform's length 2(n - 1), Tr its workspace (row stride tsr).
+bool fftconv_ar_fusable(const FftConv& c, int n, const FftDesc& fdl);
+hipError_t launch_fc_residual_ar_rows(const FftConv& c, int n, int p, const float* g, double* partials,
+                                     int* n_partials, float* Tr, int tsr, const FftDesc& fdl, const float2* twl,
+                                     hipStream_t s);
 
 // ---- framelet -----------------------------------------------------------
 // analysis level with dilation d: bands (+)= B_i B_j v, low (+)= B_0 B_0 v
@@ -301,7 +309,8 @@ int ar_workspace_stride(int n);
 hipError_t launch_ar_rows_fwd(const float* src, int n, float* Tr, int ts, const FftDesc& fd, const float2* tw,
                               hipStream_t s);
 hipError_t launch_ar_cols_filter(float* Tr, int n, int ts, const float* spec, float alpha, const float* lamr,
-                                 const FftDesc& fd, const float2* tw, hipStream_t s);
+                                 const FftDesc& fd, const float2* tw, hipStream_t s, const double* red_in = nullptr,
+                                 int red_count = 0, double* red_out = nullptr);  // red_*: see fft_cols
 hipError_t launch_ar_rows_inv(const float* Tr, int n, int ts, float* dst, const FftDesc& fd, const float2* tw,
                               hipStream_t s, int accum = 0);
 // place the PSF in the top-left corner of a zeroed n x n image

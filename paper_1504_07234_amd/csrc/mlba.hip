@@ -168,6 +168,13 @@ bool fused_fft_path(const mlba_plan_s* P) {
            fftconv_fusable(P->fc, P->n, precond_rows(P));
 }
 
+// FFT blur of the antireflective model with the antireflective transform: the
+// residual's inverse row pass runs with the transform's forward row pass.
+bool fused_ar_path(const mlba_plan_s* P) {
+    return P->blur_fft && P->bc == MLBA_BC_ANTIREFLECT && P->precond == MLBA_PRECOND_AR &&
+           fftconv_ar_fusable(P->fc, P->n, P->fd);
+}
+
 // r = g - A u with its partials and the preconditioner's forward row pass of r
 int do_blur_residual_precond_rows(mlba_plan_s* P, const float* u, const float* g, int* nparts, hipStream_t s) {
     const int n = P->n, p = P->p, N = n + p - 1;
@@ -993,6 +1000,7 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
         ~ProfGuard() { P->prof_cur = -1; }
     } prof_guard{P};
     const bool fused = !alg4 && !alg2 && fused_fft_path(P);
+    const bool fused_ar = !alg4 && !alg2 && fused_ar_path(P);
     for (int i = 0; i < iters; ++i) {
         if (i - ring_base >= P->rn_cap) {
             if (track) STCHK(drain(i));
@@ -1030,6 +1038,38 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
             // P's inverse row pass runs with A^T's forward one
             STCHK(do_precond_rows_blurT(P, implicit ? z : P->w, implicit ? 1 : 0, s));
             if (!implicit) STCHK(do_analysis(P, P->w, z, true, s));
+            P->prof_cur = -1;
+            done = i + 1;
+            continue;
+        }
+        if (fused_ar) {
+            // r = g - A u on the grid; its inverse row pass also runs the
+            // transform's forward row pass, and the transform's column pass
+            // sums the residual partials
+            const int n = P->n, p = P->p, m = n + p - 1;
+            float* Tr = (float*)P->swork;
+            HIPCHK(launch_fc_rows_fwd(P->fc, P->u, n, P->c, 0, m, s, 1));
+            MARK(BLUR, FC_ROWS_FWD);
+            HIPCHK(launch_fc_cols(P->fc, 0, 0, m, 0, nullptr, s, p - 1, p - 1 + n + (n & 1)));
+            MARK(BLUR, FC_COLS);
+            HIPCHK(launch_fc_residual_ar_rows(P->fc, n, p, g, P->partials, &np, Tr, P->ts, P->fd, P->tw, s));
+            MARK(BLUR, FC_RESIDUAL_PRECOND_ROWS);
+            HIPCHK(launch_ar_cols_filter(Tr, n, P->ts, P->spec, (float)alpha[i], nullptr, P->fd, P->tw, s,
+                                         P->partials, np, P->rn + (i - ring_base)));
+            MARK(PRECOND, FFT_COLS);
+            STCHK(check_stop(&hit));
+            if (hit) {
+                stopped = true;
+                break;
+            }
+            HIPCHK(launch_ar_rows_inv(Tr, n, P->ts, P->t, P->fd, P->tw, s));
+            MARK(PRECOND, FFT_ROWS_INV);
+            if (implicit) {
+                STCHK(do_blurT_acc(P, P->t, z, s));
+            } else {
+                STCHK(do_blurT(P, P->t, P->w, s));
+                STCHK(do_analysis(P, P->w, z, true, s));
+            }
             P->prof_cur = -1;
             done = i + 1;
             continue;

@@ -279,8 +279,9 @@ def test_example4_shape(mlba, blur):
 @pytest.mark.parametrize("implicit", [False, True])
 @pytest.mark.parametrize("pc", [opc.AR, opc.BCCB])
 def test_mlba_antireflective_fft_blur(mlba, pc, implicit):
-    """Whole runs with A and A' on the FFT grid (no fused row passes for this
-    model) against the oracle."""
+    """Whole runs with A and A' on the FFT grid against the oracle; with the
+    antireflective transform the residual's inverse row pass runs with the
+    transform's forward row pass (kernel counts of the profiled run)."""
     n, p, L, iters = (97, 31, 2, 30) if pc == opc.AR else (96, 25, 2, 30)
     alpha = 0.02 if pc == opc.AR else 0.37
     announce(f"MLBA antireflective FFT blur n={n} p={p} pc={pc} implicit={implicit}")
@@ -289,8 +290,15 @@ def test_mlba_antireflective_fft_blur(mlba, pc, implicit):
     ref = omlba.mlba(g, H, AR_BC, pc, L, np.full(iters, alpha), np.full(iters + 1, delta), 1e-3, iters)
     with mlba.Plan(n, p, mlba.ANTIREFLECT, pc, L, cuda(H)) as plan:
         plan.set_blur(mlba.BLUR_FFT)
+        plan.profile_begin(iters)
         f, info = plan.restore(cuda(g), alpha=alpha, mu=1e-3, delta=delta, iters=iters, implicit=implicit)
+        plan.profile_end()
+        kern = plan.profile_kernels()
         f = host(f)
+    fused = pc == opc.AR
+    assert kern.get("fc_residual_precond_rows", (0, 0))[1] == (iters if fused else 0)
+    assert kern.get("fc_rows_inv", (0, 0))[1] == (1 if fused else 2) * iters
+    assert kern.get("reduce", (0, 0))[1] == (0 if fused else iters)
     e = rel_err(f, ref["f"])
     print(f"  image {e:.2e} rnorm {rel_err(info.rnorm, ref['rnorm']):.2e}", flush=True)
     assert e < 1e-4
