@@ -52,7 +52,7 @@ TRAFFIC = {
     # the direct A^T accumulating into omega (p = 31), one launch per iteration
     ("conv_blur_t", "direct-implicit"): {
         "fetch_kib": 17582.1, "write_kib": 16878.0, "fetch_scale": 2.0, "write_scale": 1.0, "launches": 1,
-        "sources_sha256": "fca4913313f0458db47a0f57d873789bf9eaaa77c44d52002f03c131abdef323"},
+        "sources_sha256": "cfc1812608661acbef5070cd3eafda822ea578fa454b70c552a50152a2aa7c17"},
 }
 # the sources that define each kernel's device code
 TRAFFIC_SOURCES = {
