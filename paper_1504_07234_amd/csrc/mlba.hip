@@ -1000,7 +1000,7 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
         ~ProfGuard() { P->prof_cur = -1; }
     } prof_guard{P};
     const bool fused = !alg4 && !alg2 && fused_fft_path(P);
-    const bool fused_ar = !alg4 && !alg2 && fused_ar_path(P);
+    const bool fused_ar = !ns && !alg2 && fused_ar_path(P);  // MLBA or Algorithm 4
     for (int i = 0; i < iters; ++i) {
         if (i - ring_base >= P->rn_cap) {
             if (track) STCHK(drain(i));
@@ -1054,13 +1054,23 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
             MARK(BLUR, FC_COLS);
             HIPCHK(launch_fc_residual_ar_rows(P->fc, n, p, g, P->partials, &np, Tr, P->ts, P->fd, P->tw, s));
             MARK(BLUR, FC_RESIDUAL_PRECOND_ROWS);
-            HIPCHK(launch_ar_cols_filter(Tr, n, P->ts, P->spec, (float)alpha[i], nullptr, P->fd, P->tw, s,
-                                         P->partials, np, P->rn + (i - ring_base)));
+            // Algorithm 4: the filter carries lambda (Q' (Q Q' + alpha I)^{-1}) and
+            // the direction goes straight into the state, no A' product
+            HIPCHK(launch_ar_cols_filter(Tr, n, P->ts, P->spec, (float)alpha[i], alg4 ? P->lamr : nullptr, P->fd,
+                                         P->tw, s, P->partials, np, P->rn + (i - ring_base)));
             MARK(PRECOND, FFT_COLS);
             STCHK(check_stop(&hit));
             if (hit) {
                 stopped = true;
                 break;
+            }
+            if (alg4) {
+                HIPCHK(launch_ar_rows_inv(Tr, n, P->ts, implicit ? z : P->t, P->fd, P->tw, s, implicit ? 1 : 0));
+                MARK(PRECOND, FFT_ROWS_INV);
+                if (!implicit) STCHK(do_analysis(P, P->t, z, true, s));
+                P->prof_cur = -1;
+                done = i + 1;
+                continue;
             }
             HIPCHK(launch_ar_rows_inv(Tr, n, P->ts, P->t, P->fd, P->tw, s));
             MARK(PRECOND, FFT_ROWS_INV);

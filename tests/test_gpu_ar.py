@@ -325,6 +325,32 @@ def test_alg4_antireflective_against_oracle(mlba, n, p, pc, sym, implicit):
     assert rel_err(info.rnorm, ref["rnorm"]) < 1e-4
 
 
+@pytest.mark.parametrize("implicit", [False, True])
+def test_alg4_antireflective_fft_grid(mlba, implicit):
+    """Alg-BC4 with A on the FFT grid: the residual's inverse row pass fused
+    with the transform's forward row pass, the direction
+    Q'(Q Q' + alpha I)^{-1} r added straight into the state."""
+    n, p, L, alpha, iters = 97, 25, 2, 0.03, 30
+    announce(f"Alg4 antireflective FFT grid implicit={implicit}")
+    g, H = _problem(n, p, True, 95)
+    mu = np.linspace(1e-3, 2e-3, 8 * L + 1)
+    ref = oa4.alg4(g, H, AR_BC, opc.AR, L, np.full(iters, alpha), np.ones(iters + 1), mu, iters)
+    with mlba.Plan(n, p, mlba.ANTIREFLECT, mlba.AR, L, cuda(H)) as plan:
+        plan.set_blur(mlba.BLUR_FFT)
+        plan.profile_begin(iters)
+        f, info = plan.restore(cuda(g), alpha=alpha, mu=mu, delta=1.0, iters=iters, method=mlba.ALG4,
+                               implicit=implicit)
+        plan.profile_end()
+        kern = plan.profile_kernels()
+        f = host(f)
+    assert kern["fc_residual_precond_rows"][1] == iters and "reduce" not in kern
+    assert kern.get("fc_rows_inv", (0, 0))[1] == 0  # no A' product
+    e = rel_err(f, ref["f"])
+    print(f"  image {e:.2e}", flush=True)
+    assert e < 1e-4
+    assert rel_err(info.rnorm, ref["rnorm"]) < 1e-4
+
+
 def test_alg2_antireflective_against_oracle(mlba):
     """Alg-BC2 of Example 3: CG on A A' + alpha I preconditioned by the BCCB
     matrix, A' the reblur (the paper runs it although A A' is not symmetric);
