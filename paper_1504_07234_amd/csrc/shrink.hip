@@ -114,13 +114,18 @@ struct SsTile {
     static constexpr int BR = TY + 2 * D;      // band rows: y0-D .. y0+TY+D-1
     static constexpr int LW = kBlock + 2 * D;  // low-pass columns: x0-2D .. x0+kBlock-1
     static constexpr int LOW_FLOATS = HR * LW;
-    static constexpr int YS_FLOATS = 3 * TY * kBlock;
+    static constexpr int YS_FLOATS = 2 * TY * kBlock;
     static constexpr int LDS_FLOATS = LOW_FLOATS > YS_FLOATS ? LOW_FLOATS : YS_FLOATS;
 };
 
 // The low-pass tile is staged in LDS once (coalesced rows, reflected
 // indices); each thread then filters its extended column from LDS.  The LDS
-// is reused for the three x-synthesis inputs after the last x-filter.
+// is reused for the x-synthesis after the last x-filter.  With y_i the
+// y-synthesised input of x-filter i at a column, the three x-synthesis
+// transposes sum to
+//   out(x) = 2 (y_0 + y_2)(x) + (y_0 - y_2 + y_1)(x - d) + (y_0 - y_2 - y_1)(x + d),
+// so each thread keeps the first term and passes only the two neighbour
+// terms through LDS.
 //
 // Arithmetic: the masks are applied unnormalised, b0 = [1 2 1] / 4,
 // b1 = [-1 0 1] sqrt(2)/4, b2 = [-1 2 -1] / 4, i.e. b_i = c_i m_i with
@@ -153,24 +158,39 @@ __device__ __forceinline__ void shrink_synthesis_tile(const float* __restrict__ 
     size_t rowo[HR];
 #pragma unroll
     for (int q = 0; q < HR; ++q) rowo[q] = (size_t)reflect_index(y0 - 2 * D + q, N) * N;
+    // tile columns 0 .. kBlock-1: one per thread; the 2D columns beyond them
+    // (HR x 2D values) spread over the threads, loaded in the same batch
+    constexpr int HALO = HR * 2 * D;
+    constexpr int HPT = (HALO + kBlock - 1) / kBlock;
+    float v[HR], hv[HPT];
+    int hslot[HPT];
+    {
+        const int col = reflect_index(x0 - 2 * D + c, N);
 #pragma unroll
-    for (int k0 = 0; k0 < LW; k0 += kBlock) {
-        const int k = k0 + c;
-        if (k0 + kBlock <= LW || k < LW) {
-            const int col = reflect_index(x0 - 2 * D + k, N);
-            float v[HR];
+        for (int q = 0; q < HR; ++q) v[q] = low[rowo[q] + col];
 #pragma unroll
-            for (int q = 0; q < HR; ++q) v[q] = low[rowo[q] + col];
-#pragma unroll
-            for (int q = 0; q < HR; ++q) L[q * LW + k] = v[q];
+        for (int h = 0; h < HPT; ++h) {
+            const int e = h * kBlock + c;
+            hslot[h] = -1;
+            if (HALO % kBlock == 0 || e < HALO) {
+                const int q = e / (2 * D), k = kBlock + e % (2 * D);
+                hslot[h] = q * LW + k;
+                hv[h] = low[(size_t)reflect_index(y0 - 2 * D + q, N) * N + reflect_index(x0 - 2 * D + k, N)];
+            }
         }
     }
+    // the level above's output at this column (read by the first filter pass)
     float sc[BR];
     if constexpr (SIN) {
         const int xm = reflect_index(xe, N);
 #pragma unroll
         for (int q = 0; q < BR; ++q) sc[q] = s_in[rowo[q + D] + xm];
     }
+#pragma unroll
+    for (int q = 0; q < HR; ++q) L[q * LW + c] = v[q];
+#pragma unroll
+    for (int h = 0; h < HPT; ++h)
+        if (hslot[h] >= 0) L[hslot[h]] = hv[h];
     __syncthreads();
 
     float acc[3][TY];
@@ -223,11 +243,15 @@ __device__ __forceinline__ void shrink_synthesis_tile(const float* __restrict__ 
         }
     }
     __syncthreads();  // the low-pass tile is no longer read
-    float* ys = lds;  // [3][TY][kBlock]
+    float* ys = lds;  // [2][TY][kBlock]: the terms read from x + d, from x - d
+    float mid[TY];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int r = 0; r < TY; ++r) ys[(i * TY + r) * kBlock + c] = acc[i][r];
+    for (int r = 0; r < TY; ++r) {
+        const float dlt = acc[0][r] - acc[2][r];
+        ys[r * kBlock + c] = dlt + acc[1][r];
+        ys[(TY + r) * kBlock + c] = dlt - acc[1][r];
+        mid[r] = acc[0][r] + acc[2][r];
+    }
     __syncthreads();
 
     if (c < D || c >= kBlock - D) return;
@@ -237,13 +261,7 @@ __device__ __forceinline__ void shrink_synthesis_tile(const float* __restrict__ 
     for (int r = 0; r < TY; ++r) {
         const int y = y0 + r;
         if (y >= N) break;
-        const float* y0r = ys + (0 * TY + r) * kBlock;
-        const float* y1r = ys + (1 * TY + r) * kBlock;
-        const float* y2r = ys + (2 * TY + r) * kBlock;
-        float sum = fmaf(2.0f, y0r[c], y0r[c + D] + y0r[c - D]);
-        sum += y1r[c - D] - y1r[c + D];
-        sum += fmaf(2.0f, y2r[c], -(y2r[c + D] + y2r[c - D]));
-        out[(size_t)y * N + x] = sum;
+        out[(size_t)y * N + x] = fmaf(2.0f, mid[r], ys[r * kBlock + c - D] + ys[(TY + r) * kBlock + c + D]);
     }
 }
 
