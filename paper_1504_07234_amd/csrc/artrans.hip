@@ -52,8 +52,7 @@ __global__ __launch_bounds__(kBlock) void ar_cols_filter_kernel(float* __restric
     __shared__ float2 lin[2 * kArMaxBatch];
     if (red_out && blockIdx.x == 0) {
         __shared__ double red[kBlock / 64];
-        double acc = 0.0;
-        for (int i = threadIdx.x; i < red_count; i += kBlock) acc += red_in[i];
+        const double acc = strided_sum(red_in, red_count);
         const double t = block_sum(acc, red);
         if (threadIdx.x == 0) *red_out = t;
     }

@@ -24,6 +24,8 @@ __device__ __forceinline__ float ar_odd_detrended(At at, int k, int N, float inv
 }
 
 // G row pairs per workgroup -> Tr[j][y] (row stride ts >= n + 1, j = 0..N)
+// NT > 0 (here and in the two bodies below): L == NT with one sequence pair
+// per workgroup (G == CP == 1), the compiled fixed-size transform.
 template <int NT>
 __device__ __forceinline__ void ar_rows_fwd_body(const float* __restrict__ src, int n, float* __restrict__ Tr,
                                                  int ts, const FftDesc& fd, const float2* __restrict__ tw, int G,
@@ -31,18 +33,21 @@ __device__ __forceinline__ void ar_rows_fwd_body(const float* __restrict__ src, 
     const int N = n - 1, L = 2 * N;
     const float invN = 1.0f / (float)N;
     const int row0 = blk * 2 * G;
-    for (int idx = threadIdx.x; idx < G * L; idx += kBlock) {
-        const int g = idx / L;
-        const int k = idx - g * L;
-        const int ya = row0 + 2 * g;
-        float2 v = make_float2(0.0f, 0.0f);
-        if (ya < n) {
-            const float* ra = src + (size_t)ya * n;
-            v.x = ar_odd_detrended([&](int q) { return ra[q]; }, k, N, invN);
-            if (ya + 1 < n) v.y = ar_odd_detrended([&](int q) { return ra[n + q]; }, k, N, invN);
-        }
-        buf[lds_slot(idx)] = v;
-    }
+    strided_copy<NT, float2>(
+        G * L,
+        [&](int idx) {
+            const int g = idx / L;
+            const int k = idx - g * L;
+            const int ya = row0 + 2 * g;
+            float2 v = make_float2(0.0f, 0.0f);
+            if (ya < n) {
+                const float* ra = src + (size_t)ya * n;
+                v.x = ar_odd_detrended([&](int q) { return ra[q]; }, k, N, invN);
+                if (ya + 1 < n) v.y = ar_odd_detrended([&](int q) { return ra[n + q]; }, k, N, invN);
+            }
+            return v;
+        },
+        [&](int idx, float2 v) { buf[lds_slot(idx)] = v; });
     __syncthreads();
     lds_fft_any<-1, NT>(buf, fd, G, seq_shift, tw);
     for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
@@ -76,16 +81,19 @@ __device__ __forceinline__ void ar_cols_filter_body(float* __restrict__ Tr, int 
     const int pairs = (n + 1) / 2;
     const int p0 = blk * CP;
     const int cp = min(CP, pairs - p0);
-    for (int idx = threadIdx.x; idx < cp * L; idx += kBlock) {
-        const int q = idx / L;
-        const int k = idx - q * L;
-        const int ja = 2 * (p0 + q);
-        const float* ra = Tr + (size_t)ja * ts;
-        float2 v;
-        v.x = ar_odd_detrended([&](int i) { return ra[i]; }, k, N, invN);
-        v.y = ja + 1 < n ? ar_odd_detrended([&](int i) { return ra[ts + i]; }, k, N, invN) : 0.0f;
-        buf[lds_slot(idx)] = v;
-    }
+    strided_copy<NT, float2>(
+        cp * L,
+        [&](int idx) {
+            const int q = idx / L;
+            const int k = idx - q * L;
+            const int ja = 2 * (p0 + q);
+            const float* ra = Tr + (size_t)ja * ts;
+            float2 v;
+            v.x = ar_odd_detrended([&](int i) { return ra[i]; }, k, N, invN);
+            v.y = ja + 1 < n ? ar_odd_detrended([&](int i) { return ra[ts + i]; }, k, N, invN) : 0.0f;
+            return v;
+        },
+        [&](int idx, float2 v) { buf[lds_slot(idx)] = v; });
     // the filtered linear coefficients of every sequence
     if (threadIdx.x < 2 * cp) {
         const int q = threadIdx.x >> 1;
@@ -167,38 +175,75 @@ __device__ __forceinline__ void ar_rows_inv_body(const float* __restrict__ Tr, i
     const int N = n - 1, L = 2 * N;
     const float invN = 1.0f / (float)N;
     const int row0 = blk * 2 * G;
-    for (int idx = threadIdx.x; idx < G * L; idx += kBlock) {
-        const int k = idx / G;
-        const int g = idx - k * G;
-        const int ya = row0 + 2 * g;
-        float2 v = make_float2(0.0f, 0.0f);
-        if (ya < n && k != 0 && k != N) {
-            const int kk = k < N ? k : L - k;
-            v = *reinterpret_cast<const float2*>(Tr + (size_t)kk * ts + ya);
-            if (k > N) v = make_float2(-v.x, -v.y);
-        }
-        buf[lds_slot(g * L + k)] = v;
-    }
+    strided_copy<NT, float2>(
+        G * L,
+        [&](int idx) {
+            const int k = idx / G;
+            const int g = idx - k * G;
+            const int ya = row0 + 2 * g;
+            float2 v = make_float2(0.0f, 0.0f);
+            if (ya < n && k != 0 && k != N) {
+                const int kk = k < N ? k : L - k;
+                v = *reinterpret_cast<const float2*>(Tr + (size_t)kk * ts + ya);
+                if (k > N) v = make_float2(-v.x, -v.y);
+            }
+            return v;
+        },
+        [&](int idx, float2 v) {
+            const int k = idx / G;
+            buf[lds_slot((idx - k * G) * L + k)] = v;
+        });
     __syncthreads();
     lds_fft_any<-1, NT>(buf, fd, G, seq_shift, tw);
-    for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
-        const int g = idx / n;
-        const int x = idx - g * n;
+    auto emit = [&](int g, int x, float2 c0, float2 cN, float2 prev) {
         const int ya = row0 + 2 * g;
-        if (ya >= n) continue;
         const float2 X = buf[lds_slot(g * L + x)];
-        const float2 c0 = *reinterpret_cast<const float2*>(Tr + ya);
-        const float2 cN = *reinterpret_cast<const float2*>(Tr + (size_t)N * ts + ya);
         const float t = (float)x * invN;
         const float va = c0.x + (cN.x - c0.x) * t - 0.5f * X.y;
         const float vb = c0.y + (cN.y - c0.y) * t + 0.5f * X.x;
         const size_t oa = (size_t)ya * n + x;
         if (accum) {
-            dst[oa] += va;
-            if (ya + 1 < n) dst[oa + n] += vb;
+            dst[oa] = prev.x + va;
+            if (ya + 1 < n) dst[oa + n] = prev.y + vb;
         } else {
             dst[oa] = va;
             if (ya + 1 < n) dst[oa + n] = vb;
+        }
+    };
+    if constexpr (NT > 0) {
+        // one row pair: its linear coefficients and the accumulated values
+        // loaded as one batch
+        const int ya = row0;
+        if (ya >= n) return;
+        const float2 c0 = *reinterpret_cast<const float2*>(Tr + ya);
+        const float2 cN = *reinterpret_cast<const float2*>(Tr + (size_t)N * ts + ya);
+        strided_copy<NT / 2 + 1, float2>(
+            n,
+            [&](int x) {
+                float2 prev = make_float2(0.0f, 0.0f);
+                if (accum) {
+                    const size_t oa = (size_t)ya * n + x;
+                    prev.x = dst[oa];
+                    if (ya + 1 < n) prev.y = dst[oa + n];
+                }
+                return prev;
+            },
+            [&](int x, float2 prev) { emit(0, x, c0, cN, prev); });
+    } else {
+        for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
+            const int g = idx / n;
+            const int x = idx - g * n;
+            const int ya = row0 + 2 * g;
+            if (ya >= n) continue;
+            const float2 c0 = *reinterpret_cast<const float2*>(Tr + ya);
+            const float2 cN = *reinterpret_cast<const float2*>(Tr + (size_t)N * ts + ya);
+            float2 prev = make_float2(0.0f, 0.0f);
+            if (accum) {
+                const size_t oa = (size_t)ya * n + x;
+                prev.x = dst[oa];
+                if (ya + 1 < n) prev.y = dst[oa + n];
+            }
+            emit(g, x, c0, cN, prev);
         }
     }
 }

@@ -39,12 +39,15 @@ __device__ __forceinline__ void fft_rows_r2c_body(const float* __restrict__ src,
     const int n = NT > 0 ? NT : n_;
     const int G = NT > 0 ? 1 : G_;
     const int row0 = blk * 2 * G;
-    for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
-        const int g = idx / n;
-        const int x = idx - g * n;
-        const size_t ra = (size_t)(row0 + 2 * g) * n;
-        buf[lds_slot(idx)] = make_float2(src[ra + x], src[ra + n + x]);
-    }
+    strided_copy<NT, float2>(
+        G * n,
+        [&](int idx) {
+            const int g = idx / n;
+            const int x = idx - g * n;
+            const size_t ra = (size_t)(row0 + 2 * g) * n;
+            return make_float2(src[ra + x], src[ra + n + x]);
+        },
+        [&](int idx, float2 v) { buf[lds_slot(idx)] = v; });
     __syncthreads();
     lds_fft_any<-1, NT>(buf, fd, G, seq_shift, tw);
     const int half = n / 2 + 1;
@@ -86,9 +89,25 @@ __device__ __forceinline__ void fft_cols_body(float2* __restrict__ T, int n_, in
     const int k0 = blk * CC;
     const int cc = min(CC, half - k0);
     const size_t base = (size_t)k0 * n;  // dense [n/2+1][n] spectrum
-    for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
-        const int q = idx / n;
-        buf[lds_slot(idx)] = T[(size_t)(k0 + q) * ts + (idx - q * n)];
+    strided_copy<NT, float2>(
+        cc * n,
+        [&](int idx) {
+            const int q = idx / n;
+            return T[(size_t)(k0 + q) * ts + (idx - q * n)];
+        },
+        [&](int idx, float2 v) { buf[lds_slot(idx)] = v; });
+    // compiled length, filter modes: the filter's denominators are loaded
+    // with the column, before the transform
+    constexpr int SPER = NT > 0 ? (NT + kBlock - 1) / kBlock : 1;
+    float sreg[SPER];
+    if constexpr (NT > 0) {
+        if (mode == 0 || mode == 4) {
+#pragma unroll
+            for (int k = 0; k < SPER; ++k) {
+                const int e = k * kBlock + (int)threadIdx.x;
+                if (NT % kBlock == 0 || e < NT) sreg[k] = spec[base + e];
+            }
+        }
     }
     __syncthreads();
     if (mode != 4) lds_fft_any<-1, NT>(buf, fd, cc, seq_shift, tw);
@@ -111,10 +130,22 @@ __device__ __forceinline__ void fft_cols_body(float2* __restrict__ T, int n_, in
         return;
     }
     if (alpha_dev) alpha = (float)*alpha_dev;
-    for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
-        float2 v = cscale(buf[lds_slot(idx)], inv / (spec[base + idx] + alpha));
-        if (lamc) v = cmul(v, cconj(lamc[base + idx]));
-        buf[lds_slot(idx)] = v;
+    if constexpr (NT > 0) {
+#pragma unroll
+        for (int k = 0; k < SPER; ++k) {
+            const int idx = k * kBlock + (int)threadIdx.x;
+            if (NT % kBlock == 0 || idx < NT) {
+                float2 v = cscale(buf[lds_slot(idx)], inv / (sreg[k] + alpha));
+                if (lamc) v = cmul(v, cconj(lamc[base + idx]));
+                buf[lds_slot(idx)] = v;
+            }
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
+            float2 v = cscale(buf[lds_slot(idx)], inv / (spec[base + idx] + alpha));
+            if (lamc) v = cmul(v, cconj(lamc[base + idx]));
+            buf[lds_slot(idx)] = v;
+        }
     }
     if (sstore || eacc) {  // reverse sweep of unrolled iterations (same thread owns each slot)
         for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
@@ -162,19 +193,25 @@ __device__ __forceinline__ void fft_rows_c2r_body(const float2* __restrict__ T, 
     const int G = NT > 0 ? 1 : G_;
     const int row0 = blk * 2 * G;
     const int half = n / 2 + 1;
-    for (int idx = threadIdx.x; idx < G * half; idx += kBlock) {
-        const int k = idx / G;
-        const int g = idx - k * G;
-        const float4 q = *reinterpret_cast<const float4*>(T + (size_t)k * ts + row0 + 2 * g);
-        float2 Xa = make_float2(q.x, q.y), Xb = make_float2(q.z, q.w);
-        const bool edge = (k == 0) || (2 * k == n);
-        if (edge) {  // spectra of real rows are real at DC and Nyquist
-            Xa.y = 0.0f;
-            Xb.y = 0.0f;
-        }
-        buf[lds_slot(g * n + k)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);  // Xa + i Xb
-        if (!edge) buf[lds_slot(g * n + n - k)] = make_float2(Xa.x + Xb.y, -Xa.y + Xb.x);  // conj(Xa) + i conj(Xb)
-    }
+    strided_copy<(NT > 0 ? NT / 2 + 1 : 0), float4>(
+        G * half,
+        [&](int idx) {
+            const int k = idx / G;
+            const int g = idx - k * G;
+            return *reinterpret_cast<const float4*>(T + (size_t)k * ts + row0 + 2 * g);
+        },
+        [&](int idx, float4 q) {
+            const int k = idx / G;
+            const int g = idx - k * G;
+            float2 Xa = make_float2(q.x, q.y), Xb = make_float2(q.z, q.w);
+            const bool edge = (k == 0) || (2 * k == n);
+            if (edge) {  // spectra of real rows are real at DC and Nyquist
+                Xa.y = 0.0f;
+                Xb.y = 0.0f;
+            }
+            buf[lds_slot(g * n + k)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);  // Xa + i Xb
+            if (!edge) buf[lds_slot(g * n + n - k)] = make_float2(Xa.x + Xb.y, -Xa.y + Xb.x);  // conj(Xa) + i conj(Xb)
+        });
     __syncthreads();
     lds_fft_any<1, NT>(buf, fd, G, seq_shift, tw);
     for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
@@ -212,12 +249,18 @@ __device__ __forceinline__ void dct_rows_fwd_body(const float* __restrict__ src,
     const int n = NT > 0 ? NT : n_;
     const int G = NT > 0 ? 1 : G_;
     const int row0 = blk * 2 * G;
-    for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
-        const int g = idx / n;
-        const int x = idx - g * n;
-        const size_t ra = (size_t)(row0 + 2 * g) * n;
-        buf[lds_slot(g * n + dct_perm(x, n))] = make_float2(src[ra + x], src[ra + n + x]);
-    }
+    strided_copy<NT, float2>(
+        G * n,
+        [&](int idx) {
+            const int g = idx / n;
+            const int x = idx - g * n;
+            const size_t ra = (size_t)(row0 + 2 * g) * n;
+            return make_float2(src[ra + x], src[ra + n + x]);
+        },
+        [&](int idx, float2 v) {
+            const int g = idx / n;
+            buf[lds_slot(g * n + dct_perm(idx - g * n, n))] = v;
+        });
     __syncthreads();
     lds_fft_any<-1, NT>(buf, fd, G, seq_shift, tw);
     for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
@@ -270,12 +313,18 @@ __device__ __forceinline__ void dct_cols_filter_body(float* __restrict__ Tr, int
             }
         }
     } else {
-        for (int idx = threadIdx.x; idx < total; idx += kBlock) {
-            const int q = idx / n;
-            const int l = idx - q * n;
-            const size_t r1 = (size_t)(2 * (p0 + q)) * ts;
-            buf[lds_slot(q * n + dct_perm(l, n))] = make_float2(Tr[r1 + l], Tr[r1 + ts + l]);
-        }
+        strided_copy<NT, float2>(
+            total,
+            [&](int idx) {
+                const int q = idx / n;
+                const int l = idx - q * n;
+                const size_t r1 = (size_t)(2 * (p0 + q)) * ts;
+                return make_float2(Tr[r1 + l], Tr[r1 + ts + l]);
+            },
+            [&](int idx, float2 v) {
+                const int q = idx / n;
+                buf[lds_slot(q * n + dct_perm(idx - q * n, n))] = v;
+            });
         __syncthreads();
         lds_fft_any<-1, NT>(buf, fd, cp, seq_shift, tw);
 #pragma unroll
@@ -368,11 +417,17 @@ __device__ __forceinline__ void dct_rows_inv_body(const float* __restrict__ Tr, 
     const int G = NT > 0 ? 1 : G_;
     const int row0 = blk * 2 * G;
     const int total = G * n;
-    for (int idx = threadIdx.x; idx < total; idx += kBlock) {
-        const int k = idx / G;
-        const int g = idx - k * G;
-        buf[lds_slot(g * n + k)] = *reinterpret_cast<const float2*>(Tr + (size_t)k * ts + row0 + 2 * g);
-    }
+    strided_copy<NT, float2>(
+        total,
+        [&](int idx) {
+            const int k = idx / G;
+            const int g = idx - k * G;
+            return *reinterpret_cast<const float2*>(Tr + (size_t)k * ts + row0 + 2 * g);
+        },
+        [&](int idx, float2 v) {
+            const int k = idx / G;
+            buf[lds_slot((idx - k * G) * n + k)] = v;
+        });
     __syncthreads();
     float2 keep[FFT_EPT];
 #pragma unroll
@@ -438,8 +493,7 @@ __global__ __launch_bounds__(kBlock) void fft_cols_kernel(float2* __restrict__ T
     extern __shared__ float2 buf[];
     if (red_out && blockIdx.x == 0) {
         __shared__ double red[kBlock / 64];
-        double acc = 0.0;
-        for (int i = threadIdx.x; i < red_count; i += kBlock) acc += red_in[i];
+        const double acc = strided_sum(red_in, red_count);
         const double t = block_sum(acc, red);
         if (threadIdx.x == 0) *red_out = t;
     }

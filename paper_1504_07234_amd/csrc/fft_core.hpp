@@ -26,6 +26,50 @@ __host__ __device__ __forceinline__ int lds_slot(int i) { return i + (i >> 3); }
 __host__ __device__ constexpr int lds_data_slots(int elems) { return elems + elems / 8 + 1; }
 __host__ __device__ constexpr size_t lds_bytes(int elems, int n) { return (size_t)lds_data_slots(elems) * 8 + 0 * n; }
 
+// One strided pass of a workgroup over `count` elements, element
+// e = k * kBlock + threadIdx.x: fetch(e) for every element of the thread
+// first, then put(e, value).  With a compile-time COUNT > 0 the pass is
+// unrolled, so a thread's global loads are all in flight together (one
+// memory round trip instead of one per element); COUNT == 0 takes `count`
+// at run time and keeps the plain loop.
+template <int COUNT, typename V, typename Fetch, typename Put>
+__device__ __forceinline__ void strided_copy(int count, Fetch fetch, Put put) {
+    if constexpr (COUNT > 0) {
+        constexpr int PER = (COUNT + kBlock - 1) / kBlock;
+        V v[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = k * kBlock + (int)threadIdx.x;
+            if (COUNT % kBlock == 0 || e < COUNT) v[k] = fetch(e);
+        }
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = k * kBlock + (int)threadIdx.x;
+            if (COUNT % kBlock == 0 || e < COUNT) put(e, v[k]);
+        }
+    } else {
+        for (int e = threadIdx.x; e < count; e += kBlock) put(e, fetch(e));
+    }
+}
+
+// Sum of p[i] over i = threadIdx.x, threadIdx.x + kBlock, ... < count, added
+// in that order (the order of a plain strided loop); four loads in flight at
+// a time.
+__device__ __forceinline__ double strided_sum(const double* __restrict__ p, int count) {
+    double acc = 0.0;
+    for (int i0 = threadIdx.x; i0 < count; i0 += 4 * kBlock) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * kBlock;
+            v[u] = i < count ? p[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += v[u];
+    }
+    return acc;
+}
+
 template <int DIR>
 __device__ __forceinline__ float2 twiddle(const float2* __restrict__ tw, int q) {
     const float2 w = tw[q];

@@ -65,24 +65,27 @@ __global__ __launch_bounds__(kBlock) void fc_rows_fwd_kernel(const float* __rest
     const int M = NT > 0 ? NT : M_;
     const int G = NT > 0 ? 1 : G_;
     const int pb = pair0 + xcd_block(blockIdx.x, gridDim.x) * G;
-    for (int idx = threadIdx.x; idx < G * M; idx += kBlock) {
-        const int g = idx / M;
-        const int X = idx - g * M;
-        const int Y = 2 * (pb + g);
-        const int x = X - off;
-        float a = 0.0f, b = 0.0f;
-        const int y0 = Y - off, y1 = Y + 1 - off;
-        if (ar) {
-            if (pb + g < pair_end && x >= -off && x < S + off) {
-                if (y0 >= -off && y0 < S + off) a = fetch_ext(src, S, y0, x, EXT_ANTIREFLECT);
-                if (y1 >= -off && y1 < S + off) b = fetch_ext(src, S, y1, x, EXT_ANTIREFLECT);
+    strided_copy<NT, float2>(
+        G * M,
+        [&](int idx) {
+            const int g = idx / M;
+            const int X = idx - g * M;
+            const int Y = 2 * (pb + g);
+            const int x = X - off;
+            float a = 0.0f, b = 0.0f;
+            const int y0 = Y - off, y1 = Y + 1 - off;
+            if (ar) {
+                if (pb + g < pair_end && x >= -off && x < S + off) {
+                    if (y0 >= -off && y0 < S + off) a = fetch_ext(src, S, y0, x, EXT_ANTIREFLECT);
+                    if (y1 >= -off && y1 < S + off) b = fetch_ext(src, S, y1, x, EXT_ANTIREFLECT);
+                }
+            } else if (pb + g < pair_end && x >= 0 && x < S) {
+                if (y0 >= 0 && y0 < S) a = src[(size_t)y0 * S + x];
+                if (y1 >= 0 && y1 < S) b = src[(size_t)y1 * S + x];
             }
-        } else if (pb + g < pair_end && x >= 0 && x < S) {
-            if (y0 >= 0 && y0 < S) a = src[(size_t)y0 * S + x];
-            if (y1 >= 0 && y1 < S) b = src[(size_t)y1 * S + x];
-        }
-        buf[lds_slot(idx)] = make_float2(a, b);
-    }
+            return make_float2(a, b);
+        },
+        [&](int idx, float2 v) { buf[lds_slot(idx)] = v; });
     __syncthreads();
     lds_fft_any<-1, NT, FC_EPT>(buf, fd, G, seq_shift, tw);
     const int half = M / 2 + 1;
@@ -115,22 +118,49 @@ __global__ __launch_bounds__(kBlock) void fc_cols_kernel(float2* __restrict__ T,
     const int half = M / 2 + 1;
     const int k0 = blockIdx.x * CC;
     const int cc = min(CC, half - k0);
-    for (int idx = threadIdx.x; idx < cc * M; idx += kBlock) {
-        const int q = idx / M;
-        const int y = idx - q * M;
-        buf[lds_slot(idx)] = (y >= y_lo && y < y_hi) ? T[(size_t)(k0 + q) * ts + y] : make_float2(0.0f, 0.0f);
+    const size_t base = (size_t)k0 * M;
+    strided_copy<NT, float2>(
+        cc * M,
+        [&](int idx) {
+            const int q = idx / M;
+            const int y = idx - q * M;
+            return (y >= y_lo && y < y_hi) ? T[(size_t)(k0 + q) * ts + y] : make_float2(0.0f, 0.0f);
+        },
+        [&](int idx, float2 v) { buf[lds_slot(idx)] = v; });
+    // compiled length: the PSF spectrum of the column is loaded with the
+    // column, before the transform, and held in registers
+    constexpr int HPER = NT > 0 ? (NT + kBlock - 1) / kBlock : 1;
+    float2 hreg[HPER];
+    if constexpr (NT > 0) {
+        if (mode == 0) {
+#pragma unroll
+            for (int k = 0; k < HPER; ++k) {
+                const int e = k * kBlock + (int)threadIdx.x;
+                if (NT % kBlock == 0 || e < NT) hreg[k] = Hs[base + e];
+            }
+        }
     }
     __syncthreads();
     lds_fft_any<-1, NT, FC_EPT>(buf, fd, cc, seq_shift, tw);
-    const size_t base = (size_t)k0 * M;
     if (mode == 1) {
         for (int idx = threadIdx.x; idx < cc * M; idx += kBlock) cspec[base + idx] = buf[lds_slot(idx)];
         return;
     }
-    for (int idx = threadIdx.x; idx < cc * M; idx += kBlock) {
-        float2 h = Hs[base + idx];
-        if (conj_h) h = cconj(h);
-        buf[lds_slot(idx)] = cscale(cmul(buf[lds_slot(idx)], h), inv);
+    if constexpr (NT > 0) {
+#pragma unroll
+        for (int k = 0; k < HPER; ++k) {
+            const int e = k * kBlock + (int)threadIdx.x;
+            if (NT % kBlock == 0 || e < NT) {
+                const float2 h = conj_h ? cconj(hreg[k]) : hreg[k];
+                buf[lds_slot(e)] = cscale(cmul(buf[lds_slot(e)], h), inv);
+            }
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < cc * M; idx += kBlock) {
+            float2 h = Hs[base + idx];
+            if (conj_h) h = cconj(h);
+            buf[lds_slot(idx)] = cscale(cmul(buf[lds_slot(idx)], h), inv);
+        }
     }
     __syncthreads();
     lds_fft_any<1, NT, FC_EPT>(buf, fd, cc, seq_shift, tw);
@@ -156,47 +186,95 @@ __global__ __launch_bounds__(kBlock) void fc_rows_inv_kernel(const float2* __res
     const int M = NT > 0 ? NT : M_;
     const int G = NT > 0 ? 1 : G_;
     const int pb = pair0 + xcd_block(blockIdx.x, gridDim.x) * G;
+    constexpr int HALF_T = NT > 0 ? NT / 2 + 1 : 0;
     const int half = M / 2 + 1;
-    for (int idx = threadIdx.x; idx < G * half; idx += kBlock) {
-        const int k = idx / G;
-        const int gg = idx - k * G;
-        float2 Xa = make_float2(0.0f, 0.0f), Xb = Xa;
-        if (pb + gg < pair_end) {
-            const float4 q = *reinterpret_cast<const float4*>(T + (size_t)k * ts + 2 * (pb + gg));
-            Xa = make_float2(q.x, q.y);
-            Xb = make_float2(q.z, q.w);
+    strided_copy<HALF_T, float4>(
+        G * half,
+        [&](int idx) {
+            const int k = idx / G;
+            const int gg = idx - k * G;
+            float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (pb + gg < pair_end) q = *reinterpret_cast<const float4*>(T + (size_t)k * ts + 2 * (pb + gg));
+            return q;
+        },
+        [&](int idx, float4 q) {
+            const int k = idx / G;
+            const int gg = idx - k * G;
+            float2 Xa = make_float2(q.x, q.y), Xb = make_float2(q.z, q.w);
+            const bool edge = (k == 0) || (2 * k == M);
+            if (edge) {
+                Xa.y = 0.0f;
+                Xb.y = 0.0f;
+            }
+            buf[lds_slot(gg * M + k)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
+            if (!edge) buf[lds_slot(gg * M + M - k)] = make_float2(Xa.x + Xb.y, -Xa.y + Xb.x);
+        });
+    // compiled length: the epilogue's operand (g or the accumulated dst) is
+    // loaded before the transform, with the spectrum
+    constexpr int XPER = NT > 0 ? (NT + kBlock - 1) / kBlock : 1;
+    float2 pre[XPER];
+    if constexpr (NT > 0) {
+        const float* opnd = g ? g : (accum ? dst : nullptr);
+#pragma unroll
+        for (int k = 0; k < XPER; ++k) {
+            pre[k] = make_float2(0.0f, 0.0f);
+            const int X = k * kBlock + (int)threadIdx.x;
+            const int x = X - ox;
+            if (opnd && (NT % kBlock == 0 || X < NT) && pb < pair_end && x >= 0 && x < D) {
+                const int ya = 2 * pb - oy;
+                if (ya >= 0 && ya < D) pre[k].x = opnd[(size_t)ya * D + x];
+                if (ya + 1 >= 0 && ya + 1 < D) pre[k].y = opnd[(size_t)(ya + 1) * D + x];
+            }
         }
-        const bool edge = (k == 0) || (2 * k == M);
-        if (edge) {
-            Xa.y = 0.0f;
-            Xb.y = 0.0f;
-        }
-        buf[lds_slot(gg * M + k)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
-        if (!edge) buf[lds_slot(gg * M + M - k)] = make_float2(Xa.x + Xb.y, -Xa.y + Xb.x);
     }
     __syncthreads();
     lds_fft_any<1, NT, FC_EPT>(buf, fd, G, seq_shift, tw);
     double ss = 0.0;
-    for (int idx = threadIdx.x; idx < G * M; idx += kBlock) {
-        const int gg = idx / M;
-        const int X = idx - gg * M;
-        if (pb + gg >= pair_end) continue;
-        const int x = X - ox;
-        if (x < 0 || x >= D) continue;
-        const float2 v = buf[lds_slot(idx)];
+    if constexpr (NT > 0) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int y = 2 * (pb + gg) + h - oy;
-            if (y < 0 || y >= D) continue;
-            const size_t o = (size_t)y * D + x;
-            float val = h == 0 ? v.x : v.y;
-            if (g) {
-                val = g[o] - val;
-                ss += (double)val * (double)val;
-            } else if (accum) {
-                val = dst[o] + val;
+        for (int k = 0; k < XPER; ++k) {
+            const int X = k * kBlock + (int)threadIdx.x;
+            const int x = X - ox;
+            if ((NT % kBlock != 0 && X >= NT) || pb >= pair_end || x < 0 || x >= D) continue;
+            const float2 v = buf[lds_slot(X)];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int y = 2 * pb + h - oy;
+                if (y < 0 || y >= D) continue;
+                const size_t o = (size_t)y * D + x;
+                const float p = h == 0 ? pre[k].x : pre[k].y;
+                float val = h == 0 ? v.x : v.y;
+                if (g) {
+                    val = p - val;
+                    ss += (double)val * (double)val;
+                } else if (accum) {
+                    val = p + val;
+                }
+                dst[o] = val;
             }
-            dst[o] = val;
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < G * M; idx += kBlock) {
+            const int gg = idx / M;
+            const int X = idx - gg * M;
+            if (pb + gg >= pair_end) continue;
+            const int x = X - ox;
+            if (x < 0 || x >= D) continue;
+            const float2 v = buf[lds_slot(idx)];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int y = 2 * (pb + gg) + h - oy;
+                if (y < 0 || y >= D) continue;
+                const size_t o = (size_t)y * D + x;
+                float val = h == 0 ? v.x : v.y;
+                if (g) {
+                    val = g[o] - val;
+                    ss += (double)val * (double)val;
+                } else if (accum) {
+                    val = dst[o] + val;
+                }
+                dst[o] = val;
+            }
         }
     }
     if (partials) {
@@ -224,22 +302,35 @@ __global__ __launch_bounds__(kBlock) void fc_residual_precond_kernel(
     const int q = xcd_block(blockIdx.x, gridDim.x);  // observed rows 2q, 2q + 1
     const int pb = pair0 + q;                        // the same rows of the grid
     const int half = M / 2 + 1;
-    for (int k = threadIdx.x; k < half; k += kBlock) {
-        const float4 v = *reinterpret_cast<const float4*>(Tc + (size_t)k * tsc + 2 * pb);
-        float2 Xa = make_float2(v.x, v.y), Xb = make_float2(v.z, v.w);
-        const bool edge = (k == 0) || (2 * k == M);
-        if (edge) {
-            Xa.y = 0.0f;
-            Xb.y = 0.0f;
+    strided_copy<(NTM > 0 ? NTM / 2 + 1 : 0), float4>(
+        half, [&](int k) { return *reinterpret_cast<const float4*>(Tc + (size_t)k * tsc + 2 * pb); },
+        [&](int k, float4 v) {
+            float2 Xa = make_float2(v.x, v.y), Xb = make_float2(v.z, v.w);
+            const bool edge = (k == 0) || (2 * k == M);
+            if (edge) {
+                Xa.y = 0.0f;
+                Xb.y = 0.0f;
+            }
+            buf[lds_slot(k)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
+            if (!edge) buf[lds_slot(M - k)] = make_float2(Xa.x + Xb.y, -Xa.y + Xb.x);
+        });
+    const size_t ra = (size_t)(2 * q) * n;
+    // the observed rows, loaded with the spectrum before the transform
+    float2 gp[FC_EPT];
+#pragma unroll
+    for (int j = 0; j < FC_EPT; ++j) {
+        gp[j] = make_float2(0.0f, 0.0f);
+        const int X = (int)threadIdx.x + j * kBlock;
+        const int x = X - off;
+        if (X < M && x >= 0 && x < n) {
+            gp[j].x = g[ra + x];
+            if (true) gp[j].y = g[ra + n + x];
         }
-        buf[lds_slot(k)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
-        if (!edge) buf[lds_slot(M - k)] = make_float2(Xa.x + Xb.y, -Xa.y + Xb.x);
     }
     __syncthreads();
     lds_fft_any<1, NTM, FC_EPT>(buf, fdm, 1, 8, twm);
     float2 rr[FC_EPT];
     double ss = 0.0;
-    const size_t ra = (size_t)(2 * q) * n;
 #pragma unroll
     for (int j = 0; j < FC_EPT; ++j) {
         rr[j] = make_float2(0.0f, 0.0f);
@@ -247,9 +338,9 @@ __global__ __launch_bounds__(kBlock) void fc_residual_precond_kernel(
         const int x = X - off;
         if (X < M && x >= 0 && x < n) {
             const float2 v = buf[lds_slot(X)];
-            const float a = g[ra + x] - v.x;
+            const float a = gp[j].x - v.x;
             ss += (double)a * (double)a;
-            const float b = g[ra + n + x] - v.y;
+            const float b = gp[j].y - v.y;
             ss += (double)b * (double)b;
             rr[j] = make_float2(a, b);
             if (r_out) {
@@ -303,22 +394,35 @@ __global__ __launch_bounds__(kBlock) void fc_residual_ar_kernel(
     const int pb = pair0 + q;
     const bool has_b = 2 * q + 1 < n;
     const int half = M / 2 + 1;
-    for (int k = threadIdx.x; k < half; k += kBlock) {
-        const float4 v = *reinterpret_cast<const float4*>(Tc + (size_t)k * tsc + 2 * pb);
-        float2 Xa = make_float2(v.x, v.y), Xb = make_float2(v.z, v.w);
-        const bool edge = (k == 0) || (2 * k == M);
-        if (edge) {
-            Xa.y = 0.0f;
-            Xb.y = 0.0f;
+    strided_copy<(NTM > 0 ? NTM / 2 + 1 : 0), float4>(
+        half, [&](int k) { return *reinterpret_cast<const float4*>(Tc + (size_t)k * tsc + 2 * pb); },
+        [&](int k, float4 v) {
+            float2 Xa = make_float2(v.x, v.y), Xb = make_float2(v.z, v.w);
+            const bool edge = (k == 0) || (2 * k == M);
+            if (edge) {
+                Xa.y = 0.0f;
+                Xb.y = 0.0f;
+            }
+            buf[lds_slot(k)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
+            if (!edge) buf[lds_slot(M - k)] = make_float2(Xa.x + Xb.y, -Xa.y + Xb.x);
+        });
+    const size_t ra = (size_t)(2 * q) * n;
+    // the observed rows, loaded with the spectrum before the transform
+    float2 gp[FC_EPT];
+#pragma unroll
+    for (int j = 0; j < FC_EPT; ++j) {
+        gp[j] = make_float2(0.0f, 0.0f);
+        const int X = (int)threadIdx.x + j * kBlock;
+        const int x = X - off;
+        if (X < M && x >= 0 && x < n) {
+            gp[j].x = g[ra + x];
+            if (has_b) gp[j].y = g[ra + n + x];
         }
-        buf[lds_slot(k)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
-        if (!edge) buf[lds_slot(M - k)] = make_float2(Xa.x + Xb.y, -Xa.y + Xb.x);
     }
     __syncthreads();
     lds_fft_any<1, NTM, FC_EPT>(buf, fdm, 1, 8, twm);
     float2 rr[FC_EPT];
     double ss = 0.0;
-    const size_t ra = (size_t)(2 * q) * n;
 #pragma unroll
     for (int j = 0; j < FC_EPT; ++j) {
         rr[j] = make_float2(0.0f, 0.0f);
@@ -326,11 +430,11 @@ __global__ __launch_bounds__(kBlock) void fc_residual_ar_kernel(
         const int x = X - off;
         if (X < M && x >= 0 && x < n) {
             const float2 v = buf[lds_slot(X)];
-            const float a = g[ra + x] - v.x;
+            const float a = gp[j].x - v.x;
             ss += (double)a * (double)a;
             float b = 0.0f;
             if (has_b) {
-                b = g[ra + n + x] - v.y;
+                b = gp[j].y - v.y;
                 ss += (double)b * (double)b;
             }
             rr[j] = make_float2(a, b);
@@ -397,17 +501,18 @@ __global__ __launch_bounds__(kBlock) void precond_fc_blurT_kernel(
     const int n = NTN > 0 ? NTN : n_;
     const int q = xcd_block(blockIdx.x, gridDim.x);
     const int hn = n / 2 + 1;
-    for (int k = threadIdx.x; k < hn; k += kBlock) {
-        const float4 v = *reinterpret_cast<const float4*>(Tp + (size_t)k * tsp + 2 * q);
-        float2 Xa = make_float2(v.x, v.y), Xb = make_float2(v.z, v.w);
-        const bool edge = (k == 0) || (2 * k == n);
-        if (edge) {  // spectra of real rows are real at DC and Nyquist
-            Xa.y = 0.0f;
-            Xb.y = 0.0f;
-        }
-        buf[lds_slot(k)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
-        if (!edge) buf[lds_slot(n - k)] = make_float2(Xa.x + Xb.y, -Xa.y + Xb.x);
-    }
+    strided_copy<(NTN > 0 ? NTN / 2 + 1 : 0), float4>(
+        hn, [&](int k) { return *reinterpret_cast<const float4*>(Tp + (size_t)k * tsp + 2 * q); },
+        [&](int k, float4 v) {
+            float2 Xa = make_float2(v.x, v.y), Xb = make_float2(v.z, v.w);
+            const bool edge = (k == 0) || (2 * k == n);
+            if (edge) {  // spectra of real rows are real at DC and Nyquist
+                Xa.y = 0.0f;
+                Xb.y = 0.0f;
+            }
+            buf[lds_slot(k)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
+            if (!edge) buf[lds_slot(n - k)] = make_float2(Xa.x + Xb.y, -Xa.y + Xb.x);
+        });
     __syncthreads();
     lds_fft_any<1, NTN, FFT_EPT>(buf, fdn, 1, 8, twn);
     if (t_out) {
