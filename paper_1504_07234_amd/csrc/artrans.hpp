@@ -33,6 +33,8 @@ __device__ __forceinline__ void ar_rows_fwd_body(const float* __restrict__ src, 
     const int N = n - 1, L = 2 * N;
     const float invN = 1.0f / (float)N;
     const int row0 = blk * 2 * G;
+    FixedTw<(NT > 0 ? NT : 1)> twp;
+    if constexpr (NT > 0) fixed_tw_load<NT>(tw, twp.w);
     strided_copy<NT, float2>(
         G * L,
         [&](int idx) {
@@ -49,7 +51,7 @@ __device__ __forceinline__ void ar_rows_fwd_body(const float* __restrict__ src, 
         },
         [&](int idx, float2 v) { buf[lds_slot(idx)] = v; });
     __syncthreads();
-    lds_fft_any<-1, NT>(buf, fd, G, seq_shift, tw);
+    lds_fft_any<-1, NT>(buf, fd, G, seq_shift, tw, NT > 0 ? twp.w : nullptr);
     for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
         const int j = idx / G;
         const int g = idx - j * G;
@@ -81,6 +83,8 @@ __device__ __forceinline__ void ar_cols_filter_body(float* __restrict__ Tr, int 
     const int pairs = (n + 1) / 2;
     const int p0 = blk * CP;
     const int cp = min(CP, pairs - p0);
+    FixedTw<(NT > 0 ? NT : 1)> twp;
+    if constexpr (NT > 0) fixed_tw_load<NT>(tw, twp.w);
     strided_copy<NT, float2>(
         cp * L,
         [&](int idx) {
@@ -111,7 +115,7 @@ __device__ __forceinline__ void ar_cols_filter_body(float* __restrict__ Tr, int 
         lin[2 * q + (threadIdx.x & 1)] = c;
     }
     __syncthreads();
-    lds_fft_any<-1, NT>(buf, fd, cp, seq_shift, tw);
+    lds_fft_any<-1, NT>(buf, fd, cp, seq_shift, tw, NT > 0 ? twp.w : nullptr);
 
     // filtered sine coefficients j = 1..N-1, held in registers while the
     // sequence is rebuilt as their odd extension
@@ -153,7 +157,7 @@ __device__ __forceinline__ void ar_cols_filter_body(float* __restrict__ Tr, int 
         buf[lds_slot(q * L + ((threadIdx.x & 1) ? N : 0))] = make_float2(0.0f, 0.0f);
     }
     __syncthreads();
-    lds_fft_any<-1, NT>(buf, fd, cp, seq_shift, tw);
+    lds_fft_any<-1, NT>(buf, fd, cp, seq_shift, tw, NT > 0 ? twp.w : nullptr);
     for (int idx = threadIdx.x; idx < cp * n; idx += kBlock) {
         const int q = idx / n;
         const int k = idx - q * n;
@@ -175,6 +179,8 @@ __device__ __forceinline__ void ar_rows_inv_body(const float* __restrict__ Tr, i
     const int N = n - 1, L = 2 * N;
     const float invN = 1.0f / (float)N;
     const int row0 = blk * 2 * G;
+    FixedTw<(NT > 0 ? NT : 1)> twp;
+    if constexpr (NT > 0) fixed_tw_load<NT>(tw, twp.w);
     strided_copy<NT, float2>(
         G * L,
         [&](int idx) {
@@ -194,7 +200,7 @@ __device__ __forceinline__ void ar_rows_inv_body(const float* __restrict__ Tr, i
             buf[lds_slot((idx - k * G) * L + k)] = v;
         });
     __syncthreads();
-    lds_fft_any<-1, NT>(buf, fd, G, seq_shift, tw);
+    lds_fft_any<-1, NT>(buf, fd, G, seq_shift, tw, NT > 0 ? twp.w : nullptr);
     auto emit = [&](int g, int x, float2 c0, float2 cN, float2 prev) {
         const int ya = row0 + 2 * g;
         const float2 X = buf[lds_slot(g * L + x)];

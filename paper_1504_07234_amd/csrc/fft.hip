@@ -39,6 +39,8 @@ __device__ __forceinline__ void fft_rows_r2c_body(const float* __restrict__ src,
     const int n = NT > 0 ? NT : n_;
     const int G = NT > 0 ? 1 : G_;
     const int row0 = blk * 2 * G;
+    FixedTw<(NT > 0 ? NT : 1)> twp;
+    if constexpr (NT > 0) fixed_tw_load<NT>(tw, twp.w);
     strided_copy<NT, float2>(
         G * n,
         [&](int idx) {
@@ -49,7 +51,7 @@ __device__ __forceinline__ void fft_rows_r2c_body(const float* __restrict__ src,
         },
         [&](int idx, float2 v) { buf[lds_slot(idx)] = v; });
     __syncthreads();
-    lds_fft_any<-1, NT>(buf, fd, G, seq_shift, tw);
+    lds_fft_any<-1, NT>(buf, fd, G, seq_shift, tw, NT > 0 ? twp.w : nullptr);
     const int half = n / 2 + 1;
     for (int idx = threadIdx.x; idx < G * half; idx += kBlock) {
         const int k = idx / G;
@@ -89,6 +91,8 @@ __device__ __forceinline__ void fft_cols_body(float2* __restrict__ T, int n_, in
     const int k0 = blk * CC;
     const int cc = min(CC, half - k0);
     const size_t base = (size_t)k0 * n;  // dense [n/2+1][n] spectrum
+    FixedTw<(NT > 0 ? NT : 1)> twp;
+    if constexpr (NT > 0) fixed_tw_load<NT>(tw, twp.w);
     strided_copy<NT, float2>(
         cc * n,
         [&](int idx) {
@@ -110,7 +114,7 @@ __device__ __forceinline__ void fft_cols_body(float2* __restrict__ T, int n_, in
         }
     }
     __syncthreads();
-    if (mode != 4) lds_fft_any<-1, NT>(buf, fd, cc, seq_shift, tw);
+    if (mode != 4) lds_fft_any<-1, NT>(buf, fd, cc, seq_shift, tw, NT > 0 ? twp.w : nullptr);
     if (mode == 1) {
         for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
             const float2 v = buf[lds_slot(idx)];
@@ -158,7 +162,7 @@ __device__ __forceinline__ void fft_cols_body(float2* __restrict__ T, int n_, in
         }
     }
     __syncthreads();
-    lds_fft_any<1, NT>(buf, fd, cc, seq_shift, tw);
+    lds_fft_any<1, NT>(buf, fd, cc, seq_shift, tw, NT > 0 ? twp.w : nullptr);
     for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
         const int q = idx / n;
         T[(size_t)(k0 + q) * ts + (idx - q * n)] = buf[lds_slot(idx)];
@@ -193,6 +197,8 @@ __device__ __forceinline__ void fft_rows_c2r_body(const float2* __restrict__ T, 
     const int G = NT > 0 ? 1 : G_;
     const int row0 = blk * 2 * G;
     const int half = n / 2 + 1;
+    FixedTw<(NT > 0 ? NT : 1)> twp;
+    if constexpr (NT > 0) fixed_tw_load<NT>(tw, twp.w);
     strided_copy<(NT > 0 ? NT / 2 + 1 : 0), float4>(
         G * half,
         [&](int idx) {
@@ -213,7 +219,7 @@ __device__ __forceinline__ void fft_rows_c2r_body(const float2* __restrict__ T, 
             if (!edge) buf[lds_slot(g * n + n - k)] = make_float2(Xa.x + Xb.y, -Xa.y + Xb.x);  // conj(Xa) + i conj(Xb)
         });
     __syncthreads();
-    lds_fft_any<1, NT>(buf, fd, G, seq_shift, tw);
+    lds_fft_any<1, NT>(buf, fd, G, seq_shift, tw, NT > 0 ? twp.w : nullptr);
     for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
         const int g = idx / n;
         const int x = idx - g * n;
@@ -249,6 +255,8 @@ __device__ __forceinline__ void dct_rows_fwd_body(const float* __restrict__ src,
     const int n = NT > 0 ? NT : n_;
     const int G = NT > 0 ? 1 : G_;
     const int row0 = blk * 2 * G;
+    FixedTw<(NT > 0 ? NT : 1)> twp;
+    if constexpr (NT > 0) fixed_tw_load<NT>(tw, twp.w);
     strided_copy<NT, float2>(
         G * n,
         [&](int idx) {
@@ -262,7 +270,7 @@ __device__ __forceinline__ void dct_rows_fwd_body(const float* __restrict__ src,
             buf[lds_slot(g * n + dct_perm(idx - g * n, n))] = v;
         });
     __syncthreads();
-    lds_fft_any<-1, NT>(buf, fd, G, seq_shift, tw);
+    lds_fft_any<-1, NT>(buf, fd, G, seq_shift, tw, NT > 0 ? twp.w : nullptr);
     for (int idx = threadIdx.x; idx < G * n; idx += kBlock) {
         const int k = idx / G;
         const int g = idx - k * G;
@@ -296,6 +304,8 @@ __device__ __forceinline__ void dct_cols_filter_body(float* __restrict__ Tr, int
     const int p0 = blk * CP;
     const int cp = min(CP, pairs - p0);
     const int total = cp * n;
+    FixedTw<(NT > 0 ? NT : 1)> twp;
+    if constexpr (NT > 0) fixed_tw_load<NT>(tw, twp.w);
     float2 keep[FFT_EPT];
     if (mode == 2) {
         const float a = (float)alpha_dev[0];
@@ -326,7 +336,7 @@ __device__ __forceinline__ void dct_cols_filter_body(float* __restrict__ Tr, int
                 buf[lds_slot(q * n + dct_perm(idx - q * n, n))] = v;
             });
         __syncthreads();
-        lds_fft_any<-1, NT>(buf, fd, cp, seq_shift, tw);
+        lds_fft_any<-1, NT>(buf, fd, cp, seq_shift, tw, NT > 0 ? twp.w : nullptr);
 #pragma unroll
         for (int i = 0; i < FFT_EPT; ++i) {
             const int idx = threadIdx.x + i * kBlock;
@@ -396,7 +406,7 @@ __device__ __forceinline__ void dct_cols_filter_body(float* __restrict__ Tr, int
         if (idx < total) buf[lds_slot(idx)] = keep[i];
     }
     __syncthreads();
-    lds_fft_any<1, NT>(buf, fd, cp, seq_shift, tw);
+    lds_fft_any<1, NT>(buf, fd, cp, seq_shift, tw, NT > 0 ? twp.w : nullptr);
     for (int idx = threadIdx.x; idx < total; idx += kBlock) {
         const int q = idx / n;
         const int l = idx - q * n;
@@ -417,6 +427,8 @@ __device__ __forceinline__ void dct_rows_inv_body(const float* __restrict__ Tr, 
     const int G = NT > 0 ? 1 : G_;
     const int row0 = blk * 2 * G;
     const int total = G * n;
+    FixedTw<(NT > 0 ? NT : 1)> twp;
+    if constexpr (NT > 0) fixed_tw_load<NT>(tw, twp.w);
     strided_copy<NT, float2>(
         total,
         [&](int idx) {
@@ -451,7 +463,7 @@ __device__ __forceinline__ void dct_rows_inv_body(const float* __restrict__ Tr, 
         if (idx < total) buf[lds_slot(idx)] = keep[i];
     }
     __syncthreads();
-    lds_fft_any<1, NT>(buf, fd, G, seq_shift, tw);
+    lds_fft_any<1, NT>(buf, fd, G, seq_shift, tw, NT > 0 ? twp.w : nullptr);
     for (int idx = threadIdx.x; idx < total; idx += kBlock) {
         const int g = idx / n;
         const int x = idx - g * n;

@@ -76,26 +76,43 @@ __device__ __forceinline__ float2 twiddle(const float2* __restrict__ tw, int q) 
     return DIR < 0 ? w : make_float2(w.x, -w.y);
 }
 
-// w[r] = W^(r*e) for r = 1..R-1, W = exp(DIR 2 pi i / n), e = jm * step.
-// Powers 1, 2, 4 come from the table; the others are one product away.
+// Table entries a radix-R butterfly reads: W^e, W^2e, W^4e, W^8e, the first
+// tw_table_loads(R) of them.
+__host__ __device__ constexpr int tw_table_loads(int R) {
+    return R == 16 || R == 9 ? 4 : (R == 8 || R == 5 ? 3 : (R == 4 || R == 3 ? 2 : 1));
+}
+
+// w[r] = W^(r*e) for r = 1..R-1 from the table entries raw[t] = tw[2^t e]
+// (W = exp(DIR 2 pi i / n), e = jm * step).  Powers 1, 2, 4, 8 come from the
+// table; the others are one product away.
 template <int R, int DIR>
-__device__ __forceinline__ void twiddle_powers(const float2* __restrict__ tw, int e, int n, float2* w) {
-    w[1] = twiddle<DIR>(tw, e);
-    if constexpr (R >= 3) w[2] = twiddle<DIR>(tw, 2 * e);
+__device__ __forceinline__ void twiddle_powers_raw(const float2* raw, float2* w) {
+    auto pw = [&](int t) { return DIR < 0 ? raw[t] : make_float2(raw[t].x, -raw[t].y); };
+    w[1] = pw(0);
+    if constexpr (R >= 3) w[2] = pw(1);
     if constexpr (R >= 4) w[3] = cmul(w[1], w[2]);
-    if constexpr (R == 5) w[4] = twiddle<DIR>(tw, 4 * e);
+    if constexpr (R == 5) w[4] = pw(2);
     if constexpr (R >= 8) {
-        w[4] = twiddle<DIR>(tw, 4 * e);
+        w[4] = pw(2);
         w[5] = cmul(w[1], w[4]);
         w[6] = cmul(w[2], w[4]);
         w[7] = cmul(w[3], w[4]);
     }
-    if constexpr (R == 9) w[8] = twiddle<DIR>(tw, 8 * e);
+    if constexpr (R == 9) w[8] = pw(3);
     if constexpr (R == 16) {
-        w[8] = twiddle<DIR>(tw, 8 * e);
+        w[8] = pw(3);
 #pragma unroll
         for (int r = 9; r < 16; ++r) w[r] = cmul(w[r - 8], w[8]);
     }
+}
+
+template <int R, int DIR>
+__device__ __forceinline__ void twiddle_powers(const float2* __restrict__ tw, int e, int n, float2* w) {
+    constexpr int T = tw_table_loads(R);
+    float2 raw[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) raw[t] = tw[e << t];
+    twiddle_powers_raw<R, DIR>(raw, w);
 }
 
 // a * (DIR i)
@@ -353,11 +370,55 @@ __host__ __device__ constexpr FixedPlan fixed_plan(int n) {
     return p;
 }
 
+// Table entries of every stage of the fixed plan of length N, per thread:
+// stage S (NS > 1) holds MAXB x tw_table_loads(R) of them from offset
+// fixed_tw_offset(N, S).
+__host__ __device__ constexpr int fixed_tw_offset(int N, int S) {
+    const FixedPlan P = fixed_plan(N);
+    int off = 0;
+    for (int s = 0; s < S && s < P.nst; ++s)
+        if (P.ns[s] > 1) off += ((N / P.radix[s] + kBlock - 1) / kBlock) * tw_table_loads(P.radix[s]);
+    return off;
+}
+
+template <int N>
+struct FixedTw {
+    static constexpr int kCount = fixed_tw_offset(N, 24);
+    float2 w[kCount > 0 ? kCount : 1];
+};
+
+// Loads the table entries of every stage (one batch, in flight with the
+// pass's data loads); both directions use them (DIR +1 conjugates).
+template <int N, int S = 0>
+__device__ __forceinline__ void fixed_tw_load(const float2* __restrict__ tw, float2* out) {
+    constexpr FixedPlan P = fixed_plan(N);
+    if constexpr (S < P.nst) {
+        constexpr int R = P.radix[S], NS = P.ns[S];
+        if constexpr (NS > 1) {
+            constexpr int nb = N / R, MAXB = (nb + kBlock - 1) / kBlock, T = tw_table_loads(R);
+            constexpr int step = N / (NS * R), off = fixed_tw_offset(N, S);
+#pragma unroll
+            for (int i = 0; i < MAXB; ++i) {
+                const int j = (int)threadIdx.x + i * kBlock;
+                if (nb % kBlock == 0 || j < nb) {
+                    const int e = (j % NS) * step;
+#pragma unroll
+                    for (int t = 0; t < T; ++t) out[off + i * T + t] = tw[e << t];
+                }
+            }
+        }
+        fixed_tw_load<N, S + 1>(tw, out);
+    }
+}
+
+// pre: the stage's slice of fixed_tw_load's output, or null (table reads)
 template <int R, int DIR, int N, int NS>
-__device__ __forceinline__ void stockham_stage_fixed(float2* buf, const float2* __restrict__ tw) {
+__device__ __forceinline__ void stockham_stage_fixed(float2* buf, const float2* __restrict__ tw,
+                                                     const float2* pre) {
     constexpr int nb = N / R;
     constexpr int MAXB = (nb + kBlock - 1) / kBlock;
     constexpr int step = N / (NS * R);
+    constexpr int T = tw_table_loads(R);
     float2 v[MAXB][R];
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
@@ -365,7 +426,10 @@ __device__ __forceinline__ void stockham_stage_fixed(float2* buf, const float2* 
         if (nb % kBlock == 0 || j < nb) {
             const int jm = j % NS;
             float2 w[R];
-            if (jm > 0) twiddle_powers<R, DIR>(tw, jm * step, N, w);
+            if (jm > 0) {
+                if (pre) twiddle_powers_raw<R, DIR>(pre + i * T, w);
+                else twiddle_powers<R, DIR>(tw, jm * step, N, w);
+            }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 float2 x = buf[lds_slot(j + r * nb)];
@@ -390,20 +454,22 @@ __device__ __forceinline__ void stockham_stage_fixed(float2* buf, const float2* 
 }
 
 template <int DIR, int N, int S = 0>
-__device__ __forceinline__ void lds_fft_fixed(float2* buf, const float2* __restrict__ tw) {
+__device__ __forceinline__ void lds_fft_fixed(float2* buf, const float2* __restrict__ tw, const float2* pre) {
     constexpr FixedPlan P = fixed_plan(N);
     if constexpr (S < P.nst) {
-        stockham_stage_fixed<P.radix[S], DIR, N, P.ns[S]>(buf, tw);
-        lds_fft_fixed<DIR, N, S + 1>(buf, tw);
+        constexpr int off = fixed_tw_offset(N, S);
+        stockham_stage_fixed<P.radix[S], DIR, N, P.ns[S]>(buf, tw, pre ? pre + off : nullptr);
+        lds_fft_fixed<DIR, N, S + 1>(buf, tw, pre);
     }
 }
 
-// NT > 0: the fixed transform of length NT (one sequence per workgroup);
-// NT == 0: the run-time plan fd over nseq sequences.
+// NT > 0: the fixed transform of length NT (one sequence per workgroup),
+// with the twiddles of fixed_tw_load in `pre` when given; NT == 0: the
+// run-time plan fd over nseq sequences.
 template <int DIR, int NT, int EPT = FFT_EPT>
 __device__ __forceinline__ void lds_fft_any(float2* buf, const FftDesc& fd, int nseq, int seq_shift,
-                                            const float2* __restrict__ tw) {
-    if constexpr (NT > 0) lds_fft_fixed<DIR, NT>(buf, tw);
+                                            const float2* __restrict__ tw, const float2* pre = nullptr) {
+    if constexpr (NT > 0) lds_fft_fixed<DIR, NT>(buf, tw, pre);
     else lds_fft<DIR, EPT>(buf, fd, nseq, seq_shift, tw);
 }
 

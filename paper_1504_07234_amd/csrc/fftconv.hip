@@ -65,6 +65,8 @@ __global__ __launch_bounds__(kBlock) void fc_rows_fwd_kernel(const float* __rest
     const int M = NT > 0 ? NT : M_;
     const int G = NT > 0 ? 1 : G_;
     const int pb = pair0 + xcd_block(blockIdx.x, gridDim.x) * G;
+    FixedTw<(NT > 0 ? NT : 1)> twp;
+    if constexpr (NT > 0) fixed_tw_load<NT>(tw, twp.w);
     strided_copy<NT, float2>(
         G * M,
         [&](int idx) {
@@ -87,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void fc_rows_fwd_kernel(const float* __rest
         },
         [&](int idx, float2 v) { buf[lds_slot(idx)] = v; });
     __syncthreads();
-    lds_fft_any<-1, NT, FC_EPT>(buf, fd, G, seq_shift, tw);
+    lds_fft_any<-1, NT, FC_EPT>(buf, fd, G, seq_shift, tw, NT > 0 ? twp.w : nullptr);
     const int half = M / 2 + 1;
     for (int idx = threadIdx.x; idx < G * half; idx += kBlock) {
         const int k = idx / G;
@@ -119,6 +121,8 @@ __global__ __launch_bounds__(kBlock) void fc_cols_kernel(float2* __restrict__ T,
     const int k0 = blockIdx.x * CC;
     const int cc = min(CC, half - k0);
     const size_t base = (size_t)k0 * M;
+    FixedTw<(NT > 0 ? NT : 1)> twp;
+    if constexpr (NT > 0) fixed_tw_load<NT>(tw, twp.w);
     strided_copy<NT, float2>(
         cc * M,
         [&](int idx) {
@@ -141,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void fc_cols_kernel(float2* __restrict__ T,
         }
     }
     __syncthreads();
-    lds_fft_any<-1, NT, FC_EPT>(buf, fd, cc, seq_shift, tw);
+    lds_fft_any<-1, NT, FC_EPT>(buf, fd, cc, seq_shift, tw, NT > 0 ? twp.w : nullptr);
     if (mode == 1) {
         for (int idx = threadIdx.x; idx < cc * M; idx += kBlock) cspec[base + idx] = buf[lds_slot(idx)];
         return;
@@ -163,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void fc_cols_kernel(float2* __restrict__ T,
         }
     }
     __syncthreads();
-    lds_fft_any<1, NT, FC_EPT>(buf, fd, cc, seq_shift, tw);
+    lds_fft_any<1, NT, FC_EPT>(buf, fd, cc, seq_shift, tw, NT > 0 ? twp.w : nullptr);
     for (int idx = threadIdx.x; idx < cc * M; idx += kBlock) {
         const int q = idx / M;
         const int y = idx - q * M;
@@ -188,6 +192,8 @@ __global__ __launch_bounds__(kBlock) void fc_rows_inv_kernel(const float2* __res
     const int pb = pair0 + xcd_block(blockIdx.x, gridDim.x) * G;
     constexpr int HALF_T = NT > 0 ? NT / 2 + 1 : 0;
     const int half = M / 2 + 1;
+    FixedTw<(NT > 0 ? NT : 1)> twp;
+    if constexpr (NT > 0) fixed_tw_load<NT>(tw, twp.w);
     strided_copy<HALF_T, float4>(
         G * half,
         [&](int idx) {
@@ -228,7 +234,7 @@ __global__ __launch_bounds__(kBlock) void fc_rows_inv_kernel(const float2* __res
         }
     }
     __syncthreads();
-    lds_fft_any<1, NT, FC_EPT>(buf, fd, G, seq_shift, tw);
+    lds_fft_any<1, NT, FC_EPT>(buf, fd, G, seq_shift, tw, NT > 0 ? twp.w : nullptr);
     double ss = 0.0;
     if constexpr (NT > 0) {
 #pragma unroll
@@ -302,6 +308,8 @@ __global__ __launch_bounds__(kBlock) void fc_residual_precond_kernel(
     const int q = xcd_block(blockIdx.x, gridDim.x);  // observed rows 2q, 2q + 1
     const int pb = pair0 + q;                        // the same rows of the grid
     const int half = M / 2 + 1;
+    FixedTw<(NTM > 0 ? NTM : 1)> twpm;
+    if constexpr (NTM > 0) fixed_tw_load<NTM>(twm, twpm.w);
     strided_copy<(NTM > 0 ? NTM / 2 + 1 : 0), float4>(
         half, [&](int k) { return *reinterpret_cast<const float4*>(Tc + (size_t)k * tsc + 2 * pb); },
         [&](int k, float4 v) {
@@ -328,7 +336,9 @@ __global__ __launch_bounds__(kBlock) void fc_residual_precond_kernel(
         }
     }
     __syncthreads();
-    lds_fft_any<1, NTM, FC_EPT>(buf, fdm, 1, 8, twm);
+    lds_fft_any<1, NTM, FC_EPT>(buf, fdm, 1, 8, twm, NTM > 0 ? twpm.w : nullptr);
+    FixedTw<(NTN > 0 ? NTN : 1)> twpn;
+    if constexpr (NTN > 0) fixed_tw_load<NTN>(twn, twpn.w);
     float2 rr[FC_EPT];
     double ss = 0.0;
 #pragma unroll
@@ -357,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void fc_residual_precond_kernel(
         if (X < M && x >= 0 && x < n) buf[lds_slot(x)] = rr[j];
     }
     __syncthreads();
-    lds_fft_any<-1, NTN, FFT_EPT>(buf, fdn, 1, 8, twn);
+    lds_fft_any<-1, NTN, FFT_EPT>(buf, fdn, 1, 8, twn, NTN > 0 ? twpn.w : nullptr);
     const int hn = n / 2 + 1;
     for (int k = threadIdx.x; k < hn; k += kBlock) {
         const float2 Z = buf[lds_slot(k)];
@@ -394,6 +404,8 @@ __global__ __launch_bounds__(kBlock) void fc_residual_ar_kernel(
     const int pb = pair0 + q;
     const bool has_b = 2 * q + 1 < n;
     const int half = M / 2 + 1;
+    FixedTw<(NTM > 0 ? NTM : 1)> twpm;
+    if constexpr (NTM > 0) fixed_tw_load<NTM>(twm, twpm.w);
     strided_copy<(NTM > 0 ? NTM / 2 + 1 : 0), float4>(
         half, [&](int k) { return *reinterpret_cast<const float4*>(Tc + (size_t)k * tsc + 2 * pb); },
         [&](int k, float4 v) {
@@ -420,7 +432,9 @@ __global__ __launch_bounds__(kBlock) void fc_residual_ar_kernel(
         }
     }
     __syncthreads();
-    lds_fft_any<1, NTM, FC_EPT>(buf, fdm, 1, 8, twm);
+    lds_fft_any<1, NTM, FC_EPT>(buf, fdm, 1, 8, twm, NTM > 0 ? twpm.w : nullptr);
+    FixedTw<(NTL > 0 ? NTL : 1)> twpl;
+    if constexpr (NTL > 0) fixed_tw_load<NTL>(twl, twpl.w);
     float2 rr[FC_EPT];
     double ss = 0.0;
 #pragma unroll
@@ -471,7 +485,7 @@ __global__ __launch_bounds__(kBlock) void fc_residual_ar_kernel(
         if (k < L) buf[lds_slot(k)] = ext[j];
     }
     __syncthreads();
-    lds_fft_any<-1, NTL, FFT_EPT>(buf, fdl, 1, 8, twl);
+    lds_fft_any<-1, NTL, FFT_EPT>(buf, fdl, 1, 8, twl, NTL > 0 ? twpl.w : nullptr);
     for (int jj = threadIdx.x; jj < n; jj += kBlock) {
         float2 c;
         if (jj == 0 || jj == N) {
@@ -501,6 +515,8 @@ __global__ __launch_bounds__(kBlock) void precond_fc_blurT_kernel(
     const int n = NTN > 0 ? NTN : n_;
     const int q = xcd_block(blockIdx.x, gridDim.x);
     const int hn = n / 2 + 1;
+    FixedTw<(NTN > 0 ? NTN : 1)> twpn;
+    if constexpr (NTN > 0) fixed_tw_load<NTN>(twn, twpn.w);
     strided_copy<(NTN > 0 ? NTN / 2 + 1 : 0), float4>(
         hn, [&](int k) { return *reinterpret_cast<const float4*>(Tp + (size_t)k * tsp + 2 * q); },
         [&](int k, float4 v) {
@@ -514,7 +530,7 @@ __global__ __launch_bounds__(kBlock) void precond_fc_blurT_kernel(
             if (!edge) buf[lds_slot(n - k)] = make_float2(Xa.x + Xb.y, -Xa.y + Xb.x);
         });
     __syncthreads();
-    lds_fft_any<1, NTN, FFT_EPT>(buf, fdn, 1, 8, twn);
+    lds_fft_any<1, NTN, FFT_EPT>(buf, fdn, 1, 8, twn, NTN > 0 ? twpn.w : nullptr);
     if (t_out) {
         const size_t ra = (size_t)(2 * q) * n;
         for (int x = threadIdx.x; x < n; x += kBlock) {
@@ -523,6 +539,8 @@ __global__ __launch_bounds__(kBlock) void precond_fc_blurT_kernel(
             t_out[ra + n + x] = v.y;
         }
     }
+    FixedTw<(NTM > 0 ? NTM : 1)> twpm;
+    if constexpr (NTM > 0) fixed_tw_load<NTM>(twm, twpm.w);
     float2 e[FC_EPT];
 #pragma unroll
     for (int j = 0; j < FC_EPT; ++j) {
@@ -537,7 +555,7 @@ __global__ __launch_bounds__(kBlock) void precond_fc_blurT_kernel(
         if (X < M) buf[lds_slot(X)] = e[j];
     }
     __syncthreads();
-    lds_fft_any<-1, NTM, FC_EPT>(buf, fdm, 1, 8, twm);
+    lds_fft_any<-1, NTM, FC_EPT>(buf, fdm, 1, 8, twm, NTM > 0 ? twpm.w : nullptr);
     const int half = M / 2 + 1;
     const int pb = pair0 + q;
     for (int k = threadIdx.x; k < half; k += kBlock) {
