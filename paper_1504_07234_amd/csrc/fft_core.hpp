@@ -31,7 +31,7 @@ __host__ __device__ constexpr size_t lds_bytes(int elems, int n) { return (size_
 // first, then put(e, value).  With a compile-time COUNT > 0 the pass is
 // unrolled, so a thread's global loads are all in flight together (one
 // memory round trip instead of one per element); COUNT == 0 takes `count`
-// at run time and keeps the plain loop.
+// at run time and fetches four elements per round trip.
 template <int COUNT, typename V, typename Fetch, typename Put>
 __device__ __forceinline__ void strided_copy(int count, Fetch fetch, Put put) {
     if constexpr (COUNT > 0) {
@@ -48,7 +48,19 @@ __device__ __forceinline__ void strided_copy(int count, Fetch fetch, Put put) {
             if (COUNT % kBlock == 0 || e < COUNT) put(e, v[k]);
         }
     } else {
-        for (int e = threadIdx.x; e < count; e += kBlock) put(e, fetch(e));
+        for (int e0 = threadIdx.x; e0 < count; e0 += 4 * kBlock) {
+            V v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * kBlock;
+                if (e < count) v[u] = fetch(e);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * kBlock;
+                if (e < count) put(e, v[u]);
+            }
+        }
     }
 }
 
