@@ -168,10 +168,14 @@ int mlba_version(void);
 /* ---- plans ------------------------------------------------------------
  * mlba_plan_create: n observed side, p odd PSF side (1 <= p <= n, p <= 49), bc one of
  * MLBA_BC_*, precond one of MLBA_PRECOND_*, levels in [1, 4] with
- * 2^(levels-1) < N.  The transforms of P need n = 2^a 3^b 5^c, a >= 1,
- * 8 <= n <= 2048 for MLBA_PRECOND_BCCB and MLBA_PRECOND_DCT, and
- * 2(n - 1) = 2^a 3^b 5^c <= 2048 (e.g. n = 65, 97, 226, 257, 1025) and
- * MLBA_BC_ANTIREFLECT for MLBA_PRECOND_AR (MLBA_EUNSUPPORTED otherwise).  psf: device p x p.
+ * 2^(levels-1) < N.  The transforms of P have length L = n (BCCB and DCT:
+ * n even, n >= 8) or L = 2(n - 1) (MLBA_PRECOND_AR, which also needs
+ * MLBA_BC_ANTIREFLECT; n >= 4).  L = 2^a 3^b 5^c runs as mixed-radix
+ * Stockham passes up to L = 2048; any other L runs in Bluestein's chirp
+ * form over the smallest 2^a 3^b 5^c length m >= 2L - 1, which must be at
+ * most 2048 (L <= 1024; e.g. the 196 x 196 field of view of section 6's
+ * third example: n = 196 for BCCB and DCT, L = 390 for the antireflective
+ * transform).  MLBA_EUNSUPPORTED otherwise.  psf: device p x p.
  * Allocates the workspace, copies the PSF and computes the spectrum of
  * (C C^T) or (Q Q^T) on `stream` (section 4.1 / 4.3).  The plan keeps no
  * reference to `psf`.  With MLBA_BC_ANTIREFLECT every A^T below (operators,

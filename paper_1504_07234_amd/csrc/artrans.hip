@@ -23,7 +23,8 @@
 //   2. columns (rows of Tr): T^-1 along y, multiply by 1/(lambda^2 + alpha)
 //      (times lambda for Algorithm 4), T along y, all in LDS;
 //   3. rows: gather transposed, T along x, write the image rows.
-// The transform length 2N must be 2^a 3^b 5^c and at most FFT_MAX_ELEMS.
+// The transform length 2N is any length fft_length_supported accepts
+// (2^a 3^b 5^c up to FFT_MAX_ELEMS, other lengths in the Bluestein form).
 #include "artrans.hpp"
 #include "common.hpp"
 #include "fft_core.hpp"
@@ -84,19 +85,12 @@ static int ar_shift_for(int batch) {
 static int ar_batch(int n) {
     const int L = 2 * (n - 1), pairs = (n + 1) / 2;
     int G = 1;
+    if (!smooth235(L)) return 1;  // Bluestein: one sequence per workgroup
     while (G * 2 <= kArMaxBatch && (G * 2) * L <= FFT_MAX_ELEMS && pairs / (G * 2) >= 256) G *= 2;
     return G;
 }
 
-bool ar_transform_supported(int n) {
-    if (n < 4) return false;
-    int m = 2 * (n - 1);
-    if (m > FFT_MAX_ELEMS) return false;
-    while (m % 2 == 0) m /= 2;
-    while (m % 3 == 0) m /= 3;
-    while (m % 5 == 0) m /= 5;
-    return m == 1;
-}
+bool ar_transform_supported(int n) { return n >= 4 && fft_length_supported(2 * (n - 1)); }
 
 int ar_workspace_stride(int n) { return ((n + 1 + 15) / 16) * 16 + 16; }
 
@@ -106,7 +100,7 @@ hipError_t launch_ar_rows_fwd(const float* src, int n, float* Tr, int ts, const 
                               hipStream_t s) {
     const int G = ar_batch(n), L = 2 * (n - 1), pairs = (n + 1) / 2;
     const dim3 grid((pairs + G - 1) / G);
-    const size_t lds = lds_bytes(G * L, L);
+    const size_t lds = lds_bytes(fft_lds_elems(G * L, L), L);
     if (L == kFixedN && G == 1)
         hipLaunchKernelGGL(ar_rows_fwd_kernel<kFixedN>, grid, dim3(kBlock), lds, s, src, n, Tr, ts, fd, tw, 1,
                            ar_shift_for(1));
@@ -121,7 +115,7 @@ hipError_t launch_ar_cols_filter(float* Tr, int n, int ts, const float* spec, fl
                                  int red_count, double* red_out) {
     const int CP = ar_batch(n), L = 2 * (n - 1), pairs = (n + 1) / 2;
     const dim3 grid((pairs + CP - 1) / CP);
-    const size_t lds = lds_bytes(CP * L, L);
+    const size_t lds = lds_bytes(fft_lds_elems(CP * L, L), L);
     if (L == kFixedN && CP == 1)
         hipLaunchKernelGGL(ar_cols_filter_kernel<kFixedN>, grid, dim3(kBlock), lds, s, Tr, n, ts, spec, alpha, lamr,
                            fd, tw, 1, ar_shift_for(1), red_in, red_count, red_out);
@@ -135,7 +129,7 @@ hipError_t launch_ar_rows_inv(const float* Tr, int n, int ts, float* dst, const 
                               hipStream_t s, int accum) {
     const int G = ar_batch(n), L = 2 * (n - 1), pairs = (n + 1) / 2;
     const dim3 grid((pairs + G - 1) / G);
-    const size_t lds = lds_bytes(G * L, L);
+    const size_t lds = lds_bytes(fft_lds_elems(G * L, L), L);
     if (L == kFixedN && G == 1)
         hipLaunchKernelGGL(ar_rows_inv_kernel<kFixedN>, grid, dim3(kBlock), lds, s, Tr, n, ts, dst, fd, tw, 1,
                            ar_shift_for(1), accum);

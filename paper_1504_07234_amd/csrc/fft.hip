@@ -793,11 +793,13 @@ static int pick_pairs_per_block(int n) {
     // two rows per pair; stay within the LDS budget; keep >= ~512 workgroups
     int target = n >= 2048 ? 2 : 1;
     int G = 1;
+    if (!smooth235(n)) return 1;  // Bluestein: one sequence per workgroup
     while (G * 2 <= target && (G * 2) * n <= FFT_MAX_ELEMS && ((n / 2) % (G * 2)) == 0) G *= 2;
     return G;
 }
 
 static int pick_cols_per_block(int n) {
+    if (!smooth235(n)) return 1;
     int cc = 1;  // largest power of two with cc * n <= min(4096, FFT_MAX_ELEMS)
     while ((cc * 2) * n <= FFT_MAX_ELEMS && (cc * 2) * n <= 4096) cc *= 2;
     return cc;
@@ -805,14 +807,20 @@ static int pick_cols_per_block(int n) {
 
 int fft_rows_batch(int n) { return pick_pairs_per_block(n); }
 
+bool fft_length_supported(int n) {
+    return n >= 1 && (smooth235(n) ? n <= FFT_MAX_ELEMS : bluestein_len(n) <= FFT_MAX_ELEMS);
+}
+
 int fft_rows_batch_at_most(int n, int want) {
     int G = 1;
+    if (!smooth235(n)) return 1;
     while (G * 2 <= want && (G * 2) * n <= FFT_MAX_ELEMS && ((n / 2) % (G * 2)) == 0) G *= 2;
     return G;
 }
 
 int fft_cols_batch_at_most(int n, int want) {
     int cc = 1;
+    if (!smooth235(n)) return 1;
     while (cc * 2 <= want && (cc * 2) * n <= FFT_MAX_ELEMS) cc *= 2;
     return cc;
 }
@@ -904,7 +912,7 @@ hipError_t launch_precond_batched(const BatchImage* imgs, const int* bmap, const
 hipError_t launch_fft_rows_r2c(const float* src, int n, float2* T, int ts, const FftDesc& fd, const float2* tw,
                                hipStream_t s) {
     const int G = pick_pairs_per_block(n);
-    const size_t lds = lds_bytes(G * n, n);
+    const size_t lds = lds_bytes(fft_lds_elems(G * n, n), n);
     if (n == kFixedN && G == 1)
         hipLaunchKernelGGL(fft_rows_r2c_kernel<kFixedN>, dim3(n / 2), dim3(kBlock), lds, s, src, n, T, ts, fd, tw, 1,
                            seq_shift_for(1));
@@ -920,7 +928,7 @@ static hipError_t launch_cols(float2* T, int n, int ts, const float* spec, float
                               double* red_out = nullptr) {
     const int CC = pick_cols_per_block(n);
     const int half = n / 2 + 1;
-    const size_t lds = lds_bytes(CC * n, n);
+    const size_t lds = lds_bytes(fft_lds_elems(CC * n, n), n);
     if (n == kFixedN && CC == 1)
         hipLaunchKernelGGL(fft_cols_kernel<kFixedN>, dim3(half), dim3(kBlock), lds, s, T, n, ts, spec, alpha, inv, fd,
                            tw, 1, mode, power, seq_shift_for(1), lamc, alpha_dev, cspec, red_in, red_count, red_out);
@@ -963,7 +971,7 @@ hipError_t launch_fft_cols_power(const float2* T, int n, int ts, float* spec, co
 hipError_t launch_fft_rows_c2r(const float2* T, int n, int ts, float* dst, const FftDesc& fd, const float2* tw,
                                hipStream_t s, int accum) {
     const int G = pick_pairs_per_block(n);
-    const size_t lds = lds_bytes(G * n, n);
+    const size_t lds = lds_bytes(fft_lds_elems(G * n, n), n);
     if (n == kFixedN && G == 1)
         hipLaunchKernelGGL(fft_rows_c2r_kernel<kFixedN>, dim3(n / 2), dim3(kBlock), lds, s, T, n, ts, dst, fd, tw, 1,
                            seq_shift_for(1), accum);
@@ -976,7 +984,7 @@ hipError_t launch_fft_rows_c2r(const float2* T, int n, int ts, float* dst, const
 hipError_t launch_dct_rows_fwd(const float* src, int n, float* Tr, int ts, const FftDesc& fd, const float2* tw,
                                const float2* dtw, hipStream_t s) {
     const int G = pick_pairs_per_block(n);
-    const size_t lds = lds_bytes(G * n, n);
+    const size_t lds = lds_bytes(fft_lds_elems(G * n, n), n);
     if (n == kFixedN && G == 1)
         hipLaunchKernelGGL(dct_rows_fwd_kernel<kFixedN>, dim3(n / 2), dim3(kBlock), lds, s, src, n, Tr, ts, fd, tw,
                            dtw, 1, seq_shift_for(1));
@@ -991,7 +999,7 @@ static hipError_t launch_dct_cols(float* Tr, int n, int ts, const float* spec, f
                                   const float* lamr, int mode, const double* alpha_dev) {
     int CP = pick_cols_per_block(n);
     const int pairs = n / 2;
-    const size_t lds = lds_bytes(CP * n, n);
+    const size_t lds = lds_bytes(fft_lds_elems(CP * n, n), n);
     if (n == kFixedN && CP == 1)
         hipLaunchKernelGGL(dct_cols_filter_kernel<kFixedN>, dim3(pairs), dim3(kBlock), lds, s, Tr, n, ts, spec, alpha,
                            inv, fd, tw, dtw, 1, seq_shift_for(1), lamr, mode, alpha_dev);
@@ -1021,7 +1029,7 @@ hipError_t launch_dct_cols_filter_inverse(float* Tr, int n, int ts, const float*
 hipError_t launch_dct_rows_inv(const float* Tr, int n, int ts, float* dst, const FftDesc& fd, const float2* tw,
                                const float2* dtw, hipStream_t s, int accum) {
     const int G = pick_pairs_per_block(n);
-    const size_t lds = lds_bytes(G * n, n);
+    const size_t lds = lds_bytes(fft_lds_elems(G * n, n), n);
     if (n == kFixedN && G == 1)
         hipLaunchKernelGGL(dct_rows_inv_kernel<kFixedN>, dim3(n / 2), dim3(kBlock), lds, s, Tr, n, ts, dst, fd, tw,
                            dtw, 1, seq_shift_for(1), accum);

@@ -20,6 +20,29 @@ constexpr int kFixedM = 2304;
 constexpr int kFixedM2 = 1152;  // the FFT-blur grid of ~1K images (unknowns of 1025..1152)
 constexpr int FFT_MAX_ELEMS = FFT_EPT * kBlock;  // complex values per workgroup (16 KB of LDS)
 
+// n = 2^a 3^b 5^c: a Stockham plan of n itself; otherwise the Bluestein form
+// over bluestein_len(n), the smallest such length >= 2n - 1.
+__host__ __device__ constexpr bool smooth235(int n) {
+    if (n < 1) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    while (n % 5 == 0) n /= 5;
+    return n == 1;
+}
+
+__host__ __device__ constexpr int bluestein_len(int n) {
+    int m = 2 * n - 1;
+    while (!smooth235(m)) ++m;
+    return m;
+}
+
+// LDS elements a pass needs for `elems` values of length-n sequences (a
+// Bluestein length transforms in place over m slots, one sequence per
+// workgroup).
+__host__ __device__ constexpr int fft_lds_elems(int elems, int n) {
+    return smooth235(n) ? elems : (elems > bluestein_len(n) ? elems : bluestein_len(n));
+}
+
 // LDS slot of element i: one padding slot after every 8 elements, so that the
 // power-of-two strides of the Stockham writes do not pile onto one bank.
 __host__ __device__ __forceinline__ int lds_slot(int i) { return i + (i >> 3); }
@@ -321,18 +344,76 @@ __device__ __forceinline__ void stockham_stage(float2* buf, int n, int nseq, int
 // complex values per stage, so n <= EPT << seq_shift.  The caller synchronises
 // before the call.
 template <int DIR, int EPT = FFT_EPT>
-__device__ void lds_fft(float2* buf, const FftDesc& fd, int nseq, int seq_shift, const float2* __restrict__ tw) {
+__device__ void lds_stockham(float2* buf, int len, const FftDesc& fd, int nseq, int seq_shift,
+                             const float2* __restrict__ tw) {
     int Ns = 1, ns_shift = 0;
     for (int s = 0; s < fd.nst; ++s) {
         const int R = fd.radix[s];
-        if (R == 8) stockham_stage<8, DIR, EPT>(buf, fd.n, nseq, seq_shift, Ns, ns_shift, tw);
-        else if (R == 4) stockham_stage<4, DIR, EPT>(buf, fd.n, nseq, seq_shift, Ns, ns_shift, tw);
-        else if (R == 2) stockham_stage<2, DIR, EPT>(buf, fd.n, nseq, seq_shift, Ns, ns_shift, tw);
-        else if (R == 3) stockham_stage<3, DIR, EPT>(buf, fd.n, nseq, seq_shift, Ns, ns_shift, tw);
-        else stockham_stage<5, DIR, EPT>(buf, fd.n, nseq, seq_shift, Ns, ns_shift, tw);
+        if (R == 8) stockham_stage<8, DIR, EPT>(buf, len, nseq, seq_shift, Ns, ns_shift, tw);
+        else if (R == 4) stockham_stage<4, DIR, EPT>(buf, len, nseq, seq_shift, Ns, ns_shift, tw);
+        else if (R == 2) stockham_stage<2, DIR, EPT>(buf, len, nseq, seq_shift, Ns, ns_shift, tw);
+        else if (R == 3) stockham_stage<3, DIR, EPT>(buf, len, nseq, seq_shift, Ns, ns_shift, tw);
+        else stockham_stage<5, DIR, EPT>(buf, len, nseq, seq_shift, Ns, ns_shift, tw);
         Ns *= R;
         ns_shift = (R == 3 || R == 5 || ns_shift < 0) ? -1 : ns_shift + (R == 8 ? 3 : (R == 4 ? 2 : 1));
     }
+}
+
+// Length-n DFT of the one sequence in buf[0, n) by Bluestein's identity
+// jk = (j^2 + k^2 - (k - j)^2) / 2:
+//   X_k = c_k sum_j (x_j c_j) conj(c_{k-j}),  c_k = exp(-i pi k^2 / n),
+// the sum a circular convolution of length m >= 2n - 1 done with two m-point
+// transforms and the stored spectrum of conj(c) (scaled by 1/m).  The inverse
+// direction is conj(DFT(conj x)).  buf holds m slots; every thread of the
+// workgroup takes part (m <= FFT_MAX_ELEMS).
+template <int DIR, int EPT = FFT_EPT>
+__device__ void lds_bluestein(float2* buf, const FftDesc& fd, const float2* __restrict__ tw) {
+    constexpr int KE = FFT_MAX_ELEMS / kBlock;
+    const int n = fd.n, m = fd.m;
+    const float2* __restrict__ chirp = tw + m;
+    const float2* __restrict__ bspec = tw + m + n;
+    float2 a[KE];
+#pragma unroll
+    for (int j = 0; j < KE; ++j) {
+        const int k = (int)threadIdx.x + j * kBlock;
+        a[j] = make_float2(0.0f, 0.0f);
+        if (k < n) {
+            float2 x = buf[lds_slot(k)];
+            if (DIR > 0) x.y = -x.y;
+            a[j] = cmul(x, chirp[k]);
+        }
+    }
+    __syncthreads();  // every x read before the zero padding overwrites it
+#pragma unroll
+    for (int j = 0; j < KE; ++j) {
+        const int k = (int)threadIdx.x + j * kBlock;
+        if (k < m) buf[lds_slot(k)] = a[j];
+    }
+    __syncthreads();
+    lds_stockham<-1, EPT>(buf, m, fd, 1, 8, tw);
+#pragma unroll
+    for (int j = 0; j < KE; ++j) {
+        const int k = (int)threadIdx.x + j * kBlock;
+        if (k < m) buf[lds_slot(k)] = cmul(buf[lds_slot(k)], bspec[k]);
+    }
+    __syncthreads();
+    lds_stockham<1, EPT>(buf, m, fd, 1, 8, tw);
+#pragma unroll
+    for (int j = 0; j < KE; ++j) {
+        const int k = (int)threadIdx.x + j * kBlock;
+        if (k < n) {
+            float2 v = cmul(buf[lds_slot(k)], chirp[k]);
+            if (DIR > 0) v.y = -v.y;
+            buf[lds_slot(k)] = v;
+        }
+    }
+    __syncthreads();
+}
+
+template <int DIR, int EPT = FFT_EPT>
+__device__ void lds_fft(float2* buf, const FftDesc& fd, int nseq, int seq_shift, const float2* __restrict__ tw) {
+    if (fd.m > 0) lds_bluestein<DIR, EPT>(buf, fd, tw);  // one sequence per workgroup
+    else lds_stockham<DIR, EPT>(buf, fd.n, fd, nseq, seq_shift, tw);
 }
 
 // ---- fixed-size transforms ------------------------------------------------

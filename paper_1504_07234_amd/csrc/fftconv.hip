@@ -658,7 +658,7 @@ hipError_t launch_fc_residual_precond_rows(const FftConv& c, int n, int p, const
 }
 
 bool fftconv_ar_fusable(const FftConv& c, int n, const FftDesc& fdl) {
-    return c.M <= FC_MAX && fdl.n == 2 * (n - 1) && fdl.n <= FFT_MAX_ELEMS;
+    return c.M <= FC_MAX && fdl.m == 0 && fdl.n == 2 * (n - 1) && fdl.n <= FFT_MAX_ELEMS;
 }
 
 hipError_t launch_fc_residual_ar_rows(const FftConv& c, int n, int p, const float* g, double* partials,
@@ -693,7 +693,7 @@ hipError_t launch_precond_rows_fc_fwd(const FftConv& c, int n, int p, const Prec
 }
 
 bool fftconv_fusable(const FftConv& c, int n, const PrecondRows& pr) {
-    return c.T && n % 2 == 0 && n <= FFT_MAX_ELEMS && pr.T && pr.fd.n == n;
+    return c.T && n % 2 == 0 && n <= FFT_MAX_ELEMS && pr.T && pr.fd.n == n && pr.fd.m == 0;
 }
 
 }  // namespace mlba

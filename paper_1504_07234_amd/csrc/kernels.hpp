@@ -11,10 +11,17 @@
 namespace mlba {
 
 // Mixed-radix plan of a length-n complex FFT (n = 2^a 3^b 5^c).
+// Run-time transform plan of length n.  m == 0: Stockham stages of radix
+// radix[0..nst) over n itself (n = 2^a 3^b 5^c).  m > 0 (any other n): the
+// Bluestein form, a circular convolution of length m >= 2n - 1 (m 5-smooth),
+// and radix[] are the stages of m; the table then holds the m twiddles, the
+// chirp exp(-i pi k^2 / n) (k < n) and the spectrum of the conjugate chirp
+// divided by m (m values), in that order.
 struct FftDesc {
     int n;
     int nst;
     int radix[24];
+    int m;
 };
 
 // Soft-threshold parameters of one framelet level: mu of the low-pass input
@@ -319,6 +326,9 @@ hipError_t launch_pad_psf(const float* psf, int p, float* dst, int n, hipStream_
 hipError_t launch_pad_psf_centred(const float* psf, int p, float* dst, int n, hipStream_t s);
 // transform batching chosen for size n (row pairs / columns per workgroup)
 int fft_rows_batch(int n);
+// a run-time transform of length n fits one workgroup's LDS (directly or in
+// the Bluestein form)
+bool fft_length_supported(int n);
 int fft_cols_batch(int n);
 int fft_seq_shift(int batch);
 // the largest valid batching <= want (a power of two) for size n

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "fft_core.hpp"
 #include "kernels.hpp"
 #include "mlba.h"
 #include "plan.hpp"
@@ -38,17 +39,61 @@ bool factor_235(int n, int* a, int* b, int* c) {
 // 9 stages, as in the compiled plans, measured 3-6 % slower here: with
 // several short sequences per workgroup half the threads idle in them and the
 // larger butterflies cost occupancy.)
+// Any other n takes the Bluestein form over m = bluestein_len(n) (stages of m).
 FftDesc fft_desc(int n) {
     FftDesc d{};
     d.n = n;
     int a = 0, b = 0, c = 0;
-    factor_235(n, &a, &b, &c);
+    if (!factor_235(n, &a, &b, &c)) {
+        d.m = bluestein_len(n);
+        factor_235(d.m, &a, &b, &c);
+    }
     for (; a >= 3; a -= 3) d.radix[d.nst++] = 8;
     if (a == 2) d.radix[d.nst++] = 4;
     if (a == 1) d.radix[d.nst++] = 2;
     for (int i = 0; i < b; ++i) d.radix[d.nst++] = 3;
     for (int i = 0; i < c; ++i) d.radix[d.nst++] = 5;
     return d;
+}
+
+// The device table of a run-time plan: exp(-2 pi i q / len) for q < len
+// (len = n, or m in the Bluestein form), then for the Bluestein form the
+// chirp c_k = exp(-i pi k^2 / n) (k < n) and the m-point DFT of the
+// conjugate chirp wrapped onto the m-circle, divided by m; all in double,
+// rounded once.
+std::vector<float2> fft_table(const FftDesc& d) {
+    const double pi = 3.14159265358979323846;
+    const int len = d.m > 0 ? d.m : d.n;
+    std::vector<float2> t((size_t)len + (d.m > 0 ? (size_t)d.n + d.m : 0));
+    for (int q = 0; q < len; ++q) {
+        const double ang = -2.0 * pi * (double)q / (double)len;
+        t[q] = make_float2((float)cos(ang), (float)sin(ang));
+    }
+    if (d.m > 0) {
+        const int n = d.n, m = d.m;
+        std::vector<double> cr(n), ci(n);
+        for (int k = 0; k < n; ++k) {  // k^2 mod 2n keeps the angle small
+            const long long k2 = ((long long)k * k) % (2LL * n);
+            const double ang = -pi * (double)k2 / (double)n;
+            cr[k] = cos(ang);
+            ci[k] = sin(ang);
+            t[len + k] = make_float2((float)cr[k], (float)ci[k]);
+        }
+        // b_k = conj(c_k) at k and m - k (|k| < n), zero elsewhere
+        for (int q = 0; q < m; ++q) {
+            double sr = 0.0, si = 0.0;
+            for (int k = -(n - 1); k <= n - 1; ++k) {
+                const int kk = k < 0 ? -k : k;
+                const long long e = ((long long)q * ((k + m) % m)) % m;
+                const double ang = -2.0 * pi * (double)e / (double)m;
+                const double wr = cos(ang), wi = sin(ang);
+                sr += cr[kk] * wr + ci[kk] * wi;  // conj(c) * w
+                si += cr[kk] * wi - ci[kk] * wr;
+            }
+            t[len + n + q] = make_float2((float)(sr / m), (float)(si / m));
+        }
+    }
+    return t;
 }
 
 }  // namespace
@@ -579,11 +624,10 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
     if (levels < 1 || levels > 4) return MLBA_EINVAL;
     const int N = bc == MLBA_BC_RECT ? n + p - 1 : n;
     if ((1 << (levels - 1)) >= N) return MLBA_EINVAL;
-    int a2 = 0, b3 = 0, c5 = 0;
     if (precond == MLBA_PRECOND_AR) {  // complex FFTs of length 2(n - 1); Q antireflective like A
         if (bc != MLBA_BC_ANTIREFLECT || !ar_transform_supported(n)) return MLBA_EUNSUPPORTED;
     } else if (precond != MLBA_PRECOND_NONE) {  // row pairs: n even
-        if (!factor_235(n, &a2, &b3, &c5) || a2 < 1 || n < 8 || n > 2048) return MLBA_EUNSUPPORTED;
+        if (n % 2 != 0 || n < 8 || !fft_length_supported(n)) return MLBA_EUNSUPPORTED;
     }
 
     mlba_plan_s* P = new (std::nothrow) mlba_plan_s();
@@ -640,19 +684,16 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
         // the cosine table serves the eigenvalues: angles pi q / n (DCT) or
         // pi q / (n - 1) (antireflective transform); BCCB does not read it
         const int CN = precond == MLBA_PRECOND_AR ? n - 1 : n;
-        std::vector<float2> tw(L), dtw(n);
+        const std::vector<float2> tw = fft_table(P->fd);
+        std::vector<float2> dtw(n);
         std::vector<float> cost(2 * CN);
         const double pi = 3.14159265358979323846;
-        for (int q = 0; q < L; ++q) {
-            const double ang = -2.0 * pi * (double)q / (double)L;
-            tw[q] = make_float2((float)cos(ang), (float)sin(ang));
-        }
         for (int q = 0; q < n; ++q) {
             const double ang2 = -pi * (double)q / (2.0 * (double)n);
             dtw[q] = make_float2((float)cos(ang2), (float)sin(ang2));
         }
         for (int q = 0; q < 2 * CN; ++q) cost[q] = (float)cos(pi * (double)q / (double)CN);
-        ALLOC(P->tw, (size_t)L);
+        ALLOC(P->tw, tw.size());
         ALLOC(P->dtw, (size_t)n);
         ALLOC(P->costab, (size_t)2 * CN);
         ALLOC(P->ns, 8);
@@ -679,7 +720,7 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
             P->swork = Tr;
         }
 #undef ALLOC
-        hipError_t e = hipMemcpyAsync(P->tw, tw.data(), L * sizeof(float2), hipMemcpyHostToDevice, s);
+        hipError_t e = hipMemcpyAsync(P->tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipMemcpyAsync(P->dtw, dtw.data(), n * sizeof(float2), hipMemcpyHostToDevice, s);
         if (e == hipSuccess)
             e = hipMemcpyAsync(P->costab, cost.data(), 2 * CN * sizeof(float), hipMemcpyHostToDevice, s);

@@ -73,9 +73,9 @@ def test_status_strings():
     (64, 9, 0, 5, 1, _lib.EINVAL),        # unknown preconditioner
     (64, 9, 0, 0, 0, _lib.EINVAL),        # no framelet level
     (64, 9, 0, 0, 5, _lib.EINVAL),        # too many levels
-    (70, 9, 0, 0, 1, _lib.EUNSUPPORTED),  # 70 = 2 * 5 * 7: 7 is outside the radix 2/3/5 transforms
+    (1030, 9, 0, 0, 1, _lib.EUNSUPPORTED),  # 1030 = 2 * 5 * 103: its Bluestein length 2160 exceeds one workgroup
     (125, 9, 0, 0, 1, _lib.EUNSUPPORTED),  # odd: the row passes pair rows
-    (196, 9, 4, 3, 1, _lib.EUNSUPPORTED),  # antireflective transform length 390 = 2 * 3 * 5 * 13
+    (600, 9, 4, 3, 1, _lib.EUNSUPPORTED),  # antireflective transform length 1198 = 2 * 599: Bluestein length 2400
     (2049, 9, 4, 3, 1, _lib.EUNSUPPORTED),  # antireflective transform length 4096: beyond one workgroup
     (65, 9, 1, 3, 1, _lib.EUNSUPPORTED),    # the antireflective transform goes with the antireflective model
     (5000, 9, 0, 0, 1, _lib.EUNSUPPORTED),

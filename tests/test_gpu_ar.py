@@ -114,7 +114,9 @@ def test_affine_image_is_blurred_exactly(mlba):
     assert np.abs(Af - f).max() < 2e-6
 
 
-AR_SIZES = [4, 6, 10, 11, 13, 51, 65, 97, 193, 226, 257, 433, 1025]  # transform lengths 2^a 3^b 5^c
+# transform lengths 2^a 3^b 5^c, and (8, 15, 196, 500: lengths 14, 28, 390, 998)
+# the Bluestein form over m = 27, 60, 800, 2000
+AR_SIZES = [4, 6, 8, 10, 11, 13, 15, 51, 65, 97, 193, 196, 226, 257, 433, 500, 1025]
 
 
 @pytest.mark.parametrize("n", AR_SIZES)
@@ -180,11 +182,11 @@ def test_ar_direction(mlba, n):
     assert rel_err(t, ref) < TOL_L2 and max_err(t, ref) < TOL_MAX
 
 
-@pytest.mark.parametrize("n", [196, 2049, 3, 15])
+@pytest.mark.parametrize("n", [600, 2049, 3])
 def test_ar_sizes_outside_the_transform(mlba, n):
-    """2(n - 1) must be 2^a 3^b 5^c and at most 2048 (196, Example 3's
-    observation side, gives 390 = 2 * 3 * 5 * 13; Example 4's 226 is
-    supported)."""
+    """The transform length 2(n - 1) must fit one workgroup: at most 2048 when
+    it is 2^a 3^b 5^c, else its Bluestein length (600: 1198 = 2 * 599 needs
+    2400); n >= 4."""
     from paper_1504_07234_amd import _lib
     announce(f"antireflective transform size n={n}")
     with pytest.raises(_lib.MLBAError) as e:

@@ -223,3 +223,33 @@ def test_tile_choices_do_not_change_results(mlba):
             assert torch.equal(outs[i], ref[i]), ("tuned", i)
     for pl in plans:
         pl.close()
+
+
+@pytest.mark.parametrize("precond", [0, 3])
+def test_batched_bluestein_sizes(mlba, precond):
+    """Images whose transform lengths have a prime factor >= 7 (196 = 2^2 7^2
+    and 70 = 2 * 5 * 7 for the BCCB preconditioner; the antireflective
+    transform lengths 390 and 140 of 196 and 71) batched with 5-smooth ones:
+    equal to the per-image path bit for bit, and one against the oracle."""
+    import torch
+    announce(f"batched Bluestein sizes precond={precond}")
+    specs = [(196, 11), (70, 9), (128, 15)] if precond == 0 else [(196, 9), (71, 7), (65, 9)]
+    bcs = None if precond == 0 else [4, 4, 4]
+    plans, gs, Hs = _make(mlba, specs, levels=2, precond=precond, bcs=bcs)
+    iters = 10
+    alpha, mu, delta = (0.05, 1e-3, 0.2) if precond == 0 else (0.05, 1e-3, 0.1)
+    gdev = [cuda(g) for g in gs]
+    ref = [pl.restore(g, alpha=alpha, mu=mu, delta=delta, iters=iters)[0].clone() for pl, g in zip(plans, gdev)]
+    with mlba.Batch(plans, max_iters=iters) as batch:
+        outs, _ = batch.restore(gdev, alpha=alpha, mu=mu, delta=delta, iters=iters, use_graph=True)
+        torch.cuda.synchronize()
+        for i in range(len(plans)):
+            assert torch.equal(outs[i], ref[i]), i
+        got = host(outs[0])
+    bc = oblur.RECT if precond == 0 else oblur.ANTIREFLECT
+    want = omlba.mlba(gs[0], Hs[0], bc, precond, 2, np.full(iters, alpha), np.full(iters + 1, delta), mu,
+                      iters)["f"]
+    print(f"  image 0 vs oracle {rel_err(got, want):.2e}", flush=True)
+    assert rel_err(got, want) < 1e-4
+    for pl in plans:
+        pl.close()

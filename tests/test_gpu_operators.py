@@ -76,7 +76,9 @@ def test_blur_and_transpose(mlba, bc, n, p, kind):
     assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(Au) * np.linalg.norm(y)
 
 
-@pytest.mark.parametrize("n", [8, 10, 64, 96, 100, 192, 250, 256, 384, 512, 768, 1000, 1024, 2000, 2048])
+# 14, 196, 998 have a prime factor >= 7: Bluestein form over m = 27, 400, 2000
+@pytest.mark.parametrize("n", [8, 10, 14, 64, 96, 100, 192, 196, 250, 256, 384, 512, 768, 998, 1000, 1024, 2000,
+                               2048])
 @pytest.mark.parametrize("pc", [0, 1])
 def test_preconditioner(mlba, n, pc):
     p = 9 if n >= 9 else 3
