@@ -104,6 +104,9 @@ hipError_t launch_ar_rows_fwd(const float* src, int n, float* Tr, int ts, const 
     if (L == kFixedN && G == 1)
         hipLaunchKernelGGL(ar_rows_fwd_kernel<kFixedN>, grid, dim3(kBlock), lds, s, src, n, Tr, ts, fd, tw, 1,
                            ar_shift_for(1));
+    else if (fd.m > 0)
+        hipLaunchKernelGGL(ar_rows_fwd_kernel<kAnyLen>, grid, dim3(kBlock), lds, s, src, n, Tr, ts, fd, tw, G,
+                           ar_shift_for(G));
     else
         hipLaunchKernelGGL(ar_rows_fwd_kernel<0>, grid, dim3(kBlock), lds, s, src, n, Tr, ts, fd, tw, G,
                            ar_shift_for(G));
@@ -119,6 +122,9 @@ hipError_t launch_ar_cols_filter(float* Tr, int n, int ts, const float* spec, fl
     if (L == kFixedN && CP == 1)
         hipLaunchKernelGGL(ar_cols_filter_kernel<kFixedN>, grid, dim3(kBlock), lds, s, Tr, n, ts, spec, alpha, lamr,
                            fd, tw, 1, ar_shift_for(1), red_in, red_count, red_out);
+    else if (fd.m > 0)
+        hipLaunchKernelGGL(ar_cols_filter_kernel<kAnyLen>, grid, dim3(kBlock), lds, s, Tr, n, ts, spec, alpha, lamr, fd,
+                           tw, CP, ar_shift_for(CP), red_in, red_count, red_out);
     else
         hipLaunchKernelGGL(ar_cols_filter_kernel<0>, grid, dim3(kBlock), lds, s, Tr, n, ts, spec, alpha, lamr, fd,
                            tw, CP, ar_shift_for(CP), red_in, red_count, red_out);
@@ -133,6 +139,9 @@ hipError_t launch_ar_rows_inv(const float* Tr, int n, int ts, float* dst, const 
     if (L == kFixedN && G == 1)
         hipLaunchKernelGGL(ar_rows_inv_kernel<kFixedN>, grid, dim3(kBlock), lds, s, Tr, n, ts, dst, fd, tw, 1,
                            ar_shift_for(1), accum);
+    else if (fd.m > 0)
+        hipLaunchKernelGGL(ar_rows_inv_kernel<kAnyLen>, grid, dim3(kBlock), lds, s, Tr, n, ts, dst, fd, tw, G,
+                           ar_shift_for(G), accum);
     else
         hipLaunchKernelGGL(ar_rows_inv_kernel<0>, grid, dim3(kBlock), lds, s, Tr, n, ts, dst, fd, tw, G,
                            ar_shift_for(G), accum);

@@ -33,6 +33,7 @@ struct Map {
 
 struct mlba_batch_s {
     int count = 0, levels = 0, precond = 0, pmax = 1, nmax = 8;
+    int any_len = 0;  // some image's transform takes the Bluestein form
     bool any_reflect = false;
     std::vector<mlba_plan_t> plans;
     std::vector<BatchImage> host;
@@ -167,7 +168,7 @@ int enqueue(mlba_batch_s* B, int iters, bool fill_state, hipStream_t s) {
         if (B->precond != MLBA_PRECOND_NONE)
             for (int pass = 0; pass < 3; ++pass)
                 HIPCHK(launch_precond_batched(I, B->pre[pass].bmap, B->pre[pass].bfirst, B->pre[pass].nblocks, pass,
-                                              B->precond, B->nmax, s));
+                                              B->precond, B->nmax, s, B->any_len));
         HIPCHK(launch_conv_batched(I, B->conv_at.bmap, B->conv_at.bfirst, B->conv_at.nblocks, 0, B->pmax, nullptr,
                                    s, B->conv_ry[1]));
         if (B->any_reflect) HIPCHK(launch_fold_batched(I, B->fold.bmap, B->fold.bfirst, B->fold.nblocks, s));
@@ -243,6 +244,7 @@ int mlba_batch_create(mlba_batch_t* batch, int count, const mlba_plan_t* plans, 
         B->host[i] = plan_desc(plans[i]);
         B->pmax = std::max(B->pmax, plans[i]->p);
         B->nmax = std::max(B->nmax, plans[i]->n);
+        if (plans[i]->fd.m > 0) B->any_len = 1;  // a Bluestein-form transform
         B->any_reflect = B->any_reflect || plans[i]->bc == MLBA_BC_REFLECT;
         pmax_parts += conv_batched_tiles(B->host[i], 1, 1);
     }
@@ -308,7 +310,7 @@ int mlba_batch_autotune(mlba_batch_t B, int reps, mlba_batch_tuning* out, hipStr
             STCHK(time_phase([&]() -> int {
                 for (int pass = 0; pass < 3; pass += 2)
                     HIPCHK(launch_precond_batched(I, B->pre[pass].bmap, B->pre[pass].bfirst, B->pre[pass].nblocks,
-                                                  pass, B->precond, B->nmax, s));
+                                                  pass, B->precond, B->nmax, s, B->any_len));
                 return MLBA_OK;
             }, reps, s, &ms));
             if (out) out->rows_ms[c] = ms;
@@ -328,7 +330,7 @@ int mlba_batch_autotune(mlba_batch_t B, int reps, mlba_batch_tuning* out, hipStr
             double ms = 0.0;
             STCHK(time_phase([&]() -> int {
                 HIPCHK(launch_precond_batched(I, B->pre[1].bmap, B->pre[1].bfirst, B->pre[1].nblocks, 1, B->precond,
-                                              B->nmax, s));
+                                              B->nmax, s, B->any_len));
                 return MLBA_OK;
             }, reps, s, &ms));
             if (out) out->cols_ms[c] = ms;

@@ -171,6 +171,7 @@ __device__ __forceinline__ void fft_cols_body(float2* __restrict__ T, int n_, in
 
 // CC rows of T per workgroup: inverse FFT along the column index of the real
 // dense spectrum e ([n/2+1][n]), written to T.
+template <int NT = 0>
 __device__ __forceinline__ void fft_cols_inverse_real_body(const float* __restrict__ e, float2* __restrict__ T,
                                                            int n, int ts, const FftDesc& fd,
                                                            const float2* __restrict__ tw, int CC, int seq_shift,
@@ -181,7 +182,7 @@ __device__ __forceinline__ void fft_cols_inverse_real_body(const float* __restri
     const size_t base = (size_t)k0 * n;
     for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) buf[lds_slot(idx)] = make_float2(e[base + idx], 0.0f);
     __syncthreads();
-    lds_fft<1>(buf, fd, cc, seq_shift, tw);
+    lds_fft_any<1, NT>(buf, fd, cc, seq_shift, tw);
     for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
         const int q = idx / n;
         T[(size_t)(k0 + q) * ts + (idx - q * n)] = buf[lds_slot(idx)];
@@ -839,7 +840,7 @@ int precond_pass_tiles(const BatchImage& I, int pass) {
     return (I.n / 2 + I.fft_cols_c - 1) / I.fft_cols_c;
 }
 
-template <int PASS, int PRECOND>
+template <int PASS, int PRECOND, int NB>
 __global__ __launch_bounds__(kBlock) void precond_batched_kernel(const BatchImage* __restrict__ imgs,
                                                                  const int* __restrict__ bmap,
                                                                  const int* __restrict__ bfirst) {
@@ -855,40 +856,47 @@ __global__ __launch_bounds__(kBlock) void precond_batched_kernel(const BatchImag
     if constexpr (PRECOND == 3) {  // antireflective transform, one row pair per workgroup
         __shared__ float2 lin[2 * kArMaxBatch];
         float* Tr = (float*)I.swork;
-        if (PASS == 0) ar_rows_fwd_body<0>(I.r, n, Tr, I.ts, I.fd, I.tw, 1, I.fft_rows_shift, blk, buf);
+        if (PASS == 0) ar_rows_fwd_body<NB>(I.r, n, Tr, I.ts, I.fd, I.tw, 1, I.fft_rows_shift, blk, buf);
         if (PASS == 1)
-            ar_cols_filter_body<0>(Tr, n, I.ts, I.spec, I.alpha, nullptr, I.fd, I.tw, 1, I.fft_cols_shift, blk, buf,
+            ar_cols_filter_body<NB>(Tr, n, I.ts, I.spec, I.alpha, nullptr, I.fd, I.tw, 1, I.fft_cols_shift, blk, buf,
                                    lin);
-        if (PASS == 2) ar_rows_inv_body<0>(Tr, n, I.ts, I.t, I.fd, I.tw, 1, I.fft_rows_shift, blk, buf, 0);
+        if (PASS == 2) ar_rows_inv_body<NB>(Tr, n, I.ts, I.t, I.fd, I.tw, 1, I.fft_rows_shift, blk, buf, 0);
         return;
     }
     if (PRECOND == 0) {
         float2* T = (float2*)I.swork;
-        if (PASS == 0) fft_rows_r2c_body(I.r, n, T, I.ts, I.fd, I.tw, I.fft_rows_g, I.fft_rows_shift, blk, buf);
+        if (PASS == 0) fft_rows_r2c_body<NB>(I.r, n, T, I.ts, I.fd, I.tw, I.fft_rows_g, I.fft_rows_shift, blk, buf);
         if (PASS == 1)
-            fft_cols_body(T, n, I.ts, I.spec, I.alpha, inv, I.fd, I.tw, I.fft_cols_c, 0, nullptr, I.fft_cols_shift,
+            fft_cols_body<NB>(T, n, I.ts, I.spec, I.alpha, inv, I.fd, I.tw, I.fft_cols_c, 0, nullptr, I.fft_cols_shift,
                           blk, buf, I.sstore, I.sfwd, I.eacc);
-        if (PASS == 2) fft_rows_c2r_body(T, n, I.ts, I.t, I.fd, I.tw, I.fft_rows_g, I.fft_rows_shift, blk, buf);
+        if (PASS == 2) fft_rows_c2r_body<NB>(T, n, I.ts, I.t, I.fd, I.tw, I.fft_rows_g, I.fft_rows_shift, blk, buf);
         if (PASS == 3)
-            fft_cols_inverse_real_body(I.eacc, T, n, I.ts, I.fd, I.tw, I.fft_cols_c, I.fft_cols_shift, blk, buf);
+            fft_cols_inverse_real_body<NB>(I.eacc, T, n, I.ts, I.fd, I.tw, I.fft_cols_c, I.fft_cols_shift, blk, buf);
     } else {
         float* Tr = (float*)I.swork;
         if (PASS == 0)
-            dct_rows_fwd_body(I.r, n, Tr, I.ts, I.fd, I.tw, I.dtw, I.fft_rows_g, I.fft_rows_shift, blk, buf);
+            dct_rows_fwd_body<NB>(I.r, n, Tr, I.ts, I.fd, I.tw, I.dtw, I.fft_rows_g, I.fft_rows_shift, blk, buf);
         if (PASS == 1)
-            dct_cols_filter_body(Tr, n, I.ts, I.spec, I.alpha, inv, I.fd, I.tw, I.dtw, I.fft_cols_c,
+            dct_cols_filter_body<NB>(Tr, n, I.ts, I.spec, I.alpha, inv, I.fd, I.tw, I.dtw, I.fft_cols_c,
                                  I.fft_cols_shift, blk, buf);
         if (PASS == 2)
-            dct_rows_inv_body(Tr, n, I.ts, I.t, I.fd, I.tw, I.dtw, I.fft_rows_g, I.fft_rows_shift, blk, buf);
+            dct_rows_inv_body<NB>(Tr, n, I.ts, I.t, I.fd, I.tw, I.dtw, I.fft_rows_g, I.fft_rows_shift, blk, buf);
     }
 }
 
 hipError_t launch_precond_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks, int pass,
-                                  int precond, int nmax, hipStream_t s) {
+                                  int precond, int nmax, hipStream_t s, int any_len) {
     if (nblocks <= 0) return hipSuccess;
     const size_t lds = lds_bytes(FFT_MAX_ELEMS, nmax);
-#define MLBA_PB(PA, PC) \
-    hipLaunchKernelGGL((precond_batched_kernel<PA, PC>), dim3(nblocks), dim3(kBlock), lds, s, imgs, bmap, bfirst)
+#define MLBA_PB(PA, PC)                                                                                            \
+    do {                                                                                                           \
+        if (any_len)                                                                                               \
+            hipLaunchKernelGGL((precond_batched_kernel<PA, PC, kAnyLen>), dim3(nblocks), dim3(kBlock), lds, s, imgs, \
+                               bmap, bfirst);                                                                      \
+        else                                                                                                       \
+            hipLaunchKernelGGL((precond_batched_kernel<PA, PC, 0>), dim3(nblocks), dim3(kBlock), lds, s, imgs, bmap, \
+                               bfirst);                                                                            \
+    } while (0)
     if (precond == 0) {
         if (pass == 0) MLBA_PB(0, 0);
         else if (pass == 1) MLBA_PB(1, 0);
@@ -916,6 +924,9 @@ hipError_t launch_fft_rows_r2c(const float* src, int n, float2* T, int ts, const
     if (n == kFixedN && G == 1)
         hipLaunchKernelGGL(fft_rows_r2c_kernel<kFixedN>, dim3(n / 2), dim3(kBlock), lds, s, src, n, T, ts, fd, tw, 1,
                            seq_shift_for(1));
+    else if (fd.m > 0)
+        hipLaunchKernelGGL(fft_rows_r2c_kernel<kAnyLen>, dim3(n / (2 * G)), dim3(kBlock), lds, s, src, n, T, ts, fd, tw, G,
+                           seq_shift_for(G));
     else
         hipLaunchKernelGGL(fft_rows_r2c_kernel<0>, dim3(n / (2 * G)), dim3(kBlock), lds, s, src, n, T, ts, fd, tw, G,
                            seq_shift_for(G));
@@ -932,6 +943,10 @@ static hipError_t launch_cols(float2* T, int n, int ts, const float* spec, float
     if (n == kFixedN && CC == 1)
         hipLaunchKernelGGL(fft_cols_kernel<kFixedN>, dim3(half), dim3(kBlock), lds, s, T, n, ts, spec, alpha, inv, fd,
                            tw, 1, mode, power, seq_shift_for(1), lamc, alpha_dev, cspec, red_in, red_count, red_out);
+    else if (fd.m > 0)
+        hipLaunchKernelGGL(fft_cols_kernel<kAnyLen>, dim3((half + CC - 1) / CC), dim3(kBlock), lds, s, T, n, ts, spec,
+                           alpha, inv, fd, tw, CC, mode, power, seq_shift_for(CC), lamc, alpha_dev, cspec, red_in,
+                           red_count, red_out);
     else
         hipLaunchKernelGGL(fft_cols_kernel<0>, dim3((half + CC - 1) / CC), dim3(kBlock), lds, s, T, n, ts, spec,
                            alpha, inv, fd, tw, CC, mode, power, seq_shift_for(CC), lamc, alpha_dev, cspec, red_in,
@@ -975,6 +990,9 @@ hipError_t launch_fft_rows_c2r(const float2* T, int n, int ts, float* dst, const
     if (n == kFixedN && G == 1)
         hipLaunchKernelGGL(fft_rows_c2r_kernel<kFixedN>, dim3(n / 2), dim3(kBlock), lds, s, T, n, ts, dst, fd, tw, 1,
                            seq_shift_for(1), accum);
+    else if (fd.m > 0)
+        hipLaunchKernelGGL(fft_rows_c2r_kernel<kAnyLen>, dim3(n / (2 * G)), dim3(kBlock), lds, s, T, n, ts, dst, fd, tw, G,
+                           seq_shift_for(G), accum);
     else
         hipLaunchKernelGGL(fft_rows_c2r_kernel<0>, dim3(n / (2 * G)), dim3(kBlock), lds, s, T, n, ts, dst, fd, tw, G,
                            seq_shift_for(G), accum);
@@ -988,6 +1006,9 @@ hipError_t launch_dct_rows_fwd(const float* src, int n, float* Tr, int ts, const
     if (n == kFixedN && G == 1)
         hipLaunchKernelGGL(dct_rows_fwd_kernel<kFixedN>, dim3(n / 2), dim3(kBlock), lds, s, src, n, Tr, ts, fd, tw,
                            dtw, 1, seq_shift_for(1));
+    else if (fd.m > 0)
+        hipLaunchKernelGGL(dct_rows_fwd_kernel<kAnyLen>, dim3(n / (2 * G)), dim3(kBlock), lds, s, src, n, Tr, ts, fd, tw,
+                           dtw, G, seq_shift_for(G));
     else
         hipLaunchKernelGGL(dct_rows_fwd_kernel<0>, dim3(n / (2 * G)), dim3(kBlock), lds, s, src, n, Tr, ts, fd, tw,
                            dtw, G, seq_shift_for(G));
@@ -1003,6 +1024,9 @@ static hipError_t launch_dct_cols(float* Tr, int n, int ts, const float* spec, f
     if (n == kFixedN && CP == 1)
         hipLaunchKernelGGL(dct_cols_filter_kernel<kFixedN>, dim3(pairs), dim3(kBlock), lds, s, Tr, n, ts, spec, alpha,
                            inv, fd, tw, dtw, 1, seq_shift_for(1), lamr, mode, alpha_dev);
+    else if (fd.m > 0)
+        hipLaunchKernelGGL(dct_cols_filter_kernel<kAnyLen>, dim3((pairs + CP - 1) / CP), dim3(kBlock), lds, s, Tr, n, ts,
+                           spec, alpha, inv, fd, tw, dtw, CP, seq_shift_for(CP), lamr, mode, alpha_dev);
     else
         hipLaunchKernelGGL(dct_cols_filter_kernel<0>, dim3((pairs + CP - 1) / CP), dim3(kBlock), lds, s, Tr, n, ts,
                            spec, alpha, inv, fd, tw, dtw, CP, seq_shift_for(CP), lamr, mode, alpha_dev);
@@ -1033,6 +1057,9 @@ hipError_t launch_dct_rows_inv(const float* Tr, int n, int ts, float* dst, const
     if (n == kFixedN && G == 1)
         hipLaunchKernelGGL(dct_rows_inv_kernel<kFixedN>, dim3(n / 2), dim3(kBlock), lds, s, Tr, n, ts, dst, fd, tw,
                            dtw, 1, seq_shift_for(1), accum);
+    else if (fd.m > 0)
+        hipLaunchKernelGGL(dct_rows_inv_kernel<kAnyLen>, dim3(n / (2 * G)), dim3(kBlock), lds, s, Tr, n, ts, dst, fd, tw,
+                           dtw, G, seq_shift_for(G), accum);
     else
         hipLaunchKernelGGL(dct_rows_inv_kernel<0>, dim3(n / (2 * G)), dim3(kBlock), lds, s, Tr, n, ts, dst, fd, tw,
                            dtw, G, seq_shift_for(G), accum);

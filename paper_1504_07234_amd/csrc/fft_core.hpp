@@ -344,7 +344,7 @@ __device__ __forceinline__ void stockham_stage(float2* buf, int n, int nseq, int
 // complex values per stage, so n <= EPT << seq_shift.  The caller synchronises
 // before the call.
 template <int DIR, int EPT = FFT_EPT>
-__device__ void lds_stockham(float2* buf, int len, const FftDesc& fd, int nseq, int seq_shift,
+__device__ __forceinline__ void lds_stockham(float2* buf, int len, const FftDesc& fd, int nseq, int seq_shift,
                              const float2* __restrict__ tw) {
     int Ns = 1, ns_shift = 0;
     for (int s = 0; s < fd.nst; ++s) {
@@ -410,11 +410,17 @@ __device__ void lds_bluestein(float2* buf, const FftDesc& fd, const float2* __re
     __syncthreads();
 }
 
+// run-time 2/3/5-smooth lengths
 template <int DIR, int EPT = FFT_EPT>
-__device__ void lds_fft(float2* buf, const FftDesc& fd, int nseq, int seq_shift, const float2* __restrict__ tw) {
-    if (fd.m > 0) lds_bluestein<DIR, EPT>(buf, fd, tw);  // one sequence per workgroup
-    else lds_stockham<DIR, EPT>(buf, fd.n, fd, nseq, seq_shift, tw);
+__device__ __forceinline__ void lds_fft(float2* buf, const FftDesc& fd, int nseq, int seq_shift, const float2* __restrict__ tw) {
+    lds_stockham<DIR, EPT>(buf, fd.n, fd, nseq, seq_shift, tw);
 }
+
+// Template argument of the pass bodies and kernels for a run-time length that
+// may take the Bluestein form (fd.m > 0); NT == 0 compiles the plain
+// Stockham plan only, which keeps the Bluestein code (and its registers) out
+// of the kernels that serve 2/3/5-smooth lengths.
+constexpr int kAnyLen = -1;
 
 // ---- fixed-size transforms ------------------------------------------------
 // The same Stockham stages with the length known at compile time and one
@@ -558,12 +564,19 @@ __device__ __forceinline__ void lds_fft_fixed(float2* buf, const float2* __restr
 
 // NT > 0: the fixed transform of length NT (one sequence per workgroup),
 // with the twiddles of fixed_tw_load in `pre` when given; NT == 0: the
-// run-time plan fd over nseq sequences.
+// run-time plan fd over nseq sequences; NT == kAnyLen: that, or the
+// Bluestein form when fd.m > 0.
 template <int DIR, int NT, int EPT = FFT_EPT>
 __device__ __forceinline__ void lds_fft_any(float2* buf, const FftDesc& fd, int nseq, int seq_shift,
                                             const float2* __restrict__ tw, const float2* pre = nullptr) {
-    if constexpr (NT > 0) lds_fft_fixed<DIR, NT>(buf, tw, pre);
-    else lds_fft<DIR, EPT>(buf, fd, nseq, seq_shift, tw);
+    if constexpr (NT > 0) {
+        lds_fft_fixed<DIR, NT>(buf, tw, pre);
+    } else if constexpr (NT == kAnyLen) {
+        if (fd.m > 0) lds_bluestein<DIR, EPT>(buf, fd, tw);  // one sequence per workgroup
+        else lds_fft<DIR, EPT>(buf, fd, nseq, seq_shift, tw);
+    } else {
+        lds_fft<DIR, EPT>(buf, fd, nseq, seq_shift, tw);
+    }
 }
 
 }  // namespace mlba

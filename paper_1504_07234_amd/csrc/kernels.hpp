@@ -338,7 +338,8 @@ int fft_cols_batch_at_most(int n, int want);
 int precond_pass_tiles(const BatchImage& I, int pass);
 // pass 3: columns, inverse FFT only, of the real dense spectrum I.eacc (into swork)
 hipError_t launch_precond_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks,
-                                  int pass, int precond, int nmax, hipStream_t s);
+                                  int pass, int precond, int nmax, hipStream_t s,
+                                  int any_len = 0);
 
 // ---- PSF correlations of the reverse sweep ---------------------------------
 // Per tile of the n x n grid, running sums over the steps of

@@ -57,6 +57,7 @@ struct ImgBufs {
 
 struct mlba_unrolled_s {
     int count = 0, levels = 0, bands = 0, p = 0, iters = 0, ce = 0, J = 0, nmax = 8;
+    int any_len = 0;  // some image's transform takes the Bluestein form
     std::vector<mlba_plan_t> plans;
     std::vector<BatchImage> base;
     std::vector<ImgBufs> bufs;
@@ -131,7 +132,7 @@ int enqueue_step(const mlba_unrolled_s* U, const BatchImage* T, hipStream_t s) {
     HIPCHK(launch_conv_batched(T, U->conv_a.bmap, U->conv_a.bfirst, U->conv_a.nblocks, 1, U->p, nullptr, s));
     for (int pass = 0; pass < 3; ++pass)
         HIPCHK(launch_precond_batched(T, U->pre[pass].bmap, U->pre[pass].bfirst, U->pre[pass].nblocks, pass,
-                                      MLBA_PRECOND_BCCB, U->nmax, s));
+                                      MLBA_PRECOND_BCCB, U->nmax, s, U->any_len));
     HIPCHK(launch_conv_batched(T, U->conv_at.bmap, U->conv_at.bfirst, U->conv_at.nblocks, 0, U->p, nullptr, s));
     for (int lev = 1; lev <= U->levels; ++lev) {
         const Map& m = U->ana[lev];
@@ -213,6 +214,7 @@ int mlba_unrolled_create(mlba_unrolled_t* out, int count, const mlba_plan_t* pla
     for (int i = 0; i < count; ++i) {
         U->base[i] = plan_desc(plans[i]);
         U->nmax = std::max(U->nmax, plans[i]->n);
+        if (plans[i]->fd.m > 0) U->any_len = 1;  // a Bluestein-form transform
     }
     int st = MLBA_OK;
 #define UALLOC(ptr, cnt)                  \
@@ -439,7 +441,7 @@ int mlba_unrolled_backward(mlba_unrolled_t U, const float* const* g, double alph
             HIPCHK(launch_conv_batched(T, U->conv_a.bmap, U->conv_a.bfirst, U->conv_a.nblocks, 1, U->p, nullptr, s));
             for (int pass = 0; pass < 3; ++pass)
                 HIPCHK(launch_precond_batched(T, U->pre[pass].bmap, U->pre[pass].bfirst, U->pre[pass].nblocks, pass,
-                                              MLBA_PRECOND_BCCB, U->nmax, s));
+                                              MLBA_PRECOND_BCCB, U->nmax, s, U->any_len));
             HIPCHK(launch_conv_batched(T, U->conv_at.bmap, U->conv_at.bfirst, U->conv_at.nblocks, 0, U->p, nullptr,
                                        s));
             for (int lev = 1; lev <= U->levels; ++lev) {
@@ -455,9 +457,9 @@ int mlba_unrolled_backward(mlba_unrolled_t U, const float* const* g, double alph
     // spectral term: inverse transform of the accumulated E, then the PSF sums
     const BatchImage* T = table(U, t_end);
     HIPCHK(launch_precond_batched(T, U->pre[1].bmap, U->pre[1].bfirst, U->pre[1].nblocks, 3, MLBA_PRECOND_BCCB,
-                                  U->nmax, s));
+                                  U->nmax, s, U->any_len));
     HIPCHK(launch_precond_batched(T, U->pre[2].bmap, U->pre[2].bfirst, U->pre[2].nblocks, 2, MLBA_PRECOND_BCCB,
-                                  U->nmax, s));
+                                  U->nmax, s, U->any_len));
     HIPCHK(launch_psf_spectral_batched(T, U->count, U->p, U->spec, s));
     UnrolledSums S{};
     S.bands = U->bands;
