@@ -52,7 +52,7 @@ TRAFFIC = {
     # the direct A^T accumulating into omega (p = 31), one launch per iteration
     ("conv_blur_t", "direct-implicit"): {
         "fetch_kib": 17582.1, "write_kib": 16878.0, "fetch_scale": 2.0, "write_scale": 1.0, "launches": 1,
-        "sources_sha256": "cfc1812608661acbef5070cd3eafda822ea578fa454b70c552a50152a2aa7c17"},
+        "sources_sha256": "0cadeb24c27af3e487dec833b4026d5eb191001033c0a4f11b519d67bc769782"},
 }
 # the sources that define each kernel's device code
 TRAFFIC_SOURCES = {
