@@ -1,9 +1,10 @@
 """Example 3's shape (section 6): a 196 x 196 field of view, antireflective
 conditions, a PSF that is not quadrantally symmetric.  196 = 2^2 7^2 and the
 antireflective transform length 2 * 195 = 390 = 2 * 3 * 5 * 13 both need the
-Bluestein form of the transforms.  The four configurations of Table 3
-(Alg-BC3, Alg-BC1, Alg-Rect1, Alg-Rect3) against the FP64 oracle with its
-automatic step; bar 1e-4 on the restored image and the residual norms.
+Bluestein form of the transforms.  Table 3's MLBA configurations (Alg-BC3,
+Alg-BC1, Alg-Rect1, Alg-Rect3) against the FP64 oracle with its automatic
+step, and Alg-BC4 (Algorithm 4 with the BCCB matrix); bar 1e-4 on the
+restored image and the residual norms.
 
 The scene is a synthetic stand-in for the Boat image, and the PSF a 31-tap
 motion blur (the LDS window of the direct blur takes p <= 49)."""
@@ -54,5 +55,25 @@ def test_example3_shape(mlba, scene, name, bc, pc, alpha):
         f = host(f)
     e = rel_err(f, ref["f"])
     print(f"  delta {delta:.4f} image {e:.2e} rnorm {rel_err(info.rnorm, ref['rnorm']):.2e}", flush=True)
+    assert e < 1e-4
+    assert rel_err(info.rnorm, ref["rnorm"]) < 1e-4
+
+
+def test_example3_alg_bc4(mlba, scene):
+    """Alg-BC4 on the same shape: Algorithm 4 (section 5), the direction
+    C^T (C C^T + alpha I)^{-1} r with the BCCB matrix of the PSF (FFTs of
+    length 196 in the Bluestein form) on the antireflective model, step 1."""
+    from oracle import alg4 as oa4
+    n, p, H, g = scene
+    iters, L, alpha = 15, 2, 0.1
+    mu = np.full(8 * L + 1, 1e-3)
+    announce(f"Example 3 shape Alg-BC4 n={n} p={p}")
+    ref = oa4.alg4(g, H, ob.ANTIREFLECT, opc.BCCB, L, np.full(iters, alpha), np.ones(iters + 1), mu, iters)
+    with mlba.Plan(n, p, mlba.ANTIREFLECT, mlba.BCCB, L, cuda(H)) as plan:
+        f, info = plan.restore(cuda(g), alpha=alpha, mu=mu, delta=1.0, iters=iters, method=mlba.ALG4,
+                               implicit=True)
+        f = host(f)
+    e = rel_err(f, ref["f"])
+    print(f"  image {e:.2e} rnorm {rel_err(info.rnorm, ref['rnorm']):.2e}", flush=True)
     assert e < 1e-4
     assert rel_err(info.rnorm, ref["rnorm"]) < 1e-4
