@@ -3,8 +3,8 @@ conditions, a PSF that is not quadrantally symmetric.  196 = 2^2 7^2 and the
 antireflective transform length 2 * 195 = 390 = 2 * 3 * 5 * 13 both need the
 Bluestein form of the transforms.  Table 3's MLBA configurations (Alg-BC3,
 Alg-BC1, Alg-Rect1, Alg-Rect3) against the FP64 oracle with its automatic
-step, and Alg-BC4 (Algorithm 4 with the BCCB matrix); bar 1e-4 on the
-restored image and the residual norms.
+step, Alg-BC4 (Algorithm 4 with the BCCB matrix) and Alg-Rect2 (Algorithm
+2); bar 1e-4 on the restored image and the residual norms.
 
 The scene is a synthetic stand-in for the Boat image, and the PSF a 31-tap
 motion blur (the LDS window of the direct blur takes p <= 49)."""
@@ -77,3 +77,23 @@ def test_example3_alg_bc4(mlba, scene):
     print(f"  image {e:.2e} rnorm {rel_err(info.rnorm, ref['rnorm']):.2e}", flush=True)
     assert e < 1e-4
     assert rel_err(info.rnorm, ref["rnorm"]) < 1e-4
+
+
+def test_example3_alg_rect2(mlba, scene):
+    """Alg-Rect2 on the same shape: Algorithm 2 (section 4.2), PCG on
+    A A^T + alpha I preconditioned by the BCCB matrix (Bluestein-form FFTs of
+    length 196), at most 5 PCG steps with a tolerance every iteration misses
+    (5 steps each time, so no step count sits near its threshold)."""
+    from oracle import alg2 as oa2
+    n, p, H, g = scene
+    iters, L, alpha, delta, pcg = 10, 2, 0.03, 1.0, (5, 1e-4)
+    announce(f"Example 3 shape Alg-Rect2 n={n} p={p}")
+    ref = oa2.alg2(g, H, ob.RECT, opc.BCCB, L, np.full(iters, alpha), np.full(iters + 1, delta), 1e-3, iters,
+                   beta_max=pcg[0], tol=pcg[1])
+    with mlba.Plan(n, p, mlba.RECT, mlba.BCCB, L, cuda(H)) as plan:
+        f, info = plan.restore(cuda(g), alpha=alpha, mu=1e-3, delta=delta, iters=iters, method=mlba.ALG2, pcg=pcg)
+        f = host(f)
+    e = rel_err(f, ref["f"])
+    print(f"  betas {info.pcg_steps}; image {e:.2e}", flush=True)
+    assert info.pcg_steps == ref["betas"].tolist() == [pcg[0]] * iters
+    assert e < 1e-4
