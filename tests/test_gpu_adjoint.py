@@ -84,6 +84,7 @@ def _compare(gpu, ref):
     ([48, 36, 64], 7, 2, 7, 3),   # several tiles per image, ragged segment
     ([72], 9, 3, 5, 5),           # one segment, three levels
     ([96], 3, 1, 3, 1),           # every state checkpointed
+    ([28, 32, 42], 5, 2, 4, 2),   # 28 = 2^2 7, 42 = 2 3 7: Bluestein-form transforms beside a 2^a one
 ])
 def test_gradients_match_oracle(mlba, sizes, p, L, K, ce):
     announce(f"unrolled grad vs oracle sizes={sizes} p={p} L={L} K={K} ckpt={ce}")
