@@ -34,7 +34,7 @@ def _problem(n, p, bc, sym, seed):
     return synth.add_noise(b, synth.white_noise((n, n), g), 0.01), H, synth.noise_norm(b, 0.01), truth
 
 
-@pytest.mark.parametrize("n", [8, 64, 96, 192, 256, 512])
+@pytest.mark.parametrize("n", [8, 14, 64, 96, 192, 196, 256, 512])  # 14, 196: Bluestein-form transforms
 @pytest.mark.parametrize("kind,bc", [(oa.BCCB, ob.ZERO), (oa.BCCB, ob.PERIODIC), (oa.DCT, ob.REFLECT)])
 def test_direction_operator(mlba, n, kind, bc):
     p = min(9, n - 1 if (n - 1) % 2 else n - 2)
@@ -112,7 +112,9 @@ def _alpha_condition(g, H, bc, L, mu, alphas, kind=None):
 @pytest.mark.parametrize("implicit", [False, True])
 @pytest.mark.parametrize("bc,n,L,kind", [(ob.ZERO, 128, 2, oa.BCCB), (ob.PERIODIC, 96, 1, oa.BCCB),
                                          (ob.REFLECT, 192, 2, oa.BCCB), (ob.REFLECT, 128, 2, oa.DCT),
-                                         (ob.ANTIREFLECT, 96, 2, oa.DCT)])
+                                         (ob.ANTIREFLECT, 96, 2, oa.DCT),
+                                         # 196: Bluestein-form transforms (stops 1e-3 and 5e-4 clear of the bound)
+                                         (ob.PERIODIC, 196, 1, oa.BCCB), (ob.REFLECT, 196, 2, oa.DCT)])
 def test_alg4_ns_against_oracle(mlba, bc, n, L, kind, implicit):
     """4-NS with the BCCB spectrum and with the DCT of the symmetrised PSF
     (Alg-BC4-NS of Example 4: antireflective model, Gaussian PSF, DCT)."""
