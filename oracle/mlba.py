@@ -81,8 +81,9 @@ def delta_auto(norm_value: float) -> float:
 
 
 def delta_table(H, n, bc, precond, alphas, delta: float, count: int) -> np.ndarray:
-    """delta_k for k = 0 .. count-1 (``alphas`` must hold at least ``count``
-    entries; the last alpha is reused past its end)."""
+    """delta_k for k = 0 .. count-1 (``alphas`` holds at least one entry; the
+    last alpha is reused past its end).  The automatic step uses the norm to
+    opnorm's default tolerance (converged to rounding)."""
     if delta > 0:
         return np.full(count, float(delta))
     cache = {}
@@ -90,7 +91,7 @@ def delta_table(H, n, bc, precond, alphas, delta: float, count: int) -> np.ndarr
     for k in range(count):
         a = float(alphas[min(k, len(alphas) - 1)])
         if a not in cache:
-            cache[a] = delta_auto(opnorm(H, n, bc, precond, a, tol=1e-4))
+            cache[a] = delta_auto(opnorm(H, n, bc, precond, a))
         out[k] = cache[a]
     return out
 
