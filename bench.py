@@ -215,7 +215,7 @@ def batched_section(count: int = 64, iters: int = 100):
         plans.append(pl)
         gs.append(g)
         alphas.append(w.alpha0)
-        deltas.append(0.9 / max(pl.opnorm(w.alpha0, 50), 0.9))
+        deltas.append(pl.auto_step(w.alpha0))
     outs = [torch.empty(pl.N, pl.N, device="cuda") for pl in plans]
     torch.cuda.synchronize()
     # 64 sequential plain solves (eager launches)
@@ -278,7 +278,7 @@ def unrolled_section(reps: int = 5):
         xi = torch.as_tensor(w.xi, dtype=torch.float32).cuda()
         gs.append((b + (w.noise_level * b.double().norm() / xi.double().norm()).float() * xi).contiguous())
         truths.append(truth)
-    delta = 0.9 / max(U.plans[0].opnorm(w0.alpha0, 50), 0.9)
+    delta = U.plans[0].auto_step(w0.alpha0)
     mu = [w0.mu] * U.bands
     fs, ck = U.forward(gs, alpha=w0.alpha0, mu=mu, delta=delta)
     dfs = [(2.0 * (f - t)).contiguous() for f, t in zip(fs, truths)]
@@ -427,7 +427,7 @@ def antireflective_section(steps: int = 30, warmup: int = 3):
     with mlba.Plan(n, p, w.bc, w.precond, w.levels, psf) as plan:
         N = plan.N
         tune = plan.autotune(reps=5)
-        delta = 0.9 / max(plan.opnorm(w.alpha0, 50), 0.9)
+        delta = plan.auto_step(w.alpha0)
         f = torch.empty((N, N), dtype=torch.float32, device="cuda")
         om = torch.zeros((N, N), dtype=torch.float32, device="cuda")
         plan.restore(g, alpha=w.alpha0, mu=w.mu, delta=delta, iters=warmup, z=om, out=f, track=False,
@@ -549,8 +549,7 @@ def main() -> int:
     xi = torch.as_tensor(w.xi, dtype=torch.float32).cuda()
     g = blurred + (w.noise_level * blurred.double().norm() / xi.double().norm()).float() * xi
     g = g.contiguous()
-    opn = plan.opnorm(w.alpha0, 50)
-    delta = 0.9 / max(opn, 0.9)
+    delta = plan.auto_step(w.alpha0)  # the library's automatic step (delta <= 0)
     f = torch.empty((N, N), dtype=torch.float32, device="cuda")
 
     def run(implicit, steps, warmup, profile):

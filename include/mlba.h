@@ -129,12 +129,16 @@ typedef struct mlba_params {
     const double* mu;          /* host, n_mu values: 1 (all bands) or `bands`  */
     int n_mu;
     double delta;              /* > 0: step delta_k = delta;
-                                  <= 0: delta_k = 0.9 / max(||A^T P_{alpha_k} A||, 0.9),
-                                  estimated by mlba_plan_opnorm (section 3,
-                                  convergence theorem for MLBA)               */
+                                  <= 0: delta_k = 0.9 / max(||A^T P_{alpha_k} A||, 0.9)
+                                  (section 3, convergence theorem for MLBA), the norm
+                                  computed once per distinct alpha_k by Lanczos
+                                  (up to 1000 steps, converged to 1e-9 relative;
+                                  antireflective model: 50 power steps, see
+                                  mlba_plan_opnorm); the algorithm 4 methods use 1 */
     const double* delta_table; /* host, optional: delta_k = delta_table[k] for
                                   k = 0 .. k0+iters (k0+iters+1 values); the
-                                  last value scales the returned image        */
+                                  last value scales the returned image; its
+                                  length is delta_table_len                   */
     int iters;                 /* iterations to run                           */
     int k0;                    /* global index of the first iteration (resume) */
     const mlba_stop* stop;     /* optional discrepancy stop (NULL: fixed iters) */
@@ -145,6 +149,13 @@ typedef struct mlba_params {
     int pcg_max;               /* MLBA_METHOD_ALG2: step cap (0: 5)            */
     double pcg_tol;            /* MLBA_METHOD_ALG2: tolerance (0: 1e-3)         */
     int* pcg_steps_out;        /* host, optional: beta_n of each iteration run  */
+    double* delta_out;         /* host, optional: the delta_k used, one per
+                                  iteration run plus the one scaling the
+                                  returned image (iters_done + 1 values, at most
+                                  iters + 1)                                   */
+    int delta_table_len;       /* values in delta_table; MLBA_EINVAL when
+                                  delta_table is given with fewer than
+                                  k0 + iters + 1                               */
 } mlba_params;
 
 /* State kept between iterations.  Explicit: the frame coefficients z
@@ -205,7 +216,15 @@ int mlba_plan_set_blur(mlba_plan_t plan, int mode, hipStream_t stream);
 int mlba_plan_autotune(mlba_plan_t plan, int reps, double* ms_out, hipStream_t stream);
 /* Sizes: observed side n, PSF side p, unknown side N, number of bands. */
 int mlba_plan_dims(mlba_plan_t plan, int* n, int* p, int* N, int* bands);
-/* ||A^T P_alpha A|| by `iters` power iterations (synchronous; result on host). */
+/* ||A^T P_alpha A||, the largest eigenvalue of the symmetric positive
+ * semidefinite A^T P_alpha A (section 3, convergence theorem), by Lanczos from a
+ * fixed pseudo-random start: at most `iters` steps (and at most 32768), stopping
+ * once the largest Ritz value has changed by at most 1e-9 (relative) over 8
+ * steps; the tridiagonal coefficients are read back every 8 steps.  With
+ * MLBA_BC_ANTIREFLECT the operator A' P_alpha A is not symmetric and the
+ * result is ||M v|| / ||v|| after `iters` power steps (an estimate of its
+ * largest eigenvalue modulus).  Synchronous; result on host; uses the plan's
+ * scratch buffers. */
 int mlba_plan_opnorm(mlba_plan_t plan, double alpha, int iters, double* out, hipStream_t stream);
 
 /* ---- operators (asynchronous) ---------------------------------------------- */

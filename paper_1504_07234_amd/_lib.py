@@ -44,7 +44,8 @@ class Params(ctypes.Structure):
     _fields_ = [("alpha", AlphaSchedule), ("mu", c_dbl_p), ("n_mu", c_int), ("delta", c_double),
                 ("delta_table", c_dbl_p), ("iters", c_int), ("k0", c_int),
                 ("stop", ctypes.POINTER(Stop)), ("state", c_int), ("method", c_int), ("alpha_out", c_dbl_p),
-                ("pcg_max", c_int), ("pcg_tol", c_double), ("pcg_steps_out", c_int_p)]
+                ("pcg_max", c_int), ("pcg_tol", c_double), ("pcg_steps_out", c_int_p),
+                ("delta_out", c_dbl_p), ("delta_table_len", c_int)]
 
 
 # name -> (restype, argtypes); every symbol declared in include/mlba.h

@@ -382,11 +382,7 @@ int mlba_batch_restore(mlba_batch_t B, const float* const* g, const double* alph
         if (!g[i] || !f_out[i]) return MLBA_EINVAL;
         if (B->precond != MLBA_PRECOND_NONE && !(alpha[i] > 0.0)) return MLBA_EINVAL;
         double dl = delta[i];
-        if (!(dl > 0.0)) {
-            double nrm = 0.0;
-            STCHK(mlba_internal_opnorm(B->plans[i], alpha[i], 50, &nrm, s));
-            dl = 0.9 / (nrm > 0.9 ? nrm : 0.9);
-        }
+        if (!(dl > 0.0)) STCHK(mlba_internal_auto_delta(B->plans[i], alpha[i], &dl, s));
         d.alpha = (float)alpha[i];
         d.delta = (float)dl;
         for (int b = 0; b < bands; ++b) {

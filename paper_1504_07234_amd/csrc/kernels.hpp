@@ -382,6 +382,9 @@ hipError_t launch_pcg_update(float* t, float* res, const float* d, const float* 
 hipError_t launch_pcg_dir(float* d, const float* z, size_t count, const double* rho_new, const double* rho,
                           hipStream_t s);
 hipError_t launch_axpy(float* y, const float* x, size_t count, float a, hipStream_t s);  // y += a x
+// w -= ab[0] v + sqrt(*beta2) vprev (vprev may be null), partial sums of w^2
+hipError_t launch_lanczos_step(float* w, const float* v, const float* vprev, size_t count, const double* ab,
+                               const double* beta2, double* partials, int* n_partials, hipStream_t s);
 // rn[image][k] = sum of that image's residual-norm partials (one workgroup per image)
 hipError_t launch_sum_partials_batched(const BatchImage* imgs, const double* partials, const int* pcount,
                                        int count, int k, hipStream_t s);

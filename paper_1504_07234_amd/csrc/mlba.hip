@@ -549,19 +549,122 @@ int expand_mu(const mlba_plan_s* P, const double* mu, int n_mu, float* out) {
 
 }  // namespace
 
-int mlba_internal_opnorm(mlba_plan_s* P, double alpha, int iters, double* out, hipStream_t s) {
+namespace {
+
+// y = A^T P_alpha A v (A' P_alpha A for antireflective conditions)
+int normal_matvec(mlba_plan_s* P, const float* v, float* y, double alpha, hipStream_t s) {
+    STCHK(do_blur(P, v, nullptr, P->r, false, nullptr, s));
+    STCHK(do_precond(P, P->r, P->t, alpha, s));
+    return do_blurT(P, P->t, y, s);
+}
+
+// Largest eigenvalue of the symmetric tridiagonal matrix with diagonal a[0..k)
+// and off-diagonal b[1..k) (b[j] couples rows j-1 and j), by bisection on the
+// Sturm count (the number of negative pivots of T - xI is the number of
+// eigenvalues below x).
+double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b, int k) {
+    double lo = a[0], hi = a[0];
+    for (int i = 0; i < k; ++i) {
+        const double r = (i > 0 ? fabs(b[i]) : 0.0) + (i + 1 < k ? fabs(b[i + 1]) : 0.0);
+        lo = fmin(lo, a[i] - r);
+        hi = fmax(hi, a[i] + r);
+    }
+    auto below = [&](double x) {
+        int c = 0;
+        double d = 1.0;
+        for (int i = 0; i < k; ++i) {
+            d = a[i] - x - (i > 0 ? b[i] * b[i] / d : 0.0);
+            if (fabs(d) < 1e-300) d = -1e-300;
+            if (d < 0.0) ++c;
+        }
+        return c;
+    };
+    for (int it = 0; it < 400 && hi - lo > 1e-16 * fmax(fabs(hi), fabs(lo)); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (below(mid) == k) hi = mid;
+        else lo = mid;
+    }
+    return hi;
+}
+
+// Lanczos on the symmetric operator A^T P A (no reorthogonalisation: lost
+// orthogonality duplicates converged Ritz values but leaves the largest one
+// converging to the largest eigenvalue).  The tridiagonal entries are device
+// doubles in the plan's norm ring (hist[2k] = alpha_k, hist[2k+1] =
+// beta_{k+1}^2), read back every kBatch steps; the largest Ritz value grows
+// monotonically with k (interlacing), and the run stops once it has changed
+// by at most tol (relative) over kBatch steps, at an invariant subspace
+// (beta ~ 0) or after max_steps.
+int lanczos_norm(mlba_plan_s* P, double alpha, int max_steps, double tol, double* out, int* steps_out,
+                 hipStream_t s) {
+    constexpr int kBatch = 8;
+    const size_t nn = NN(P);
+    if (max_steps > P->rn_cap / 2) max_steps = P->rn_cap / 2;
+    float* v = P->pv;
+    float* vp = P->tmp[0];
+    float* w = P->u;  // the synthesis buffer is free while estimating
+    double* hist = P->rn;
+    HIPCHK(launch_fill_hash(v, nn, 7u, s));
+    int np = 0;
+    HIPCHK(launch_dot_partials(v, v, nn, P->partials, &np, s));
+    HIPCHK(launch_sum_partials(P->partials, np, P->scal, s));
+    HIPCHK(launch_scale(v, nn, P->scal, 1.0f, s));
+    std::vector<double> a, b(1, 0.0), theta, buf(2 * kBatch);
+    int k = 0;
+    bool done = false;
+    while (!done && k < max_steps) {
+        const int k1 = k + kBatch < max_steps ? k + kBatch : max_steps;
+        for (int j = k; j < k1; ++j) {
+            STCHK(normal_matvec(P, v, w, alpha, s));
+            HIPCHK(launch_dot_partials(v, w, nn, P->partials, &np, s));
+            HIPCHK(launch_sum_partials(P->partials, np, hist + 2 * j, s));
+            HIPCHK(launch_lanczos_step(w, v, j ? vp : nullptr, nn, hist + 2 * j, j ? hist + 2 * j - 1 : nullptr,
+                                       P->partials, &np, s));
+            HIPCHK(launch_sum_partials(P->partials, np, hist + 2 * j + 1, s));
+            HIPCHK(launch_scale(w, nn, hist + 2 * j + 1, 1.0f, s));
+            float* x = vp;
+            vp = v;
+            v = w;
+            w = x;
+        }
+        HIPCHK(hipMemcpyAsync(buf.data(), hist + 2 * k, 2 * (k1 - k) * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int j = k; j < k1 && !done; ++j) {
+            const double aj = buf[2 * (j - k)], b2 = buf[2 * (j - k) + 1];
+            if (!isfinite(aj)) {
+                done = true;
+                break;
+            }
+            a.push_back(aj);
+            theta.push_back(tridiag_max_eig(a, b, (int)a.size()));
+            const double th = theta.back();
+            if (!isfinite(b2) || b2 <= 1e-24 * th * th) done = true;  // invariant subspace
+            else b.push_back(sqrt(b2));
+        }
+        k = (int)a.size();
+        if (k > kBatch && fabs(theta[k - 1] - theta[k - 1 - kBatch]) <= tol * fabs(theta[k - 1])) done = true;
+        if ((int)a.size() < k1) done = true;
+    }
+    if (a.empty()) return MLBA_EHIP;
+    *out = theta.back();
+    if (steps_out) *steps_out = (int)a.size();
+    return MLBA_OK;
+}
+
+// The antireflective model's A' P A is not symmetric: power iteration on it,
+// ||M v|| / ||v|| after `iters` steps.
+int power_norm(mlba_plan_s* P, double alpha, int iters, double* out, hipStream_t s) {
     const size_t nn = NN(P);
     float* v = P->pv;
-    float* w = P->u;  // the synthesis buffer is free while estimating
+    float* w = P->u;
     HIPCHK(launch_fill_hash(v, nn, 7u, s));
     int np = 0;
     HIPCHK(launch_dot_partials(v, v, nn, P->partials, &np, s));
     HIPCHK(launch_sum_partials(P->partials, np, P->scal, s));
     HIPCHK(launch_scale(v, nn, P->scal, 1.0f, s));
     for (int it = 0; it < iters; ++it) {
-        STCHK(do_blur(P, v, nullptr, P->r, false, nullptr, s));
-        STCHK(do_precond(P, P->r, P->t, alpha, s));
-        STCHK(do_blurT(P, P->t, w, s));
+        STCHK(normal_matvec(P, v, w, alpha, s));
         HIPCHK(launch_dot_partials(v, w, nn, P->partials, &np, s));
         HIPCHK(launch_sum_partials(P->partials, np, P->scal + 1, s));
         HIPCHK(launch_dot_partials(w, w, nn, P->partials, &np, s));
@@ -575,6 +678,25 @@ int mlba_internal_opnorm(mlba_plan_s* P, double alpha, int iters, double* out, h
     HIPCHK(hipMemcpyAsync(host, P->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     *out = host[1];
+    return MLBA_OK;
+}
+
+}  // namespace
+
+int mlba_internal_opnorm(mlba_plan_s* P, double alpha, int iters, double tol, double* out, int* steps_out,
+                         hipStream_t s) {
+    if (P->bc == MLBA_BC_ANTIREFLECT) {
+        if (steps_out) *steps_out = iters;
+        return power_norm(P, alpha, iters, out, s);
+    }
+    return lanczos_norm(P, alpha, iters, tol, out, steps_out, s);
+}
+
+int mlba_internal_auto_delta(mlba_plan_s* P, double alpha, double* delta, hipStream_t s) {
+    double nrm = 0.0;
+    if (P->bc == MLBA_BC_ANTIREFLECT) STCHK(mlba_internal_opnorm(P, alpha, kAutoPowerSteps, 0.0, &nrm, nullptr, s));
+    else STCHK(mlba_internal_opnorm(P, alpha, kAutoLanczosSteps, kAutoLanczosTol, &nrm, nullptr, s));
+    *delta = 0.9 / (nrm > 0.9 ? nrm : 0.9);
     return MLBA_OK;
 }
 
@@ -873,7 +995,7 @@ int mlba_plan_dims(mlba_plan_t P, int* n, int* p, int* N, int* bands) {
 
 int mlba_plan_opnorm(mlba_plan_t P, double alpha, int iters, double* out, hipStream_t s) {
     if (!P || !out || iters < 1 || !(alpha > 0.0 || P->precond == MLBA_PRECOND_NONE)) return MLBA_EINVAL;
-    return mlba_internal_opnorm(P, alpha, iters, out, s);
+    return mlba_internal_opnorm(P, alpha, iters, kAutoLanczosTol, out, nullptr, s);
 }
 
 int mlba_apply_A(mlba_plan_t P, const float* u, float* y, hipStream_t s) {
@@ -957,6 +1079,7 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
     if (as.kind < MLBA_ALPHA_CONST || as.kind > MLBA_ALPHA_NS) return MLBA_EINVAL;
     if (as.kind == MLBA_ALPHA_TABLE && (!as.table || as.table_len < k0 + iters)) return MLBA_EINVAL;
     if (as.kind == MLBA_ALPHA_GEOMETRIC && !(as.ratio > 0.0)) return MLBA_EINVAL;
+    if (prm->delta_table && prm->delta_table_len < k0 + iters + 1) return MLBA_EINVAL;
     const mlba_stop* stop = prm->stop;
     if (stop && (stop->check_every < 1 || !(stop->noise_norm >= 0.0))) return MLBA_EINVAL;
     if (prm->state != MLBA_STATE_EXPLICIT && prm->state != MLBA_STATE_IMPLICIT) return MLBA_EINVAL;
@@ -1003,10 +1126,10 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
             size_t j = 0;
             while (j < seen_a.size() && seen_a[j] != alpha[i]) ++j;
             if (j == seen_a.size()) {
-                double nrm = 0.0;
-                STCHK(mlba_internal_opnorm(P, alpha[i], 50, &nrm, s));
+                double dl = 0.0;
+                STCHK(mlba_internal_auto_delta(P, alpha[i], &dl, s));
                 seen_a.push_back(alpha[i]);
-                seen_d.push_back(0.9 / (nrm > 0.9 ? nrm : 0.9));
+                seen_d.push_back(dl);
             }
             delta[i] = seen_d[j];
         }
@@ -1183,6 +1306,8 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
         else STCHK(do_synthesis(P, z, f_out, true, mub, (float)delta[done], s));
     }
 
+    if (prm->delta_out)
+        for (int i = 0; i <= done; ++i) prm->delta_out[i] = delta[i];
     if (prm->alpha_out && done > 0) {
         if (ns) {
             HIPCHK(hipMemcpyAsync(prm->alpha_out, P->ahist, (size_t)done * sizeof(double), hipMemcpyDeviceToHost, s));

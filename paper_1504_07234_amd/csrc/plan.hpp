@@ -72,7 +72,18 @@ struct mlba_plan_s {
     int prof_kl[MLBA_NKERNELS] = {};
 };
 
-int mlba_internal_opnorm(mlba_plan_s* P, double alpha, int iters, double* out, hipStream_t s);
+// ||A^T P_alpha A||: Lanczos (at most `iters` steps, stopping once the largest
+// Ritz value changes by at most `tol` relative over 8 steps) for the
+// symmetric models; power iteration (`iters` steps) on A' P_alpha A for the
+// antireflective model.
+int mlba_internal_opnorm(mlba_plan_s* P, double alpha, int iters, double tol, double* out, int* steps_out,
+                         hipStream_t s);
+// The automatic step of the convergence theorem of section 3:
+// delta = 0.9 / max(||A^T P_alpha A||, 0.9).
+constexpr int kAutoLanczosSteps = 1000;
+constexpr double kAutoLanczosTol = 1e-9;
+constexpr int kAutoPowerSteps = 50;
+int mlba_internal_auto_delta(mlba_plan_s* P, double alpha, double* delta, hipStream_t s);
 
 // Descriptor of a plan's sizes and buffers (the per-image record of a batch;
 // the single-image path builds the same record so both run identical jobs).

@@ -145,6 +145,39 @@ __global__ __launch_bounds__(kBlock) void axpy_kernel(float* __restrict__ y, con
         y[i] = fmaf(a, x[i], y[i]);
 }
 
+// One Lanczos three-term update: w -= alpha_k v + beta_k vprev, with alpha_k =
+// ab[0] and beta_k^2 = *beta2 (device doubles; vprev and beta2 null at the
+// first step), and the partial sums of the new w^2 per workgroup.
+__global__ __launch_bounds__(kBlock) void lanczos_step_kernel(float* __restrict__ w, const float* __restrict__ v,
+                                                              const float* __restrict__ vprev, size_t count,
+                                                              const double* __restrict__ ab,
+                                                              const double* __restrict__ beta2,
+                                                              double* __restrict__ partials) {
+    __shared__ double red[kBlock / 64];
+    const float a = (float)ab[0];
+    const float b = vprev ? (float)sqrt(*beta2) : 0.0f;
+    double s = 0.0;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (size_t)gridDim.x * kBlock) {
+        float x = fmaf(-a, v[i], w[i]);
+        if (vprev) x = fmaf(-b, vprev[i], x);
+        w[i] = x;
+        s += (double)x * (double)x;
+    }
+    const double t = block_sum(s, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+hipError_t launch_lanczos_step(float* w, const float* v, const float* vprev, size_t count, const double* ab,
+                               const double* beta2, double* partials, int* n_partials, hipStream_t s) {
+    size_t blocks = (count + kBlock - 1) / kBlock;
+    if (blocks > (size_t)kReduceBlocks) blocks = kReduceBlocks;
+    if (blocks == 0) blocks = 1;
+    *n_partials = (int)blocks;
+    hipLaunchKernelGGL(lanczos_step_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, w, v, vprev, count, ab,
+                       beta2, partials);
+    return hipGetLastError();
+}
+
 static unsigned elementwise_blocks(size_t count) {
     size_t b = (count + kBlock - 1) / kBlock;
     if (b > 4096) b = 4096;

@@ -50,6 +50,7 @@ class RestoreInfo:
     rnorm: list
     alphas: list = None
     pcg_steps: list = None
+    deltas: list = None
 
 
 class Plan:
@@ -107,11 +108,20 @@ class Plan:
         return {"blur": "fft" if mode == _lib.BLUR_FFT else "direct",
                 "direct_ms": [ms[0], ms[1]], "fft_ms": [ms[2], ms[3]] if ms[2] >= 0 else None}
 
-    def opnorm(self, alpha: float, iters: int = 50, stream=None) -> float:
+    def opnorm(self, alpha: float, iters: int = 1000, stream=None) -> float:
+        """||A^T P_alpha A|| (Lanczos, at most `iters` steps; power steps for the
+        antireflective model), see mlba_plan_opnorm."""
         out = ctypes.c_double()
         check(self._lib.mlba_plan_opnorm(self._h, float(alpha), int(iters), ctypes.byref(out), _stream(stream)),
               "mlba_plan_opnorm")
         return out.value
+
+    def auto_step(self, alpha: float, stream=None) -> float:
+        """The step the library takes for delta <= 0 at a constant alpha (a
+        zero-iteration restore that reports its delta_k)."""
+        g = torch.zeros((self.n, self.n), dtype=torch.float32, device="cuda")
+        _, info = self.restore(g, alpha=alpha, mu=0.0, delta=0.0, iters=0, stream=stream)
+        return info.deltas[0]
 
     # -- operators ---------------------------------------------------------
     def apply_A(self, u, out=None, stream=None):
@@ -252,6 +262,7 @@ class Plan:
             darr, dptr = _dbl_array(delta_table)
             keep.append(darr)
             prm.delta_table = dptr
+            prm.delta_table_len = len(delta_table)
         prm.iters = int(iters)
         prm.k0 = int(k0)
         if stop is not None:
@@ -269,6 +280,8 @@ class Plan:
             prm.pcg_max, prm.pcg_tol = int(pcg[0]), float(pcg[1])
         bout = (ctypes.c_int * max(1, iters))() if track else None
         prm.pcg_steps_out = ctypes.cast(bout, _lib.c_int_p) if track else None
+        dout = (ctypes.c_double * (iters + 1))() if track else None
+        prm.delta_out = ctypes.cast(dout, _lib.c_dbl_p) if track else None
         zshape = (self.N, self.N) if implicit else (self.bands, self.N, self.N)
         zp = ctypes.c_void_p() if z is None else _dev(z, "z", zshape)
         rn = (ctypes.c_double * max(1, iters))() if track else None
@@ -280,7 +293,8 @@ class Plan:
         check(status, "mlba_restore")
         info = RestoreInfo(status, done.value, list(rn[:done.value]) if track else [],
                            list(aout[:done.value]) if track else [],
-                           list(bout[:done.value]) if (track and method == _lib.METHOD_ALG2) else [])
+                           list(bout[:done.value]) if (track and method == _lib.METHOD_ALG2) else [],
+                           list(dout[:done.value + 1]) if track else [])
         return out, info
 
 
