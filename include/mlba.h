@@ -263,6 +263,26 @@ int mlba_soft_threshold(const float* z, float* x, int bands, size_t band_elems,
 int mlba_shrink_synthesis(mlba_plan_t plan, const float* omega, const double* mu, int n_mu, double delta,
                           float* f, hipStream_t stream);
 
+/* ---- preconditioner without a plan and without allocation ---------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): t = P_alpha r
+ * exactly as mlba_apply_P computes it for a plan with this PSF, n and
+ * preconditioner (MLBA_PRECOND_BCCB, section 4.1, or MLBA_PRECOND_DCT,
+ * section 4.3), with no plan.  psf: device p x p (p odd, p <= n); r, t: device
+ * n x n (may alias); alpha > 0.  n even, 8 <= n <= MLBA_STATIC_MAX_N,
+ * n = 2^a 3^b 5^c; MLBA_EUNSUPPORTED for larger or other n and for the other
+ * preconditioners, MLBA_EINVAL for bad arguments.  Each call rebuilds the
+ * transform tables and the spectrum of the PSF, then runs the three transform
+ * passes (asynchronous, on `stream`).  Working memory: one static device array
+ * of about 50.5 MB per device, kept from the first call on that device until
+ * the process ends (its address is looked up once per device); the call
+ * allocates nothing.  Every call on a device shares that array, so calls that
+ * overlap on one device (two streams, two host threads) race; calls in order
+ * on one stream do not. */
+#define MLBA_STATIC_MAX_N 2048
+int mlba_apply_P_static(const float* psf, int n, int p, int precond, const float* r, float* t, double alpha,
+                        hipStream_t stream);
+
 /* ---- restoration --------------------------------------------------------
  * Runs params->iters iterations of eq. (MLBA2) from the state z_state
  * (device, in/out: [bands][N][N] for the explicit state, N x N omega for the

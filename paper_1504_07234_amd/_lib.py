@@ -71,6 +71,7 @@ SIGNATURES = {
     "mlba_threshold_synthesis": (c_int, [c_void_p, c_void_p, c_dbl_p, c_int, c_double, c_void_p, c_void_p]),
     "mlba_shrink_synthesis": (c_int, [c_void_p, c_void_p, c_dbl_p, c_int, c_double, c_void_p, c_void_p]),
     "mlba_soft_threshold": (c_int, [c_void_p, c_void_p, c_int, c_size_t, c_dbl_p, c_int, c_double, c_void_p]),
+    "mlba_apply_P_static": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_double, c_void_p]),
     "mlba_restore": (c_int, [c_void_p, c_void_p, ctypes.POINTER(Params), c_void_p, c_void_p, c_dbl_p, c_int_p,
                              c_void_p]),
     "mlba_batch_create": (c_int, [ctypes.POINTER(c_void_p), c_int, ctypes.POINTER(c_void_p), c_int, c_void_p]),

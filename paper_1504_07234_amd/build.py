@@ -37,7 +37,7 @@ COMMON_FLAGS = [
 ]
 
 SOURCES = ["conv.hip", "framelet.hip", "shrink.hip", "fft.hip", "artrans.hip", "fftconv.hip", "reduce.hip",
-           "psfgrad.hip", "mlba.hip", "batch.hip", "unrolled.hip"]
+           "psfgrad.hip", "mlba.hip", "batch.hip", "unrolled.hip", "noalloc.hip"]
 
 
 def _compile(src: str) -> str:

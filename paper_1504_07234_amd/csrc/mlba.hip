@@ -98,6 +98,8 @@ std::vector<float2> fft_table(const FftDesc& d) {
 
 }  // namespace
 
+FftDesc mlba_internal_fft_desc(int n) { return fft_desc(n); }
+
 namespace {
 
 int dalloc(mlba_plan_s* P, void** ptr, size_t bytes) {

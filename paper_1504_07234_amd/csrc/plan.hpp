@@ -7,6 +7,8 @@
 #include "mlba.h"
 
 int mlba_internal_last_hip();
+// Run-time transform plan of length n (mixed radix, or the Bluestein form).
+mlba::FftDesc mlba_internal_fft_desc(int n);
 void mlba_internal_set_hip(hipError_t e);
 
 #define HIPCHK(expr)                         \

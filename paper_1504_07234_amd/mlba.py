@@ -311,6 +311,17 @@ def soft_threshold(z: torch.Tensor, mu, delta: float = 1.0, out=None, stream=Non
     return out
 
 
+def apply_P_static(psf: torch.Tensor, n: int, precond: int, r: torch.Tensor, alpha: float, out=None, stream=None):
+    """t = P_alpha r without a plan and without device allocation (see
+    mlba_apply_P_static): BCCB or DCT, the PSF's spectrum rebuilt per call."""
+    lib = _lib.load()
+    p = psf.shape[0]
+    out = torch.empty((n, n), dtype=torch.float32, device=r.device) if out is None else out
+    check(lib.mlba_apply_P_static(_dev(psf, "psf", (p, p)), int(n), int(p), int(precond), _dev(r, "r", (n, n)),
+                                  _dev(out, "out", (n, n)), float(alpha), _stream(stream)), "mlba_apply_P_static")
+    return out
+
+
 class Batch:
     """Many restorations advanced together (one launch per phase covering all
     images), optionally replayed from a captured hipGraph.  The batch uses the

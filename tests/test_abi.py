@@ -99,3 +99,23 @@ def test_null_arguments_rejected():
     assert lib.mlba_restore(None, None, None, None, None, None, None, None) == _lib.EINVAL
     assert lib.mlba_soft_threshold(None, None, 1, 1, None, 1, 1.0, None) == _lib.EINVAL
     assert lib.mlba_plan_destroy(None) == _lib.EINVAL
+
+
+@pytest.mark.parametrize("n,p,pc,alpha,expect", [
+    (4096, 9, 0, 0.05, _lib.EUNSUPPORTED),  # beyond MLBA_STATIC_MAX_N
+    (2050, 9, 1, 0.05, _lib.EUNSUPPORTED),  # 2050 = 2 * 5^2 * 41: no Bluestein form in the static variant
+    (98, 9, 0, 0.05, _lib.EUNSUPPORTED),    # 98 = 2 * 7^2
+    (126, 9, 0, 0.05, _lib.EUNSUPPORTED),   # 126 = 2 * 3^2 * 7
+    (125, 9, 0, 0.05, _lib.EUNSUPPORTED),   # odd
+    (256, 9, 2, 0.05, _lib.EUNSUPPORTED),   # no preconditioner
+    (256, 9, 3, 0.05, _lib.EUNSUPPORTED),   # antireflective transform
+    (256, 8, 0, 0.05, _lib.EINVAL),         # even PSF side
+    (8, 9, 0, 0.05, _lib.EINVAL),           # PSF larger than the image
+    (256, 9, 0, 0.0, _lib.EINVAL),          # alpha must be positive
+])
+def test_static_preconditioner_rejects_bad_arguments(n, p, pc, alpha, expect):
+    """mlba_apply_P_static validates before any device call."""
+    lib = _lib.load()
+    d = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    assert lib.mlba_apply_P_static(d, n, p, pc, d, d, alpha, None) == expect
+    assert lib.mlba_apply_P_static(None, 64, 9, 0, d, d, 0.05, None) == _lib.EINVAL
