@@ -49,29 +49,30 @@ __host__ __device__ __forceinline__ int lds_slot(int i) { return i + (i >> 3); }
 __host__ __device__ constexpr int lds_data_slots(int elems) { return elems + elems / 8 + 1; }
 __host__ __device__ constexpr size_t lds_bytes(int elems, int n) { return (size_t)lds_data_slots(elems) * 8 + 0 * n; }
 
-// One strided pass of a workgroup over `count` elements, element
-// e = k * kBlock + threadIdx.x: fetch(e) for every element of the thread
+// One strided pass of kBlock threads over `count` elements, element
+// e = k * kBlock + tid (tid: the thread's index among them, by default
+// threadIdx.x): fetch(e) for every element of the thread
 // first, then put(e, value).  With a compile-time COUNT > 0 the pass is
 // unrolled, so a thread's global loads are all in flight together (one
 // memory round trip instead of one per element); COUNT == 0 takes `count`
 // at run time and fetches four elements per round trip.
 template <int COUNT, typename V, typename Fetch, typename Put>
-__device__ __forceinline__ void strided_copy(int count, Fetch fetch, Put put) {
+__device__ __forceinline__ void strided_copy(int count, Fetch fetch, Put put, int tid = threadIdx.x) {
     if constexpr (COUNT > 0) {
         constexpr int PER = (COUNT + kBlock - 1) / kBlock;
         V v[PER];
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
-            const int e = k * kBlock + (int)threadIdx.x;
+            const int e = k * kBlock + tid;
             if (COUNT % kBlock == 0 || e < COUNT) v[k] = fetch(e);
         }
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
-            const int e = k * kBlock + (int)threadIdx.x;
+            const int e = k * kBlock + tid;
             if (COUNT % kBlock == 0 || e < COUNT) put(e, v[k]);
         }
     } else {
-        for (int e0 = threadIdx.x; e0 < count; e0 += 4 * kBlock) {
+        for (int e0 = tid; e0 < count; e0 += 4 * kBlock) {
             V v[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -489,7 +490,7 @@ struct FixedTw {
 // Loads the table entries of every stage (one batch, in flight with the
 // pass's data loads); both directions use them (DIR +1 conjugates).
 template <int N, int S = 0>
-__device__ __forceinline__ void fixed_tw_load(const float2* __restrict__ tw, float2* out) {
+__device__ __forceinline__ void fixed_tw_load(const float2* __restrict__ tw, float2* out, int tid = threadIdx.x) {
     constexpr FixedPlan P = fixed_plan(N);
     if constexpr (S < P.nst) {
         constexpr int R = P.radix[S], NS = P.ns[S];
@@ -498,7 +499,7 @@ __device__ __forceinline__ void fixed_tw_load(const float2* __restrict__ tw, flo
             constexpr int step = N / (NS * R), off = fixed_tw_offset(N, S);
 #pragma unroll
             for (int i = 0; i < MAXB; ++i) {
-                const int j = (int)threadIdx.x + i * kBlock;
+                const int j = tid + i * kBlock;
                 if (nb % kBlock == 0 || j < nb) {
                     const int e = (j % NS) * step;
 #pragma unroll
@@ -506,22 +507,29 @@ __device__ __forceinline__ void fixed_tw_load(const float2* __restrict__ tw, flo
                 }
             }
         }
-        fixed_tw_load<N, S + 1>(tw, out);
+        fixed_tw_load<N, S + 1>(tw, out, tid);
     }
 }
 
-// pre: the stage's slice of fixed_tw_load's output, or null (table reads)
+// pre: the stage's slice of fixed_tw_load's output, or null (table reads).
+// LDS addresses: slot(i + c) = slot(i) + c + c/8 whenever c is a multiple of 8,
+// so when the strides nb and NS are multiples of 8 (or NS == 1 with R a
+// multiple of 8) each butterfly computes one base slot and reaches its R
+// values at compile-time offsets (immediate offsets of the LDS instructions).
+// tid: the thread's index inside the kBlock threads that own the sequence
 template <int R, int DIR, int N, int NS>
 __device__ __forceinline__ void stockham_stage_fixed(float2* buf, const float2* __restrict__ tw,
-                                                     const float2* pre) {
+                                                     const float2* pre, int tid = threadIdx.x) {
     constexpr int nb = N / R;
     constexpr int MAXB = (nb + kBlock - 1) / kBlock;
     constexpr int step = N / (NS * R);
     constexpr int T = tw_table_loads(R);
+    constexpr bool rd_off = nb % 8 == 0;
+    constexpr bool wr_off = NS % 8 == 0 || (NS == 1 && R % 8 == 0);
     float2 v[MAXB][R];
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
-        const int j = (int)threadIdx.x + i * kBlock;
+        const int j = tid + i * kBlock;
         if (nb % kBlock == 0 || j < nb) {
             const int jm = j % NS;
             float2 w[R];
@@ -529,9 +537,10 @@ __device__ __forceinline__ void stockham_stage_fixed(float2* buf, const float2* 
                 if (pre) twiddle_powers_raw<R, DIR>(pre + i * T, w);
                 else twiddle_powers<R, DIR>(tw, jm * step, N, w);
             }
+            const int sb = lds_slot(j);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                float2 x = buf[lds_slot(j + r * nb)];
+                float2 x = rd_off ? buf[sb + r * (nb + nb / 8)] : buf[lds_slot(j + r * nb)];
                 if (r > 0 && jm > 0) x = cmul(x, w[r]);
                 v[i][r] = x;
             }
@@ -541,24 +550,30 @@ __device__ __forceinline__ void stockham_stage_fixed(float2* buf, const float2* 
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
-        const int j = (int)threadIdx.x + i * kBlock;
+        const int j = tid + i * kBlock;
         if (nb % kBlock == 0 || j < nb) {
             const int jm = j % NS;
             const int dst = (j - jm) * R + jm;
+            const int sb = lds_slot(dst);
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[lds_slot(dst + r * NS)] = v[i][r];
+            for (int r = 0; r < R; ++r) {
+                if constexpr (!wr_off) buf[lds_slot(dst + r * NS)] = v[i][r];
+                else if constexpr (NS == 1) buf[sb + r + r / 8] = v[i][r];  // dst = j R, R a multiple of 8
+                else buf[sb + r * (NS + NS / 8)] = v[i][r];
+            }
         }
     }
     __syncthreads();
 }
 
 template <int DIR, int N, int S = 0>
-__device__ __forceinline__ void lds_fft_fixed(float2* buf, const float2* __restrict__ tw, const float2* pre) {
+__device__ __forceinline__ void lds_fft_fixed(float2* buf, const float2* __restrict__ tw, const float2* pre,
+                                              int tid = threadIdx.x) {
     constexpr FixedPlan P = fixed_plan(N);
     if constexpr (S < P.nst) {
         constexpr int off = fixed_tw_offset(N, S);
-        stockham_stage_fixed<P.radix[S], DIR, N, P.ns[S]>(buf, tw, pre ? pre + off : nullptr);
-        lds_fft_fixed<DIR, N, S + 1>(buf, tw, pre);
+        stockham_stage_fixed<P.radix[S], DIR, N, P.ns[S]>(buf, tw, pre ? pre + off : nullptr, tid);
+        lds_fft_fixed<DIR, N, S + 1>(buf, tw, pre, tid);
     }
 }
 
