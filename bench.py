@@ -199,7 +199,8 @@ def batched_section(count: int = 64, iters: int = 100):
     """64 uneven images (sides 128..1024, Gaussian PSFs 9..25, own alpha and
     noise), 2 levels, `iters` iterations: one batched hipGraph replay (tile
     shapes picked by the library's autotuner) against 64 sequential
-    single-image restorations on the same stream."""
+    single-image restorations on the same stream, for the implicit state
+    (omega) and for the explicit one (z)."""
     import torch
 
     import synth
@@ -217,42 +218,48 @@ def batched_section(count: int = 64, iters: int = 100):
         alphas.append(w.alpha0)
         deltas.append(pl.auto_step(w.alpha0))
     outs = [torch.empty(pl.N, pl.N, device="cuda") for pl in plans]
-    torch.cuda.synchronize()
-    # 64 sequential plain solves (eager launches)
-    for pl, g, a, d, o in zip(plans, gs, alphas, deltas, outs):  # warm-up
-        pl.restore(g, alpha=a, mu=1e-3, delta=d, iters=2, out=o, track=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for pl, g, a, d, o in zip(plans, gs, alphas, deltas, outs):
-        pl.restore(g, alpha=a, mu=1e-3, delta=d, iters=iters, out=o, track=False)
-    torch.cuda.synchronize()
-    t_seq = time.perf_counter() - t0
-    seq_ref = [o.clone() for o in outs]
-    # batched: autotune the tile shapes, capture once, then time a replay
+    px = sum(w.n * w.n for w in ws)
     batch = mlba.Batch(plans, max_iters=iters)
     tuned = batch.autotune(reps=5)
-    batch.restore(gs, alpha=alphas, mu=1e-3, delta=deltas, iters=iters, outs=outs, use_graph=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    batch.restore(gs, alpha=alphas, mu=1e-3, delta=deltas, iters=iters, outs=outs, use_graph=True)
-    torch.cuda.synchronize()
-    t_bat = time.perf_counter() - t0
-    identical = all(torch.equal(a, b) for a, b in zip(outs, seq_ref))
-    px = sum(w.n * w.n for w in ws)
+    res = {"images": count, "iters": iters, "observed_pixels": px, "sides": sorted({w.n for w in ws}),
+           "autotuned": {"conv_rows": tuned["conv_rows"], "fft_rows_cap": tuned["fft_rows_cap"],
+                         "fft_cols_cap": tuned["fft_cols_cap"]}}
+    for implicit in (True, False):
+        # 64 sequential single-image solves (eager launches), the same state
+        torch.cuda.synchronize()
+        for pl, g, a, d, o in zip(plans, gs, alphas, deltas, outs):  # warm-up
+            pl.restore(g, alpha=a, mu=1e-3, delta=d, iters=2, out=o, track=False, implicit=implicit)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for pl, g, a, d, o in zip(plans, gs, alphas, deltas, outs):
+            pl.restore(g, alpha=a, mu=1e-3, delta=d, iters=iters, out=o, track=False, implicit=implicit)
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t0
+        seq_ref = [o.clone() for o in outs]
+        # batched: capture once, then time a replay (host submission: one graph launch)
+        batch.restore(gs, alpha=alphas, mu=1e-3, delta=deltas, iters=iters, outs=outs, use_graph=True,
+                      implicit=implicit)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch.restore(gs, alpha=alphas, mu=1e-3, delta=deltas, iters=iters, outs=outs, use_graph=True,
+                      implicit=implicit)
+        t_submit = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        t_bat = time.perf_counter() - t0
+        identical = all(torch.equal(a, b) for a, b in zip(outs, seq_ref))
+        key = "implicit" if implicit else "explicit"
+        res[key] = {
+            "batched_graph_s": round(t_bat, 5), "sequential_s": round(t_seq, 5),
+            "speedup": round(t_seq / t_bat, 3),
+            "batched_Mpx_it_s": round(px * iters / t_bat / 1e6, 1),
+            "sequential_Mpx_it_s": round(px * iters / t_seq / 1e6, 1),
+            "host_submit_ms": round(t_submit * 1e3, 3),
+            "identical_to_sequential": identical,
+        }
     batch.close()
     for pl in plans:
         pl.close()
-    return {
-        "images": count, "iters": iters, "observed_pixels": px,
-        "sides": sorted({w.n for w in ws}),
-        "batched_graph_s": round(t_bat, 5), "sequential_s": round(t_seq, 5),
-        "speedup": round(t_seq / t_bat, 3),
-        "batched_Mpx_it_s": round(px * iters / t_bat / 1e6, 1),
-        "sequential_Mpx_it_s": round(px * iters / t_seq / 1e6, 1),
-        "identical_to_sequential": identical,
-        "autotuned": {"conv_rows": tuned["conv_rows"], "fft_rows_cap": tuned["fft_rows_cap"],
-                      "fft_cols_cap": tuned["fft_cols_cap"]},
-    }
+    return res
 
 
 def unrolled_section(reps: int = 5):

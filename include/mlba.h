@@ -314,22 +314,26 @@ int mlba_restore(mlba_plan_t plan, const float* g, const mlba_params* params,
  * mlba_batch_restore: g, f_out: host arrays of `count` device pointers
  * (image i: n_i x n_i input, N_i x N_i output).  alpha, delta: host arrays of
  * `count` values (delta <= 0: automatic step per image, see mlba_params).
- * mu: host array of count * n_mu values (n_mu = 1 or bands).  z_state: NULL
- * to start every image from z = 0 in its plan's state buffer, or a host array
- * of `count` device pointers ([bands][N_i][N_i], in/out).  rnorm_out:
+ * mu: host array of count * n_mu values (n_mu = 1 or bands).  state:
+ * MLBA_STATE_EXPLICIT (the frame coefficients z) or MLBA_STATE_IMPLICIT (omega
+ * with z = W omega: per iteration the low-pass chain, one shrink-synthesis
+ * launch per level, the blur, the preconditioner and omega += A^T t in the
+ * A^T launch; no analysis).  z_state: NULL to start every image from zero in
+ * its plan's state buffer, or a host array of `count` device pointers
+ * ([bands][N_i][N_i] explicit, [N_i][N_i] implicit; in/out).  rnorm_out:
  * optional host array of count * iters residual norms (synchronous; returns
  * MLBA_WARN_DIVERGED as mlba_restore does).  use_graph != 0: the whole
  * sequence for this iteration count is captured once into a hipGraph on a
  * private stream (first call; instantiation allocates) and replayed on
- * `stream`; later calls with the same count and state mode only update the
- * descriptor table and replay. */
+ * `stream`; later calls with the same iteration count, state mode and
+ * z_state presence only update the descriptor table and replay. */
 typedef struct mlba_batch_s* mlba_batch_t;
 int mlba_batch_create(mlba_batch_t* batch, int count, const mlba_plan_t* plans, int max_iters,
                       hipStream_t stream);
 int mlba_batch_destroy(mlba_batch_t batch);
 int mlba_batch_restore(mlba_batch_t batch, const float* const* g, const double* alpha, const double* mu,
                        int n_mu, const double* delta, int iters, float* const* f_out, float* const* z_state,
-                       double* rnorm_out, int use_graph, hipStream_t stream);
+                       double* rnorm_out, int state, int use_graph, hipStream_t stream);
 
 /* Autotuner of the batch's tile shapes.  Times every candidate of each
  * tunable phase on the batch's own images, `reps` launches each after one

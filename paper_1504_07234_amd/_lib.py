@@ -77,7 +77,8 @@ SIGNATURES = {
     "mlba_batch_create": (c_int, [ctypes.POINTER(c_void_p), c_int, ctypes.POINTER(c_void_p), c_int, c_void_p]),
     "mlba_batch_destroy": (c_int, [c_void_p]),
     "mlba_batch_restore": (c_int, [c_void_p, ctypes.POINTER(c_void_p), c_dbl_p, c_dbl_p, c_int, c_dbl_p, c_int,
-                                   ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_dbl_p, c_int, c_void_p]),
+                                   ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_dbl_p, c_int, c_int,
+                                   c_void_p]),
     "mlba_batch_autotune": (c_int, [c_void_p, c_int, ctypes.POINTER(BatchTuning), c_void_p]),
     "mlba_batch_set_tiles": (c_int, [c_void_p, ctypes.POINTER(BatchTuning), c_void_p]),
     "mlba_unrolled_create": (c_int, [ctypes.POINTER(c_void_p), c_int, ctypes.POINTER(c_void_p), c_int, c_int,

@@ -39,7 +39,7 @@ struct mlba_batch_s {
     std::vector<BatchImage> host;
     BatchImage* imgs = nullptr;
     int* maps = nullptr;  // one device buffer holding every map
-    Map conv_a, conv_at, fold, fill, pre[3], syn[5], ana[5];
+    Map conv_a, conv_at, fold, fill, pre[3], syn[5], ana[5], low[5], shr[5], fill_om;
     // tile choices (set by mlba_batch_autotune)
     int conv_ry[2] = {1, 1};          // output rows per thread of the A and A^T launches
     int rows_want = 0, cols_want = 0;  // transform batching caps (0: built-in choice per size)
@@ -49,7 +49,7 @@ struct mlba_batch_s {
     int rn_cap = 0;
     hipStream_t cap = nullptr;  // private stream for graph capture
     hipGraphExec_t exec = nullptr;
-    int exec_iters = -1, exec_fill = -1;
+    int exec_iters = -1, exec_fill = -1, exec_state = -1;
 };
 
 namespace {
@@ -116,8 +116,14 @@ int configure(mlba_batch_s* B, hipStream_t s) {
     add(B->conv_at, t);
     for (int i = 0; i < count; ++i) t[i] = B->host[i].bc == MLBA_BC_REFLECT ? B->host[i].n : 0;
     add(B->fold, t);
-    for (int i = 0; i < count; ++i) t[i] = fill_tiles(B->host[i]);
-    add(B->fill, t);
+    for (int planes : {-1, 1}) {  // the explicit state (bands planes), then the implicit one (omega)
+        for (int i = 0; i < count; ++i) {
+            BatchImage d = B->host[i];
+            d.state_planes = planes < 0 ? d.bands : planes;
+            t[i] = fill_tiles(d);
+        }
+        add(planes < 0 ? B->fill : B->fill_om, t);
+    }
     for (int pass = 0; pass < 3; ++pass) {
         for (int i = 0; i < count; ++i) t[i] = precond_pass_tiles(B->host[i], pass);
         add(B->pre[pass], t);
@@ -127,6 +133,10 @@ int configure(mlba_batch_s* B, hipStream_t s) {
         add(B->syn[lev], t);
         for (int i = 0; i < count; ++i) t[i] = analysis_level_tiles(B->host[i].N, 1 << (lev - 1));
         add(B->ana[lev], t);
+        for (int i = 0; i < count; ++i) t[i] = lev < B->levels ? lowpass_level_tiles(B->host[i].N) : 0;
+        add(B->low[lev], t);
+        for (int i = 0; i < count; ++i) t[i] = shrink_level_tiles(B->host[i].N, 1 << (lev - 1));
+        add(B->shr[lev], t);
     }
     if (B->exec) {
         HIPCHK(hipGraphExecDestroy(B->exec));
@@ -154,7 +164,46 @@ int configure(mlba_batch_s* B, hipStream_t s) {
     return MLBA_OK;
 }
 
-int enqueue(mlba_batch_s* B, int iters, bool fill_state, hipStream_t s) {
+// u (f when final_out) = W^T(delta S_mu(W omega)) of every image: the low-pass
+// chain, then the shrink-synthesis levels from the top
+int enqueue_shrink_synthesis(mlba_batch_s* B, int final_out, hipStream_t s) {
+    const BatchImage* I = B->imgs;
+    for (int lev = 1; lev < B->levels; ++lev) {
+        const Map& m = B->low[lev];
+        HIPCHK(launch_lowpass_batched(I, m.bmap, m.bfirst, m.nblocks, lev, 1 << (lev - 1), s));
+    }
+    for (int lev = B->levels; lev >= 1; --lev) {
+        const Map& m = B->shr[lev];
+        HIPCHK(launch_shrink_synthesis_batched(I, m.bmap, m.bfirst, m.nblocks, lev, 1 << (lev - 1),
+                                               lev == B->levels ? 1 : 0, final_out, s));
+    }
+    return MLBA_OK;
+}
+
+// Implicit state: per iteration the shrink-synthesis, r = g - A u, t = P r and
+// omega += A^T t (accumulated by the A^T launch, or by the fold of the
+// reflective model); no analysis.
+int enqueue_implicit(mlba_batch_s* B, int iters, bool fill_state, hipStream_t s) {
+    const BatchImage* I = B->imgs;
+    if (fill_state) HIPCHK(launch_fill_batched(I, B->fill_om.bmap, B->fill_om.bfirst, B->fill_om.nblocks, s));
+    for (int k = 0; k < iters; ++k) {
+        STCHK(enqueue_shrink_synthesis(B, 0, s));
+        HIPCHK(launch_conv_batched(I, B->conv_a.bmap, B->conv_a.bfirst, B->conv_a.nblocks, 1, B->pmax, B->partials,
+                                   s, B->conv_ry[0]));
+        HIPCHK(launch_sum_partials_batched(I, B->partials, B->pcount, B->count, k, s));
+        if (B->precond != MLBA_PRECOND_NONE)
+            for (int pass = 0; pass < 3; ++pass)
+                HIPCHK(launch_precond_batched(I, B->pre[pass].bmap, B->pre[pass].bfirst, B->pre[pass].nblocks, pass,
+                                              B->precond, B->nmax, s, B->any_len));
+        HIPCHK(launch_conv_batched(I, B->conv_at.bmap, B->conv_at.bfirst, B->conv_at.nblocks, 0, B->pmax, nullptr,
+                                   s, B->conv_ry[1]));
+        if (B->any_reflect) HIPCHK(launch_fold_batched(I, B->fold.bmap, B->fold.bfirst, B->fold.nblocks, s));
+    }
+    return enqueue_shrink_synthesis(B, 1, s);
+}
+
+int enqueue(mlba_batch_s* B, int iters, bool fill_state, bool implicit, hipStream_t s) {
+    if (implicit) return enqueue_implicit(B, iters, fill_state, s);
     const BatchImage* I = B->imgs;
     if (fill_state) HIPCHK(launch_fill_batched(I, B->fill.bmap, B->fill.bfirst, B->fill.nblocks, s));
     for (int k = 0; k < iters; ++k) {
@@ -372,8 +421,10 @@ int mlba_batch_destroy(mlba_batch_t B) {
 
 int mlba_batch_restore(mlba_batch_t B, const float* const* g, const double* alpha, const double* mu, int n_mu,
                        const double* delta, int iters, float* const* f_out, float* const* z_state, double* rnorm_out,
-                       int use_graph, hipStream_t s) {
+                       int state, int use_graph, hipStream_t s) {
     if (!B || !g || !alpha || !mu || !delta || !f_out || iters < 0 || iters > B->rn_cap) return MLBA_EINVAL;
+    if (state != MLBA_STATE_EXPLICIT && state != MLBA_STATE_IMPLICIT) return MLBA_EINVAL;
+    const bool implicit = state == MLBA_STATE_IMPLICIT;
     const int count = B->count;
     const int bands = 8 * B->levels + 1;
     if (n_mu != 1 && n_mu != bands) return MLBA_EINVAL;
@@ -392,21 +443,37 @@ int mlba_batch_restore(mlba_batch_t B, const float* const* g, const double* alph
         }
         d.g = g[i];
         d.f = f_out[i];
-        d.z = z_state ? z_state[i] : B->plans[i]->z;
+        if (implicit) {
+            d.z = z_state ? z_state[i] : B->plans[i]->omega;
+            d.w = d.z;  // omega += A^T t
+            d.blur_acc = 1;
+            d.state_planes = 1;
+            for (int lev = 1; lev <= B->levels; ++lev) {
+                LevelMu lm;
+                lm.low = d.mu[0];
+                for (int q = 0; q < 8; ++q) lm.band[q] = d.mu[1 + 8 * (lev - 1) + q];
+                d.ss[lev - 1] = ss_coef(lm, d.delta, lev < B->levels);
+            }
+        } else {
+            d.z = z_state ? z_state[i] : B->plans[i]->z;
+            d.w = B->plans[i]->w;
+            d.blur_acc = 0;
+            d.state_planes = d.bands;
+        }
         d.zin = d.z;
         if (!d.z) return MLBA_EINVAL;
     }
     HIPCHK(hipMemcpyAsync(B->imgs, B->host.data(), count * sizeof(BatchImage), hipMemcpyHostToDevice, s));
     const bool fill_state = z_state == nullptr;
     if (use_graph) {
-        if (!B->exec || B->exec_iters != iters || B->exec_fill != (int)fill_state) {
+        if (!B->exec || B->exec_iters != iters || B->exec_fill != (int)fill_state || B->exec_state != state) {
             if (B->exec) {
                 HIPCHK(hipGraphExecDestroy(B->exec));
                 B->exec = nullptr;
             }
             hipGraph_t graph = nullptr;
             HIPCHK(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
-            const int st = enqueue(B, iters, fill_state, B->cap);
+            const int st = enqueue(B, iters, fill_state, implicit, B->cap);
             hipError_t e = hipStreamEndCapture(B->cap, &graph);
             if (st < 0) {
                 if (graph) hipGraphDestroy(graph);
@@ -418,10 +485,11 @@ int mlba_batch_restore(mlba_batch_t B, const float* const* g, const double* alph
             HIPCHK(e);
             B->exec_iters = iters;
             B->exec_fill = (int)fill_state;
+            B->exec_state = state;
         }
         HIPCHK(hipGraphLaunch(B->exec, s));
     } else {
-        STCHK(enqueue(B, iters, fill_state, s));
+        STCHK(enqueue(B, iters, fill_state, implicit, s));
     }
     if (rnorm_out && iters > 0) {
         std::vector<double> buf((size_t)count * B->rn_cap);

@@ -382,7 +382,7 @@ __global__ __launch_bounds__(kBlock) void fold_batched_kernel(const BatchImage* 
     const BatchImage& I = imgs[im];
     const int y = blockIdx.x - bfirst[im];
     const int m = I.n + I.p - 1;
-    for (int x = threadIdx.x; x < I.n; x += kBlock) fold_pixel(I.wext, m, I.w, I.n, I.c, y, x);
+    for (int x = threadIdx.x; x < I.n; x += kBlock) fold_pixel(I.wext, m, I.w, I.n, I.c, y, x, I.blur_acc);
 }
 
 hipError_t launch_fold_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks,

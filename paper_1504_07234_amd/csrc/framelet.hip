@@ -466,7 +466,7 @@ hipError_t launch_analysis_batched(const BatchImage* imgs, const int* bmap, cons
 constexpr int FILL_CHUNK = kBlock * 1024;
 
 int fill_tiles(const BatchImage& I) {
-    const size_t count = (size_t)I.bands * I.N * I.N;
+    const size_t count = (size_t)I.state_planes * I.N * I.N;
     return (int)((count + FILL_CHUNK - 1) / FILL_CHUNK);
 }
 
@@ -476,7 +476,7 @@ __global__ __launch_bounds__(kBlock) void fill_batched_kernel(const BatchImage* 
     const int xb = xcd_block(blockIdx.x, gridDim.x);  // adjacent tiles of an image in one L2
     const int im = bmap[xb];
     const BatchImage& I = imgs[im];
-    const size_t count = (size_t)I.bands * I.N * I.N;
+    const size_t count = (size_t)I.state_planes * I.N * I.N;
     const size_t beg = (size_t)(xb - bfirst[im]) * FILL_CHUNK;
     const size_t end = beg + FILL_CHUNK < count ? beg + FILL_CHUNK : count;
     for (size_t i = beg + threadIdx.x; i < end; i += kBlock) I.z[i] = 0.0f;

@@ -35,6 +35,17 @@ struct BandMu {
     float v[64];
 };
 
+// Shrink-synthesis coefficients of one level (implicit state): per band (i, j)
+// the threshold of the coefficient computed with the unnormalised masks and
+// its synthesis weight (see shrink.hip).
+struct SsCoef {
+    float thr[3][3];
+    float wgt[3][3];
+};
+// The coefficients of a level from its thresholds and the step; from_above:
+// the (0, 0) input is the output of the level above (unthresholded).
+SsCoef ss_coef(const LevelMu& mu, float delta, bool from_above);
+
 // One blur: dst[y][x] = (g ? g[y][x] - s : (acc ? dst[y][x] + s : s)) over D x D
 // outputs, s = sum_{a,b} K[a][b] src_ext[y+org+a][x+org+b] (src S x S, extension ext).
 struct ConvJob {
@@ -72,6 +83,14 @@ struct BatchImage {
     const float2* tw;
     const float2* dtw;
     double* rn;  // ||r^k||^2 per iteration
+    // implicit state (z = W omega): z holds omega (state_planes = 1, else
+    // bands); the A^T blur accumulates into w (= omega) when blur_acc; the
+    // low-pass chain low_1 .. low_{levels-1}; the shrink-synthesis
+    // coefficients of levels 1 .. levels
+    int state_planes;
+    int blur_acc;
+    float* lows[3];
+    SsCoef ss[4];
     // reverse sweep of unrolled iterations (null elsewhere)
     float2* sstore;      // the preconditioner's filtered spectrum is stored here ([n/2+1][n])
     const float2* sfwd;  // filtered spectrum of the forward step being reversed
@@ -126,6 +145,7 @@ __host__ __device__ inline ConvJob blurT_job(const BatchImage& I) {
         j.dst = I.w;
         j.D = I.n;
     }
+    if (j.dst == I.w) j.acc = I.blur_acc;  // the reflective model accumulates in its fold
     return j;
 }
 
@@ -228,6 +248,15 @@ hipError_t launch_lowpass_level(const float* v, int N, int d, float* out, hipStr
 // the level above, or null at the top level (thresholded low-pass)
 // low1 = (b0 x b0) v, low2 = (b0 x b0) low1 (dilations 1 and 2) in one pass
 hipError_t launch_lowpass_two_levels(const float* v, int N, float* low1, float* low2, hipStream_t s);
+// batched implicit state: level `lev` of the low-pass chain (low_lev from
+// low_{lev-1}, dilation d = 2^(lev-1)) and the shrink-synthesis of level lev
+// (final_out: level 1 writes f instead of u), over the tiles of all images
+int lowpass_level_tiles(int N);
+int shrink_level_tiles(int N, int d);
+hipError_t launch_lowpass_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks, int lev,
+                                  int d, hipStream_t s);
+hipError_t launch_shrink_synthesis_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks,
+                                           int lev, int d, int top, int final_out, hipStream_t s);
 hipError_t launch_shrink_synthesis_level(const float* low, const float* s_in, int N, int d, float* out,
                                          LevelMu mu, float delta, hipStream_t s);
 // batched framelet levels (all images share `levels`); tiles per image:

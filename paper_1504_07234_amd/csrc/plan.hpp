@@ -115,6 +115,9 @@ inline mlba::BatchImage plan_desc(const mlba_plan_s* P) {
     d.tw = P->tw;
     d.dtw = P->dtw;
     d.fd = P->fd;
+    d.state_planes = P->bands;
+    d.blur_acc = 0;
+    for (int l = 0; l < 3; ++l) d.lows[l] = P->lows[l];
     if (P->precond == MLBA_PRECOND_AR) {  // one row pair per workgroup
         d.fft_rows_g = d.fft_cols_c = 1;
         d.fft_rows_shift = d.fft_cols_shift = mlba::fft_seq_shift(1);

@@ -22,12 +22,13 @@ namespace mlba {
 // synthesis transposes need (the sign flips of synthesis_tile come out of the
 // arithmetic), and no other boundary logic is required.
 
-// low_out = (b0 x b0) v with dilation D: the (0,0) band of analysis_tile
+// low_out = (b0 x b0) v with dilation D: the (0,0) band of analysis_tile,
+// over the AN_TY-row strip by of the kBlock-column block bx
 template <int D>
-__global__ __launch_bounds__(kBlock) void lowpass_level_kernel(const float* __restrict__ v, int N,
-                                                               float* __restrict__ out) {
-    const int x = blockIdx.x * kBlock + threadIdx.x;
-    const int y0 = blockIdx.y * AN_TY;
+__device__ __forceinline__ void lowpass_tile(const float* __restrict__ v, int N, float* __restrict__ out, int bx,
+                                             int by) {
+    const int x = bx * kBlock + threadIdx.x;
+    const int y0 = by * AN_TY;
     if (x >= N) return;
     const int rows = min(AN_TY, N - y0);
     const int xl = reflect_index(x - D, N), xr = reflect_index(x + D, N);
@@ -42,6 +43,12 @@ __global__ __launch_bounds__(kBlock) void lowpass_level_kernel(const float* __re
         if (r >= rows) break;
         out[(size_t)(y0 + r) * N + x] = fmaf(0.25f, h0[r] + h0[r + 2 * D], 0.5f * h0[r + D]);
     }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void lowpass_level_kernel(const float* __restrict__ v, int N,
+                                                               float* __restrict__ out) {
+    lowpass_tile<D>(v, N, out, blockIdx.x, blockIdx.y);
 }
 
 // low_1 = (b0 x b0) v (dilation 1) and low_2 = (b0 x b0) low_1 (dilation 2)
@@ -137,11 +144,7 @@ struct SsTile {
 // level the (0, 0) input is the level above's output itself, weighted by
 // c_0^2 only.
 // Per band (i, j): the threshold of the unnormalised coefficient and its
-// synthesis weight (computed on the host).
-struct SsCoef {
-    float thr[3][3];
-    float wgt[3][3];
-};
+// synthesis weight (SsCoef, computed on the host by ss_coef).
 
 template <int D, int TY, bool SIN>
 __device__ __forceinline__ void shrink_synthesis_tile(const float* __restrict__ low, const float* __restrict__ s_in,
@@ -291,11 +294,7 @@ hipError_t launch_lowpass_level(const float* v, int N, int d, float* out, hipStr
     return hipGetLastError();
 }
 
-template <int D>
-static hipError_t launch_ss(const float* low, const float* s_in, int N, float* out, LevelMu mu, float delta,
-                            hipStream_t s) {
-    constexpr int IW = kBlock - 2 * D;
-    constexpr int TY = ss_rows<D>();
+SsCoef ss_coef(const LevelMu& mu, float delta, bool from_above) {
     const double cs[3] = {0.25, 0.35355339059327376, 0.25};  // c_i of b_i = c_i m_i
     SsCoef cf;
     for (int i = 0; i < 3; ++i)
@@ -305,14 +304,108 @@ static hipError_t launch_ss(const float* low, const float* s_in, int N, float* o
             cf.thr[i][j] = (float)(m / cc);
             cf.wgt[i][j] = (float)(delta * cc * cc);
         }
+    if (from_above) cf.wgt[0][0] = 0.0625f;  // c_0^2: the level above's output enters unthresholded
+    return cf;
+}
+
+template <int D>
+static hipError_t launch_ss(const float* low, const float* s_in, int N, float* out, LevelMu mu, float delta,
+                            hipStream_t s) {
+    constexpr int IW = kBlock - 2 * D;
+    constexpr int TY = ss_rows<D>();
+    const SsCoef cf = ss_coef(mu, delta, s_in != nullptr);
     dim3 grid((N + IW - 1) / IW, (N + TY - 1) / TY);
-    if (s_in) {
-        cf.wgt[0][0] = 0.0625f;  // c_0^2: the level above's output enters unthresholded
+    if (s_in)
         hipLaunchKernelGGL((shrink_synthesis_kernel<D, true>), grid, dim3(kBlock), 0, s, low, s_in, N, out, cf);
-    } else {
+    else
         hipLaunchKernelGGL((shrink_synthesis_kernel<D, false>), grid, dim3(kBlock), 0, s, low, s_in, N, out, cf);
+    return hipGetLastError();
+}
+
+// ---- batched implicit state --------------------------------------------
+// The tiles of many images per launch (workgroup -> image bmap[b], local tile
+// b - bfirst[image]), each running the single-image tile body on its image's
+// buffers, so that every image gets exactly its own plan's arithmetic.
+
+int lowpass_level_tiles(int N) { return ((N + kBlock - 1) / kBlock) * ((N + AN_TY - 1) / AN_TY); }
+
+int shrink_level_tiles(int N, int d) {
+    const int iw = kBlock - 2 * d;
+    return ((N + iw - 1) / iw) * ((N + 8 - 1) / 8);
+}
+
+// low_lev = (b0 x b0) low_{lev-1}, low_0 = omega (the state z)
+template <int D>
+__global__ __launch_bounds__(kBlock) void lowpass_batched_kernel(const BatchImage* __restrict__ imgs,
+                                                                 const int* __restrict__ bmap,
+                                                                 const int* __restrict__ bfirst, int lev) {
+    const int xb = xcd_block(blockIdx.x, gridDim.x);
+    const int im = bmap[xb];
+    const BatchImage& I = imgs[im];
+    const float* in = lev == 1 ? I.zin : I.lows[lev - 2];
+    const int gx = (I.N + kBlock - 1) / kBlock;
+    const int local = xb - bfirst[im];
+    const int by = local / gx;
+    lowpass_tile<D>(in, I.N, I.lows[lev - 1], local - by * gx, by);
+}
+
+hipError_t launch_lowpass_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks, int lev,
+                                  int d, hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    switch (d) {
+        case 1: hipLaunchKernelGGL(lowpass_batched_kernel<1>, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst, lev); break;
+        case 2: hipLaunchKernelGGL(lowpass_batched_kernel<2>, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst, lev); break;
+        case 4: hipLaunchKernelGGL(lowpass_batched_kernel<4>, dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap, bfirst, lev); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// Level lev of W^T(delta S_mu(W omega)) as the single-image sequence runs it:
+// the bands of low_{lev-1} (omega at level 1), the level above's output
+// (tmp[(lev + 1) & 1]) below the top, the output to tmp[lev & 1], or at level 1
+// to u (f for the final image).
+template <int D, bool SIN>
+__global__ __launch_bounds__(kBlock) void shrink_synthesis_batched_kernel(const BatchImage* __restrict__ imgs,
+                                                                          const int* __restrict__ bmap,
+                                                                          const int* __restrict__ bfirst, int lev,
+                                                                          int final_out) {
+    constexpr int TY = ss_rows<D>();
+    __shared__ float lds[SsTile<D, TY>::LDS_FLOATS];
+    const int xb = xcd_block(blockIdx.x, gridDim.x);
+    const int im = bmap[xb];
+    const BatchImage& I = imgs[im];
+    const float* low = lev == 1 ? I.zin : I.lows[lev - 2];
+    const float* s_in = SIN ? (((lev + 1) & 1) ? I.tmp1 : I.tmp0) : nullptr;
+    float* out = lev == 1 ? (final_out ? I.f : I.u) : ((lev & 1) ? I.tmp1 : I.tmp0);
+    const int gx = (I.N + SsTile<D, TY>::IW - 1) / SsTile<D, TY>::IW;
+    const int local = xb - bfirst[im];
+    const int by = local / gx;
+    shrink_synthesis_tile<D, TY, SIN>(low, s_in, I.N, out, I.ss[lev - 1], local - by * gx, by, lds);
+}
+
+template <int D>
+static hipError_t launch_ssb(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks, int lev,
+                             int top, int final_out, hipStream_t s) {
+    if (top)
+        hipLaunchKernelGGL((shrink_synthesis_batched_kernel<D, false>), dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap,
+                           bfirst, lev, final_out);
+    else
+        hipLaunchKernelGGL((shrink_synthesis_batched_kernel<D, true>), dim3(nblocks), dim3(kBlock), 0, s, imgs, bmap,
+                           bfirst, lev, final_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_shrink_synthesis_batched(const BatchImage* imgs, const int* bmap, const int* bfirst, int nblocks,
+                                           int lev, int d, int top, int final_out, hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    switch (d) {
+        case 1: return launch_ssb<1>(imgs, bmap, bfirst, nblocks, lev, top, final_out, s);
+        case 2: return launch_ssb<2>(imgs, bmap, bfirst, nblocks, lev, top, final_out, s);
+        case 4: return launch_ssb<4>(imgs, bmap, bfirst, nblocks, lev, top, final_out, s);
+        case 8: return launch_ssb<8>(imgs, bmap, bfirst, nblocks, lev, top, final_out, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_shrink_synthesis_level(const float* low, const float* s_in, int N, int d, float* out,

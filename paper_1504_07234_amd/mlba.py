@@ -371,8 +371,9 @@ class Batch:
         check(self._lib.mlba_batch_set_tiles(self._h, ctypes.byref(t), _stream(stream)), "mlba_batch_set_tiles")
 
     def restore(self, gs, *, alpha, mu=1e-3, delta=None, iters: int = 100, outs=None, zs=None,
-                use_graph: bool = True, track: bool = False, stream=None):
-        """Returns (list of restored images, residual norms [count][iters] or None)."""
+                use_graph: bool = True, track: bool = False, implicit: bool = False, stream=None):
+        """Returns (list of restored images, residual norms [count][iters] or None).
+        implicit: keep omega (z = W omega, zs [N, N] per image) instead of z."""
         count = len(self.plans)
         if len(gs) != count:
             raise ValueError("one observed image per plan")
@@ -381,7 +382,8 @@ class Batch:
         fp = (ctypes.c_void_p * count)(*[_dev(f, "f", (p.N, p.N)).value for f, p in zip(outs, self.plans)])
         zp = None
         if zs is not None:
-            zp = (ctypes.c_void_p * count)(*[_dev(z, "z", (p.bands, p.N, p.N)).value for z, p in zip(zs, self.plans)])
+            zp = (ctypes.c_void_p * count)(*[_dev(z, "z", (p.N, p.N) if implicit else (p.bands, p.N, p.N)).value
+                                             for z, p in zip(zs, self.plans)])
         alphas = [alpha] * count if isinstance(alpha, (int, float)) else list(alpha)
         deltas = [0.0] * count if delta is None else ([delta] * count if isinstance(delta, (int, float)) else list(delta))
         if isinstance(mu, (int, float)):
@@ -395,8 +397,9 @@ class Batch:
         darr, dp = _dbl_array(deltas)
         rn = (ctypes.c_double * (count * max(iters, 1)))() if track else None
         st = self._lib.mlba_batch_restore(self._h, gp, ap, mp, n_mu, dp, int(iters), fp, zp,
-                                          ctypes.cast(rn, _lib.c_dbl_p) if track else None, int(bool(use_graph)),
-                                          _stream(stream))
+                                          ctypes.cast(rn, _lib.c_dbl_p) if track else None,
+                                          _lib.STATE_IMPLICIT if implicit else _lib.STATE_EXPLICIT,
+                                          int(bool(use_graph)), _stream(stream))
         check(st, "mlba_batch_restore")
         norms = None
         if track:

@@ -13,7 +13,7 @@ import pytest
 import synth
 from oracle import blur as oblur
 from oracle import mlba as omlba
-from tests._util import announce, cuda, host, rel_err
+from tests._util import announce, cuda, host, max_err, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -251,5 +251,76 @@ def test_batched_bluestein_sizes(mlba, precond):
                       iters)["f"]
     print(f"  image 0 vs oracle {rel_err(got, want):.2e}", flush=True)
     assert rel_err(got, want) < 1e-4
+    for pl in plans:
+        pl.close()
+
+
+@pytest.mark.parametrize("levels,precond,bcs", [(2, 0, None), (3, 0, [0, 3, 2, 4, 0, 0, 3, 0]),
+                                                (3, 1, [1, 0, 1, 3, 1, 0, 1, 3]), (1, 0, None)])
+def test_batched_implicit_equals_per_image(mlba, levels, precond, bcs):
+    """The implicit state (omega, z = W omega; the low-pass chain, the
+    shrink-synthesis levels and omega += A^T t in the A^T launch) batched over
+    uneven images equals per-image implicit restorations bit for bit, eager and
+    from the graph, with the residual-norm histories."""
+    import torch
+    announce(f"batched implicit == per-image implicit (levels={levels}, precond={precond})")
+    specs = SIZES if precond == 0 else [(64, 9), (96, 7), (128, 15), (192, 9), (72, 5), (160, 13), (96, 11), (64, 3)]
+    plans, gs, _ = _make(mlba, specs, levels=levels, precond=precond, bcs=bcs)
+    iters = 12
+    alphas = [0.03 + 0.02 * i for i in range(len(plans))]
+    deltas = [0.15 + 0.01 * i for i in range(len(plans))]
+    mus = [1e-3 * (1 + i % 3) for i in range(len(plans))]
+    gdev = [cuda(g) for g in gs]
+    ref = []
+    for pl, g, a, d, m in zip(plans, gdev, alphas, deltas, mus):
+        f, info = pl.restore(g, alpha=a, mu=m, delta=d, iters=iters, implicit=True)
+        ref.append((f.clone(), info.rnorm))
+    with mlba.Batch(plans, max_iters=iters) as batch:
+        for use_graph in (False, True, True):
+            outs, norms = batch.restore(gdev, alpha=alphas, mu=mus, delta=deltas, iters=iters, use_graph=use_graph,
+                                        track=True, implicit=True)
+            torch.cuda.synchronize()
+            for i, (f_ref, rn_ref) in enumerate(ref):
+                assert torch.equal(outs[i], f_ref), (use_graph, i)
+                assert np.allclose(norms[i], rn_ref, rtol=1e-12, atol=0), (use_graph, i)
+        # the explicit state again on the same batch (descriptors and graph switch back)
+        eo, _ = batch.restore(gdev, alpha=alphas, mu=mus, delta=deltas, iters=iters, use_graph=True)
+        for i, (pl, g, a, d, m) in enumerate(zip(plans, gdev, alphas, deltas, mus)):
+            fe, _ = pl.restore(g, alpha=a, mu=m, delta=d, iters=iters)
+            assert torch.equal(eo[i], fe), ("explicit after implicit", i)
+    for pl in plans:
+        pl.close()
+
+
+def test_batched_implicit_against_oracle_and_resume(mlba):
+    """Batched implicit restorations against the FP64 oracle (1e-4, image and
+    residual norms, element-wise bar too), and caller-owned omega states: 5 + 7
+    iterations equal 12."""
+    import torch
+    announce("batched implicit vs FP64 oracle, resume")
+    specs = [(64, 9), (96, 17), (192, 11), (128, 25)]
+    plans, gs, Hs = _make(mlba, specs)
+    iters = 30
+    alphas = [0.05, 0.1, 0.03, 0.08]
+    deltas = [omlba.delta_auto(omlba.opnorm(H, n, 0, 0, a)) for (n, p), H, a in zip(specs, Hs, alphas)]
+    gdev = [cuda(g) for g in gs]
+    with mlba.Batch(plans, max_iters=iters) as batch:
+        outs, norms = batch.restore(gdev, alpha=alphas, mu=1e-3, delta=deltas, iters=iters, use_graph=True,
+                                    track=True, implicit=True)
+        got = [host(o) for o in outs]
+        full, _ = batch.restore(gdev, alpha=alphas, mu=1e-3, delta=deltas, iters=12, use_graph=False, implicit=True)
+        full = [f.clone() for f in full]
+        zs = [torch.zeros(p.N, p.N, device="cuda") for p in plans]
+        batch.restore(gdev, alpha=alphas, mu=1e-3, delta=deltas, iters=5, zs=zs, use_graph=True, implicit=True)
+        res, _ = batch.restore(gdev, alpha=alphas, mu=1e-3, delta=deltas, iters=7, zs=zs, use_graph=True,
+                               implicit=True)
+        torch.cuda.synchronize()
+        for i in range(len(plans)):
+            assert torch.equal(res[i], full[i]), i
+    for i, ((n, p), H, g) in enumerate(zip(specs, Hs, gs)):
+        ref = omlba.mlba(g, H, 0, 0, 2, np.full(iters, alphas[i]), np.full(iters + 1, deltas[i]), 1e-3, iters)
+        print(f"  image {i}: rel {rel_err(got[i], ref['f']):.2e} max {max_err(got[i], ref['f']):.2e}", flush=True)
+        assert rel_err(got[i], ref["f"]) < 1e-4 and max_err(got[i], ref["f"]) < 1e-4
+        assert rel_err(norms[i], ref["rnorm"]) < 1e-4
     for pl in plans:
         pl.close()
