@@ -33,7 +33,9 @@
  *     mlba_plan_create / mlba_plan_destroy / mlba_batch_create /
  *     mlba_batch_destroy / mlba_unrolled_create / mlba_unrolled_destroy
  *     allocate no device memory (graph instantiation aside, see
- *     mlba_batch_restore).
+ *     mlba_batch_restore).  Each object records a completion event on the
+ *     stream of every call that enqueues work on its buffers; its destroy
+ *     call waits for that event (not for the whole device), then frees.
  *   - Errors: every call returns an int status.  Negative values are
  *     errors (nothing was enqueued), MLBA_WARN_DIVERGED is a warning.
  *     No C++ exception crosses this interface.
@@ -110,8 +112,9 @@ typedef struct mlba_alpha_schedule {
  * beta_n = min{pcg_max, beta_tol} steps of CG preconditioned by the plan's
  * (C C^T + alpha I)^{-1} (BCCB or DCT), started from zero; beta_tol is the first
  * step whose preconditioned relative residual sqrt(res^T M^-1 res / r^T M^-1 r)
- * is at most pcg_tol (eq. bet; the paper: 5 and 1e-3).  One scalar is read
- * back per CG step. */
+ * is at most pcg_tol (eq. bet; the paper: 5 and 1e-3).  The stopping test
+ * runs on the device: every iteration enqueues pcg_max CG steps and the steps
+ * after the stop leave t unchanged (no host round trip; iters <= 65536). */
 #define MLBA_METHOD_ALG2 2
 
 /* Discrepancy-principle stop, eq. (discrpr): stop at the first k with
@@ -309,7 +312,9 @@ int mlba_restore(mlba_plan_t plan, const float* g, const mlba_params* params,
  * `levels` and the preconditioner kind); the batch uses each plan's workspace
  * and state buffer, so those plans must not run other work while the batch
  * runs.  max_iters bounds the iteration count of one call.  Allocates the
- * batch's descriptor table, tile maps and norm buffers (synchronous).
+ * batch's descriptor table, norm buffers and tile maps, the maps sized for
+ * the tile choice with the most workgroups, so that mlba_batch_autotune and
+ * mlba_batch_set_tiles allocate nothing (synchronous).
  *
  * mlba_batch_restore: g, f_out: host arrays of `count` device pointers
  * (image i: n_i x n_i input, N_i x N_i output).  alpha, delta: host arrays of

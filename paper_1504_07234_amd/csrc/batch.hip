@@ -39,6 +39,7 @@ struct mlba_batch_s {
     std::vector<BatchImage> host;
     BatchImage* imgs = nullptr;
     int* maps = nullptr;  // one device buffer holding every map
+    size_t maps_cap = 0;  // its size in ints: the largest over every tile choice
     Map conv_a, conv_at, fold, fill, pre[3], syn[5], ana[5], low[5], shr[5], fill_om;
     // tile choices (set by mlba_batch_autotune)
     int conv_ry[2] = {1, 1};          // output rows per thread of the A and A^T launches
@@ -50,11 +51,13 @@ struct mlba_batch_s {
     hipStream_t cap = nullptr;  // private stream for graph capture
     hipGraphExec_t exec = nullptr;
     int exec_iters = -1, exec_fill = -1, exec_state = -1;
+    hipEvent_t done = nullptr;  // recorded after every call that enqueues work
 };
 
 namespace {
 
 void destroy_batch(mlba_batch_s* B) {
+    if (B->done) hipEventDestroy(B->done);
     if (B->exec) hipGraphExecDestroy(B->exec);
     if (B->cap) hipStreamDestroy(B->cap);
     hipFree(B->imgs);
@@ -81,9 +84,11 @@ void build_map(const std::vector<int>& tiles, std::vector<int>& host_maps, std::
 }
 
 // Applies the batch's tile choices: per-image transform batching and residual
-// partial offsets, every phase map (device buffer rebuilt), descriptors and
-// partial counts uploaded.  Drops a captured graph (its maps are stale).
-int configure(mlba_batch_s* B, hipStream_t s) {
+// partial offsets, every phase map (uploaded into the map buffer allocated at
+// creation for the largest choice), descriptors and partial counts uploaded.
+// Drops a captured graph (its maps are stale).  dry_run: only returns the
+// map size in ints through *ints (nothing is uploaded).
+int configure(mlba_batch_s* B, hipStream_t s, bool dry_run = false, size_t* ints = nullptr) {
     const int count = B->count;
     int pbase = 0;
     std::vector<int> pcount(count);
@@ -138,20 +143,14 @@ int configure(mlba_batch_s* B, hipStream_t s) {
         for (int i = 0; i < count; ++i) t[i] = shrink_level_tiles(B->host[i].N, 1 << (lev - 1));
         add(B->shr[lev], t);
     }
+    if (dry_run) {
+        *ints = hm.size();
+        return MLBA_OK;
+    }
+    if (hm.size() > B->maps_cap) return MLBA_EINVAL;  // cannot happen: sized for the largest choice
     if (B->exec) {
         HIPCHK(hipGraphExecDestroy(B->exec));
         B->exec = nullptr;
-    }
-    if (B->maps) {
-        HIPCHK(hipStreamSynchronize(s));  // work still reading the old maps
-        HIPCHK(hipFree(B->maps));
-        B->maps = nullptr;
-    }
-    hipError_t e = hipMalloc(&B->maps, hm.size() * sizeof(int));
-    if (e != hipSuccess) {
-        mlba_internal_set_hip(e);
-        B->maps = nullptr;
-        return MLBA_ENOMEM;
     }
     for (size_t q = 0; q < order.size(); ++q) {
         order[q]->bmap = B->maps + offs[2 * q];
@@ -307,7 +306,28 @@ int mlba_batch_create(mlba_batch_t* batch, int count, const mlba_plan_t* plans, 
         return MLBA_ENOMEM;
     }
     for (int i = 0; i < count; ++i) B->host[i].rn = B->rn + (size_t)i * max_iters;
-    int st = configure(B, s);
+    // the map buffer for the tile choice with the most workgroups in every
+    // phase (one output row per thread, one row pair and one column per
+    // transform workgroup), so that changing the choice allocates nothing
+    B->conv_ry[0] = B->conv_ry[1] = 1;
+    B->rows_want = B->cols_want = 1;
+    size_t need = 0, need0 = 0;
+    int st = configure(B, s, true, &need);
+    B->rows_want = B->cols_want = 0;
+    if (st >= 0) st = configure(B, s, true, &need0);
+    if (st < 0) {
+        destroy_batch(B);
+        return st;
+    }
+    B->maps_cap = std::max(need, need0);
+    e = hipMalloc(&B->maps, B->maps_cap * sizeof(int));
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&B->done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        mlba_internal_set_hip(e);
+        destroy_batch(B);
+        return MLBA_ENOMEM;
+    }
+    st = configure(B, s);
     if (st < 0) {
         destroy_batch(B);
         return st;
@@ -414,7 +434,7 @@ int mlba_batch_set_tiles(mlba_batch_t B, const mlba_batch_tuning* choice, hipStr
 
 int mlba_batch_destroy(mlba_batch_t B) {
     if (!B) return MLBA_EINVAL;
-    hipDeviceSynchronize();
+    if (B->done) (void)hipEventSynchronize(B->done);  // the batch's last enqueued work
     destroy_batch(B);
     return MLBA_OK;
 }
@@ -491,6 +511,10 @@ int mlba_batch_restore(mlba_batch_t B, const float* const* g, const double* alph
     } else {
         STCHK(enqueue(B, iters, fill_state, implicit, s));
     }
+    // the batch's and its plans' completion events (their buffers were used)
+    HIPCHK(hipEventRecord(B->done, s));
+    for (mlba_plan_t P : B->plans)
+        if (P->done) HIPCHK(hipEventRecord(P->done, s));
     if (rnorm_out && iters > 0) {
         std::vector<double> buf((size_t)count * B->rn_cap);
         HIPCHK(hipMemcpyAsync(buf.data(), B->rn, buf.size() * sizeof(double), hipMemcpyDeviceToHost, s));

@@ -406,10 +406,14 @@ hipError_t launch_fill(float* x, size_t count, float value, hipStream_t s);
 int reduce_partials_cap();
 // preconditioned CG of Algorithm 2: t += a d, res -= a q with a = *rho / *pq
 hipError_t launch_pcg_update(float* t, float* res, const float* d, const float* q, size_t count, const double* rho,
-                             const double* pq, hipStream_t s);
-// d = z + (*rho_new / *rho) d
+                             const double* pq, const double* act, hipStream_t s);
+// d = z + (*rho_new / *rho) d; both skipped once *act == 0
 hipError_t launch_pcg_dir(float* d, const float* z, size_t count, const double* rho_new, const double* rho,
-                          hipStream_t s);
+                          const double* act, hipStream_t s);
+// CG state st[] (see reduce.hip): begin after rho_0 is in st[0]; check after step j
+hipError_t launch_pcg_begin(double* st, int* hist, hipStream_t s);
+hipError_t launch_pcg_check(double* st, const double* rn, int j, int max_steps, double tol, int* hist,
+                            hipStream_t s);
 hipError_t launch_axpy(float* y, const float* x, size_t count, float a, hipStream_t s);  // y += a x
 // w -= ab[0] v + sqrt(*beta2) vprev (vprev may be null), partial sums of w^2
 hipError_t launch_lanczos_step(float* w, const float* v, const float* vprev, size_t count, const double* ab,

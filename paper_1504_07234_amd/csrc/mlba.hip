@@ -162,7 +162,15 @@ int prof_mark(mlba_plan_s* P, int phase, int kernel, int launches, hipStream_t s
 
 #define MARK(ph, k) STCHK(prof_mark(P, MLBA_PHASE_##ph, MLBA_KERNEL_##k, 1, s))
 
+// Records the plan's completion event on s after a call that enqueued work
+// (mlba_plan_destroy waits for it instead of for the whole device).
+int note_work(mlba_plan_s* P, int st, hipStream_t s) {
+    if (st >= 0 && P->done) HIPCHK(hipEventRecord(P->done, s));
+    return st;
+}
+
 void free_plan(mlba_plan_s* P) {
+    if (P->done) (void)hipEventDestroy(P->done);
     release_events(P);
     for (void* a : P->allocs) hipFree(a);
     P->allocs.clear();
@@ -496,27 +504,27 @@ int do_blurT_acc(mlba_plan_s* P, const float* y, float* omega, hipStream_t s) {
 // Algorithm 2: P->pcg[0 .. n^2) <- t ~ (A A^T + alpha I)^{-1} r (r = P->r, used
 // as the CG residual and overwritten) by preconditioned CG from t = 0, at most
 // max_steps steps, stopping at the first step with sqrt(rho_j / rho_0) <= tol,
-// rho_j = res_j^T M^{-1} res_j (eq. bet).  *steps_out = beta_n.
-int do_pcg(mlba_plan_s* P, double alpha, int max_steps, double tol, int* steps_out, hipStream_t s) {
+// rho_j = res_j^T M^{-1} res_j (eq. bet).  The test runs on the device: all
+// max_steps steps are enqueued, and once the CG has stopped the updates of
+// t, res and d are skipped; *hist (device) receives beta_n.  No host round trip.
+int do_pcg(mlba_plan_s* P, double alpha, int max_steps, double tol, int* hist, hipStream_t s) {
     const size_t nn = (size_t)P->n * P->n;
     float* t = P->pcg;
     float* zc = P->pcg + nn;
     float* d = P->pcg + 2 * nn;
     float* q = P->pcg + 3 * nn;
     float* res = P->r;
-    double* rho[2] = {P->pcgs, P->pcgs + 1};
-    double* pq = P->pcgs + 2;
+    double* st = P->pcgs;
+    double* rho[2] = {st, st + 1};
+    double* pq = st + 2;
+    const double* act = st + 4;
     int np = 0;
     HIPCHK(launch_fill(t, nn, 0.0f, s));
     STCHK(do_precond(P, res, zc, alpha, s));
     HIPCHK(hipMemcpyAsync(d, zc, nn * sizeof(float), hipMemcpyDeviceToDevice, s));
     HIPCHK(launch_dot_partials(res, zc, nn, P->partials, &np, s));
     HIPCHK(launch_sum_partials(P->partials, np, rho[0], s));
-    double rho0 = 0.0;
-    HIPCHK(hipMemcpyAsync(&rho0, rho[0], sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    *steps_out = 0;
-    if (!(rho0 > 0.0)) return MLBA_OK;  // r = 0: t = 0
+    HIPCHK(launch_pcg_begin(st, hist, s));
     for (int j = 1; j <= max_steps; ++j) {
         double* rc = rho[(j - 1) & 1];
         double* rn = rho[j & 1];
@@ -525,16 +533,12 @@ int do_pcg(mlba_plan_s* P, double alpha, int max_steps, double tol, int* steps_o
         HIPCHK(launch_axpy(q, d, nn, (float)alpha, s));
         HIPCHK(launch_dot_partials(d, q, nn, P->partials, &np, s));
         HIPCHK(launch_sum_partials(P->partials, np, pq, s));
-        HIPCHK(launch_pcg_update(t, res, d, q, nn, rc, pq, s));
+        HIPCHK(launch_pcg_update(t, res, d, q, nn, rc, pq, act, s));
         STCHK(do_precond(P, res, zc, alpha, s));
         HIPCHK(launch_dot_partials(res, zc, nn, P->partials, &np, s));
         HIPCHK(launch_sum_partials(P->partials, np, rn, s));
-        double rho_j = 0.0;
-        HIPCHK(hipMemcpyAsync(&rho_j, rn, sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        *steps_out = j;
-        if (sqrt(rho_j / rho0) <= tol || j == max_steps) break;
-        HIPCHK(launch_pcg_dir(d, zc, nn, rn, rc, s));
+        HIPCHK(launch_pcg_check(st, rn, j, max_steps, tol, hist, s));
+        if (j < max_steps) HIPCHK(launch_pcg_dir(d, zc, nn, rn, rc, act, s));
     }
     return MLBA_OK;
 }
@@ -798,6 +802,7 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
     if (precond != MLBA_PRECOND_NONE) {
         ALLOC(P->pcg, 4 * obs);
         ALLOC(P->pcgs, 8);
+        ALLOC(P->pcgh, (size_t)P->rn_cap);
     }
     if (bc == MLBA_BC_REFLECT) ALLOC(P->wext, (size_t)m * m);
 
@@ -855,6 +860,15 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
             return MLBA_EHIP;
         }
     }
+    {
+        const hipError_t e = hipEventCreateWithFlags(&P->done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            P->done = nullptr;
+            mlba_internal_set_hip(e);
+            free_plan(P);
+            return MLBA_EHIP;
+        }
+    }
     st = mlba_plan_set_psf(P, psf, s);
     if (st < 0) {
         free_plan(P);
@@ -868,7 +882,7 @@ int mlba_plan_set_psf(mlba_plan_t P, const float* psf, hipStream_t s) {
     if (!P || !psf) return MLBA_EINVAL;
     HIPCHK(hipMemcpyAsync(P->psf, psf, (size_t)P->p * P->p * sizeof(float), hipMemcpyDeviceToDevice, s));
     if (P->fc.H) HIPCHK(launch_fftconv_spectrum(P->fc, P->psf, P->p, s));
-    return compute_spectrum(P, s);
+    return note_work(P, compute_spectrum(P, s), s);
 }
 
 }  // extern "C"
@@ -981,7 +995,7 @@ int mlba_plan_autotune(mlba_plan_t P, int reps, double* ms_out, hipStream_t s) {
 
 int mlba_plan_destroy(mlba_plan_t P) {
     if (!P) return MLBA_EINVAL;
-    hipDeviceSynchronize();
+    if (P->done) (void)hipEventSynchronize(P->done);  // the plan's last enqueued work
     free_plan(P);
     return MLBA_OK;
 }
@@ -997,49 +1011,49 @@ int mlba_plan_dims(mlba_plan_t P, int* n, int* p, int* N, int* bands) {
 
 int mlba_plan_opnorm(mlba_plan_t P, double alpha, int iters, double* out, hipStream_t s) {
     if (!P || !out || iters < 1 || !(alpha > 0.0 || P->precond == MLBA_PRECOND_NONE)) return MLBA_EINVAL;
-    return mlba_internal_opnorm(P, alpha, iters, kAutoLanczosTol, out, nullptr, s);
+    return note_work(P, mlba_internal_opnorm(P, alpha, iters, kAutoLanczosTol, out, nullptr, s), s);
 }
 
 int mlba_apply_A(mlba_plan_t P, const float* u, float* y, hipStream_t s) {
     if (!P || !u || !y) return MLBA_EINVAL;
-    return do_blur(P, u, nullptr, y, false, nullptr, s);
+    return note_work(P, do_blur(P, u, nullptr, y, false, nullptr, s), s);
 }
 
 int mlba_residual(mlba_plan_t P, const float* g, const float* u, float* r, hipStream_t s) {
     if (!P || !g || !u || !r) return MLBA_EINVAL;
-    return do_blur(P, u, g, r, false, nullptr, s);
+    return note_work(P, do_blur(P, u, g, r, false, nullptr, s), s);
 }
 
 int mlba_apply_At(mlba_plan_t P, const float* y, float* w, hipStream_t s) {
     if (!P || !y || !w) return MLBA_EINVAL;
-    return do_blurT(P, y, w, s);
+    return note_work(P, do_blurT(P, y, w, s), s);
 }
 
 int mlba_apply_P(mlba_plan_t P, const float* r, float* t, double alpha, hipStream_t s) {
     if (!P || !r || !t) return MLBA_EINVAL;
     if (P->precond != MLBA_PRECOND_NONE && !(alpha > 0.0)) return MLBA_EINVAL;
-    return do_precond(P, r, t, alpha, s);
+    return note_work(P, do_precond(P, r, t, alpha, s), s);
 }
 
 int mlba_apply_CtP(mlba_plan_t P, const float* r, float* t, double alpha, hipStream_t s) {
     if (!P || !r || !t || r == t || !(alpha > 0.0)) return MLBA_EINVAL;
     if (P->bc == MLBA_BC_RECT || P->precond == MLBA_PRECOND_NONE) return MLBA_EUNSUPPORTED;
-    return do_ct_precond(P, r, t, alpha, 0, s);
+    return note_work(P, do_ct_precond(P, r, t, alpha, 0, s), s);
 }
 
 int mlba_framelet_analysis(mlba_plan_t P, const float* f, float* z, hipStream_t s) {
     if (!P || !f || !z) return MLBA_EINVAL;
-    return do_analysis(P, f, z, false, s);
+    return note_work(P, do_analysis(P, f, z, false, s), s);
 }
 
 int mlba_analysis_update(mlba_plan_t P, const float* w, float* z, hipStream_t s) {
     if (!P || !w || !z) return MLBA_EINVAL;
-    return do_analysis(P, w, z, true, s);
+    return note_work(P, do_analysis(P, w, z, true, s), s);
 }
 
 int mlba_framelet_synthesis(mlba_plan_t P, const float* z, float* f, hipStream_t s) {
     if (!P || !z || !f) return MLBA_EINVAL;
-    return do_synthesis(P, z, f, false, nullptr, 1.0f, s);
+    return note_work(P, do_synthesis(P, z, f, false, nullptr, 1.0f, s), s);
 }
 
 int mlba_threshold_synthesis(mlba_plan_t P, const float* z, const double* mu, int n_mu, double delta, float* f,
@@ -1047,7 +1061,7 @@ int mlba_threshold_synthesis(mlba_plan_t P, const float* z, const double* mu, in
     if (!P || !z || !f || !isfinite(delta)) return MLBA_EINVAL;
     float mub[64];
     STCHK(expand_mu(P, mu, n_mu, mub));
-    return do_synthesis(P, z, f, true, mub, (float)delta, s);
+    return note_work(P, do_synthesis(P, z, f, true, mub, (float)delta, s), s);
 }
 
 int mlba_shrink_synthesis(mlba_plan_t P, const float* omega, const double* mu, int n_mu, double delta, float* f,
@@ -1055,7 +1069,7 @@ int mlba_shrink_synthesis(mlba_plan_t P, const float* omega, const double* mu, i
     if (!P || !omega || !f || omega == f || !isfinite(delta)) return MLBA_EINVAL;
     float mub[64];
     STCHK(expand_mu(P, mu, n_mu, mub));
-    return do_shrink_synthesis(P, omega, f, mub, (float)delta, s);
+    return note_work(P, do_shrink_synthesis(P, omega, f, mub, (float)delta, s), s);
 }
 
 int mlba_soft_threshold(const float* z, float* x, int bands, size_t band_elems, const double* mu, int n_mu,
@@ -1092,7 +1106,7 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
     if (alg2 && P->precond == MLBA_PRECOND_NONE) return MLBA_EUNSUPPORTED;
     const int pcg_max = prm->pcg_max > 0 ? prm->pcg_max : 5;
     const double pcg_tol = prm->pcg_tol > 0.0 ? prm->pcg_tol : 1e-3;
-    if (alg2 && (pcg_max > 1000 || !isfinite(pcg_tol))) return MLBA_EINVAL;
+    if (alg2 && (pcg_max > 1000 || !isfinite(pcg_tol) || iters > P->rn_cap)) return MLBA_EINVAL;
     if (alg4 && (P->bc == MLBA_BC_RECT || P->precond == MLBA_PRECOND_NONE)) return MLBA_EUNSUPPORTED;
     const bool ns = as.kind == MLBA_ALPHA_NS;
     mlba_stop ns_stop{};
@@ -1274,13 +1288,11 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
             continue;
         }
         if (alg2) {
-            int steps = 0;
             const int cur = P->prof_cur;  // the PCG is timed as one sequence
             P->prof_cur = -1;
-            STCHK(do_pcg(P, alpha[i], pcg_max, pcg_tol, &steps, s));
+            STCHK(do_pcg(P, alpha[i], pcg_max, pcg_tol, P->pcgh + i, s));
             P->prof_cur = cur;
             STCHK(prof_mark(P, MLBA_PHASE_PRECOND, MLBA_KERNEL_OTHER, 1, s));
-            if (prm->pcg_steps_out) prm->pcg_steps_out[i] = steps;
             float* tsol = P->pcg;  // the CG solution t
             if (implicit) {
                 STCHK(do_blurT_acc(P, tsol, z, s));
@@ -1310,6 +1322,10 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
 
     if (prm->delta_out)
         for (int i = 0; i <= done; ++i) prm->delta_out[i] = delta[i];
+    if (alg2 && prm->pcg_steps_out && done > 0) {
+        HIPCHK(hipMemcpyAsync(prm->pcg_steps_out, P->pcgh, (size_t)done * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
     if (prm->alpha_out && done > 0) {
         if (ns) {
             HIPCHK(hipMemcpyAsync(prm->alpha_out, P->ahist, (size_t)done * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1331,7 +1347,7 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
         }
         if (iters_done) *iters_done = done;
     }
-    return status;
+    return note_work(P, status, s);
 }
 
 int mlba_profile_begin(mlba_plan_t P, int max_iters) {

@@ -40,7 +40,8 @@ struct mlba_plan_s {
     double* ns = nullptr;      // Algorithm 4-NS device state
     double* ahist = nullptr;   // alpha_k used (ring like rn)
     float* pcg = nullptr;      // Algorithm 2: t, z, d, q (n x n each)
-    double* pcgs = nullptr;    // Algorithm 2 scalars: rho (two slots), pq, rho0
+    double* pcgs = nullptr;    // Algorithm 2 scalars: rho (two slots), pq, rho0, running flag
+    int* pcgh = nullptr;       // Algorithm 2: beta_n of each iteration (rn_cap entries)
     float2* tw = nullptr;      // exp(-2 pi i q / L), L = fd.n (n; 2(n-1) for AR)
     float2* dtw = nullptr;     // exp(-i pi k / (2n))
     float* costab = nullptr;   // cos(pi q / n), q < 2n (AR: cos(pi q / (n-1)), q < 2(n-1))
@@ -61,6 +62,7 @@ struct mlba_plan_s {
     double* rn = nullptr;      // ||r^k||^2 history ring
     int rn_cap = 0;
     std::vector<void*> allocs;
+    hipEvent_t done = nullptr;  // recorded after every call that enqueues work
     // kernel timing (mlba_profile_begin / end): per profiled iteration one
     // start event and up to kMaxMarks - 1 marks, each an event recorded after
     // a launch (or a launch sequence) and labelled with the phase and kernel

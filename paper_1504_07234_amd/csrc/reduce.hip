@@ -117,11 +117,35 @@ hipError_t launch_fill(float* x, size_t count, float value, hipStream_t s) {
 }
 
 // ---- preconditioned CG of Algorithm 2 (device scalars, no host round trip) ----
-// t += a d, res -= a q with a = rho / pq (both device doubles)
+// The CG state lives in device doubles st[]: st[0], st[1] the two rho slots,
+// st[2] = d^T q, st[3] = rho_0, st[4] = 1 while the CG is running (0 once it
+// has stopped: every later update is skipped, so the result is that of the
+// stopped CG), and hist[] the step count of each outer iteration.
+
+// rho_0 = st[0]: the CG runs unless the right-hand side is zero
+__global__ void pcg_begin_kernel(double* __restrict__ st, int* __restrict__ hist) {
+    st[3] = st[0];
+    st[4] = st[0] > 0.0 ? 1.0 : 0.0;
+    *hist = 0;
+}
+
+// after step j with rho_j = *rn: count the step, stop at the first
+// sqrt(rho_j / rho_0) <= tol or at the step cap
+__global__ void pcg_check_kernel(double* __restrict__ st, const double* __restrict__ rn, int j, int max_steps,
+                                 double tol, int* __restrict__ hist) {
+    if (st[4] == 0.0) return;
+    *hist = j;
+    if (sqrt(*rn / st[3]) <= tol || j == max_steps) st[4] = 0.0;
+}
+
+// t += a d, res -= a q with a = rho / pq (both device doubles); nothing once
+// the CG has stopped (*act == 0)
 __global__ __launch_bounds__(kBlock) void pcg_update_kernel(float* __restrict__ t, float* __restrict__ res,
                                                             const float* __restrict__ d, const float* __restrict__ q,
                                                             size_t count, const double* __restrict__ rho,
-                                                            const double* __restrict__ pq) {
+                                                            const double* __restrict__ pq,
+                                                            const double* __restrict__ act) {
+    if (*act == 0.0) return;
     const float a = (float)(*rho / *pq);
     for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (size_t)gridDim.x * kBlock) {
         t[i] = fmaf(a, d[i], t[i]);
@@ -129,10 +153,12 @@ __global__ __launch_bounds__(kBlock) void pcg_update_kernel(float* __restrict__ 
     }
 }
 
-// d = z + (rho_new / rho) d
+// d = z + (rho_new / rho) d; nothing once the CG has stopped
 __global__ __launch_bounds__(kBlock) void pcg_dir_kernel(float* __restrict__ d, const float* __restrict__ z,
                                                          size_t count, const double* __restrict__ rho_new,
-                                                         const double* __restrict__ rho) {
+                                                         const double* __restrict__ rho,
+                                                         const double* __restrict__ act) {
+    if (*act == 0.0) return;
     const float b = (float)(*rho_new / *rho);
     for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (size_t)gridDim.x * kBlock)
         d[i] = fmaf(b, d[i], z[i]);
@@ -185,16 +211,27 @@ static unsigned elementwise_blocks(size_t count) {
 }
 
 hipError_t launch_pcg_update(float* t, float* res, const float* d, const float* q, size_t count, const double* rho,
-                             const double* pq, hipStream_t s) {
+                             const double* pq, const double* act, hipStream_t s) {
     hipLaunchKernelGGL(pcg_update_kernel, dim3(elementwise_blocks(count)), dim3(kBlock), 0, s, t, res, d, q, count,
-                       rho, pq);
+                       rho, pq, act);
     return hipGetLastError();
 }
 
 hipError_t launch_pcg_dir(float* d, const float* z, size_t count, const double* rho_new, const double* rho,
-                          hipStream_t s) {
+                          const double* act, hipStream_t s) {
     hipLaunchKernelGGL(pcg_dir_kernel, dim3(elementwise_blocks(count)), dim3(kBlock), 0, s, d, z, count, rho_new,
-                       rho);
+                       rho, act);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_begin(double* st, int* hist, hipStream_t s) {
+    hipLaunchKernelGGL(pcg_begin_kernel, dim3(1), dim3(1), 0, s, st, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_check(double* st, const double* rn, int j, int max_steps, double tol, int* hist,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(pcg_check_kernel, dim3(1), dim3(1), 0, s, st, rn, j, max_steps, tol, hist);
     return hipGetLastError();
 }
 

@@ -75,13 +75,23 @@ struct mlba_unrolled_s {
     BatchImage* tables = nullptr;  // device descriptor tables
     int table_cap = 0;             // tables of `count` descriptors
     std::vector<BatchImage> host_tables;
+    hipEvent_t done = nullptr;  // recorded after every call that enqueues work
 };
 
 namespace {
 
 void destroy_unrolled(mlba_unrolled_s* U) {
+    if (U->done) hipEventDestroy(U->done);
     for (void* a : U->allocs) hipFree(a);
     delete U;
+}
+
+// The object's and its plans' completion events on s (their buffers were used).
+int note_unrolled(mlba_unrolled_s* U, hipStream_t s) {
+    HIPCHK(hipEventRecord(U->done, s));
+    for (mlba_plan_t P : U->plans)
+        if (P->done) HIPCHK(hipEventRecord(P->done, s));
+    return MLBA_OK;
 }
 
 int ualloc(mlba_unrolled_s* U, void** ptr, size_t bytes) {
@@ -305,6 +315,7 @@ int mlba_unrolled_create(mlba_unrolled_t* out, int count, const mlba_plan_t* pla
 #undef UALLOC
     hipError_t e = hipMemcpyAsync(U->maps, hm.data(), hm.size() * sizeof(int), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&U->done, hipEventDisableTiming);
     if (e != hipSuccess) {
         mlba_internal_set_hip(e);
         destroy_unrolled(U);
@@ -316,7 +327,7 @@ int mlba_unrolled_create(mlba_unrolled_t* out, int count, const mlba_plan_t* pla
 
 int mlba_unrolled_destroy(mlba_unrolled_t U) {
     if (!U) return MLBA_EINVAL;
-    hipDeviceSynchronize();
+    if (U->done) (void)hipEventSynchronize(U->done);  // the object's last enqueued work
     destroy_unrolled(U);
     return MLBA_OK;
 }
@@ -364,7 +375,7 @@ int mlba_unrolled_forward(mlba_unrolled_t U, const float* const* g, double alpha
         const Map& m = U->syn[lev];
         HIPCHK(launch_synthesis_batched(table(U, t_out), m.bmap, m.bfirst, m.nblocks, lev, 1 << (lev - 1), 1, s));
     }
-    return MLBA_OK;
+    return note_unrolled(U, s);
 }
 
 int mlba_unrolled_backward(mlba_unrolled_t U, const float* const* g, double alpha, const double* mu, int n_mu,
@@ -475,7 +486,7 @@ int mlba_unrolled_backward(mlba_unrolled_t U, const float* const* g, double alph
     S.corr_part = U->corr_part;
     S.spec = U->spec;
     HIPCHK(launch_unrolled_reduce(S, dmu, dalpha, dpsf, s));
-    return MLBA_OK;
+    return note_unrolled(U, s);
 }
 
 }  // extern "C"
