@@ -324,3 +324,24 @@ def test_batched_implicit_against_oracle_and_resume(mlba):
         assert rel_err(norms[i], ref["rnorm"]) < 1e-4
     for pl in plans:
         pl.close()
+
+
+def test_tile_changes_allocate_nothing(mlba):
+    """The tile maps are sized at creation for the choice with the most
+    workgroups: set_tiles and the autotuner leave the device's free memory
+    unchanged."""
+    import torch
+    announce("batch tile changes allocate nothing")
+    plans, gs, _ = _make(mlba, SIZES[:4])
+    gdev = [cuda(g) for g in gs]
+    with mlba.Batch(plans, max_iters=4) as batch:
+        batch.restore(gdev, alpha=0.05, mu=1e-3, delta=0.25, iters=4, use_graph=False)
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        for conv_rows, rc, cc in (((2, 2), 1, 1), ((1, 1), 4, 16), ((1, 2), 0, 0)):
+            batch.set_tiles(conv_rows, rc, cc)
+        batch.autotune(reps=1)
+        torch.cuda.synchronize()
+        assert torch.cuda.mem_get_info()[0] == free0
+    for pl in plans:
+        pl.close()
