@@ -480,6 +480,62 @@ __device__ __forceinline__ void dct_rows_inv_body(const float* __restrict__ Tr, 
     }
 }
 
+// ---- Algorithm 4 with the periodic model: the blur inside the transform ----
+// For periodic boundary conditions A is the BCCB matrix C of the PSF centred
+// at the origin (eigenvalues Lambda_c), so the residual is formed in the
+// spectrum: R = F g - Lambda_c F u, and ||r||^2 = sum |R|^2 / n^2 (Parseval;
+// the half spectrum counts the columns 0 < k < n/2 twice).  Over CC columns of
+// T holding the row transforms of u: forward FFT, R, the partial of ||r||^2
+// per workgroup into part[blockIdx.x]; then (store_r == 0) the direction of
+// eq. (Alg4), conj(Lambda_c) R inv / (|Lambda|^2 + alpha), inverse FFT, or
+// (store_r) R itself, for the 4-NS alpha and the filter that follows.
+template <int NT>
+__global__ __launch_bounds__(kBlock) void fft_cols_residual_kernel(float2* __restrict__ T, int n_, int ts,
+                                                                   const float2* __restrict__ ghat,
+                                                                   const float2* __restrict__ lamc,
+                                                                   const float* __restrict__ spec, float alpha,
+                                                                   float inv, FftDesc fd,
+                                                                   const float2* __restrict__ tw, int CC_,
+                                                                   int seq_shift, int store_r,
+                                                                   double* __restrict__ part) {
+    extern __shared__ float2 buf[];
+    __shared__ double red[kBlock / 64];
+    const int n = NT > 0 ? NT : n_;
+    const int CC = NT > 0 ? 1 : CC_;
+    const int half = n / 2 + 1;
+    const int k0 = blockIdx.x * CC;
+    const int cc = min(CC, half - k0);
+    const size_t base = (size_t)k0 * n;  // dense [n/2+1][n] spectra
+    FixedTw<(NT > 0 ? NT : 1)> twp;
+    if constexpr (NT > 0) fixed_tw_load<NT>(tw, twp.w);
+    strided_copy<NT, float2>(
+        cc * n,
+        [&](int idx) {
+            const int q = idx / n;
+            return T[(size_t)(k0 + q) * ts + (idx - q * n)];
+        },
+        [&](int idx, float2 v) { buf[lds_slot(idx)] = v; });
+    __syncthreads();
+    lds_fft_any<-1, NT>(buf, fd, cc, seq_shift, tw, NT > 0 ? twp.w : nullptr);
+    const double to_r = 1.0 / ((double)n * (double)n);
+    double ss = 0.0;
+    for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
+        const int kx = k0 + idx / n;
+        const float2 L = lamc[base + idx];
+        const float2 R = csub(ghat[base + idx], cmul(L, buf[lds_slot(idx)]));
+        const double wgt = (kx == 0 || 2 * kx == n) ? to_r : 2.0 * to_r;
+        ss += wgt * ((double)R.x * (double)R.x + (double)R.y * (double)R.y);
+        buf[lds_slot(idx)] = store_r ? R : cmul(cscale(R, inv / (spec[base + idx] + alpha)), cconj(L));
+    }
+    const double t = block_sum(ss, red);  // its barriers also order the writes above before the transform
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+    if (!store_r) lds_fft_any<1, NT>(buf, fd, cc, seq_shift, tw, NT > 0 ? twp.w : nullptr);
+    for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
+        const int q = idx / n;
+        T[(size_t)(k0 + q) * ts + (idx - q * n)] = buf[lds_slot(idx)];
+    }
+}
+
 // ---- single-image kernels ------------------------------------------------
 
 template <int NT>
@@ -951,6 +1007,28 @@ static hipError_t launch_cols(float2* T, int n, int ts, const float* spec, float
         hipLaunchKernelGGL(fft_cols_kernel<0>, dim3((half + CC - 1) / CC), dim3(kBlock), lds, s, T, n, ts, spec,
                            alpha, inv, fd, tw, CC, mode, power, seq_shift_for(CC), lamc, alpha_dev, cspec, red_in,
                            red_count, red_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_cols_residual(float2* T, int n, int ts, const float2* ghat, const float2* lamc,
+                                    const float* spec, float alpha, float inv, const FftDesc& fd, const float2* tw,
+                                    int store_r, double* part, int* n_part, hipStream_t s) {
+    const int CC = pick_cols_per_block(n);
+    const int half = n / 2 + 1;
+    const size_t lds = lds_bytes(fft_lds_elems(CC * n, n), n);
+    if (n == kFixedN && CC == 1) {
+        *n_part = half;
+        hipLaunchKernelGGL(fft_cols_residual_kernel<kFixedN>, dim3(half), dim3(kBlock), lds, s, T, n, ts, ghat, lamc,
+                           spec, alpha, inv, fd, tw, 1, seq_shift_for(1), store_r, part);
+    } else {
+        *n_part = (half + CC - 1) / CC;
+        if (fd.m > 0)
+            hipLaunchKernelGGL(fft_cols_residual_kernel<kAnyLen>, dim3(*n_part), dim3(kBlock), lds, s, T, n, ts, ghat,
+                               lamc, spec, alpha, inv, fd, tw, CC, seq_shift_for(CC), store_r, part);
+        else
+            hipLaunchKernelGGL(fft_cols_residual_kernel<0>, dim3(*n_part), dim3(kBlock), lds, s, T, n, ts, ghat, lamc,
+                               spec, alpha, inv, fd, tw, CC, seq_shift_for(CC), store_r, part);
+    }
     return hipGetLastError();
 }
 

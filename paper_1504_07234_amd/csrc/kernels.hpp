@@ -294,6 +294,13 @@ hipError_t launch_fft_rows_r2c(const float* src, int n, float2* T, int ts, const
 hipError_t launch_fft_cols_filter(float2* T, int n, int ts, const float* spec, float alpha, float inv,
                                   const FftDesc& fd, const float2* tw, hipStream_t s, const float2* lamc = nullptr,
                                   const double* red_in = nullptr, int red_count = 0, double* red_out = nullptr);
+// columns, Algorithm 4 with the periodic model (A = C): forward FFT, R = ghat -
+// lamc * (F u) with the partial of ||r||^2 = sum |R|^2 / n^2 per workgroup
+// into part (*n_part partials), then the direction conj(lamc) R inv /
+// (spec + alpha) and the inverse FFT, or (store_r) R itself
+hipError_t launch_fft_cols_residual(float2* T, int n, int ts, const float2* ghat, const float2* lamc,
+                                    const float* spec, float alpha, float inv, const FftDesc& fd, const float2* tw,
+                                    int store_r, double* part, int* n_part, hipStream_t s);
 // columns: forward FFT only (T then holds the 2-D half spectrum)
 hipError_t launch_fft_cols_forward(float2* T, int n, int ts, const FftDesc& fd, const float2* tw, hipStream_t s);
 // columns: the filter of launch_fft_cols_filter with alpha read on the device, inverse FFT

@@ -837,6 +837,7 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
             P->ts = n + 16;
             ALLOC(P->spec, (size_t)(n / 2 + 1) * n);
             if (bc != MLBA_BC_RECT) ALLOC(P->lamc, (size_t)(n / 2 + 1) * n);
+            if (bc == MLBA_BC_PERIODIC) ALLOC(P->ghat, (size_t)(n / 2 + 1) * n);  // Algorithm 4: F g
             float2* T = nullptr;
             ALLOC(T, (size_t)(n / 2 + 1) * P->ts);
             P->swork = T;
@@ -1180,6 +1181,15 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
         ~ProfGuard() { P->prof_cur = -1; }
     } prof_guard{P};
     const bool fused = !alg4 && !alg2 && fused_fft_path(P);
+    // Algorithm 4 with the periodic model and the BCCB matrix: A = C, so the
+    // residual is formed in the spectrum (F g computed once here) and an
+    // iteration is the synthesis and one 2-D transform pair
+    const bool fold4 = alg4 && P->bc == MLBA_BC_PERIODIC && P->precond == MLBA_PRECOND_BCCB && P->ghat &&
+                       (P->n / 2 + 1) <= P->partials_cap;
+    if (fold4 && iters > 0) {
+        HIPCHK(launch_fft_rows_r2c(g, P->n, (float2*)P->swork, P->ts, P->fd, P->tw, s));
+        HIPCHK(launch_fft_cols_complex((const float2*)P->swork, P->n, P->ts, P->ghat, P->fd, P->tw, s));
+    }
     const bool fused_ar = !ns && !alg2 && fused_ar_path(P);  // MLBA or Algorithm 4
     for (int i = 0; i < iters; ++i) {
         if (i - ring_base >= P->rn_cap) {
@@ -1260,6 +1270,37 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
                 STCHK(do_blurT(P, P->t, P->w, s));
                 STCHK(do_analysis(P, P->w, z, true, s));
             }
+            P->prof_cur = -1;
+            done = i + 1;
+            continue;
+        }
+        if (fold4) {
+            const int n = P->n;
+            const float inv = (float)(1.0 / ((double)n * (double)n));
+            float2* T = (float2*)P->swork;
+            HIPCHK(launch_fft_rows_r2c(P->u, n, T, P->ts, P->fd, P->tw, s));
+            MARK(BLUR, FFT_ROWS_FWD);
+            HIPCHK(launch_fft_cols_residual(T, n, P->ts, P->ghat, P->lamc, P->spec, (float)alpha[i], inv, P->fd,
+                                            P->tw, ns ? 1 : 0, P->partials, &np, s));
+            MARK(PRECOND, FFT_COLS);
+            HIPCHK(launch_sum_partials(P->partials, np, P->rn + (i - ring_base), s));
+            MARK(BLUR, REDUCE);
+            STCHK(check_stop(&hit));
+            if (hit) {
+                stopped = true;
+                break;
+            }
+            if (ns) {  // T holds F r: alpha_n, then the filter and the inverse column transform
+                HIPCHK(launch_ns_alpha(T, 0, n, P->ts, P->spec, P->ns, P->partials, P->rn + (i - ring_base), P->psf,
+                                       P->p, stop->noise_norm, as.ns_q, as.ns_rho, as.alpha0, i == 0 ? 1 : 0,
+                                       12, P->ahist + (i - ring_base), s));
+                STCHK(prof_mark(P, MLBA_PHASE_PRECOND, MLBA_KERNEL_OTHER, 1 + 2 * 12, s));
+                HIPCHK(launch_fft_cols_filter_inverse(T, n, P->ts, P->spec, P->ns, inv, P->lamc, P->fd, P->tw, s));
+                MARK(PRECOND, FFT_COLS);
+            }
+            HIPCHK(launch_fft_rows_c2r(T, n, P->ts, implicit ? z : P->t, P->fd, P->tw, s, implicit ? 1 : 0));
+            MARK(PRECOND, FFT_ROWS_INV);
+            if (!implicit) STCHK(do_analysis(P, P->t, z, true, s));
             P->prof_cur = -1;
             done = i + 1;
             continue;

@@ -36,6 +36,7 @@ struct mlba_plan_s {
     float* psf = nullptr;
     float* spec = nullptr;     // BCCB: [n/2+1][n] |Lambda|^2 (transposed); DCT, AR: [n][n] lambda^2
     float2* lamc = nullptr;    // square models, BCCB: Lambda_c of the centred PSF (layout of spec)
+    float2* ghat = nullptr;    // periodic model, BCCB: F g of the current restoration (layout of spec)
     float* lamr = nullptr;     // square models, DCT and AR: lambda (layout of spec)
     double* ns = nullptr;      // Algorithm 4-NS device state
     double* ahist = nullptr;   // alpha_k used (ring like rn)

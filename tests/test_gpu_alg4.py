@@ -80,6 +80,32 @@ def test_alg4_against_oracle(mlba, bc, kind, sym, alpha, iters, L, n, implicit):
     assert np.allclose(info.alphas, alpha)
 
 
+@pytest.mark.parametrize("implicit", [False, True])
+@pytest.mark.parametrize("n,p,L,iters", [(2048, 31, 3, 4), (250, 17, 2, 60), (96, 5, 1, 80)])
+def test_alg4_periodic_spectral_residual(mlba, n, p, L, iters, implicit):
+    """Periodic model with the BCCB matrix: A = C, the residual formed in the
+    spectrum (F g - Lambda_c F u, ||r|| by Parseval) and one transform pair per
+    iteration; the 2048 case is the bench's Algorithm 4 shape (31 x 31 disk,
+    3 levels), 250 a 2/5-smooth run-time length.  Image and residual norms
+    against the oracle, which forms r = g - C u with the periodic blur."""
+    announce(f"Alg4 periodic spectral residual n={n} p={p} L={L} iters={iters} implicit={implicit}")
+    gen = synth.rng(900 + n)
+    truth = synth.shapes_image(n, gen, n_rect=8, n_disk=4, n_bumps=3)
+    H = synth.disk_psf(p, (p - 1) / 2.0) if p > 9 else synth.motion_psf(p, p - 2.0, 0.4)
+    b = ob.blur(truth, H, ob.PERIODIC)
+    g = synth.add_noise(b, synth.white_noise((n, n), gen), 0.01)
+    alpha, mu = 0.02, np.linspace(1e-3, 2e-3, 8 * L + 1)
+    ref = oa.alg4(g, H, ob.PERIODIC, oa.BCCB, L, np.full(iters, alpha), np.ones(iters + 1), mu, iters)
+    with mlba.Plan(n, p, ob.PERIODIC, oa.BCCB, L, cuda(H)) as plan:
+        f, info = plan.restore(cuda(g), alpha=alpha, mu=mu, delta=1.0, iters=iters, method=mlba.ALG4,
+                               implicit=implicit)
+        f = host(f)
+    e, em, er = rel_err(f, ref["f"]), max_err(f, ref["f"]), rel_err(info.rnorm, ref["rnorm"])
+    print(f"  image rel {e:.2e} max {em:.2e} rnorm {er:.2e}", flush=True)
+    assert e < 1e-4 and em < 1e-4
+    assert er < 1e-4
+
+
 def _alpha_condition(g, H, bc, L, mu, alphas, kind=None):
     """kappa_n = |d log alpha_n / d log q_n| along the oracle's 4-NS run.
 
