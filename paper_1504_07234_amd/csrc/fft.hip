@@ -695,40 +695,191 @@ __global__ __launch_bounds__(kBlock) void pad_psf_kernel(const float* __restrict
 // narrows, falling back to bisection of log alpha when a step leaves it.
 // state (device doubles): [0] alpha, [1] log lo, [2] log hi, [3] q_n.
 // ---------------------------------------------------------------------------
-constexpr int NS_BLOCKS = 256;
+constexpr int NS_BLOCKS = 512;
+constexpr int NS_UNROLL = 8;
 
-// REAL: the 2-D DCT-II coefficients Tr[kx][ky] (real, n rows) of the DCT
-// plan instead; with the unnormalised X_k = sum_j x_j cos(pi k (2j+1) / 2n)
-// the orthonormal coefficient is sqrt((2 - [k == 0]) / n) X_k along each axis,
-// so Parseval weighs X^2 by (kx ? 2 : 1)(ky ? 2 : 1) (the common 1/n^2
-// cancels in the equation).
+// Layout of the 4-NS state buffer (24 doubles): [0, 4) the result
+// {alpha, log lo, log hi, q_n}; [4] sum |psf| (written with the PSF); the
+// steps' states alternately at [8, 13) and [16, 21) (the four values, then a
+// converged flag).
+constexpr int NS_L1 = 4;
+__host__ __device__ constexpr int ns_buf(int k) { return 8 + 8 * (k & 1); }
+
+// The state after one Newton step from the sums S0, S1, R at st[0] = alpha;
+// true once converged: the step stays (r = 0, or h matches to rounding), or
+// moves log alpha by less than kNsLogStep.  The sums take alpha in FP32, so a
+// step that small is below what they resolve (4 units in the last place of
+// an FP32 alpha), and no later step is taken.
+constexpr double kNsLogStep = 0x1p-22;
+__device__ __forceinline__ bool ns_newton(double* st, double S0, double S1, double R) {
+    const double a = st[0], la = log(a);
+    double lo = st[1], hi = st[2];
+    const double qn = st[3];
+    const double h = a * a * S0, target = qn * qn * R;
+    const double g = log(h) - log(target);
+    if (R <= 0.0 || fabs(g) < 1e-13) return true;
+    if (g > 0.0) hi = la; else lo = la;
+    const double slope = 2.0 * S1 / S0;
+    double t = (slope > 0.0 && isfinite(g)) ? la - g / slope : 0.5 * (lo + hi);
+    // a Newton point on the bracket's closed interval is kept (it sits on the
+    // end just moved when g is near rounding); outside it, bisect
+    if (!(t >= lo && t <= hi)) t = 0.5 * (lo + hi);
+    st[0] = exp(t);
+    st[1] = lo;
+    st[2] = hi;
+    return fabs(t - la) < kNsLogStep;
+}
+
+// q_n from ||r^n||^2 (rn_sq) and the noise level; bracket [hi 1e-14, hi] with
+// hi = q_n smax / (1 - q_n), smax = (sum |H|)^2 >= max |Lambda|^2 (there
+// alpha / (s + alpha) >= q_n for every s); start from the previous alpha (a)
+// when it lies inside, else from hi / 2.
+__device__ __forceinline__ void ns_init(double* st, double a, double rn_sq, double l1, double noise, double q,
+                                        double rho) {
+    const double smax = l1 * l1;
+    const double tau_n = sqrt(rn_sq) / noise;
+    const double qn = fmax(q, 2.0 * rho + (1.0 + rho) / tau_n);
+    const double hi = qn * smax / (1.0 - qn) * 1.0001 + 1e-30;
+    const double lo = hi * 1e-14;
+    if (!(a > lo && a < hi)) a = 0.5 * hi;
+    st[0] = a;
+    st[1] = log(lo);
+    st[2] = log(hi);
+    st[3] = qn;
+}
+
+// sum |psf| in index order (one thread), for the bracket of every iteration
+__global__ void ns_psf_l1_kernel(const float* __restrict__ psf, int p, double* __restrict__ state) {
+    double l1 = 0.0;
+    for (int i = 0; i < p * p; ++i) l1 += fabs((double)psf[i]);
+    state[NS_L1] = l1;
+}
+
+// The sums S0, S1, R of one step's NS_BLOCKS x 3 partials, in one fixed
+// order (the same in every workgroup that forms them); all threads call.
+__device__ __forceinline__ void ns_sums(const double* __restrict__ part, double (*red)[kBlock / 64], double* S) {
+    double u[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < NS_BLOCKS; b += kBlock)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) u[q] += part[(size_t)b * 3 + q];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        double x = u[q];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) red[q][wid] = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        S[q] = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) S[q] += red[q][w];
+    }
+    __syncthreads();
+}
+
+struct NsStep {
+    const double* rn_sq;
+    double noise, q, rho, alpha_first;
+    int first;  // start from alpha_first rather than the previous alpha
+    int k;      // the step
+};
+
+// Newton step k of the 4-NS alpha.  Every workgroup first brings the state
+// up to date itself: step 0 starts it (ns_init); a later step takes the
+// Newton update of step k-1's state with step k-1's partials (each
+// workgroup forms the same sums), unless step k-1 had converged.  Workgroup 0
+// stores the state for the next step; unless converged, every workgroup then
+// sums S0 = sum w / (s + a)^2, S1 = sum w s / (s + a)^3 and R = sum w over
+// its share of the spectrum into this step's partials.
+//
+// Weights w: the BCCB half spectrum T[kx][ky] (kx <= n/2) counts the columns
+// 0 < kx < n/2 twice (Parseval for real r).  REAL: the 2-D DCT-II
+// coefficients Tr[kx][ky] (real, n rows) of the DCT plan instead; with the
+// unnormalised X_k = sum_j x_j cos(pi k (2j+1) / 2n) the orthonormal
+// coefficient is sqrt((2 - [k == 0]) / n) X_k along each axis, so Parseval
+// weighs X^2 by (kx ? 2 : 1)(ky ? 2 : 1) (the common 1/n^2 cancels in the
+// equation).
 template <bool REAL>
-__global__ __launch_bounds__(kBlock) void ns_partials_kernel(const void* __restrict__ Tv, int n, int ts,
-                                                             const float* __restrict__ spec,
-                                                             const double* __restrict__ state,
-                                                             double* __restrict__ part) {
+__global__ __launch_bounds__(kBlock) void ns_step_kernel(const void* __restrict__ Tv, int n, int ts,
+                                                         const float* __restrict__ spec, double* __restrict__ st,
+                                                         double* __restrict__ part, NsStep a_) {
     __shared__ double red[3][kBlock / 64];
-    const float a = (float)state[0];
-    const int rows = REAL ? n : n / 2 + 1;
-    const size_t total = (size_t)rows * n;
-    double s0 = 0.0, s1 = 0.0, rr = 0.0;
-    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (size_t)gridDim.x * kBlock) {
-        const int kx = (int)(i / n);
-        const int ky = (int)(i - (size_t)kx * n);
-        float w;
-        if constexpr (REAL) {
-            const float v = static_cast<const float*>(Tv)[(size_t)kx * ts + ky];
-            w = (kx == 0 ? 1.0f : 2.0f) * (ky == 0 ? 1.0f : 2.0f) * (v * v);
-        } else {
-            const float2 v = static_cast<const float2*>(Tv)[(size_t)kx * ts + ky];
-            w = ((kx == 0 || 2 * kx == n) ? 1.0f : 2.0f) * (v.x * v.x + v.y * v.y);
+    __shared__ double stl[5];
+    const int k = a_.k;
+    if (k == 0) {
+        if (threadIdx.x == 0) {
+            double v[4];
+            ns_init(v, a_.first ? a_.alpha_first : st[0], *a_.rn_sq, st[NS_L1], a_.noise, a_.q, a_.rho);
+            for (int i = 0; i < 4; ++i) stl[i] = v[i];
+            stl[4] = 0.0;
         }
-        const float sk = spec[i];
-        const float id = 1.0f / (sk + a);
-        const float t0 = w * id * id;
-        s0 += (double)t0;
-        s1 += (double)(t0 * sk * id);
-        rr += (double)w;
+    } else {
+        const double* prev = st + ns_buf(k - 1);
+        if (prev[4] != 0.0) {
+            if (threadIdx.x < 5) stl[threadIdx.x] = prev[threadIdx.x];
+        } else {
+            double S[3];
+            ns_sums(part + (size_t)3 * NS_BLOCKS * ((k - 1) & 1), red, S);
+            if (threadIdx.x == 0) {
+                double v[4] = {prev[0], prev[1], prev[2], prev[3]};
+                const bool stay = ns_newton(v, S[0], S[1], S[2]);
+                for (int i = 0; i < 4; ++i) stl[i] = v[i];
+                stl[4] = stay ? 1.0 : 0.0;
+            }
+        }
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x < 5) st[ns_buf(k) + threadIdx.x] = stl[threadIdx.x];
+    if (stl[4] != 0.0) return;
+    double* __restrict__ out = part + (size_t)3 * NS_BLOCKS * (k & 1);
+    const float a = (float)stl[0];
+    const int rows = REAL ? n : n / 2 + 1;
+    const int total = rows * n;
+    // a contiguous share of the row-major spectrum per workgroup (a multiple
+    // of kBlock elements), NS_UNROLL loads per thread in flight at a time
+    const int per = (total + NS_BLOCKS * kBlock - 1) / (NS_BLOCKS * kBlock) * kBlock;
+    const int i0 = blockIdx.x * per;
+    const int i1 = min(total, i0 + per);
+    const float rn = 1.0f / (float)n;
+    double s0 = 0.0, s1 = 0.0, rr = 0.0;
+    for (int b = i0 + (int)threadIdx.x; b < i1; b += NS_UNROLL * kBlock) {
+        using V = typename std::conditional<REAL, float, float2>::type;
+        V tv[NS_UNROLL];
+        float wf[NS_UNROLL], sk[NS_UNROLL];
+#pragma unroll
+        for (int u = 0; u < NS_UNROLL; ++u) {
+            // past the share's end: reread its last element with weight 0
+            const int i = b + u * kBlock;
+            const bool ok = i < i1;
+            const int ic = ok ? i : i1 - 1;
+            // row kx = ic / n: a float estimate (ic < 2^24, off by at most
+            // one), then exact
+            int kx = (int)((float)ic * rn);
+            kx -= kx * n > ic ? 1 : 0;
+            kx += (kx + 1) * n <= ic ? 1 : 0;
+            const int ky = ic - kx * n;
+            if constexpr (REAL) wf[u] = ok ? (kx == 0 ? 1.0f : 2.0f) * (ky == 0 ? 1.0f : 2.0f) : 0.0f;
+            else wf[u] = ok ? ((kx == 0 || 2 * kx == n) ? 1.0f : 2.0f) : 0.0f;
+            tv[u] = static_cast<const V*>(Tv)[(size_t)kx * ts + ky];
+            sk[u] = spec[ic];
+        }
+        // every load of the batch is issued before the first use
+        asm volatile("" ::: "memory");
+        float w[NS_UNROLL];
+#pragma unroll
+        for (int u = 0; u < NS_UNROLL; ++u) {
+            if constexpr (REAL) w[u] = wf[u] * (tv[u] * tv[u]);
+            else w[u] = wf[u] * (tv[u].x * tv[u].x + tv[u].y * tv[u].y);
+        }
+#pragma unroll
+        for (int u = 0; u < NS_UNROLL; ++u) {  // w = 0 adds exact zeros
+            const float id = 1.0f / (sk[u] + a);
+            const float t0 = w[u] * id * id;
+            s0 += (double)t0;
+            s1 += (double)(t0 * sk[u] * id);
+            rr += (double)w[u];
+        }
     }
     double v[3] = {s0, s1, rr};
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -742,95 +893,53 @@ __global__ __launch_bounds__(kBlock) void ns_partials_kernel(const void* __restr
     if (threadIdx.x < 3) {
         double t = 0.0;
         for (int w = 0; w < kBlock / 64; ++w) t += red[threadIdx.x][w];
-        part[(size_t)blockIdx.x * 3 + threadIdx.x] = t;
+        out[(size_t)blockIdx.x * 3 + threadIdx.x] = t;
     }
 }
 
-// q_n from ||r^n||^2 (rn_sq) and the noise level; bracket [hi 1e-14, hi] with
-// hi = q_n smax / (1 - q_n), smax = (sum |H|)^2 >= max |Lambda|^2 (there
-// alpha / (s + alpha) >= q_n for every s); start from the previous alpha when
-// it lies inside, else from hi / 2.
-__global__ void ns_init_kernel(double* __restrict__ state, const double* __restrict__ rn_sq,
-                               const float* __restrict__ psf, int p, double noise, double q, double rho,
-                               double alpha_first, int first) {
-    double l1 = 0.0;
-    for (int i = 0; i < p * p; ++i) l1 += fabs((double)psf[i]);
-    const double smax = l1 * l1;
-    const double tau_n = sqrt(*rn_sq) / noise;
-    const double qn = fmax(q, 2.0 * rho + (1.0 + rho) / tau_n);
-    const double hi = qn * smax / (1.0 - qn) * 1.0001 + 1e-30;
-    const double lo = hi * 1e-14;
-    double a = first ? alpha_first : state[0];
-    if (!(a > lo && a < hi)) a = 0.5 * hi;
-    state[0] = a;
-    state[1] = log(lo);
-    state[2] = log(hi);
-    state[3] = qn;
-}
-
-__global__ __launch_bounds__(kBlock) void ns_update_kernel(const double* __restrict__ part, int nparts,
-                                                           double* __restrict__ state, double* __restrict__ hist) {
+// The update after the last step: the result to st[0, 4) and hist.
+__global__ __launch_bounds__(kBlock) void ns_final_kernel(double* __restrict__ st, const double* __restrict__ part,
+                                                          int k_last, double* __restrict__ hist) {
     __shared__ double red[3][kBlock / 64];
-    double v[3] = {0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < nparts; b += kBlock)
-#pragma unroll
-        for (int q = 0; q < 3; ++q) v[q] += part[(size_t)b * 3 + q];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        double x = v[q];
-        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-        if (lane == 0) red[q][wid] = x;
+    const double* prev = st + ns_buf(k_last);
+    double v[4] = {prev[0], prev[1], prev[2], prev[3]};
+    if (prev[4] == 0.0) {
+        double S[3];
+        ns_sums(part + (size_t)3 * NS_BLOCKS * (k_last & 1), red, S);
+        ns_newton(v, S[0], S[1], S[2]);
     }
-    __syncthreads();
     if (threadIdx.x != 0) return;
-    double S0 = 0.0, S1 = 0.0, R = 0.0;
-    for (int w = 0; w < kBlock / 64; ++w) {
-        S0 += red[0][w];
-        S1 += red[1][w];
-        R += red[2][w];
-    }
-    const double a = state[0], la = log(a);
-    double lo = state[1], hi = state[2];
-    const double qn = state[3];
-    const double h = a * a * S0, target = qn * qn * R;
-    double t;
-    const double g = log(h) - log(target);
-    if (R <= 0.0 || fabs(g) < 1e-13) {
-        t = la;  // r = 0 (nothing to solve), or solved to rounding: stay
-    } else {
-        if (g > 0.0) hi = la; else lo = la;
-        const double slope = 2.0 * S1 / S0;
-        t = (slope > 0.0 && isfinite(g)) ? la - g / slope : 0.5 * (lo + hi);
-        // a Newton point on the bracket's closed interval is kept (it sits on
-        // the end just moved when g is near rounding); outside it, bisect
-        if (!(t >= lo && t <= hi)) t = 0.5 * (lo + hi);
-    }
-    state[0] = exp(t);
-    state[1] = lo;
-    state[2] = hi;
-    if (hist) *hist = state[0];
+    for (int i = 0; i < 4; ++i) st[i] = v[i];
+    if (hist) *hist = v[0];
 }
 
+// `steps` Newton steps (steps + 1 launches); state: the 24-double buffer
+// above (sum |psf| set by launch_ns_psf_l1), part: 2 x 3 NS_BLOCKS doubles.
 hipError_t launch_ns_alpha(const void* T, int real, int n, int ts, const float* spec, double* state, double* part,
-                           const double* rn_sq, const float* psf, int p, double noise, double q, double rho,
-                           double alpha_first, int first, int steps, double* hist, hipStream_t s) {
-    hipLaunchKernelGGL(ns_init_kernel, dim3(1), dim3(1), 0, s, state, rn_sq, psf, p, noise, q, rho, alpha_first,
-                       first);
+                           const double* rn_sq, double noise, double q, double rho, double alpha_first, int first,
+                           int steps, double* hist, hipStream_t s) {
+    if (steps < 1 || (long)(real ? n : n / 2 + 1) * n >= (1L << 24)) return hipErrorInvalidValue;
     for (int k = 0; k < steps; ++k) {
+        const NsStep a{rn_sq, noise, q, rho, alpha_first, first, k};
         if (real)
-            hipLaunchKernelGGL(ns_partials_kernel<true>, dim3(NS_BLOCKS), dim3(kBlock), 0, s, T, n, ts, spec,
-                               (const double*)state, part);
+            hipLaunchKernelGGL(ns_step_kernel<true>, dim3(NS_BLOCKS), dim3(kBlock), 0, s, T, n, ts, spec, state, part,
+                               a);
         else
-            hipLaunchKernelGGL(ns_partials_kernel<false>, dim3(NS_BLOCKS), dim3(kBlock), 0, s, T, n, ts, spec,
-                               (const double*)state, part);
-        hipLaunchKernelGGL(ns_update_kernel, dim3(1), dim3(kBlock), 0, s, (const double*)part, NS_BLOCKS, state,
-                           k == steps - 1 ? hist : (double*)nullptr);
+            hipLaunchKernelGGL(ns_step_kernel<false>, dim3(NS_BLOCKS), dim3(kBlock), 0, s, T, n, ts, spec, state,
+                               part, a);
     }
+    hipLaunchKernelGGL(ns_final_kernel, dim3(1), dim3(kBlock), 0, s, state, (const double*)part, steps - 1, hist);
     return hipGetLastError();
 }
 
-int ns_partials_needed() { return 3 * NS_BLOCKS; }
+hipError_t launch_ns_psf_l1(const float* psf, int p, double* state, hipStream_t s) {
+    hipLaunchKernelGGL(ns_psf_l1_kernel, dim3(1), dim3(1), 0, s, psf, p, state);
+    return hipGetLastError();
+}
+
+int ns_partials_needed() { return 2 * 3 * NS_BLOCKS; }
+int ns_state_doubles() { return 24; }
+int ns_alpha_launches(int steps) { return steps + 1; }
 
 // ---------------------------------------------------------------------------
 // launch helpers

@@ -310,12 +310,18 @@ hipError_t launch_fft_cols_filter_inverse(float2* T, int n, int ts, const float*
 // columns: forward FFT, complex values into cspec (dense [n/2+1][n])
 hipError_t launch_fft_cols_complex(const float2* T, int n, int ts, float2* cspec, const FftDesc& fd,
                                    const float2* tw, hipStream_t s);
-// Algorithm 4-NS: alpha_n on the device (state, hist: device doubles; part: >= ns_partials_needed())
-// from the BCCB half spectrum T (float2, real = 0) or the DCT coefficients (float, real = 1)
+// Algorithm 4-NS: alpha_n on the device from the BCCB half spectrum T
+// (float2, real = 0) or the DCT coefficients (float, real = 1); state:
+// ns_state_doubles() device doubles (launch_ns_psf_l1 after every PSF
+// change), alpha_n at state[0]; hist: a device double or null; part: at
+// least ns_partials_needed() device doubles
 hipError_t launch_ns_alpha(const void* T, int real, int n, int ts, const float* spec, double* state, double* part,
-                           const double* rn_sq, const float* psf, int p, double noise, double q, double rho,
-                           double alpha_first, int first, int steps, double* hist, hipStream_t s);
+                           const double* rn_sq, double noise, double q, double rho, double alpha_first, int first,
+                           int steps, double* hist, hipStream_t s);
+hipError_t launch_ns_psf_l1(const float* psf, int p, double* state, hipStream_t s);
 int ns_partials_needed();
+int ns_state_doubles();
+int ns_alpha_launches(int steps);  // kernels launch_ns_alpha enqueues
 // columns: forward FFT, write spec = |.|^2 (same transposed layout)
 hipError_t launch_fft_cols_power(const float2* T, int n, int ts, float* spec, const FftDesc& fd,
                                  const float2* tw, hipStream_t s);

@@ -390,9 +390,9 @@ int do_ct_precond_ns(mlba_plan_s* P, const float* r, float* t, const double* rn_
         MARK(PRECOND, FFT_ROWS_FWD);
         HIPCHK(launch_dct_cols_forward(Tr, n, P->ts, P->fd, P->tw, P->dtw, s));
         MARK(PRECOND, FFT_COLS);
-        HIPCHK(launch_ns_alpha(Tr, 1, n, P->ts, P->spec, P->ns, P->partials, rn_sq, P->psf, P->p, noise, q, rho,
-                               alpha_first, first, 12, hist, s));
-        STCHK(prof_mark(P, MLBA_PHASE_PRECOND, MLBA_KERNEL_OTHER, 1 + 2 * 12, s));
+        HIPCHK(launch_ns_alpha(Tr, 1, n, P->ts, P->spec, P->ns, P->partials, rn_sq, noise, q, rho,
+                               alpha_first, first, kNsSteps, hist, s));
+        STCHK(prof_mark(P, MLBA_PHASE_PRECOND, MLBA_KERNEL_OTHER, ns_alpha_launches(kNsSteps), s));
         HIPCHK(launch_dct_cols_filter_inverse(Tr, n, P->ts, P->spec, P->ns, inv, P->lamr, P->fd, P->tw, P->dtw, s));
         MARK(PRECOND, FFT_COLS);
         HIPCHK(launch_dct_rows_inv(Tr, n, P->ts, t, P->fd, P->tw, P->dtw, s, accum));
@@ -404,9 +404,9 @@ int do_ct_precond_ns(mlba_plan_s* P, const float* r, float* t, const double* rn_
     MARK(PRECOND, FFT_ROWS_FWD);
     HIPCHK(launch_fft_cols_forward(T, n, P->ts, P->fd, P->tw, s));
     MARK(PRECOND, FFT_COLS);
-    HIPCHK(launch_ns_alpha(T, 0, n, P->ts, P->spec, P->ns, P->partials, rn_sq, P->psf, P->p, noise, q, rho,
-                           alpha_first, first, 12, hist, s));
-    STCHK(prof_mark(P, MLBA_PHASE_PRECOND, MLBA_KERNEL_OTHER, 1 + 2 * 12, s));
+    HIPCHK(launch_ns_alpha(T, 0, n, P->ts, P->spec, P->ns, P->partials, rn_sq, noise, q, rho,
+                           alpha_first, first, kNsSteps, hist, s));
+    STCHK(prof_mark(P, MLBA_PHASE_PRECOND, MLBA_KERNEL_OTHER, ns_alpha_launches(kNsSteps), s));
     HIPCHK(launch_fft_cols_filter_inverse(T, n, P->ts, P->spec, P->ns, inv, P->lamc, P->fd, P->tw, s));
     MARK(PRECOND, FFT_COLS);
     HIPCHK(launch_fft_rows_c2r(T, n, P->ts, t, P->fd, P->tw, s, accum));
@@ -825,7 +825,11 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
         ALLOC(P->tw, tw.size());
         ALLOC(P->dtw, (size_t)n);
         ALLOC(P->costab, (size_t)2 * CN);
-        ALLOC(P->ns, 8);
+        ALLOC(P->ns, (size_t)ns_state_doubles());
+        if (hipMemsetAsync(P->ns, 0, (size_t)ns_state_doubles() * sizeof(double), s) != hipSuccess) {
+            free_plan(P);
+            return MLBA_EHIP;
+        }
         if (precond == MLBA_PRECOND_AR) {
             P->ts = ar_workspace_stride(n);
             ALLOC(P->spec, obs);
@@ -883,6 +887,7 @@ int mlba_plan_set_psf(mlba_plan_t P, const float* psf, hipStream_t s) {
     if (!P || !psf) return MLBA_EINVAL;
     HIPCHK(hipMemcpyAsync(P->psf, psf, (size_t)P->p * P->p * sizeof(float), hipMemcpyDeviceToDevice, s));
     if (P->fc.H) HIPCHK(launch_fftconv_spectrum(P->fc, P->psf, P->p, s));
+    if (P->ns) HIPCHK(launch_ns_psf_l1(P->psf, P->p, P->ns, s));
     return note_work(P, compute_spectrum(P, s), s);
 }
 
@@ -1291,10 +1296,10 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
                 break;
             }
             if (ns) {  // T holds F r: alpha_n, then the filter and the inverse column transform
-                HIPCHK(launch_ns_alpha(T, 0, n, P->ts, P->spec, P->ns, P->partials, P->rn + (i - ring_base), P->psf,
-                                       P->p, stop->noise_norm, as.ns_q, as.ns_rho, as.alpha0, i == 0 ? 1 : 0,
-                                       12, P->ahist + (i - ring_base), s));
-                STCHK(prof_mark(P, MLBA_PHASE_PRECOND, MLBA_KERNEL_OTHER, 1 + 2 * 12, s));
+                HIPCHK(launch_ns_alpha(T, 0, n, P->ts, P->spec, P->ns, P->partials, P->rn + (i - ring_base),
+                                       stop->noise_norm, as.ns_q, as.ns_rho, as.alpha0, i == 0 ? 1 : 0,
+                                       kNsSteps, P->ahist + (i - ring_base), s));
+                STCHK(prof_mark(P, MLBA_PHASE_PRECOND, MLBA_KERNEL_OTHER, ns_alpha_launches(kNsSteps), s));
                 HIPCHK(launch_fft_cols_filter_inverse(T, n, P->ts, P->spec, P->ns, inv, P->lamc, P->fd, P->tw, s));
                 MARK(PRECOND, FFT_COLS);
             }

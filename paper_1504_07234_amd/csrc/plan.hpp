@@ -89,6 +89,8 @@ constexpr int kAutoLanczosSteps = 1000;
 constexpr double kAutoLanczosTol = 1e-9;
 constexpr int kAutoPowerSteps = 50;
 int mlba_internal_auto_delta(mlba_plan_s* P, double alpha, double* delta, hipStream_t s);
+// Newton steps for alpha_n of Algorithm 4-NS in every iteration.
+constexpr int kNsSteps = 12;
 
 // Descriptor of a plan's sizes and buffers (the per-image record of a batch;
 // the single-image path builds the same record so both run identical jobs).
