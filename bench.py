@@ -415,6 +415,7 @@ def alg4_section(w, g, noise, steps: int = 30):
     # 4-NS with the DCT of the symmetrised PSF on the reflective model (the DCT
     # form of Example 4's Alg-BC4-NS)
     with mlba.Plan(n, w.p, mlba.REFLECT, mlba.DCT, w.levels, psf) as plan:
+        blur = plan.autotune(reps=3)["blur"]  # the residual's A
         f = torch.empty((n, n), dtype=torch.float32, device="cuda")
         plan.restore(g, alpha=0.5, mu=w.mu, delta=1.0, iters=2, out=f, implicit=True, method=mlba.ALG4,
                      ns=(0.5, 1e-4), stop=(noise, 0.0, 1), track=False)
@@ -424,9 +425,44 @@ def alg4_section(w, g, noise, steps: int = 30):
                                method=mlba.ALG4, ns=(0.5, 1e-4), stop=(noise, 0.0, 1))
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        out["ns_dct"] = {"model": "reflective", "precond": "dct", "q": 0.5, "rho": 1e-4,
+        out["ns_dct"] = {"model": "reflective", "precond": "dct", "blur": blur, "q": 0.5, "rho": 1e-4,
                          "iters_to_stop": info.iters_done, "s_total": round(el, 5),
                          "ms_per_step": round(el * 1e3 / max(info.iters_done, 1), 5)}
+    return out
+
+
+def square_models_section(w, g, steps: int = 30):
+    """Eq. (MLBA2) on the square models of Table 1 at 2048^2 (p = 31, L = 3,
+    alpha = 0.02, implicit state, the library's automatic step, the blur the
+    plan autotuner picks): zero and reflective pads with the BCCB
+    preconditioner (Algorithm 1), the reflective pad with the DCT of the
+    symmetrised PSF (Algorithm 3), and the periodic pad with the BCCB matrix
+    (there A = C and the residual is formed in the spectrum)."""
+    import torch
+
+    from paper_1504_07234_amd import mlba
+
+    psf = torch.as_tensor(w.psf, dtype=torch.float32).cuda()
+    n = w.n
+    out = []
+    for bc, pc in (("zero", "bccb"), ("reflect", "bccb"), ("reflect", "dct"), ("periodic", "bccb")):
+        BC = {"zero": mlba.ZERO, "reflect": mlba.REFLECT, "periodic": mlba.PERIODIC}[bc]
+        PC = {"bccb": mlba.BCCB, "dct": mlba.DCT}[pc]
+        with mlba.Plan(n, w.p, BC, PC, w.levels, psf) as plan:
+            tune = plan.autotune(reps=3)
+            delta = plan.auto_step(w.alpha0)
+            f = torch.empty((n, n), dtype=torch.float32, device="cuda")
+            om = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+            plan.restore(g, alpha=w.alpha0, mu=w.mu, delta=delta, iters=3, z=om, out=f, track=False,
+                         implicit=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.restore(g, alpha=w.alpha0, mu=w.mu, delta=delta, iters=steps, k0=3, z=om, out=f, track=False,
+                         implicit=True)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+        out.append({"model": bc, "precond": pc, "blur": tune["blur"], "delta": round(delta, 6), "steps": steps,
+                    "ms_per_step": round(el * 1e3 / steps, 5), "Mpx_it_s": round(n * n * steps / el / 1e6, 2)})
     return out
 
 
@@ -776,6 +812,7 @@ def main() -> int:
     if not args.no_alg4:
         out["alg4"] = alg4_section(w, g, float(w.noise_level * blurred.double().norm()))
         out["alg2"] = alg2_section(w, g, delta)
+        out["square_models"] = square_models_section(w, g)
     if not args.no_ar:
         out["antireflective"] = antireflective_section()
     if not args.no_cpu:

@@ -52,15 +52,16 @@ static int fc_seq_shift(int batch) {
 }
 
 // Rows pass: row pairs pair0 + blk*G + g of the M grid; entry (Y, X) is
-// src[Y - off][X - off] inside the S x S box at (off, off), else 0.  With
-// `ar`, the box is widened by off on every side and holds the source's
-// antireflective pad there (section 2.2): the grid then carries E src E^T.
-// NT > 0: M == NT and G == 1.
+// src[Y - off][X - off] inside the S x S box at (off, off), else 0.  With an
+// extension `ext` other than EXT_ZERO, the box is widened by off on every
+// side and holds the source's extension there (Table 1 and section 2.2: the
+// reflective, periodic or antireflective pad): the grid then carries
+// E src E^T.  NT > 0: M == NT and G == 1.
 template <int NT>
 __global__ __launch_bounds__(kBlock) void fc_rows_fwd_kernel(const float* __restrict__ src, int S, int off, int M_,
                                                              float2* __restrict__ T, int ts, FftDesc fd,
                                                              const float2* __restrict__ tw, int G_, int seq_shift,
-                                                             int pair0, int pair_end, int ar) {
+                                                             int pair0, int pair_end, int ext) {
     extern __shared__ float2 buf[];
     const int M = NT > 0 ? NT : M_;
     const int G = NT > 0 ? 1 : G_;
@@ -76,10 +77,10 @@ __global__ __launch_bounds__(kBlock) void fc_rows_fwd_kernel(const float* __rest
             const int x = X - off;
             float a = 0.0f, b = 0.0f;
             const int y0 = Y - off, y1 = Y + 1 - off;
-            if (ar) {
+            if (ext != EXT_ZERO) {
                 if (pb + g < pair_end && x >= -off && x < S + off) {
-                    if (y0 >= -off && y0 < S + off) a = fetch_ext(src, S, y0, x, EXT_ANTIREFLECT);
-                    if (y1 >= -off && y1 < S + off) b = fetch_ext(src, S, y1, x, EXT_ANTIREFLECT);
+                    if (y0 >= -off && y0 < S + off) a = fetch_ext(src, S, y0, x, ext);
+                    if (y1 >= -off && y1 < S + off) b = fetch_ext(src, S, y1, x, ext);
                 }
             } else if (pb + g < pair_end && x >= 0 && x < S) {
                 if (y0 >= 0 && y0 < S) a = src[(size_t)y0 * S + x];
@@ -104,16 +105,48 @@ __global__ __launch_bounds__(kBlock) void fc_rows_fwd_kernel(const float* __rest
     }
 }
 
+// The transpose E^T of a square model's extension along one axis: the grid
+// positions (0 <= Y < n + 2c) whose extended value is pixel k of the n-point
+// axis: k + c itself, and under the reflective or periodic model its copies
+// in the pads of width c (p <= n keeps them distinct).
+__device__ __forceinline__ int ext_preimages(int k, int n, int c, int ext, int* pre) {
+    int cnt = 0;
+    pre[cnt++] = k + c;
+    if (ext == EXT_REFLECT) {
+        if (k < c) pre[cnt++] = c - 1 - k;
+        if (k >= n - c) pre[cnt++] = 2 * n - 1 - k + c;
+    } else if (ext == EXT_PERIODIC) {
+        if (k < c) pre[cnt++] = k + n + c;
+        if (k >= n - c) pre[cnt++] = k - n + c;
+    }
+    return cnt;
+}
+
+// Sum of v(Y) over the preimages Y of pixel k (fold < 0: v(k) itself).
+template <class F>
+__device__ __forceinline__ float2 fold_sum(int k, int n, int c, int fold, F v) {
+    if (fold < 0) return v(k);
+    int pre[3];
+    const int cnt = ext_preimages(k, n, c, fold, pre);
+    float2 a = v(pre[0]);
+    for (int i = 1; i < cnt; ++i) a = cadd(a, v(pre[i]));
+    return a;
+}
+
 // Columns pass over CC half-spectrum rows per workgroup; rows outside
 // [y_lo, y_hi) of the input are zero.  mode 0: forward FFT, times Hs (or
 // conj(Hs)) * inv, inverse FFT, written back for the rows [o_lo, o_hi) that the
-// inverse row pass reads; mode 1: forward FFT into cspec.
+// inverse row pass reads; mode 1: forward FFT into cspec.  With fold >= 0
+// (a square model's extension, n-point image, pad c) mode 0 stores instead
+// the rows of E^T applied along the columns: row y < n holds the sum over the
+// preimages of y, rows [0, n + (n & 1)) are written (an odd n's last one 0).
 template <int NT>
 __global__ __launch_bounds__(kBlock) void fc_cols_kernel(float2* __restrict__ T, int M_, int ts,
                                                          const float2* __restrict__ Hs, int conj_h, float inv,
                                                          int y_lo, int y_hi, int mode, float2* __restrict__ cspec,
                                                          FftDesc fd, const float2* __restrict__ tw, int CC_,
-                                                         int seq_shift, int o_lo, int o_hi) {
+                                                         int seq_shift, int o_lo, int o_hi, int fold, int fn,
+                                                         int fcn) {
     extern __shared__ float2 buf[];
     const int M = NT > 0 ? NT : M_;
     const int CC = NT > 0 ? 1 : CC_;
@@ -168,6 +201,17 @@ __global__ __launch_bounds__(kBlock) void fc_cols_kernel(float2* __restrict__ T,
     }
     __syncthreads();
     lds_fft_any<1, NT, FC_EPT>(buf, fd, cc, seq_shift, tw, NT > 0 ? twp.w : nullptr);
+    if (fold >= 0) {
+        const int rows = fn + (fn & 1);
+        for (int idx = threadIdx.x; idx < cc * rows; idx += kBlock) {
+            const int q = idx / rows;
+            const int y = idx - q * rows;
+            T[(size_t)(k0 + q) * ts + y] =
+                y < fn ? fold_sum(y, fn, fcn, fold, [&](int Y) { return buf[lds_slot(q * M + Y)]; })
+                       : make_float2(0.0f, 0.0f);
+        }
+        return;
+    }
     for (int idx = threadIdx.x; idx < cc * M; idx += kBlock) {
         const int q = idx / M;
         const int y = idx - q * M;
@@ -178,13 +222,16 @@ __global__ __launch_bounds__(kBlock) void fc_cols_kernel(float2* __restrict__ T,
 // Inverse rows pass over row pairs pair0 + blk*G + g; output (Y, X) of the M
 // grid inside [oy, oy + D) x [ox, ox + D) goes to dst[Y - oy][X - ox]:
 // g ? g - v (squared-norm partial per workgroup) : (accum ? dst + v : v).
+// With fold >= 0 (ox = 0) the value at x is instead the sum over the
+// preimages of x under the square model's extension (E^T along the rows, pad
+// fcn).
 template <int NT>
 __global__ __launch_bounds__(kBlock) void fc_rows_inv_kernel(const float2* __restrict__ T, int M_, int ts,
                                                              FftDesc fd, const float2* __restrict__ tw, int G_,
                                                              int seq_shift, int pair0, int pair_end, int oy, int ox,
                                                              int D, float* __restrict__ dst,
                                                              const float* __restrict__ g, int accum,
-                                                             double* __restrict__ partials) {
+                                                             double* __restrict__ partials, int fold, int fcn) {
     extern __shared__ float2 buf[];
     __shared__ double red[kBlock / 64];
     const int M = NT > 0 ? NT : M_;
@@ -242,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void fc_rows_inv_kernel(const float2* __res
             const int X = k * kBlock + (int)threadIdx.x;
             const int x = X - ox;
             if ((NT % kBlock != 0 && X >= NT) || pb >= pair_end || x < 0 || x >= D) continue;
-            const float2 v = buf[lds_slot(X)];
+            const float2 v = fold_sum(X, D, fcn, fold, [&](int Xs) { return buf[lds_slot(Xs)]; });
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int y = 2 * pb + h - oy;
@@ -266,7 +313,7 @@ __global__ __launch_bounds__(kBlock) void fc_rows_inv_kernel(const float2* __res
             if (pb + gg >= pair_end) continue;
             const int x = X - ox;
             if (x < 0 || x >= D) continue;
-            const float2 v = buf[lds_slot(idx)];
+            const float2 v = fold_sum(X, D, fcn, fold, [&](int Xs) { return buf[lds_slot(gg * M + Xs)]; });
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int y = 2 * (pb + gg) + h - oy;
@@ -571,45 +618,46 @@ __global__ __launch_bounds__(kBlock) void precond_fc_blurT_kernel(
 // ---- launchers ------------------------------------------------------------
 
 hipError_t launch_fc_rows_fwd(const FftConv& c, const float* src, int S, int off, int y_lo, int y_hi,
-                              hipStream_t s, int ar) {
+                              hipStream_t s, int ext) {
     const int G = fc_pairs_per_block(c.M);
     const int p0 = y_lo / 2, p1 = (y_hi + 1) / 2;
     const int blocks = (p1 - p0 + G - 1) / G;
     if (blocks <= 0) return hipSuccess;
     if (c.M == kFixedM && G == 1)
         hipLaunchKernelGGL(fc_rows_fwd_kernel<kFixedM>, dim3(blocks), dim3(kBlock), lds_bytes(c.M, c.M), s, src, S,
-                           off, c.M, c.T, c.ts, c.fd, c.tw, 1, fc_seq_shift(1), p0, p1, ar);
+                           off, c.M, c.T, c.ts, c.fd, c.tw, 1, fc_seq_shift(1), p0, p1, ext);
     else if (c.M == kFixedM2 && G == 1)
         hipLaunchKernelGGL(fc_rows_fwd_kernel<kFixedM2>, dim3(blocks), dim3(kBlock), lds_bytes(c.M, c.M), s, src, S,
-                           off, c.M, c.T, c.ts, c.fd, c.tw, 1, fc_seq_shift(1), p0, p1, ar);
+                           off, c.M, c.T, c.ts, c.fd, c.tw, 1, fc_seq_shift(1), p0, p1, ext);
     else
         hipLaunchKernelGGL(fc_rows_fwd_kernel<0>, dim3(blocks), dim3(kBlock), lds_bytes(G * c.M, c.M), s, src, S, off,
-                           c.M, c.T, c.ts, c.fd, c.tw, G, fc_seq_shift(G), p0, p1, ar);
+                           c.M, c.T, c.ts, c.fd, c.tw, G, fc_seq_shift(G), p0, p1, ext);
     return hipGetLastError();
 }
 
 hipError_t launch_fc_cols(const FftConv& c, int conj_h, int y_lo, int y_hi, int mode, float2* cspec, hipStream_t s,
-                          int o_lo, int o_hi) {
+                          int o_lo, int o_hi, int fold, int fn, int fcn) {
     const int CC = fc_cols_per_block(c.M);
     const int half = c.M / 2 + 1;
     const float inv = (float)(1.0 / ((double)c.M * (double)c.M));
     if (c.M == kFixedM && CC == 1)
         hipLaunchKernelGGL(fc_cols_kernel<kFixedM>, dim3(half), dim3(kBlock), lds_bytes(c.M, c.M), s, c.T, c.M, c.ts,
                            (const float2*)c.H, conj_h, inv, y_lo, y_hi, mode, cspec, c.fd, c.tw, 1, fc_seq_shift(1), o_lo,
-                           o_hi);
+                           o_hi, fold, fn, fcn);
     else if (c.M == kFixedM2 && CC == 1)
         hipLaunchKernelGGL(fc_cols_kernel<kFixedM2>, dim3(half), dim3(kBlock), lds_bytes(c.M, c.M), s, c.T, c.M, c.ts,
                            (const float2*)c.H, conj_h, inv, y_lo, y_hi, mode, cspec, c.fd, c.tw, 1, fc_seq_shift(1), o_lo,
-                           o_hi);
+                           o_hi, fold, fn, fcn);
     else
         hipLaunchKernelGGL(fc_cols_kernel<0>, dim3((half + CC - 1) / CC), dim3(kBlock), lds_bytes(CC * c.M, c.M), s,
                            c.T, c.M, c.ts, (const float2*)c.H, conj_h, inv, y_lo, y_hi, mode, cspec, c.fd, c.tw, CC,
-                           fc_seq_shift(CC), o_lo, o_hi);
+                           fc_seq_shift(CC), o_lo, o_hi, fold, fn, fcn);
     return hipGetLastError();
 }
 
 hipError_t launch_fc_rows_inv(const FftConv& c, int oy, int ox, int D, float* dst, const float* g, int accum,
-                              double* partials, int* n_partials, hipStream_t s) {
+                              double* partials, int* n_partials, hipStream_t s, int fold, int fcn) {
+    if (fold >= 0 && ox != 0) return hipErrorInvalidValue;
     const int G = fc_pairs_per_block(c.M);
     const int p0 = oy / 2, p1 = (oy + D + 1) / 2;
     const int blocks = (p1 - p0 + G - 1) / G;
@@ -617,15 +665,15 @@ hipError_t launch_fc_rows_inv(const FftConv& c, int oy, int ox, int D, float* ds
     if (c.M == kFixedM && G == 1)
         hipLaunchKernelGGL(fc_rows_inv_kernel<kFixedM>, dim3(blocks), dim3(kBlock), lds_bytes(c.M, c.M), s,
                            (const float2*)c.T, c.M, c.ts, c.fd, c.tw, 1, fc_seq_shift(1), p0, p1, oy, ox, D, dst, g,
-                           accum, partials);
+                           accum, partials, fold, fcn);
     else if (c.M == kFixedM2 && G == 1)
         hipLaunchKernelGGL(fc_rows_inv_kernel<kFixedM2>, dim3(blocks), dim3(kBlock), lds_bytes(c.M, c.M), s,
                            (const float2*)c.T, c.M, c.ts, c.fd, c.tw, 1, fc_seq_shift(1), p0, p1, oy, ox, D, dst, g,
-                           accum, partials);
+                           accum, partials, fold, fcn);
     else
         hipLaunchKernelGGL(fc_rows_inv_kernel<0>, dim3(blocks), dim3(kBlock), lds_bytes(G * c.M, c.M), s,
                            (const float2*)c.T, c.M, c.ts, c.fd, c.tw, G, fc_seq_shift(G), p0, p1, oy, ox, D, dst, g,
-                           accum, partials);
+                           accum, partials, fold, fcn);
     return hipGetLastError();
 }
 
@@ -637,7 +685,7 @@ int fftconv_partials_count(int M, int n) {
 hipError_t launch_fftconv_spectrum(const FftConv& c, const float* psf, int p, hipStream_t s) {
     hipError_t e = launch_fc_rows_fwd(c, psf, p, 0, 0, p, s);
     if (e != hipSuccess) return e;
-    return launch_fc_cols(c, 0, 0, p, 1, c.H, s, 0, c.M);
+    return launch_fc_cols(c, 0, 0, p, 1, c.H, s, 0, c.M, -1, 0, 0);
 }
 
 hipError_t launch_fc_residual_precond_rows(const FftConv& c, int n, int p, const float* g, float* r_out,

@@ -199,18 +199,22 @@ struct PrecondRows {
     const float2* tw;
 };
 // The three passes of the FFT blur, one launch each: forward rows of the
-// S x S image placed at (off, off) (rows outside [y_lo, y_hi) are zero; `ar`:
-// with its antireflective pad of width off around it, i.e. E src E^T at 0),
-// columns (mode 0: product with the PSF spectrum or its conjugate and the
-// inverse, stored for the rows [o_lo, o_hi) only, whole row pairs; mode 1:
-// forward only into cspec), inverse rows cropped to the
-// D x D window at (oy, ox) with the epilogue g - . (partials) / plain / +=.
+// S x S image placed at (off, off) (rows outside [y_lo, y_hi) are zero; `ext`
+// other than EXT_ZERO: with its pad of width off around it under that
+// extension, i.e. E src E^T at 0), columns (mode 0: product with the PSF
+// spectrum or its conjugate and the inverse, stored for the rows
+// [o_lo, o_hi) only, whole row pairs; mode 1: forward only into cspec),
+// inverse rows cropped to the D x D window at (oy, ox) with the epilogue
+// g - . (partials) / plain / +=.  fold >= 0 (an Ext of a square model, fn x fn
+// image, pad fcn): the column pass stores E^T along the columns in rows
+// [0, fn + (fn & 1)) and the row pass (oy = ox = 0, D = fn) applies E^T along
+// the rows.
 hipError_t launch_fc_rows_fwd(const FftConv& c, const float* src, int S, int off, int y_lo, int y_hi, hipStream_t s,
-                              int ar = 0);
+                              int ext = EXT_ZERO);
 hipError_t launch_fc_cols(const FftConv& c, int conj_h, int y_lo, int y_hi, int mode, float2* cspec, hipStream_t s,
-                          int o_lo, int o_hi);
+                          int o_lo, int o_hi, int fold = -1, int fn = 0, int fcn = 0);
 hipError_t launch_fc_rows_inv(const FftConv& c, int oy, int ox, int D, float* dst, const float* g, int accum,
-                              double* partials, int* n_partials, hipStream_t s);
+                              double* partials, int* n_partials, hipStream_t s, int fold = -1, int fcn = 0);
 // Row passes fused with the preconditioner's (n even, n <= 2048):
 // the residual rows r = g - A u (after launch_fc_cols of u) with their
 // squared-norm partials, then the preconditioner's forward row transform of r

@@ -180,17 +180,34 @@ void free_plan(mlba_plan_s* P) {
 size_t NN(const mlba_plan_s* P) { return (size_t)P->N * P->N; }
 
 // r = g - A u (g may be null: y = A u); partial sums of r^2 into P->partials
+// The first two passes of A u on the FFT grid (section 2.1): the m x m grid
+// (m = n + p - 1) holds the rectangular model's unknown at the origin, or a
+// square model's image at (c, c) with its pad of Table 1 or section 2.2 around
+// it (E u; the zero pad's rows are skipped); the column pass keeps the rows
+// [p - 1, p - 1 + n) that the output crop reads.
+int blur_grid_forward(mlba_plan_s* P, const float* u, hipStream_t s) {
+    const int n = P->n, p = P->p, m = n + p - 1, c = P->c;
+    int y_lo = 0, y_hi = m;
+    if (P->bc == MLBA_BC_RECT) {
+        HIPCHK(launch_fc_rows_fwd(P->fc, u, m, 0, 0, m, s));
+    } else if (P->bc == MLBA_BC_ZERO) {
+        y_lo = c;
+        y_hi = c + n;
+        HIPCHK(launch_fc_rows_fwd(P->fc, u, n, c, y_lo, y_hi, s));
+    } else {
+        HIPCHK(launch_fc_rows_fwd(P->fc, u, n, c, 0, m, s, ext_of_bc(P->bc)));
+    }
+    MARK(BLUR, FC_ROWS_FWD);
+    HIPCHK(launch_fc_cols(P->fc, 0, y_lo, y_hi, 0, nullptr, s, p - 1, p - 1 + n + (n & 1)));
+    MARK(BLUR, FC_COLS);
+    return MLBA_OK;
+}
+
 int do_blur(mlba_plan_s* P, const float* u, const float* g, float* y, bool want_norm, int* nparts,
             hipStream_t s) {
-    if (P->blur_fft) {  // the grid holds u (rectangular) or its antireflective extension, m x m at the origin
-        const int n = P->n, p = P->p, N = n + p - 1;
-        if (P->bc == MLBA_BC_ANTIREFLECT)
-            HIPCHK(launch_fc_rows_fwd(P->fc, u, n, P->c, 0, N, s, 1));
-        else
-            HIPCHK(launch_fc_rows_fwd(P->fc, u, N, 0, 0, N, s));
-        MARK(BLUR, FC_ROWS_FWD);
-        HIPCHK(launch_fc_cols(P->fc, 0, 0, N, 0, nullptr, s, p - 1, p - 1 + n + (n & 1)));
-        MARK(BLUR, FC_COLS);
+    if (P->blur_fft) {
+        const int n = P->n, p = P->p;
+        STCHK(blur_grid_forward(P, u, s));
         HIPCHK(launch_fc_rows_inv(P->fc, p - 1, p - 1, n, y, g, 0, g && want_norm ? P->partials : nullptr, nparts,
                                   s));
         MARK(BLUR, FC_ROWS_INV);
@@ -219,7 +236,7 @@ PrecondRows precond_rows(const mlba_plan_s* P) {
 // the preconditioner's forward row pass run as one launch (as do the
 // preconditioner's inverse row pass and the forward row pass of A^T).
 bool fused_fft_path(const mlba_plan_s* P) {
-    return P->blur_fft && P->bc == MLBA_BC_RECT && P->precond == MLBA_PRECOND_BCCB &&
+    return P->blur_fft && P->bc != MLBA_BC_ANTIREFLECT && P->precond == MLBA_PRECOND_BCCB &&
            fftconv_fusable(P->fc, P->n, precond_rows(P));
 }
 
@@ -232,36 +249,50 @@ bool fused_ar_path(const mlba_plan_s* P) {
 
 // r = g - A u with its partials and the preconditioner's forward row pass of r
 int do_blur_residual_precond_rows(mlba_plan_s* P, const float* u, const float* g, int* nparts, hipStream_t s) {
-    const int n = P->n, p = P->p, N = n + p - 1;
-    HIPCHK(launch_fc_rows_fwd(P->fc, u, N, 0, 0, N, s));
-    MARK(BLUR, FC_ROWS_FWD);
-    HIPCHK(launch_fc_cols(P->fc, 0, 0, N, 0, nullptr, s, p - 1, p - 1 + n + (n & 1)));
-    MARK(BLUR, FC_COLS);
+    const int n = P->n, p = P->p;
+    STCHK(blur_grid_forward(P, u, s));
     HIPCHK(launch_fc_residual_precond_rows(P->fc, n, p, g, nullptr, P->partials, nparts, precond_rows(P), s));
     MARK(BLUR, FC_RESIDUAL_PRECOND_ROWS);
     return MLBA_OK;
 }
 
-// the preconditioner's inverse row pass, then w (+)= A^T t
-int do_precond_rows_blurT(mlba_plan_s* P, float* w, int accum, hipStream_t s) {
-    const int n = P->n, p = P->p, N = n + p - 1;
-    HIPCHK(launch_precond_rows_fc_fwd(P->fc, n, p, precond_rows(P), nullptr, s));
-    MARK(BLUR_T, PRECOND_ROWS_FC_FWD);
-    HIPCHK(launch_fc_cols(P->fc, 1, p - 1, N, 0, nullptr, s, 0, N + (N & 1)));
-    MARK(BLUR_T, FC_COLS);
-    HIPCHK(launch_fc_rows_inv(P->fc, 0, 0, N, w, nullptr, accum, nullptr, nullptr, s));
+// The last two passes of w (+)= A^T y on the FFT grid, after the forward rows
+// of y placed at (p - 1, p - 1): the column pass with the conjugate spectrum,
+// then the inverse rows; the circular correlation cropped to [0, m)^2
+// (rectangular model), or folded back onto the n x n image by E^T, the
+// transpose of the square model's pad (zero: the crop at (c, c)).
+int blurT_grid_finish(mlba_plan_s* P, float* w, int accum, hipStream_t s) {
+    const int n = P->n, p = P->p, m = n + p - 1;
+    if (P->bc == MLBA_BC_RECT) {
+        HIPCHK(launch_fc_cols(P->fc, 1, p - 1, m, 0, nullptr, s, 0, m + (m & 1)));
+        MARK(BLUR_T, FC_COLS);
+        HIPCHK(launch_fc_rows_inv(P->fc, 0, 0, m, w, nullptr, accum, nullptr, nullptr, s));
+    } else {
+        const int fold = ext_of_bc(P->bc);
+        HIPCHK(launch_fc_cols(P->fc, 1, p - 1, m, 0, nullptr, s, 0, 0, fold, n, P->c));
+        MARK(BLUR_T, FC_COLS);
+        HIPCHK(launch_fc_rows_inv(P->fc, 0, 0, n, w, nullptr, accum, nullptr, nullptr, s, fold, P->c));
+    }
     MARK(BLUR_T, FC_ROWS_INV);
     return MLBA_OK;
 }
 
+// the preconditioner's inverse row pass, then w (+)= A^T t
+int do_precond_rows_blurT(mlba_plan_s* P, float* w, int accum, hipStream_t s) {
+    HIPCHK(launch_precond_rows_fc_fwd(P->fc, P->n, P->p, precond_rows(P), nullptr, s));
+    MARK(BLUR_T, PRECOND_ROWS_FC_FWD);
+    return blurT_grid_finish(P, w, accum, s);
+}
+
 // w (+)= A^T y on the FFT grid: the circular correlation of y placed at
-// (p-1, p-1), cropped to [0, N)^2; antireflective model: the reblur A' y, the
-// circular correlation of y's antireflective extension (m x m at the origin)
-// cropped to [0, n)^2 (the valid part of its convolution with the rotated PSF)
+// (p-1, p-1), cropped to [0, m)^2 (rectangular model) or folded by E^T (square
+// models); antireflective model: the reblur A' y, the circular correlation of
+// y's antireflective extension (m x m at the origin) cropped to [0, n)^2 (the
+// valid part of its convolution with the rotated PSF)
 int do_blurT_fft(mlba_plan_s* P, const float* y, float* w, int accum, hipStream_t s) {
     const int n = P->n, p = P->p, N = n + p - 1;
     if (P->bc == MLBA_BC_ANTIREFLECT) {
-        HIPCHK(launch_fc_rows_fwd(P->fc, y, n, P->c, 0, N, s, 1));
+        HIPCHK(launch_fc_rows_fwd(P->fc, y, n, P->c, 0, N, s, EXT_ANTIREFLECT));
         MARK(BLUR_T, FC_ROWS_FWD);
         HIPCHK(launch_fc_cols(P->fc, 1, 0, N, 0, nullptr, s, 0, n + (n & 1)));
         MARK(BLUR_T, FC_COLS);
@@ -271,11 +302,7 @@ int do_blurT_fft(mlba_plan_s* P, const float* y, float* w, int accum, hipStream_
     }
     HIPCHK(launch_fc_rows_fwd(P->fc, y, n, p - 1, p - 1, N, s));
     MARK(BLUR_T, FC_ROWS_FWD);
-    HIPCHK(launch_fc_cols(P->fc, 1, p - 1, N, 0, nullptr, s, 0, N + (N & 1)));
-    MARK(BLUR_T, FC_COLS);
-    HIPCHK(launch_fc_rows_inv(P->fc, 0, 0, N, w, nullptr, accum, nullptr, nullptr, s));
-    MARK(BLUR_T, FC_ROWS_INV);
-    return MLBA_OK;
+    return blurT_grid_finish(P, w, accum, s);
 }
 
 int do_blurT(mlba_plan_s* P, const float* y, float* w, hipStream_t s) {
@@ -841,7 +868,7 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
             P->ts = n + 16;
             ALLOC(P->spec, (size_t)(n / 2 + 1) * n);
             if (bc != MLBA_BC_RECT) ALLOC(P->lamc, (size_t)(n / 2 + 1) * n);
-            if (bc == MLBA_BC_PERIODIC) ALLOC(P->ghat, (size_t)(n / 2 + 1) * n);  // Algorithm 4: F g
+            if (bc == MLBA_BC_PERIODIC) ALLOC(P->ghat, (size_t)(n / 2 + 1) * n);  // the spectral residual: F g
             float2* T = nullptr;
             ALLOC(T, (size_t)(n / 2 + 1) * P->ts);
             P->swork = T;
@@ -908,7 +935,6 @@ int fft_grid_size(int N) {
 // and computes the PSF spectrum on that grid.
 int ensure_fftconv(mlba_plan_s* P, hipStream_t s) {
     if (P->fc.H) return MLBA_OK;
-    if (P->bc != MLBA_BC_RECT && P->bc != MLBA_BC_ANTIREFLECT) return MLBA_EUNSUPPORTED;
     const int M = fft_grid_size(P->n + P->p - 1);  // the (extended) unknown, m x m
     if (M == 0) return MLBA_EUNSUPPORTED;
     if (fftconv_partials_count(M, P->n) > P->partials_cap) return MLBA_EUNSUPPORTED;
@@ -1185,12 +1211,14 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
         mlba_plan_s* P;
         ~ProfGuard() { P->prof_cur = -1; }
     } prof_guard{P};
-    const bool fused = !alg4 && !alg2 && fused_fft_path(P);
-    // Algorithm 4 with the periodic model and the BCCB matrix: A = C, so the
-    // residual is formed in the spectrum (F g computed once here) and an
-    // iteration is the synthesis and one 2-D transform pair
-    const bool fold4 = alg4 && P->bc == MLBA_BC_PERIODIC && P->precond == MLBA_PRECOND_BCCB && P->ghat &&
-                       (P->n / 2 + 1) <= P->partials_cap;
+    // The periodic model with the BCCB matrix: A = C, so A^T P_alpha r is
+    // Algorithm 4's direction C^T (C C^T + alpha I)^{-1} r; for Algorithm 4,
+    // and for MLBA with the blur evaluated by FFTs, the residual is formed in
+    // the spectrum (F g computed once here) and an iteration is the synthesis
+    // and one 2-D transform pair
+    const bool fold4 = (alg4 || (!alg2 && P->blur_fft)) && P->bc == MLBA_BC_PERIODIC &&
+                       P->precond == MLBA_PRECOND_BCCB && P->ghat && (P->n / 2 + 1) <= P->partials_cap;
+    const bool fused = !fold4 && !alg4 && !alg2 && fused_fft_path(P);
     if (fold4 && iters > 0) {
         HIPCHK(launch_fft_rows_r2c(g, P->n, (float2*)P->swork, P->ts, P->fd, P->tw, s));
         HIPCHK(launch_fft_cols_complex((const float2*)P->swork, P->n, P->ts, P->ghat, P->fd, P->tw, s));
@@ -1243,7 +1271,7 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
             // sums the residual partials
             const int n = P->n, p = P->p, m = n + p - 1;
             float* Tr = (float*)P->swork;
-            HIPCHK(launch_fc_rows_fwd(P->fc, P->u, n, P->c, 0, m, s, 1));
+            HIPCHK(launch_fc_rows_fwd(P->fc, P->u, n, P->c, 0, m, s, EXT_ANTIREFLECT));
             MARK(BLUR, FC_ROWS_FWD);
             HIPCHK(launch_fc_cols(P->fc, 0, 0, m, 0, nullptr, s, p - 1, p - 1 + n + (n & 1)));
             MARK(BLUR, FC_COLS);

@@ -1,11 +1,15 @@
-"""The rectangular model's blur A and its transpose computed by FFTs of an
-M x M grid (section 2.1), against the FP64 oracle; and the restoration with
-it.  Bars: 1e-5 (relative, L2) per operator, 1e-4 on restored images."""
+"""The blur A and its transpose computed by FFTs of an M x M grid (section
+2.1): the rectangular model's unknown, or a square model's image with its pad
+of Table 1 (zero, reflective, periodic) placed on the grid and the transpose
+folded back by E^T; against the FP64 oracle, and the restoration with it.
+Bars: 1e-5 (relative, L2) and 1e-4 (element by element, relative to the
+largest value) per operator, 1e-4 on restored images."""
 import numpy as np
 import pytest
 
 import synth
 from oracle import blur as ob
+from oracle import alg4 as oa
 from oracle import mlba as omlba
 from tests._util import announce, cuda, host, max_err, rel_err
 
@@ -48,14 +52,43 @@ def test_fft_blur_and_transpose(mlba, n, p):
     assert rel_err(res, gobs - ref_A) < 1e-5
 
 
-def test_fft_blur_needs_rect_and_fits(mlba):
+# square models: (n, p) with p = 1 (no pad), odd n, pads wider than a row
+# pair, the largest PSF, the bench size
+SQUARE = [(8, 1), (64, 9), (97, 5), (100, 17), (256, 49), (2048, 31)]
+
+
+@pytest.mark.parametrize("bc", ["REFLECT", "PERIODIC", "ZERO"])
+@pytest.mark.parametrize("n,p", SQUARE)
+def test_fft_blur_square_models(mlba, bc, n, p):
+    announce(f"FFT blur {bc} n={n} p={p}")
+    g = synth.rng(9100 + n + p)
+    H = g.random((p, p)) + 0.05
+    H /= H.sum()
+    u = g.standard_normal((n, n))
+    y = g.standard_normal((n, n))
+    gobs = g.standard_normal((n, n))
+    obc = getattr(ob, bc)
+    with mlba.Plan(n, p, getattr(mlba, bc), mlba.NONE, 1, cuda(H)) as plan:
+        plan.set_blur(mlba.BLUR_FFT)
+        Au = host(plan.apply_A(cuda(u)))
+        Aty = host(plan.apply_At(cuda(y)))
+        res = host(plan.residual(cuda(gobs), cuda(u)))
+        plan.set_blur(mlba.BLUR_DIRECT)
+        Aty_d = host(plan.apply_At(cuda(y)))
+    ref_A = ob.blur(u, H, obc)
+    ref_At = ob.blurT(y, H, obc)
+    print(f"  A {rel_err(Au, ref_A):.2e} max {max_err(Au, ref_A):.2e}  A^T {rel_err(Aty, ref_At):.2e} "
+          f"max {max_err(Aty, ref_At):.2e}", flush=True)
+    assert rel_err(Au, ref_A) < 1e-5 and max_err(Au, ref_A) < 1e-4
+    assert rel_err(Aty, ref_At) < 1e-5 and max_err(Aty, ref_At) < 1e-4
+    assert rel_err(res, gobs - ref_A) < 1e-5
+    assert rel_err(Aty, Aty_d) < 1e-5
+
+
+def test_fft_blur_fits(mlba):
     from paper_1504_07234_amd import _lib
     announce("FFT blur argument checks")
     H = cuda(synth.gaussian_psf(5, 1.0))
-    with mlba.Plan(64, 5, mlba.REFLECT, mlba.NONE, 1, H) as plan:
-        with pytest.raises(_lib.MLBAError) as e:
-            plan.set_blur(mlba.BLUR_FFT)
-        assert e.value.status == _lib.EUNSUPPORTED
     with mlba.Plan(3100, 5, mlba.RECT, mlba.NONE, 1, H) as plan:  # M would exceed 3072
         with pytest.raises(_lib.MLBAError) as e:
             plan.set_blur(mlba.BLUR_FFT)
@@ -158,3 +191,59 @@ def test_profile_every(mlba):
         kern = plan.profile_kernels()
     assert rec == 4  # iterations 0, 3, 6, 9
     assert kern["conv_blur"][1] == 4 and kern["conv_blur"][0] > 0.0
+
+
+@pytest.mark.parametrize("bc,pc,method,implicit", [
+    ("REFLECT", 0, "MLBA", True),    # BCCB: residual and P row passes fused
+    ("REFLECT", 1, "MLBA", False),   # DCT (Algorithm 3): the three grid passes
+    ("ZERO", 0, "MLBA", False),
+    ("ZERO", 1, "MLBA", True),
+    ("PERIODIC", 0, "MLBA", True),   # A = C: the residual formed in the spectrum
+    ("PERIODIC", 0, "MLBA", False),
+    ("PERIODIC", 1, "MLBA", True),
+    ("REFLECT", 1, "ALG4", True),    # Algorithm 4's residual on the grid
+    ("ZERO", 0, "ALG4", False),
+])
+def test_restore_square_models_fft_blur(mlba, bc, pc, method, implicit):
+    """MLBA (eq. MLBA2) and Algorithm 4 on the square models with the FFT
+    blur, against the oracle; the launches show which path ran."""
+    n, p, L, iters = 96, 9, 2, 25
+    announce(f"restore {bc} precond={pc} {method} FFT blur implicit={implicit}")
+    gen = synth.rng(4600 + n + pc + len(bc))
+    H = synth.gaussian_psf(p, 1.5)
+    obc = getattr(ob, bc)
+    truth = synth.shapes_image(n + p - 1, gen, n_rect=6, n_disk=3)
+    g = synth.add_noise(ob.blur(truth, H, ob.RECT), synth.white_noise((n, n), gen), 0.01)
+    alphas = np.full(iters, 0.05)
+    mu = np.linspace(1e-3, 2e-3, 8 * L + 1)
+    alg4 = method == "ALG4"
+    with mlba.Plan(n, p, getattr(mlba, bc), pc, L, cuda(H)) as plan:
+        plan.set_blur(mlba.BLUR_FFT)
+        plan.profile_begin(iters)
+        if alg4:
+            f, info = plan.restore(cuda(g), alpha_table=alphas, mu=mu, delta=1.0, iters=iters, method=mlba.ALG4,
+                                   implicit=implicit)
+        else:
+            deltas = omlba.delta_table(H, n, obc, pc, alphas, 0.0, iters + 1)
+            f, info = plan.restore(cuda(g), alpha_table=alphas, mu=mu, delta_table=deltas, iters=iters,
+                                   implicit=implicit)
+        plan.profile_end()
+        kern = plan.profile_kernels()
+        f = host(f)
+    if alg4:
+        ref = oa.alg4(g, H, obc, pc, L, alphas, np.ones(iters + 1), mu, iters)
+    else:
+        ref = omlba.mlba(g, H, obc, pc, L, alphas, deltas, mu, iters)
+    print(f"  image {rel_err(f, ref['f']):.2e} max {max_err(f, ref['f']):.2e} "
+          f"rnorm {rel_err(info.rnorm, ref['rnorm']):.2e}; {sorted(kern)}", flush=True)
+    assert rel_err(f, ref["f"]) < 1e-4 and max_err(f, ref["f"]) < 1e-4
+    assert rel_err(info.rnorm, ref["rnorm"]) < 1e-4
+    spectral = bc == "PERIODIC" and pc == 0
+    fused = pc == 0 and not alg4 and not spectral
+    assert ("fc_cols" in kern) == (not spectral)
+    if spectral:  # one 2-D transform pair per iteration
+        assert kern["fft_rows_fwd"][1] == kern["fft_cols"][1] == kern["fft_rows_inv"][1] == iters
+    assert kern.get("fc_residual_precond_rows", (0, 0))[1] == (iters if fused else 0)
+    assert kern.get("precond_rows_fc_fwd", (0, 0))[1] == (iters if fused else 0)
+    if not spectral:
+        assert kern["fc_cols"][1] == (1 if alg4 else 2) * iters
