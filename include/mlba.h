@@ -199,15 +199,18 @@ int mlba_plan_create(mlba_plan_t* plan, int n, int p, int bc, int precond, int l
 /* Replace the PSF (same p) and recompute the spectrum. psf: device p x p. */
 int mlba_plan_set_psf(mlba_plan_t plan, const float* psf, hipStream_t stream);
 int mlba_plan_destroy(mlba_plan_t plan);
-/* How the blur A and its transpose (rectangular model) or its reblur A'
- * (antireflective model) are computed:
+/* How the blur A and its transpose (or, antireflective model, its reblur
+ * A') are computed:
  * MLBA_BLUR_DIRECT (default): LDS-tiled direct convolution, p^2 taps per
  * output; MLBA_BLUR_FFT: circular convolution on an M x M grid, M >= m =
- * n + p - 1, M = 2^a 3^b (section 2.1's FFT evaluation; the antireflective
- * model places the m x m antireflective extension on the grid), three
- * transform passes per product.  mlba_plan_set_blur: MLBA_BLUR_FFT allocates
- * the grid's workspace and PSF spectrum on first use (synchronous) and returns
- * MLBA_EUNSUPPORTED for the reflective, periodic and zero models or when M
+ * n + p - 1, M = 2^a 3^b (section 2.1's FFT evaluation), three transform
+ * passes per product.  The square models place the n x n image with its pad
+ * (Table 1, section 2.2) on the grid, m x m; A^T folds the correlation back
+ * by the pad's transpose.  With the periodic model and MLBA_PRECOND_BCCB,
+ * MLBA_BLUR_FFT also selects for eq. (MLBA2) the spectral residual of
+ * Algorithm 4 (A = C there): one 2-D transform pair per iteration.
+ * mlba_plan_set_blur: MLBA_BLUR_FFT allocates the grid's workspace and PSF
+ * spectrum on first use (synchronous) and returns MLBA_EUNSUPPORTED when M
  * would exceed 3072.  mlba_plan_autotune:
  * times both on the plan's own scratch buffers (`reps` calls each, HIP events,
  * synchronous), keeps the faster pair, writes the mean ms per call to ms_out
