@@ -91,6 +91,34 @@ __device__ __forceinline__ void fft_cols_body(float2* __restrict__ T, int n_, in
     const int k0 = blk * CC;
     const int cc = min(CC, half - k0);
     const size_t base = (size_t)k0 * n;  // dense [n/2+1][n] spectrum
+    if constexpr (NT > 0 && fixed_conv_ok<(NT > 0 ? NT : 1)>()) {
+        if (mode == 0) {  // the filter between the transforms, in registers
+            constexpr int SL = fixed_conv_slots<NT>();
+            FixedTw<NT> twf;
+            FixedTw<NT, true> twi;
+            fixed_tw_load<NT>(tw, twf.w);
+            fixed_tw_load<NT, 0, true>(tw, twi.w);
+            float sr[SL];
+#pragma unroll
+            for (int r = 0; r < SL; ++r) sr[r] = spec[base + threadIdx.x + r * kBlock];
+            if (alpha_dev) alpha = (float)*alpha_dev;
+            float2* col = T + (size_t)k0 * ts;
+            fixed_conv<NT>(
+                buf, tw, twf.w, twi.w, [&](int y) { return col[y]; },
+                [&](int r, int y, float2 v) {
+                    v = cscale(v, inv / (sr[r] + alpha));
+                    if (lamc) v = cmul(v, cconj(lamc[base + y]));
+                    if (sstore) sstore[base + y] = v;  // reverse sweep of unrolled iterations
+                    if (eacc) {
+                        const float2 f = sfwd[base + y];
+                        eacc[base + y] += fmaf(v.x, f.x, v.y * f.y);
+                    }
+                    return v;
+                },
+                [&](int y, float2 v) { col[y] = v; }, false);
+            return;
+        }
+    }
     FixedTw<(NT > 0 ? NT : 1)> twp;
     if constexpr (NT > 0) fixed_tw_load<NT>(tw, twp.w);
     strided_copy<NT, float2>(
@@ -506,6 +534,28 @@ __global__ __launch_bounds__(kBlock) void fft_cols_residual_kernel(float2* __res
     const int k0 = blockIdx.x * CC;
     const int cc = min(CC, half - k0);
     const size_t base = (size_t)k0 * n;  // dense [n/2+1][n] spectra
+    const double to_r = 1.0 / ((double)n * (double)n);
+    if constexpr (NT > 0 && fixed_conv_ok<(NT > 0 ? NT : 1)>()) {  // R and the filter in registers
+        FixedTw<NT> twf;
+        FixedTw<NT, true> twi;
+        fixed_tw_load<NT>(tw, twf.w);
+        if (!store_r) fixed_tw_load<NT, 0, true>(tw, twi.w);
+        const double wgt = (k0 == 0 || 2 * k0 == n) ? to_r : 2.0 * to_r;
+        double ss = 0.0;
+        float2* col = T + (size_t)k0 * ts;
+        fixed_conv<NT>(
+            buf, tw, twf.w, twi.w, [&](int y) { return col[y]; },
+            [&](int, int y, float2 v) {
+                const float2 L = lamc[base + y];
+                const float2 R = csub(ghat[base + y], cmul(L, v));
+                ss += wgt * ((double)R.x * (double)R.x + (double)R.y * (double)R.y);
+                return store_r ? R : cmul(cscale(R, inv / (spec[base + y] + alpha)), cconj(L));
+            },
+            [&](int y, float2 v) { col[y] = v; }, store_r != 0);
+        const double t = block_sum(ss, red);
+        if (threadIdx.x == 0) part[blockIdx.x] = t;
+        return;
+    }
     FixedTw<(NT > 0 ? NT : 1)> twp;
     if constexpr (NT > 0) fixed_tw_load<NT>(tw, twp.w);
     strided_copy<NT, float2>(
@@ -517,7 +567,6 @@ __global__ __launch_bounds__(kBlock) void fft_cols_residual_kernel(float2* __res
         [&](int idx, float2 v) { buf[lds_slot(idx)] = v; });
     __syncthreads();
     lds_fft_any<-1, NT>(buf, fd, cc, seq_shift, tw, NT > 0 ? twp.w : nullptr);
-    const double to_r = 1.0 / ((double)n * (double)n);
     double ss = 0.0;
     for (int idx = threadIdx.x; idx < cc * n; idx += kBlock) {
         const int kx = k0 + idx / n;

@@ -470,33 +470,50 @@ __host__ __device__ constexpr FixedPlan fixed_plan(int n) {
     return p;
 }
 
+// The same radices in reverse order (the plan of the inverse transform in
+// fixed_conv: its first butterflies take the forward transform's last
+// outputs from registers).
+__host__ __device__ constexpr FixedPlan fixed_plan(int n, bool rev) {
+    const FixedPlan f = fixed_plan(n);
+    if (!rev) return f;
+    FixedPlan p{};
+    p.nst = f.nst;
+    int ns = 1;
+    for (int s = 0; s < p.nst; ++s) {
+        p.radix[s] = f.radix[f.nst - 1 - s];
+        p.ns[s] = ns;
+        ns *= p.radix[s];
+    }
+    return p;
+}
+
 // Table entries of every stage of the fixed plan of length N, per thread:
 // stage S (NS > 1) holds MAXB x tw_table_loads(R) of them from offset
 // fixed_tw_offset(N, S).
-__host__ __device__ constexpr int fixed_tw_offset(int N, int S) {
-    const FixedPlan P = fixed_plan(N);
+__host__ __device__ constexpr int fixed_tw_offset(int N, int S, bool rev = false) {
+    const FixedPlan P = fixed_plan(N, rev);
     int off = 0;
     for (int s = 0; s < S && s < P.nst; ++s)
         if (P.ns[s] > 1) off += ((N / P.radix[s] + kBlock - 1) / kBlock) * tw_table_loads(P.radix[s]);
     return off;
 }
 
-template <int N>
+template <int N, bool REV = false>
 struct FixedTw {
-    static constexpr int kCount = fixed_tw_offset(N, 24);
+    static constexpr int kCount = fixed_tw_offset(N, 24, REV);
     float2 w[kCount > 0 ? kCount : 1];
 };
 
 // Loads the table entries of every stage (one batch, in flight with the
 // pass's data loads); both directions use them (DIR +1 conjugates).
-template <int N, int S = 0>
+template <int N, int S = 0, bool REV = false>
 __device__ __forceinline__ void fixed_tw_load(const float2* __restrict__ tw, float2* out, int tid = threadIdx.x) {
-    constexpr FixedPlan P = fixed_plan(N);
+    constexpr FixedPlan P = fixed_plan(N, REV);
     if constexpr (S < P.nst) {
         constexpr int R = P.radix[S], NS = P.ns[S];
         if constexpr (NS > 1) {
             constexpr int nb = N / R, MAXB = (nb + kBlock - 1) / kBlock, T = tw_table_loads(R);
-            constexpr int step = N / (NS * R), off = fixed_tw_offset(N, S);
+            constexpr int step = N / (NS * R), off = fixed_tw_offset(N, S, REV);
 #pragma unroll
             for (int i = 0; i < MAXB; ++i) {
                 const int j = tid + i * kBlock;
@@ -507,7 +524,7 @@ __device__ __forceinline__ void fixed_tw_load(const float2* __restrict__ tw, flo
                 }
             }
         }
-        fixed_tw_load<N, S + 1>(tw, out, tid);
+        fixed_tw_load<N, S + 1, REV>(tw, out, tid);
     }
 }
 
@@ -566,14 +583,117 @@ __device__ __forceinline__ void stockham_stage_fixed(float2* buf, const float2* 
     __syncthreads();
 }
 
-template <int DIR, int N, int S = 0>
+// Stages [S, SEND) of the fixed plan (SEND < 0: to the end), LDS to LDS.
+template <int DIR, int N, int S = 0, bool REV = false, int SEND = -1>
 __device__ __forceinline__ void lds_fft_fixed(float2* buf, const float2* __restrict__ tw, const float2* pre,
                                               int tid = threadIdx.x) {
-    constexpr FixedPlan P = fixed_plan(N);
-    if constexpr (S < P.nst) {
-        constexpr int off = fixed_tw_offset(N, S);
+    constexpr FixedPlan P = fixed_plan(N, REV);
+    if constexpr (S < (SEND < 0 ? P.nst : SEND)) {
+        constexpr int off = fixed_tw_offset(N, S, REV);
         stockham_stage_fixed<P.radix[S], DIR, N, P.ns[S]>(buf, tw, pre ? pre + off : nullptr, tid);
-        lds_fft_fixed<DIR, N, S + 1>(buf, tw, pre, tid);
+        lds_fft_fixed<DIR, N, S + 1, REV, SEND>(buf, tw, pre, tid);
+    }
+}
+
+// ---- transforms whose first and last stages skip LDS ----------------------
+// A plan's first stage (NS = 1) reads elements j + r nb (nb = N / R) and
+// writes j R + r; its last stage (NS = nb) reads j + r nb and writes
+// j + r nb.  So the first stage can take its inputs straight from registers
+// (loaded from global memory), and the last stage can leave its outputs in
+// registers: thread j then holds the elements j + r nb, r < R.
+
+// The first stage from registers for butterfly j (< nb): v[r] holds
+// element j + r nb; DFT, then the write to LDS (j R + r).
+template <int R, int DIR, int N>
+__device__ __forceinline__ void stage_first_from_regs(float2 (&v)[R], float2* buf, int j) {
+    dft<R, DIR>(v);
+    const int sb = lds_slot(j * R);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if constexpr (R % 8 == 0) buf[sb + r + r / 8] = v[r];
+        else buf[lds_slot(j * R + r)] = v[r];
+    }
+}
+
+// The last stage into registers for butterfly j (< nb): v[r] becomes
+// output element j + r nb.  raw: the butterfly's table entries
+// (fixed_tw_load), or null to read the table tw.
+template <int R, int DIR, int N>
+__device__ __forceinline__ void stage_last_to_regs(const float2* buf, const float2* __restrict__ tw,
+                                                   const float2* raw, float2 (&v)[R], int j) {
+    constexpr int nb = N / R;
+    constexpr bool rd_off = nb % 8 == 0;
+    float2 w[R];
+    if (j > 0) {  // twiddles W^(j r) of the length-N transform
+        if (raw) twiddle_powers_raw<R, DIR>(raw, w);
+        else twiddle_powers<R, DIR>(tw, j, N, w);
+    }
+    const int sb = lds_slot(j);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        float2 x = rd_off ? buf[sb + r * (nb + nb / 8)] : buf[lds_slot(j + r * nb)];
+        if (r > 0 && j > 0) x = cmul(x, w[r]);
+        v[r] = x;
+    }
+    dft<R, DIR>(v);
+}
+
+// fixed_conv applies when the forward plan has two stages or more and its
+// last stage has one butterfly per thread (N / R_last == kBlock), so that
+// output element y = tid + r kBlock sits in slot r of every thread.
+template <int N>
+__host__ __device__ constexpr bool fixed_conv_ok() {
+    constexpr FixedPlan P = fixed_plan(N);
+    return P.nst >= 2 && N / P.radix[P.nst - 1] == kBlock;
+}
+template <int N>
+__host__ __device__ constexpr int fixed_conv_slots() {
+    return fixed_plan(N).radix[fixed_plan(N).nst - 1];
+}
+
+// Forward transform (DIR -1) of a length-N sequence read by load(y), a
+// pointwise op on its spectrum in registers (op(r, y, v) returns the new
+// value of element y = tid + r kBlock), and unless `forward_only` the inverse
+// transform (DIR +1, the forward radices in reverse order) with each result
+// passed to store(y, v); forward_only stores the spectrum after op.  LDS holds
+// only the middle stages.  twf / twi: fixed_tw_load of the forward / reversed
+// plan.  Every thread of the workgroup calls this (barriers inside).
+template <int N, class Load, class Op, class Store>
+__device__ __forceinline__ void fixed_conv(float2* buf, const float2* __restrict__ tw, const float2* twf,
+                                           const float2* twi, Load load, Op op, Store store, bool forward_only,
+                                           int tid = threadIdx.x) {
+    static_assert(fixed_conv_ok<N>(), "fixed_conv: plan shape");
+    constexpr FixedPlan F = fixed_plan(N), B = fixed_plan(N, true);
+    constexpr int R0 = F.radix[0], RL = F.radix[F.nst - 1];
+    constexpr int nb0 = N / R0;
+    constexpr int offF = fixed_tw_offset(N, F.nst - 1), offB = fixed_tw_offset(N, B.nst - 1, true);
+    static_assert(nb0 <= kBlock, "fixed_conv: one first-stage butterfly per thread");
+    if (nb0 == kBlock || tid < nb0) {
+        float2 v[R0];
+#pragma unroll
+        for (int r = 0; r < R0; ++r) v[r] = load(tid + r * nb0);
+        stage_first_from_regs<R0, -1, N>(v, buf, tid);
+    }
+    __syncthreads();
+    lds_fft_fixed<-1, N, 1, false, F.nst - 1>(buf, tw, twf, tid);
+    float2 u[RL];
+    stage_last_to_regs<RL, -1, N>(buf, tw, twf ? twf + offF : nullptr, u, tid);
+#pragma unroll
+    for (int r = 0; r < RL; ++r) u[r] = op(r, tid + r * kBlock, u[r]);
+    if (forward_only) {
+#pragma unroll
+        for (int r = 0; r < RL; ++r) store(tid + r * kBlock, u[r]);
+        return;
+    }
+    __syncthreads();  // the last forward stage's reads before the inverse's writes
+    stage_first_from_regs<RL, 1, N>(u, buf, tid);
+    __syncthreads();
+    lds_fft_fixed<1, N, 1, true, B.nst - 1>(buf, tw, twi, tid);
+    if (nb0 == kBlock || tid < nb0) {
+        float2 v[R0];
+        stage_last_to_regs<R0, 1, N>(buf, tw, twi ? twi + offB : nullptr, v, tid);
+#pragma unroll
+        for (int r = 0; r < R0; ++r) store(tid + r * nb0, v[r]);
     }
 }
 

@@ -154,6 +154,31 @@ __global__ __launch_bounds__(kBlock) void fc_cols_kernel(float2* __restrict__ T,
     const int k0 = blockIdx.x * CC;
     const int cc = min(CC, half - k0);
     const size_t base = (size_t)k0 * M;
+    if constexpr (NT > 0 && fixed_conv_ok<(NT > 0 ? NT : 1)>()) {
+        if (mode == 0 && fold < 0) {  // the product with the PSF spectrum in registers
+            constexpr int SL = fixed_conv_slots<NT>();
+            FixedTw<NT> twf;
+            FixedTw<NT, true> twi;
+            fixed_tw_load<NT>(tw, twf.w);
+            fixed_tw_load<NT, 0, true>(tw, twi.w);
+            float2 h[SL];
+#pragma unroll
+            for (int r = 0; r < SL; ++r) {
+                const float2 hv = Hs[base + threadIdx.x + r * kBlock];
+                h[r] = conj_h ? cconj(hv) : hv;
+            }
+            float2* col = T + (size_t)k0 * ts;
+            fixed_conv<NT>(
+                buf, tw, twf.w, twi.w,
+                [&](int y) { return (y >= y_lo && y < y_hi) ? col[y] : make_float2(0.0f, 0.0f); },
+                [&](int r, int, float2 v) { return cscale(cmul(v, h[r]), inv); },
+                [&](int y, float2 v) {
+                    if (y >= o_lo && y < o_hi) col[y] = v;
+                },
+                false);
+            return;
+        }
+    }
     FixedTw<(NT > 0 ? NT : 1)> twp;
     if constexpr (NT > 0) fixed_tw_load<NT>(tw, twp.w);
     strided_copy<NT, float2>(
