@@ -48,8 +48,8 @@ PROFILE_EVERY = 4              # kernel events on every 4th timed iteration (the
 TRAFFIC = {
     # 2078^2, 3 levels: the three shrink-synthesis launches of one iteration (d = 4, 2, 1)
     ("shrink_synthesis", "fft-implicit"): {
-        "fetch_kib": 43450.9, "write_kib": 50610.6, "fetch_scale": 2.0, "write_scale": 1.0, "launches": 3,
-        "sources_sha256": "a58c1e0e3decd0bd53476559c61115c484f256b50387a2eb467a4cbbc7bb0be1"},
+        "fetch_kib": 43445.9, "write_kib": 50610.5, "fetch_scale": 2.0, "write_scale": 1.0, "launches": 3,
+        "sources_sha256": "665fbf6605b9a5faa8a04d7e0780ec5e11622f280cde6b5f55668b05c3c17a88"},
     # the direct A^T accumulating into omega (p = 31), one launch per iteration
     ("conv_blur_t", "direct-implicit"): {
         "fetch_kib": 17582.1, "write_kib": 16878.0, "fetch_scale": 2.0, "write_scale": 1.0, "launches": 1,

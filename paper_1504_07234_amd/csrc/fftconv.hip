@@ -133,6 +133,13 @@ __device__ __forceinline__ float2 fold_sum(int k, int n, int c, int fold, F v) {
     return a;
 }
 
+// The factor of the column pass's product: H (conj_h 0), conj(H) (1) or
+// |H|^2 (2: A A^T of the rectangular model in one transform pair).
+__device__ __forceinline__ float2 spectrum_factor(float2 h, int conj_h) {
+    if (conj_h == 2) return make_float2(h.x * h.x + h.y * h.y, 0.0f);
+    return conj_h ? cconj(h) : h;
+}
+
 // Columns pass over CC half-spectrum rows per workgroup; rows outside
 // [y_lo, y_hi) of the input are zero.  mode 0: forward FFT, times Hs (or
 // conj(Hs)) * inv, inverse FFT, written back for the rows [o_lo, o_hi) that the
@@ -165,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void fc_cols_kernel(float2* __restrict__ T,
 #pragma unroll
             for (int r = 0; r < SL; ++r) {
                 const float2 hv = Hs[base + threadIdx.x + r * kBlock];
-                h[r] = conj_h ? cconj(hv) : hv;
+                h[r] = spectrum_factor(hv, conj_h);
             }
             float2* col = T + (size_t)k0 * ts;
             fixed_conv<NT>(
@@ -213,14 +220,14 @@ __global__ __launch_bounds__(kBlock) void fc_cols_kernel(float2* __restrict__ T,
         for (int k = 0; k < HPER; ++k) {
             const int e = k * kBlock + (int)threadIdx.x;
             if (NT % kBlock == 0 || e < NT) {
-                const float2 h = conj_h ? cconj(hreg[k]) : hreg[k];
+                const float2 h = spectrum_factor(hreg[k], conj_h);
                 buf[lds_slot(e)] = cscale(cmul(buf[lds_slot(e)], h), inv);
             }
         }
     } else {
         for (int idx = threadIdx.x; idx < cc * M; idx += kBlock) {
             float2 h = Hs[base + idx];
-            if (conj_h) h = cconj(h);
+            h = spectrum_factor(h, conj_h);
             buf[lds_slot(idx)] = cscale(cmul(buf[lds_slot(idx)], h), inv);
         }
     }
@@ -249,14 +256,16 @@ __global__ __launch_bounds__(kBlock) void fc_cols_kernel(float2* __restrict__ T,
 // g ? g - v (squared-norm partial per workgroup) : (accum ? dst + v : v).
 // With fold >= 0 (ox = 0) the value at x is instead the sum over the
 // preimages of x under the square model's extension (E^T along the rows, pad
-// fcn).
+// fcn).  axd (instead of g): dst = v + axa axd with the partials of
+// sum axd dst (the PCG product (A A^T + alpha I) d and d . q of Algorithm 2).
 template <int NT>
 __global__ __launch_bounds__(kBlock) void fc_rows_inv_kernel(const float2* __restrict__ T, int M_, int ts,
                                                              FftDesc fd, const float2* __restrict__ tw, int G_,
                                                              int seq_shift, int pair0, int pair_end, int oy, int ox,
                                                              int D, float* __restrict__ dst,
                                                              const float* __restrict__ g, int accum,
-                                                             double* __restrict__ partials, int fold, int fcn) {
+                                                             double* __restrict__ partials, int fold, int fcn,
+                                                             const float* __restrict__ axd, float axa) {
     extern __shared__ float2 buf[];
     __shared__ double red[kBlock / 64];
     const int M = NT > 0 ? NT : M_;
@@ -292,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void fc_rows_inv_kernel(const float2* __res
     constexpr int XPER = NT > 0 ? (NT + kBlock - 1) / kBlock : 1;
     float2 pre[XPER];
     if constexpr (NT > 0) {
-        const float* opnd = g ? g : (accum ? dst : nullptr);
+        const float* opnd = g ? g : (axd ? axd : (accum ? dst : nullptr));
 #pragma unroll
         for (int k = 0; k < XPER; ++k) {
             pre[k] = make_float2(0.0f, 0.0f);
@@ -325,6 +334,9 @@ __global__ __launch_bounds__(kBlock) void fc_rows_inv_kernel(const float2* __res
                 if (g) {
                     val = p - val;
                     ss += (double)val * (double)val;
+                } else if (axd) {
+                    val = fmaf(axa, p, val);
+                    ss += (double)p * (double)val;
                 } else if (accum) {
                     val = p + val;
                 }
@@ -348,6 +360,10 @@ __global__ __launch_bounds__(kBlock) void fc_rows_inv_kernel(const float2* __res
                 if (g) {
                     val = g[o] - val;
                     ss += (double)val * (double)val;
+                } else if (axd) {
+                    const float dv = axd[o];
+                    val = fmaf(axa, dv, val);
+                    ss += (double)dv * (double)val;
                 } else if (accum) {
                     val = dst[o] + val;
                 }
@@ -681,7 +697,8 @@ hipError_t launch_fc_cols(const FftConv& c, int conj_h, int y_lo, int y_hi, int 
 }
 
 hipError_t launch_fc_rows_inv(const FftConv& c, int oy, int ox, int D, float* dst, const float* g, int accum,
-                              double* partials, int* n_partials, hipStream_t s, int fold, int fcn) {
+                              double* partials, int* n_partials, hipStream_t s, int fold, int fcn, const float* axd,
+                              float axa) {
     if (fold >= 0 && ox != 0) return hipErrorInvalidValue;
     const int G = fc_pairs_per_block(c.M);
     const int p0 = oy / 2, p1 = (oy + D + 1) / 2;
@@ -690,15 +707,15 @@ hipError_t launch_fc_rows_inv(const FftConv& c, int oy, int ox, int D, float* ds
     if (c.M == kFixedM && G == 1)
         hipLaunchKernelGGL(fc_rows_inv_kernel<kFixedM>, dim3(blocks), dim3(kBlock), lds_bytes(c.M, c.M), s,
                            (const float2*)c.T, c.M, c.ts, c.fd, c.tw, 1, fc_seq_shift(1), p0, p1, oy, ox, D, dst, g,
-                           accum, partials, fold, fcn);
+                           accum, partials, fold, fcn, axd, axa);
     else if (c.M == kFixedM2 && G == 1)
         hipLaunchKernelGGL(fc_rows_inv_kernel<kFixedM2>, dim3(blocks), dim3(kBlock), lds_bytes(c.M, c.M), s,
                            (const float2*)c.T, c.M, c.ts, c.fd, c.tw, 1, fc_seq_shift(1), p0, p1, oy, ox, D, dst, g,
-                           accum, partials, fold, fcn);
+                           accum, partials, fold, fcn, axd, axa);
     else
         hipLaunchKernelGGL(fc_rows_inv_kernel<0>, dim3(blocks), dim3(kBlock), lds_bytes(G * c.M, c.M), s,
                            (const float2*)c.T, c.M, c.ts, c.fd, c.tw, G, fc_seq_shift(G), p0, p1, oy, ox, D, dst, g,
-                           accum, partials, fold, fcn);
+                           accum, partials, fold, fcn, axd, axa);
     return hipGetLastError();
 }
 

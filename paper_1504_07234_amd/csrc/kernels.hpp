@@ -208,13 +208,15 @@ struct PrecondRows {
 // g - . (partials) / plain / +=.  fold >= 0 (an Ext of a square model, fn x fn
 // image, pad fcn): the column pass stores E^T along the columns in rows
 // [0, fn + (fn & 1)) and the row pass (oy = ox = 0, D = fn) applies E^T along
-// the rows.
+// the rows.  conj_h: the column product with H (0), conj(H) (1) or |H|^2 (2).
+// axd: the row pass writes v + axa axd with the partials of sum axd (v + axa axd).
 hipError_t launch_fc_rows_fwd(const FftConv& c, const float* src, int S, int off, int y_lo, int y_hi, hipStream_t s,
                               int ext = EXT_ZERO);
 hipError_t launch_fc_cols(const FftConv& c, int conj_h, int y_lo, int y_hi, int mode, float2* cspec, hipStream_t s,
                           int o_lo, int o_hi, int fold = -1, int fn = 0, int fcn = 0);
 hipError_t launch_fc_rows_inv(const FftConv& c, int oy, int ox, int D, float* dst, const float* g, int accum,
-                              double* partials, int* n_partials, hipStream_t s, int fold = -1, int fcn = 0);
+                              double* partials, int* n_partials, hipStream_t s, int fold = -1, int fcn = 0,
+                              const float* axd = nullptr, float axa = 0.0f);
 // Row passes fused with the preconditioner's (n even, n <= 2048):
 // the residual rows r = g - A u (after launch_fc_cols of u) with their
 // squared-norm partials, then the preconditioner's forward row transform of r

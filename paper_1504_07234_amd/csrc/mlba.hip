@@ -534,6 +534,30 @@ int do_blurT_acc(mlba_plan_s* P, const float* y, float* omega, hipStream_t s) {
 // rho_j = res_j^T M^{-1} res_j (eq. bet).  The test runs on the device: all
 // max_steps steps are enqueued, and once the CG has stopped the updates of
 // t, res and d are skipped; *hist (device) receives beta_n.  No host round trip.
+// q = (A A^T + alpha I) d with the partials of d . q (np of them).  The
+// rectangular model on the FFT grid takes one transform pair with |H|^2:
+// the correlation A^T d of d placed at (p-1, p-1) vanishes outside
+// [0, m)^2, and M >= m, so the crop between A^T and A changes nothing.
+int do_gram(mlba_plan_s* P, const float* d, float* q, double alpha, int* np, hipStream_t s) {
+    const int n = P->n, p = P->p, m = n + p - 1;
+    const size_t nn = (size_t)n * n;
+    if (P->blur_fft && P->bc == MLBA_BC_RECT) {
+        HIPCHK(launch_fc_rows_fwd(P->fc, d, n, p - 1, p - 1, m, s));
+        MARK(BLUR_T, FC_ROWS_FWD);
+        HIPCHK(launch_fc_cols(P->fc, 2, p - 1, m, 0, nullptr, s, p - 1, p - 1 + n + (n & 1)));
+        MARK(BLUR, FC_COLS);
+        HIPCHK(launch_fc_rows_inv(P->fc, p - 1, p - 1, n, q, nullptr, 0, P->partials, np, s, -1, 0, d,
+                                  (float)alpha));
+        MARK(BLUR, FC_ROWS_INV);
+        return MLBA_OK;
+    }
+    STCHK(do_blurT(P, d, P->w, s));
+    STCHK(do_blur(P, P->w, nullptr, q, false, nullptr, s));
+    HIPCHK(launch_axpy(q, d, nn, (float)alpha, s));
+    HIPCHK(launch_dot_partials(d, q, nn, P->partials, np, s));
+    return MLBA_OK;
+}
+
 int do_pcg(mlba_plan_s* P, double alpha, int max_steps, double tol, int* hist, hipStream_t s) {
     const size_t nn = (size_t)P->n * P->n;
     float* t = P->pcg;
@@ -555,10 +579,7 @@ int do_pcg(mlba_plan_s* P, double alpha, int max_steps, double tol, int* hist, h
     for (int j = 1; j <= max_steps; ++j) {
         double* rc = rho[(j - 1) & 1];
         double* rn = rho[j & 1];
-        STCHK(do_blurT(P, d, P->w, s));                 // q = (A A^T + alpha I) d
-        STCHK(do_blur(P, P->w, nullptr, q, false, nullptr, s));
-        HIPCHK(launch_axpy(q, d, nn, (float)alpha, s));
-        HIPCHK(launch_dot_partials(d, q, nn, P->partials, &np, s));
+        STCHK(do_gram(P, d, q, alpha, &np, s));  // q = (A A^T + alpha I) d, d . q
         HIPCHK(launch_sum_partials(P->partials, np, pq, s));
         HIPCHK(launch_pcg_update(t, res, d, q, nn, rc, pq, act, s));
         STCHK(do_precond(P, res, zc, alpha, s));

@@ -8,7 +8,7 @@ import pytest
 import synth
 from oracle import alg2 as oa2
 from oracle import blur as ob
-from tests._util import announce, cuda, host, rel_err
+from tests._util import announce, cuda, host, max_err, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -52,10 +52,13 @@ def test_alg2_against_oracle(mlba, n, p, bc, pc, L, alpha, pcg, implicit):
 
 
 @pytest.mark.parametrize("implicit", [False, True])
-def test_alg2_with_the_fft_blur(mlba, implicit):
-    """The PCG's A A^T products and the final A^T evaluated on the FFT grid."""
-    n, p, L, alpha, pcg = 96, 9, 2, 0.05, (5, 0.05)
-    announce(f"Alg2 FFT blur n={n} p={p} implicit={implicit}")
+@pytest.mark.parametrize("n,p,pcg", [(96, 9, (5, 0.05)), (128, 17, (5, 1e-3))])
+def test_alg2_with_the_fft_blur(mlba, implicit, n, p, pcg):
+    """The PCG's products (A A^T + alpha I) d as one transform pair of the FFT
+    grid (|H|^2) with the epilogue + alpha d and d . q, and the final A^T;
+    the same beta_n as the oracle and the direct blur."""
+    L, alpha = 2, 0.05
+    announce(f"Alg2 FFT blur n={n} p={p} pcg={pcg} implicit={implicit}")
     gen = synth.rng(n + p + 11)
     truth = synth.shapes_image(n + p - 1, gen, n_rect=6, n_disk=3, n_bumps=3)
     H = synth.motion_psf(p, p - 2.0, gen.uniform(0, np.pi))
@@ -68,10 +71,16 @@ def test_alg2_with_the_fft_blur(mlba, implicit):
         f, info = plan.restore(cuda(g), alpha=alpha, mu=1e-3, delta=0.8, iters=iters, method=mlba.ALG2, pcg=pcg,
                                implicit=implicit)
         f = host(f)
-    print(f"  betas gpu {info.pcg_steps} oracle {ref['betas'].tolist()}; image {rel_err(f, ref['f']):.2e}",
-          flush=True)
-    assert info.pcg_steps == ref["betas"].tolist()
-    assert rel_err(f, ref["f"]) < 1e-4
+        plan.set_blur(mlba.BLUR_DIRECT)
+        f_d, info_d = plan.restore(cuda(g), alpha=alpha, mu=1e-3, delta=0.8, iters=iters, method=mlba.ALG2,
+                                   pcg=pcg, implicit=implicit)
+        f_d = host(f_d)
+    print(f"  betas gpu {info.pcg_steps} oracle {ref['betas'].tolist()}; image {rel_err(f, ref['f']):.2e} "
+          f"max {max_err(f, ref['f']):.2e}; vs direct {rel_err(f, f_d):.2e}", flush=True)
+    assert info.pcg_steps == ref["betas"].tolist() == info_d.pcg_steps
+    assert rel_err(f, ref["f"]) < 1e-4 and max_err(f, ref["f"]) < 1e-4
+    assert rel_err(info.rnorm, ref["rnorm"]) < 1e-4
+    assert rel_err(f, f_d) < 1e-4
 
 
 def test_alg2_exact_preconditioner_takes_one_step(mlba):
