@@ -49,3 +49,20 @@ def unknown_init(w):
         return w.truth
     c = (w.p - 1) // 2
     return w.truth[c:c + w.n, c:c + w.n]
+
+
+_CACHE = {}
+
+
+def cached(key, compute):
+    """compute() once per test process for `key` (several tests compare the GPU
+    against the same oracle run; the cached value is shared, never modified)."""
+    if key not in _CACHE:
+        _CACHE[key] = compute()
+    return _CACHE[key]
+
+
+def workload_key(w, iters):
+    """Everything that fixes a synthetic workload's oracle run: its name (the
+    seeded inputs), its schedule parameters and the iteration count."""
+    return (w.name, w.alpha_kind, w.alpha0, w.alpha_ratio, w.alpha_floor, w.delta, iters)

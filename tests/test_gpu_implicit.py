@@ -14,7 +14,7 @@ import synth
 from oracle import blur as oblur
 from oracle import framelet as ofr
 from oracle import mlba as omlba
-from tests._util import announce, cuda, host, max_err, observed, rel_err
+from tests._util import announce, cached, cuda, host, max_err, observed, rel_err, workload_key
 
 pytestmark = pytest.mark.gpu
 
@@ -53,9 +53,10 @@ def test_shrink_synthesis_operator(mlba, N, L):
 
 
 def _schedules(w, iters):
-    alphas = omlba.alpha_table(w.alpha_kind, w.alpha0, iters, w.alpha_ratio, w.alpha_floor)
-    deltas = omlba.delta_table(w.psf, w.n, w.bc, w.precond, alphas, w.delta, iters + 1)
-    return alphas, deltas
+    def compute():
+        alphas = omlba.alpha_table(w.alpha_kind, w.alpha0, iters, w.alpha_ratio, w.alpha_floor)
+        return alphas, omlba.delta_table(w.psf, w.n, w.bc, w.precond, alphas, w.delta, iters + 1)
+    return cached(("schedules",) + workload_key(w, iters), compute)
 
 
 @pytest.mark.parametrize("name", ["plain-fp64-72", "rect-bccb-512", "reflect-dct-512", "rect-bccb-geometric-512"])
@@ -71,7 +72,8 @@ def test_workloads_implicit(mlba, name):
         f, info = plan.restore(cuda(g), alpha_table=alphas, mu=w.mu, delta_table=deltas, iters=w.iters,
                                implicit=True)
         f = host(f)
-    ref = omlba.mlba(g, w.psf, w.bc, w.precond, w.levels, alphas, deltas, w.mu, w.iters)
+    ref = cached(("mlba",) + workload_key(w, w.iters),
+                 lambda: omlba.mlba(g, w.psf, w.bc, w.precond, w.levels, alphas, deltas, w.mu, w.iters))
     e, er = rel_err(f, ref["f"]), rel_err(info.rnorm, ref["rnorm"])
     print(f"  image rel err {e:.2e}, rnorm rel err {er:.2e}", flush=True)
     assert info.status == 0 and info.iters_done == w.iters

@@ -17,7 +17,7 @@ import pytest
 import synth
 from oracle import blur as oblur
 from oracle import mlba as omlba
-from tests._util import announce, cuda, host, max_err, observed, rel_err
+from tests._util import announce, cached, cuda, host, max_err, observed, rel_err, workload_key
 
 pytestmark = pytest.mark.gpu
 
@@ -38,9 +38,10 @@ def mlba():
 
 
 def _schedules(w, iters):
-    alphas = omlba.alpha_table(w.alpha_kind, w.alpha0, iters, w.alpha_ratio, w.alpha_floor)
-    deltas = omlba.delta_table(w.psf, w.n, w.bc, w.precond, alphas, w.delta, iters + 1)
-    return alphas, deltas
+    def compute():
+        alphas = omlba.alpha_table(w.alpha_kind, w.alpha0, iters, w.alpha_ratio, w.alpha_floor)
+        return alphas, omlba.delta_table(w.psf, w.n, w.bc, w.precond, alphas, w.delta, iters + 1)
+    return cached(("schedules",) + workload_key(w, iters), compute)
 
 
 def _run_both(mlba, w, iters, alphas, deltas, g):
@@ -59,7 +60,8 @@ def _run_library_schedules(mlba, w, iters, g, **kw):
                                alpha_floor=w.alpha_floor, mu=w.mu, delta=w.delta, iters=iters, **kw)
         f = host(f)
     alphas, deltas = _schedules(w, iters)
-    ref = omlba.mlba(g, w.psf, w.bc, w.precond, w.levels, alphas, deltas, w.mu, iters)
+    ref = cached(("mlba",) + workload_key(w, iters),
+                 lambda: omlba.mlba(g, w.psf, w.bc, w.precond, w.levels, alphas, deltas, w.mu, iters))
     return f, info, ref, alphas, deltas
 
 
