@@ -31,11 +31,11 @@ namespace mlba {
 
 // G row pairs per workgroup -> T[k][row], k = 0..n/2 (row stride ts complex).
 // NT > 0: n == NT and one row pair per workgroup (fixed-size transform).
-template <int NT = 0>
-__device__ __forceinline__ void fft_rows_r2c_body(const float* __restrict__ src, int n_,
-                                                  float2* __restrict__ T, int ts, const FftDesc& fd,
-                                                  const float2* __restrict__ tw, int G_, int seq_shift, int blk,
-                                                  float2* buf) {
+// src(i): the value at flat index i of the n x n input (read once per element).
+template <int NT, class Src>
+__device__ __forceinline__ void fft_rows_r2c_body_f(Src src, int n_, float2* __restrict__ T, int ts,
+                                                    const FftDesc& fd, const float2* __restrict__ tw, int G_,
+                                                    int seq_shift, int blk, float2* buf) {
     const int n = NT > 0 ? NT : n_;
     const int G = NT > 0 ? 1 : G_;
     const int row0 = blk * 2 * G;
@@ -47,7 +47,7 @@ __device__ __forceinline__ void fft_rows_r2c_body(const float* __restrict__ src,
             const int g = idx / n;
             const int x = idx - g * n;
             const size_t ra = (size_t)(row0 + 2 * g) * n;
-            return make_float2(src[ra + x], src[ra + n + x]);
+            return make_float2(src(ra + x), src(ra + n + x));
         },
         [&](int idx, float2 v) { buf[lds_slot(idx)] = v; });
     __syncthreads();
@@ -63,6 +63,13 @@ __device__ __forceinline__ void fft_rows_r2c_body(const float* __restrict__ src,
         const float2 Xb = make_float2(0.5f * D.y, -0.5f * D.x);  // D / (2i)
         *reinterpret_cast<float4*>(T + (size_t)k * ts + row0 + 2 * g) = make_float4(Xa.x, Xa.y, Xb.x, Xb.y);
     }
+}
+
+template <int NT = 0>
+__device__ __forceinline__ void fft_rows_r2c_body(const float* __restrict__ src, int n_, float2* __restrict__ T,
+                                                  int ts, const FftDesc& fd, const float2* __restrict__ tw, int G_,
+                                                  int seq_shift, int blk, float2* buf) {
+    fft_rows_r2c_body_f<NT>([&](size_t i) { return src[i]; }, n_, T, ts, fd, tw, G_, seq_shift, blk, buf);
 }
 
 // CC rows of T per workgroup, along the column index:
@@ -217,11 +224,11 @@ __device__ __forceinline__ void fft_cols_inverse_real_body(const float* __restri
     }
 }
 
-template <int NT = 0>
-__device__ __forceinline__ void fft_rows_c2r_body(const float2* __restrict__ T, int n_, int ts,
-                                                  float* __restrict__ dst, const FftDesc& fd,
-                                                  const float2* __restrict__ tw, int G_, int seq_shift, int blk,
-                                                  float2* buf, int accum = 0) {
+// put(i, v): the value v of flat index i of the n x n output.
+template <int NT, class Put>
+__device__ __forceinline__ void fft_rows_c2r_body_f(const float2* __restrict__ T, int n_, int ts, Put put,
+                                                    const FftDesc& fd, const float2* __restrict__ tw, int G_,
+                                                    int seq_shift, int blk, float2* buf) {
     const int n = NT > 0 ? NT : n_;
     const int G = NT > 0 ? 1 : G_;
     const int row0 = blk * 2 * G;
@@ -254,14 +261,20 @@ __device__ __forceinline__ void fft_rows_c2r_body(const float2* __restrict__ T, 
         const int x = idx - g * n;
         const size_t ra = (size_t)(row0 + 2 * g) * n;
         const float2 v = buf[lds_slot(idx)];
-        if (accum) {
-            dst[ra + x] += v.x;
-            dst[ra + n + x] += v.y;
-        } else {
-            dst[ra + x] = v.x;
-            dst[ra + n + x] = v.y;
-        }
+        put(ra + x, v.x);
+        put(ra + n + x, v.y);
     }
+}
+
+template <int NT = 0>
+__device__ __forceinline__ void fft_rows_c2r_body(const float2* __restrict__ T, int n_, int ts,
+                                                  float* __restrict__ dst, const FftDesc& fd,
+                                                  const float2* __restrict__ tw, int G_, int seq_shift, int blk,
+                                                  float2* buf, int accum = 0) {
+    if (accum)
+        fft_rows_c2r_body_f<NT>(T, n_, ts, [&](size_t i, float v) { dst[i] += v; }, fd, tw, G_, seq_shift, blk, buf);
+    else
+        fft_rows_c2r_body_f<NT>(T, n_, ts, [&](size_t i, float v) { dst[i] = v; }, fd, tw, G_, seq_shift, blk, buf);
 }
 
 // ---------------------------------------------------------------------------
@@ -583,6 +596,49 @@ __global__ __launch_bounds__(kBlock) void fft_cols_residual_kernel(float2* __res
         const int q = idx / n;
         T[(size_t)(k0 + q) * ts + (idx - q * n)] = buf[lds_slot(idx)];
     }
+}
+
+// ---- Algorithm 2: the PCG step's vector updates in P's row passes --------
+// (BCCB plan.)  The forward row pass applies the step's update t += a d,
+// res -= a q (a = rho / pq, device doubles; nothing once the CG has stopped)
+// to the rows it reads and transforms the new res; the inverse row pass
+// writes z = P res with the partial sums of res . z per workgroup.  The
+// arithmetic of every value is that of the separate update and dot kernels.
+template <int NT>
+__global__ __launch_bounds__(kBlock) void pcg_rows_r2c_kernel(int n, float2* __restrict__ T, int ts, FftDesc fd,
+                                                              const float2* __restrict__ tw, int G, int seq_shift,
+                                                              PcgVec v) {
+    extern __shared__ float2 buf[];
+    const bool on = *v.act != 0.0;
+    const float a = on ? (float)(*v.rho / *v.pq) : 0.0f;
+    fft_rows_r2c_body_f<NT>(
+        [&](size_t i) {
+            if (!on) return v.res[i];
+            v.t[i] = fmaf(a, v.d[i], v.t[i]);
+            const float r = fmaf(-a, v.q[i], v.res[i]);
+            v.res[i] = r;
+            return r;
+        },
+        n, T, ts, fd, tw, G, seq_shift, xcd_block(blockIdx.x, gridDim.x), buf);
+}
+
+template <int NT>
+__global__ __launch_bounds__(kBlock) void pcg_rows_c2r_kernel(const float2* __restrict__ T, int n, int ts,
+                                                              float* __restrict__ z, const float* __restrict__ res,
+                                                              FftDesc fd, const float2* __restrict__ tw, int G,
+                                                              int seq_shift, double* __restrict__ part) {
+    extern __shared__ float2 buf[];
+    __shared__ double red[kBlock / 64];
+    double acc = 0.0;
+    fft_rows_c2r_body_f<NT>(
+        T, n, ts,
+        [&](size_t i, float val) {
+            z[i] = val;
+            acc += (double)res[i] * (double)val;
+        },
+        fd, tw, G, seq_shift, xcd_block(blockIdx.x, gridDim.x), buf);
+    const double t = block_sum(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 // ---- single-image kernels ------------------------------------------------
@@ -1232,6 +1288,41 @@ hipError_t launch_fft_rows_c2r(const float2* T, int n, int ts, float* dst, const
     else
         hipLaunchKernelGGL(fft_rows_c2r_kernel<0>, dim3(n / (2 * G)), dim3(kBlock), lds, s, T, n, ts, dst, fd, tw, G,
                            seq_shift_for(G), accum);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_rows_r2c(int n, float2* T, int ts, const FftDesc& fd, const float2* tw, const PcgVec& v,
+                               hipStream_t s) {
+    const int G = pick_pairs_per_block(n);
+    const size_t lds = lds_bytes(fft_lds_elems(G * n, n), n);
+    if (n == kFixedN && G == 1)
+        hipLaunchKernelGGL(pcg_rows_r2c_kernel<kFixedN>, dim3(n / 2), dim3(kBlock), lds, s, n, T, ts, fd, tw, 1,
+                           seq_shift_for(1), v);
+    else if (fd.m > 0)
+        hipLaunchKernelGGL(pcg_rows_r2c_kernel<kAnyLen>, dim3(n / (2 * G)), dim3(kBlock), lds, s, n, T, ts, fd, tw, G,
+                           seq_shift_for(G), v);
+    else
+        hipLaunchKernelGGL(pcg_rows_r2c_kernel<0>, dim3(n / (2 * G)), dim3(kBlock), lds, s, n, T, ts, fd, tw, G,
+                           seq_shift_for(G), v);
+    return hipGetLastError();
+}
+
+int pcg_rows_c2r_partials(int n) { return n / (2 * pick_pairs_per_block(n)); }
+
+hipError_t launch_pcg_rows_c2r(const float2* T, int n, int ts, float* z, const float* res, const FftDesc& fd,
+                               const float2* tw, double* part, int* n_part, hipStream_t s) {
+    const int G = pick_pairs_per_block(n);
+    const size_t lds = lds_bytes(fft_lds_elems(G * n, n), n);
+    *n_part = n / (2 * G);
+    if (n == kFixedN && G == 1)
+        hipLaunchKernelGGL(pcg_rows_c2r_kernel<kFixedN>, dim3(n / 2), dim3(kBlock), lds, s, T, n, ts, z, res, fd, tw, 1,
+                           seq_shift_for(1), part);
+    else if (fd.m > 0)
+        hipLaunchKernelGGL(pcg_rows_c2r_kernel<kAnyLen>, dim3(n / (2 * G)), dim3(kBlock), lds, s, T, n, ts, z, res, fd,
+                           tw, G, seq_shift_for(G), part);
+    else
+        hipLaunchKernelGGL(pcg_rows_c2r_kernel<0>, dim3(n / (2 * G)), dim3(kBlock), lds, s, T, n, ts, z, res, fd, tw, G,
+                           seq_shift_for(G), part);
     return hipGetLastError();
 }
 

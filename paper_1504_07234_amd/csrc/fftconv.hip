@@ -57,15 +57,34 @@ static int fc_seq_shift(int batch) {
 // side and holds the source's extension there (Table 1 and section 2.2: the
 // reflective, periodic or antireflective pad): the grid then carries
 // E src E^T.  NT > 0: M == NT and G == 1.
-template <int NT>
+// DIR (Algorithm 2's PCG): the source is the direction d, first updated in
+// place to d = z + b d with b = rho_new / rho (nothing once the CG has
+// stopped), as the separate direction kernel does.
+template <int NT, bool DIR = false>
 __global__ __launch_bounds__(kBlock) void fc_rows_fwd_kernel(const float* __restrict__ src, int S, int off, int M_,
                                                              float2* __restrict__ T, int ts, FftDesc fd,
                                                              const float2* __restrict__ tw, int G_, int seq_shift,
-                                                             int pair0, int pair_end, int ext) {
+                                                             int pair0, int pair_end, int ext, PcgDir dir) {
     extern __shared__ float2 buf[];
     const int M = NT > 0 ? NT : M_;
     const int G = NT > 0 ? 1 : G_;
     const int pb = pair0 + xcd_block(blockIdx.x, gridDim.x) * G;
+    bool dir_on = false;
+    float dir_b = 0.0f;
+    if constexpr (DIR) {
+        dir_on = *dir.act != 0.0;
+        if (dir_on) dir_b = (float)(*dir.rho_new / *dir.rho);
+    }
+    auto rd = [&](size_t i) {
+        if constexpr (DIR) {
+            if (!dir_on) return src[i];
+            const float v = fmaf(dir_b, dir.d[i], dir.z[i]);
+            dir.d[i] = v;
+            return v;
+        } else {
+            return src[i];
+        }
+    };
     FixedTw<(NT > 0 ? NT : 1)> twp;
     if constexpr (NT > 0) fixed_tw_load<NT>(tw, twp.w);
     strided_copy<NT, float2>(
@@ -83,8 +102,8 @@ __global__ __launch_bounds__(kBlock) void fc_rows_fwd_kernel(const float* __rest
                     if (y1 >= -off && y1 < S + off) b = fetch_ext(src, S, y1, x, ext);
                 }
             } else if (pb + g < pair_end && x >= 0 && x < S) {
-                if (y0 >= 0 && y0 < S) a = src[(size_t)y0 * S + x];
-                if (y1 >= 0 && y1 < S) b = src[(size_t)y1 * S + x];
+                if (y0 >= 0 && y0 < S) a = rd((size_t)y0 * S + x);
+                if (y1 >= 0 && y1 < S) b = rd((size_t)y1 * S + x);
             }
             return make_float2(a, b);
         },
@@ -658,22 +677,32 @@ __global__ __launch_bounds__(kBlock) void precond_fc_blurT_kernel(
 
 // ---- launchers ------------------------------------------------------------
 
-hipError_t launch_fc_rows_fwd(const FftConv& c, const float* src, int S, int off, int y_lo, int y_hi,
-                              hipStream_t s, int ext) {
+template <bool DIR>
+static hipError_t launch_fc_rows_fwd_t(const FftConv& c, const float* src, int S, int off, int y_lo, int y_hi,
+                                       hipStream_t s, int ext, const PcgDir& dir) {
     const int G = fc_pairs_per_block(c.M);
     const int p0 = y_lo / 2, p1 = (y_hi + 1) / 2;
     const int blocks = (p1 - p0 + G - 1) / G;
     if (blocks <= 0) return hipSuccess;
     if (c.M == kFixedM && G == 1)
-        hipLaunchKernelGGL(fc_rows_fwd_kernel<kFixedM>, dim3(blocks), dim3(kBlock), lds_bytes(c.M, c.M), s, src, S,
-                           off, c.M, c.T, c.ts, c.fd, c.tw, 1, fc_seq_shift(1), p0, p1, ext);
+        hipLaunchKernelGGL((fc_rows_fwd_kernel<kFixedM, DIR>), dim3(blocks), dim3(kBlock), lds_bytes(c.M, c.M), s, src,
+                           S, off, c.M, c.T, c.ts, c.fd, c.tw, 1, fc_seq_shift(1), p0, p1, ext, dir);
     else if (c.M == kFixedM2 && G == 1)
-        hipLaunchKernelGGL(fc_rows_fwd_kernel<kFixedM2>, dim3(blocks), dim3(kBlock), lds_bytes(c.M, c.M), s, src, S,
-                           off, c.M, c.T, c.ts, c.fd, c.tw, 1, fc_seq_shift(1), p0, p1, ext);
+        hipLaunchKernelGGL((fc_rows_fwd_kernel<kFixedM2, DIR>), dim3(blocks), dim3(kBlock), lds_bytes(c.M, c.M), s,
+                           src, S, off, c.M, c.T, c.ts, c.fd, c.tw, 1, fc_seq_shift(1), p0, p1, ext, dir);
     else
-        hipLaunchKernelGGL(fc_rows_fwd_kernel<0>, dim3(blocks), dim3(kBlock), lds_bytes(G * c.M, c.M), s, src, S, off,
-                           c.M, c.T, c.ts, c.fd, c.tw, G, fc_seq_shift(G), p0, p1, ext);
+        hipLaunchKernelGGL((fc_rows_fwd_kernel<0, DIR>), dim3(blocks), dim3(kBlock), lds_bytes(G * c.M, c.M), s, src,
+                           S, off, c.M, c.T, c.ts, c.fd, c.tw, G, fc_seq_shift(G), p0, p1, ext, dir);
     return hipGetLastError();
+}
+
+hipError_t launch_fc_rows_fwd(const FftConv& c, const float* src, int S, int off, int y_lo, int y_hi,
+                              hipStream_t s, int ext, const PcgDir* dir) {
+    if (dir) {
+        if (ext != EXT_ZERO || dir->d != src) return hipErrorInvalidValue;
+        return launch_fc_rows_fwd_t<true>(c, src, S, off, y_lo, y_hi, s, ext, *dir);
+    }
+    return launch_fc_rows_fwd_t<false>(c, src, S, off, y_lo, y_hi, s, ext, PcgDir{});
 }
 
 hipError_t launch_fc_cols(const FftConv& c, int conj_h, int y_lo, int y_hi, int mode, float2* cspec, hipStream_t s,

@@ -210,8 +210,17 @@ struct PrecondRows {
 // [0, fn + (fn & 1)) and the row pass (oy = ox = 0, D = fn) applies E^T along
 // the rows.  conj_h: the column product with H (0), conj(H) (1) or |H|^2 (2).
 // axd: the row pass writes v + axa axd with the partials of sum axd (v + axa axd).
+// Algorithm 2's direction update folded into a forward row pass (src == d):
+// d = z + (*rho_new / *rho) d while *act != 0
+struct PcgDir {
+    float* d;
+    const float* z;
+    const double* rho_new;
+    const double* rho;
+    const double* act;
+};
 hipError_t launch_fc_rows_fwd(const FftConv& c, const float* src, int S, int off, int y_lo, int y_hi, hipStream_t s,
-                              int ext = EXT_ZERO);
+                              int ext = EXT_ZERO, const PcgDir* dir = nullptr);
 hipError_t launch_fc_cols(const FftConv& c, int conj_h, int y_lo, int y_hi, int mode, float2* cspec, hipStream_t s,
                           int o_lo, int o_hi, int fold = -1, int fn = 0, int fcn = 0);
 hipError_t launch_fc_rows_inv(const FftConv& c, int oy, int ox, int D, float* dst, const float* g, int accum,
@@ -316,6 +325,28 @@ hipError_t launch_fft_cols_filter_inverse(float2* T, int n, int ts, const float*
 // columns: forward FFT, complex values into cspec (dense [n/2+1][n])
 hipError_t launch_fft_cols_complex(const float2* T, int n, int ts, float2* cspec, const FftDesc& fd,
                                    const float2* tw, hipStream_t s);
+// Algorithm 2's PCG vectors (device): t += a d and res -= a q with
+// a = *rho / *pq while *act != 0
+struct PcgVec {
+    float* t;
+    float* res;
+    const float* d;
+    const float* q;
+    const double* rho;
+    const double* pq;
+    const double* act;
+};
+// BCCB plan: P's forward row pass with the step's update applied to res (and
+// t) first; P's inverse row pass writing z with the partials of res . z
+// (pcg_rows_c2r_partials(n) of them)
+hipError_t launch_pcg_rows_r2c(int n, float2* T, int ts, const FftDesc& fd, const float2* tw, const PcgVec& v,
+                               hipStream_t s);
+hipError_t launch_pcg_rows_c2r(const float2* T, int n, int ts, float* z, const float* res, const FftDesc& fd,
+                               const float2* tw, double* part, int* n_part, hipStream_t s);
+int pcg_rows_c2r_partials(int n);
+// pcg_check after summing the np partials of rho_j into *rn (one workgroup)
+hipError_t launch_pcg_check_sum(double* st, const double* part, int np, double* rn, int j, int max_steps,
+                                double tol, int* hist, hipStream_t s);
 // Algorithm 4-NS: alpha_n on the device from the BCCB half spectrum T
 // (float2, real = 0) or the DCT coefficients (float, real = 1); state:
 // ns_state_doubles() device doubles (launch_ns_psf_l1 after every PSF

@@ -538,11 +538,19 @@ int do_blurT_acc(mlba_plan_s* P, const float* y, float* omega, hipStream_t s) {
 // rectangular model on the FFT grid takes one transform pair with |H|^2:
 // the correlation A^T d of d placed at (p-1, p-1) vanishes outside
 // [0, m)^2, and M >= m, so the crop between A^T and A changes nothing.
-int do_gram(mlba_plan_s* P, const float* d, float* q, double alpha, int* np, hipStream_t s) {
+// dir (optional): first update d = z + b d in the same pass (FFT grid) or as
+// a separate pass.
+bool gram_on_grid(const mlba_plan_s* P) { return P->blur_fft && P->bc == MLBA_BC_RECT; }
+
+int do_gram(mlba_plan_s* P, float* d, float* q, double alpha, int* np, const PcgDir* dir, hipStream_t s) {
     const int n = P->n, p = P->p, m = n + p - 1;
     const size_t nn = (size_t)n * n;
-    if (P->blur_fft && P->bc == MLBA_BC_RECT) {
-        HIPCHK(launch_fc_rows_fwd(P->fc, d, n, p - 1, p - 1, m, s));
+    if (dir && !gram_on_grid(P)) {
+        HIPCHK(launch_pcg_dir(d, dir->z, nn, dir->rho_new, dir->rho, dir->act, s));
+        dir = nullptr;
+    }
+    if (gram_on_grid(P)) {
+        HIPCHK(launch_fc_rows_fwd(P->fc, d, n, p - 1, p - 1, m, s, EXT_ZERO, dir));
         MARK(BLUR_T, FC_ROWS_FWD);
         HIPCHK(launch_fc_cols(P->fc, 2, p - 1, m, 0, nullptr, s, p - 1, p - 1 + n + (n & 1)));
         MARK(BLUR, FC_COLS);
@@ -576,17 +584,32 @@ int do_pcg(mlba_plan_s* P, double alpha, int max_steps, double tol, int* hist, h
     HIPCHK(launch_dot_partials(res, zc, nn, P->partials, &np, s));
     HIPCHK(launch_sum_partials(P->partials, np, rho[0], s));
     HIPCHK(launch_pcg_begin(st, hist, s));
+    // BCCB plan: the update t += a d, res -= a q runs inside P's forward row
+    // pass and the dot product res . z inside its inverse row pass
+    const bool fused = P->precond == MLBA_PRECOND_BCCB && pcg_rows_c2r_partials(P->n) <= P->partials_cap;
+    const float inv = (float)(1.0 / ((double)P->n * (double)P->n));
     for (int j = 1; j <= max_steps; ++j) {
         double* rc = rho[(j - 1) & 1];
         double* rn = rho[j & 1];
-        STCHK(do_gram(P, d, q, alpha, &np, s));  // q = (A A^T + alpha I) d, d . q
+        // q = (A A^T + alpha I) d, d . q; from the second step on, first the
+        // direction d = z + (rho_{j-1} / rho_{j-2}) d of the previous step
+        const PcgDir dir{d, zc, rc, rn, act};
+        STCHK(do_gram(P, d, q, alpha, &np, j > 1 ? &dir : nullptr, s));
         HIPCHK(launch_sum_partials(P->partials, np, pq, s));
-        HIPCHK(launch_pcg_update(t, res, d, q, nn, rc, pq, act, s));
-        STCHK(do_precond(P, res, zc, alpha, s));
-        HIPCHK(launch_dot_partials(res, zc, nn, P->partials, &np, s));
-        HIPCHK(launch_sum_partials(P->partials, np, rn, s));
-        HIPCHK(launch_pcg_check(st, rn, j, max_steps, tol, hist, s));
-        if (j < max_steps) HIPCHK(launch_pcg_dir(d, zc, nn, rn, rc, act, s));
+        if (fused) {
+            const PcgVec v{t, res, d, q, rc, pq, act};
+            HIPCHK(launch_pcg_rows_r2c(P->n, (float2*)P->swork, P->ts, P->fd, P->tw, v, s));
+            HIPCHK(launch_fft_cols_filter((float2*)P->swork, P->n, P->ts, P->spec, (float)alpha, inv, P->fd, P->tw, s));
+            HIPCHK(launch_pcg_rows_c2r((const float2*)P->swork, P->n, P->ts, zc, res, P->fd, P->tw, P->partials, &np,
+                                       s));
+            HIPCHK(launch_pcg_check_sum(st, P->partials, np, rn, j, max_steps, tol, hist, s));
+        } else {
+            HIPCHK(launch_pcg_update(t, res, d, q, nn, rc, pq, act, s));
+            STCHK(do_precond(P, res, zc, alpha, s));
+            HIPCHK(launch_dot_partials(res, zc, nn, P->partials, &np, s));
+            HIPCHK(launch_sum_partials(P->partials, np, rn, s));
+            HIPCHK(launch_pcg_check(st, rn, j, max_steps, tol, hist, s));
+        }
     }
     return MLBA_OK;
 }

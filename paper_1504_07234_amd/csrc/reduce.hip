@@ -138,6 +138,22 @@ __global__ void pcg_check_kernel(double* __restrict__ st, const double* __restri
     if (sqrt(*rn / st[3]) <= tol || j == max_steps) st[4] = 0.0;
 }
 
+// the same after summing the np partials of rho_j (fixed order) into *rn
+__global__ __launch_bounds__(kBlock) void pcg_check_sum_kernel(double* __restrict__ st,
+                                                               const double* __restrict__ part, int np,
+                                                               double* __restrict__ rn, int j, int max_steps,
+                                                               double tol, int* __restrict__ hist) {
+    __shared__ double red[kBlock / 64];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < np; i += kBlock) acc += part[i];
+    const double total = block_sum(acc, red);
+    if (threadIdx.x != 0) return;
+    *rn = total;
+    if (st[4] == 0.0) return;
+    *hist = j;
+    if (sqrt(total / st[3]) <= tol || j == max_steps) st[4] = 0.0;
+}
+
 // t += a d, res -= a q with a = rho / pq (both device doubles); nothing once
 // the CG has stopped (*act == 0)
 __global__ __launch_bounds__(kBlock) void pcg_update_kernel(float* __restrict__ t, float* __restrict__ res,
@@ -232,6 +248,12 @@ hipError_t launch_pcg_begin(double* st, int* hist, hipStream_t s) {
 hipError_t launch_pcg_check(double* st, const double* rn, int j, int max_steps, double tol, int* hist,
                             hipStream_t s) {
     hipLaunchKernelGGL(pcg_check_kernel, dim3(1), dim3(1), 0, s, st, rn, j, max_steps, tol, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_check_sum(double* st, const double* part, int np, double* rn, int j, int max_steps,
+                                double tol, int* hist, hipStream_t s) {
+    hipLaunchKernelGGL(pcg_check_sum_kernel, dim3(1), dim3(kBlock), 0, s, st, part, np, rn, j, max_steps, tol, hist);
     return hipGetLastError();
 }
 
