@@ -190,6 +190,34 @@ def test_full_size_iterations(mlba):
         assert rel_err(info.rnorm, ref["rnorm"]) < 1e-6
 
 
+@pytest.mark.parametrize("bc,pc", [(oblur.ZERO, 0), (oblur.REFLECT, 0), (oblur.REFLECT, 1), (oblur.PERIODIC, 0)])
+def test_full_size_square_models(mlba, bc, pc):
+    """The bench's square-model runs at full size: 2048 x 2048 image, 31 x 31
+    disk, 3 levels, implicit state, FFT-grid blur (the pad on the grid and E^T
+    folded back; periodic + BCCB: the residual in the spectrum), 3 iterations
+    against the oracle, image and residual norms element by element."""
+    w = synth.make_workload("rect-bccb-2048")
+    iters, n = 3, w.n
+    announce(f"restore 2048 bc={bc} precond={pc} {iters} iterations, FFT blur, implicit")
+    g, _ = observed(w, oblur)
+    alphas = np.full(iters, w.alpha0)
+    deltas = np.full(iters + 1, 0.3)
+    ref = omlba.mlba(g, w.psf, bc, pc, w.levels, alphas, deltas, w.mu, iters)
+    with mlba.Plan(n, w.p, bc, pc, w.levels, cuda(w.psf)) as plan:
+        plan.set_blur(mlba.BLUR_FFT)
+        plan.profile_begin(iters)
+        f, info = plan.restore(cuda(g), alpha_table=alphas, mu=w.mu, delta_table=deltas, iters=iters, implicit=True)
+        plan.profile_end()
+        kern = plan.profile_kernels()
+        f = host(f)
+    e, em, er = rel_err(f, ref["f"]), max_err(f, ref["f"]), rel_err(info.rnorm, ref["rnorm"])
+    print(f"  image {e:.2e} max {em:.2e} rnorm {er:.2e}", flush=True)
+    assert e < 1e-5 and em < 1e-4
+    assert er < 1e-6
+    spectral = bc == oblur.PERIODIC and pc == 0
+    assert ("fc_cols" in kern) == (not spectral)
+
+
 @pytest.mark.parametrize("n,p,bc,pc,L", [(96, 17, 0, 0, 2), (96, 17, 1, 1, 3), (192, 11, 3, 0, 2),
                                          (128, 7, 2, 0, 4), (384, 25, 0, 1, 2)])
 def test_ragged_and_mixed_models(mlba, n, p, bc, pc, L):
