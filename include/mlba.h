@@ -88,7 +88,11 @@ extern "C" {
                                     tau_n = ||r^n|| / noise (eq. Alg4_rev_7); the run stops at
                                     the first n with ||r^n|| <= tau noise, tau = (1 + 2 ns_rho) /
                                     (1 - 2 ns_rho) (eq. Alg4_rev_12); noise = stop->noise_norm
-                                    (required); alpha0 is the first Newton start */
+                                    (required); alpha0 is the first Newton start.  alpha_n
+                                    is found on the device (at most 12 Newton steps in log
+                                    alpha inside a shrinking bracket, stopping once a step
+                                    moves log alpha by < 2^-22: the FP32 sums resolve no
+                                    finer); alpha_out reports it */
 
 typedef struct mlba_alpha_schedule {
     int kind;
@@ -102,7 +106,8 @@ typedef struct mlba_alpha_schedule {
 } mlba_alpha_schedule;
 
 /* Update direction (section 5).  MLBA: eq. (MLBA2), z += W A^T P_alpha r with
- * the preconditioner of the plan.  ALG4: eq. (Alg4), z += W C^T (C C^T +
+ * the preconditioner of the plan (periodic model, BCCB plan, MLBA_BLUR_FFT:
+ * computed as ALG4's direction, since A = C there).  ALG4: eq. (Alg4), z += W C^T (C C^T +
  * alpha I)^{-1} r, C the periodic (BCCB plan) or reflective-of-the-symmetrised-
  * PSF (DCT plan) blur: no A^T product; square boundary models only (plans
  * with MLBA_BC_RECT return MLBA_EUNSUPPORTED), preconditioner BCCB or DCT. */
@@ -114,7 +119,9 @@ typedef struct mlba_alpha_schedule {
  * step whose preconditioned relative residual sqrt(res^T M^-1 res / r^T M^-1 r)
  * is at most pcg_tol (eq. bet; the paper: 5 and 1e-3).  The stopping test
  * runs on the device: every iteration enqueues pcg_max CG steps and the steps
- * after the stop leave t unchanged (no host round trip; iters <= 65536). */
+ * after the stop leave t unchanged (no host round trip; iters <= 65536).  With
+ * MLBA_BC_RECT and MLBA_BLUR_FFT each (A A^T + alpha I) d is one transform
+ * pair of the grid with |H|^2. */
 #define MLBA_METHOD_ALG2 2
 
 /* Discrepancy-principle stop, eq. (discrpr): stop at the first k with
