@@ -169,6 +169,24 @@ def test_opnorm(mlba, n, psf, bc, pc, alpha):
     assert abs(got / ref - 1.0) <= 1e-6
 
 
+@pytest.mark.parametrize("n,bc,pc,alpha", [(96, 1, 0, 0.05), (96, 2, 0, 0.1), (96, 3, 1, 0.2), (256, 1, 1, 0.05),
+                                         (256, 0, 0, 0.02)])
+def test_opnorm_fft_blur(mlba, n, bc, pc, alpha):
+    """The same norm with A and A^T on the FFT grid (the square models' pad
+    placed on the grid and folded back by its transpose): against the oracle
+    and against the direct blur's Lanczos."""
+    announce(f"opnorm FFT blur n={n} bc={bc} pc={pc} alpha={alpha}")
+    H = synth.motion_psf(17, 15.0, 0.7) if n == 256 else synth.gaussian_psf(9, 2.0)
+    with mlba.Plan(n, H.shape[0], bc, pc, 1, cuda(H)) as plan:
+        direct = plan.opnorm(alpha)
+        plan.set_blur(mlba.BLUR_FFT)
+        got = plan.opnorm(alpha)
+    ref = omlba.opnorm(H, n, bc, pc, alpha, tol=1e-12)
+    print(f"  fft={got:.9f} direct={direct:.9f} oracle={ref:.9f} rel {abs(got / ref - 1):.1e}", flush=True)
+    assert abs(got / ref - 1.0) <= 1e-6
+    assert abs(got / direct - 1.0) <= 1e-6
+
+
 def test_full_size_operators(mlba):
     """The 2048 x 2048 throughput workload's shapes: p = 31 disk, 3 levels."""
     w = synth.make_workload("rect-bccb-2048")
