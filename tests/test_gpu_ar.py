@@ -369,7 +369,7 @@ def test_alg2_antireflective_against_oracle(mlba):
     print(f"  betas gpu {info.pcg_steps} oracle {ref['betas'].tolist()}; image {rel_err(f, ref['f']):.2e}",
           flush=True)
     assert info.pcg_steps == ref["betas"].tolist()
-    assert rel_err(f, ref["f"]) < 1e-4
+    assert rel_err(f, ref["f"]) < 1e-4 and max_err(f, ref["f"]) < 1e-4
 
 
 def test_alg2_with_the_exact_antireflective_preconditioner(mlba):

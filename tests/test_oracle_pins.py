@@ -503,6 +503,16 @@ def test_literal_unit_step_diverges():
 
 
 def test_alpha_table():
-    a = mlba.alpha_table(1, 0.5, 30, ratio=0.8, floor=0.02)
-    assert a[0] == 0.5 and abs(a[3] - 0.5 * 0.8 ** 3) < 1e-16 and a[-1] == 0.02
+    """The geometric schedule (reading R9) against its recursive form
+    a_{k+1} = max(r a_k, floor) and the index where the floor takes over,
+    ceil(log(floor / a_0) / log r); the constant schedule."""
+    a0, r, floor, K = 0.5, 0.8, 0.02, 30
+    a = mlba.alpha_table(1, a0, K, ratio=r, floor=floor)
+    rec = [a0]
+    for _ in range(K - 1):
+        rec.append(max(rec[-1] * r, floor))
+    assert np.allclose(a, rec, rtol=1e-13, atol=0.0)
+    k_floor = int(np.ceil(np.log(floor / a0) / np.log(r)))
+    assert np.all(a[:k_floor] > floor) and np.all(a[k_floor:] == floor)
+    assert np.all(np.diff(a) <= 0.0)
     assert np.all(mlba.alpha_table(0, 0.05, 4) == 0.05)
