@@ -59,7 +59,7 @@ static int fc_seq_shift(int batch) {
 // E src E^T.  NT > 0: M == NT and G == 1.
 // DIR (Algorithm 2's PCG): the source is the direction d, first updated in
 // place to d = z + b d with b = rho_new / rho (nothing once the CG has
-// stopped), as the separate direction kernel does.
+// stopped), as the separate direction kernel does; rho_new null: d = z.
 template <int NT, bool DIR = false>
 __global__ __launch_bounds__(kBlock) void fc_rows_fwd_kernel(const float* __restrict__ src, int S, int off, int M_,
                                                              float2* __restrict__ T, int ts, FftDesc fd,
@@ -69,16 +69,17 @@ __global__ __launch_bounds__(kBlock) void fc_rows_fwd_kernel(const float* __rest
     const int M = NT > 0 ? NT : M_;
     const int G = NT > 0 ? 1 : G_;
     const int pb = pair0 + xcd_block(blockIdx.x, gridDim.x) * G;
-    bool dir_on = false;
+    bool dir_on = false, dir_copy = false;
     float dir_b = 0.0f;
     if constexpr (DIR) {
-        dir_on = *dir.act != 0.0;
-        if (dir_on) dir_b = (float)(*dir.rho_new / *dir.rho);
+        dir_copy = dir.rho_new == nullptr;  // the first direction: d = z
+        dir_on = dir_copy || *dir.act != 0.0;
+        if (dir_on && !dir_copy) dir_b = (float)(*dir.rho_new / *dir.rho);
     }
     auto rd = [&](size_t i) {
         if constexpr (DIR) {
             if (!dir_on) return src[i];
-            const float v = fmaf(dir_b, dir.d[i], dir.z[i]);
+            const float v = dir_copy ? dir.z[i] : fmaf(dir_b, dir.d[i], dir.z[i]);
             dir.d[i] = v;
             return v;
         } else {

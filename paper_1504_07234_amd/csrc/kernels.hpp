@@ -211,7 +211,7 @@ struct PrecondRows {
 // the rows.  conj_h: the column product with H (0), conj(H) (1) or |H|^2 (2).
 // axd: the row pass writes v + axa axd with the partials of sum axd (v + axa axd).
 // Algorithm 2's direction update folded into a forward row pass (src == d):
-// d = z + (*rho_new / *rho) d while *act != 0
+// d = z + (*rho_new / *rho) d while *act != 0; rho_new null: d = z
 struct PcgDir {
     float* d;
     const float* z;
@@ -344,6 +344,8 @@ hipError_t launch_pcg_rows_r2c(int n, float2* T, int ts, const FftDesc& fd, cons
 hipError_t launch_pcg_rows_c2r(const float2* T, int n, int ts, float* z, const float* res, const FftDesc& fd,
                                const float2* tw, double* part, int* n_part, hipStream_t s);
 int pcg_rows_c2r_partials(int n);
+// pcg_begin after summing the np partials of rho_0 into st[0] (one workgroup)
+hipError_t launch_pcg_begin_sum(double* st, const double* part, int np, int* hist, hipStream_t s);
 // pcg_check after summing the np partials of rho_j into *rn (one workgroup)
 hipError_t launch_pcg_check_sum(double* st, const double* part, int np, double* rn, int j, int max_steps,
                                 double tol, int* hist, hipStream_t s);

@@ -546,7 +546,8 @@ int do_gram(mlba_plan_s* P, float* d, float* q, double alpha, int* np, const Pcg
     const int n = P->n, p = P->p, m = n + p - 1;
     const size_t nn = (size_t)n * n;
     if (dir && !gram_on_grid(P)) {
-        HIPCHK(launch_pcg_dir(d, dir->z, nn, dir->rho_new, dir->rho, dir->act, s));
+        if (dir->rho_new) HIPCHK(launch_pcg_dir(d, dir->z, nn, dir->rho_new, dir->rho, dir->act, s));
+        else HIPCHK(hipMemcpyAsync(d, dir->z, nn * sizeof(float), hipMemcpyDeviceToDevice, s));
         dir = nullptr;
     }
     if (gram_on_grid(P)) {
@@ -566,7 +567,15 @@ int do_gram(mlba_plan_s* P, float* d, float* q, double alpha, int* np, const Pcg
     return MLBA_OK;
 }
 
-int do_pcg(mlba_plan_s* P, double alpha, int max_steps, double tol, int* hist, hipStream_t s) {
+// The PCG's start through the fused row kernels: BCCB plan, the partials of
+// the c2r pass fit, and (for the residual's fused row pass) the fused FFT path.
+bool pcg_fused_rows(const mlba_plan_s* P) {
+    return P->precond == MLBA_PRECOND_BCCB && pcg_rows_c2r_partials(P->n) <= P->partials_cap;
+}
+bool pcg_fused_start(const mlba_plan_s* P) { return pcg_fused_rows(P) && fused_fft_path(P); }
+
+// rows_ready: P's forward row pass of res is already in the plan's workspace
+int do_pcg(mlba_plan_s* P, double alpha, int max_steps, double tol, int* hist, bool rows_ready, hipStream_t s) {
     const size_t nn = (size_t)P->n * P->n;
     float* t = P->pcg;
     float* zc = P->pcg + nn;
@@ -578,23 +587,32 @@ int do_pcg(mlba_plan_s* P, double alpha, int max_steps, double tol, int* hist, h
     double* pq = st + 2;
     const double* act = st + 4;
     int np = 0;
-    HIPCHK(launch_fill(t, nn, 0.0f, s));
-    STCHK(do_precond(P, res, zc, alpha, s));
-    HIPCHK(hipMemcpyAsync(d, zc, nn * sizeof(float), hipMemcpyDeviceToDevice, s));
-    HIPCHK(launch_dot_partials(res, zc, nn, P->partials, &np, s));
-    HIPCHK(launch_sum_partials(P->partials, np, rho[0], s));
-    HIPCHK(launch_pcg_begin(st, hist, s));
     // BCCB plan: the update t += a d, res -= a q runs inside P's forward row
-    // pass and the dot product res . z inside its inverse row pass
-    const bool fused = P->precond == MLBA_PRECOND_BCCB && pcg_rows_c2r_partials(P->n) <= P->partials_cap;
+    // pass and the dot product res . z inside its inverse row pass; the first
+    // direction d = z is copied by the first Gram product's forward row pass
+    const bool fused = pcg_fused_rows(P);
     const float inv = (float)(1.0 / ((double)P->n * (double)P->n));
+    HIPCHK(launch_fill(t, nn, 0.0f, s));
+    if (fused) {
+        if (!rows_ready) HIPCHK(launch_fft_rows_r2c(res, P->n, (float2*)P->swork, P->ts, P->fd, P->tw, s));
+        HIPCHK(launch_fft_cols_filter((float2*)P->swork, P->n, P->ts, P->spec, (float)alpha, inv, P->fd, P->tw, s));
+        HIPCHK(launch_pcg_rows_c2r((const float2*)P->swork, P->n, P->ts, zc, res, P->fd, P->tw, P->partials, &np, s));
+        HIPCHK(launch_pcg_begin_sum(st, P->partials, np, hist, s));
+    } else {
+        STCHK(do_precond(P, res, zc, alpha, s));
+        HIPCHK(hipMemcpyAsync(d, zc, nn * sizeof(float), hipMemcpyDeviceToDevice, s));
+        HIPCHK(launch_dot_partials(res, zc, nn, P->partials, &np, s));
+        HIPCHK(launch_sum_partials(P->partials, np, rho[0], s));
+        HIPCHK(launch_pcg_begin(st, hist, s));
+    }
     for (int j = 1; j <= max_steps; ++j) {
         double* rc = rho[(j - 1) & 1];
         double* rn = rho[j & 1];
         // q = (A A^T + alpha I) d, d . q; from the second step on, first the
         // direction d = z + (rho_{j-1} / rho_{j-2}) d of the previous step
-        const PcgDir dir{d, zc, rc, rn, act};
-        STCHK(do_gram(P, d, q, alpha, &np, j > 1 ? &dir : nullptr, s));
+        // (fused start: at the first step the copy d = z, rho_new null)
+        const PcgDir dir{d, zc, j > 1 ? rc : nullptr, rn, act};
+        STCHK(do_gram(P, d, q, alpha, &np, (j > 1 || fused) ? &dir : nullptr, s));
         HIPCHK(launch_sum_partials(P->partials, np, pq, s));
         if (fused) {
             const PcgVec v{t, res, d, q, rc, pq, act};
@@ -1382,7 +1400,16 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
             done = i + 1;
             continue;
         }
-        STCHK(do_blur(P, P->u, g, P->r, true, &np, s));
+        // Algorithm 2 on the fused FFT path: the residual's inverse row pass
+        // also runs P's forward row pass of r (the PCG's first P application)
+        const bool pcg_rows = alg2 && pcg_fused_start(P);
+        if (pcg_rows) {
+            STCHK(blur_grid_forward(P, P->u, s));
+            HIPCHK(launch_fc_residual_precond_rows(P->fc, P->n, P->p, g, P->r, P->partials, &np, precond_rows(P), s));
+            MARK(BLUR, FC_RESIDUAL_PRECOND_ROWS);
+        } else {
+            STCHK(do_blur(P, P->u, g, P->r, true, &np, s));
+        }
         HIPCHK(launch_sum_partials(P->partials, np, P->rn + (i - ring_base), s));
         MARK(BLUR, REDUCE);
         STCHK(check_stop(&hit));
@@ -1408,7 +1435,7 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
         if (alg2) {
             const int cur = P->prof_cur;  // the PCG is timed as one sequence
             P->prof_cur = -1;
-            STCHK(do_pcg(P, alpha[i], pcg_max, pcg_tol, P->pcgh + i, s));
+            STCHK(do_pcg(P, alpha[i], pcg_max, pcg_tol, P->pcgh + i, pcg_rows, s));
             P->prof_cur = cur;
             STCHK(prof_mark(P, MLBA_PHASE_PRECOND, MLBA_KERNEL_OTHER, 1, s));
             float* tsol = P->pcg;  // the CG solution t

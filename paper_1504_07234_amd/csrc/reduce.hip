@@ -138,7 +138,22 @@ __global__ void pcg_check_kernel(double* __restrict__ st, const double* __restri
     if (sqrt(*rn / st[3]) <= tol || j == max_steps) st[4] = 0.0;
 }
 
-// the same after summing the np partials of rho_j (fixed order) into *rn
+// pcg_begin after summing the np partials of rho_0 (fixed order) into st[0]
+__global__ __launch_bounds__(kBlock) void pcg_begin_sum_kernel(double* __restrict__ st,
+                                                               const double* __restrict__ part, int np,
+                                                               int* __restrict__ hist) {
+    __shared__ double red[kBlock / 64];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < np; i += kBlock) acc += part[i];
+    const double total = block_sum(acc, red);
+    if (threadIdx.x != 0) return;
+    st[0] = total;
+    st[3] = total;
+    st[4] = total > 0.0 ? 1.0 : 0.0;
+    *hist = 0;
+}
+
+// pcg_check after summing the np partials of rho_j (fixed order) into *rn
 __global__ __launch_bounds__(kBlock) void pcg_check_sum_kernel(double* __restrict__ st,
                                                                const double* __restrict__ part, int np,
                                                                double* __restrict__ rn, int j, int max_steps,
@@ -248,6 +263,11 @@ hipError_t launch_pcg_begin(double* st, int* hist, hipStream_t s) {
 hipError_t launch_pcg_check(double* st, const double* rn, int j, int max_steps, double tol, int* hist,
                             hipStream_t s) {
     hipLaunchKernelGGL(pcg_check_kernel, dim3(1), dim3(1), 0, s, st, rn, j, max_steps, tol, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_begin_sum(double* st, const double* part, int np, int* hist, hipStream_t s) {
+    hipLaunchKernelGGL(pcg_begin_sum_kernel, dim3(1), dim3(kBlock), 0, s, st, part, np, hist);
     return hipGetLastError();
 }
 
