@@ -15,10 +15,13 @@ Prints one JSON line: Mpixel-iter/s over the observed pixels, the per-kernel
 and per-phase breakdown measured with HIP events on the library's stream on
 every 4th iteration of the timed region, the roofline of the dominant kernel
 (the one with the largest share of the iteration), and the FP64 oracle timed
-on the host cores over a bounded sample of the same workload.  Two
-sections follow: 64 uneven images batched under a hipGraph against 64
-sequential solves, and the forward / backward time of 30 unrolled
-iterations over 16 images of 256^2 with their gradients.
+on the host cores over a bounded sample of the same workload, and the FP32
+transforms' error against FP64.  Sections follow: 64 uneven images batched
+under a hipGraph against 64 sequential solves (implicit state and frame
+coefficients); the forward / backward time of 30 unrolled iterations over 16
+images of 256^2 with their gradients; Algorithm 4 and 4-NS (section 5) and
+Algorithm 2 (section 4.2) on the 2048^2 observation; eq. (MLBA2) on the square
+boundary models of Table 1; and the antireflective model (section 2.2).
 """
 from __future__ import annotations
 
