@@ -603,7 +603,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="rect-bccb-2048")
-    ap.add_argument("--cpu-iters", type=int, default=3, help="oracle iterations for the CPU baseline")
+    ap.add_argument("--cpu-iters", type=int, default=5, help="oracle iterations for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-sequential section")
     ap.add_argument("--no-unrolled", action="store_true", help="skip the unrolled forward/backward section")
