@@ -22,6 +22,11 @@
 
 namespace mlba {
 
+// Makhoul's DCT through an n-point FFT (as the DCT plan's row passes):
+// sample l goes to position dct_perm(l) (evens ascending, odds descending).
+__device__ __forceinline__ int fc_dct_perm(int l, int n) { return (l & 1) ? n - 1 - (l >> 1) : (l >> 1); }
+__device__ __forceinline__ float fc_re_mul(float2 w, float2 v) { return w.x * v.x - w.y * v.y; }
+
 constexpr int FC_EPT = 12;
 constexpr int FC_MAX = FC_EPT * kBlock;
 
@@ -404,11 +409,12 @@ __global__ __launch_bounds__(kBlock) void fc_rows_inv_kernel(const float2* __res
 // (with its squared-norm partial), then the forward transform of the two
 // residual rows, split and written transposed into the preconditioner's half
 // spectrum.  The arithmetic of every value is that of the separate passes.
-template <int NTM, int NTN>
+template <int NTM, int NTN, bool DCT = false>
 __global__ __launch_bounds__(kBlock) void fc_residual_precond_kernel(
     const float2* __restrict__ Tc, int M_, int tsc, FftDesc fdm, const float2* __restrict__ twm, int pair0, int n_,
     int off, const float* __restrict__ g, float* __restrict__ r_out, double* __restrict__ partials,
-    float2* __restrict__ Tp, int tsp, FftDesc fdn, const float2* __restrict__ twn) {
+    float2* __restrict__ Tp, int tsp, FftDesc fdn, const float2* __restrict__ twn,
+    const float2* __restrict__ dtw) {
     extern __shared__ float2 buf[];
     __shared__ double red[kBlock / 64];
     const int M = NTM > 0 ? NTM : M_;
@@ -472,18 +478,31 @@ __global__ __launch_bounds__(kBlock) void fc_residual_precond_kernel(
     for (int j = 0; j < FC_EPT; ++j) {
         const int X = (int)threadIdx.x + j * kBlock;
         const int x = X - off;
-        if (X < M && x >= 0 && x < n) buf[lds_slot(x)] = rr[j];
+        if (X < M && x >= 0 && x < n) buf[lds_slot(DCT ? fc_dct_perm(x, n) : x)] = rr[j];
     }
     __syncthreads();
     lds_fft_any<-1, NTN, FFT_EPT>(buf, fdn, 1, 8, twn, NTN > 0 ? twpn.w : nullptr);
-    const int hn = n / 2 + 1;
-    for (int k = threadIdx.x; k < hn; k += kBlock) {
-        const float2 Z = buf[lds_slot(k)];
-        const float2 Zc = cconj(buf[lds_slot(k == 0 ? 0 : n - k)]);
-        const float2 Xa = cscale(cadd(Z, Zc), 0.5f);
-        const float2 D = csub(Z, Zc);
-        const float2 Xb = make_float2(0.5f * D.y, -0.5f * D.x);  // D / (2i)
-        *reinterpret_cast<float4*>(Tp + (size_t)k * tsp + 2 * q) = make_float4(Xa.x, Xa.y, Xb.x, Xb.y);
+    if constexpr (DCT) {  // DCT-II of the two rows, written transposed as the DCT row pass does
+        float* Tr = reinterpret_cast<float*>(Tp);
+        for (int k = threadIdx.x; k < n; k += kBlock) {
+            const float2 Z = buf[lds_slot(k)];
+            const float2 Zc = cconj(buf[lds_slot(k == 0 ? 0 : n - k)]);
+            const float2 Va = cscale(cadd(Z, Zc), 0.5f);
+            const float2 D = csub(Z, Zc);
+            const float2 Vb = make_float2(0.5f * D.y, -0.5f * D.x);
+            const float2 w = dtw[k];
+            *reinterpret_cast<float2*>(Tr + (size_t)k * tsp + 2 * q) = make_float2(fc_re_mul(w, Va), fc_re_mul(w, Vb));
+        }
+    } else {
+        const int hn = n / 2 + 1;
+        for (int k = threadIdx.x; k < hn; k += kBlock) {
+            const float2 Z = buf[lds_slot(k)];
+            const float2 Zc = cconj(buf[lds_slot(k == 0 ? 0 : n - k)]);
+            const float2 Xa = cscale(cadd(Z, Zc), 0.5f);
+            const float2 D = csub(Z, Zc);
+            const float2 Xb = make_float2(0.5f * D.y, -0.5f * D.x);  // D / (2i)
+            *reinterpret_cast<float4*>(Tp + (size_t)k * tsp + 2 * q) = make_float4(Xa.x, Xa.y, Xb.x, Xb.y);
+        }
     }
     if (partials) {
         const double t = block_sum(ss, red);
@@ -613,11 +632,11 @@ __global__ __launch_bounds__(kBlock) void fc_residual_ar_kernel(
 // The preconditioner's inverse row pass (t = P r, two observed rows) and the
 // forward row pass of A^T on the FFT-blur grid, where those rows sit at
 // (y + off, x + off), in one workgroup.
-template <int NTN, int NTM>
+template <int NTN, int NTM, bool DCT = false>
 __global__ __launch_bounds__(kBlock) void precond_fc_blurT_kernel(
     const float2* __restrict__ Tp, int n_, int tsp, FftDesc fdn, const float2* __restrict__ twn,
     float* __restrict__ t_out, int off, float2* __restrict__ Tc, int M_, int tsc, FftDesc fdm,
-    const float2* __restrict__ twm, int pair0) {
+    const float2* __restrict__ twm, int pair0, const float2* __restrict__ dtw) {
     extern __shared__ float2 buf[];
     const int M = NTM > 0 ? NTM : M_;
     const int n = NTN > 0 ? NTN : n_;
@@ -625,24 +644,53 @@ __global__ __launch_bounds__(kBlock) void precond_fc_blurT_kernel(
     const int hn = n / 2 + 1;
     FixedTw<(NTN > 0 ? NTN : 1)> twpn;
     if constexpr (NTN > 0) fixed_tw_load<NTN>(twn, twpn.w);
-    strided_copy<(NTN > 0 ? NTN / 2 + 1 : 0), float4>(
-        hn, [&](int k) { return *reinterpret_cast<const float4*>(Tp + (size_t)k * tsp + 2 * q); },
-        [&](int k, float4 v) {
-            float2 Xa = make_float2(v.x, v.y), Xb = make_float2(v.z, v.w);
-            const bool edge = (k == 0) || (2 * k == n);
-            if (edge) {  // spectra of real rows are real at DC and Nyquist
-                Xa.y = 0.0f;
-                Xb.y = 0.0f;
+    if constexpr (DCT) {  // DCT-III of the two rows as the DCT plan's inverse row pass
+        const float* Tr = reinterpret_cast<const float*>(Tp);
+        strided_copy<(NTN > 0 ? NTN : 0), float2>(
+            n, [&](int k) { return *reinterpret_cast<const float2*>(Tr + (size_t)k * tsp + 2 * q); },
+            [&](int k, float2 v) { buf[lds_slot(k)] = v; });
+        __syncthreads();
+        float2 keep[FFT_EPT];
+#pragma unroll
+        for (int i = 0; i < FFT_EPT; ++i) {
+            const int k = threadIdx.x + i * kBlock;
+            if (k < n) {
+                const float2 Y = buf[lds_slot(k)];
+                const float2 Yr = (k == 0) ? make_float2(0.0f, 0.0f) : buf[lds_slot(n - k)];
+                const float2 wc = cconj(dtw[k]);
+                const float2 Va = cmul(wc, make_float2(Y.x, -Yr.x));
+                const float2 Vb = cmul(wc, make_float2(Y.y, -Yr.y));
+                keep[i] = make_float2(Va.x - Vb.y, Va.y + Vb.x);
             }
-            buf[lds_slot(k)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
-            if (!edge) buf[lds_slot(n - k)] = make_float2(Xa.x + Xb.y, -Xa.y + Xb.x);
-        });
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < FFT_EPT; ++i) {
+            const int k = threadIdx.x + i * kBlock;
+            if (k < n) buf[lds_slot(k)] = keep[i];
+        }
+    } else {
+        strided_copy<(NTN > 0 ? NTN / 2 + 1 : 0), float4>(
+            hn, [&](int k) { return *reinterpret_cast<const float4*>(Tp + (size_t)k * tsp + 2 * q); },
+            [&](int k, float4 v) {
+                float2 Xa = make_float2(v.x, v.y), Xb = make_float2(v.z, v.w);
+                const bool edge = (k == 0) || (2 * k == n);
+                if (edge) {  // spectra of real rows are real at DC and Nyquist
+                    Xa.y = 0.0f;
+                    Xb.y = 0.0f;
+                }
+                buf[lds_slot(k)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
+                if (!edge) buf[lds_slot(n - k)] = make_float2(Xa.x + Xb.y, -Xa.y + Xb.x);
+            });
+    }
     __syncthreads();
     lds_fft_any<1, NTN, FFT_EPT>(buf, fdn, 1, 8, twn, NTN > 0 ? twpn.w : nullptr);
+    // t at column x of the two rows
+    auto tv = [&](int x) { return buf[lds_slot(DCT ? fc_dct_perm(x, n) : x)]; };
     if (t_out) {
         const size_t ra = (size_t)(2 * q) * n;
         for (int x = threadIdx.x; x < n; x += kBlock) {
-            const float2 v = buf[lds_slot(x)];
+            const float2 v = tv(x);
             t_out[ra + x] = v.x;
             t_out[ra + n + x] = v.y;
         }
@@ -654,7 +702,7 @@ __global__ __launch_bounds__(kBlock) void precond_fc_blurT_kernel(
     for (int j = 0; j < FC_EPT; ++j) {
         const int X = (int)threadIdx.x + j * kBlock;
         const int x = X - off;
-        e[j] = (X < M && x >= 0 && x < n) ? buf[lds_slot(x)] : make_float2(0.0f, 0.0f);
+        e[j] = (X < M && x >= 0 && x < n) ? tv(x) : make_float2(0.0f, 0.0f);
     }
     __syncthreads();
 #pragma unroll
@@ -760,21 +808,28 @@ hipError_t launch_fftconv_spectrum(const FftConv& c, const float* psf, int p, hi
     return launch_fc_cols(c, 0, 0, p, 1, c.H, s, 0, c.M, -1, 0, 0);
 }
 
+template <bool DCT>
+static hipError_t launch_frp(const FftConv& c, int n, int p, const float* g, float* r_out, double* partials,
+                             const PrecondRows& pr, hipStream_t s) {
+    const int blocks = n / 2;
+    const size_t lds = lds_bytes(c.M > n ? c.M : n, 0);
+    if (c.M == kFixedM && n == kFixedN)
+        hipLaunchKernelGGL((fc_residual_precond_kernel<kFixedM, kFixedN, DCT>), dim3(blocks), dim3(kBlock), lds, s,
+                           (const float2*)c.T, c.M, c.ts, c.fd, c.tw, (p - 1) / 2, n, p - 1, g, r_out, partials, pr.T,
+                           pr.ts, pr.fd, pr.tw, pr.dtw);
+    else
+        hipLaunchKernelGGL((fc_residual_precond_kernel<0, 0, DCT>), dim3(blocks), dim3(kBlock), lds, s,
+                           (const float2*)c.T, c.M, c.ts, c.fd, c.tw, (p - 1) / 2, n, p - 1, g, r_out, partials, pr.T,
+                           pr.ts, pr.fd, pr.tw, pr.dtw);
+    return hipGetLastError();
+}
+
 hipError_t launch_fc_residual_precond_rows(const FftConv& c, int n, int p, const float* g, float* r_out,
                                            double* partials, int* n_partials, const PrecondRows& pr, hipStream_t s) {
     if (!fftconv_fusable(c, n, pr)) return hipErrorInvalidValue;
-    const int blocks = n / 2;
-    if (n_partials) *n_partials = blocks;
-    const size_t lds = lds_bytes(c.M > n ? c.M : n, 0);
-    if (c.M == kFixedM && n == kFixedN)
-        hipLaunchKernelGGL((fc_residual_precond_kernel<kFixedM, kFixedN>), dim3(blocks), dim3(kBlock), lds, s,
-                           (const float2*)c.T, c.M, c.ts, c.fd, c.tw, (p - 1) / 2, n, p - 1, g, r_out, partials, pr.T,
-                           pr.ts, pr.fd, pr.tw);
-    else
-        hipLaunchKernelGGL((fc_residual_precond_kernel<0, 0>), dim3(blocks), dim3(kBlock), lds, s, (const float2*)c.T,
-                           c.M, c.ts, c.fd, c.tw, (p - 1) / 2, n, p - 1, g, r_out, partials, pr.T, pr.ts, pr.fd,
-                           pr.tw);
-    return hipGetLastError();
+    if (n_partials) *n_partials = n / 2;
+    return pr.dtw ? launch_frp<true>(c, n, p, g, r_out, partials, pr, s)
+                  : launch_frp<false>(c, n, p, g, r_out, partials, pr, s);
 }
 
 bool fftconv_ar_fusable(const FftConv& c, int n, const FftDesc& fdl) {
@@ -798,18 +853,24 @@ hipError_t launch_fc_residual_ar_rows(const FftConv& c, int n, int p, const floa
     return hipGetLastError();
 }
 
+template <bool DCT>
+static hipError_t launch_pfb(const FftConv& c, int n, int p, const PrecondRows& pr, float* t_out, hipStream_t s) {
+    const size_t lds = lds_bytes(c.M > n ? c.M : n, 0);
+    if (c.M == kFixedM && n == kFixedN)
+        hipLaunchKernelGGL((precond_fc_blurT_kernel<kFixedN, kFixedM, DCT>), dim3(n / 2), dim3(kBlock), lds, s,
+                           (const float2*)pr.T, n, pr.ts, pr.fd, pr.tw, t_out, p - 1, c.T, c.M, c.ts, c.fd, c.tw,
+                           (p - 1) / 2, pr.dtw);
+    else
+        hipLaunchKernelGGL((precond_fc_blurT_kernel<0, 0, DCT>), dim3(n / 2), dim3(kBlock), lds, s,
+                           (const float2*)pr.T, n, pr.ts, pr.fd, pr.tw, t_out, p - 1, c.T, c.M, c.ts, c.fd, c.tw,
+                           (p - 1) / 2, pr.dtw);
+    return hipGetLastError();
+}
+
 hipError_t launch_precond_rows_fc_fwd(const FftConv& c, int n, int p, const PrecondRows& pr, float* t_out,
                                       hipStream_t s) {
     if (!fftconv_fusable(c, n, pr)) return hipErrorInvalidValue;
-    const size_t lds = lds_bytes(c.M > n ? c.M : n, 0);
-    if (c.M == kFixedM && n == kFixedN)
-        hipLaunchKernelGGL((precond_fc_blurT_kernel<kFixedN, kFixedM>), dim3(n / 2), dim3(kBlock), lds, s,
-                           (const float2*)pr.T, n, pr.ts, pr.fd, pr.tw, t_out, p - 1, c.T, c.M, c.ts, c.fd, c.tw,
-                           (p - 1) / 2);
-    else
-        hipLaunchKernelGGL((precond_fc_blurT_kernel<0, 0>), dim3(n / 2), dim3(kBlock), lds, s, (const float2*)pr.T, n,
-                           pr.ts, pr.fd, pr.tw, t_out, p - 1, c.T, c.M, c.ts, c.fd, c.tw, (p - 1) / 2);
-    return hipGetLastError();
+    return pr.dtw ? launch_pfb<true>(c, n, p, pr, t_out, s) : launch_pfb<false>(c, n, p, pr, t_out, s);
 }
 
 bool fftconv_fusable(const FftConv& c, int n, const PrecondRows& pr) {

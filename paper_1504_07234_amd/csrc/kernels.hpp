@@ -193,10 +193,11 @@ hipError_t launch_fftconv_spectrum(const FftConv& c, const float* psf, int p, hi
 // The transposed half spectrum of the BCCB preconditioner (n x n, row stride
 // ts complex) and its transform plan, for the passes fused with the FFT blur.
 struct PrecondRows {
-    float2* T;
+    float2* T;            // BCCB: the transposed half spectrum; DCT: the real coefficients (float)
     int ts;
     FftDesc fd;
     const float2* tw;
+    const float2* dtw;    // DCT plan: the DCT twiddles (null: BCCB)
 };
 // The three passes of the FFT blur, one launch each: forward rows of the
 // S x S image placed at (off, off) (rows outside [y_lo, y_hi) are zero; `ext`

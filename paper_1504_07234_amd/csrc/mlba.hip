@@ -222,21 +222,24 @@ int do_blur(mlba_plan_s* P, const float* u, const float* g, float* y, bool want_
     return MLBA_OK;
 }
 
-// The preconditioner's half spectrum and transform plan (BCCB plans).
+// The preconditioner's transposed workspace and transform plan (BCCB: the
+// half spectrum; DCT: the real coefficients and the DCT twiddles).
 PrecondRows precond_rows(const mlba_plan_s* P) {
     PrecondRows pr{};
     pr.T = (float2*)P->swork;
     pr.ts = P->ts;
     pr.fd = P->fd;
     pr.tw = P->tw;
+    pr.dtw = P->precond == MLBA_PRECOND_DCT ? P->dtw : nullptr;
     return pr;
 }
 
-// FFT blur with the BCCB preconditioner: the residual's inverse row pass and
-// the preconditioner's forward row pass run as one launch (as do the
+// FFT blur with the BCCB or DCT preconditioner: the residual's inverse row
+// pass and the preconditioner's forward row pass run as one launch (as do the
 // preconditioner's inverse row pass and the forward row pass of A^T).
 bool fused_fft_path(const mlba_plan_s* P) {
-    return P->blur_fft && P->bc != MLBA_BC_ANTIREFLECT && P->precond == MLBA_PRECOND_BCCB &&
+    return P->blur_fft && P->bc != MLBA_BC_ANTIREFLECT &&
+           (P->precond == MLBA_PRECOND_BCCB || P->precond == MLBA_PRECOND_DCT) &&
            fftconv_fusable(P->fc, P->n, precond_rows(P));
 }
 
@@ -1312,8 +1315,15 @@ int mlba_restore(mlba_plan_t P, const float* g, const mlba_params* prm, float* f
             // r = g - A u with P's forward row pass; the partials are summed by P's column pass
             STCHK(do_blur_residual_precond_rows(P, P->u, g, &np, s));
             const float inv = (float)(1.0 / ((double)P->n * (double)P->n));
-            HIPCHK(launch_fft_cols_filter((float2*)P->swork, P->n, P->ts, P->spec, (float)alpha[i], inv, P->fd,
-                                          P->tw, s, nullptr, P->partials, np, P->rn + (i - ring_base)));
+            if (P->precond == MLBA_PRECOND_DCT) {
+                HIPCHK(launch_sum_partials(P->partials, np, P->rn + (i - ring_base), s));
+                MARK(BLUR, REDUCE);
+                HIPCHK(launch_dct_cols_filter((float*)P->swork, P->n, P->ts, P->spec, (float)alpha[i], inv, P->fd,
+                                              P->tw, P->dtw, s, nullptr));
+            } else {
+                HIPCHK(launch_fft_cols_filter((float2*)P->swork, P->n, P->ts, P->spec, (float)alpha[i], inv, P->fd,
+                                              P->tw, s, nullptr, P->partials, np, P->rn + (i - ring_base)));
+            }
             MARK(PRECOND, FFT_COLS);
             STCHK(check_stop(&hit));
             if (hit) {

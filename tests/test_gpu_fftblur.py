@@ -136,11 +136,11 @@ def test_autotune_picks_a_working_blur(mlba):
 @pytest.mark.parametrize("n,p,pc,implicit", [(97, 9, 2, False), (96, 9, 1, True), (96, 9, 0, True),
                                              (96, 9, 0, False)])
 def test_restore_small_fft_blur_and_kernel_profile(mlba, n, p, pc, implicit):
-    """Without the BCCB preconditioner (P = I, or the DCT of Algorithm 3) the
-    FFT blur runs its three passes; with it, the residual row pass is fused
-    with the preconditioner's forward row pass and the preconditioner's
-    inverse row pass with the forward row pass of A^T.  Both against the
-    oracle, and the kernel profile of the iteration."""
+    """Without a spectral preconditioner (P = I) the FFT blur runs its three
+    passes; with the BCCB matrix or the DCT of Algorithm 3 the residual row
+    pass is fused with the preconditioner's forward row pass and the
+    preconditioner's inverse row pass with the forward row pass of A^T.  Both
+    against the oracle, and the kernel profile of the iteration."""
     announce(f"restore n={n} p={p} precond={pc} FFT blur implicit={implicit}")
     gen = synth.rng(4400 + n + pc)
     H = synth.gaussian_psf(p, 1.5)
@@ -164,13 +164,13 @@ def test_restore_small_fft_blur_and_kernel_profile(mlba, n, p, pc, implicit):
     assert rel_err(f, ref["f"]) < 1e-4 and max_err(f, ref["f"]) < 1e-4
     assert rel_err(info.rnorm, ref["rnorm"]) < 1e-4
     assert rec == iters
-    fused = pc == 0
+    fused = pc in (0, 1)  # BCCB and DCT: P's row passes run inside the grid's
     assert kern["fc_cols"][1] == 2 * iters
     assert kern.get("fc_residual_precond_rows", (0, 0))[1] == (iters if fused else 0)
     assert kern.get("precond_rows_fc_fwd", (0, 0))[1] == (iters if fused else 0)
     assert kern.get("fc_rows_fwd", (0, 0))[1] == (1 if fused else 2) * iters
     assert kern.get("fft_cols", (0, 0))[1] == (0 if pc == 2 else iters)
-    assert kern.get("fft_rows_fwd", (0, 0))[1] == (iters if pc == 1 else 0)
+    assert kern.get("fft_rows_fwd", (0, 0))[1] == 0 and kern.get("fft_rows_inv", (0, 0))[1] == 0
     assert kern["shrink_synthesis" if implicit else "synthesis_level"][1] == 2 * iters
     assert ("analysis_level" in kern) == (not implicit)
     # every launch of an iteration is accounted to one phase
@@ -195,7 +195,7 @@ def test_profile_every(mlba):
 
 @pytest.mark.parametrize("bc,pc,method,implicit", [
     ("REFLECT", 0, "MLBA", True),    # BCCB: residual and P row passes fused
-    ("REFLECT", 1, "MLBA", False),   # DCT (Algorithm 3): the three grid passes
+    ("REFLECT", 1, "MLBA", False),   # DCT (Algorithm 3): its row passes fused likewise
     ("ZERO", 0, "MLBA", False),
     ("ZERO", 1, "MLBA", True),
     ("PERIODIC", 0, "MLBA", True),   # A = C: the residual formed in the spectrum
@@ -239,7 +239,7 @@ def test_restore_square_models_fft_blur(mlba, bc, pc, method, implicit):
     assert rel_err(f, ref["f"]) < 1e-4 and max_err(f, ref["f"]) < 1e-4
     assert rel_err(info.rnorm, ref["rnorm"]) < 1e-4
     spectral = bc == "PERIODIC" and pc == 0
-    fused = pc == 0 and not alg4 and not spectral
+    fused = pc in (0, 1) and not alg4 and not spectral
     assert ("fc_cols" in kern) == (not spectral)
     if spectral:  # one 2-D transform pair per iteration
         assert kern["fft_rows_fwd"][1] == kern["fft_cols"][1] == kern["fft_rows_inv"][1] == iters
