@@ -43,10 +43,20 @@ __host__ __device__ constexpr int fft_lds_elems(int elems, int n) {
     return smooth235(n) ? elems : (elems > bluestein_len(n) ? elems : bluestein_len(n));
 }
 
-// LDS slot of element i: one padding slot after every 8 elements, so that the
-// power-of-two strides of the Stockham writes do not pile onto one bank.
-__host__ __device__ __forceinline__ int lds_slot(int i) { return i + (i >> 3); }
-__host__ __device__ constexpr int lds_data_slots(int elems) { return elems + elems / 8 + 1; }
+// LDS slot of element i: one padding slot after every kLdsPad elements (0:
+// none), so that the power-of-two strides of the Stockham writes do not pile
+// onto one bank.
+#ifndef MLBA_LDS_PAD
+#define MLBA_LDS_PAD 16
+#endif
+constexpr int kLdsPad = MLBA_LDS_PAD;
+static_assert(kLdsPad == 0 || (kLdsPad & (kLdsPad - 1)) == 0, "LDS padding period: a power of two");
+// padding slots before element c (c >= 0)
+__host__ __device__ constexpr int lds_pad_of(int c) { return kLdsPad ? (int)((unsigned)c / kLdsPad) : 0; }
+// slot(i + c) == slot(i) + c + lds_pad_of(c) for every i when this holds
+__host__ __device__ constexpr bool lds_pad_aligned(int c) { return kLdsPad == 0 || c % kLdsPad == 0; }
+__host__ __device__ __forceinline__ int lds_slot(int i) { return i + lds_pad_of(i); }
+__host__ __device__ constexpr int lds_data_slots(int elems) { return elems + lds_pad_of(elems) + 1; }
 __host__ __device__ constexpr size_t lds_bytes(int elems, int n) { return (size_t)lds_data_slots(elems) * 8 + 0 * n; }
 
 // One strided pass of kBlock threads over `count` elements, element
@@ -529,10 +539,11 @@ __device__ __forceinline__ void fixed_tw_load(const float2* __restrict__ tw, flo
 }
 
 // pre: the stage's slice of fixed_tw_load's output, or null (table reads).
-// LDS addresses: slot(i + c) = slot(i) + c + c/8 whenever c is a multiple of 8,
-// so when the strides nb and NS are multiples of 8 (or NS == 1 with R a
-// multiple of 8) each butterfly computes one base slot and reaches its R
-// values at compile-time offsets (immediate offsets of the LDS instructions).
+// LDS addresses: slot(i + c) = slot(i) + c + lds_pad_of(c) whenever c is a
+// multiple of the padding period, so when the strides nb and NS are (or
+// NS == 1 with R a multiple of it) each butterfly computes one base slot and
+// reaches its R values at compile-time offsets (immediate offsets of the LDS
+// instructions).
 // tid: the thread's index inside the kBlock threads that own the sequence
 template <int R, int DIR, int N, int NS>
 __device__ __forceinline__ void stockham_stage_fixed(float2* buf, const float2* __restrict__ tw,
@@ -541,8 +552,8 @@ __device__ __forceinline__ void stockham_stage_fixed(float2* buf, const float2* 
     constexpr int MAXB = (nb + kBlock - 1) / kBlock;
     constexpr int step = N / (NS * R);
     constexpr int T = tw_table_loads(R);
-    constexpr bool rd_off = nb % 8 == 0;
-    constexpr bool wr_off = NS % 8 == 0 || (NS == 1 && R % 8 == 0);
+    constexpr bool rd_off = lds_pad_aligned(nb);
+    constexpr bool wr_off = lds_pad_aligned(NS) || (NS == 1 && lds_pad_aligned(R));
     float2 v[MAXB][R];
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
@@ -557,7 +568,7 @@ __device__ __forceinline__ void stockham_stage_fixed(float2* buf, const float2* 
             const int sb = lds_slot(j);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                float2 x = rd_off ? buf[sb + r * (nb + nb / 8)] : buf[lds_slot(j + r * nb)];
+                float2 x = rd_off ? buf[sb + r * (nb + lds_pad_of(nb))] : buf[lds_slot(j + r * nb)];
                 if (r > 0 && jm > 0) x = cmul(x, w[r]);
                 v[i][r] = x;
             }
@@ -575,8 +586,8 @@ __device__ __forceinline__ void stockham_stage_fixed(float2* buf, const float2* 
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 if constexpr (!wr_off) buf[lds_slot(dst + r * NS)] = v[i][r];
-                else if constexpr (NS == 1) buf[sb + r + r / 8] = v[i][r];  // dst = j R, R a multiple of 8
-                else buf[sb + r * (NS + NS / 8)] = v[i][r];
+                else if constexpr (NS == 1) buf[sb + r + lds_pad_of(r)] = v[i][r];  // dst = j R, R aligned
+                else buf[sb + r * (NS + lds_pad_of(NS))] = v[i][r];
             }
         }
     }
@@ -610,7 +621,7 @@ __device__ __forceinline__ void stage_first_from_regs(float2 (&v)[R], float2* bu
     const int sb = lds_slot(j * R);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        if constexpr (R % 8 == 0) buf[sb + r + r / 8] = v[r];
+        if constexpr (lds_pad_aligned(R)) buf[sb + r + lds_pad_of(r)] = v[r];
         else buf[lds_slot(j * R + r)] = v[r];
     }
 }
@@ -622,7 +633,7 @@ template <int R, int DIR, int N>
 __device__ __forceinline__ void stage_last_to_regs(const float2* buf, const float2* __restrict__ tw,
                                                    const float2* raw, float2 (&v)[R], int j) {
     constexpr int nb = N / R;
-    constexpr bool rd_off = nb % 8 == 0;
+    constexpr bool rd_off = lds_pad_aligned(nb);
     float2 w[R];
     if (j > 0) {  // twiddles W^(j r) of the length-N transform
         if (raw) twiddle_powers_raw<R, DIR>(raw, w);
@@ -631,7 +642,7 @@ __device__ __forceinline__ void stage_last_to_regs(const float2* buf, const floa
     const int sb = lds_slot(j);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        float2 x = rd_off ? buf[sb + r * (nb + nb / 8)] : buf[lds_slot(j + r * nb)];
+        float2 x = rd_off ? buf[sb + r * (nb + lds_pad_of(nb))] : buf[lds_slot(j + r * nb)];
         if (r > 0 && j > 0) x = cmul(x, w[r]);
         v[r] = x;
     }
