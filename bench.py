@@ -73,6 +73,12 @@ TRAFFIC_SOURCES = {
 }
 
 
+def direct_cols(p: int) -> bool:
+    """PSF sizes whose FFT-grid column pass is the compiled p-tap convolution
+    along y (the library's fftconv_direct_taps)."""
+    return p in (9, 31)
+
+
 def sources_hash(kernel: str):
     import hashlib
     files = TRAFFIC_SOURCES.get(kernel)
@@ -128,8 +134,12 @@ def kernel_model(n, p, N, L, implicit, fft_blur):
       fft_rows_fwd / _inv       n^2 reals <-> (n/2+1) n complex (transposed)
       fft_cols                  read + write (n/2+1) n complex, read the filter
       fc_rows_fwd (A)           read u (N^2), write (M/2+1) N complex
-      fc_cols (A, A^T)          read the nonzero rows ((M/2+1) N, (M/2+1) n),
-                                read the PSF spectrum and write (M/2+1) M
+      fc_cols (A, A^T)          read the nonzero rows ((M/2+1) N, (M/2+1) n)
+                                and write the kept ones ((M/2+1) n, (M/2+1) N);
+                                with compiled taps (p = 9, 31) a p-tap
+                                convolution along y reading the (M/2+1) p
+                                taps, else the transform pair reading the PSF
+                                spectrum and writing (M/2+1) M
       fc_rows_inv (A^T)         read (M/2+1) N complex, write w (omega: +read)
       fc_residual_precond_rows  read (M/2+1) n complex and g, write (n/2+1) n
       precond_rows_fc_fwd       read (n/2+1) n complex, write (M/2+1) n
@@ -155,7 +165,11 @@ def kernel_model(n, p, N, L, implicit, fft_blur):
         M = fft_grid(N)
         hm = M // 2 + 1
         m["fc_rows_fwd"] = {"bytes": f4 * NN + c8 * hm * N, "flops": 0.0, "launches": 1}
-        m["fc_cols"] = {"bytes": c8 * hm * (N + n) + 2 * 2 * c8 * hm * M, "flops": 0.0, "launches": 2}
+        if direct_cols(p):
+            m["fc_cols"] = {"bytes": 2 * c8 * hm * (N + n) + 2 * c8 * hm * p, "flops": 8.0 * p * hm * (N + n),
+                            "launches": 2}
+        else:
+            m["fc_cols"] = {"bytes": c8 * hm * (N + n) + 2 * 2 * c8 * hm * M, "flops": 0.0, "launches": 2}
         m["fc_residual_precond_rows"] = {"bytes": c8 * hm * n + f4 * nn + c8 * hp, "flops": 0.0, "launches": 1}
         m["fft_cols"] = {"bytes": 2 * c8 * hp + f4 * hp, "flops": 0.0, "launches": 1}
         m["precond_rows_fc_fwd"] = {"bytes": c8 * hp + c8 * hm * n, "flops": 0.0, "launches": 1}
@@ -569,7 +583,11 @@ def antireflective_section(steps: int = 30, warmup: int = 3):
         for k in ("conv_blur", "conv_blur_t"):
             model.pop(k)
         model["fc_rows_fwd"] = {"bytes": 2 * (nn + 8.0 * hm * m_), "flops": 0.0, "launches": 2, "bound": "hbm"}
-        model["fc_cols"] = {"bytes": 2 * 8.0 * hm * (m_ + M + n), "flops": 0.0, "launches": 2, "bound": "hbm"}
+        if direct_cols(p):
+            model["fc_cols"] = {"bytes": 2 * 8.0 * hm * (m_ + n) + 2 * 8.0 * hm * p,
+                                "flops": 8.0 * p * hm * (m_ + n), "launches": 2, "bound": "hbm"}
+        else:
+            model["fc_cols"] = {"bytes": 2 * 8.0 * hm * (m_ + M + n), "flops": 0.0, "launches": 2, "bound": "hbm"}
         # the residual's inverse rows fused with the transform's forward rows: read the
         # kept half-spectrum rows and g, write Tr; the reblur's inverse rows into omega
         model["fc_residual_precond_rows"] = {"bytes": 8.0 * hm * n + 2 * nn, "flops": 0.0, "launches": 1,

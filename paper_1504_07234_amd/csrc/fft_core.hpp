@@ -325,12 +325,14 @@ __device__ __forceinline__ void stockham_stage(float2* buf, int n, int nseq, int
         const int j = tl + i * nthr;
         if (live && j < nb) {
             const int jm = ns_shift >= 0 ? (j & (Ns - 1)) : (j % Ns);
+            // W^0 = 1 exactly, so butterflies with jm == 0 take the same
+            // products (a per-lane skip would only add branches)
             float2 w[R];
-            if (jm > 0) twiddle_powers<R, DIR>(tw, jm * step, n, w);
+            if (Ns > 1) twiddle_powers<R, DIR>(tw, jm * step, n, w);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 float2 x = buf[lds_slot(base0 + j + r * nb)];
-                if (r > 0 && jm > 0) x = cmul(x, w[r]);
+                if (r > 0 && Ns > 1) x = cmul(x, w[r]);
                 v[i][r] = x;
             }
             dft<R, DIR>(v[i]);
@@ -560,8 +562,8 @@ __device__ __forceinline__ void stockham_stage_fixed(float2* buf, const float2* 
         const int j = tid + i * kBlock;
         if (nb % kBlock == 0 || j < nb) {
             const int jm = j % NS;
-            float2 w[R];
-            if (jm > 0) {
+            float2 w[R];  // jm == 0 multiplies by W^0 = 1 exactly: no per-lane branch
+            if constexpr (NS > 1) {
                 if (pre) twiddle_powers_raw<R, DIR>(pre + i * T, w);
                 else twiddle_powers<R, DIR>(tw, jm * step, N, w);
             }
@@ -569,7 +571,7 @@ __device__ __forceinline__ void stockham_stage_fixed(float2* buf, const float2* 
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 float2 x = rd_off ? buf[sb + r * (nb + lds_pad_of(nb))] : buf[lds_slot(j + r * nb)];
-                if (r > 0 && jm > 0) x = cmul(x, w[r]);
+                if (NS > 1 && r > 0) x = cmul(x, w[r]);
                 v[i][r] = x;
             }
             dft<R, DIR>(v[i]);
@@ -634,16 +636,14 @@ __device__ __forceinline__ void stage_last_to_regs(const float2* buf, const floa
                                                    const float2* raw, float2 (&v)[R], int j) {
     constexpr int nb = N / R;
     constexpr bool rd_off = lds_pad_aligned(nb);
-    float2 w[R];
-    if (j > 0) {  // twiddles W^(j r) of the length-N transform
-        if (raw) twiddle_powers_raw<R, DIR>(raw, w);
-        else twiddle_powers<R, DIR>(tw, j, N, w);
-    }
+    float2 w[R];  // twiddles W^(j r) of the length-N transform (W^0 = 1 exactly for j == 0)
+    if (raw) twiddle_powers_raw<R, DIR>(raw, w);
+    else twiddle_powers<R, DIR>(tw, j, N, w);
     const int sb = lds_slot(j);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         float2 x = rd_off ? buf[sb + r * (nb + lds_pad_of(nb))] : buf[lds_slot(j + r * nb)];
-        if (r > 0 && j > 0) x = cmul(x, w[r]);
+        if (r > 0) x = cmul(x, w[r]);
         v[r] = x;
     }
     dft<R, DIR>(v);

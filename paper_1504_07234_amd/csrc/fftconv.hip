@@ -754,8 +754,128 @@ hipError_t launch_fc_rows_fwd(const FftConv& c, const float* src, int S, int off
     return launch_fc_rows_fwd_t<false>(c, src, S, off, y_lo, y_hi, s, ext, PcgDir{});
 }
 
+// ---- the column pass without column transforms ----------------------------
+// After the row pass, column k of the grid holds U(y, k) = sum_x u(y, x) W^(x k)
+// (W = exp(-2 pi i / M)).  In those coordinates the 2-D convolution with the
+// PSF is, column by column, a P-tap convolution along y whose taps are the
+// PSF's rows transformed the same way, G(a, k) = sum_b h(a, b) W^(b k):
+//   A:   V(o, k) = sum_a G(a, k) U(o - a, k)
+//   A^T: V(o, k) = sum_a conj(G(a, k)) U(o + a, k)     (the correlation)
+// These are the values the column transform pair with F(pad H) (or its
+// conjugate) gives on every output whose inputs do not wrap around the grid;
+// `scale` is the 1/M of the inverse row pass (no column transforms, so no
+// second 1/M).  One column per workgroup and R consecutive outputs per
+// thread: the column's inputs are staged in LDS once, each thread reads its
+// R + P - 1 of them, the P taps are uniform over the workgroup, and the
+// outputs leave through LDS as one coalesced store.
+template <int P, int R, bool CORR>
+__global__ __launch_bounds__(kBlock) void fc_cols_direct_kernel(float2* __restrict__ T, int ts,
+                                                                const float2* __restrict__ G, float scale, int y_lo,
+                                                                int y_hi, int o_lo, int o_hi) {
+    constexpr int W = R + P - 1;           // inputs per thread
+    constexpr int S = kBlock * R + P - 1;  // inputs per column
+    constexpr bool PAD = R % 2 == 0;       // lanes read at stride R: an odd stride meets no bank twice already
+    auto slot = [](int l) { return PAD ? l + l / 8 : l; };
+    __shared__ float2 buf[PAD ? S + S / 8 + 1 : S];
+    const int k = blockIdx.x;
+    float2* col = T + (size_t)k * ts;
+    const int base = CORR ? o_lo : o_lo - (P - 1);  // grid row of LDS entry 0
+    const float2* __restrict__ g = G + (size_t)k * P;
+    float2 tap[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) tap[a] = g[a];
+#pragma unroll
+    for (int j = 0; j < (S + kBlock - 1) / kBlock; ++j) {
+        const int l = j * kBlock + (int)threadIdx.x;
+        if (S % kBlock == 0 || l < S) {
+            const int i = base + l;
+            buf[slot(l)] = (i >= y_lo && i < y_hi) ? col[i] : make_float2(0.0f, 0.0f);
+        }
+    }
+    __syncthreads();
+    const int t0 = (int)threadIdx.x * R;
+    float2 u[W];
+#pragma unroll
+    for (int c = 0; c < W; ++c) u[c] = buf[slot(t0 + c)];
+    float2 acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        float ax = 0.0f, ay = 0.0f;
+#pragma unroll
+        for (int a = 0; a < P; ++a) {
+            const float2 v = u[CORR ? r + a : r + P - 1 - a];  // U(o + a) or U(o - a), o = base-relative t0 + r
+            const float2 h = tap[a];
+            if constexpr (CORR) {  // conj(h) v
+                ax = fmaf(h.x, v.x, ax);
+                ax = fmaf(h.y, v.y, ax);
+                ay = fmaf(h.x, v.y, ay);
+                ay = fmaf(-h.y, v.x, ay);
+            } else {
+                ax = fmaf(h.x, v.x, ax);
+                ax = fmaf(-h.y, v.y, ax);
+                ay = fmaf(h.x, v.y, ay);
+                ay = fmaf(h.y, v.x, ay);
+            }
+        }
+        acc[r] = make_float2(ax * scale, ay * scale);
+    }
+    __syncthreads();  // every window has been read
+#pragma unroll
+    for (int r = 0; r < R; ++r) buf[slot(t0 + r)] = acc[r];
+    __syncthreads();
+    const int count = o_hi - o_lo;
+    for (int l = threadIdx.x; l < count; l += kBlock) col[o_lo + l] = buf[slot(l)];
+}
+
+// The taps G of the direct column pass: the first p rows of every column
+// after the row pass of the PSF placed at the origin.
+__global__ __launch_bounds__(kBlock) void fc_taps_kernel(const float2* __restrict__ T, int ts, int half, int p,
+                                                         float2* __restrict__ G) {
+    const int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= half * p) return;
+    const int k = idx / p;
+    G[idx] = T[(size_t)k * ts + (idx - k * p)];
+}
+
+// The direct column pass, when the plan has the taps for this PSF size and
+// the outputs' inputs stay inside the grid; false: not taken.
+template <int P>
+static bool fc_cols_direct_t(const FftConv& c, bool corr, int y_lo, int y_hi, int o_lo, int o_hi, hipStream_t s) {
+    const int count = o_hi - o_lo;
+    if (count <= 0 || count > 9 * kBlock) return false;
+    if (corr ? (o_hi - 1 + P - 1 >= c.M || o_lo < 0) : (o_lo - (P - 1) < 0 || o_hi > c.M)) return false;
+    const int half = c.M / 2 + 1;
+    const float scale = (float)(1.0 / (double)c.M);
+    const bool r8 = count <= 8 * kBlock;
+#define FC_DIRECT(R, CO)                                                                                     \
+    hipLaunchKernelGGL((fc_cols_direct_kernel<P, R, CO>), dim3(half), dim3(kBlock), 0, s, c.T, c.ts,        \
+                       (const float2*)c.G, scale, y_lo, y_hi, o_lo, o_hi)
+    if (r8) {
+        if (corr) FC_DIRECT(8, true);
+        else FC_DIRECT(8, false);
+    } else {
+        if (corr) FC_DIRECT(9, true);
+        else FC_DIRECT(9, false);
+    }
+#undef FC_DIRECT
+    return true;
+}
+
+static bool fc_cols_direct(const FftConv& c, int conj_h, int y_lo, int y_hi, int mode, int o_lo, int o_hi,
+                           int fold, hipStream_t s) {
+    if (!c.G || mode != 0 || fold >= 0 || (conj_h != 0 && conj_h != 1)) return false;
+    switch (c.p) {
+        case 9: return fc_cols_direct_t<9>(c, conj_h == 1, y_lo, y_hi, o_lo, o_hi, s);
+        case 31: return fc_cols_direct_t<31>(c, conj_h == 1, y_lo, y_hi, o_lo, o_hi, s);
+        default: return false;
+    }
+}
+
+bool fftconv_direct_taps(int p) { return p == 9 || p == 31; }
+
 hipError_t launch_fc_cols(const FftConv& c, int conj_h, int y_lo, int y_hi, int mode, float2* cspec, hipStream_t s,
                           int o_lo, int o_hi, int fold, int fn, int fcn) {
+    if (fc_cols_direct(c, conj_h, y_lo, y_hi, mode, o_lo, o_hi, fold, s)) return hipGetLastError();
     const int CC = fc_cols_per_block(c.M);
     const int half = c.M / 2 + 1;
     const float inv = (float)(1.0 / ((double)c.M * (double)c.M));
@@ -805,6 +925,13 @@ int fftconv_partials_count(int M, int n) {
 hipError_t launch_fftconv_spectrum(const FftConv& c, const float* psf, int p, hipStream_t s) {
     hipError_t e = launch_fc_rows_fwd(c, psf, p, 0, 0, p, s);
     if (e != hipSuccess) return e;
+    if (c.G) {
+        if (c.p != p) return hipErrorInvalidValue;
+        const int n = (c.M / 2 + 1) * p;
+        hipLaunchKernelGGL(fc_taps_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, (const float2*)c.T,
+                           c.ts, c.M / 2 + 1, p, c.G);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     return launch_fc_cols(c, 0, 0, p, 1, c.H, s, 0, c.M, -1, 0, 0);
 }
 

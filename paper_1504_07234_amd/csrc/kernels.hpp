@@ -185,9 +185,16 @@ struct FftConv {
     const float2* tw;
     float2* T;
     float2* H;
+    // the PSF's rows transformed along x on the grid, G[k * p + a] for the
+    // half-spectrum column k and PSF row a (null: the column pass always
+    // transforms)
+    float2* G;
+    int p;
 };
 int fftconv_max_size();
 int fftconv_partials_count(int M, int n);
+// PSF sizes with a compiled direct column pass (FftConv::G)
+bool fftconv_direct_taps(int p);
 hipError_t launch_fftconv_spectrum(const FftConv& c, const float* psf, int p, hipStream_t s);
 
 // The transposed half spectrum of the BCCB preconditioner (n x n, row stride

@@ -1013,10 +1013,15 @@ int ensure_fftconv(mlba_plan_s* P, hipStream_t s) {
         const double ang = -2.0 * pi * (double)q / (double)M;
         tw[q] = make_float2((float)cos(ang), (float)sin(ang));
     }
-    float2 *twd = nullptr, *T = nullptr, *H = nullptr;
+    float2 *twd = nullptr, *T = nullptr, *H = nullptr, *G = nullptr;
     STCHK(dalloc_t(P, &twd, (size_t)M));
     STCHK(dalloc_t(P, &T, (size_t)(M / 2 + 1) * c.ts));
     STCHK(dalloc_t(P, &H, (size_t)(M / 2 + 1) * M));
+    if (fftconv_direct_taps(P->p)) {
+        STCHK(dalloc_t(P, &G, (size_t)(M / 2 + 1) * P->p));
+        c.G = G;
+        c.p = P->p;
+    }
     HIPCHK(hipMemcpyAsync(twd, tw.data(), M * sizeof(float2), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));  // the host table goes out of scope
     c.tw = twd;
