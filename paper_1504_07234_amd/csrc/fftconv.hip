@@ -764,68 +764,89 @@ hipError_t launch_fc_rows_fwd(const FftConv& c, const float* src, int S, int off
 // These are the values the column transform pair with F(pad H) (or its
 // conjugate) gives on every output whose inputs do not wrap around the grid;
 // `scale` is the 1/M of the inverse row pass (no column transforms, so no
-// second 1/M).  One column per workgroup and R consecutive outputs per
-// thread: the column's inputs are staged in LDS once, each thread reads its
-// R + P - 1 of them, the P taps are uniform over the workgroup, and the
-// outputs leave through LDS as one coalesced store.
+// second 1/M).  R consecutive outputs per thread: a column's inputs are
+// staged in LDS once, each thread reads its R + P - 1 of them, the P taps are
+// uniform over the workgroup (scalar registers), and the outputs leave through
+// LDS as one coalesced store.  Each workgroup walks the columns k =
+// blockIdx.x, + gridDim.x, ...: the next column's global loads are issued
+// before the current one's multiply-adds, so that the loads of one column and
+// the arithmetic of another overlap.
 template <int P, int R, bool CORR>
 __global__ __launch_bounds__(kBlock) void fc_cols_direct_kernel(float2* __restrict__ T, int ts,
                                                                 const float2* __restrict__ G, float scale, int y_lo,
-                                                                int y_hi, int o_lo, int o_hi) {
+                                                                int y_hi, int o_lo, int o_hi, int half) {
     constexpr int W = R + P - 1;           // inputs per thread
     constexpr int S = kBlock * R + P - 1;  // inputs per column
+    constexpr int J = (S + kBlock - 1) / kBlock;
     constexpr bool PAD = R % 2 == 0;       // lanes read at stride R: an odd stride meets no bank twice already
     auto slot = [](int l) { return PAD ? l + l / 8 : l; };
-    __shared__ float2 buf[PAD ? S + S / 8 + 1 : S];
-    const int k = blockIdx.x;
-    float2* col = T + (size_t)k * ts;
+    __shared__ float2 in[PAD ? S + S / 8 + 1 : S];
+    __shared__ float2 out[PAD ? kBlock * R + kBlock * R / 8 : kBlock * R];
     const int base = CORR ? o_lo : o_lo - (P - 1);  // grid row of LDS entry 0
-    const float2* __restrict__ g = G + (size_t)k * P;
-    float2 tap[P];
-#pragma unroll
-    for (int a = 0; a < P; ++a) tap[a] = g[a];
-#pragma unroll
-    for (int j = 0; j < (S + kBlock - 1) / kBlock; ++j) {
-        const int l = j * kBlock + (int)threadIdx.x;
-        if (S % kBlock == 0 || l < S) {
-            const int i = base + l;
-            buf[slot(l)] = (i >= y_lo && i < y_hi) ? col[i] : make_float2(0.0f, 0.0f);
-        }
-    }
-    __syncthreads();
+    const int count = o_hi - o_lo;
     const int t0 = (int)threadIdx.x * R;
-    float2 u[W];
+    float2 pre[J];
+    auto fetch = [&](int k) {
+        const float2* col = T + (size_t)k * ts;
 #pragma unroll
-    for (int c = 0; c < W; ++c) u[c] = buf[slot(t0 + c)];
-    float2 acc[R];
+        for (int j = 0; j < J; ++j) {
+            const int l = j * kBlock + (int)threadIdx.x;
+            const int i = base + l;
+            pre[j] = ((S % kBlock == 0 || l < S) && i >= y_lo && i < y_hi) ? col[i] : make_float2(0.0f, 0.0f);
+        }
+    };
+    int k = blockIdx.x;
+    fetch(k);
+    for (; k < half; k += gridDim.x) {
+        const float2* __restrict__ g = G + (size_t)k * P;
+        float2 tap[P];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        float ax = 0.0f, ay = 0.0f;
+        for (int a = 0; a < P; ++a) tap[a] = g[a];
 #pragma unroll
-        for (int a = 0; a < P; ++a) {
-            const float2 v = u[CORR ? r + a : r + P - 1 - a];  // U(o + a) or U(o - a), o = base-relative t0 + r
-            const float2 h = tap[a];
-            if constexpr (CORR) {  // conj(h) v
-                ax = fmaf(h.x, v.x, ax);
-                ax = fmaf(h.y, v.y, ax);
-                ay = fmaf(h.x, v.y, ay);
-                ay = fmaf(-h.y, v.x, ay);
-            } else {
-                ax = fmaf(h.x, v.x, ax);
-                ax = fmaf(-h.y, v.y, ax);
-                ay = fmaf(h.x, v.y, ay);
-                ay = fmaf(h.y, v.x, ay);
+        for (int j = 0; j < J; ++j) {
+            const int l = j * kBlock + (int)threadIdx.x;
+            if (S % kBlock == 0 || l < S) in[slot(l)] = pre[j];
+        }
+        __syncthreads();  // the column is staged (and the previous one's outputs are stored)
+        if (k + (int)gridDim.x < half) fetch(k + gridDim.x);
+        // window entry c (input t0 + c) meets output r through tap a = c - r
+        // (A^T) or r + P - 1 - c (A); each entry is read once from LDS
+        float ax[R], ay[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) ax[r] = ay[r] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+            const float2 v = in[slot(t0 + c)];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int a = CORR ? c - r : r + P - 1 - c;
+                if (a < 0 || a >= P) continue;
+                const float2 h = tap[a];
+                if constexpr (CORR) {  // conj(h) v
+                    ax[r] = fmaf(h.x, v.x, ax[r]);
+                    ax[r] = fmaf(h.y, v.y, ax[r]);
+                    ay[r] = fmaf(h.x, v.y, ay[r]);
+                    ay[r] = fmaf(-h.y, v.x, ay[r]);
+                } else {
+                    ax[r] = fmaf(h.x, v.x, ax[r]);
+                    ax[r] = fmaf(-h.y, v.y, ax[r]);
+                    ay[r] = fmaf(h.x, v.y, ay[r]);
+                    ay[r] = fmaf(h.y, v.x, ay[r]);
+                }
             }
         }
-        acc[r] = make_float2(ax * scale, ay * scale);
-    }
-    __syncthreads();  // every window has been read
 #pragma unroll
-    for (int r = 0; r < R; ++r) buf[slot(t0 + r)] = acc[r];
-    __syncthreads();
-    const int count = o_hi - o_lo;
-    for (int l = threadIdx.x; l < count; l += kBlock) col[o_lo + l] = buf[slot(l)];
+        for (int r = 0; r < R; ++r) out[slot(t0 + r)] = make_float2(ax[r] * scale, ay[r] * scale);
+        __syncthreads();  // the outputs are complete and every window has been read
+        float2* col = T + (size_t)k * ts;
+        for (int l = threadIdx.x; l < count; l += kBlock) col[o_lo + l] = out[slot(l)];
+    }
 }
+
+// Workgroups of the direct column pass: three per CU of the 256-CU device,
+// each walking about 1.5 columns of the 2304-point grid (measured against one
+// column per workgroup: 17.5 against 18.5 us per launch).
+constexpr int kDirectGrid = 768;
 
 // The taps G of the direct column pass: the first p rows of every column
 // after the row pass of the PSF placed at the origin.
@@ -847,9 +868,10 @@ static bool fc_cols_direct_t(const FftConv& c, bool corr, int y_lo, int y_hi, in
     const int half = c.M / 2 + 1;
     const float scale = (float)(1.0 / (double)c.M);
     const bool r8 = count <= 8 * kBlock;
+    const int grid = half < kDirectGrid ? half : kDirectGrid;
 #define FC_DIRECT(R, CO)                                                                                     \
-    hipLaunchKernelGGL((fc_cols_direct_kernel<P, R, CO>), dim3(half), dim3(kBlock), 0, s, c.T, c.ts,        \
-                       (const float2*)c.G, scale, y_lo, y_hi, o_lo, o_hi)
+    hipLaunchKernelGGL((fc_cols_direct_kernel<P, R, CO>), dim3(grid), dim3(kBlock), 0, s, c.T, c.ts,        \
+                       (const float2*)c.G, scale, y_lo, y_hi, o_lo, o_hi, half)
     if (r8) {
         if (corr) FC_DIRECT(8, true);
         else FC_DIRECT(8, false);
