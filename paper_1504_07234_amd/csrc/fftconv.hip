@@ -65,14 +65,25 @@ static int fc_seq_shift(int batch) {
 // DIR (Algorithm 2's PCG): the source is the direction d, first updated in
 // place to d = z + b d with b = rho_new / rho (nothing once the CG has
 // stopped), as the separate direction kernel does; rho_new null: d = z.
-template <int NT, bool DIR = false>
-__global__ __launch_bounds__(kBlock) void fc_rows_fwd_kernel(const float* __restrict__ src, int S, int off, int M_,
-                                                             float2* __restrict__ T, int ts, FftDesc fd,
-                                                             const float2* __restrict__ tw, int G_, int seq_shift,
-                                                             int pair0, int pair_end, int ext, PcgDir dir) {
-    extern __shared__ float2 buf[];
+// GT > 1 (compiled length only): GT row pairs per workgroup of GT x kBlock
+// threads, each pair transformed by its own kBlock threads in its own LDS
+// slice; the transposed half spectrum is then written with the GT pairs of
+// one frequency next to each other (16 GT contiguous bytes per frequency
+// instead of 16).
+template <int NT, bool DIR = false, int GT = 1>
+__global__ __launch_bounds__(kBlock * GT) void fc_rows_fwd_kernel(const float* __restrict__ src, int S, int off, int M_,
+                                                                  float2* __restrict__ T, int ts, FftDesc fd,
+                                                                  const float2* __restrict__ tw, int G_, int seq_shift,
+                                                                  int pair0, int pair_end, int ext, PcgDir dir) {
+    static_assert(GT == 1 || NT > 0, "several pairs of kBlock threads: compiled lengths only");
+    extern __shared__ float2 lds[];
     const int M = NT > 0 ? NT : M_;
-    const int G = NT > 0 ? 1 : G_;
+    const int G = NT > 0 ? GT : G_;
+    // this thread's pair slice (GT > 1) or the whole workgroup's (GT == 1)
+    const int gs = GT > 1 ? (int)threadIdx.x / kBlock : 0;
+    const int tid = GT > 1 ? (int)threadIdx.x % kBlock : (int)threadIdx.x;
+    constexpr int SL = NT > 0 ? lds_data_slots(NT > 0 ? NT : 1) : 0;
+    float2* buf = lds + gs * SL;
     const int pb = pair0 + xcd_block(blockIdx.x, gridDim.x) * G;
     bool dir_on = false, dir_copy = false;
     float dir_b = 0.0f;
@@ -91,38 +102,50 @@ __global__ __launch_bounds__(kBlock) void fc_rows_fwd_kernel(const float* __rest
             return src[i];
         }
     };
-    FixedTw<(NT > 0 ? NT : 1)> twp;
-    if constexpr (NT > 0) fixed_tw_load<NT>(tw, twp.w);
-    strided_copy<NT, float2>(
-        G * M,
-        [&](int idx) {
-            const int g = idx / M;
-            const int X = idx - g * M;
-            const int Y = 2 * (pb + g);
-            const int x = X - off;
-            float a = 0.0f, b = 0.0f;
-            const int y0 = Y - off, y1 = Y + 1 - off;
-            if (ext != EXT_ZERO) {
-                if (pb + g < pair_end && x >= -off && x < S + off) {
-                    if (y0 >= -off && y0 < S + off) a = fetch_ext(src, S, y0, x, ext);
-                    if (y1 >= -off && y1 < S + off) b = fetch_ext(src, S, y1, x, ext);
-                }
-            } else if (pb + g < pair_end && x >= 0 && x < S) {
-                if (y0 >= 0 && y0 < S) a = rd((size_t)y0 * S + x);
-                if (y1 >= 0 && y1 < S) b = rd((size_t)y1 * S + x);
+    // value X of pair q (zero outside the image and past pair_end)
+    auto fetch = [&](int q, int X) {
+        const int Y = 2 * q;
+        const int x = X - off;
+        float a = 0.0f, b = 0.0f;
+        const int y0 = Y - off, y1 = Y + 1 - off;
+        if (ext != EXT_ZERO) {
+            if (q < pair_end && x >= -off && x < S + off) {
+                if (y0 >= -off && y0 < S + off) a = fetch_ext(src, S, y0, x, ext);
+                if (y1 >= -off && y1 < S + off) b = fetch_ext(src, S, y1, x, ext);
             }
-            return make_float2(a, b);
-        },
-        [&](int idx, float2 v) { buf[lds_slot(idx)] = v; });
-    __syncthreads();
-    lds_fft_any<-1, NT, FC_EPT>(buf, fd, G, seq_shift, tw, NT > 0 ? twp.w : nullptr);
+        } else if (q < pair_end && x >= 0 && x < S) {
+            if (y0 >= 0 && y0 < S) a = rd((size_t)y0 * S + x);
+            if (y1 >= 0 && y1 < S) b = rd((size_t)y1 * S + x);
+        }
+        return make_float2(a, b);
+    };
+    FixedTw<(NT > 0 ? NT : 1)> twp;
+    if constexpr (NT > 0) {
+        fixed_tw_load<NT>(tw, twp.w, tid);
+        strided_copy<NT, float2>(
+            NT, [&](int X) { return fetch(pb + gs, X); }, [&](int X, float2 v) { buf[lds_slot(X)] = v; }, tid);
+        __syncthreads();
+        lds_fft_fixed<-1, NT>(buf, tw, twp.w, tid);
+    } else {
+        strided_copy<NT, float2>(
+            G * M,
+            [&](int idx) {
+                const int g = idx / M;
+                return fetch(pb + g, idx - g * M);
+            },
+            [&](int idx, float2 v) { buf[lds_slot(idx)] = v; });
+        __syncthreads();
+        lds_fft_any<-1, NT, FC_EPT>(buf, fd, G, seq_shift, tw, nullptr);
+    }
     const int half = M / 2 + 1;
-    for (int idx = threadIdx.x; idx < G * half; idx += kBlock) {
+    for (int idx = threadIdx.x; idx < G * half; idx += kBlock * GT) {
         const int k = idx / G;
         const int g = idx - k * G;
         if (pb + g >= pair_end) continue;
-        const float2 Z = buf[lds_slot(g * M + k)];
-        const float2 Zc = cconj(buf[lds_slot(g * M + (k == 0 ? 0 : M - k))]);
+        // compiled length: pair g's slice; run-time plan: the G sequences back to back
+        auto at = [&](int e) { return NT > 0 ? lds[g * SL + lds_slot(e)] : lds[lds_slot(g * M + e)]; };
+        const float2 Z = at(k);
+        const float2 Zc = cconj(at(k == 0 ? 0 : M - k));
         const float2 Xa = cscale(cadd(Z, Zc), 0.5f);
         const float2 D = csub(Z, Zc);
         const float2 Xb = make_float2(0.5f * D.y, -0.5f * D.x);
@@ -733,9 +756,10 @@ static hipError_t launch_fc_rows_fwd_t(const FftConv& c, const float* src, int S
     const int p0 = y_lo / 2, p1 = (y_hi + 1) / 2;
     const int blocks = (p1 - p0 + G - 1) / G;
     if (blocks <= 0) return hipSuccess;
-    if (c.M == kFixedM && G == 1)
-        hipLaunchKernelGGL((fc_rows_fwd_kernel<kFixedM, DIR>), dim3(blocks), dim3(kBlock), lds_bytes(c.M, c.M), s, src,
-                           S, off, c.M, c.T, c.ts, c.fd, c.tw, 1, fc_seq_shift(1), p0, p1, ext, dir);
+    if (c.M == kFixedM && G == 1)  // two row pairs per workgroup: 32-byte transposed writes
+        hipLaunchKernelGGL((fc_rows_fwd_kernel<kFixedM, DIR, 2>), dim3((p1 - p0 + 1) / 2), dim3(2 * kBlock),
+                           2 * lds_bytes(c.M, c.M), s, src, S, off, c.M, c.T, c.ts, c.fd, c.tw, 2, fc_seq_shift(1), p0,
+                           p1, ext, dir);
     else if (c.M == kFixedM2 && G == 1)
         hipLaunchKernelGGL((fc_rows_fwd_kernel<kFixedM2, DIR>), dim3(blocks), dim3(kBlock), lds_bytes(c.M, c.M), s,
                            src, S, off, c.M, c.T, c.ts, c.fd, c.tw, 1, fc_seq_shift(1), p0, p1, ext, dir);
