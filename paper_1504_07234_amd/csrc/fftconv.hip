@@ -795,10 +795,15 @@ hipError_t launch_fc_rows_fwd(const FftConv& c, const float* src, int S, int off
 // blockIdx.x, + gridDim.x, ...: the next column's global loads are issued
 // before the current one's multiply-adds, so that the loads of one column and
 // the arithmetic of another overlap.
+// fold >= 0 (A^T of a square model): the outputs are the grid rows [0, m)
+// and the column's rows [0, fn) receive E^T of them, the sum over each
+// pixel's preimages under the pad of width fcn, as the transform pair's
+// write-back does.
 template <int P, int R, bool CORR>
 __global__ __launch_bounds__(kBlock) void fc_cols_direct_kernel(float2* __restrict__ T, int ts,
                                                                 const float2* __restrict__ G, float scale, int y_lo,
-                                                                int y_hi, int o_lo, int o_hi, int half) {
+                                                                int y_hi, int o_lo, int o_hi, int half, int fold,
+                                                                int fn, int fcn) {
     constexpr int W = R + P - 1;           // inputs per thread
     constexpr int S = kBlock * R + P - 1;  // inputs per column
     constexpr int J = (S + kBlock - 1) / kBlock;
@@ -863,7 +868,14 @@ __global__ __launch_bounds__(kBlock) void fc_cols_direct_kernel(float2* __restri
         for (int r = 0; r < R; ++r) out[slot(t0 + r)] = make_float2(ax[r] * scale, ay[r] * scale);
         __syncthreads();  // the outputs are complete and every window has been read
         float2* col = T + (size_t)k * ts;
-        for (int l = threadIdx.x; l < count; l += kBlock) col[o_lo + l] = out[slot(l)];
+        if (fold >= 0) {
+            const int rows = fn + (fn & 1);
+            for (int l = threadIdx.x; l < rows; l += kBlock)
+                col[l] = l < fn ? fold_sum(l, fn, fcn, fold, [&](int Y) { return out[slot(Y - o_lo)]; })
+                                : make_float2(0.0f, 0.0f);
+        } else {
+            for (int l = threadIdx.x; l < count; l += kBlock) col[o_lo + l] = out[slot(l)];
+        }
     }
 }
 
@@ -885,17 +897,23 @@ __global__ __launch_bounds__(kBlock) void fc_taps_kernel(const float2* __restric
 // The direct column pass, when the plan has the taps for this PSF size and
 // the outputs' inputs stay inside the grid; false: not taken.
 template <int P>
-static bool fc_cols_direct_t(const FftConv& c, bool corr, int y_lo, int y_hi, int o_lo, int o_hi, hipStream_t s) {
+static bool fc_cols_direct_t(const FftConv& c, bool corr, int y_lo, int y_hi, int o_lo, int o_hi, int fold, int fn,
+                             int fcn, hipStream_t s) {
     const int count = o_hi - o_lo;
-    if (count <= 0 || count > 9 * kBlock) return false;
-    if (corr ? (o_hi - 1 + P - 1 >= c.M || o_lo < 0) : (o_lo - (P - 1) < 0 || o_hi > c.M)) return false;
+    if (count <= 0 || count > 9 * kBlock || o_lo < 0 || o_hi > c.M || y_lo < 0 || y_hi > c.M) return false;
+    // the transform pair's convolution is circular: an input index past the
+    // grid wraps around, and the direct pass (which reads zero there) agrees
+    // only while no wrapped index lands on a nonzero row
+    if (corr ? (o_hi + P - 2 >= c.M && o_hi + P - 2 - c.M >= y_lo)
+             : (o_lo - (P - 1) < 0 && o_lo - (P - 1) + c.M < y_hi))
+        return false;
     const int half = c.M / 2 + 1;
     const float scale = (float)(1.0 / (double)c.M);
     const bool r8 = count <= 8 * kBlock;
     const int grid = half < kDirectGrid ? half : kDirectGrid;
 #define FC_DIRECT(R, CO)                                                                                     \
     hipLaunchKernelGGL((fc_cols_direct_kernel<P, R, CO>), dim3(grid), dim3(kBlock), 0, s, c.T, c.ts,        \
-                       (const float2*)c.G, scale, y_lo, y_hi, o_lo, o_hi, half)
+                       (const float2*)c.G, scale, y_lo, y_hi, o_lo, o_hi, half, fold, fn, fcn)
     if (r8) {
         if (corr) FC_DIRECT(8, true);
         else FC_DIRECT(8, false);
@@ -908,11 +926,16 @@ static bool fc_cols_direct_t(const FftConv& c, bool corr, int y_lo, int y_hi, in
 }
 
 static bool fc_cols_direct(const FftConv& c, int conj_h, int y_lo, int y_hi, int mode, int o_lo, int o_hi,
-                           int fold, hipStream_t s) {
-    if (!c.G || mode != 0 || fold >= 0 || (conj_h != 0 && conj_h != 1)) return false;
+                           int fold, int fn, int fcn, hipStream_t s) {
+    if (!c.G || mode != 0 || (conj_h != 0 && conj_h != 1)) return false;
+    if (fold >= 0) {  // E^T folds the grid rows [0, fn + 2 fcn) of the correlation
+        if (conj_h != 1) return false;
+        o_lo = 0;
+        o_hi = fn + 2 * fcn;
+    }
     switch (c.p) {
-        case 9: return fc_cols_direct_t<9>(c, conj_h == 1, y_lo, y_hi, o_lo, o_hi, s);
-        case 31: return fc_cols_direct_t<31>(c, conj_h == 1, y_lo, y_hi, o_lo, o_hi, s);
+        case 9: return fc_cols_direct_t<9>(c, conj_h == 1, y_lo, y_hi, o_lo, o_hi, fold, fn, fcn, s);
+        case 31: return fc_cols_direct_t<31>(c, conj_h == 1, y_lo, y_hi, o_lo, o_hi, fold, fn, fcn, s);
         default: return false;
     }
 }
@@ -921,7 +944,7 @@ bool fftconv_direct_taps(int p) { return p == 9 || p == 31; }
 
 hipError_t launch_fc_cols(const FftConv& c, int conj_h, int y_lo, int y_hi, int mode, float2* cspec, hipStream_t s,
                           int o_lo, int o_hi, int fold, int fn, int fcn) {
-    if (fc_cols_direct(c, conj_h, y_lo, y_hi, mode, o_lo, o_hi, fold, s)) return hipGetLastError();
+    if (fc_cols_direct(c, conj_h, y_lo, y_hi, mode, o_lo, o_hi, fold, fn, fcn, s)) return hipGetLastError();
     const int CC = fc_cols_per_block(c.M);
     const int half = c.M / 2 + 1;
     const float inv = (float)(1.0 / ((double)c.M * (double)c.M));
