@@ -76,7 +76,7 @@ TRAFFIC_SOURCES = {
 def direct_cols(p: int) -> bool:
     """PSF sizes whose FFT-grid column pass is the compiled p-tap convolution
     along y (the library's fftconv_direct_taps)."""
-    return p in (9, 31)
+    return p in (5, 9, 17, 31)
 
 
 def sources_hash(kernel: str):
@@ -136,7 +136,7 @@ def kernel_model(n, p, N, L, implicit, fft_blur):
       fc_rows_fwd (A)           read u (N^2), write (M/2+1) N complex
       fc_cols (A, A^T)          read the nonzero rows ((M/2+1) N, (M/2+1) n)
                                 and write the kept ones ((M/2+1) n, (M/2+1) N);
-                                with compiled taps (p = 9, 31) a p-tap
+                                with compiled taps (p = 5, 9, 17, 31) a p-tap
                                 convolution along y reading the (M/2+1) p
                                 taps, else the transform pair reading the PSF
                                 spectrum and writing (M/2+1) M

@@ -934,13 +934,15 @@ static bool fc_cols_direct(const FftConv& c, int conj_h, int y_lo, int y_hi, int
         o_hi = fn + 2 * fcn;
     }
     switch (c.p) {
+        case 5: return fc_cols_direct_t<5>(c, conj_h == 1, y_lo, y_hi, o_lo, o_hi, fold, fn, fcn, s);
         case 9: return fc_cols_direct_t<9>(c, conj_h == 1, y_lo, y_hi, o_lo, o_hi, fold, fn, fcn, s);
+        case 17: return fc_cols_direct_t<17>(c, conj_h == 1, y_lo, y_hi, o_lo, o_hi, fold, fn, fcn, s);
         case 31: return fc_cols_direct_t<31>(c, conj_h == 1, y_lo, y_hi, o_lo, o_hi, fold, fn, fcn, s);
         default: return false;
     }
 }
 
-bool fftconv_direct_taps(int p) { return p == 9 || p == 31; }
+bool fftconv_direct_taps(int p) { return p == 5 || p == 9 || p == 17 || p == 31; }
 
 hipError_t launch_fc_cols(const FftConv& c, int conj_h, int y_lo, int y_hi, int mode, float2* cspec, hipStream_t s,
                           int o_lo, int o_hi, int fold, int fn, int fcn) {
