@@ -788,7 +788,8 @@ hipError_t launch_fc_rows_fwd(const FftConv& c, const float* src, int S, int off
 // These are the values the column transform pair with F(pad H) (or its
 // conjugate) gives on every output whose inputs do not wrap around the grid;
 // `scale` is the 1/M of the inverse row pass (no column transforms, so no
-// second 1/M).  R consecutive outputs per thread: a column's inputs are
+// second 1/M).  R consecutive outputs per thread (4, 5, 8 or 9, the fewest
+// that cover the column): a column's inputs are
 // staged in LDS once, each thread reads its R + P - 1 of them, the P taps are
 // uniform over the workgroup (scalar registers), and the outputs leave through
 // LDS as one coalesced store.  Each workgroup walks the columns k =
@@ -807,10 +808,12 @@ __global__ __launch_bounds__(kBlock) void fc_cols_direct_kernel(float2* __restri
     constexpr int W = R + P - 1;           // inputs per thread
     constexpr int S = kBlock * R + P - 1;  // inputs per column
     constexpr int J = (S + kBlock - 1) / kBlock;
-    constexpr bool PAD = R % 2 == 0;       // lanes read at stride R: an odd stride meets no bank twice already
-    auto slot = [](int l) { return PAD ? l + l / 8 : l; };
-    __shared__ float2 in[PAD ? S + S / 8 + 1 : S];
-    __shared__ float2 out[PAD ? kBlock * R + kBlock * R / 8 : kBlock * R];
+    // lanes read at stride R: an odd stride meets no bank twice already, an
+    // even one gets a spare slot every R entries (stride R + 1)
+    constexpr bool PAD = R % 2 == 0;
+    auto slot = [](int l) { return PAD ? l + l / R : l; };
+    __shared__ float2 in[PAD ? S + S / R + 1 : S];
+    __shared__ float2 out[PAD ? kBlock * R + kBlock : kBlock * R];
     const int base = CORR ? o_lo : o_lo - (P - 1);  // grid row of LDS entry 0
     const int count = o_hi - o_lo;
     const int t0 = (int)threadIdx.x * R;
@@ -909,17 +912,29 @@ static bool fc_cols_direct_t(const FftConv& c, bool corr, int y_lo, int y_hi, in
         return false;
     const int half = c.M / 2 + 1;
     const float scale = (float)(1.0 / (double)c.M);
-    const bool r8 = count <= 8 * kBlock;
+    // outputs per thread: the fewest of 4, 5, 8, 9 that cover the column
+    const int R = count <= 4 * kBlock ? 4 : count <= 5 * kBlock ? 5 : count <= 8 * kBlock ? 8 : 9;
     const int grid = half < kDirectGrid ? half : kDirectGrid;
 #define FC_DIRECT(R, CO)                                                                                     \
     hipLaunchKernelGGL((fc_cols_direct_kernel<P, R, CO>), dim3(grid), dim3(kBlock), 0, s, c.T, c.ts,        \
                        (const float2*)c.G, scale, y_lo, y_hi, o_lo, o_hi, half, fold, fn, fcn)
-    if (r8) {
-        if (corr) FC_DIRECT(8, true);
-        else FC_DIRECT(8, false);
-    } else {
-        if (corr) FC_DIRECT(9, true);
-        else FC_DIRECT(9, false);
+    switch (R) {
+        case 4:
+            if (corr) FC_DIRECT(4, true);
+            else FC_DIRECT(4, false);
+            break;
+        case 5:
+            if (corr) FC_DIRECT(5, true);
+            else FC_DIRECT(5, false);
+            break;
+        case 8:
+            if (corr) FC_DIRECT(8, true);
+            else FC_DIRECT(8, false);
+            break;
+        default:
+            if (corr) FC_DIRECT(9, true);
+            else FC_DIRECT(9, false);
+            break;
     }
 #undef FC_DIRECT
     return true;
