@@ -210,8 +210,13 @@ int mlba_plan_destroy(mlba_plan_t plan);
  * A') are computed:
  * MLBA_BLUR_DIRECT (default): LDS-tiled direct convolution, p^2 taps per
  * output; MLBA_BLUR_FFT: circular convolution on an M x M grid, M >= m =
- * n + p - 1, M = 2^a 3^b (section 2.1's FFT evaluation), three transform
- * passes per product.  The square models place the n x n image with its pad
+ * n + p - 1, M = 2^a 3^b (section 2.1's FFT evaluation), three passes per
+ * product: row transforms, a column pass, inverse row transforms.  For
+ * p = 5, 9, 17 and 31 the column pass is the p-tap convolution along y with
+ * the PSF's rows transformed the same way (the same values as the column
+ * transform pair with F(pad H) on every output that does not wrap around;
+ * the taps, (M/2 + 1) p complex, are kept with the spectrum); otherwise it is
+ * that transform pair.  The square models place the n x n image with its pad
  * (Table 1, section 2.2) on the grid, m x m; A^T folds the correlation back
  * by the pad's transpose.  With the periodic model and MLBA_PRECOND_BCCB,
  * MLBA_BLUR_FFT also selects for eq. (MLBA2) the spectral residual of
