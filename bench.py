@@ -779,7 +779,7 @@ def main() -> int:
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4)}
     # the same launch against the arithmetic roofs: the published FP32 peak
-    # (packed FMA) and the non-packed peak of this build (no packed FP32)
+    # (packed FMA) and the non-packed peak of the library's code (built without packed FP32)
     tfl = per_launch_flops / launch_s / 1e12
     roof["alu"] = {"achieved_tflops": round(tfl, 2), "frac_published": round(tfl / FP32_PEAK_TFLOPS, 4),
                    "frac_nonpacked": round(tfl / FP32_VALU_PEAK_TFLOPS, 4)}
