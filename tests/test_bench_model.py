@@ -67,3 +67,19 @@ def test_kernel_model_byte_counts():
     # take less time than its bytes; the direct 31 x 31 blur is bound by its taps
     assert m["shrink_synthesis"]["bound"] == "hbm"
     assert m["conv_blur_t"]["bound"] == "alu"
+
+
+def test_kernel_model_direct_column_pass():
+    """The grid's column pass with compiled taps: A reads the N rows of the
+    unknown and keeps n, A^T reads n and keeps N, both read the (M/2+1) p
+    taps; 4 FMAs (8 flops) per complex tap and output.  Other PSF sizes keep
+    the transform pair, which also reads the PSF spectrum."""
+    n, N = 2048, 2078
+    hm = bench.fft_grid(N) // 2 + 1
+    m = bench.kernel_model(n, 31, N, 3, True, True)
+    assert bench.direct_cols(31) and not bench.direct_cols(49)
+    assert m["fc_cols"]["bytes"] == 2 * 8 * hm * (N + n) + 2 * 8 * hm * 31
+    assert m["fc_cols"]["flops"] == 8 * 31 * hm * (N + n)
+    m49 = bench.kernel_model(2048, 49, 2096, 3, True, True)
+    M49 = bench.fft_grid(2096)
+    assert m49["fc_cols"]["bytes"] == 8 * (M49 // 2 + 1) * (2096 + 2048) + 4 * 8 * (M49 // 2 + 1) * M49
