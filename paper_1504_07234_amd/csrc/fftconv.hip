@@ -786,16 +786,17 @@ hipError_t launch_fc_rows_fwd(const FftConv& c, const float* src, int S, int off
 //   A:   V(o, k) = sum_a G(a, k) U(o - a, k)
 //   A^T: V(o, k) = sum_a conj(G(a, k)) U(o + a, k)     (the correlation)
 // These are the values the column transform pair with F(pad H) (or its
-// conjugate) gives on every output whose inputs do not wrap around the grid;
-// `scale` is the 1/M of the inverse row pass (no column transforms, so no
-// second 1/M).  R consecutive outputs per thread (4, 5, 8 or 9, the fewest
-// that cover the column): a column's inputs are
-// staged in LDS once, each thread reads its R + P - 1 of them, the P taps are
-// uniform over the workgroup (scalar registers), and the outputs leave through
-// LDS as one coalesced store.  Each workgroup walks the columns k =
-// blockIdx.x, + gridDim.x, ...: the next column's global loads are issued
-// before the current one's multiply-adds, so that the loads of one column and
-// the arithmetic of another overlap.
+// conjugate) gives, as long as no input index that wraps around the grid
+// lands on a nonzero row (the launcher checks); `scale` is the 1/M of the
+// inverse row pass (no column transforms, so no second 1/M).  R consecutive
+// outputs per thread (4, 5, 8 or 9, the fewest that cover the column): a
+// column's inputs are staged in LDS once (rows outside [y_lo, y_hi) as zero),
+// each thread reads its R + P - 1 of them, the P taps are uniform over the
+// workgroup (scalar registers), and the outputs leave through LDS as one
+// coalesced store.  Each workgroup walks the columns k = blockIdx.x,
+// + gridDim.x, ...: the next column's global loads are issued before the
+// current one's multiply-adds, so that the loads of one column and the
+// arithmetic of another overlap.
 // fold >= 0 (A^T of a square model): the outputs are the grid rows [0, m)
 // and the column's rows [0, fn) receive E^T of them, the sum over each
 // pixel's preimages under the pad of width fcn, as the transform pair's
