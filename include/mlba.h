@@ -437,8 +437,9 @@ int mlba_unrolled_backward(mlba_unrolled_t unrolled, const float* const* g, doub
  * Phases of one iteration of eq. (MLBA2) as the library runs them. */
 #define MLBA_PHASE_SYNTHESIS 0  /* x = delta S_mu(z), u = W^T x                        */
 #define MLBA_PHASE_BLUR      1  /* r = g - A u and ||r||^2 (with the FFT blur and the
-                                   BCCB preconditioner also the preconditioner's
-                                   forward row pass, fused with the residual's)     */
+                                   BCCB or DCT preconditioner also the
+                                   preconditioner's forward row pass, fused with
+                                   the residual's)                                  */
 #define MLBA_PHASE_PRECOND   2  /* t = P_alpha r (the transform passes)              */
 #define MLBA_PHASE_BLUR_T    3  /* w = A^T t (fused FFT path: from the
                                    preconditioner's inverse row pass on)            */
@@ -456,7 +457,8 @@ int mlba_unrolled_backward(mlba_unrolled_t unrolled, const float* const* g, doub
 #define MLBA_KERNEL_FFT_COLS          8  /* preconditioner: column pass with the filter  */
 #define MLBA_KERNEL_FFT_ROWS_INV      9  /* preconditioner: inverse row pass             */
 #define MLBA_KERNEL_FC_ROWS_FWD      10  /* FFT blur: forward row pass                   */
-#define MLBA_KERNEL_FC_COLS          11  /* FFT blur: column pass                        */
+#define MLBA_KERNEL_FC_COLS          11  /* FFT blur: column pass (p-tap convolution
+                                            along y, or the transform pair)       */
 #define MLBA_KERNEL_FC_ROWS_INV      12  /* FFT blur: inverse row pass                   */
 #define MLBA_KERNEL_FC_RESIDUAL_PRECOND_ROWS 13  /* fused residual rows + preconditioner
                                                     forward rows                        */
